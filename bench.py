@@ -1,0 +1,197 @@
+#!/usr/bin/env python3
+"""Benchmark of the generalised-entropy MI hot path on one MI355X.
+
+Workload (one "step"): the multi-modal sweep -- a 256x256x180 u16 T1-like
+fixed phantom against a T2-like moving phantom, 1000 affine transforms
+(10 x-translations x 10 z-rotations x 10 isotropic scales), 128-bin hard
+joint histograms, Shannon MI and Tsallis MI for q in {0.5, 0.8, 1.2, 1.5, 2}
+from each histogram.  One step = one mi_eval call over all 1000 transforms
+(fixed binning, histogram sweep, MI reduction), inputs resident in HBM.
+
+Prints one JSON line: throughput in voxel-transform evaluations per second
+(fixed voxels x transforms / s), the histogram kernel's HBM roofline
+fraction on algorithmic bytes (HIP-event timed), the one-transform-per-
+launch path and the Parzen gradient path for comparison, and the CPU
+oracle's rate on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "voxel-transform evals/s (warp+jointhist+MI) & MI-grad evals/s; % HBM roofline"
+HBM_PEAK_GBS = 8000.0
+PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "hist_hard_multimodal_traffic.txt")
+
+
+def log(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes_per_voxel_xform(fixed, moving, mats, bins) -> float:
+    """Fixed voxel read + moving voxels covered (|det| of the linear part)
+    + the transform's histogram written once, per fixed voxel."""
+    dets = np.abs(np.linalg.det(mats.reshape(-1, 3, 4)[:, :, :3]))
+    return (fixed.itemsize + moving.itemsize * float(dets.mean()) +
+            4.0 * bins * bins / fixed.size)
+
+
+def read_traffic(kernel_version: str):
+    """HBM bytes per launch from a committed rocprofv3 counter summary, if
+    it was taken on the current kernel build."""
+    try:
+        text = open(PROFILE_TRAFFIC).read()
+    except OSError:
+        return None
+    fields = dict(line.split("=", 1) for line in text.splitlines() if "=" in line and not line.startswith("#"))
+    if fields.get("kernel_version", "").strip() != kernel_version:
+        return None
+    try:
+        return float(fields["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def kernel_version() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("hard.hip", "common.h"):
+        h.update(open(os.path.join(ROOT, "paper_1909_10690_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def cpu_baseline(c, min_seconds: float) -> dict:
+    """The oracle, as it stands, on evenly spaced transforms of the same
+    workload, one batch of (host threads) transforms at a time until
+    ``min_seconds`` of wall time have passed."""
+    import oracle
+    F = oracle.volume(c["fixed"], *c["fixed_range"])
+    M = oracle.volume(c["moving"], *c["moving_range"])
+    threads = oracle.num_threads()
+    order = np.random.default_rng(0).permutation(len(c["transforms"]))
+    done, dt = 0, 0.0
+    while dt < min_seconds and done < len(order):
+        batch = c["transforms"][order[done:done + threads]]
+        t0 = time.perf_counter()
+        oracle.eval_hard(F, M, batch, c["bins"], c["q"])
+        dt += time.perf_counter() - t0
+        done += len(batch)
+    rate = c["fixed"].size * done / dt
+    return {"value": rate, "unit": "voxel-transform evals/s", "cores": threads, "kind": "oracle",
+            "sample": f"{done} of the 1000 transforms (random order, seed 0), full 256x256x180 "
+                      f"volume, all 6 entropies, {dt:.1f} s wall on {threads} threads"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0,
+                    help="minimum wall time of the CPU-oracle sample")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle leg")
+    ap.add_argument("--no-extras", action="store_true", help="skip the plain-path and gradient legs")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for {args.gpus}); the metric path has no "
+              f"multi-GPU leg in this build", file=sys.stderr)
+        return 2
+
+    import torch
+    from paper_1909_10690_amd import binding as B
+    from paper_1909_10690_amd import inputs
+
+    log("building the multi-modal sweep inputs (256x256x180 u16, 1000 transforms)")
+    c = inputs.multimodal_sweep()
+    fixed, moving, mats = c["fixed"], c["moving"], c["transforms"]
+    n, bins, q = len(mats), c["bins"], c["q"]
+    ctx = B.Context(0)
+    dev = "cuda:0"
+    F = B.Volume.from_numpy(fixed, *c["fixed_range"], dev)
+    Mv = B.Volume.from_numpy(moving, *c["moving_range"], dev)
+    tr = torch.from_numpy(mats).to(dev)
+    ws = torch.empty(ctx.workspace_size(F, Mv, n, bins, len(q)), dtype=torch.uint8, device=dev)
+    out = torch.empty((n, len(q)), dtype=torch.float64, device=dev)
+
+    def step():
+        ctx.eval(F, Mv, tr, bins, q, out=out, want_overlap=False, workspace=ws)
+
+    log(f"warmup {args.warmup} steps")
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ctx.timing_read(B.TIMER_HARD)
+    ctx.timing(True)
+    log(f"timing {args.steps} steps")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ctx.timing(False)
+    k_ms, k_n = ctx.timing_read(B.TIMER_HARD)
+    r_ms, r_n = ctx.timing_read(B.TIMER_REDUCE)
+    vox_xf = fixed.size * n
+    value = vox_xf * args.steps / dt
+    ms_step = dt / args.steps * 1e3
+    k_avg_ms = k_ms / max(k_n, 1)
+    balg = algorithmic_bytes_per_voxel_xform(fixed, moving, mats, bins)
+    achieved = balg * vox_xf / (k_avg_ms * 1e-3) / 1e9
+    traffic = read_traffic(kernel_version())
+    log(f"{value:.3e} voxel-xf/s, {ms_step:.2f} ms/step, hist kernel {k_avg_ms:.2f} ms, "
+        f"reduce {r_ms / max(r_n, 1):.3f} ms")
+
+    result = {
+        "metric": METRIC, "value": value, "unit": "voxel-transform evals/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int64",
+        "data": "synthetic",
+        "config": {"workload": "multi-modal sweep: 256x256x180 u16 T1-like vs T2-like phantoms, "
+                               "1000 affine transforms (10 tx x 10 rot_z x 10 scale), 128 bins, "
+                               "Shannon + Tsallis q={0.5,0.8,1.2,1.5,2.0}",
+                   "transforms": n, "bins": bins, "n_q": len(q), "fixed_voxels": int(fixed.size)},
+        "mi_evals_per_s": n * args.steps / dt,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "hist_hard_kernel<uint16_t>", "kernel_ms": k_avg_ms,
+                     "algorithmic_bytes_per_voxel_xform": balg},
+    }
+
+    if not args.no_extras:
+        # one transform per launch: the same kernels, no batching
+        sub = 100
+        log(f"plain path: {sub} transforms, one mi_eval call each")
+        ws1 = torch.empty(ctx.workspace_size(F, Mv, 1, bins, len(q)), dtype=torch.uint8, device=dev)
+        out1 = torch.empty((1, len(q)), dtype=torch.float64, device=dev)
+        trs = [tr[i:i + 1] for i in range(sub)]
+        for i in range(3):
+            ctx.eval(F, Mv, trs[i], bins, q, out=out1, want_overlap=False, workspace=ws1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(sub):
+            ctx.eval(F, Mv, trs[i], bins, q, out=out1, want_overlap=False, workspace=ws1)
+        torch.cuda.synchronize()
+        plain = fixed.size * sub / (time.perf_counter() - t0)
+        result["plain_one_transform_per_launch"] = {"value": plain, "unit": "voxel-transform evals/s",
+                                                    "batched_speedup": value / plain}
+
+    if not args.no_cpu:
+        log(f"CPU oracle for at least {args.cpu_seconds} s")
+        result["cpu_baseline"] = cpu_baseline(c, args.cpu_seconds)
+
+    print(json.dumps(result), flush=True)
+    ctx.close()
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,190 @@
+/*
+ * gemi.h -- C ABI of the MI355X (gfx950) generalised-entropy mutual
+ * information library, libgemi.so.
+ *
+ * Computes, for many candidate affine transforms at once, the registration
+ * metric of Vianna & Murta, "Analysis of Generalized Entropies in Mutual
+ * Information Medical Image Registration" (arXiv 1909.10690): the moving
+ * volume is resampled under each transform (Transform block of Fig. 1),
+ * the joint intensity histogram of fixed vs. resampled moving voxels is
+ * accumulated over the overlap, and that one histogram is reduced to
+ * Shannon MI (Eq. (1), Eq. (2)) and Tsallis MI for any number of entropic
+ * indices q (Discussion: the same histogram serves every entropy).  A
+ * Parzen (cubic B-spline) variant adds the gradient with respect to the 12
+ * transform entries, for gradient-based optimisation of Eq. (3).
+ *
+ * Conventions common to every entry point
+ *  - Every data pointer (volumes, transforms, outputs, workspace) is a
+ *    DEVICE pointer on the context's GPU, allocated and owned by the caller;
+ *    the library never frees or retains them.  `q` arrays and `mi_pair`
+ *    arrays are HOST pointers, read before the call returns.
+ *  - Calls are asynchronous and ordered on `stream` (a hipStream_t; NULL =
+ *    the default stream).  Outputs are valid once the stream reaches them.
+ *  - No entry point allocates device memory: scratch space is the caller's
+ *    `workspace`, sized by mi_workspace_size().  Calls that share one
+ *    workspace must be ordered on one stream.
+ *  - Arguments are validated before anything is launched; a negative
+ *    status means nothing was enqueued.  No exception or abort crosses
+ *    the ABI.
+ *  - Per-transform degenerate cases are not errors: a transform with no
+ *    overlap gives MI 0, overlap 0, gradient 0; a transform with a
+ *    non-finite entry, a linear entry beyond +-2^16 or a translation beyond
+ *    +-2^24 gives MI NaN, overlap 0, gradient 0.
+ *
+ * Definitions (the paper prints only Eq. (1)-(3); these are the readings
+ * the library implements, identical in the CPU oracle used to test it):
+ *  - Transform: an index-space 3x4 matrix M, row-major, mapping fixed voxel
+ *    index (i, j, k, 1) to a continuous moving voxel index.  M is quantised
+ *    to signed Q32 fixed point, Mq = round-half-even(M * 2^32); coordinates
+ *    are the exact int64 products Mq * (i, j, k, 1).
+ *  - Overlap: MI_BOUNDARY_EXCLUDE keeps a fixed voxel iff every moving
+ *    coordinate lies in [0, n - 1] (closed); MI_BOUNDARY_CLAMP clamps the
+ *    coordinate to that interval and keeps every fixed voxel.
+ *  - Intensities are clamped to the volume's [lo, hi] before use.
+ *  - Hard histogram: trilinear interpolation with 16-bit truncated weights
+ *    w = floor(frac * 2^16), exact integer sum V = sum v' * w_x w_y w_z over
+ *    the 8 corners (v' = clamped value - lo); moving bin
+ *    floor(V * B / (R * 2^48)), R = hi - lo + 1; fixed bin
+ *    floor((u' * B) / R) for integer dtypes, min(B-1, floor(((u-lo)/(hi-lo))
+ *    * B)) in fp64 for MI_F32.  Counts are exact; the histogram is unique.
+ *  - Entropies in nats.  Shannon H = -sum p ln p.  Tsallis
+ *    S_q = (1 - sum p^q)/(q - 1).  MI = H(F) + H(M) - H(F,M) (Eq. (2));
+ *    Tsallis MI additive S_q(F) + S_q(M) - S_q(F,M), or with
+ *    MI_TSALLIS_PSEUDOADDITIVE the extra term (1 - q) S_q(F) S_q(M).
+ *    q == 1 means Shannon.  Reduced in fp64 with compensated sums.
+ *  - Parzen histogram: fixed side hard-binned; moving side weighted by the
+ *    centred cubic B-spline at s = 1 + (v - lo)/(hi - lo) * (B - 4), v the
+ *    trilinear value with full-precision weights; p = table / N with N the
+ *    number of fixed voxels that take part.
+ */
+#ifndef GEMI_H
+#define GEMI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define MI_OK 0
+#define MI_ERR_NULL (-1)        /* a required pointer is NULL             */
+#define MI_ERR_DIMS (-2)        /* a volume edge outside [2, 4096] or too many bytes */
+#define MI_ERR_DTYPE (-3)       /* unknown dtype, or MI_F32 moving volume on the hard path */
+#define MI_ERR_BINS (-4)        /* bins outside [2, 256] ([8, 256] for Parzen) */
+#define MI_ERR_RANGE (-5)       /* lo/hi not finite, hi <= lo, or (integer dtypes) not
+                                   integral, |lo|,|hi| > 2^31, or hi - lo + 1 > 65536 */
+#define MI_ERR_Q (-6)           /* n_q outside [1, 16], or a q not finite or <= 0 */
+#define MI_ERR_WORKSPACE (-7)   /* workspace NULL or smaller than mi_workspace_size() */
+#define MI_ERR_UNSUPPORTED (-8) /* a valid request this build does not serve */
+#define MI_ERR_FLAGS (-9)       /* unknown flag bits */
+#define MI_ERR_COUNT (-10)      /* n_transforms (or n_pairs) negative or above 2^24 */
+#define MI_ERR_HIP (-20)        /* the HIP runtime reported an error (see mi_status_string) */
+#define MI_ERR_NO_DEVICE (-21)  /* no usable GPU with the requested index */
+
+/* ---- volume element types ---------------------------------------------- */
+#define MI_U8 0
+#define MI_U16 1
+#define MI_I16 2
+#define MI_F32 3
+
+/* ---- flags (bitwise OR) ------------------------------------------------ */
+#define MI_BOUNDARY_EXCLUDE 0x000
+#define MI_BOUNDARY_CLAMP 0x001
+#define MI_TSALLIS_ADDITIVE 0x000
+#define MI_TSALLIS_PSEUDOADDITIVE 0x010
+#define MI_HIST_HARD 0x000
+#define MI_HIST_PARZEN 0x100
+
+#define MI_MAX_Q 16
+#define MI_MAX_EDGE 4096
+
+/* A volume: tightly packed C-order [nz][ny][nx] (x fastest) on the device. */
+typedef struct mi_volume {
+  const void *data; /* device pointer, nx*ny*nz elements of `dtype`        */
+  int32_t nx, ny, nz; /* each in [2, 4096]; nx*ny*nz*sizeof(dtype) < 2^32 */
+  int32_t dtype;      /* MI_U8, MI_U16, MI_I16 or MI_F32                   */
+  double lo, hi;      /* intensity range mapped onto the bins              */
+} mi_volume;
+
+/* Opaque per-device state: device properties, tuning choices, timers. */
+typedef struct mi_context mi_context;
+
+/* Creates a context on HIP device `device` (made current for the call).
+ * *out receives the context.  MI_ERR_NO_DEVICE if the device does not exist
+ * or is not a gfx950 GPU. */
+int mi_create(mi_context **out, int device);
+
+/* Destroys a context (NULL is accepted).  Waits for nothing: the caller
+ * must have synchronised any stream still using the context. */
+int mi_destroy(mi_context *ctx);
+
+/* Bytes of device workspace that mi_eval (hard or Parzen, per `flags`) or,
+ * with `for_grad` != 0, mi_grad needs for these arguments.  Host-only; no
+ * GPU is touched.  Validates like the call it sizes. */
+int mi_workspace_size(const mi_volume *fixed, const mi_volume *moving, int32_t n_transforms,
+                      int32_t bins, int32_t n_q, int32_t flags, int32_t for_grad, size_t *bytes);
+
+/* MI of `n_transforms` candidate transforms (Fig. 1 Transform + Metric;
+ * Eq. (1), Eq. (2); one histogram, every q).
+ *   transforms  device double[n][12], row-major index-space 3x4 matrices
+ *   bins        histogram bins per axis, 2..256
+ *   q, n_q      HOST double[n_q] entropic indices (1.0 = Shannon), n_q <= 16
+ *   flags       boundary | tsallis form | MI_HIST_HARD or MI_HIST_PARZEN
+ *   mi_out      device double[n][n_q]
+ *   overlap_out device uint64[n] voxels that took part, or NULL
+ *   hist_out    device uint32[n][bins][bins] joint counts (row = fixed bin),
+ *               or NULL; hard histograms only (NULL required with Parzen)
+ * The hard path needs an integer moving dtype (MI_U8, MI_U16, MI_I16). */
+int mi_eval(mi_context *ctx, const mi_volume *fixed, const mi_volume *moving,
+            const double *transforms, int32_t n_transforms, int32_t bins, const double *q,
+            int32_t n_q, int32_t flags, double *mi_out, uint64_t *overlap_out,
+            uint32_t *hist_out, void *workspace, size_t workspace_bytes, void *stream);
+
+/* Parzen MI and its gradient with respect to the 12 entries of each
+ * index-space matrix (what a gradient optimiser of Eq. (3) consumes).
+ *   mi_out    device double[n][n_q]
+ *   grad_out  device double[n][n_q][12], d MI / d M[r][c] at index r*4+c
+ * `flags` selects boundary and Tsallis form; the histogram is always the
+ * Parzen one (MI_HIST_PARZEN may be given or not).  The gradient holds the
+ * set of overlapping voxels fixed (exact for MI_BOUNDARY_CLAMP). */
+int mi_grad(mi_context *ctx, const mi_volume *fixed, const mi_volume *moving,
+            const double *transforms, int32_t n_transforms, int32_t bins, const double *q,
+            int32_t n_q, int32_t flags, double *mi_out, double *grad_out, void *workspace,
+            size_t workspace_bytes, void *stream);
+
+/* One fixed/moving pair and its own transforms (device double[n][12]). */
+typedef struct mi_pair {
+  mi_volume fixed, moving;
+  const double *transforms;
+  int32_t n_transforms;
+} mi_pair;
+
+/* Hard-binned MI of many volume pairs of uneven sizes in one persistent
+ * launch.  `pairs` is a HOST array; mi_out is device double[sum n][n_q],
+ * pairs' rows concatenated in order.  Every pair uses `bins`, `q`, `flags`.
+ * Workspace: mi_pairs_workspace_size(). */
+int mi_pairs_workspace_size(const mi_pair *pairs, int32_t n_pairs, int32_t bins, int32_t n_q,
+                            int32_t flags, size_t *bytes);
+int mi_eval_pairs(mi_context *ctx, const mi_pair *pairs, int32_t n_pairs, int32_t bins,
+                  const double *q, int32_t n_q, int32_t flags, double *mi_out, void *workspace,
+                  size_t workspace_bytes, void *stream);
+
+/* Kernel timing.  While enabled, the library brackets every launch of its
+ * histogram kernels with HIP events on the caller's stream.
+ * mi_timing_read() synchronises on those events and returns the summed
+ * duration (ms) and number of launches of kernel `which`
+ * (0 = hard histogram, 1 = Parzen forward, 2 = Parzen backward,
+ * 3 = pairs histogram, 4 = MI reduction), then clears that record. */
+int mi_timing_enable(mi_context *ctx, int enable);
+int mi_timing_read(mi_context *ctx, int which, double *total_ms, int64_t *launches);
+
+/* Static description of a status code (never NULL).  For MI_ERR_HIP the
+ * text of the last HIP error seen by this thread is appended. */
+const char *mi_status_string(int status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GEMI_H */

@@ -1,16 +1,8 @@
 """MI355X-native generalised-entropy mutual-information metric (arXiv 1909.10690).
 
-``binding`` wraps the C-ABI library ``libgemi.so`` (hand-written HIP for
-gfx950); ``inputs`` and ``transforms`` build seeded synthetic workloads.
-The binding is imported lazily so that the input generators can be used on
-machines without the built library.
+Submodules: ``binding`` wraps the C-ABI library ``libgemi.so`` (hand-written
+HIP for gfx950); ``autograd`` exposes the gradient as a torch autograd
+Function; ``inputs`` and ``transforms`` build seeded synthetic workloads.
+Nothing is imported eagerly, so the input generators work on machines
+without the built library or a GPU.
 """
-
-__all__ = ["binding", "inputs", "transforms"]
-
-
-def __getattr__(name):
-    if name == "binding":
-        from . import binding
-        return binding
-    raise AttributeError(name)

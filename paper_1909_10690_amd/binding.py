@@ -1,0 +1,250 @@
+"""Python binding of libgemi.so (include/gemi.h): argument marshalling only.
+
+Torch tensors provide device memory and the current HIP stream; every step
+of the metric runs in the library's HIP kernels.  There is no fallback: if
+the library is not built, or no gfx950 device is present, calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgemi.so")
+
+# status codes, dtypes and flags (mirror include/gemi.h)
+MI_OK = 0
+MI_ERR_NULL, MI_ERR_DIMS, MI_ERR_DTYPE, MI_ERR_BINS, MI_ERR_RANGE = -1, -2, -3, -4, -5
+MI_ERR_Q, MI_ERR_WORKSPACE, MI_ERR_UNSUPPORTED, MI_ERR_FLAGS, MI_ERR_COUNT = -6, -7, -8, -9, -10
+MI_ERR_HIP, MI_ERR_NO_DEVICE = -20, -21
+U8, U16, I16, F32 = 0, 1, 2, 3
+BOUNDARY_EXCLUDE, BOUNDARY_CLAMP = 0x0, 0x1
+TSALLIS_ADDITIVE, TSALLIS_PSEUDOADDITIVE = 0x0, 0x10
+HIST_HARD, HIST_PARZEN = 0x0, 0x100
+TIMER_HARD, TIMER_PARZEN_FWD, TIMER_PARZEN_BWD, TIMER_PAIRS, TIMER_REDUCE = 0, 1, 2, 3, 4
+
+_TORCH_DTYPES = {torch.uint8: U8, torch.uint16: U16, torch.int16: I16, torch.float32: F32}
+
+
+class GemiError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__(f"{where}: status {status}: {status_string(status)}")
+
+
+class MiVolume(ctypes.Structure):
+    _fields_ = [("data", ctypes.c_void_p), ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+                ("nz", ctypes.c_int32), ("dtype", ctypes.c_int32), ("lo", ctypes.c_double),
+                ("hi", ctypes.c_double)]
+
+
+class MiPair(ctypes.Structure):
+    _fields_ = [("fixed", MiVolume), ("moving", MiVolume), ("transforms", ctypes.c_void_p),
+                ("n_transforms", ctypes.c_int32)]
+
+
+EXPORTS = ["mi_create", "mi_destroy", "mi_workspace_size", "mi_eval", "mi_grad",
+           "mi_pairs_workspace_size", "mi_eval_pairs", "mi_timing_enable", "mi_timing_read",
+           "mi_status_string"]
+
+_lib = None
+
+
+def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Loads libgemi.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with __graft_entry__.build()")
+    lib = ctypes.CDLL(path)
+    P, vp, sz = ctypes.POINTER, ctypes.c_void_p, ctypes.c_size_t
+    i32, dp = ctypes.c_int32, P(ctypes.c_double)
+    lib.mi_create.argtypes = [P(vp), ctypes.c_int]
+    lib.mi_destroy.argtypes = [vp]
+    lib.mi_workspace_size.argtypes = [P(MiVolume), P(MiVolume), i32, i32, i32, i32, i32, P(sz)]
+    lib.mi_eval.argtypes = [vp, P(MiVolume), P(MiVolume), vp, i32, i32, dp, i32, i32, vp, vp, vp,
+                            vp, sz, vp]
+    lib.mi_grad.argtypes = [vp, P(MiVolume), P(MiVolume), vp, i32, i32, dp, i32, i32, vp, vp, vp,
+                            sz, vp]
+    lib.mi_pairs_workspace_size.argtypes = [P(MiPair), i32, i32, i32, i32, P(sz)]
+    lib.mi_eval_pairs.argtypes = [vp, P(MiPair), i32, i32, dp, i32, i32, vp, vp, sz, vp]
+    lib.mi_timing_enable.argtypes = [vp, ctypes.c_int]
+    lib.mi_timing_read.argtypes = [vp, ctypes.c_int, dp, P(ctypes.c_int64)]
+    lib.mi_status_string.argtypes = [ctypes.c_int]
+    lib.mi_status_string.restype = ctypes.c_char_p
+    for name in EXPORTS:
+        if name != "mi_status_string":
+            getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def status_string(status: int) -> str:
+    return load().mi_status_string(int(status)).decode()
+
+
+def _check(status: int, where: str) -> None:
+    if status != MI_OK:
+        raise GemiError(status, where)
+
+
+def _ptr(t) -> int | None:
+    return None if t is None else t.data_ptr()
+
+
+class Volume:
+    """A device volume [nz][ny][nx] with the intensity range mapped onto bins."""
+
+    def __init__(self, tensor: torch.Tensor, lo: float, hi: float):
+        if tensor.dim() != 3:
+            raise ValueError("volume must be 3-D [nz][ny][nx]")
+        if tensor.dtype not in _TORCH_DTYPES:
+            raise ValueError(f"unsupported dtype {tensor.dtype}")
+        self.tensor = tensor.contiguous()
+        self.lo, self.hi = float(lo), float(hi)
+
+    @classmethod
+    def from_numpy(cls, arr: np.ndarray, lo: float, hi: float, device="cuda") -> "Volume":
+        t = torch.from_numpy(np.ascontiguousarray(arr))
+        return cls(t.to(device), lo, hi)
+
+    def c(self) -> MiVolume:
+        nz, ny, nx = self.tensor.shape
+        return MiVolume(self.tensor.data_ptr(), nx, ny, nz, _TORCH_DTYPES[self.tensor.dtype],
+                        self.lo, self.hi)
+
+
+def _qarr(q) -> tuple:
+    qs = np.ascontiguousarray(np.atleast_1d(np.asarray(q, dtype=np.float64)))
+    return qs, qs.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def flags_of(boundary: str = "exclude", tsallis: str = "additive", parzen: bool = False) -> int:
+    f = {"exclude": BOUNDARY_EXCLUDE, "clamp": BOUNDARY_CLAMP}[boundary]
+    f |= {"additive": TSALLIS_ADDITIVE, "pseudoadditive": TSALLIS_PSEUDOADDITIVE}[tsallis]
+    if parzen:
+        f |= HIST_PARZEN
+    return f
+
+
+class Context:
+    """A libgemi context on one HIP device."""
+
+    def __init__(self, device: int = 0):
+        self.lib = load()
+        self.device = device
+        h = ctypes.c_void_p()
+        _check(self.lib.mi_create(ctypes.byref(h), device), "mi_create")
+        self.handle = h
+        self._ws = None
+
+    def close(self) -> None:
+        if self.handle:
+            self.lib.mi_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _stream(self, stream) -> int:
+        s = torch.cuda.current_stream(self.device) if stream is None else stream
+        return s.cuda_stream
+
+    def workspace(self, nbytes: int) -> torch.Tensor:
+        """A cached device workspace of at least ``nbytes`` bytes."""
+        if self._ws is None or self._ws.numel() < nbytes:
+            self._ws = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=f"cuda:{self.device}")
+        return self._ws
+
+    def workspace_size(self, fixed: Volume, moving: Volume, n: int, bins: int, n_q: int,
+                       flags: int = 0, for_grad: bool = False) -> int:
+        out = ctypes.c_size_t()
+        f, m = fixed.c(), moving.c()
+        _check(self.lib.mi_workspace_size(ctypes.byref(f), ctypes.byref(m), n, bins, n_q, flags,
+                                          int(for_grad), ctypes.byref(out)), "mi_workspace_size")
+        return out.value
+
+    def eval(self, fixed: Volume, moving: Volume, transforms: torch.Tensor, bins: int, q=(1.0,),
+             flags: int = 0, want_hist: bool = False, want_overlap: bool = True, out=None,
+             workspace: torch.Tensor | None = None, stream=None):
+        """MI[n][n_q] (+ overlap[n], hist[n][bins][bins]) of n transforms."""
+        dev = fixed.tensor.device
+        transforms = transforms.to(device=dev, dtype=torch.float64).reshape(-1, 12).contiguous()
+        n = transforms.shape[0]
+        qs, qp = _qarr(q)
+        mi = out if out is not None else torch.empty((n, len(qs)), dtype=torch.float64, device=dev)
+        ov = torch.empty(n, dtype=torch.int64, device=dev) if want_overlap else None
+        hist = torch.empty((n, bins, bins), dtype=torch.int32, device=dev) if want_hist else None
+        if workspace is None:
+            workspace = self.workspace(self.workspace_size(fixed, moving, n, bins, len(qs), flags))
+        f, m = fixed.c(), moving.c()
+        st = self.lib.mi_eval(self.handle, ctypes.byref(f), ctypes.byref(m), _ptr(transforms), n,
+                              bins, qp, len(qs), flags, _ptr(mi), _ptr(ov), _ptr(hist),
+                              _ptr(workspace), workspace.numel(), self._stream(stream))
+        _check(st, "mi_eval")
+        return mi, ov, hist
+
+    def grad(self, fixed: Volume, moving: Volume, transforms: torch.Tensor, bins: int, q=(1.0,),
+             flags: int = BOUNDARY_CLAMP, workspace: torch.Tensor | None = None, stream=None):
+        """Parzen MI[n][n_q] and dMI/dM[n][n_q][12]."""
+        dev = fixed.tensor.device
+        transforms = transforms.to(device=dev, dtype=torch.float64).reshape(-1, 12).contiguous()
+        n = transforms.shape[0]
+        qs, qp = _qarr(q)
+        mi = torch.empty((n, len(qs)), dtype=torch.float64, device=dev)
+        g = torch.empty((n, len(qs), 12), dtype=torch.float64, device=dev)
+        if workspace is None:
+            workspace = self.workspace(self.workspace_size(fixed, moving, n, bins, len(qs), flags | HIST_PARZEN, True))
+        f, m = fixed.c(), moving.c()
+        st = self.lib.mi_grad(self.handle, ctypes.byref(f), ctypes.byref(m), _ptr(transforms), n,
+                              bins, qp, len(qs), flags, _ptr(mi), _ptr(g), _ptr(workspace),
+                              workspace.numel(), self._stream(stream))
+        _check(st, "mi_grad")
+        return mi, g
+
+    def eval_pairs(self, pairs, bins: int, q=(1.0,), flags: int = 0,
+                   workspace: torch.Tensor | None = None, stream=None):
+        """Hard MI of many (fixed, moving, transforms) pairs in one launch;
+        returns MI[sum n][n_q] with the pairs' rows concatenated."""
+        qs, qp = _qarr(q)
+        arr = (MiPair * len(pairs))()
+        total = 0
+        keep = []
+        dev = None
+        for i, (fv, mv, tr) in enumerate(pairs):
+            tr = tr.to(device=fv.tensor.device, dtype=torch.float64).reshape(-1, 12).contiguous()
+            keep.append(tr)
+            dev = fv.tensor.device
+            arr[i].fixed = fv.c()
+            arr[i].moving = mv.c()
+            arr[i].transforms = tr.data_ptr()
+            arr[i].n_transforms = tr.shape[0]
+            total += tr.shape[0]
+        mi = torch.empty((total, len(qs)), dtype=torch.float64, device=dev)
+        if workspace is None:
+            nb = ctypes.c_size_t()
+            _check(self.lib.mi_pairs_workspace_size(arr, len(pairs), bins, len(qs), flags,
+                                                    ctypes.byref(nb)), "mi_pairs_workspace_size")
+            workspace = self.workspace(nb.value)
+        st = self.lib.mi_eval_pairs(self.handle, arr, len(pairs), bins, qp, len(qs), flags,
+                                    _ptr(mi), _ptr(workspace), workspace.numel(),
+                                    self._stream(stream))
+        _check(st, "mi_eval_pairs")
+        return mi
+
+    def timing(self, enable: bool) -> None:
+        _check(self.lib.mi_timing_enable(self.handle, int(enable)), "mi_timing_enable")
+
+    def timing_read(self, which: int) -> tuple[float, int]:
+        ms = ctypes.c_double()
+        n = ctypes.c_int64()
+        _check(self.lib.mi_timing_read(self.handle, which, ctypes.byref(ms), ctypes.byref(n)),
+               "mi_timing_read")
+        return ms.value, n.value

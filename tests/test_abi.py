@@ -1,0 +1,153 @@
+"""CPU tests of the C ABI boundary: the library loads, exports every entry
+point include/gemi.h declares, and rejects invalid arguments with the
+documented status before touching a GPU (no device is needed)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1909_10690_amd import binding as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "gemi.h")
+
+FAKE = 0x10000  # a non-NULL address that validation must never dereference
+
+
+def header_functions():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^(?:int|const char \*)\s*(mi_\w+)\(", text, re.M)))
+
+
+def test_header_declares_expected_entry_points():
+    assert header_functions() == sorted(B.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = B.load()
+    for name in header_functions():
+        assert hasattr(lib, name), name
+
+
+def test_header_constants_match_binding():
+    text = open(HEADER).read()
+    consts = dict((k, int(v, 0)) for k, v in re.findall(r"#define (MI_\w+) \(?(-?\w+)\)?", text))
+    assert consts["MI_ERR_NULL"] == B.MI_ERR_NULL and consts["MI_ERR_HIP"] == B.MI_ERR_HIP
+    assert consts["MI_ERR_COUNT"] == B.MI_ERR_COUNT and consts["MI_ERR_NO_DEVICE"] == B.MI_ERR_NO_DEVICE
+    assert consts["MI_HIST_PARZEN"] == B.HIST_PARZEN and consts["MI_BOUNDARY_CLAMP"] == B.BOUNDARY_CLAMP
+    assert consts["MI_TSALLIS_PSEUDOADDITIVE"] == B.TSALLIS_PSEUDOADDITIVE
+    assert ctypes.sizeof(B.MiVolume) == 40
+
+
+def test_status_strings():
+    for s in [0, -1, -2, -3, -4, -5, -6, -7, -8, -9, -10, -20, -21, 12345]:
+        assert isinstance(B.status_string(s), str) and B.status_string(s)
+    assert B.status_string(0) == "ok"
+
+
+def vol(nx=8, ny=8, nz=8, dtype=B.U8, lo=0.0, hi=255.0, data=FAKE):
+    return B.MiVolume(data, nx, ny, nz, dtype, lo, hi)
+
+
+def call_eval(f, m, n=4, bins=32, q=(1.0,), flags=0, transforms=FAKE, mi=FAKE, ws=FAKE,
+              ws_bytes=1 << 40, hist=None, ctx=None):
+    lib = B.load()
+    qs = np.asarray(q, dtype=np.float64) if q is not None else None
+    qp = qs.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if q is not None else None
+    return lib.mi_eval(ctx, ctypes.byref(f), ctypes.byref(m), transforms, n, bins, qp,
+                       0 if q is None else len(qs), flags, mi, None, hist, ws, ws_bytes, None)
+
+
+def test_valid_arguments_reach_the_context_check():
+    # everything valid but the context: MI_ERR_NULL, nothing launched
+    assert call_eval(vol(), vol()) == B.MI_ERR_NULL
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(nx=1), B.MI_ERR_DIMS), (dict(ny=4097), B.MI_ERR_DIMS), (dict(nz=0), B.MI_ERR_DIMS),
+    (dict(nx=4096, ny=4096, nz=300), B.MI_ERR_DIMS),
+    (dict(dtype=7), B.MI_ERR_DTYPE), (dict(dtype=-1), B.MI_ERR_DTYPE),
+    (dict(lo=5.0, hi=5.0), B.MI_ERR_RANGE), (dict(lo=0.5), B.MI_ERR_RANGE),
+    (dict(hi=float("nan")), B.MI_ERR_RANGE), (dict(lo=0.0, hi=65536.0), B.MI_ERR_RANGE),
+    (dict(data=None), B.MI_ERR_NULL),
+])
+def test_volume_validation(kw, status):
+    assert call_eval(vol(**kw), vol()) == status
+    assert call_eval(vol(), vol(**kw)) == status
+
+
+def test_float_moving_needs_parzen():
+    assert call_eval(vol(), vol(dtype=B.F32, lo=0.0, hi=1.0)) == B.MI_ERR_DTYPE
+    assert call_eval(vol(dtype=B.F32, lo=0.0, hi=1.0), vol()) == B.MI_ERR_NULL  # fixed f32 is fine
+    assert call_eval(vol(), vol(dtype=B.F32, lo=0.0, hi=0.5), flags=B.HIST_PARZEN) == B.MI_ERR_NULL
+
+
+def test_full_u16_range_is_valid():
+    assert call_eval(vol(dtype=B.U16, lo=0.0, hi=65535.0), vol(dtype=B.I16, lo=-32768.0, hi=32767.0)) == B.MI_ERR_NULL
+
+
+@pytest.mark.parametrize("bins,flags,status", [
+    (1, 0, B.MI_ERR_BINS), (257, 0, B.MI_ERR_BINS), (2, 0, B.MI_ERR_NULL), (256, 0, B.MI_ERR_NULL),
+    (7, B.HIST_PARZEN, B.MI_ERR_BINS), (8, B.HIST_PARZEN, B.MI_ERR_NULL),
+])
+def test_bins_validation(bins, flags, status):
+    assert call_eval(vol(), vol(), bins=bins, flags=flags) == status
+
+
+@pytest.mark.parametrize("q,status", [
+    ((), B.MI_ERR_Q), ((0.0,), B.MI_ERR_Q), ((-1.0,), B.MI_ERR_Q), ((float("nan"),), B.MI_ERR_Q),
+    ((float("inf"),), B.MI_ERR_Q), (tuple([1.0] * 17), B.MI_ERR_Q), (tuple([1.5] * 16), B.MI_ERR_NULL),
+])
+def test_q_validation(q, status):
+    assert call_eval(vol(), vol(), q=q) == status
+
+
+def test_q_null():
+    assert call_eval(vol(), vol(), q=None) == B.MI_ERR_Q
+
+
+def test_flags_count_pointers_workspace():
+    assert call_eval(vol(), vol(), flags=0x2) == B.MI_ERR_FLAGS
+    assert call_eval(vol(), vol(), n=-1) == B.MI_ERR_COUNT
+    assert call_eval(vol(), vol(), n=(1 << 24) + 1) == B.MI_ERR_COUNT
+    assert call_eval(vol(), vol(), transforms=None) == B.MI_ERR_NULL
+    assert call_eval(vol(), vol(), ws=None) == B.MI_ERR_WORKSPACE
+    assert call_eval(vol(), vol(), ws_bytes=100) == B.MI_ERR_WORKSPACE
+    assert call_eval(vol(), vol(), hist=FAKE, flags=B.HIST_PARZEN) == B.MI_ERR_UNSUPPORTED
+
+
+def ws_size(f, m, n, bins, n_q, flags=0, grad=0):
+    out = ctypes.c_size_t()
+    st = B.load().mi_workspace_size(ctypes.byref(f), ctypes.byref(m), n, bins, n_q, flags, grad,
+                                    ctypes.byref(out))
+    return st, out.value
+
+
+def test_workspace_size_layout():
+    a = lambda x: (x + 255) // 256 * 256
+    st, n = ws_size(vol(10, 11, 12), vol(), 5, 32, 2)
+    assert st == 0 and n == a(10 * 11 * 12) + a(5 * 32 * 32 * 4)
+    st, n = ws_size(vol(10, 11, 12), vol(), 5, 32, 2, B.HIST_PARZEN)
+    assert st == 0 and n == a(1320) + a(5 * 32 * 32 * 8) + a(5 * 8)
+    st, n = ws_size(vol(10, 11, 12), vol(), 5, 32, 2, 0, 1)
+    assert st == 0 and n == a(1320) + a(5 * 32 * 32 * 8) + a(5 * 8) + a(5 * 2 * 32 * 32 * 4)
+    assert ws_size(vol(), vol(), 5, 1, 1)[0] == B.MI_ERR_BINS
+    assert ws_size(vol(), vol(), 5, 32, 0)[0] == B.MI_ERR_Q
+
+
+def test_create_without_gpu_reports_no_device():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    h = ctypes.c_void_p()
+    assert B.load().mi_create(ctypes.byref(h), 0) == B.MI_ERR_NO_DEVICE
+    assert B.load().mi_destroy(None) == 0
+
+
+def test_timing_and_pairs_null_checks():
+    lib = B.load()
+    assert lib.mi_timing_enable(None, 1) == B.MI_ERR_NULL
+    ms, n = ctypes.c_double(), ctypes.c_int64()
+    assert lib.mi_timing_read(None, 0, ctypes.byref(ms), ctypes.byref(n)) == B.MI_ERR_NULL

@@ -1,0 +1,186 @@
+"""GPU parity of the hard-binned path (mi_eval through the C ABI) against
+the CPU oracle: joint histograms bit-exact, overlap counts exact, MI within
+1e-12 * max(1, |MI|) for Shannon and every Tsallis q."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1909_10690_amd import inputs
+from paper_1909_10690_amd import transforms as T
+
+pytestmark = pytest.mark.gpu
+
+MI_TOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    from paper_1909_10690_amd import binding as B
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    c = B.Context(0)
+    yield c
+    c.close()
+
+
+def run_gpu(ctx, fixed, moving, frange, mrange, mats, bins, q, flags=0):
+    import torch
+    from paper_1909_10690_amd import binding as B
+    F = B.Volume.from_numpy(fixed, *frange)
+    Mv = B.Volume.from_numpy(moving, *mrange)
+    tr = torch.from_numpy(np.ascontiguousarray(np.asarray(mats, dtype=np.float64).reshape(-1, 12))).cuda()
+    mi, ov, hist = ctx.eval(F, Mv, tr, bins, q, flags=flags, want_hist=True)
+    torch.cuda.synchronize()
+    return mi.cpu().numpy(), ov.cpu().numpy(), hist.cpu().numpy().astype(np.uint32)
+
+
+def run_oracle(fixed, moving, frange, mrange, mats, bins, q, flags=0):
+    F = oracle.volume(fixed, *frange)
+    Mv = oracle.volume(moving, *mrange)
+    return oracle.eval_hard(F, Mv, mats, bins, q, boundary=flags & 1,
+                            form=oracle.PSEUDOADDITIVE if flags & 0x10 else oracle.ADDITIVE,
+                            want_hist=True)
+
+
+def assert_parity(g, o, label=""):
+    gmi, gov, gh = g
+    omi, oov, oh = o
+    assert np.array_equal(gov.astype(np.int64), oov), label
+    for t in range(len(oov)):
+        assert np.array_equal(gh[t], oh[t]), f"{label} histogram of transform {t}"
+    nan = np.isnan(omi)
+    assert np.array_equal(np.isnan(gmi), nan), label
+    err = np.abs(gmi[~nan] - omi[~nan]) / np.maximum(1.0, np.abs(omi[~nan]))
+    assert err.size == 0 or err.max() <= MI_TOL, f"{label} max rel err {err.max()}"
+
+
+@pytest.mark.parametrize("flags", [0, 1, 0x10])
+def test_plain_translation_sweep(ctx, flags):
+    c = inputs.plain_translation()
+    q = [1.0, 0.5, 2.0, 1.3]
+    args = (c["fixed"], c["moving"], c["fixed_range"], c["moving_range"], c["transforms"], c["bins"], q, flags)
+    g = run_gpu(ctx, *args)
+    o = run_oracle(*args)
+    assert_parity(g, o, f"flags={flags}")
+    assert int(np.argmax(g[0][:, 0])) - 10 in (3, 4)
+
+
+CASES = [
+    # dtype fixed, dtype moving, shape fixed (nx,ny,nz), shape moving, frange, mrange, bins
+    (np.uint8, np.uint8, (67, 45, 33), (61, 50, 29), (0, 255), (0, 255), 32),
+    (np.uint16, np.uint16, (40, 36, 30), (44, 30, 33), (0, 4095), (0, 4095), 128),
+    (np.int16, np.int16, (33, 35, 31), (30, 40, 32), (-1000, 1500), (-1000, 1500), 100),
+    (np.uint16, np.uint8, (50, 17, 9), (70, 13, 21), (0, 65535), (0, 255), 7),
+    (np.uint8, np.uint16, (31, 29, 27), (32, 28, 26), (10, 200), (0, 65535), 256),
+    (np.int16, np.uint16, (64, 20, 10), (65, 21, 11), (-32768, 32767), (300, 2999), 129),
+    (np.float32, np.int16, (37, 21, 19), (36, 22, 18), (0.0, 1.0), (-200, 200), 200),
+    (np.uint8, np.uint8, (2, 2, 2), (2, 2, 2), (0, 255), (0, 255), 2),
+    (np.uint8, np.uint8, (130, 3, 2), (129, 2, 3), (0, 255), (0, 255), 64),
+]
+
+
+def _random_case(case, seed):
+    fd, md, fs, ms, fr, mr, bins = CASES[case]
+    rng = np.random.default_rng(1000 + 17 * case + seed)
+
+    def vol(dtype, shape, r):
+        if np.dtype(dtype).kind == "f":
+            return inputs.random_volume(rng, shape, dtype, -0.2, 1.2)
+        info = np.iinfo(dtype)
+        return inputs.random_volume(rng, shape, dtype, max(info.min, int(r[0]) - 50), min(info.max, int(r[1]) + 50))
+
+    fixed, moving = vol(fd, fs, fr), vol(md, ms, mr)
+    mats = [T.translation((0, 0, 0)), T.translation((1, -1, 0)), T.translation((0.5, 0.25, -0.75))]
+    for _ in range(13):
+        A = T.affine_matrix(rng.uniform(-40, 40, 3), rng.uniform(0.7, 1.3, 3), rng.uniform(-0.2, 0.2, 3))
+        mats.append(T.index_matrix(A, rng.uniform(-6, 6, 3), fs))
+    return fixed, moving, fr, mr, np.stack(mats).reshape(-1, 12), bins
+
+
+@pytest.mark.parametrize("case", range(len(CASES)))
+@pytest.mark.parametrize("flags", [0, 1])
+def test_random_affines(ctx, case, flags):
+    fixed, moving, fr, mr, mats, bins = _random_case(case, flags)
+    q = [1.0, 0.5, 0.8, 1.2, 1.5, 2.0]
+    assert_parity(run_gpu(ctx, fixed, moving, fr, mr, mats, bins, q, flags),
+                  run_oracle(fixed, moving, fr, mr, mats, bins, q, flags), f"case {case}")
+
+
+def test_integer_translations_tiny(ctx):
+    import itertools
+    rng = np.random.default_rng(5)
+    fixed = inputs.random_volume(rng, (4, 4, 4), np.uint16, 0, 4095)
+    moving = inputs.random_volume(rng, (4, 4, 4), np.uint16, 0, 4095)
+    mats = np.stack([T.translation(t) for t in itertools.product(range(-4, 5), repeat=3)]).reshape(-1, 12)
+    args = (fixed, moving, (0, 4095), (100, 3000), mats, 8, [1.0, 2.0])
+    assert_parity(run_gpu(ctx, *args), run_oracle(*args), "4^3 translations")
+
+
+def test_degenerate_transforms(ctx):
+    rng = np.random.default_rng(6)
+    fixed = inputs.random_volume(rng, (20, 18, 16), np.uint8, 0, 255)
+    moving = inputs.random_volume(rng, (21, 17, 15), np.uint8, 0, 255)
+    mats = [T.translation((0, 0, 0)), T.translation((np.nan, 0, 0)), T.translation((1000, 0, 0)),
+            T.translation((2 ** 24 + 1, 0, 0)), T.translation((-21, 0, 0)), T.translation((20, 16, 14)),
+            np.array([[70000.0, 0, 0, 0], [0, 1, 0, 0], [0, 0, 1, 0]]), np.zeros((3, 4)),
+            T.translation((np.inf, 0, 0))]
+    mats = np.stack(mats).reshape(-1, 12)
+    for flags in (0, 1):
+        args = (fixed, moving, (0, 255), (0, 255), mats, 16, [1.0, 0.7], flags)
+        g, o = run_gpu(ctx, *args), run_oracle(*args)
+        assert_parity(g, o, f"degenerate flags={flags}")
+        assert np.all(np.isnan(g[0][[1, 3, 6, 8]]))
+        if flags == 0:
+            assert g[1][2] == 0 and np.all(g[0][2] == 0)
+
+
+def test_no_transforms(ctx):
+    import torch
+    from paper_1909_10690_amd import binding as B
+    v = B.Volume(torch.zeros((4, 4, 4), dtype=torch.uint8, device="cuda"), 0, 255)
+    mi, ov, _ = ctx.eval(v, v, torch.zeros((0, 12), dtype=torch.float64, device="cuda"), 8, [1.0])
+    assert mi.shape == (0, 1)
+
+
+def test_deterministic_and_self_information(ctx):
+    from scipy.stats import entropy
+    c = inputs.multimodal_sweep(shape_xyz=(96, 80, 40), n_tx=3, n_rot=3, n_scale=3)
+    args = (c["fixed"], c["moving"], c["fixed_range"], c["moving_range"], c["transforms"], c["bins"], c["q"])
+    a, b = run_gpu(ctx, *args), run_gpu(ctx, *args)
+    assert np.array_equal(a[2], b[2]) and np.array_equal(a[0], b[0])
+    ident = T.translation((0, 0, 0))
+    g = run_gpu(ctx, c["fixed"], c["fixed"], (0, 4095), (0, 4095), ident, 128, [1.0])
+    counts = np.bincount((c["fixed"].ravel().astype(np.int64) * 128) // 4096, minlength=128)
+    assert abs(g[0][0, 0] - entropy(counts.astype(float))) <= 1e-12 * 5
+
+
+def test_multimodal_sweep_full_size_sampled(ctx):
+    """The benchmark's launch: 1000 transforms over 256x256x180 u16, 128
+    bins, 6 entropies.  Sampled transforms against the oracle; every
+    transform checked for mass == overlap and Shannon MI >= 0."""
+    c = inputs.multimodal_sweep()
+    g = run_gpu(ctx, c["fixed"], c["moving"], c["fixed_range"], c["moving_range"], c["transforms"],
+                c["bins"], c["q"])
+    gmi, gov, gh = g
+    assert np.array_equal(gh.reshape(len(gov), -1).sum(axis=1, dtype=np.int64), gov.astype(np.int64))
+    assert np.all(np.isfinite(gmi)) and np.all(gmi[:, 0] >= -1e-12)
+    pick = [0, 137, 555, 999]
+    o = run_oracle(c["fixed"], c["moving"], c["fixed_range"], c["moving_range"], c["transforms"][pick],
+                   c["bins"], c["q"])
+    assert_parity((gmi[pick], gov[pick], gh[pick]), o, "full-size sample")
+
+
+def test_timing_counts_launches(ctx):
+    import torch
+    from paper_1909_10690_amd import binding as B
+    c = inputs.plain_translation(n=32)
+    F = B.Volume.from_numpy(c["fixed"], 0, 255)
+    tr = torch.from_numpy(c["transforms"]).cuda()
+    ctx.timing(True)
+    for _ in range(3):
+        ctx.eval(F, F, tr, 32, [1.0])
+    ctx.timing(False)
+    ms, n = ctx.timing_read(B.TIMER_HARD)
+    assert n == 3 and ms > 0
+    ms, n = ctx.timing_read(B.TIMER_HARD)
+    assert n == 0
