@@ -99,6 +99,9 @@ def main() -> int:
                     help="minimum wall time of the CPU-oracle sample")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle leg")
     ap.add_argument("--no-extras", action="store_true", help="skip the plain-path and gradient legs")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="also run an elementwise copy of MIB MiB (read + write), the reference "
+                         "kernel for scaling HBM byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for {args.gpus}); the metric path has no "
@@ -165,6 +168,16 @@ def main() -> int:
                      "kernel": "hist_hard_kernel<uint16_t>", "kernel_ms": k_avg_ms,
                      "algorithmic_bytes_per_voxel_xform": balg},
     }
+
+    if args.calibrate_copy:
+        nel = args.calibrate_copy * (1 << 20) // 4
+        src = torch.ones(nel, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.mul(src, 1.0, out=dst)
+        torch.cuda.synchronize()
+        result["copy_calibration"] = {"bytes_read": 4 * nel, "bytes_written": 4 * nel,
+                                      "launches": 3}
 
     if not args.no_extras:
         # one transform per launch: the same kernels, no batching

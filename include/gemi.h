@@ -70,7 +70,7 @@ extern "C" {
 /* ---- status codes ------------------------------------------------------ */
 #define MI_OK 0
 #define MI_ERR_NULL (-1)        /* a required pointer is NULL             */
-#define MI_ERR_DIMS (-2)        /* a volume edge outside [2, 4096] or too many bytes */
+#define MI_ERR_DIMS (-2)        /* a volume edge outside [2, 4096], or more than 2^28 voxels */
 #define MI_ERR_DTYPE (-3)       /* unknown dtype, or MI_F32 moving volume on the hard path */
 #define MI_ERR_BINS (-4)        /* bins outside [2, 256] ([8, 256] for Parzen) */
 #define MI_ERR_RANGE (-5)       /* lo/hi not finite, hi <= lo, or (integer dtypes) not
@@ -103,7 +103,7 @@ extern "C" {
 /* A volume: tightly packed C-order [nz][ny][nx] (x fastest) on the device. */
 typedef struct mi_volume {
   const void *data; /* device pointer, nx*ny*nz elements of `dtype`        */
-  int32_t nx, ny, nz; /* each in [2, 4096]; nx*ny*nz*sizeof(dtype) < 2^32 */
+  int32_t nx, ny, nz; /* each in [2, 4096]; nx*ny*nz <= 2^28 */
   int32_t dtype;      /* MI_U8, MI_U16, MI_I16 or MI_F32                   */
   double lo, hi;      /* intensity range mapped onto the bins              */
 } mi_volume;

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <mutex>
@@ -48,7 +49,7 @@ int check_volume(const mi_volume* v, bool need_integer) {
   const int32_t n[3] = {v->nx, v->ny, v->nz};
   for (int r = 0; r < 3; ++r)
     if (n[r] < 2 || n[r] > MI_MAX_EDGE) return MI_ERR_DIMS;
-  if ((double)voxels(v) * (double)dtype_size(v->dtype) >= 4294967040.0) return MI_ERR_DIMS;
+  if (voxels(v) > ((size_t)1 << 28)) return MI_ERR_DIMS;
   if (!isfinite(v->lo) || !isfinite(v->hi) || !(v->hi > v->lo)) return MI_ERR_RANGE;
   if (v->dtype != MI_F32) {
     if (v->lo != floor(v->lo) || v->hi != floor(v->hi)) return MI_ERR_RANGE;
@@ -84,21 +85,24 @@ int check_common(const mi_volume* f, const mi_volume* m, int32_t n, int32_t bins
 
 // Workspace layout (each region 256-byte aligned):
 //   fixed bins   u8[nvox_fixed]
-//   hard:        hist u32[n][B][B]          (only when the caller passes no hist_out)
+//   hard:        moving pair volume u32[mnz+1][mny+1][mnx],
+//                hist u32[n][B][B]          (only when the caller passes no hist_out)
 //   Parzen:      table f64[n][B][B], count u64[n]
 //   Parzen grad: + dMI/dp tables f32[n][n_q][B][B]
 struct Layout {
-  size_t fbins = 0, hist = 0, table = 0, count = 0, gtab = 0, total = 0;
+  size_t fbins = 0, pairs = 0, hist = 0, table = 0, count = 0, gtab = 0, total = 0;
 };
 
-Layout layout(const mi_volume* f, int32_t n, int32_t bins, int32_t n_q, bool parzen, bool grad,
-              bool need_hist) {
+Layout layout(const mi_volume* f, const mi_volume* m, int32_t n, int32_t bins, int32_t n_q,
+              bool parzen, bool grad, bool need_hist) {
   Layout L;
   size_t off = 0;
   L.fbins = off;
   off += align256(voxels(f));
   const size_t bb = (size_t)bins * bins;
   if (!parzen) {
+    L.pairs = off;
+    off += align256(pair_volume_bytes(m->nx, m->ny, m->nz));
     L.hist = off;
     if (need_hist) off += align256(bb * 4 * (size_t)n);
   } else {
@@ -141,6 +145,7 @@ QList qlist(const double* q, int32_t n_q, int32_t flags) {
 struct mi_context {
   int device = 0;
   int cu_count = 256;
+  int hard_block = 512;   // threads per workgroup of the histogram sweep
   bool timing = false;
   std::mutex mu;
   std::vector<EventPair> events[kTimers];
@@ -204,7 +209,7 @@ const char* mi_status_string(int status) {
   switch (status) {
   case MI_OK: return "ok";
   case MI_ERR_NULL: return "a required pointer is NULL";
-  case MI_ERR_DIMS: return "volume edge outside [2, 4096] or volume too large";
+  case MI_ERR_DIMS: return "volume edge outside [2, 4096] or more than 2^28 voxels";
   case MI_ERR_DTYPE: return "unknown dtype, or float32 moving volume on the hard-binned path";
   case MI_ERR_BINS: return "bins outside [2, 256] (Parzen: [8, 256])";
   case MI_ERR_RANGE: return "intensity range lo/hi invalid";
@@ -238,6 +243,10 @@ int mi_create(mi_context** out, int device) {
   if ((e = configure_parzen_kernels()) != hipSuccess) return hip_fail(e, "configure kernels");
   mi_context* c = new mi_context();
   c->device = device;
+  if (const char* b = getenv("MI_TUNE_HARD_BLOCK")) {
+    const int v = atoi(b);
+    if (v == 256 || v == 512 || v == 1024) c->hard_block = v;
+  }
   c->cu_count = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
   *out = c;
   return MI_OK;
@@ -261,7 +270,7 @@ int mi_workspace_size(const mi_volume* fixed, const mi_volume* moving, int32_t n
   int st = check_common(fixed, moving, n, bins, nullptr, 0, flags, parzen);
   if (st != MI_OK) return st;
   if (n_q < 1 || n_q > MI_MAX_Q) return MI_ERR_Q;
-  *bytes = layout(fixed, n, bins, n_q, parzen, for_grad != 0, true).total;
+  *bytes = layout(fixed, moving, n, bins, n_q, parzen, for_grad != 0, true).total;
   return MI_OK;
 }
 
@@ -305,7 +314,7 @@ int mi_eval(mi_context* ctx, const mi_volume* fixed, const mi_volume* moving,
   if ((st = check_q(q, n_q)) != MI_OK) return st;
   if (n > 0 && (!transforms || !mi_out)) return MI_ERR_NULL;
   if (parzen && hist_out) return MI_ERR_UNSUPPORTED;
-  const Layout L = layout(fixed, n, bins, n_q, parzen, false, hist_out == nullptr);
+  const Layout L = layout(fixed, moving, n, bins, n_q, parzen, false, hist_out == nullptr);
   if (!workspace || workspace_bytes < L.total) return MI_ERR_WORKSPACE;
   if (!ctx) return MI_ERR_NULL;
   if (n == 0) return MI_OK;
@@ -327,10 +336,13 @@ int mi_eval(mi_context* ctx, const mi_volume* fixed, const mi_volume* moving,
   R.overlap_out = overlap_out;
   if (!parzen) {
     uint32_t* hist = hist_out ? hist_out : (uint32_t*)(ws + L.hist);
+    uint32_t* pairs = (uint32_t*)(ws + L.pairs);
+    if ((e = launch_pack_pairs(desc(moving), pairs, s)) != hipSuccess) return hip_fail(e, "pack");
     if ((e = launch_fill_u32(hist, bb * n, 0u, s)) != hipSuccess) return hip_fail(e, "fill");
     HardLaunch H;
     H.transforms = transforms;
     H.fbins = fb;
+    H.pairs = pairs;
     H.fixed = desc(fixed);
     H.moving = desc(moving);
     H.hist = hist;
@@ -338,6 +350,7 @@ int mi_eval(mi_context* ctx, const mi_volume* fixed, const mi_volume* moving,
     H.bins = bins;
     H.clamp = (flags & MI_BOUNDARY_CLAMP) ? 1 : 0;
     H.packed = bins > 128 ? 1 : 0;
+    H.block = ctx->hard_block;
     H.chunks = plan_chunks(ctx, fixed, n, H.packed != 0);
     TimedLaunch tl(ctx, 0, s);
     if ((e = launch_hist_hard(H, s)) != hipSuccess) return hip_fail(e, "hist_hard");

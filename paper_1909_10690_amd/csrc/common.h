@@ -9,7 +9,7 @@
 namespace gemi {
 
 constexpr int kMaxQ = 16;
-constexpr int kBlock = 256;  // threads per workgroup for the voxel sweeps (4 wave64)
+constexpr int kBlock = 256;  // threads per workgroup of the reduction kernels (4 wave64)
 
 // Entropic indices passed by value to the reduction kernels.
 struct QList {
@@ -66,12 +66,19 @@ struct VolumeDesc {
 struct HardLaunch {
   const double* transforms;  // [n][12]
   const uint8_t* fbins;      // fixed-volume bins, [fnz][fny][fnx]
+  const uint32_t* pairs;     // moving pair volume, [mnz+1][mny+1][mnx]
   VolumeDesc fixed, moving;
   uint32_t* hist;  // [n][B][B]
   int32_t n, bins, clamp;
   int32_t chunks;  // workgroups per transform, multiple of 8
   int32_t packed;  // 1: two 16-bit counters per LDS word (bins > 128)
+  int32_t block;   // threads per workgroup: 256, 512 or 1024
 };
+
+// Bytes of the moving pair volume of an nx x ny x nz volume.
+inline size_t pair_volume_bytes(int32_t nx, int32_t ny, int32_t nz) {
+  return (size_t)nx * (size_t)(ny + 1) * (size_t)(nz + 1) * 4;
+}
 
 struct ReduceLaunch {
   const uint32_t* hist;  // [n][B][B] counts, or NULL when `table` is used
@@ -87,6 +94,7 @@ struct ReduceLaunch {
 hipError_t launch_fill_u32(uint32_t* p, size_t n, uint32_t value, hipStream_t s);
 hipError_t launch_fill_f64(double* p, size_t n, hipStream_t s);
 hipError_t launch_prebin_fixed(const VolumeDesc& f, int bins, uint8_t* out, hipStream_t s);
+hipError_t launch_pack_pairs(const VolumeDesc& m, uint32_t* out, hipStream_t s);
 hipError_t launch_hist_hard(const HardLaunch& L, hipStream_t s);
 hipError_t launch_mi_reduce(const ReduceLaunch& L, hipStream_t s);
 hipError_t configure_kernels();

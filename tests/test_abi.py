@@ -67,7 +67,7 @@ def test_valid_arguments_reach_the_context_check():
 
 @pytest.mark.parametrize("kw,status", [
     (dict(nx=1), B.MI_ERR_DIMS), (dict(ny=4097), B.MI_ERR_DIMS), (dict(nz=0), B.MI_ERR_DIMS),
-    (dict(nx=4096, ny=4096, nz=300), B.MI_ERR_DIMS),
+    (dict(nx=4096, ny=4096, nz=17), B.MI_ERR_DIMS), (dict(nx=4096, ny=4096, nz=16), B.MI_ERR_NULL),
     (dict(dtype=7), B.MI_ERR_DTYPE), (dict(dtype=-1), B.MI_ERR_DTYPE),
     (dict(lo=5.0, hi=5.0), B.MI_ERR_RANGE), (dict(lo=0.5), B.MI_ERR_RANGE),
     (dict(hi=float("nan")), B.MI_ERR_RANGE), (dict(lo=0.0, hi=65536.0), B.MI_ERR_RANGE),
@@ -127,8 +127,8 @@ def ws_size(f, m, n, bins, n_q, flags=0, grad=0):
 
 def test_workspace_size_layout():
     a = lambda x: (x + 255) // 256 * 256
-    st, n = ws_size(vol(10, 11, 12), vol(), 5, 32, 2)
-    assert st == 0 and n == a(10 * 11 * 12) + a(5 * 32 * 32 * 4)
+    st, n = ws_size(vol(10, 11, 12), vol(9, 8, 7), 5, 32, 2)
+    assert st == 0 and n == a(10 * 11 * 12) + a(9 * 9 * 8 * 4) + a(5 * 32 * 32 * 4)
     st, n = ws_size(vol(10, 11, 12), vol(), 5, 32, 2, B.HIST_PARZEN)
     assert st == 0 and n == a(1320) + a(5 * 32 * 32 * 8) + a(5 * 8)
     st, n = ws_size(vol(10, 11, 12), vol(), 5, 32, 2, 0, 1)
