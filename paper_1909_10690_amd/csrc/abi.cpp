@@ -85,12 +85,12 @@ int check_common(const mi_volume* f, const mi_volume* m, int32_t n, int32_t bins
 
 // Workspace layout (each region 256-byte aligned):
 //   fixed bins   u8[nvox_fixed]
-//   hard:        moving pair volume u32[mnz+1][mny+1][mnx],
+//   hard:        moving quad volume u16x4[mnz+1][mny][mnx],
 //                hist u32[n][B][B]          (only when the caller passes no hist_out)
 //   Parzen:      table f64[n][B][B], count u64[n]
 //   Parzen grad: + dMI/dp tables f32[n][n_q][B][B]
 struct Layout {
-  size_t fbins = 0, pairs = 0, hist = 0, table = 0, count = 0, gtab = 0, total = 0;
+  size_t fbins = 0, quads = 0, hist = 0, table = 0, count = 0, gtab = 0, total = 0;
 };
 
 Layout layout(const mi_volume* f, const mi_volume* m, int32_t n, int32_t bins, int32_t n_q,
@@ -101,8 +101,8 @@ Layout layout(const mi_volume* f, const mi_volume* m, int32_t n, int32_t bins, i
   off += align256(voxels(f));
   const size_t bb = (size_t)bins * bins;
   if (!parzen) {
-    L.pairs = off;
-    off += align256(pair_volume_bytes(m->nx, m->ny, m->nz));
+    L.quads = off;
+    off += align256(quad_volume_bytes(m->nx, m->ny, m->nz));
     L.hist = off;
     if (need_hist) off += align256(bb * 4 * (size_t)n);
   } else {
@@ -146,6 +146,8 @@ struct mi_context {
   int device = 0;
   int cu_count = 256;
   int hard_block = 512;   // threads per workgroup of the histogram sweep
+  int hard_slab_major = 1;
+  int hard_chunks = 0;    // workgroups per transform; 0 = planned per call
   bool timing = false;
   std::mutex mu;
   std::vector<EventPair> events[kTimers];
@@ -176,28 +178,29 @@ struct TimedLaunch {
   }
 };
 
-// Workgroups per transform for the histogram sweep: enough to fill the
-// chip several times over, a multiple of 8 (one share per XCD), at most one
-// per fixed row, and -- with 16-bit packed LDS counters -- few enough rows
-// per workgroup that no counter can exceed 65535.
+// Workgroups per transform for the histogram sweep.  The fixed volume is
+// swept in groups of 4 rows; a transform's groups are split into `c`
+// slabs: enough workgroups to fill the chip several times over, at least
+// 32 thin slabs in slab-major order (the moving footprint of one slab must
+// fit an XCD's L2), a multiple of 8 (one share per XCD), and -- with 16-bit
+// packed LDS counters -- few enough voxels per workgroup that no counter
+// can exceed 65535.
 int plan_chunks(const mi_context* ctx, const mi_volume* f, int32_t n, bool packed) {
-  const int64_t rows = (int64_t)f->ny * f->nz;
-  const int64_t target = (int64_t)ctx->cu_count * 8;
-  int64_t c = (target + n - 1) / n;
+  const int64_t groups = (int64_t)((f->ny + 3) / 4) * f->nz;
+  int64_t c;
+  if (ctx->hard_chunks) {
+    c = ctx->hard_chunks;
+  } else {
+    c = ((int64_t)ctx->cu_count * 8 + n - 1) / n;
+    if (ctx->hard_slab_major && c < 32) c = 32;
+  }
+  if (c > groups) c = groups;
   if (packed) {
-    const int64_t rows_per = 65535 / f->nx;
-    const int64_t need = (rows + rows_per - 1) / rows_per;
+    const int64_t per = 65535 / (4 * (int64_t)f->nx);  // groups per workgroup
+    const int64_t need = (groups + per - 1) / per;
     if (c < need) c = need;
   }
-  if (c < 8) c = 8;
-  if (c > rows) c = rows;
   c = ((c + 7) / 8) * 8;
-  if (packed) {
-    // rounding up to a multiple of 8 only shortens slabs; re-check
-    while ((rows + c - 1) / c * (int64_t)f->nx > 65535) c += 8;
-  }
-  // keep the grid within the launch limit
-  while ((int64_t)n * c > 0x7FFFFFFFll && c > 8) c -= 8;
   return (int)c;
 }
 
@@ -246,6 +249,11 @@ int mi_create(mi_context** out, int device) {
   if (const char* b = getenv("MI_TUNE_HARD_BLOCK")) {
     const int v = atoi(b);
     if (v == 256 || v == 512 || v == 1024) c->hard_block = v;
+  }
+  if (const char* o = getenv("MI_TUNE_HARD_ORDER")) c->hard_slab_major = atoi(o) != 0;
+  if (const char* k = getenv("MI_TUNE_HARD_CHUNKS")) {
+    const int v = atoi(k);
+    if (v >= 8 && v % 8 == 0) c->hard_chunks = v;
   }
   c->cu_count = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
   *out = c;
@@ -336,13 +344,13 @@ int mi_eval(mi_context* ctx, const mi_volume* fixed, const mi_volume* moving,
   R.overlap_out = overlap_out;
   if (!parzen) {
     uint32_t* hist = hist_out ? hist_out : (uint32_t*)(ws + L.hist);
-    uint32_t* pairs = (uint32_t*)(ws + L.pairs);
-    if ((e = launch_pack_pairs(desc(moving), pairs, s)) != hipSuccess) return hip_fail(e, "pack");
+    uint2* quads = (uint2*)(ws + L.quads);
+    if ((e = launch_pack_quads(desc(moving), quads, s)) != hipSuccess) return hip_fail(e, "pack");
     if ((e = launch_fill_u32(hist, bb * n, 0u, s)) != hipSuccess) return hip_fail(e, "fill");
     HardLaunch H;
     H.transforms = transforms;
     H.fbins = fb;
-    H.pairs = pairs;
+    H.quads = quads;
     H.fixed = desc(fixed);
     H.moving = desc(moving);
     H.hist = hist;
@@ -351,10 +359,19 @@ int mi_eval(mi_context* ctx, const mi_volume* fixed, const mi_volume* moving,
     H.clamp = (flags & MI_BOUNDARY_CLAMP) ? 1 : 0;
     H.packed = bins > 128 ? 1 : 0;
     H.block = ctx->hard_block;
+    H.slab_major = ctx->hard_slab_major;
     H.chunks = plan_chunks(ctx, fixed, n, H.packed != 0);
-    TimedLaunch tl(ctx, 0, s);
-    if ((e = launch_hist_hard(H, s)) != hipSuccess) return hip_fail(e, "hist_hard");
-    tl.done();
+    // one launch covers at most 2^31 - 1 workgroups: split the transforms
+    const int64_t per_launch = 0x7FFFFFFFll / H.chunks;
+    for (int64_t t0 = 0; t0 < n; t0 += per_launch) {
+      HardLaunch part = H;
+      part.n = (int32_t)(n - t0 < per_launch ? n - t0 : per_launch);
+      part.transforms = transforms + 12 * t0;
+      part.hist = hist + bb * t0;
+      TimedLaunch tl(ctx, 0, s);
+      if ((e = launch_hist_hard(part, s)) != hipSuccess) return hip_fail(e, "hist_hard");
+      tl.done();
+    }
     R.hist = hist;
   } else {
     return MI_ERR_UNSUPPORTED;  // Parzen forward: see mi_grad

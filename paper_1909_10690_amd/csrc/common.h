@@ -66,18 +66,20 @@ struct VolumeDesc {
 struct HardLaunch {
   const double* transforms;  // [n][12]
   const uint8_t* fbins;      // fixed-volume bins, [fnz][fny][fnx]
-  const uint32_t* pairs;     // moving pair volume, [mnz+1][mny+1][mnx]
+  const uint2* quads;        // moving quad volume, [mnz+1][mny][mnx]
   VolumeDesc fixed, moving;
   uint32_t* hist;  // [n][B][B]
   int32_t n, bins, clamp;
   int32_t chunks;  // workgroups per transform, multiple of 8
   int32_t packed;  // 1: two 16-bit counters per LDS word (bins > 128)
   int32_t block;   // threads per workgroup: 256, 512 or 1024
+  int32_t slab_major;  // workgroup order: 1 slab-major, 0 transform-major
 };
 
-// Bytes of the moving pair volume of an nx x ny x nz volume.
-inline size_t pair_volume_bytes(int32_t nx, int32_t ny, int32_t nz) {
-  return (size_t)nx * (size_t)(ny + 1) * (size_t)(nz + 1) * 4;
+// Bytes of the moving quad volume of an nx x ny x nz volume (< 2^32 for
+// at most 2^28 voxels).
+inline size_t quad_volume_bytes(int32_t nx, int32_t ny, int32_t nz) {
+  return (size_t)nx * (size_t)ny * (size_t)(nz + 1) * 8;
 }
 
 struct ReduceLaunch {
@@ -94,7 +96,7 @@ struct ReduceLaunch {
 hipError_t launch_fill_u32(uint32_t* p, size_t n, uint32_t value, hipStream_t s);
 hipError_t launch_fill_f64(double* p, size_t n, hipStream_t s);
 hipError_t launch_prebin_fixed(const VolumeDesc& f, int bins, uint8_t* out, hipStream_t s);
-hipError_t launch_pack_pairs(const VolumeDesc& m, uint32_t* out, hipStream_t s);
+hipError_t launch_pack_quads(const VolumeDesc& m, uint2* out, hipStream_t s);
 hipError_t launch_hist_hard(const HardLaunch& L, hipStream_t s);
 hipError_t launch_mi_reduce(const ReduceLaunch& L, hipStream_t s);
 hipError_t configure_kernels();

@@ -3,16 +3,17 @@
 // Discussion), for gfx950.
 //
 // Per call, the fixed volume is reduced to one bin byte per voxel and the
-// moving volume to a padded "pair volume": each element holds the clamped,
-// offset intensities of a voxel and of its +x neighbour as two 16-bit
-// halves, so the 2x2x2 trilinear neighbourhood is four aligned 32-bit
-// loads, and one zero row per slice plus one zero slice make the +y/+z
-// neighbours of the last row/slice addressable (their weight is 0).
+// moving volume to a "quad volume": each 8-byte element holds the clamped,
+// offset intensities of a voxel and of its +x, +y and +x+y neighbours as
+// 16-bit values, so the 2x2x2 trilinear neighbourhood is two aligned
+// 64-bit loads; one zero slice makes the +z neighbours of the last slice
+// addressable (their weight is 0).
 //
 // One workgroup = one transform x one slab of fixed rows.  Each wave64
-// walks its own run of rows with scalar row coordinates; its 64 lanes take
-// consecutive x (coalesced fixed-bin reads) and step the exact Q32 moving
-// coordinate by 64 * M[:,0] per iteration.  Each lane forms the exact
+// walks its own run of 4-row groups with scalar coordinates; its 64 lanes
+// cover a 16 x 4 tile of fixed voxels (a compact footprint in the moving
+// volume even under rotation, so few cache lines per load) and step the
+// exact Q32 moving coordinate by 16 * M[:,0] per iteration.  Each lane forms the exact
 // 16-bit-weight trilinear value: x-lerps with v_dot2_u32_u16 in integers
 // (< 2^32), y-lerps in fp64 (exact: integers < 2^48), the z-lerp as one
 // fp64 fma (the exact value rounded once).  The bin floor(V B / (R 2^48))
@@ -108,41 +109,49 @@ hipError_t launch_prebin_fixed(const VolumeDesc& f, int bins, uint8_t* out, hipS
 }
 
 // ---------------------------------------------------------------------------
-// moving pair volume, once per call
+// moving quad volume, once per call
 // ---------------------------------------------------------------------------
 
-// out[z][y][x] (z <= nz, y <= ny) = v'(x,y,z) | v'(min(x+1, nx-1),y,z) << 16
-// with v' = clamp(v, lo, hi) - lo; zero on the padding row and slice.
+// out[z][y][x] (z <= nz) holds four 16-bit clamped, offset intensities
+// v' = clamp(v, lo, hi) - lo: (x, y), (x1, y) in .x and (x, y+1), (x1, y+1)
+// in .y, with x1 = min(x+1, nx-1).  On the last row the y+1 values are 0
+// and slice nz is all 0: those corners always carry weight 0.
 template <typename T>
-__global__ void pack_pairs_kernel(const T* __restrict__ v, int32_t nx, int32_t ny, int32_t nz,
-                                  int32_t lo, int32_t hi, uint32_t* __restrict__ out) {
+__global__ void pack_quads_kernel(const T* __restrict__ v, int32_t nx, int32_t ny, int32_t nz,
+                                  int32_t lo, int32_t hi, uint2* __restrict__ out) {
   const int32_t y = blockIdx.y, z = blockIdx.z;
-  uint32_t* __restrict__ orow = out + ((size_t)z * (ny + 1) + y) * nx;
-  if (y >= ny || z >= nz) {
-    for (int32_t x = threadIdx.x; x < nx; x += blockDim.x) orow[x] = 0u;
+  uint2* __restrict__ orow = out + ((size_t)z * ny + y) * nx;
+  if (z >= nz) {
+    for (int32_t x = threadIdx.x; x < nx; x += blockDim.x) orow[x] = make_uint2(0u, 0u);
     return;
   }
-  const T* __restrict__ row = v + ((size_t)z * ny + y) * nx;
-  for (int32_t x = threadIdx.x; x < nx; x += blockDim.x) {
-    int32_t a = (int32_t)row[x];
-    int32_t b = (int32_t)row[x + 1 < nx ? x + 1 : nx - 1];
+  const T* __restrict__ r0 = v + ((size_t)z * ny + y) * nx;
+  const bool has1 = y + 1 < ny;
+  const T* __restrict__ r1 = r0 + (has1 ? nx : 0);
+  auto c = [&](T raw) -> uint32_t {
+    int32_t a = (int32_t)raw;
     a = a < lo ? lo : (a > hi ? hi : a);
-    b = b < lo ? lo : (b > hi ? hi : b);
-    orow[x] = (uint32_t)(a - lo) | ((uint32_t)(b - lo) << 16);
+    return (uint32_t)(a - lo);
+  };
+  for (int32_t x = threadIdx.x; x < nx; x += blockDim.x) {
+    const int32_t x1 = x + 1 < nx ? x + 1 : nx - 1;
+    const uint32_t lo_pair = c(r0[x]) | (c(r0[x1]) << 16);
+    const uint32_t hi_pair = has1 ? (c(r1[x]) | (c(r1[x1]) << 16)) : 0u;
+    orow[x] = make_uint2(lo_pair, hi_pair);
   }
 }
 
-hipError_t launch_pack_pairs(const VolumeDesc& m, uint32_t* out, hipStream_t s) {
-  const dim3 grid(1, (unsigned)m.ny + 1, (unsigned)m.nz + 1);
+hipError_t launch_pack_quads(const VolumeDesc& m, uint2* out, hipStream_t s) {
+  const dim3 grid(1, (unsigned)m.ny, (unsigned)m.nz + 1);
   const int32_t lo = (int32_t)m.lo, hi = (int32_t)m.hi;
   if (m.dtype == 0)
-    hipLaunchKernelGGL(pack_pairs_kernel<uint8_t>, grid, dim3(256), 0, s, (const uint8_t*)m.data,
+    hipLaunchKernelGGL(pack_quads_kernel<uint8_t>, grid, dim3(256), 0, s, (const uint8_t*)m.data,
                        m.nx, m.ny, m.nz, lo, hi, out);
   else if (m.dtype == 1)
-    hipLaunchKernelGGL(pack_pairs_kernel<uint16_t>, grid, dim3(256), 0, s, (const uint16_t*)m.data,
+    hipLaunchKernelGGL(pack_quads_kernel<uint16_t>, grid, dim3(256), 0, s, (const uint16_t*)m.data,
                        m.nx, m.ny, m.nz, lo, hi, out);
   else if (m.dtype == 2)
-    hipLaunchKernelGGL(pack_pairs_kernel<int16_t>, grid, dim3(256), 0, s, (const int16_t*)m.data,
+    hipLaunchKernelGGL(pack_quads_kernel<int16_t>, grid, dim3(256), 0, s, (const int16_t*)m.data,
                        m.nx, m.ny, m.nz, lo, hi, out);
   else
     return hipErrorInvalidValue;
@@ -156,28 +165,40 @@ hipError_t launch_pack_pairs(const VolumeDesc& m, uint32_t* out, hipStream_t s) 
 struct HardArgs {
   const double* transforms;
   const uint8_t* fbins;
-  const uint32_t* pairs;
+  const uint2* quads;
   uint32_t* hist;
   int32_t fnx, fny, fnz;
   int32_t mnx, mny, mnz;
-  uint32_t pair_bytes;
-  int32_t bins, chunks;
+  uint32_t quad_bytes;
+  int32_t n, bins, chunks;
+  int32_t slab_major;  // 1: consecutive workgroups of an XCD share a slab
   double scale;  // B / (R 2^48)
   Divider div;   // floor(X / R) for the exact fallback
 };
 
 typedef unsigned short ushort2_t __attribute__((ext_vector_type(2)));
+typedef unsigned int uint2_t __attribute__((ext_vector_type(2)));
 
 // Maps workgroup id -> (transform, slab).  Workgroups are dealt round-robin
 // to the 8 XCDs, so XCD x receives ids x, x+8, ...; those all take slabs
-// from the x-th eighth of the fixed volume, whose moving footprint then
-// stays in that XCD's L2 across transforms.
-__device__ __forceinline__ void block_work(int32_t chunks, uint32_t& t, uint32_t& chunk) {
+// from the x-th eighth of the fixed volume.  Slab-major order then walks
+// that eighth one thin slab at a time, all transforms per slab, so the
+// workgroups resident on an XCD at once share one slab's moving footprint
+// in that XCD's L2; transform-major order finishes a transform's slabs
+// before the next transform.
+__device__ __forceinline__ void block_work(int32_t chunks, int32_t n, int32_t slab_major,
+                                           uint32_t& t, uint32_t& chunk) {
   const uint32_t bid = blockIdx.x;
   const uint32_t xcd = bid & 7u, slot = bid >> 3;
   const uint32_t c8 = (uint32_t)chunks >> 3;
-  t = slot / c8;
-  chunk = xcd * c8 + (slot - t * c8);
+  if (slab_major) {
+    const uint32_t cl = slot / (uint32_t)n;
+    t = slot - cl * (uint32_t)n;
+    chunk = xcd * c8 + cl;
+  } else {
+    t = slot / c8;
+    chunk = xcd * c8 + (slot - t * c8);
+  }
 }
 
 // v0 (1 - w) + v1 w at 16-bit weight w = fx >> 16, exact: the pair's low
@@ -199,6 +220,7 @@ __device__ __noinline__ uint32_t exact_bin(uint32_t a00, uint32_t a10, uint32_t 
 }
 
 constexpr double kEdge = 1.0 / 536870912.0;  // 2^-29
+constexpr int kTileX = 16, kTileY = 4;       // a wave64 sweeps 16 x 4 fixed voxels at a time
 
 template <bool CLAMP, bool PACKED, int NT>
 __global__ __launch_bounds__(NT) void hist_hard_kernel(HardArgs a) {
@@ -208,84 +230,93 @@ __global__ __launch_bounds__(NT) void hist_hard_kernel(HardArgs a) {
   for (int e = threadIdx.x; e < words; e += NT) lds_hist[e] = 0;
 
   uint32_t t, chunk;
-  block_work(a.chunks, t, chunk);
+  block_work(a.chunks, a.n, a.slab_major, t, chunk);
   int64_t Mq[12];
   const bool ok = quantize_transform(a.transforms + 12 * (size_t)t, Mq);
   __syncthreads();
   if (ok) {
     constexpr int NW = NT / 64;
-    const int64_t rows = (int64_t)a.fny * a.fnz;
-    const int64_t r0 = rows * chunk / a.chunks, r1 = rows * (chunk + 1) / a.chunks;
+    // the fixed volume as groups of kTileY consecutive rows of one slice
+    const int32_t G = (a.fny + kTileY - 1) / kTileY;
+    const int64_t groups = (int64_t)G * a.fnz;
+    const int64_t g0 = groups * chunk / a.chunks, g1 = groups * (chunk + 1) / a.chunks;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    const int64_t w0 = r0 + (r1 - r0) * wave / NW, w1 = r0 + (r1 - r0) * (wave + 1) / NW;
-    int32_t k = (int32_t)(w0 / a.fny), j = (int32_t)(w0 - (int64_t)k * a.fny);
-    // Q32 coordinate of voxel (0, j, k); per-row and per-slice-wrap deltas
-    int64_t rx = Mq[1] * j + Mq[2] * k + Mq[3];
-    int64_t ry = Mq[5] * j + Mq[6] * k + Mq[7];
-    int64_t rz = Mq[9] * j + Mq[10] * k + Mq[11];
-    const int64_t wrapx = Mq[2] - Mq[1] * a.fny, wrapy = Mq[6] - Mq[5] * a.fny,
-                  wrapz = Mq[10] - Mq[9] * a.fny;
-    const int64_t lx = Mq[0] * lane, ly = Mq[4] * lane, lz = Mq[8] * lane;
-    const int64_t sx = Mq[0] * 64, sy = Mq[4] * 64, sz = Mq[8] * 64;
+    const int dx = lane & (kTileX - 1), dy = lane / kTileX;
+    const int64_t w0 = g0 + (g1 - g0) * wave / NW, w1 = g0 + (g1 - g0) * (wave + 1) / NW;
+    int32_t k = (int32_t)(w0 / G);
+    int32_t j0 = (int32_t)(w0 - (int64_t)k * G) * kTileY;
+    // Q32 coordinate of voxel (0, j0, k); per-group and slice-wrap deltas
+    int64_t rx = Mq[1] * j0 + Mq[2] * k + Mq[3];
+    int64_t ry = Mq[5] * j0 + Mq[6] * k + Mq[7];
+    int64_t rz = Mq[9] * j0 + Mq[10] * k + Mq[11];
+    const int64_t wrapx = Mq[2] - Mq[1] * ((int64_t)G * kTileY);
+    const int64_t wrapy = Mq[6] - Mq[5] * ((int64_t)G * kTileY);
+    const int64_t wrapz = Mq[10] - Mq[9] * ((int64_t)G * kTileY);
+    const int64_t lx = Mq[0] * dx + Mq[1] * dy, ly = Mq[4] * dx + Mq[5] * dy,
+                  lz = Mq[8] * dx + Mq[9] * dy;
+    const int64_t sx = Mq[0] * kTileX, sy = Mq[4] * kTileX, sz = Mq[8] * kTileX;
     const uint64_t topx = (uint64_t)(a.mnx - 1) << 32;
     const uint64_t topy = (uint64_t)(a.mny - 1) << 32;
     const uint64_t topz = (uint64_t)(a.mnz - 1) << 32;
-    const uint32_t PY = (uint32_t)a.mny + 1, MX = (uint32_t)a.mnx;
-    const int32_t SY = 4 * a.mnx, SZ = 4 * a.mnx * (a.mny + 1);
+    const uint32_t NY = (uint32_t)a.mny, MX = (uint32_t)a.mnx;
+    const int32_t SZ = 8 * a.mnx * a.mny;
     const __amdgpu_buffer_rsrc_t rsrc =
-        __builtin_amdgcn_make_buffer_rsrc((void*)a.pairs, (short)0, (int)a.pair_bytes, 0x00020000);
+        __builtin_amdgcn_make_buffer_rsrc((void*)a.quads, (short)0, (int)a.quad_bytes, 0x00020000);
     const uint32_t Bu = (uint32_t)B;
     const double scale = a.scale;
 
-    for (int64_t r = w0; r < w1; ++r) {
-      const uint8_t* __restrict__ frow = a.fbins + r * a.fnx;
-      int64_t qx = rx + lx, qy = ry + ly, qz = rz + lz;
-      for (int x = lane; x < a.fnx; x += 64, qx += sx, qy += sy, qz += sz) {
-        uint64_t cx = (uint64_t)qx, cy = (uint64_t)qy, cz = (uint64_t)qz;
-        if (CLAMP) {
-          cx = qx < 0 ? 0 : (cx > topx ? topx : cx);
-          cy = qy < 0 ? 0 : (cy > topy ? topy : cy);
-          cz = qz < 0 ? 0 : (cz > topz ? topz : cz);
-        } else {
-          // 0 <= q <= top; a negative q wraps to a huge unsigned value
-          if (cx > topx || cy > topy || cz > topz) continue;
+    for (int64_t g = w0; g < w1; ++g) {
+      const int32_t j = j0 + dy;
+      if (j < a.fny) {
+        const uint8_t* __restrict__ frow = a.fbins + ((int64_t)k * a.fny + j) * a.fnx;
+        int64_t qx = rx + lx, qy = ry + ly, qz = rz + lz;
+        for (int x = dx; x < a.fnx; x += kTileX, qx += sx, qy += sy, qz += sz) {
+          uint64_t cx = (uint64_t)qx, cy = (uint64_t)qy, cz = (uint64_t)qz;
+          if (CLAMP) {
+            cx = qx < 0 ? 0 : (cx > topx ? topx : cx);
+            cy = qy < 0 ? 0 : (cy > topy ? topy : cy);
+            cz = qz < 0 ? 0 : (cz > topz ? topz : cz);
+          } else {
+            // 0 <= q <= top; a negative q wraps to a huge unsigned value
+            if (cx > topx || cy > topy || cz > topz) continue;
+          }
+          const uint32_t ix = (uint32_t)(cx >> 32), iy = (uint32_t)(cy >> 32), iz = (uint32_t)(cz >> 32);
+          const uint32_t fx = (uint32_t)cx, fy = (uint32_t)cy, fz = (uint32_t)cz;
+          // (nz+1) * ny < 2^24 rows, so 24-bit multiplies are exact
+          const uint32_t off = (__umul24(__umul24(iz, NY) + iy, MX) + ix) * 8u;
+          const uint2_t q0 = __builtin_amdgcn_raw_buffer_load_b64(rsrc, off, 0, 0);
+          const uint2_t q1 = __builtin_amdgcn_raw_buffer_load_b64(rsrc, off, SZ, 0);
+          const uint32_t fb = frow[x];
+          // (65535 - wx) in the low half, wx in the high half
+          const uint32_t wpack = (fx & 0xFFFF0000u) | ((fx >> 16) ^ 0xFFFFu);
+          const uint32_t a00 = lerp_x(q0.x, wpack), a10 = lerp_x(q0.y, wpack);
+          const uint32_t a01 = lerp_x(q1.x, wpack), a11 = lerp_x(q1.y, wpack);
+          const uint32_t wy = fy >> 16, wz = fz >> 16;
+          const double wyd = (double)wy, wzd = (double)wz;
+          const double A00 = (double)a00, A10 = (double)a10, A01 = (double)a01, A11 = (double)a11;
+          const double b0 = fma(A10 - A00, wyd, A00 * 65536.0);  // exact, < 2^48
+          const double b1 = fma(A11 - A01, wyd, A01 * 65536.0);  // exact, < 2^48
+          const double V = fma(b1 - b0, wzd, b0 * 65536.0);      // exact value rounded once
+          const double tb = V * scale;
+          uint32_t bm = (uint32_t)tb;
+          const double fr = tb - (double)bm;
+          if (fr < kEdge || fr > 1.0 - kEdge) bm = exact_bin(a00, a10, a01, a11, wy, wz, Bu, a.div);
+          const uint32_t cell = __umul24(fb, Bu) + bm;
+          if (PACKED)
+            atomicAdd(&lds_hist[cell >> 1], 1u << ((cell & 1u) * 16u));
+          else
+            atomicAdd(&lds_hist[cell], 1u);
         }
-        const uint32_t ix = (uint32_t)(cx >> 32), iy = (uint32_t)(cy >> 32), iz = (uint32_t)(cz >> 32);
-        const uint32_t fx = (uint32_t)cx, fy = (uint32_t)cy, fz = (uint32_t)cz;
-        // padded row index < 4096 * 4097 < 2^24, so 24-bit multiplies are exact
-        const uint32_t off = (__umul24(__umul24(iz, PY) + iy, MX) + ix) * 4u;
-        const uint32_t p00 = __builtin_amdgcn_raw_buffer_load_b32(rsrc, off, 0, 0);
-        const uint32_t p10 = __builtin_amdgcn_raw_buffer_load_b32(rsrc, off, SY, 0);
-        const uint32_t p01 = __builtin_amdgcn_raw_buffer_load_b32(rsrc, off, SZ, 0);
-        const uint32_t p11 = __builtin_amdgcn_raw_buffer_load_b32(rsrc, off, SY + SZ, 0);
-        const uint32_t fb = frow[x];
-        // (65535 - wx) in the low half, wx in the high half
-        const uint32_t wpack = (fx & 0xFFFF0000u) | ((fx >> 16) ^ 0xFFFFu);
-        const uint32_t a00 = lerp_x(p00, wpack), a10 = lerp_x(p10, wpack);
-        const uint32_t a01 = lerp_x(p01, wpack), a11 = lerp_x(p11, wpack);
-        const uint32_t wy = fy >> 16, wz = fz >> 16;
-        const double wyd = (double)wy, wzd = (double)wz;
-        const double A00 = (double)a00, A10 = (double)a10, A01 = (double)a01, A11 = (double)a11;
-        const double b0 = fma(A10 - A00, wyd, A00 * 65536.0);  // exact, < 2^48
-        const double b1 = fma(A11 - A01, wyd, A01 * 65536.0);  // exact, < 2^48
-        const double V = fma(b1 - b0, wzd, b0 * 65536.0);      // exact value rounded once
-        const double tb = V * scale;
-        uint32_t bm = (uint32_t)tb;
-        const double fr = tb - (double)bm;
-        if (fr < kEdge || fr > 1.0 - kEdge) bm = exact_bin(a00, a10, a01, a11, wy, wz, Bu, a.div);
-        const uint32_t cell = __umul24(fb, Bu) + bm;
-        if (PACKED)
-          atomicAdd(&lds_hist[cell >> 1], 1u << ((cell & 1u) * 16u));
-        else
-          atomicAdd(&lds_hist[cell], 1u);
       }
-      // next row: (j+1, k), or (0, k+1) after the last row of a slice
-      rx += Mq[1];
-      ry += Mq[5];
-      rz += Mq[9];
-      if (++j == a.fny) {
-        j = 0;
+      // next group: rows j0+kTileY.., or the first group of the next slice
+      j0 += kTileY;
+      rx += Mq[1] * kTileY;
+      ry += Mq[5] * kTileY;
+      rz += Mq[9] * kTileY;
+      if (j0 >= G * kTileY) {
+        j0 = 0;
+        ++k;
         rx += wrapx;
         ry += wrapy;
         rz += wrapz;
@@ -327,7 +358,7 @@ hipError_t launch_hist_hard(const HardLaunch& L, hipStream_t s) {
   HardArgs a;
   a.transforms = L.transforms;
   a.fbins = L.fbins;
-  a.pairs = L.pairs;
+  a.quads = L.quads;
   a.hist = L.hist;
   a.fnx = L.fixed.nx;
   a.fny = L.fixed.ny;
@@ -335,9 +366,11 @@ hipError_t launch_hist_hard(const HardLaunch& L, hipStream_t s) {
   a.mnx = L.moving.nx;
   a.mny = L.moving.ny;
   a.mnz = L.moving.nz;
-  a.pair_bytes = (uint32_t)((size_t)L.moving.nx * (L.moving.ny + 1) * (L.moving.nz + 1) * 4);
+  a.quad_bytes = (uint32_t)quad_volume_bytes(L.moving.nx, L.moving.ny, L.moving.nz);
+  a.n = L.n;
   a.bins = L.bins;
   a.chunks = L.chunks;
+  a.slab_major = L.slab_major;
   const uint32_t R = (uint32_t)((int32_t)L.moving.hi - (int32_t)L.moving.lo + 1);
   a.scale = ldexp((double)L.bins / (double)R, -48);
   a.div = make_divider(R);

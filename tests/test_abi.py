@@ -128,7 +128,7 @@ def ws_size(f, m, n, bins, n_q, flags=0, grad=0):
 def test_workspace_size_layout():
     a = lambda x: (x + 255) // 256 * 256
     st, n = ws_size(vol(10, 11, 12), vol(9, 8, 7), 5, 32, 2)
-    assert st == 0 and n == a(10 * 11 * 12) + a(9 * 9 * 8 * 4) + a(5 * 32 * 32 * 4)
+    assert st == 0 and n == a(10 * 11 * 12) + a(9 * 8 * 8 * 8) + a(5 * 32 * 32 * 4)
     st, n = ws_size(vol(10, 11, 12), vol(), 5, 32, 2, B.HIST_PARZEN)
     assert st == 0 and n == a(1320) + a(5 * 32 * 32 * 8) + a(5 * 8)
     st, n = ws_size(vol(10, 11, 12), vol(), 5, 32, 2, 0, 1)
