@@ -214,6 +214,8 @@ class Context:
         """Hard MI of many (fixed, moving, transforms) pairs in one launch;
         returns MI[sum n][n_q] with the pairs' rows concatenated."""
         qs, qp = _qarr(q)
+        if not pairs:
+            return torch.zeros((0, len(qs)), dtype=torch.float64)
         arr = (MiPair * len(pairs))()
         total = 0
         keep = []

@@ -87,7 +87,8 @@ int check_common(const mi_volume* f, const mi_volume* m, int32_t n, int32_t bins
 //   fixed bins   u8[nvox_fixed]
 //   hard:        moving quad volume u16x4[mnz+1][mny][mnx],
 //                hist u32[n][B][B]          (only when the caller passes no hist_out)
-//   Parzen:      table f64[n][B][B], count u64[n]
+//   Parzen:      moving quad volume (u16x4, or f32x4 for a float moving
+//                volume) [mnz+1][mny][mnx], table f64[n][B][B], count u64[n]
 //   Parzen grad: + dMI/dp tables f32[n][n_q][B][B]
 struct Layout {
   size_t fbins = 0, quads = 0, hist = 0, table = 0, count = 0, gtab = 0, total = 0;
@@ -106,6 +107,8 @@ Layout layout(const mi_volume* f, const mi_volume* m, int32_t n, int32_t bins, i
     L.hist = off;
     if (need_hist) off += align256(bb * 4 * (size_t)n);
   } else {
+    L.quads = off;
+    off += align256(quad_volume_bytes(m->nx, m->ny, m->nz) * (m->dtype == MI_F32 ? 2 : 1));
     L.table = off;
     off += align256(bb * 8 * (size_t)n);
     L.count = off;
@@ -142,7 +145,12 @@ QList qlist(const double* q, int32_t n_q, int32_t flags) {
 
 }  // namespace
 
+constexpr size_t kStageBytes = 4u << 20;  // pinned staging for the pairs' tables
+
 struct mi_context {
+  void* stage = nullptr;            // pinned host buffer, kStageBytes
+  hipEvent_t stage_done = nullptr;  // recorded after the last copy out of `stage`
+  bool stage_pending = false;
   int device = 0;
   int cu_count = 256;
   int hard_block = 512;   // threads per workgroup of the histogram sweep
@@ -204,6 +212,202 @@ int plan_chunks(const mi_context* ctx, const mi_volume* f, int32_t n, bool packe
   return (int)c;
 }
 
+
+// Workgroups per transform and band for the Parzen sweeps (as plan_chunks).
+int plan_parzen_chunks(const mi_context* ctx, const mi_volume* f, int64_t units) {
+  const int64_t groups = (int64_t)((f->ny + 3) / 4) * f->nz;
+  int64_t c = ((int64_t)ctx->cu_count * 8 + units - 1) / units;
+  if (c < 32) c = 32;
+  if (c > groups) c = groups;
+  return (int)(((c + 7) / 8) * 8);
+}
+
+// Rows of the table per band when `tables` fp32 tables of `bins` columns
+// share a 64 KiB LDS budget.
+int32_t band_rows_for(int32_t bins, int32_t tables) {
+  int32_t r = (int32_t)(65536 / (4 * bins * tables));
+  return r < bins ? r : bins;
+}
+
+// The Parzen path: forward table, MI, and (grad_out != NULL) the gradient.
+int run_parzen(mi_context* ctx, const mi_volume* fixed, const mi_volume* moving,
+               const double* transforms, int32_t n, int32_t bins, const double* q, int32_t n_q,
+               int32_t flags, double* mi_out, uint64_t* overlap_out, double* grad_out, char* ws,
+               const Layout& L, hipStream_t s) {
+  hipError_t e;
+  uint8_t* fb = (uint8_t*)(ws + L.fbins);
+  if ((e = launch_prebin_fixed(desc(fixed), bins, fb, s)) != hipSuccess) return hip_fail(e, "prebin");
+  const bool fq = moving->dtype == MI_F32;
+  void* quads = ws + L.quads;
+  e = fq ? launch_pack_quads_f32(desc(moving), (float4*)quads, s)
+         : launch_pack_quads(desc(moving), (uint2*)quads, s);
+  if (e != hipSuccess) return hip_fail(e, "pack");
+  const size_t bb = (size_t)bins * bins;
+  double* table = (double*)(ws + L.table);
+  uint64_t* count = (uint64_t*)(ws + L.count);
+  if ((e = launch_fill_f64(table, bb * n, s)) != hipSuccess) return hip_fail(e, "fill");
+  if ((e = launch_fill_u32((uint32_t*)count, 2 * (size_t)n, 0u, s)) != hipSuccess) return hip_fail(e, "fill");
+  if (grad_out && (e = launch_fill_f64(grad_out, (size_t)n * n_q * 12, s)) != hipSuccess)
+    return hip_fail(e, "fill");
+
+  ParzenLaunch P;
+  memset(&P, 0, sizeof P);
+  ParzenArgs& a = P.args;
+  a.transforms = transforms;
+  a.fbins = fb;
+  a.quads = quads;
+  a.table = table;
+  a.count = count;
+  a.gtab = (const float*)(ws + L.gtab);
+  a.grad = grad_out;
+  a.fnx = fixed->nx;
+  a.fny = fixed->ny;
+  a.fnz = fixed->nz;
+  a.mnx = moving->nx;
+  a.mny = moving->ny;
+  a.mnz = moving->nz;
+  a.quad_bytes = (uint32_t)(quad_volume_bytes(moving->nx, moving->ny, moving->nz) * (fq ? 2 : 1));
+  a.n = n;
+  a.bins = bins;
+  a.slab_major = 1;
+  a.n_q = n_q;
+  a.sscale = (float)((double)(bins - 4) / (moving->hi - moving->lo));
+  a.dsdv = (double)(bins - 4) / (moving->hi - moving->lo);
+  P.float_quads = fq ? 1 : 0;
+  P.clamp = (flags & MI_BOUNDARY_CLAMP) ? 1 : 0;
+
+  // one launch covers at most 2^31 - 1 workgroups: split the transforms
+  auto sweep = [&](bool backward, int which) -> int {
+    ParzenLaunch part = P;
+    ParzenArgs& pa = part.args;
+    pa.band_rows = band_rows_for(bins, backward ? kParzenQGroup : 1);
+    pa.bands = (bins + pa.band_rows - 1) / pa.band_rows;
+    pa.chunks = plan_parzen_chunks(ctx, fixed, (int64_t)n * pa.bands);
+    const int64_t per_launch = 0x7FFFFFFFll / ((int64_t)pa.chunks * pa.bands);
+    for (int64_t t0 = 0; t0 < n; t0 += per_launch) {
+      pa.n = (int32_t)(n - t0 < per_launch ? n - t0 : per_launch);
+      pa.transforms = transforms + 12 * t0;
+      pa.table = table + bb * t0;
+      pa.count = count + t0;
+      pa.gtab = (const float*)(ws + L.gtab) + bb * n_q * t0;
+      pa.grad = grad_out ? grad_out + (size_t)n_q * 12 * t0 : nullptr;
+      TimedLaunch tl(ctx, which, s);
+      hipError_t err = backward ? launch_parzen_bwd(part, s) : launch_parzen_fwd(part, s);
+      if (err != hipSuccess) return hip_fail(err, backward ? "parzen_bwd" : "parzen_fwd");
+      tl.done();
+    }
+    return MI_OK;
+  };
+  int st;
+  if ((st = sweep(false, 1)) != MI_OK) return st;
+
+  ReduceLaunch R;
+  memset(&R, 0, sizeof R);
+  R.table = table;
+  R.count = count;
+  R.transforms = transforms;
+  R.n = n;
+  R.bins = bins;
+  R.q = qlist(q, n_q, flags);
+  R.mi_out = mi_out;
+  R.overlap_out = overlap_out;
+  TimedLaunch tr(ctx, 4, s);
+  if ((e = launch_mi_reduce(R, s)) != hipSuccess) return hip_fail(e, "mi_reduce");
+  tr.done();
+  if (!grad_out) return MI_OK;
+
+  if ((e = launch_dmi_dp(P, R.q, s)) != hipSuccess) return hip_fail(e, "dmi_dp");
+  for (int32_t q0 = 0; q0 < n_q; q0 += kParzenQGroup) {
+    P.args.q0 = q0;
+    if ((st = sweep(true, 2)) != MI_OK) return st;
+  }
+  return MI_OK;
+}
+
+
+// Layout and work split of a multi-pair call (hard histograms).
+struct PairsPlan {
+  size_t tables = 0, table_bytes = 0, counters = 0, transforms = 0, hist = 0, total = 0;
+  size_t off_desc = 0, off_frow = 0, off_mrow = 0, off_tbase = 0, off_xcd = 0;
+  std::vector<size_t> fbins, quads;
+  std::vector<int32_t> chunks;
+  std::vector<int64_t> frow_base, mrow_base, t_base, xcd_base;  // xcd_base: [8][P+1]
+  int64_t total_t = 0;
+};
+
+int plan_pairs(const mi_pair* pairs, int32_t n_pairs, int32_t bins, int32_t n_q, int32_t flags,
+               PairsPlan& plan) {
+  if (flags & ~(MI_BOUNDARY_CLAMP | MI_TSALLIS_PSEUDOADDITIVE)) return MI_ERR_FLAGS;
+  if (n_pairs < 0 || n_pairs > (1 << 24)) return MI_ERR_COUNT;
+  if (n_pairs > 0 && !pairs) return MI_ERR_NULL;
+  if (bins < 2 || bins > 256) return MI_ERR_BINS;
+  if (n_q < 1 || n_q > MI_MAX_Q) return MI_ERR_Q;
+  const int P = n_pairs;
+  plan.fbins.resize(P);
+  plan.quads.resize(P);
+  plan.chunks.resize(P);
+  plan.frow_base.assign(P + 1, 0);
+  plan.mrow_base.assign(P + 1, 0);
+  plan.t_base.assign(P + 1, 0);
+  plan.xcd_base.assign(8 * (size_t)(P + 1), 0);
+  const bool packed = bins > 128;
+  for (int p = 0; p < P; ++p) {
+    const mi_pair& pr = pairs[p];
+    int st;
+    if ((st = check_volume(&pr.fixed, false)) != MI_OK) return st;
+    if ((st = check_volume(&pr.moving, true)) != MI_OK) return st;
+    if (pr.n_transforms < 0) return MI_ERR_COUNT;
+    if (pr.n_transforms > 0 && !pr.transforms) return MI_ERR_NULL;
+    // slabs of about 128 K voxels (at most 65535 with 16-bit counters),
+    // 8 or more, a multiple of 8
+    const int64_t groups = (int64_t)((pr.fixed.ny + 3) / 4) * pr.fixed.nz;
+    const int64_t gvox = 4 * (int64_t)pr.fixed.nx;
+    int64_t per = (packed ? 65535 : 131072) / gvox;
+    if (per < 1) per = 1;
+    int64_t c = (groups + per - 1) / per;
+    if (c < 8) c = 8;
+    c = ((c + 7) / 8) * 8;
+    plan.chunks[p] = (int32_t)c;
+    plan.frow_base[p + 1] = plan.frow_base[p] + (int64_t)pr.fixed.ny * pr.fixed.nz;
+    plan.mrow_base[p + 1] = plan.mrow_base[p] + (int64_t)pr.moving.ny * (pr.moving.nz + 1);
+    plan.t_base[p + 1] = plan.t_base[p] + pr.n_transforms;
+    for (int x = 0; x < 8; ++x)
+      plan.xcd_base[(size_t)x * (P + 1) + p + 1] =
+          plan.xcd_base[(size_t)x * (P + 1) + p] + (c / 8) * pr.n_transforms;
+  }
+  plan.total_t = plan.t_base[P];
+  if (plan.total_t > (1 << 24)) return MI_ERR_COUNT;
+  size_t off = 0;
+  plan.off_desc = 0;
+  off = align256(sizeof(PairDesc) * P);
+  plan.off_frow = off;
+  off += align256(8 * (size_t)(P + 1));
+  plan.off_mrow = off;
+  off += align256(8 * (size_t)(P + 1));
+  plan.off_tbase = off;
+  off += align256(8 * (size_t)(P + 1));
+  plan.off_xcd = off;
+  off += align256(64 * (size_t)(P + 1));
+  plan.table_bytes = off;
+  size_t w = 0;
+  plan.tables = w;
+  w += plan.table_bytes;
+  plan.counters = w;
+  w += align256(8 * 8);
+  plan.transforms = w;
+  w += align256(96 * (size_t)plan.total_t);
+  plan.hist = w;
+  w += align256(4 * (size_t)bins * bins * (size_t)plan.total_t);
+  for (int p = 0; p < P; ++p) {
+    plan.fbins[p] = w;
+    w += align256(voxels(&pairs[p].fixed));
+    plan.quads[p] = w;
+    w += align256(quad_volume_bytes(pairs[p].moving.nx, pairs[p].moving.ny, pairs[p].moving.nz));
+  }
+  plan.total = w;
+  return MI_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -246,6 +450,12 @@ int mi_create(mi_context** out, int device) {
   if ((e = configure_parzen_kernels()) != hipSuccess) return hip_fail(e, "configure kernels");
   mi_context* c = new mi_context();
   c->device = device;
+  if ((e = hipHostMalloc(&c->stage, kStageBytes, hipHostMallocDefault)) != hipSuccess ||
+      (e = hipEventCreateWithFlags(&c->stage_done, hipEventDisableTiming)) != hipSuccess) {
+    if (c->stage) (void)hipHostFree(c->stage);
+    delete c;
+    return hip_fail(e, "staging buffer");
+  }
   if (const char* b = getenv("MI_TUNE_HARD_BLOCK")) {
     const int v = atoi(b);
     if (v == 256 || v == 512 || v == 1024) c->hard_block = v;
@@ -262,6 +472,9 @@ int mi_create(mi_context** out, int device) {
 
 int mi_destroy(mi_context* ctx) {
   if (!ctx) return MI_OK;
+  if (ctx->stage_pending) (void)hipEventSynchronize(ctx->stage_done);
+  if (ctx->stage_done) (void)hipEventDestroy(ctx->stage_done);
+  if (ctx->stage) (void)hipHostFree(ctx->stage);
   for (int w = 0; w < kTimers; ++w)
     for (auto& ev : ctx->events[w]) {
       (void)hipEventDestroy(ev.start);
@@ -332,7 +545,6 @@ int mi_eval(mi_context* ctx, const mi_volume* fixed, const mi_volume* moving,
   if ((e = hipSetDevice(ctx->device)) != hipSuccess) return hip_fail(e, "hipSetDevice");
   char* ws = (char*)workspace;
   uint8_t* fb = (uint8_t*)(ws + L.fbins);
-  if ((e = launch_prebin_fixed(desc(fixed), bins, fb, s)) != hipSuccess) return hip_fail(e, "prebin");
   const size_t bb = (size_t)bins * bins;
   ReduceLaunch R;
   memset(&R, 0, sizeof R);
@@ -343,6 +555,7 @@ int mi_eval(mi_context* ctx, const mi_volume* fixed, const mi_volume* moving,
   R.mi_out = mi_out;
   R.overlap_out = overlap_out;
   if (!parzen) {
+    if ((e = launch_prebin_fixed(desc(fixed), bins, fb, s)) != hipSuccess) return hip_fail(e, "prebin");
     uint32_t* hist = hist_out ? hist_out : (uint32_t*)(ws + L.hist);
     uint2* quads = (uint2*)(ws + L.quads);
     if ((e = launch_pack_quads(desc(moving), quads, s)) != hipSuccess) return hip_fail(e, "pack");
@@ -374,7 +587,8 @@ int mi_eval(mi_context* ctx, const mi_volume* fixed, const mi_volume* moving,
     }
     R.hist = hist;
   } else {
-    return MI_ERR_UNSUPPORTED;  // Parzen forward: see mi_grad
+    return run_parzen(ctx, fixed, moving, transforms, n, bins, q, n_q, flags, mi_out, overlap_out,
+                      nullptr, ws, L, s);
   }
   TimedLaunch tr(ctx, 4, s);
   if ((e = launch_mi_reduce(R, s)) != hipSuccess) return hip_fail(e, "mi_reduce");
@@ -386,45 +600,132 @@ int mi_grad(mi_context* ctx, const mi_volume* fixed, const mi_volume* moving,
             const double* transforms, int32_t n, int32_t bins, const double* q, int32_t n_q,
             int32_t flags, double* mi_out, double* grad_out, void* workspace,
             size_t workspace_bytes, void* stream) {
-  int st = check_common(fixed, moving, n, bins, q, n_q, flags | MI_HIST_PARZEN, true);
+  int st = check_common(fixed, moving, n, bins, q, n_q, flags, true);
   if (st != MI_OK) return st;
   if ((st = check_q(q, n_q)) != MI_OK) return st;
-  (void)ctx;
-  (void)transforms;
-  (void)mi_out;
-  (void)grad_out;
-  (void)workspace;
-  (void)workspace_bytes;
-  (void)stream;
-  return MI_ERR_UNSUPPORTED;
+  if (n > 0 && (!transforms || !mi_out || !grad_out)) return MI_ERR_NULL;
+  const Layout L = layout(fixed, moving, n, bins, n_q, true, true, false);
+  if (!workspace || workspace_bytes < L.total) return MI_ERR_WORKSPACE;
+  if (!ctx) return MI_ERR_NULL;
+  if (n == 0) return MI_OK;
+  hipError_t e;
+  if ((e = hipSetDevice(ctx->device)) != hipSuccess) return hip_fail(e, "hipSetDevice");
+  return run_parzen(ctx, fixed, moving, transforms, n, bins, q, n_q, flags, mi_out, nullptr,
+                    grad_out, (char*)workspace, L, (hipStream_t)stream);
 }
 
 int mi_pairs_workspace_size(const mi_pair* pairs, int32_t n_pairs, int32_t bins, int32_t n_q,
                             int32_t flags, size_t* bytes) {
-  (void)pairs;
-  (void)n_pairs;
-  (void)bins;
-  (void)n_q;
-  (void)flags;
   if (!bytes) return MI_ERR_NULL;
-  return MI_ERR_UNSUPPORTED;
+  PairsPlan plan;
+  int st = plan_pairs(pairs, n_pairs, bins, n_q, flags, plan);
+  if (st != MI_OK) return st;
+  *bytes = plan.total;
+  return MI_OK;
 }
 
 int mi_eval_pairs(mi_context* ctx, const mi_pair* pairs, int32_t n_pairs, int32_t bins,
                   const double* q, int32_t n_q, int32_t flags, double* mi_out, void* workspace,
                   size_t workspace_bytes, void* stream) {
-  (void)ctx;
-  (void)pairs;
-  (void)n_pairs;
-  (void)bins;
-  (void)q;
-  (void)n_q;
-  (void)flags;
-  (void)mi_out;
-  (void)workspace;
-  (void)workspace_bytes;
-  (void)stream;
-  return MI_ERR_UNSUPPORTED;
+  int st = check_q(q, n_q);
+  if (st != MI_OK) return st;
+  PairsPlan plan;
+  if ((st = plan_pairs(pairs, n_pairs, bins, n_q, flags, plan)) != MI_OK) return st;
+  if (plan.total_t > 0 && !mi_out) return MI_ERR_NULL;
+  if (!workspace || workspace_bytes < plan.total) return MI_ERR_WORKSPACE;
+  if (!ctx) return MI_ERR_NULL;
+  if (plan.total_t == 0) return MI_OK;
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e;
+  if ((e = hipSetDevice(ctx->device)) != hipSuccess) return hip_fail(e, "hipSetDevice");
+  char* ws = (char*)workspace;
+
+  // device tables: descriptors, row / transform / per-XCD item prefixes
+  const int P = n_pairs;
+  std::vector<PairDesc> desc_v(P);
+  for (int p = 0; p < P; ++p) {
+    const mi_pair& pr = pairs[p];
+    PairDesc& d = desc_v[p];
+    memset(&d, 0, sizeof d);
+    d.fixed = pr.fixed.data;
+    d.moving = pr.moving.data;
+    d.transforms = pr.transforms;
+    d.geom = make_hard_geom(desc(&pr.fixed), desc(&pr.moving), (const uint8_t*)(ws + plan.fbins[p]),
+                            (const uint2*)(ws + plan.quads[p]), bins);
+    d.fdtype = pr.fixed.dtype;
+    d.mdtype = pr.moving.dtype;
+    d.flo = pr.fixed.lo;
+    d.fhi = pr.fixed.hi;
+    d.mlo = (int32_t)pr.moving.lo;
+    d.mhi = (int32_t)pr.moving.hi;
+    if (pr.fixed.dtype != MI_F32) d.fdiv = make_divider((uint32_t)(pr.fixed.hi - pr.fixed.lo + 1.0));
+    d.n_t = pr.n_transforms;
+    d.chunks = plan.chunks[p];
+  }
+  std::vector<char> blob(plan.table_bytes, 0);
+  char* b = blob.data();
+  memcpy(b + plan.off_desc, desc_v.data(), sizeof(PairDesc) * P);
+  memcpy(b + plan.off_frow, plan.frow_base.data(), 8 * (P + 1));
+  memcpy(b + plan.off_mrow, plan.mrow_base.data(), 8 * (P + 1));
+  memcpy(b + plan.off_tbase, plan.t_base.data(), 8 * (P + 1));
+  memcpy(b + plan.off_xcd, plan.xcd_base.data(), 8 * 8 * (P + 1));
+  char* dtab = ws + plan.tables;
+  if (plan.table_bytes <= kStageBytes) {
+    if (ctx->stage_pending && (e = hipEventSynchronize(ctx->stage_done)) != hipSuccess)
+      return hip_fail(e, "staging");
+    memcpy(ctx->stage, b, plan.table_bytes);
+    if ((e = hipMemcpyAsync(dtab, ctx->stage, plan.table_bytes, hipMemcpyHostToDevice, s)) != hipSuccess)
+      return hip_fail(e, "table upload");
+    if ((e = hipEventRecord(ctx->stage_done, s)) != hipSuccess) return hip_fail(e, "staging");
+    ctx->stage_pending = true;
+  } else {
+    // tables beyond the staging buffer: wait for earlier users of the
+    // workspace, then copy synchronously from pageable memory
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "table upload");
+    if ((e = hipMemcpy(dtab, b, plan.table_bytes, hipMemcpyHostToDevice)) != hipSuccess)
+      return hip_fail(e, "table upload");
+  }
+
+  PairsLaunch L;
+  memset(&L, 0, sizeof L);
+  PairsArgs& a = L.args;
+  a.pairs = (const PairDesc*)(dtab + plan.off_desc);
+  a.n_pairs = P;
+  a.frow_base = (const int64_t*)(dtab + plan.off_frow);
+  a.mrow_base = (const int64_t*)(dtab + plan.off_mrow);
+  a.t_base = (const int64_t*)(dtab + plan.off_tbase);
+  a.xcd_base = (const int64_t*)(dtab + plan.off_xcd);
+  a.counters = (unsigned long long*)(ws + plan.counters);
+  a.transforms = (double*)(ws + plan.transforms);
+  a.hist = (uint32_t*)(ws + plan.hist);
+  a.bins = bins;
+  L.total_t = plan.total_t;
+  L.fixed_rows = plan.frow_base[P];
+  L.moving_rows = plan.mrow_base[P];
+  L.clamp = (flags & MI_BOUNDARY_CLAMP) ? 1 : 0;
+  L.packed = bins > 128 ? 1 : 0;
+  L.cu_count = ctx->cu_count;
+  const size_t bb = (size_t)bins * bins;
+  if ((e = launch_fill_u32((uint32_t*)a.counters, 16, 0u, s)) != hipSuccess) return hip_fail(e, "fill");
+  if ((e = launch_fill_u32(a.hist, bb * plan.total_t, 0u, s)) != hipSuccess) return hip_fail(e, "fill");
+  if ((e = launch_pairs_prep(L, s)) != hipSuccess) return hip_fail(e, "pairs prep");
+  {
+    TimedLaunch tl(ctx, 3, s);
+    if ((e = launch_pairs_hist(L, s)) != hipSuccess) return hip_fail(e, "pairs hist");
+    tl.done();
+  }
+  ReduceLaunch R;
+  memset(&R, 0, sizeof R);
+  R.hist = a.hist;
+  R.transforms = a.transforms;
+  R.n = (int32_t)plan.total_t;
+  R.bins = bins;
+  R.q = qlist(q, n_q, flags);
+  R.mi_out = mi_out;
+  TimedLaunch tr(ctx, 4, s);
+  if ((e = launch_mi_reduce(R, s)) != hipSuccess) return hip_fail(e, "mi_reduce");
+  tr.done();
+  return MI_OK;
 }
 
 }  // extern "C"

@@ -56,6 +56,123 @@ __device__ __forceinline__ bool quantize_transform(const double* __restrict__ M,
   return ok;
 }
 
+// ---------------------------------------------------------------------------
+// per-voxel input preparation shared by the single-pair and multi-pair paths
+// ---------------------------------------------------------------------------
+
+// Fixed bin of an integer intensity: floor((clamp(u) - lo) * B / R).
+__device__ __forceinline__ uint32_t fixed_bin_int(int32_t u, int32_t lo, int32_t hi, uint32_t bins,
+                                                  Divider d) {
+  u = u < lo ? lo : (u > hi ? hi : u);
+  return div_small((uint32_t)(u - lo) * bins, d);
+}
+
+// Fixed bin of a float intensity: min(B-1, floor(((u - lo)/(hi - lo)) * B))
+// in fp64, each step one IEEE operation.
+__device__ __forceinline__ uint32_t fixed_bin_real(double u, double lo, double hi, int32_t bins) {
+  u = u < lo ? lo : (u > hi ? hi : u);
+  const double r = __ddiv_rn(__dsub_rn(u, lo), __dsub_rn(hi, lo));
+  const int32_t b = (int32_t)floor(__dmul_rn(r, (double)bins));
+  return (uint32_t)(b > bins - 1 ? bins - 1 : (b < 0 ? 0 : b));
+}
+
+// Clamped, offset intensity v' = clamp(v, lo, hi) - lo.
+__device__ __forceinline__ uint32_t clamp_offset(int32_t v, int32_t lo, int32_t hi) {
+  v = v < lo ? lo : (v > hi ? hi : v);
+  return (uint32_t)(v - lo);
+}
+
+// ---------------------------------------------------------------------------
+// the fixed-volume sweep shared by the histogram kernels
+// ---------------------------------------------------------------------------
+
+constexpr int kTileX = 16, kTileY = 4;  // a wave64 covers 16 x 4 fixed voxels at a time
+
+// Maps workgroup id -> (transform, slab, band).  Workgroups are dealt
+// round-robin to the 8 XCDs, so XCD x receives ids x, x+8, ...; those all
+// take slabs from the x-th eighth of the fixed volume.  Slab-major order
+// walks that eighth one thin slab at a time, all transforms (and bands) per
+// slab, so the workgroups resident on an XCD at once share one slab's
+// moving footprint in that XCD's L2; transform-major order finishes a
+// transform's slabs before the next transform.
+__device__ __forceinline__ void block_work(int32_t chunks, int32_t n, int32_t bands,
+                                           int32_t slab_major, uint32_t& t, uint32_t& chunk,
+                                           uint32_t& band) {
+  const uint32_t bid = blockIdx.x;
+  const uint32_t xcd = bid & 7u, slot = bid >> 3;
+  const uint32_t c8 = (uint32_t)chunks >> 3;
+  const uint32_t nb = (uint32_t)bands;
+  if (slab_major) {
+    const uint32_t per = (uint32_t)n * nb;
+    const uint32_t cl = slot / per, rem = slot - cl * per;
+    t = rem / nb;
+    band = rem - t * nb;
+    chunk = xcd * c8 + cl;
+  } else {
+    const uint32_t per = c8 * nb;
+    t = slot / per;
+    const uint32_t rem = slot - t * per;
+    band = rem / c8;
+    chunk = xcd * c8 + (rem - band * c8);
+  }
+}
+
+// One wave's walk over its share of a slab: groups of kTileY consecutive
+// rows of one slice, visited in order with exact Q32 row coordinates.
+// Lane (dx, dy) of the 16 x 4 tile starts at r + lane_off and steps by
+// `step` = 16 M[:,0] along x.
+struct GroupWalk {
+  int64_t g, g1;
+  int32_t j0, k, G;
+  int64_t r[3], lane_off[3], step[3], adv[3], wrap[3];
+
+  __device__ __forceinline__ void init(const int64_t* Mq, int32_t fny, int32_t fnz,
+                                       int32_t chunks, uint32_t chunk, int wave, int nwaves,
+                                       int dx, int dy) {
+    G = (fny + kTileY - 1) / kTileY;
+    const int64_t groups = (int64_t)G * fnz;
+    const int64_t s0 = groups * chunk / chunks, s1 = groups * (chunk + 1) / chunks;
+    g = s0 + (s1 - s0) * wave / nwaves;
+    g1 = s0 + (s1 - s0) * (wave + 1) / nwaves;
+    k = (int32_t)(g / G);
+    j0 = (int32_t)(g - (int64_t)k * G) * kTileY;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const int64_t m0 = Mq[4 * a], m1 = Mq[4 * a + 1], m2 = Mq[4 * a + 2], m3 = Mq[4 * a + 3];
+      r[a] = m1 * j0 + m2 * k + m3;
+      lane_off[a] = m0 * dx + m1 * dy;
+      step[a] = m0 * kTileX;
+      adv[a] = m1 * kTileY;
+      wrap[a] = m2 - m1 * ((int64_t)G * kTileY);
+    }
+  }
+
+  __device__ __forceinline__ void next() {
+    ++g;
+    j0 += kTileY;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) r[a] += adv[a];
+    if (j0 >= G * kTileY) {
+      j0 = 0;
+      ++k;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) r[a] += wrap[a];
+    }
+  }
+};
+
+// Geometry of one fixed/moving pair for the hard-binned sweep.
+struct HardGeom {
+  const uint8_t* fbins;  // fixed bins, [fnz][fny][fnx]
+  const uint2* quads;    // moving quad volume, [mnz+1][mny][mnx]
+  int32_t fnx, fny, fnz;
+  int32_t mnx, mny, mnz;
+  uint32_t quad_bytes;
+  int32_t bins;
+  double scale;  // B / (R 2^48), R = moving hi - lo + 1
+  Divider div;   // floor(X / R) for the exact fallback
+};
+
 // Host-side launch descriptions.
 struct VolumeDesc {
   const void* data;
@@ -93,12 +210,79 @@ struct ReduceLaunch {
   uint64_t* overlap_out; // [n] or NULL
 };
 
+// Parzen sweeps (see parzen.hip).
+struct ParzenArgs {
+  const double* transforms;
+  const uint8_t* fbins;
+  const void* quads;   // uint2 (integer moving) or float4 (float moving) per voxel
+  double* table;       // [n][B][B] forward masses (fp64)
+  uint64_t* count;     // [n] voxels that took part
+  const float* gtab;   // [n][n_q][B][B] d MI / d p
+  double* grad;        // [n][n_q][12]
+  int32_t fnx, fny, fnz;
+  int32_t mnx, mny, mnz;
+  uint32_t quad_bytes;
+  int32_t n, bins, chunks, bands, band_rows, slab_major;
+  int32_t n_q, q0;     // backward: entropies [q0, q0 + NQG) of n_q
+  float sscale;        // (B - 4) / (hi - lo)
+  double dsdv;         // (B - 4) / (hi - lo), fp64
+};
+
+constexpr int kParzenQGroup = 2;  // entropies per backward sweep
+
+struct ParzenLaunch {
+  ParzenArgs args;
+  int32_t float_quads;  // 1: moving volume is fp32 (16-byte quads)
+  int32_t clamp;
+};
+
 hipError_t launch_fill_u32(uint32_t* p, size_t n, uint32_t value, hipStream_t s);
 hipError_t launch_fill_f64(double* p, size_t n, hipStream_t s);
 hipError_t launch_prebin_fixed(const VolumeDesc& f, int bins, uint8_t* out, hipStream_t s);
 hipError_t launch_pack_quads(const VolumeDesc& m, uint2* out, hipStream_t s);
 hipError_t launch_hist_hard(const HardLaunch& L, hipStream_t s);
+
+// Many fixed/moving pairs of uneven sizes (see pairs.hip).
+struct PairDesc {
+  const void* fixed;
+  const void* moving;
+  const double* transforms;  // caller's [n_t][12]
+  HardGeom geom;             // fbins / quads point into the workspace
+  int32_t fdtype, mdtype;
+  double flo, fhi;           // fixed range (fp64 rule for float fixed volumes)
+  int32_t mlo, mhi;          // moving range
+  Divider fdiv;              // floor(X / R_fixed)
+  int32_t n_t, chunks;       // transforms, slabs (a multiple of 8)
+};
+
+struct PairsArgs {
+  const PairDesc* pairs;
+  int32_t n_pairs;
+  const int64_t* frow_base;  // [P+1] prefix of fixed rows
+  const int64_t* mrow_base;  // [P+1] prefix of quad rows, (mnz+1)*mny per pair
+  const int64_t* t_base;     // [P+1] prefix of transforms
+  const int64_t* xcd_base;   // [8][P+1] prefix of work items per XCD
+  unsigned long long* counters;  // [8] work-queue heads
+  double* transforms;        // [T][12], gathered
+  uint32_t* hist;            // [T][B][B]
+  int32_t bins;
+};
+
+struct PairsLaunch {
+  PairsArgs args;
+  int64_t total_t, fixed_rows, moving_rows;
+  int32_t clamp, packed, cu_count;
+};
+
+hipError_t launch_pairs_prep(const PairsLaunch& L, hipStream_t s);
+hipError_t launch_pairs_hist(const PairsLaunch& L, hipStream_t s);
+HardGeom make_hard_geom(const VolumeDesc& fixed, const VolumeDesc& moving, const uint8_t* fbins,
+                        const uint2* quads, int32_t bins);
 hipError_t launch_mi_reduce(const ReduceLaunch& L, hipStream_t s);
+hipError_t launch_pack_quads_f32(const VolumeDesc& m, float4* out, hipStream_t s);
+hipError_t launch_parzen_fwd(const ParzenLaunch& L, hipStream_t s);
+hipError_t launch_dmi_dp(const ParzenLaunch& L, const QList& q, hipStream_t s);
+hipError_t launch_parzen_bwd(const ParzenLaunch& L, hipStream_t s);
 hipError_t configure_kernels();
 
 }  // namespace gemi

@@ -1,0 +1,173 @@
+// Hard-binned MI of many fixed/moving pairs of uneven sizes, each with its
+// own transforms, in one persistent launch (the batched evaluation behind
+// the exhaustive per-family sweeps of the Methodology, for many volumes).
+//
+// Work items are (pair, slab, transform) triples.  Each pair's slabs are
+// split into 8 equal shares, one per XCD, and every XCD has its own work
+// queue: a workgroup (resident for the whole launch) repeatedly takes the
+// next item of its XCD's queue with one atomic, sweeps that slab for that
+// transform into its LDS histogram, adds the histogram into the
+// transform's HBM histogram and clears it.  Items are ordered pair-major,
+// then slab-major, so the workgroups of an XCD work on one slab of one pair
+// at a time and share its moving footprint in L2.  Every workgroup leaves
+// the loop once its queue is empty, so the grid always drains.
+//
+// Per-pair fixed bins and moving quad volumes are prepared by two row
+// kernels over all pairs, and the transforms are gathered into one array
+// for the MI reduction.
+#include "common.h"
+#include "sweep.h"
+
+namespace gemi {
+
+// Largest p with base[p] <= v, for base[0] = 0 <= v < base[P].
+__device__ __forceinline__ int find_pair(const int64_t* __restrict__ base, int P, int64_t v) {
+  int lo = 0, hi = P;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (base[mid] <= v)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ int32_t load_int(const void* p, int32_t dtype, size_t i) {
+  switch (dtype) {
+  case 0: return ((const uint8_t*)p)[i];
+  case 1: return ((const uint16_t*)p)[i];
+  default: return ((const int16_t*)p)[i];
+  }
+}
+
+__global__ void gather_transforms_kernel(PairsArgs a, int64_t total) {
+  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < total;
+       g += (int64_t)gridDim.x * blockDim.x) {
+    const int p = find_pair(a.t_base, a.n_pairs, g);
+    const double* src = a.pairs[p].transforms + 12 * (g - a.t_base[p]);
+    for (int e = 0; e < 12; ++e) a.transforms[12 * g + e] = src[e];
+  }
+}
+
+// One workgroup per fixed row: fixed bins.
+__global__ void prep_fixed_kernel(PairsArgs a, int64_t rows) {
+  for (int64_t r = blockIdx.x; r < rows; r += gridDim.x) {
+    const int p = find_pair(a.frow_base, a.n_pairs, r);
+    const PairDesc& d = a.pairs[p];
+    const int64_t row = r - a.frow_base[p];
+    const int32_t nx = d.geom.fnx;
+    uint8_t* __restrict__ out = (uint8_t*)d.geom.fbins + row * nx;
+    const size_t base = (size_t)row * nx;
+    for (int32_t x = threadIdx.x; x < nx; x += blockDim.x) {
+      uint32_t b;
+      if (d.fdtype == 3)
+        b = fixed_bin_real((double)((const float*)d.fixed)[base + x], d.flo, d.fhi, d.geom.bins);
+      else
+        b = fixed_bin_int(load_int(d.fixed, d.fdtype, base + x), (int32_t)d.flo, (int32_t)d.fhi,
+                          (uint32_t)d.geom.bins, d.fdiv);
+      out[x] = (uint8_t)b;
+    }
+  }
+}
+
+// One workgroup per quad row (z <= nz, y < ny): the moving quad volume, with
+// the layout and clamping of the single-pair path.
+__global__ void prep_moving_kernel(PairsArgs a, int64_t rows) {
+  for (int64_t r = blockIdx.x; r < rows; r += gridDim.x) {
+    const int p = find_pair(a.mrow_base, a.n_pairs, r);
+    const PairDesc& d = a.pairs[p];
+    const int64_t row = r - a.mrow_base[p];
+    const int32_t nx = d.geom.mnx, ny = d.geom.mny, nz = d.geom.mnz;
+    const int32_t z = (int32_t)(row / ny), y = (int32_t)(row - (int64_t)z * ny);
+    const int32_t zs = z < nz ? z : nz - 1;
+    const size_t r0 = ((size_t)zs * ny + y) * nx;
+    const size_t r1 = r0 + (y + 1 < ny ? nx : 0);
+    uint2* __restrict__ out = (uint2*)d.geom.quads + row * nx;
+    for (int32_t x = threadIdx.x; x < nx; x += blockDim.x) {
+      const int32_t x1 = x + 1 < nx ? x + 1 : nx - 1;
+      const uint32_t a0 = clamp_offset(load_int(d.moving, d.mdtype, r0 + x), d.mlo, d.mhi);
+      const uint32_t a1 = clamp_offset(load_int(d.moving, d.mdtype, r0 + x1), d.mlo, d.mhi);
+      const uint32_t b0 = clamp_offset(load_int(d.moving, d.mdtype, r1 + x), d.mlo, d.mhi);
+      const uint32_t b1 = clamp_offset(load_int(d.moving, d.mdtype, r1 + x1), d.mlo, d.mhi);
+      out[x] = make_uint2(a0 | (a1 << 16), b0 | (b1 << 16));
+    }
+  }
+}
+
+template <bool CLAMP, bool PACKED, int NT>
+__global__ __launch_bounds__(NT) void hist_pairs_kernel(PairsArgs a) {
+  extern __shared__ uint32_t lds_hist[];
+  __shared__ int64_t item_sh;
+  const int B = a.bins;
+  const int words = PACKED ? (B * B + 1) / 2 : B * B;
+  for (int e = threadIdx.x; e < words; e += NT) lds_hist[e] = 0;
+  const uint32_t xcd = blockIdx.x & 7u;
+  const int64_t* __restrict__ xbase = a.xcd_base + (int64_t)xcd * (a.n_pairs + 1);
+  const int64_t total = xbase[a.n_pairs];
+  for (;;) {
+    if (threadIdx.x == 0) item_sh = (int64_t)atomicAdd(&a.counters[xcd], 1ull);
+    __syncthreads();
+    const int64_t item = item_sh;
+    if (item >= total) break;  // the same for every thread of the workgroup
+    const int p = find_pair(xbase, a.n_pairs, item);
+    const PairDesc& d = a.pairs[p];
+    const int64_t rem = item - xbase[p];
+    const int64_t slab = rem / d.n_t, tl = rem - slab * d.n_t;
+    const uint32_t chunk = xcd * (uint32_t)(d.chunks >> 3) + (uint32_t)slab;
+    const int64_t t = a.t_base[p] + tl;
+    int64_t Mq[12];
+    const bool ok = quantize_transform(a.transforms + 12 * t, Mq);
+    if (ok) sweep_hard<CLAMP, PACKED, NT / 64>(d.geom, Mq, d.chunks, chunk, lds_hist);
+    __syncthreads();
+    if (ok) flush_hist<PACKED, NT>(lds_hist, B, a.hist + (size_t)t * B * B, true);
+    __syncthreads();
+  }
+}
+
+static unsigned row_grid(int64_t rows) {
+  return (unsigned)(rows < 65536 ? (rows > 0 ? rows : 1) : 65536);
+}
+
+hipError_t launch_pairs_prep(const PairsLaunch& L, hipStream_t s) {
+  if (L.total_t > 0) {
+    const int64_t blocks = (L.total_t + 255) / 256;
+    hipLaunchKernelGGL(gather_transforms_kernel, dim3((unsigned)(blocks < 4096 ? blocks : 4096)),
+                       dim3(256), 0, s, L.args, L.total_t);
+  }
+  if (L.fixed_rows > 0)
+    hipLaunchKernelGGL(prep_fixed_kernel, dim3(row_grid(L.fixed_rows)), dim3(256), 0, s, L.args,
+                       L.fixed_rows);
+  if (L.moving_rows > 0)
+    hipLaunchKernelGGL(prep_moving_kernel, dim3(row_grid(L.moving_rows)), dim3(256), 0, s, L.args,
+                       L.moving_rows);
+  return hipGetLastError();
+}
+
+constexpr int kPairsBlock = 512;
+
+template <bool CLAMP, bool PACKED>
+static hipError_t pairs_variant(const PairsLaunch& L, hipStream_t s) {
+  const int B = L.args.bins;
+  const size_t lds = PACKED ? (((size_t)B * B + 1) / 2) * 4 : (size_t)B * B * 4;
+  const void* fn = (const void*)hist_pairs_kernel<CLAMP, PACKED, kPairsBlock>;
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
+  if (e != hipSuccess) return e;
+  int per_cu = 0;
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kPairsBlock, lds);
+  if (e != hipSuccess) return e;
+  if (per_cu < 1) per_cu = 1;
+  // every queue needs workgroups: a multiple of 8 (one share per XCD)
+  const unsigned grid = (unsigned)(((per_cu * L.cu_count + 7) / 8) * 8);
+  hipLaunchKernelGGL((hist_pairs_kernel<CLAMP, PACKED, kPairsBlock>), dim3(grid), dim3(kPairsBlock),
+                     lds, s, L.args);
+  return hipGetLastError();
+}
+
+hipError_t launch_pairs_hist(const PairsLaunch& L, hipStream_t s) {
+  if (L.clamp)
+    return L.packed ? pairs_variant<true, true>(L, s) : pairs_variant<true, false>(L, s);
+  return L.packed ? pairs_variant<false, true>(L, s) : pairs_variant<false, false>(L, s);
+}
+
+}  // namespace gemi

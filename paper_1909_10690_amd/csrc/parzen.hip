@@ -1,8 +1,448 @@
-// Parzen (cubic B-spline) joint histogram and its backward pass.
+// Parzen-windowed (cubic B-spline) joint histogram, its MI gradient table
+// and the backward sweep, for gfx950.
+//
+// The fixed side keeps its hard bin; the moving side spreads each voxel
+// over 4 bins with the centred cubic B-spline beta3 at
+// s = 1 + (v - lo)/(hi - lo) * (B - 4), v the trilinear moving value.  The
+// table p = h / N makes MI a smooth function of the transform, so a
+// gradient optimiser of Eq. (3) can use d MI / d M, the derivative with
+// respect to the 12 entries of the index-space matrix:
+//   d MI/d M[r][c] = (ds/dv) / N * sum_x w(x) * dv/dy_r(x) * x~_c,
+//   w(x) = -sum_kappa G(bf(x), kappa) * beta3'(kappa - s(x)),
+// with G = d MI / d p (per entropy) built once per transform from the
+// forward table.  The backward sweep recomputes every voxel's taps rather
+// than storing them.
+//
+// Both sweeps walk the fixed volume like the hard-binned one (16 x 4 voxel
+// wave tiles, slab-major workgroup order) and read the same quad volume:
+// the 2x2x2 neighbourhood in two loads, as exact 16-bit integers (integer
+// moving volumes) or fp32 (float moving volumes).  A workgroup accumulates
+// one band of table rows (fixed bins) in LDS in fp32; bands keep large
+// tables within LDS, and a voxel outside the band costs only its fixed-bin
+// read.  Workgroup partials are merged into fp64 in HBM.
 #include "common.h"
 
 namespace gemi {
 
-hipError_t configure_parzen_kernels() { return hipSuccess; }
+// ---------------------------------------------------------------------------
+// fp32 quad volume for float moving volumes
+// ---------------------------------------------------------------------------
+
+// out[z][y][x] (z <= nz) = (v'(x,y), v'(x1,y), v'(x,y1), v'(x1,y1)),
+// v' = clamp(v, lo, hi) - lo, neighbour indices clamped, slice nz = nz-1.
+__global__ void pack_quads_f32_kernel(const float* __restrict__ v, int32_t nx, int32_t ny,
+                                      int32_t nz, float lo, float hi, float4* __restrict__ out) {
+  const int32_t y = blockIdx.y, z = blockIdx.z;
+  float4* __restrict__ orow = out + ((size_t)z * ny + y) * nx;
+  const int32_t zs = z < nz ? z : nz - 1;
+  const float* __restrict__ r0 = v + ((size_t)zs * ny + y) * nx;
+  const float* __restrict__ r1 = r0 + (y + 1 < ny ? nx : 0);
+  auto c = [&](float a) -> float { return fminf(fmaxf(a, lo), hi) - lo; };
+  for (int32_t x = threadIdx.x; x < nx; x += blockDim.x) {
+    const int32_t x1 = x + 1 < nx ? x + 1 : nx - 1;
+    orow[x] = make_float4(c(r0[x]), c(r0[x1]), c(r1[x]), c(r1[x1]));
+  }
+}
+
+hipError_t launch_pack_quads_f32(const VolumeDesc& m, float4* out, hipStream_t s) {
+  const dim3 grid(1, (unsigned)m.ny, (unsigned)m.nz + 1);
+  hipLaunchKernelGGL(pack_quads_f32_kernel, grid, dim3(256), 0, s, (const float*)m.data, m.nx,
+                     m.ny, m.nz, (float)m.lo, (float)m.hi, out);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// per-voxel sample shared by the forward and backward sweeps
+// ---------------------------------------------------------------------------
+
+typedef unsigned int uint2_t __attribute__((ext_vector_type(2)));
+typedef float float4_t __attribute__((ext_vector_type(4)));
+
+// Corner values c[z][y][x] of the 2x2x2 neighbourhood.
+template <bool FQ>
+__device__ __forceinline__ void gather(const __amdgpu_buffer_rsrc_t& rsrc, uint32_t idx,
+                                       int32_t slice_bytes, float c[2][2][2]) {
+  if (FQ) {
+    const float4_t a = __builtin_bit_cast(float4_t, __builtin_amdgcn_raw_buffer_load_b128(rsrc, idx * 16u, 0, 0));
+    const float4_t b = __builtin_bit_cast(float4_t, __builtin_amdgcn_raw_buffer_load_b128(rsrc, idx * 16u, slice_bytes, 0));
+    c[0][0][0] = a.x; c[0][0][1] = a.y; c[0][1][0] = a.z; c[0][1][1] = a.w;
+    c[1][0][0] = b.x; c[1][0][1] = b.y; c[1][1][0] = b.z; c[1][1][1] = b.w;
+  } else {
+    const uint2_t a = __builtin_amdgcn_raw_buffer_load_b64(rsrc, idx * 8u, 0, 0);
+    const uint2_t b = __builtin_amdgcn_raw_buffer_load_b64(rsrc, idx * 8u, slice_bytes, 0);
+    c[0][0][0] = (float)(a.x & 0xFFFFu); c[0][0][1] = (float)(a.x >> 16);
+    c[0][1][0] = (float)(a.y & 0xFFFFu); c[0][1][1] = (float)(a.y >> 16);
+    c[1][0][0] = (float)(b.x & 0xFFFFu); c[1][0][1] = (float)(b.x >> 16);
+    c[1][1][0] = (float)(b.y & 0xFFFFu); c[1][1][1] = (float)(b.y >> 16);
+  }
+}
+
+__device__ __forceinline__ float lerpf(float a, float b, float t) { return fmaf(t, b - a, a); }
+
+// The four B-spline weights beta3(kappa0 + i - s), kappa0 = floor(s) - 1,
+// as polynomials in the fraction f = s - floor(s).
+__device__ __forceinline__ void bspline_weights(float f, float w[4]) {
+  const float f2 = f * f, f3 = f2 * f, g = 1.0f - f;
+  w[0] = g * g * g * (1.0f / 6.0f);
+  w[1] = fmaf(0.5f, f3, 2.0f / 3.0f - f2);
+  w[2] = (fmaf(-3.0f, f3, fmaf(3.0f, f2, fmaf(3.0f, f, 1.0f)))) * (1.0f / 6.0f);
+  w[3] = f3 * (1.0f / 6.0f);
+}
+
+// Their derivatives beta3'(kappa0 + i - s).
+__device__ __forceinline__ void bspline_slopes(float f, float d[4]) {
+  const float g = 1.0f - f;
+  d[0] = 0.5f * g * g;
+  d[1] = f * fmaf(-1.5f, f, 2.0f);
+  d[2] = g * fmaf(1.5f, g, -2.0f);
+  d[3] = -0.5f * f * f;
+}
+
+// Sweep geometry of one workgroup.
+struct SweepCtx {
+  uint32_t t, chunk, band;
+  int32_t r_lo, r_hi;  // fixed-bin rows of this band
+};
+
+// ---------------------------------------------------------------------------
+// forward: Parzen table
+// ---------------------------------------------------------------------------
+
+template <bool FQ, bool CLAMP, int NT>
+__global__ __launch_bounds__(NT) void parzen_fwd_kernel(ParzenArgs a) {
+  extern __shared__ float lds_tab[];
+  __shared__ uint32_t lds_count;
+  const int B = a.bins;
+  SweepCtx sc;
+  block_work(a.chunks, a.n, a.bands, a.slab_major, sc.t, sc.chunk, sc.band);
+  sc.r_lo = (int32_t)sc.band * a.band_rows;
+  sc.r_hi = min(B, sc.r_lo + a.band_rows);
+  const int cells = (sc.r_hi - sc.r_lo) * B;
+  for (int e = threadIdx.x; e < cells; e += NT) lds_tab[e] = 0.0f;
+  if (threadIdx.x == 0) lds_count = 0;
+  int64_t Mq[12];
+  const bool ok = quantize_transform(a.transforms + 12 * (size_t)sc.t, Mq);
+  __syncthreads();
+  uint32_t taken = 0;
+  if (ok) {
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int dx = lane & (kTileX - 1), dy = lane / kTileX;
+    GroupWalk w;
+    w.init(Mq, a.fny, a.fnz, a.chunks, sc.chunk, wave, NT / 64, dx, dy);
+    const uint64_t top[3] = {(uint64_t)(a.mnx - 1) << 32, (uint64_t)(a.mny - 1) << 32,
+                             (uint64_t)(a.mnz - 1) << 32};
+    const uint32_t NY = (uint32_t)a.mny, MX = (uint32_t)a.mnx;
+    const int32_t SZ = (FQ ? 16 : 8) * a.mnx * a.mny;
+    const __amdgpu_buffer_rsrc_t rsrc =
+        __builtin_amdgcn_make_buffer_rsrc((void*)a.quads, (short)0, (int)a.quad_bytes, 0x00020000);
+    const float smax = (float)(B - 3);
+    for (; w.g < w.g1; w.next()) {
+      const int32_t j = w.j0 + dy;
+      if (j >= a.fny) continue;
+      const uint8_t* __restrict__ frow = a.fbins + ((int64_t)w.k * a.fny + j) * a.fnx;
+      int64_t q[3];
+#pragma unroll
+      for (int r = 0; r < 3; ++r) q[r] = w.r[r] + w.lane_off[r];
+      for (int x = dx; x < a.fnx; x += kTileX) {
+        uint64_t cq[3];
+        bool inside = true;
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+          cq[r] = (uint64_t)q[r];
+          if (CLAMP) cq[r] = q[r] < 0 ? 0 : (cq[r] > top[r] ? top[r] : cq[r]);
+          else inside = inside && cq[r] <= top[r];
+          q[r] += w.step[r];
+        }
+        if (!inside) continue;
+        ++taken;
+        const int32_t fb = frow[x];
+        if (fb < sc.r_lo || fb >= sc.r_hi) continue;
+        const uint32_t idx = __umul24(__umul24((uint32_t)(cq[2] >> 32), NY) + (uint32_t)(cq[1] >> 32), MX) +
+                             (uint32_t)(cq[0] >> 32);
+        float c[2][2][2];
+        gather<FQ>(rsrc, idx, SZ, c);
+        const float tx = (float)(uint32_t)cq[0] * 2.3283064365386963e-10f;
+        const float ty = (float)(uint32_t)cq[1] * 2.3283064365386963e-10f;
+        const float tz = (float)(uint32_t)cq[2] * 2.3283064365386963e-10f;
+        const float v0 = lerpf(lerpf(c[0][0][0], c[0][0][1], tx), lerpf(c[0][1][0], c[0][1][1], tx), ty);
+        const float v1 = lerpf(lerpf(c[1][0][0], c[1][0][1], tx), lerpf(c[1][1][0], c[1][1][1], tx), ty);
+        const float v = lerpf(v0, v1, tz);
+        const float s = fminf(fmaxf(fmaf(v, a.sscale, 1.0f), 1.0f), smax);
+        const float fl = floorf(s);
+        float wt[4];
+        bspline_weights(s - fl, wt);
+        float* cell = lds_tab + (fb - sc.r_lo) * B + ((int32_t)fl - 1);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) atomicAdd(cell + i, wt[i]);
+      }
+    }
+  }
+  if (sc.band == 0 && taken) atomicAdd(&lds_count, taken);
+  __syncthreads();
+  if (!ok) return;
+  double* __restrict__ out = a.table + (size_t)sc.t * B * B + (size_t)sc.r_lo * B;
+  for (int e = threadIdx.x; e < cells; e += NT) {
+    const float v = lds_tab[e];
+    if (v != 0.0f) atomicAdd(&out[e], (double)v);
+  }
+  if (threadIdx.x == 0 && sc.band == 0 && lds_count)
+    atomicAdd((unsigned long long*)&a.count[sc.t], (unsigned long long)lds_count);
+}
+
+// ---------------------------------------------------------------------------
+// d MI / d p tables
+// ---------------------------------------------------------------------------
+
+// One workgroup per transform:
+//   Shannon           G = ln(p / p_m)
+//   Tsallis additive  G = q/(q-1) * (p^(q-1) - p_m^(q-1))
+//   Tsallis pseudo    G = q/(q-1) * (p^(q-1) - (1 + (1-q) S_q(F)) p_m^(q-1))
+// and G = 0 where p = 0 (no voxel there has a non-zero B-spline slope).
+__global__ __launch_bounds__(256) void dmi_dp_kernel(ParzenArgs a, QList ql) {
+  const int B = a.bins;
+  const size_t BB = (size_t)B * B;
+  const int t = blockIdx.x;
+  __shared__ double pm[256], pf[256];
+  __shared__ double red[256];
+  const double* __restrict__ h = a.table + (size_t)t * BB;
+  float* __restrict__ G = (float*)a.gtab + (size_t)t * ql.n * BB;
+  int64_t Mq[12];
+  const bool ok = quantize_transform(a.transforms + 12 * (size_t)t, Mq);
+  const double N = (double)a.count[t];
+  if (!ok || !(N > 0)) {
+    for (size_t e = threadIdx.x; e < BB * ql.n; e += 256) G[e] = 0.0f;
+    return;
+  }
+  const double invN = 1.0 / N;
+  for (int i = threadIdx.x; i < B; i += 256) {
+    double r = 0, c = 0;
+    for (int k = 0; k < B; ++k) {
+      r += h[(size_t)i * B + k];
+      c += h[(size_t)k * B + i];
+    }
+    pf[i] = r * invN;
+    pm[i] = c * invN;
+  }
+  __syncthreads();
+  for (int iq = 0; iq < ql.n; ++iq) {
+    const double q = ql.q[iq], e1 = q - 1.0;
+    double fac = 1.0;
+    if (q != 1.0 && ql.pseudo) {
+      // S_q(F) = -sum p expm1((q-1) ln p) / (q-1)
+      double part = 0;
+      for (int i = threadIdx.x; i < B; i += 256)
+        if (pf[i] > 0) part += pf[i] * expm1(e1 * log(pf[i]));
+      red[threadIdx.x] = part;
+      __syncthreads();
+      for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+      }
+      fac = 1.0 + (1.0 - q) * (-red[0] / e1);
+      __syncthreads();
+    }
+    float* __restrict__ Gq = G + (size_t)iq * BB;
+    for (size_t e = threadIdx.x; e < BB; e += 256) {
+      const double hv = h[e];
+      double g = 0.0;
+      if (hv > 0) {
+        const double p = hv * invN, m = pm[e % B];
+        if (q == 1.0)
+          g = log(p / m);
+        else
+          g = q / e1 * (pow(p, e1) - fac * pow(m, e1));
+      }
+      Gq[e] = (float)g;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// backward: gradient sweep
+// ---------------------------------------------------------------------------
+
+template <bool FQ, bool CLAMP, int NQG, int NT>
+__global__ __launch_bounds__(NT) void parzen_bwd_kernel(ParzenArgs a) {
+  extern __shared__ float lds_g[];  // [NQG][band rows][B]
+  constexpr int NW = NT / 64;
+  __shared__ double part[NW][NQG * 12];
+  const int B = a.bins;
+  const size_t BB = (size_t)B * B;
+  SweepCtx sc;
+  block_work(a.chunks, a.n, a.bands, a.slab_major, sc.t, sc.chunk, sc.band);
+  sc.r_lo = (int32_t)sc.band * a.band_rows;
+  sc.r_hi = min(B, sc.r_lo + a.band_rows);
+  const int cells = (sc.r_hi - sc.r_lo) * B;
+  int64_t Mq[12];
+  const bool ok = quantize_transform(a.transforms + 12 * (size_t)sc.t, Mq);
+  const int nqg = min(NQG, a.n_q - a.q0);
+  for (int g = 0; g < nqg; ++g) {
+    const float* __restrict__ src = a.gtab + ((size_t)sc.t * a.n_q + a.q0 + g) * BB + (size_t)sc.r_lo * B;
+    for (int e = threadIdx.x; e < cells; e += NT) lds_g[g * cells + e] = src[e];
+  }
+  __syncthreads();
+  float acc[NQG][12];
+#pragma unroll
+  for (int g = 0; g < NQG; ++g)
+#pragma unroll
+    for (int e = 0; e < 12; ++e) acc[g][e] = 0.0f;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (ok && a.count[sc.t] > 0) {
+    const int dx = lane & (kTileX - 1), dy = lane / kTileX;
+    GroupWalk w;
+    w.init(Mq, a.fny, a.fnz, a.chunks, sc.chunk, wave, NW, dx, dy);
+    const uint64_t top[3] = {(uint64_t)(a.mnx - 1) << 32, (uint64_t)(a.mny - 1) << 32,
+                             (uint64_t)(a.mnz - 1) << 32};
+    const uint32_t NY = (uint32_t)a.mny, MX = (uint32_t)a.mnx;
+    const int32_t SZ = (FQ ? 16 : 8) * a.mnx * a.mny;
+    const __amdgpu_buffer_rsrc_t rsrc =
+        __builtin_amdgcn_make_buffer_rsrc((void*)a.quads, (short)0, (int)a.quad_bytes, 0x00020000);
+    const float smax = (float)(B - 3);
+    for (; w.g < w.g1; w.next()) {
+      const int32_t j = w.j0 + dy;
+      if (j >= a.fny) continue;
+      const uint8_t* __restrict__ frow = a.fbins + ((int64_t)w.k * a.fny + j) * a.fnx;
+      const float fj = (float)j, fk = (float)w.k;
+      int64_t q[3];
+#pragma unroll
+      for (int r = 0; r < 3; ++r) q[r] = w.r[r] + w.lane_off[r];
+      for (int x = dx; x < a.fnx; x += kTileX) {
+        uint64_t cq[3];
+        bool inside = true, moves[3];
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+          cq[r] = (uint64_t)q[r];
+          // a clamped coordinate does not move with the transform
+          moves[r] = cq[r] <= top[r];
+          if (CLAMP) cq[r] = q[r] < 0 ? 0 : (cq[r] > top[r] ? top[r] : cq[r]);
+          else inside = inside && moves[r];
+          q[r] += w.step[r];
+        }
+        if (!inside) continue;
+        const int32_t fb = frow[x];
+        if (fb < sc.r_lo || fb >= sc.r_hi) continue;
+        const uint32_t idx = __umul24(__umul24((uint32_t)(cq[2] >> 32), NY) + (uint32_t)(cq[1] >> 32), MX) +
+                             (uint32_t)(cq[0] >> 32);
+        float c[2][2][2];
+        gather<FQ>(rsrc, idx, SZ, c);
+        const float tx = (float)(uint32_t)cq[0] * 2.3283064365386963e-10f;
+        const float ty = (float)(uint32_t)cq[1] * 2.3283064365386963e-10f;
+        const float tz = (float)(uint32_t)cq[2] * 2.3283064365386963e-10f;
+        // x-lerps per (y, z) edge and their x-slopes
+        const float e00 = lerpf(c[0][0][0], c[0][0][1], tx), e01 = lerpf(c[0][1][0], c[0][1][1], tx);
+        const float e10 = lerpf(c[1][0][0], c[1][0][1], tx), e11 = lerpf(c[1][1][0], c[1][1][1], tx);
+        const float d00 = c[0][0][1] - c[0][0][0], d01 = c[0][1][1] - c[0][1][0];
+        const float d10 = c[1][0][1] - c[1][0][0], d11 = c[1][1][1] - c[1][1][0];
+        const float v0 = lerpf(e00, e01, ty), v1 = lerpf(e10, e11, ty);
+        const float v = lerpf(v0, v1, tz);
+        float dv[3];
+        dv[0] = lerpf(lerpf(d00, d01, ty), lerpf(d10, d11, ty), tz);
+        dv[1] = lerpf(e01 - e00, e11 - e10, tz);
+        dv[2] = v1 - v0;
+#pragma unroll
+        for (int r = 0; r < 3; ++r) dv[r] = moves[r] ? dv[r] : 0.0f;
+        const float s = fminf(fmaxf(fmaf(v, a.sscale, 1.0f), 1.0f), smax);
+        const float fl = floorf(s);
+        float d[4];
+        bspline_slopes(s - fl, d);
+        const int col = (fb - sc.r_lo) * B + ((int32_t)fl - 1);
+        const float xt[4] = {(float)x, fj, fk, 1.0f};
+#pragma unroll
+        for (int g = 0; g < NQG; ++g) {
+          if (g < nqg) {
+            const float* Gr = lds_g + g * cells + col;
+            const float wv = -(Gr[0] * d[0] + Gr[1] * d[1] + Gr[2] * d[2] + Gr[3] * d[3]);
+#pragma unroll
+            for (int r = 0; r < 3; ++r) {
+              const float gr = wv * dv[r];
+#pragma unroll
+              for (int cc = 0; cc < 4; ++cc) acc[g][4 * r + cc] = fmaf(gr, xt[cc], acc[g][4 * r + cc]);
+            }
+          }
+        }
+      }
+    }
+  }
+  // workgroup sum in fp64: shuffle tree per wave, then waves in order
+#pragma unroll
+  for (int g = 0; g < NQG; ++g)
+#pragma unroll
+    for (int e = 0; e < 12; ++e) {
+      double v = (double)acc[g][e];
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+      if (lane == 0) part[wave][g * 12 + e] = v;
+    }
+  __syncthreads();
+  if (!ok || threadIdx.x >= nqg * 12) return;
+  double sum = 0;
+  for (int ww = 0; ww < NW; ++ww) sum += part[ww][threadIdx.x];
+  const double N = (double)a.count[sc.t];
+  if (N > 0 && sum != 0.0) {
+    const int g = threadIdx.x / 12, e = threadIdx.x - g * 12;
+    atomicAdd(&a.grad[((size_t)sc.t * a.n_q + a.q0 + g) * 12 + e], sum * a.dsdv / N);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+
+template <bool FQ, bool CLAMP>
+static hipError_t fwd_variant(const ParzenArgs& a, size_t lds, hipStream_t s) {
+  hipLaunchKernelGGL((parzen_fwd_kernel<FQ, CLAMP, 512>), dim3((unsigned)(a.n * a.chunks * a.bands)),
+                     dim3(512), lds, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_parzen_fwd(const ParzenLaunch& L, hipStream_t s) {
+  ParzenArgs a = L.args;
+  const size_t lds = (size_t)a.band_rows * a.bins * 4;
+  if (L.float_quads)
+    return L.clamp ? fwd_variant<true, true>(a, lds, s) : fwd_variant<true, false>(a, lds, s);
+  return L.clamp ? fwd_variant<false, true>(a, lds, s) : fwd_variant<false, false>(a, lds, s);
+}
+
+hipError_t launch_dmi_dp(const ParzenLaunch& L, const QList& q, hipStream_t s) {
+  hipLaunchKernelGGL(dmi_dp_kernel, dim3((unsigned)L.args.n), dim3(256), 0, s, L.args, q);
+  return hipGetLastError();
+}
+
+template <bool FQ, bool CLAMP>
+static hipError_t bwd_variant(const ParzenArgs& a, size_t lds, hipStream_t s) {
+  hipLaunchKernelGGL((parzen_bwd_kernel<FQ, CLAMP, 2, 512>), dim3((unsigned)(a.n * a.chunks * a.bands)),
+                     dim3(512), lds, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_parzen_bwd(const ParzenLaunch& L, hipStream_t s) {
+  ParzenArgs a = L.args;
+  const size_t lds = (size_t)kParzenQGroup * a.band_rows * a.bins * 4;
+  if (L.float_quads)
+    return L.clamp ? bwd_variant<true, true>(a, lds, s) : bwd_variant<true, false>(a, lds, s);
+  return L.clamp ? bwd_variant<false, true>(a, lds, s) : bwd_variant<false, false>(a, lds, s);
+}
+
+// The bands are sized for at most 64 KiB of dynamic LDS per workgroup.
+template <bool FQ, bool CLAMP>
+static hipError_t allow_lds() {
+  const int bytes = 64 * 1024;
+  hipError_t e;
+  if ((e = hipFuncSetAttribute((const void*)parzen_fwd_kernel<FQ, CLAMP, 512>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, bytes)) != hipSuccess)
+    return e;
+  return hipFuncSetAttribute((const void*)parzen_bwd_kernel<FQ, CLAMP, 2, 512>,
+                             hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+}
+
+hipError_t configure_parzen_kernels() {
+  hipError_t e;
+  if ((e = allow_lds<false, false>()) != hipSuccess) return e;
+  if ((e = allow_lds<false, true>()) != hipSuccess) return e;
+  if ((e = allow_lds<true, false>()) != hipSuccess) return e;
+  return allow_lds<true, true>();
+}
 
 }  // namespace gemi

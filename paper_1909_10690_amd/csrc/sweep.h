@@ -1,0 +1,120 @@
+// The hard-binned histogram sweep of one slab of the fixed volume for one
+// transform, shared by the single-pair kernel (hard.hip) and the persistent
+// multi-pair kernel (pairs.hip).  Internal to libgemi.so.
+#pragma once
+
+#include "common.h"
+
+#pragma clang fp contract(off)
+
+namespace gemi {
+
+typedef unsigned short ushort2_t __attribute__((ext_vector_type(2)));
+typedef unsigned int uint2_t __attribute__((ext_vector_type(2)));
+
+// v0 (1 - w) + v1 w at 16-bit weight w = fx >> 16, exact: the pair's low
+// half times (65535 - w), high half times w, plus the low half once more.
+__device__ __forceinline__ uint32_t lerp_x(uint32_t pair, uint32_t wpack) {
+  return __builtin_amdgcn_udot2(__builtin_bit_cast(ushort2_t, pair),
+                                __builtin_bit_cast(ushort2_t, wpack), pair & 0xFFFFu, false);
+}
+
+// Exact bin of V = sum over corners, from the four exact x-lerps.
+static __device__ __noinline__ uint32_t exact_bin(uint32_t a00, uint32_t a10, uint32_t a01, uint32_t a11,
+                                           uint32_t wy, uint32_t wz, uint32_t B, Divider div) {
+  const uint64_t b0 = (uint64_t)a00 * (65536u - wy) + (uint64_t)a10 * wy;
+  const uint64_t b1 = (uint64_t)a01 * (65536u - wy) + (uint64_t)a11 * wy;
+  const uint64_t V = b0 * (65536u - wz) + b1 * wz;
+  // floor(V B / (R 2^48)) = floor(X / R), X = floor(V B / 2^48) < 2^24
+  const uint32_t X = (uint32_t)(V >> 48) * B + (uint32_t)(((V & 0xFFFFFFFFFFFFull) * B) >> 48);
+  return div_small(X, div);
+}
+
+constexpr double kEdge = 1.0 / 536870912.0;  // 2^-29
+
+// Sweeps one slab of the fixed volume for one transform (Mq) into the
+// workgroup's LDS histogram.  NW waves share the slab's 4-row groups.
+template <bool CLAMP, bool PACKED, int NW>
+__device__ __forceinline__ void sweep_hard(const HardGeom& g, const int64_t* Mq, int32_t chunks,
+                                           uint32_t chunk, uint32_t* lds_hist) {
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int dx = lane & (kTileX - 1), dy = lane / kTileX;
+  GroupWalk w;
+  w.init(Mq, g.fny, g.fnz, chunks, chunk, wave, NW, dx, dy);
+  const int64_t sx = w.step[0], sy = w.step[1], sz = w.step[2];
+  const uint64_t topx = (uint64_t)(g.mnx - 1) << 32;
+  const uint64_t topy = (uint64_t)(g.mny - 1) << 32;
+  const uint64_t topz = (uint64_t)(g.mnz - 1) << 32;
+  const uint32_t NY = (uint32_t)g.mny, MX = (uint32_t)g.mnx;
+  const int32_t SZ = 8 * g.mnx * g.mny;
+  const __amdgpu_buffer_rsrc_t rsrc =
+      __builtin_amdgcn_make_buffer_rsrc((void*)g.quads, (short)0, (int)g.quad_bytes, 0x00020000);
+  const uint32_t Bu = (uint32_t)g.bins;
+  const double scale = g.scale;
+
+  for (; w.g < w.g1; w.next()) {
+    const int32_t j = w.j0 + dy;
+    if (j >= g.fny) continue;
+    const uint8_t* __restrict__ frow = g.fbins + ((int64_t)w.k * g.fny + j) * g.fnx;
+    int64_t qx = w.r[0] + w.lane_off[0], qy = w.r[1] + w.lane_off[1], qz = w.r[2] + w.lane_off[2];
+    for (int x = dx; x < g.fnx; x += kTileX, qx += sx, qy += sy, qz += sz) {
+      uint64_t cx = (uint64_t)qx, cy = (uint64_t)qy, cz = (uint64_t)qz;
+      if (CLAMP) {
+        cx = qx < 0 ? 0 : (cx > topx ? topx : cx);
+        cy = qy < 0 ? 0 : (cy > topy ? topy : cy);
+        cz = qz < 0 ? 0 : (cz > topz ? topz : cz);
+      } else {
+        // 0 <= q <= top; a negative q wraps to a huge unsigned value
+        if (cx > topx || cy > topy || cz > topz) continue;
+      }
+      const uint32_t ix = (uint32_t)(cx >> 32), iy = (uint32_t)(cy >> 32), iz = (uint32_t)(cz >> 32);
+      const uint32_t fx = (uint32_t)cx, fy = (uint32_t)cy, fz = (uint32_t)cz;
+      // (nz+1) * ny < 2^24 rows, so 24-bit multiplies are exact
+      const uint32_t off = (__umul24(__umul24(iz, NY) + iy, MX) + ix) * 8u;
+      const uint2_t q0 = __builtin_amdgcn_raw_buffer_load_b64(rsrc, off, 0, 0);
+      const uint2_t q1 = __builtin_amdgcn_raw_buffer_load_b64(rsrc, off, SZ, 0);
+      const uint32_t fb = frow[x];
+      // (65535 - wx) in the low half, wx in the high half
+      const uint32_t wpack = (fx & 0xFFFF0000u) | ((fx >> 16) ^ 0xFFFFu);
+      const uint32_t a00 = lerp_x(q0.x, wpack), a10 = lerp_x(q0.y, wpack);
+      const uint32_t a01 = lerp_x(q1.x, wpack), a11 = lerp_x(q1.y, wpack);
+      const uint32_t wy = fy >> 16, wz = fz >> 16;
+      const double wyd = (double)wy, wzd = (double)wz;
+      const double A00 = (double)a00, A10 = (double)a10, A01 = (double)a01, A11 = (double)a11;
+      const double b0 = fma(A10 - A00, wyd, A00 * 65536.0);  // exact, < 2^48
+      const double b1 = fma(A11 - A01, wyd, A01 * 65536.0);  // exact, < 2^48
+      const double V = fma(b1 - b0, wzd, b0 * 65536.0);      // exact value rounded once
+      const double tb = V * scale;
+      uint32_t bm = (uint32_t)tb;
+      const double fr = tb - (double)bm;
+      if (fr < kEdge || fr > 1.0 - kEdge) bm = exact_bin(a00, a10, a01, a11, wy, wz, Bu, g.div);
+      const uint32_t cell = __umul24(fb, Bu) + bm;
+      if (PACKED)
+        atomicAdd(&lds_hist[cell >> 1], 1u << ((cell & 1u) * 16u));
+      else
+        atomicAdd(&lds_hist[cell], 1u);
+    }
+  }
+}
+
+// Adds the non-zero LDS bins into a transform's HBM histogram (and clears
+// them for the next use of the LDS histogram when `rezero`).
+template <bool PACKED, int NT>
+__device__ __forceinline__ void flush_hist(uint32_t* lds_hist, int B, uint32_t* __restrict__ out,
+                                           bool rezero) {
+  const int words = PACKED ? (B * B + 1) / 2 : B * B;
+  for (int e = threadIdx.x; e < words; e += NT) {
+    const uint32_t v = lds_hist[e];
+    if (v == 0) continue;
+    if (rezero) lds_hist[e] = 0;
+    if (PACKED) {
+      if (v & 0xFFFFu) atomicAdd(&out[2 * e], v & 0xFFFFu);
+      if (v >> 16) atomicAdd(&out[2 * e + 1], v >> 16);  // never set past the last bin
+    } else {
+      atomicAdd(&out[e], v);
+    }
+  }
+}
+
+}  // namespace gemi

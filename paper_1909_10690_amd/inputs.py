@@ -25,18 +25,20 @@ BG, CSF, GREY, WHITE = 0, 1, 2, 3
 
 
 def _ellipsoid(p, c, a):
-    return (((p[..., 0] - c[0]) / a[0]) ** 2 + ((p[..., 1] - c[1]) / a[1]) ** 2 +
-            ((p[..., 2] - c[2]) / a[2]) ** 2) <= 1.0
+    return (((p[0] - c[0]) / a[0]) ** 2 + ((p[1] - c[1]) / a[1]) ** 2 +
+            ((p[2] - c[2]) / a[2]) ** 2) <= 1.0
 
 
-def head_labels(points_xyz: np.ndarray, shape_xyz, jitter: float = 1.0, lesion: bool = True,
+def head_labels(points_xyz, shape_xyz, jitter: float = 1.0, lesion: bool = True,
                 scale_xyz=(1.0, 1.0, 1.0)) -> np.ndarray:
-    """Tissue labels at points (..., 3) given in index units of a volume of
-    ``shape_xyz``; ``scale_xyz`` stretches the anatomy per axis."""
+    """Tissue labels at points given in index units of a volume of
+    ``shape_xyz``; ``points_xyz`` is a sequence of three broadcastable
+    coordinate arrays (x, y, z); ``scale_xyz`` stretches the anatomy per axis."""
     n = np.asarray(shape_xyz, dtype=np.float64)
     c = (n - 1.0) / 2.0
     h = n / 2.0 * np.asarray(scale_xyz, dtype=np.float64) * jitter
-    lab = np.zeros(points_xyz.shape[:-1], dtype=np.uint8)
+    shape = np.broadcast_shapes(*(np.shape(v) for v in points_xyz))
+    lab = np.zeros(shape, dtype=np.uint8)
     lab[_ellipsoid(points_xyz, c, h * np.array([0.85, 0.75, 0.80]))] = CSF
     lab[_ellipsoid(points_xyz, c, h * np.array([0.78, 0.68, 0.72]))] = GREY
     lab[_ellipsoid(points_xyz, c, h * np.array([0.60, 0.50, 0.55]))] = WHITE
@@ -49,15 +51,21 @@ def head_labels(points_xyz: np.ndarray, shape_xyz, jitter: float = 1.0, lesion: 
     return lab
 
 
-def _grid_points(shape_xyz, z0: int, z1: int) -> np.ndarray:
+def _slab_points(shape_xyz, z0: int, z1: int, M=None):
+    """Coordinates (x, y, z) of voxels [z0, z1) x all y x all x, mapped by
+    the 3x4 matrix M if given; separable, so built by broadcasting 1-D axes."""
     nx, ny, _ = shape_xyz
-    zz, yy, xx = np.meshgrid(np.arange(z0, z1, dtype=np.float64), np.arange(ny, dtype=np.float64),
-                             np.arange(nx, dtype=np.float64), indexing="ij")
-    return np.stack([xx, yy, zz], axis=-1)
+    x = np.arange(nx, dtype=np.float32)[None, None, :]
+    y = np.arange(ny, dtype=np.float32)[None, :, None]
+    z = np.arange(z0, z1, dtype=np.float32)[:, None, None]
+    if M is None:
+        return x, y, z
+    M = np.asarray(M, dtype=np.float32)
+    return tuple(M[r, 0] * x + M[r, 1] * y + M[r, 2] * z + M[r, 3] for r in range(3))
 
 
 def render_labels(shape_xyz, inv_map=None, jitter=1.0, lesion=True, scale_xyz=(1.0, 1.0, 1.0),
-                  anatomy_shape_xyz=None, chunk=32) -> np.ndarray:
+                  anatomy_shape_xyz=None, chunk=64) -> np.ndarray:
     """Label volume [nz][ny][nx].  ``inv_map`` (3x4) takes this volume's voxel
     index to the anatomy's index frame (``anatomy_shape_xyz``, default the
     same shape); identity when None."""
@@ -66,10 +74,8 @@ def render_labels(shape_xyz, inv_map=None, jitter=1.0, lesion=True, scale_xyz=(1
     out = np.empty((nz, ny, nx), dtype=np.uint8)
     for z0 in range(0, nz, chunk):
         z1 = min(nz, z0 + chunk)
-        p = _grid_points(shape_xyz, z0, z1)
-        if inv_map is not None:
-            p = p @ inv_map[:, :3].T + inv_map[:, 3]
-        out[z0:z1] = head_labels(p, ana, jitter, lesion, scale_xyz)
+        p = _slab_points(shape_xyz, z0, z1, inv_map)
+        out[z0:z1] = np.broadcast_to(head_labels(p, ana, jitter, lesion, scale_xyz), (z1 - z0, ny, nx))
     return out
 
 
@@ -84,13 +90,13 @@ def invert(M: np.ndarray) -> np.ndarray:
 def intensities(labels: np.ndarray, levels, rng: np.random.Generator, sigma: float, rician: bool,
                 lo: float, hi: float, dtype) -> np.ndarray:
     """Class intensities + N(0, sigma) (or Rician magnitude) noise, rounded and clipped."""
-    s = np.asarray(levels, dtype=np.float64)[labels]
+    s = np.asarray(levels, dtype=np.float32)[labels]
     if rician:
-        n1 = rng.standard_normal(labels.shape, dtype=np.float64)
-        n2 = rng.standard_normal(labels.shape, dtype=np.float64)
-        v = np.sqrt((s + sigma * n1) ** 2 + (sigma * n2) ** 2)
+        n1 = rng.standard_normal(labels.shape, dtype=np.float32)
+        n2 = rng.standard_normal(labels.shape, dtype=np.float32)
+        v = np.sqrt((s + np.float32(sigma) * n1) ** 2 + (np.float32(sigma) * n2) ** 2)
     else:
-        v = s + sigma * rng.standard_normal(labels.shape, dtype=np.float64)
+        v = s + np.float32(sigma) * rng.standard_normal(labels.shape, dtype=np.float32)
     v = np.clip(np.rint(v), lo, hi)
     return v.astype(dtype)
 
@@ -100,8 +106,8 @@ def resample_trilinear(vol: np.ndarray, M: np.ndarray) -> np.ndarray:
     from scipy import ndimage
     nz, ny, nx = vol.shape
     Mi = invert(M)
-    p = _grid_points((nx, ny, nz), 0, nz) @ Mi[:, :3].T + Mi[:, 3]
-    coords = np.stack([p[..., 2], p[..., 1], p[..., 0]])
+    p = [np.broadcast_to(v, (nz, ny, nx)).astype(np.float64) for v in _slab_points((nx, ny, nz), 0, nz, Mi)]
+    coords = np.stack([p[2], p[1], p[0]])
     return ndimage.map_coordinates(vol.astype(np.float64), coords, order=1, mode="nearest")
 
 
@@ -174,23 +180,34 @@ def parzen_gradient(n: int = 128, seed: int = 2, n_transforms: int = 64) -> dict
 EDGES = (64, 96, 128, 160, 192, 256)
 
 
-def uneven_pairs(n_pairs: int = 256, seed: int = 3, per_pair: int = 16, edges=EDGES) -> list:
+def _one_pair(seed_seq, edges) -> dict:
+    rng = np.random.default_rng(seed_seq)
+    shape = tuple(int(e) for e in rng.choice(edges, 3))
+    jit = rng.uniform(0.85, 1.1)
+    lab = render_labels(shape, jitter=jit)
+    fixed = intensities(lab, (20, 90, 160, 230), rng, 8.0, False, 0, 255, np.uint8)
+    truth = T.index_matrix(T.affine_matrix(rng.uniform(-5, 5, 3)), rng.uniform(-4, 4, 3), shape)
+    lab_m = render_labels(shape, inv_map=invert(truth), jitter=jit)
+    moving = intensities(lab_m, (20, 90, 160, 230), rng, 8.0, False, 0, 255, np.uint8)
+    mats = random_affines(rng, 16, shape, rot=10.0, trans=8.0, scale=(1.0, 1.0), shear=0.0)
+    return dict(fixed=fixed, moving=moving, transforms=mats)
+
+
+def uneven_pairs(n_pairs: int = 256, seed: int = 3, per_pair: int = 16, edges=EDGES,
+                 threads: int = 0) -> list:
     """Volume pairs with per-axis edge lengths drawn from ``edges``; u8 head
     phantoms with per-pair radius jitter; each pair gets ``per_pair`` rigid
-    transforms (angles +-10 deg, translation +-8 voxels); 64 bins."""
-    rng = np.random.default_rng(seed)
-    pairs = []
-    for _ in range(n_pairs):
-        shape = tuple(int(e) for e in rng.choice(edges, 3))
-        jit = rng.uniform(0.85, 1.1)
-        lab = render_labels(shape, jitter=jit)
-        fixed = intensities(lab, (20, 90, 160, 230), rng, 8.0, False, 0, 255, np.uint8)
-        truth = T.index_matrix(T.affine_matrix(rng.uniform(-5, 5, 3)), rng.uniform(-4, 4, 3), shape)
-        lab_m = render_labels(shape, inv_map=invert(truth), jitter=jit)
-        moving = intensities(lab_m, (20, 90, 160, 230), rng, 8.0, False, 0, 255, np.uint8)
-        mats = random_affines(rng, per_pair, shape, rot=10.0, trans=8.0, scale=(1.0, 1.0), shear=0.0)
-        pairs.append(dict(fixed=fixed, moving=moving, transforms=mats))
-    return pairs
+    transforms (angles +-10 deg, translation +-8 voxels); 64 bins.  Pair k
+    draws from its own child of SeedSequence(seed), so the result does not
+    depend on ``threads`` (0 = one per host core, at most 16)."""
+    import os
+    from concurrent.futures import ThreadPoolExecutor
+    seqs = np.random.SeedSequence(seed).spawn(n_pairs)
+    if per_pair != 16:
+        raise ValueError("per_pair is fixed at 16 by the workload")
+    workers = threads or min(16, os.cpu_count() or 1)
+    with ThreadPoolExecutor(max_workers=workers) as ex:
+        return list(ex.map(lambda sq: _one_pair(sq, edges), seqs))
 
 
 def ct_mr_pair(fixed_shape=(512, 512, 300), moving_shape=(256, 256, 256), seed: int = 4) -> dict:

@@ -129,10 +129,14 @@ def test_workspace_size_layout():
     a = lambda x: (x + 255) // 256 * 256
     st, n = ws_size(vol(10, 11, 12), vol(9, 8, 7), 5, 32, 2)
     assert st == 0 and n == a(10 * 11 * 12) + a(9 * 8 * 8 * 8) + a(5 * 32 * 32 * 4)
+    quads = a(8 * 8 * 9 * 8)
     st, n = ws_size(vol(10, 11, 12), vol(), 5, 32, 2, B.HIST_PARZEN)
-    assert st == 0 and n == a(1320) + a(5 * 32 * 32 * 8) + a(5 * 8)
+    assert st == 0 and n == a(1320) + quads + a(5 * 32 * 32 * 8) + a(5 * 8)
     st, n = ws_size(vol(10, 11, 12), vol(), 5, 32, 2, 0, 1)
-    assert st == 0 and n == a(1320) + a(5 * 32 * 32 * 8) + a(5 * 8) + a(5 * 2 * 32 * 32 * 4)
+    assert st == 0 and n == a(1320) + quads + a(5 * 32 * 32 * 8) + a(5 * 8) + a(5 * 2 * 32 * 32 * 4)
+    # a float moving volume keeps fp32 quads: twice the bytes
+    st, n = ws_size(vol(10, 11, 12), vol(dtype=B.F32, lo=0.0, hi=1.0), 5, 32, 2, B.HIST_PARZEN)
+    assert st == 0 and n == a(1320) + 2 * quads + a(5 * 32 * 32 * 8) + a(5 * 8)
     assert ws_size(vol(), vol(), 5, 1, 1)[0] == B.MI_ERR_BINS
     assert ws_size(vol(), vol(), 5, 32, 0)[0] == B.MI_ERR_Q
 
