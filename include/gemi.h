@@ -96,6 +96,14 @@ extern "C" {
 #define MI_TSALLIS_PSEUDOADDITIVE 0x010
 #define MI_HIST_HARD 0x000
 #define MI_HIST_PARZEN 0x100
+/* Capture the call's kernels into a HIP graph the first time a call with
+ * exactly these arguments (pointers, sizes, q, flags, workspace, stream) is
+ * seen, and replay the graph on later identical calls: one launch instead
+ * of several.  Needs a non-NULL stream; ignored (eager launches) on the
+ * NULL stream or while kernel timing is enabled.  Device data behind the
+ * pointers may change between replays (e.g. transforms updated in place);
+ * the context keeps the 16 most recent graphs. */
+#define MI_USE_GRAPH 0x1000
 
 #define MI_MAX_Q 16
 #define MI_MAX_EDGE 4096
@@ -170,6 +178,20 @@ int mi_pairs_workspace_size(const mi_pair *pairs, int32_t n_pairs, int32_t bins,
 int mi_eval_pairs(mi_context *ctx, const mi_pair *pairs, int32_t n_pairs, int32_t bins,
                   const double *q, int32_t n_q, int32_t flags, double *mi_out, void *workspace,
                   size_t workspace_bytes, void *stream);
+
+/* Autotuner of the hard-binned sweep (mi_eval and mi_eval_pairs share its
+ * kernel).  Times the histogram kernel on these arguments for every
+ * candidate launch shape (workgroup size 256/512/1024, slab-major or
+ * transform-major workgroup order, three slab counts), keeps the fastest
+ * for this problem class (volume shapes, moving dtype, bins, boundary, and
+ * the power-of-two bucket of n_transforms) in the context, and, when the
+ * environment variable MI_TUNE_CACHE names a file, records it there; later
+ * contexts read that file at mi_create.  Results are unaffected (the sweep
+ * is exact whatever its shape).  Synchronous: waits for `stream`.  The
+ * workspace is the one mi_eval would use with hist_out = NULL. */
+int mi_tune(mi_context *ctx, const mi_volume *fixed, const mi_volume *moving,
+            const double *transforms, int32_t n_transforms, int32_t bins, int32_t flags,
+            void *workspace, size_t workspace_bytes, void *stream);
 
 /* Kernel timing.  While enabled, the library brackets every launch of its
  * histogram kernels with HIP events on the caller's stream.

@@ -24,6 +24,7 @@ U8, U16, I16, F32 = 0, 1, 2, 3
 BOUNDARY_EXCLUDE, BOUNDARY_CLAMP = 0x0, 0x1
 TSALLIS_ADDITIVE, TSALLIS_PSEUDOADDITIVE = 0x0, 0x10
 HIST_HARD, HIST_PARZEN = 0x0, 0x100
+USE_GRAPH = 0x1000
 TIMER_HARD, TIMER_PARZEN_FWD, TIMER_PARZEN_BWD, TIMER_PAIRS, TIMER_REDUCE = 0, 1, 2, 3, 4
 
 _TORCH_DTYPES = {torch.uint8: U8, torch.uint16: U16, torch.int16: I16, torch.float32: F32}
@@ -47,8 +48,8 @@ class MiPair(ctypes.Structure):
 
 
 EXPORTS = ["mi_create", "mi_destroy", "mi_workspace_size", "mi_eval", "mi_grad",
-           "mi_pairs_workspace_size", "mi_eval_pairs", "mi_timing_enable", "mi_timing_read",
-           "mi_status_string"]
+           "mi_pairs_workspace_size", "mi_eval_pairs", "mi_tune", "mi_timing_enable",
+           "mi_timing_read", "mi_status_string"]
 
 _lib = None
 
@@ -72,6 +73,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
                             sz, vp]
     lib.mi_pairs_workspace_size.argtypes = [P(MiPair), i32, i32, i32, i32, P(sz)]
     lib.mi_eval_pairs.argtypes = [vp, P(MiPair), i32, i32, dp, i32, i32, vp, vp, sz, vp]
+    lib.mi_tune.argtypes = [vp, P(MiVolume), P(MiVolume), vp, i32, i32, i32, vp, sz, vp]
     lib.mi_timing_enable.argtypes = [vp, ctypes.c_int]
     lib.mi_timing_read.argtypes = [vp, ctypes.c_int, dp, P(ctypes.c_int64)]
     lib.mi_status_string.argtypes = [ctypes.c_int]
@@ -240,6 +242,18 @@ class Context:
                                     self._stream(stream))
         _check(st, "mi_eval_pairs")
         return mi
+
+    def tune(self, fixed: Volume, moving: Volume, transforms: torch.Tensor, bins: int, flags: int = 0,
+             workspace: torch.Tensor | None = None, stream=None) -> None:
+        """Autotunes the hard-binned sweep's launch shape for this problem class
+        (synchronous; results are unaffected)."""
+        transforms = transforms.to(device=fixed.tensor.device, dtype=torch.float64).reshape(-1, 12).contiguous()
+        n = transforms.shape[0]
+        if workspace is None:
+            workspace = self.workspace(self.workspace_size(fixed, moving, n, bins, 1, flags))
+        f, m = fixed.c(), moving.c()
+        _check(self.lib.mi_tune(self.handle, ctypes.byref(f), ctypes.byref(m), _ptr(transforms), n, bins,
+                                flags, _ptr(workspace), workspace.numel(), self._stream(stream)), "mi_tune")
 
     def timing(self, enable: bool) -> None:
         _check(self.lib.mi_timing_enable(self.handle, int(enable)), "mi_timing_enable")

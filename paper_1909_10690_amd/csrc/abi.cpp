@@ -9,6 +9,8 @@
 #include <string.h>
 
 #include <mutex>
+#include <fstream>
+#include <sstream>
 #include <string>
 #include <vector>
 
@@ -67,7 +69,8 @@ int check_q(const double* q, int32_t n_q) {
   return MI_OK;
 }
 
-constexpr int32_t kKnownFlags = MI_BOUNDARY_CLAMP | MI_TSALLIS_PSEUDOADDITIVE | MI_HIST_PARZEN;
+constexpr int32_t kKnownFlags =
+    MI_BOUNDARY_CLAMP | MI_TSALLIS_PSEUDOADDITIVE | MI_HIST_PARZEN | MI_USE_GRAPH;
 
 int check_common(const mi_volume* f, const mi_volume* m, int32_t n, int32_t bins, const double* q,
                  int32_t n_q, int32_t flags, bool parzen) {
@@ -147,18 +150,39 @@ QList qlist(const double* q, int32_t n_q, int32_t flags) {
 
 constexpr size_t kStageBytes = 4u << 20;  // pinned staging for the pairs' tables
 
+// Launch shape of the hard-binned sweep for one problem class.
+struct HardTune {
+  int32_t block = 512;
+  int32_t slab_major = 1;
+  int32_t chunks = 0;  // 0 = planned per call
+};
+
+// Problem class of the tuning cache.
+struct TuneKey {
+  int32_t v[10];
+  bool operator==(const TuneKey& o) const { return memcmp(v, o.v, sizeof v) == 0; }
+};
+
+struct GraphEntry {
+  std::vector<uint64_t> key;
+  hipGraphExec_t exec;
+};
+
+constexpr size_t kMaxGraphs = 16;
+
 struct mi_context {
   void* stage = nullptr;            // pinned host buffer, kStageBytes
   hipEvent_t stage_done = nullptr;  // recorded after the last copy out of `stage`
   bool stage_pending = false;
   int device = 0;
   int cu_count = 256;
-  int hard_block = 512;   // threads per workgroup of the histogram sweep
-  int hard_slab_major = 1;
-  int hard_chunks = 0;    // workgroups per transform; 0 = planned per call
+  HardTune hard_default;  // launch shape when no tuned entry matches
   bool timing = false;
   std::mutex mu;
   std::vector<EventPair> events[kTimers];
+  std::vector<std::pair<TuneKey, HardTune>> tuned;  // from mi_tune or the cache file
+  std::string tune_file;                            // MI_TUNE_CACHE, if set
+  std::vector<GraphEntry> graphs;                   // MI_USE_GRAPH replays, oldest first
 };
 
 namespace {
@@ -193,14 +217,15 @@ struct TimedLaunch {
 // fit an XCD's L2), a multiple of 8 (one share per XCD), and -- with 16-bit
 // packed LDS counters -- few enough voxels per workgroup that no counter
 // can exceed 65535.
-int plan_chunks(const mi_context* ctx, const mi_volume* f, int32_t n, bool packed) {
+int plan_chunks(const mi_context* ctx, const mi_volume* f, int32_t n, bool packed,
+                const HardTune& tune) {
   const int64_t groups = (int64_t)((f->ny + 3) / 4) * f->nz;
   int64_t c;
-  if (ctx->hard_chunks) {
-    c = ctx->hard_chunks;
+  if (tune.chunks) {
+    c = tune.chunks;
   } else {
     c = ((int64_t)ctx->cu_count * 8 + n - 1) / n;
-    if (ctx->hard_slab_major && c < 32) c = 32;
+    if (tune.slab_major && c < 32) c = 32;
   }
   if (c > groups) c = groups;
   if (packed) {
@@ -337,7 +362,7 @@ struct PairsPlan {
 
 int plan_pairs(const mi_pair* pairs, int32_t n_pairs, int32_t bins, int32_t n_q, int32_t flags,
                PairsPlan& plan) {
-  if (flags & ~(MI_BOUNDARY_CLAMP | MI_TSALLIS_PSEUDOADDITIVE)) return MI_ERR_FLAGS;
+  if (flags & ~(MI_BOUNDARY_CLAMP | MI_TSALLIS_PSEUDOADDITIVE | MI_USE_GRAPH)) return MI_ERR_FLAGS;
   if (n_pairs < 0 || n_pairs > (1 << 24)) return MI_ERR_COUNT;
   if (n_pairs > 0 && !pairs) return MI_ERR_NULL;
   if (bins < 2 || bins > 256) return MI_ERR_BINS;
@@ -408,6 +433,179 @@ int plan_pairs(const mi_pair* pairs, int32_t n_pairs, int32_t bins, int32_t n_q,
   return MI_OK;
 }
 
+// ---- tuning cache ---------------------------------------------------------
+
+TuneKey tune_key(const mi_volume* f, const mi_volume* m, int32_t n, int32_t bins, int32_t flags) {
+  TuneKey k;
+  int32_t nb = 0;
+  while ((1 << nb) < n && nb < 30) ++nb;
+  const int32_t v[10] = {f->nx, f->ny, f->nz, m->nx, m->ny, m->nz, m->dtype, bins,
+                         (flags & MI_BOUNDARY_CLAMP) ? 1 : 0, nb};
+  memcpy(k.v, v, sizeof v);
+  return k;
+}
+
+HardTune tune_for(const mi_context* ctx, const mi_volume* f, const mi_volume* m, int32_t n,
+                  int32_t bins, int32_t flags) {
+  const TuneKey k = tune_key(f, m, n, bins, flags);
+  for (const auto& e : ctx->tuned)
+    if (e.first == k) return e.second;
+  return ctx->hard_default;
+}
+
+// Cache file: one problem class per line,
+//   gemi-tune fnx fny fnz mnx mny mnz mdtype bins clamp nbucket block slab_major chunks
+void load_tune_file(mi_context* c) {
+  std::ifstream in(c->tune_file);
+  std::string line;
+  while (std::getline(in, line)) {
+    std::istringstream ss(line);
+    std::string tag;
+    TuneKey k;
+    HardTune t;
+    if (!(ss >> tag) || tag != "gemi-tune") continue;
+    bool ok = true;
+    for (int i = 0; i < 10 && ok; ++i) ok = static_cast<bool>(ss >> k.v[i]);
+    ok = ok && (ss >> t.block >> t.slab_major >> t.chunks);
+    if (!ok || (t.block != 256 && t.block != 512 && t.block != 1024) || t.chunks < 0 ||
+        t.chunks % 8 != 0)
+      continue;
+    c->tuned.emplace_back(k, t);
+  }
+}
+
+void save_tune_file(const mi_context* c) {
+  if (c->tune_file.empty()) return;
+  std::ofstream out(c->tune_file, std::ios::trunc);
+  for (const auto& e : c->tuned) {
+    out << "gemi-tune";
+    for (int i = 0; i < 10; ++i) out << ' ' << e.first.v[i];
+    out << ' ' << e.second.block << ' ' << e.second.slab_major << ' ' << e.second.chunks << '\n';
+  }
+}
+
+// ---- graphs -----------------------------------------------------------------
+
+bool use_graph(const mi_context* ctx, int32_t flags, hipStream_t s) {
+  return (flags & MI_USE_GRAPH) && s != nullptr && !ctx->timing;
+}
+
+void key_volume(std::vector<uint64_t>& key, const mi_volume* v) {
+  uint64_t lo, hi;
+  memcpy(&lo, &v->lo, 8);
+  memcpy(&hi, &v->hi, 8);
+  key.insert(key.end(), {(uint64_t)(uintptr_t)v->data, (uint64_t)v->nx, (uint64_t)v->ny,
+                         (uint64_t)v->nz, (uint64_t)v->dtype, lo, hi});
+}
+
+void key_q(std::vector<uint64_t>& key, const double* q, int32_t n_q) {
+  for (int i = 0; i < n_q; ++i) {
+    uint64_t b;
+    memcpy(&b, &q[i], 8);
+    key.push_back(b);
+  }
+}
+
+// Replays the graph recorded for `key`, or records `body`'s launches on `s`
+// into a new graph and replays it.
+template <class F>
+int graph_run(mi_context* ctx, const std::vector<uint64_t>& key, hipStream_t s, F&& body) {
+  hipError_t e;
+  for (auto& g : ctx->graphs)
+    if (g.key == key) {
+      if ((e = hipGraphLaunch(g.exec, s)) != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+      return MI_OK;
+    }
+  if ((e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+    return hip_fail(e, "hipStreamBeginCapture");
+  const int st = body();
+  hipGraph_t graph = nullptr;
+  e = hipStreamEndCapture(s, &graph);
+  if (st != MI_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return st;
+  }
+  if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+  hipGraphExec_t exec = nullptr;
+  e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+  if (ctx->graphs.size() >= kMaxGraphs) {
+    (void)hipGraphExecDestroy(ctx->graphs.front().exec);
+    ctx->graphs.erase(ctx->graphs.begin());
+  }
+  ctx->graphs.push_back(GraphEntry{key, exec});
+  if ((e = hipGraphLaunch(exec, s)) != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+  return MI_OK;
+}
+
+// ---- the hard-binned path ---------------------------------------------------
+
+// Fixed bins, quad volume, zeroed histograms and the sweep (no reduction).
+int launch_hard_hist(mi_context* ctx, const mi_volume* fixed, const mi_volume* moving,
+                     const double* transforms, int32_t n, int32_t bins, int32_t flags,
+                     uint32_t* hist, char* ws, const Layout& L, hipStream_t s,
+                     const HardTune& tune, bool prepare) {
+  hipError_t e;
+  uint8_t* fb = (uint8_t*)(ws + L.fbins);
+  uint2* quads = (uint2*)(ws + L.quads);
+  const size_t bb = (size_t)bins * bins;
+  if (prepare) {
+    if ((e = launch_prebin_fixed(desc(fixed), bins, fb, s)) != hipSuccess) return hip_fail(e, "prebin");
+    if ((e = launch_pack_quads(desc(moving), quads, s)) != hipSuccess) return hip_fail(e, "pack");
+  }
+  if ((e = launch_fill_u32(hist, bb * n, 0u, s)) != hipSuccess) return hip_fail(e, "fill");
+  HardLaunch H;
+  H.transforms = transforms;
+  H.fbins = fb;
+  H.quads = quads;
+  H.fixed = desc(fixed);
+  H.moving = desc(moving);
+  H.hist = hist;
+  H.n = n;
+  H.bins = bins;
+  H.clamp = (flags & MI_BOUNDARY_CLAMP) ? 1 : 0;
+  H.packed = bins > 128 ? 1 : 0;
+  H.block = tune.block;
+  H.slab_major = tune.slab_major;
+  H.chunks = plan_chunks(ctx, fixed, n, H.packed != 0, tune);
+  // one launch covers at most 2^31 - 1 workgroups: split the transforms
+  const int64_t per_launch = 0x7FFFFFFFll / H.chunks;
+  for (int64_t t0 = 0; t0 < n; t0 += per_launch) {
+    HardLaunch part = H;
+    part.n = (int32_t)(n - t0 < per_launch ? n - t0 : per_launch);
+    part.transforms = transforms + 12 * t0;
+    part.hist = hist + bb * t0;
+    TimedLaunch tl(ctx, 0, s);
+    if ((e = launch_hist_hard(part, s)) != hipSuccess) return hip_fail(e, "hist_hard");
+    tl.done();
+  }
+  return MI_OK;
+}
+
+int run_hard(mi_context* ctx, const mi_volume* fixed, const mi_volume* moving,
+             const double* transforms, int32_t n, int32_t bins, const double* q, int32_t n_q,
+             int32_t flags, double* mi_out, uint64_t* overlap_out, uint32_t* hist_out, char* ws,
+             const Layout& L, hipStream_t s, const HardTune& tune) {
+  uint32_t* hist = hist_out ? hist_out : (uint32_t*)(ws + L.hist);
+  int st = launch_hard_hist(ctx, fixed, moving, transforms, n, bins, flags, hist, ws, L, s, tune, true);
+  if (st != MI_OK) return st;
+  ReduceLaunch R;
+  memset(&R, 0, sizeof R);
+  R.hist = hist;
+  R.transforms = transforms;
+  R.n = n;
+  R.bins = bins;
+  R.q = qlist(q, n_q, flags);
+  R.mi_out = mi_out;
+  R.overlap_out = overlap_out;
+  TimedLaunch tr(ctx, 4, s);
+  hipError_t e;
+  if ((e = launch_mi_reduce(R, s)) != hipSuccess) return hip_fail(e, "mi_reduce");
+  tr.done();
+  return MI_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -458,12 +656,16 @@ int mi_create(mi_context** out, int device) {
   }
   if (const char* b = getenv("MI_TUNE_HARD_BLOCK")) {
     const int v = atoi(b);
-    if (v == 256 || v == 512 || v == 1024) c->hard_block = v;
+    if (v == 256 || v == 512 || v == 1024) c->hard_default.block = v;
   }
-  if (const char* o = getenv("MI_TUNE_HARD_ORDER")) c->hard_slab_major = atoi(o) != 0;
+  if (const char* o = getenv("MI_TUNE_HARD_ORDER")) c->hard_default.slab_major = atoi(o) != 0;
   if (const char* k = getenv("MI_TUNE_HARD_CHUNKS")) {
     const int v = atoi(k);
-    if (v >= 8 && v % 8 == 0) c->hard_chunks = v;
+    if (v >= 8 && v % 8 == 0) c->hard_default.chunks = v;
+  }
+  if (const char* f = getenv("MI_TUNE_CACHE")) {
+    c->tune_file = f;
+    load_tune_file(c);
   }
   c->cu_count = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
   *out = c;
@@ -472,6 +674,7 @@ int mi_create(mi_context** out, int device) {
 
 int mi_destroy(mi_context* ctx) {
   if (!ctx) return MI_OK;
+  for (auto& g : ctx->graphs) (void)hipGraphExecDestroy(g.exec);
   if (ctx->stage_pending) (void)hipEventSynchronize(ctx->stage_done);
   if (ctx->stage_done) (void)hipEventDestroy(ctx->stage_done);
   if (ctx->stage) (void)hipHostFree(ctx->stage);
@@ -492,6 +695,79 @@ int mi_workspace_size(const mi_volume* fixed, const mi_volume* moving, int32_t n
   if (st != MI_OK) return st;
   if (n_q < 1 || n_q > MI_MAX_Q) return MI_ERR_Q;
   *bytes = layout(fixed, moving, n, bins, n_q, parzen, for_grad != 0, true).total;
+  return MI_OK;
+}
+
+int mi_tune(mi_context* ctx, const mi_volume* fixed, const mi_volume* moving,
+            const double* transforms, int32_t n, int32_t bins, int32_t flags, void* workspace,
+            size_t workspace_bytes, void* stream) {
+  int st = check_common(fixed, moving, n, bins, nullptr, 0, flags & ~MI_USE_GRAPH, false);
+  if (st != MI_OK) return st;
+  if (flags & MI_HIST_PARZEN) return MI_ERR_UNSUPPORTED;
+  if (n > 0 && !transforms) return MI_ERR_NULL;
+  const Layout L = layout(fixed, moving, n, bins, 1, false, false, true);
+  if (!workspace || workspace_bytes < L.total) return MI_ERR_WORKSPACE;
+  if (!ctx) return MI_ERR_NULL;
+  if (n == 0) return MI_OK;
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e;
+  if ((e = hipSetDevice(ctx->device)) != hipSuccess) return hip_fail(e, "hipSetDevice");
+  char* ws = (char*)workspace;
+  uint32_t* hist = (uint32_t*)(ws + L.hist);
+  const bool was_timing = ctx->timing;
+  ctx->timing = false;
+  // fixed bins and quads once
+  st = launch_hard_hist(ctx, fixed, moving, transforms, n, bins, flags, hist, ws, L, s,
+                        ctx->hard_default, true);
+  hipEvent_t t0 = nullptr, t1 = nullptr;
+  if (st == MI_OK && ((e = hipEventCreate(&t0)) != hipSuccess || (e = hipEventCreate(&t1)) != hipSuccess))
+    st = hip_fail(e, "tune events");
+  HardTune best = ctx->hard_default;
+  float best_ms = 3.4e38f;
+  HardTune base = ctx->hard_default;
+  base.chunks = plan_chunks(ctx, fixed, n, bins > 128, base);
+  const int32_t chunk_opts[3] = {base.chunks / 2, base.chunks, base.chunks * 2};
+  for (int32_t block : {256, 512, 1024}) {
+    for (int32_t order : {1, 0}) {
+      for (int32_t c : chunk_opts) {
+        if (st != MI_OK) break;
+        HardTune cand;
+        cand.block = block;
+        cand.slab_major = order;
+        cand.chunks = ((c < 8 ? 8 : c) + 7) / 8 * 8;
+        float total = 0;
+        for (int rep = 0; rep < 3 && st == MI_OK; ++rep) {
+          if ((e = hipEventRecord(t0, s)) != hipSuccess) { st = hip_fail(e, "tune"); break; }
+          st = launch_hard_hist(ctx, fixed, moving, transforms, n, bins, flags, hist, ws, L, s, cand, false);
+          if (st != MI_OK) break;
+          if ((e = hipEventRecord(t1, s)) != hipSuccess || (e = hipEventSynchronize(t1)) != hipSuccess) {
+            st = hip_fail(e, "tune");
+            break;
+          }
+          float ms = 0;
+          (void)hipEventElapsedTime(&ms, t0, t1);
+          if (rep > 0) total += ms;  // the first run warms caches
+        }
+        if (st == MI_OK && total < best_ms) {
+          best_ms = total;
+          best = cand;
+        }
+      }
+    }
+  }
+  if (t0) (void)hipEventDestroy(t0);
+  if (t1) (void)hipEventDestroy(t1);
+  ctx->timing = was_timing;
+  if (st != MI_OK) return st;
+  const TuneKey k = tune_key(fixed, moving, n, bins, flags);
+  bool found = false;
+  for (auto& entry : ctx->tuned)
+    if (entry.first == k) {
+      entry.second = best;
+      found = true;
+    }
+  if (!found) ctx->tuned.emplace_back(k, best);
+  save_tune_file(ctx);
   return MI_OK;
 }
 
@@ -539,61 +815,26 @@ int mi_eval(mi_context* ctx, const mi_volume* fixed, const mi_volume* moving,
   if (!workspace || workspace_bytes < L.total) return MI_ERR_WORKSPACE;
   if (!ctx) return MI_ERR_NULL;
   if (n == 0) return MI_OK;
-
   hipStream_t s = (hipStream_t)stream;
   hipError_t e;
   if ((e = hipSetDevice(ctx->device)) != hipSuccess) return hip_fail(e, "hipSetDevice");
   char* ws = (char*)workspace;
-  uint8_t* fb = (uint8_t*)(ws + L.fbins);
-  const size_t bb = (size_t)bins * bins;
-  ReduceLaunch R;
-  memset(&R, 0, sizeof R);
-  R.transforms = transforms;
-  R.n = n;
-  R.bins = bins;
-  R.q = qlist(q, n_q, flags);
-  R.mi_out = mi_out;
-  R.overlap_out = overlap_out;
-  if (!parzen) {
-    if ((e = launch_prebin_fixed(desc(fixed), bins, fb, s)) != hipSuccess) return hip_fail(e, "prebin");
-    uint32_t* hist = hist_out ? hist_out : (uint32_t*)(ws + L.hist);
-    uint2* quads = (uint2*)(ws + L.quads);
-    if ((e = launch_pack_quads(desc(moving), quads, s)) != hipSuccess) return hip_fail(e, "pack");
-    if ((e = launch_fill_u32(hist, bb * n, 0u, s)) != hipSuccess) return hip_fail(e, "fill");
-    HardLaunch H;
-    H.transforms = transforms;
-    H.fbins = fb;
-    H.quads = quads;
-    H.fixed = desc(fixed);
-    H.moving = desc(moving);
-    H.hist = hist;
-    H.n = n;
-    H.bins = bins;
-    H.clamp = (flags & MI_BOUNDARY_CLAMP) ? 1 : 0;
-    H.packed = bins > 128 ? 1 : 0;
-    H.block = ctx->hard_block;
-    H.slab_major = ctx->hard_slab_major;
-    H.chunks = plan_chunks(ctx, fixed, n, H.packed != 0);
-    // one launch covers at most 2^31 - 1 workgroups: split the transforms
-    const int64_t per_launch = 0x7FFFFFFFll / H.chunks;
-    for (int64_t t0 = 0; t0 < n; t0 += per_launch) {
-      HardLaunch part = H;
-      part.n = (int32_t)(n - t0 < per_launch ? n - t0 : per_launch);
-      part.transforms = transforms + 12 * t0;
-      part.hist = hist + bb * t0;
-      TimedLaunch tl(ctx, 0, s);
-      if ((e = launch_hist_hard(part, s)) != hipSuccess) return hip_fail(e, "hist_hard");
-      tl.done();
-    }
-    R.hist = hist;
-  } else {
-    return run_parzen(ctx, fixed, moving, transforms, n, bins, q, n_q, flags, mi_out, overlap_out,
-                      nullptr, ws, L, s);
-  }
-  TimedLaunch tr(ctx, 4, s);
-  if ((e = launch_mi_reduce(R, s)) != hipSuccess) return hip_fail(e, "mi_reduce");
-  tr.done();
-  return MI_OK;
+  auto body = [&]() -> int {
+    if (parzen)
+      return run_parzen(ctx, fixed, moving, transforms, n, bins, q, n_q, flags, mi_out, overlap_out,
+                        nullptr, ws, L, s);
+    return run_hard(ctx, fixed, moving, transforms, n, bins, q, n_q, flags, mi_out, overlap_out,
+                    hist_out, ws, L, s, tune_for(ctx, fixed, moving, n, bins, flags));
+  };
+  if (!use_graph(ctx, flags, s)) return body();
+  std::vector<uint64_t> key = {1, (uint64_t)(uintptr_t)transforms, (uint64_t)n, (uint64_t)bins,
+                               (uint64_t)flags, (uint64_t)(uintptr_t)mi_out,
+                               (uint64_t)(uintptr_t)overlap_out, (uint64_t)(uintptr_t)hist_out,
+                               (uint64_t)(uintptr_t)workspace, (uint64_t)(uintptr_t)s};
+  key_volume(key, fixed);
+  key_volume(key, moving);
+  key_q(key, q, n_q);
+  return graph_run(ctx, key, s, body);
 }
 
 int mi_grad(mi_context* ctx, const mi_volume* fixed, const mi_volume* moving,
@@ -610,8 +851,20 @@ int mi_grad(mi_context* ctx, const mi_volume* fixed, const mi_volume* moving,
   if (n == 0) return MI_OK;
   hipError_t e;
   if ((e = hipSetDevice(ctx->device)) != hipSuccess) return hip_fail(e, "hipSetDevice");
-  return run_parzen(ctx, fixed, moving, transforms, n, bins, q, n_q, flags, mi_out, nullptr,
-                    grad_out, (char*)workspace, L, (hipStream_t)stream);
+  hipStream_t s = (hipStream_t)stream;
+  auto body = [&]() -> int {
+    return run_parzen(ctx, fixed, moving, transforms, n, bins, q, n_q, flags, mi_out, nullptr,
+                      grad_out, (char*)workspace, L, s);
+  };
+  if (!use_graph(ctx, flags, s)) return body();
+  std::vector<uint64_t> key = {2, (uint64_t)(uintptr_t)transforms, (uint64_t)n, (uint64_t)bins,
+                               (uint64_t)flags, (uint64_t)(uintptr_t)mi_out,
+                               (uint64_t)(uintptr_t)grad_out, (uint64_t)(uintptr_t)workspace,
+                               (uint64_t)(uintptr_t)s};
+  key_volume(key, fixed);
+  key_volume(key, moving);
+  key_q(key, q, n_q);
+  return graph_run(ctx, key, s, body);
 }
 
 int mi_pairs_workspace_size(const mi_pair* pairs, int32_t n_pairs, int32_t bins, int32_t n_q,
@@ -706,26 +959,41 @@ int mi_eval_pairs(mi_context* ctx, const mi_pair* pairs, int32_t n_pairs, int32_
   L.packed = bins > 128 ? 1 : 0;
   L.cu_count = ctx->cu_count;
   const size_t bb = (size_t)bins * bins;
-  if ((e = launch_fill_u32((uint32_t*)a.counters, 16, 0u, s)) != hipSuccess) return hip_fail(e, "fill");
-  if ((e = launch_fill_u32(a.hist, bb * plan.total_t, 0u, s)) != hipSuccess) return hip_fail(e, "fill");
-  if ((e = launch_pairs_prep(L, s)) != hipSuccess) return hip_fail(e, "pairs prep");
-  {
-    TimedLaunch tl(ctx, 3, s);
-    if ((e = launch_pairs_hist(L, s)) != hipSuccess) return hip_fail(e, "pairs hist");
-    tl.done();
+  auto body = [&]() -> int {
+    hipError_t err;
+    if ((err = launch_fill_u32((uint32_t*)a.counters, 16, 0u, s)) != hipSuccess) return hip_fail(err, "fill");
+    if ((err = launch_fill_u32(a.hist, bb * plan.total_t, 0u, s)) != hipSuccess) return hip_fail(err, "fill");
+    if ((err = launch_pairs_prep(L, s)) != hipSuccess) return hip_fail(err, "pairs prep");
+    {
+      TimedLaunch tl(ctx, 3, s);
+      if ((err = launch_pairs_hist(L, s)) != hipSuccess) return hip_fail(err, "pairs hist");
+      tl.done();
+    }
+    ReduceLaunch R;
+    memset(&R, 0, sizeof R);
+    R.hist = a.hist;
+    R.transforms = a.transforms;
+    R.n = (int32_t)plan.total_t;
+    R.bins = bins;
+    R.q = qlist(q, n_q, flags);
+    R.mi_out = mi_out;
+    TimedLaunch tr(ctx, 4, s);
+    if ((err = launch_mi_reduce(R, s)) != hipSuccess) return hip_fail(err, "mi_reduce");
+    tr.done();
+    return MI_OK;
+  };
+  if (!use_graph(ctx, flags, s)) return body();
+  std::vector<uint64_t> key = {3, (uint64_t)P, (uint64_t)bins, (uint64_t)flags,
+                               (uint64_t)(uintptr_t)mi_out, (uint64_t)(uintptr_t)workspace,
+                               (uint64_t)(uintptr_t)s};
+  key_q(key, q, n_q);
+  for (int p = 0; p < P; ++p) {
+    key_volume(key, &pairs[p].fixed);
+    key_volume(key, &pairs[p].moving);
+    key.push_back((uint64_t)(uintptr_t)pairs[p].transforms);
+    key.push_back((uint64_t)pairs[p].n_transforms);
   }
-  ReduceLaunch R;
-  memset(&R, 0, sizeof R);
-  R.hist = a.hist;
-  R.transforms = a.transforms;
-  R.n = (int32_t)plan.total_t;
-  R.bins = bins;
-  R.q = qlist(q, n_q, flags);
-  R.mi_out = mi_out;
-  TimedLaunch tr(ctx, 4, s);
-  if ((e = launch_mi_reduce(R, s)) != hipSuccess) return hip_fail(e, "mi_reduce");
-  tr.done();
-  return MI_OK;
+  return graph_run(ctx, key, s, body);
 }
 
 }  // extern "C"

@@ -38,6 +38,7 @@ def test_header_constants_match_binding():
     assert consts["MI_ERR_COUNT"] == B.MI_ERR_COUNT and consts["MI_ERR_NO_DEVICE"] == B.MI_ERR_NO_DEVICE
     assert consts["MI_HIST_PARZEN"] == B.HIST_PARZEN and consts["MI_BOUNDARY_CLAMP"] == B.BOUNDARY_CLAMP
     assert consts["MI_TSALLIS_PSEUDOADDITIVE"] == B.TSALLIS_PSEUDOADDITIVE
+    assert consts["MI_USE_GRAPH"] == B.USE_GRAPH
     assert ctypes.sizeof(B.MiVolume) == 40
 
 
@@ -155,3 +156,41 @@ def test_timing_and_pairs_null_checks():
     assert lib.mi_timing_enable(None, 1) == B.MI_ERR_NULL
     ms, n = ctypes.c_double(), ctypes.c_int64()
     assert lib.mi_timing_read(None, 0, ctypes.byref(ms), ctypes.byref(n)) == B.MI_ERR_NULL
+
+
+def test_graph_flag_accepted_and_unknown_bits_rejected():
+    assert call_eval(vol(), vol(), flags=B.USE_GRAPH) == B.MI_ERR_NULL
+    assert call_eval(vol(), vol(), flags=B.USE_GRAPH | B.HIST_PARZEN) == B.MI_ERR_NULL
+    assert call_eval(vol(), vol(), flags=0x2000) == B.MI_ERR_FLAGS
+
+
+def test_tune_validation():
+    lib = B.load()
+    f, m = vol(), vol()
+    assert lib.mi_tune(None, ctypes.byref(f), ctypes.byref(m), FAKE, 4, 32, 0, FAKE, 1 << 40, None) == B.MI_ERR_NULL
+    assert lib.mi_tune(None, ctypes.byref(f), ctypes.byref(m), FAKE, 4, 32, B.HIST_PARZEN, FAKE, 1 << 40,
+                       None) == B.MI_ERR_UNSUPPORTED
+    assert lib.mi_tune(None, ctypes.byref(f), ctypes.byref(m), FAKE, 4, 1, 0, FAKE, 1 << 40, None) == B.MI_ERR_BINS
+
+
+def pairs_ws(pairs, bins=32, n_q=1, flags=0):
+    arr = (B.MiPair * len(pairs))(*pairs)
+    out = ctypes.c_size_t()
+    st = B.load().mi_pairs_workspace_size(arr, len(pairs), bins, n_q, flags, ctypes.byref(out))
+    return st, out.value
+
+
+def test_pairs_validation_and_layout():
+    p1 = B.MiPair(vol(8, 8, 8), vol(9, 8, 7), FAKE, 3)
+    p2 = B.MiPair(vol(16, 4, 2), vol(5, 6, 7, dtype=B.U16, lo=0.0, hi=4095.0), FAKE, 0)
+    st, n = pairs_ws([p1, p2], bins=32, n_q=2)
+    assert st == 0 and n > 0
+    # per-pair fixed bins + quad volumes + 3 transforms' histograms are included
+    assert n >= 8 * 8 * 8 + 9 * 8 * 8 * 8 + 16 * 4 * 2 + 5 * 6 * 8 * 8 + 3 * 32 * 32 * 4
+    bad = B.MiPair(vol(8, 8, 8), vol(dtype=B.F32, lo=0.0, hi=1.0), FAKE, 3)
+    assert pairs_ws([p1, bad])[0] == B.MI_ERR_DTYPE
+    assert pairs_ws([B.MiPair(vol(), vol(), None, 3)])[0] == B.MI_ERR_NULL
+    assert pairs_ws([B.MiPair(vol(), vol(), FAKE, -1)])[0] == B.MI_ERR_COUNT
+    assert pairs_ws([p1], bins=300)[0] == B.MI_ERR_BINS
+    assert pairs_ws([p1], flags=B.HIST_PARZEN)[0] == B.MI_ERR_FLAGS
+    assert pairs_ws([])[0] == 0

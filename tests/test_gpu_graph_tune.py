@@ -1,0 +1,128 @@
+"""GPU tests of HIP-graph replay (MI_USE_GRAPH) and of the autotuner.
+
+Each graph is replayed several times with the program's own eager work and
+synchronisations in between, and every replay is checked against an eager
+call; the transforms are updated in place between replays, so a replay
+must read the current device data.  The autotuner must leave results
+bit-identical (the sweep is exact whatever its launch shape) and record its
+choice in the cache file named by MI_TUNE_CACHE."""
+import os
+
+import numpy as np
+import pytest
+
+from paper_1909_10690_amd import inputs
+from paper_1909_10690_amd import transforms as T
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    from paper_1909_10690_amd import binding as B
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    c = B.Context(0)
+    yield c
+    c.close()
+
+
+def _case():
+    c = inputs.multimodal_sweep(shape_xyz=(96, 80, 48), n_tx=3, n_rot=3, n_scale=3)
+    return c
+
+
+def test_graph_replays_match_eager(ctx):
+    import torch
+    from paper_1909_10690_amd import binding as B
+    c = _case()
+    F = B.Volume.from_numpy(c["fixed"], 0, 4095)
+    M = B.Volume.from_numpy(c["moving"], 0, 4095)
+    base = torch.from_numpy(c["transforms"]).cuda()
+    tr = base.clone()
+    n, bins, q = len(base), c["bins"], c["q"]
+    stream = torch.cuda.Stream()
+    ws = torch.empty(ctx.workspace_size(F, M, n, bins, len(q)), dtype=torch.uint8, device="cuda")
+    out = torch.empty((n, len(q)), dtype=torch.float64, device="cuda")
+    hist = None
+    rng = np.random.default_rng(0)
+    for rep in range(4):
+        if rep:
+            # new transforms, written in place into the captured buffer
+            shift = torch.from_numpy(rng.uniform(-2, 2, (n, 3))).cuda()
+            tr.copy_(base)
+            tr.view(n, 3, 4)[:, :, 3] += shift
+        with torch.cuda.stream(stream):
+            ctx.eval(F, M, tr, bins, q, flags=B.USE_GRAPH, out=out, workspace=ws, want_overlap=False)
+        stream.synchronize()
+        got = out.cpu().numpy().copy()
+        ref, _, _ = ctx.eval(F, M, tr.clone(), bins, q)   # eager, default stream
+        torch.cuda.synchronize()
+        assert np.array_equal(got, ref.cpu().numpy()), f"replay {rep}"
+
+
+def test_graph_gradient_and_pairs(ctx):
+    import torch
+    from paper_1909_10690_amd import binding as B
+    c = inputs.parzen_gradient(n=40, n_transforms=5)
+    F = B.Volume.from_numpy(c["fixed"], 0.0, 1.0)
+    M = B.Volume.from_numpy(c["moving"], 0.0, 1.0)
+    tr = torch.from_numpy(c["transforms"]).cuda()
+    stream = torch.cuda.Stream()
+    ws = torch.empty(ctx.workspace_size(F, M, 5, 32, 2, B.BOUNDARY_CLAMP | B.HIST_PARZEN, True),
+                     dtype=torch.uint8, device="cuda")
+    ref_mi, ref_g = ctx.grad(F, M, tr, 32, [1.0, 1.5])
+    torch.cuda.synchronize()
+    for rep in range(3):
+        with torch.cuda.stream(stream):
+            mi, g = ctx.grad(F, M, tr, 32, [1.0, 1.5], flags=B.BOUNDARY_CLAMP | B.USE_GRAPH, workspace=ws)
+        stream.synchronize()
+        # fp64 atomics merge workgroup partials in any order
+        np.testing.assert_allclose(mi.cpu().numpy(), ref_mi.cpu().numpy(), rtol=1e-12, atol=1e-15)
+        np.testing.assert_allclose(g.cpu().numpy(), ref_g.cpu().numpy(), rtol=1e-9, atol=1e-12)
+        torch.cuda.synchronize()
+
+    rng = np.random.default_rng(4)
+    pairs = []
+    for shape in [(20, 18, 16), (33, 9, 12), (17, 17, 40)]:
+        f = inputs.random_volume(rng, shape, np.uint8, 0, 255)
+        m = inputs.random_volume(rng, shape, np.uint8, 0, 255)
+        mats = inputs.random_affines(rng, 3, shape, rot=10, trans=3)
+        pairs.append((B.Volume.from_numpy(f, 0, 255), B.Volume.from_numpy(m, 0, 255),
+                      torch.from_numpy(mats).cuda()))
+    ref = ctx.eval_pairs(pairs, 16, [1.0, 2.0]).cpu().numpy()
+    for rep in range(3):
+        with torch.cuda.stream(stream):
+            got = ctx.eval_pairs(pairs, 16, [1.0, 2.0], flags=B.USE_GRAPH)
+        stream.synchronize()
+        assert np.array_equal(got.cpu().numpy(), ref), f"pairs replay {rep}"
+
+
+def test_tune_keeps_results_and_writes_cache(tmp_path):
+    import torch
+    from paper_1909_10690_amd import binding as B
+    path = tmp_path / "tune.txt"
+    os.environ["MI_TUNE_CACHE"] = str(path)
+    try:
+        ctx = B.Context(0)
+        c = _case()
+        F = B.Volume.from_numpy(c["fixed"], 0, 4095)
+        M = B.Volume.from_numpy(c["moving"], 0, 4095)
+        tr = torch.from_numpy(c["transforms"]).cuda()
+        before, _, hb = ctx.eval(F, M, tr, 128, c["q"], want_hist=True)
+        ctx.tune(F, M, tr, 128)
+        after, _, ha = ctx.eval(F, M, tr, 128, c["q"], want_hist=True)
+        torch.cuda.synchronize()
+        assert torch.equal(hb, ha) and torch.equal(before, after)
+        lines = [l for l in path.read_text().splitlines() if l.startswith("gemi-tune")]
+        assert len(lines) == 1
+        fields = lines[0].split()
+        assert fields[1:4] == ["96", "80", "48"] and fields[11] in ("256", "512", "1024")
+        ctx.close()
+        ctx2 = B.Context(0)   # reads the cache file
+        again, _, _ = ctx2.eval(F, M, tr, 128, c["q"])
+        torch.cuda.synchronize()
+        assert torch.equal(again, before)
+        ctx2.close()
+    finally:
+        del os.environ["MI_TUNE_CACHE"]
