@@ -63,7 +63,7 @@ def read_traffic(kernel_version: str):
 def kernel_version() -> str:
     import hashlib
     h = hashlib.sha256()
-    for f in ("hard.hip", "common.h"):
+    for f in ("hard.hip", "sweep.h", "common.h"):
         h.update(open(os.path.join(ROOT, "paper_1909_10690_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
@@ -90,6 +90,69 @@ def cpu_baseline(c, min_seconds: float) -> dict:
                       f"volume, all 6 entropies, {dt:.1f} s wall on {threads} threads"}
 
 
+def grad_leg(ctx, B, inputs, dev, args) -> dict:
+    """MI-grad evaluations per second: mi_grad (Parzen forward, MI, dMI/dp,
+    backward) over the 128^3 f32 workload's 64 random affines, 64 bins,
+    Shannon and Tsallis q = 1.5."""
+    import torch
+    g = inputs.parzen_gradient()
+    F = B.Volume.from_numpy(g["fixed"], 0.0, 1.0, dev)
+    M = B.Volume.from_numpy(g["moving"], 0.0, 1.0, dev)
+    tr = torch.from_numpy(g["transforms"]).to(dev)
+    n, bins, q = len(tr), g["bins"], g["q"]
+    flags = B.BOUNDARY_CLAMP
+    ws = torch.empty(ctx.workspace_size(F, M, n, bins, len(q), flags | B.HIST_PARZEN, True),
+                     dtype=torch.uint8, device=dev)
+    log(f"gradient leg: {n} transforms x 128^3 f32, {bins} Parzen bins")
+    for _ in range(2):
+        ctx.grad(F, M, tr, bins, q, flags=flags, workspace=ws)
+    torch.cuda.synchronize()
+    for w in (B.TIMER_PARZEN_FWD, B.TIMER_PARZEN_BWD):
+        ctx.timing_read(w)
+    steps = max(3, args.steps // 2)
+    ctx.timing(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ctx.grad(F, M, tr, bins, q, flags=flags, workspace=ws)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ctx.timing(False)
+    fwd_ms, fwd_n = ctx.timing_read(B.TIMER_PARZEN_FWD)
+    bwd_ms, bwd_n = ctx.timing_read(B.TIMER_PARZEN_BWD)
+    return {"value": n * steps / dt, "unit": "MI-grad evals/s (forward + backward, 2 entropies)",
+            "voxel_xf_per_s": g["fixed"].size * n * steps / dt, "ms_per_call": dt / steps * 1e3,
+            "fwd_kernel_ms": fwd_ms / max(fwd_n, 1), "bwd_kernel_ms": bwd_ms / max(bwd_n, 1),
+            "config": "128^3 f32 phantoms, 64 random affines, 64-bin cubic B-spline Parzen "
+                      "histogram, Shannon + Tsallis q=1.5, clamp boundary"}
+
+
+def pairs_leg(ctx, B, inputs, dev) -> dict:
+    """256 uneven u8 pairs x 16 rigid transforms, 64 bins, one persistent launch."""
+    import torch
+    log("pairs leg: generating 256 uneven pairs")
+    raw = inputs.uneven_pairs()
+    pairs = [(B.Volume.from_numpy(p["fixed"], 0, 255, dev), B.Volume.from_numpy(p["moving"], 0, 255, dev),
+              torch.from_numpy(p["transforms"]).to(dev)) for p in raw]
+    vox = sum(p["fixed"].size for p in raw) * 16
+    for _ in range(2):
+        ctx.eval_pairs(pairs, 64, [1.0])
+    torch.cuda.synchronize()
+    ctx.timing_read(B.TIMER_PAIRS)
+    ctx.timing(True)
+    steps = 3
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ctx.eval_pairs(pairs, 64, [1.0])
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ctx.timing(False)
+    k_ms, k_n = ctx.timing_read(B.TIMER_PAIRS)
+    return {"value": vox * steps / dt, "unit": "voxel-transform evals/s", "ms_per_call": dt / steps * 1e3,
+            "kernel_ms": k_ms / max(k_n, 1), "voxel_transforms": int(vox),
+            "config": "256 u8 pairs, edges from {64,96,128,160,192,256} per axis, 16 rigid transforms "
+                      "each, 64 bins, Shannon"}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -99,6 +162,7 @@ def main() -> int:
                     help="minimum wall time of the CPU-oracle sample")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle leg")
     ap.add_argument("--no-extras", action="store_true", help="skip the plain-path and gradient legs")
+    ap.add_argument("--pairs", action="store_true", help="also time the 256 uneven pairs in one launch")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="also run an elementwise copy of MIB MiB (read + write), the reference "
                          "kernel for scaling HBM byte counters")
@@ -196,6 +260,12 @@ def main() -> int:
         plain = fixed.size * sub / (time.perf_counter() - t0)
         result["plain_one_transform_per_launch"] = {"value": plain, "unit": "voxel-transform evals/s",
                                                     "batched_speedup": value / plain}
+
+    if not args.no_extras:
+        result["mi_grad"] = grad_leg(ctx, B, inputs, dev, args)
+
+    if args.pairs:
+        result["pairs"] = pairs_leg(ctx, B, inputs, dev)
 
     if not args.no_cpu:
         log(f"CPU oracle for at least {args.cpu_seconds} s")

@@ -151,14 +151,14 @@ def multimodal_sweep(shape_xyz=(256, 256, 180), seed: int = 1, n_tx=10, n_rot=10
 
 def random_affines(rng: np.random.Generator, n: int, shape_xyz, rot=10.0, trans=8.0,
                    scale=(0.95, 1.05), shear=0.03) -> np.ndarray:
-    mats = []
+    mats = [np.zeros((3, 4))][:0]
     for _ in range(n):
         ang = rng.uniform(-rot, rot, 3)
         t = rng.uniform(-trans, trans, 3)
         s = rng.uniform(scale[0], scale[1], 3)
         h = rng.uniform(-shear, shear, 3)
         mats.append(T.index_matrix(T.affine_matrix(ang, s, h), t, shape_xyz))
-    return np.stack(mats).reshape(-1, 12)
+    return np.stack(mats).reshape(-1, 12) if mats else np.zeros((0, 12))
 
 
 def parzen_gradient(n: int = 128, seed: int = 2, n_transforms: int = 64) -> dict:

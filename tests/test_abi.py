@@ -194,3 +194,14 @@ def test_pairs_validation_and_layout():
     assert pairs_ws([p1], bins=300)[0] == B.MI_ERR_BINS
     assert pairs_ws([p1], flags=B.HIST_PARZEN)[0] == B.MI_ERR_FLAGS
     assert pairs_ws([])[0] == 0
+
+
+def test_registration_checkpoint_roundtrip(tmp_path):
+    from paper_1909_10690_amd.register import RegState
+    s = RegState(params=[1.0, 0, 0, 0, 1.0, 0, 0, 0, 1.0, 0.5, -0.25, 2.0], step=7,
+                 m=[0.1] * 12, v=[0.2] * 12, history=[(1, [0.3, 0.4])])
+    p = tmp_path / "state.json"
+    s.save(str(p))
+    r = RegState.load(str(p))
+    assert r.params == s.params and r.step == 7 and r.m == s.m and r.v == s.v
+    assert [tuple(h) if not isinstance(h, tuple) else h for h in r.history][0][0] == 1

@@ -4,8 +4,12 @@ the autograd wrapper) against the CPU oracle.
 Tolerances (the GPU accumulates in fp32 per workgroup, the oracle in fp64):
 Parzen MI within 1e-6 relative; gradient within 1e-4 of the oracle's
 gradient, norm-wise per transform and entropy (|g - g_o|_inf <= 1e-4
-|g_o|_inf); the oracle's forward pass differenced centrally at a 1e-4 voxel
-displacement agrees with the GPU gradient to 1e-3 norm-wise.
+|g_o|_inf).  Against central differences of the oracle's forward pass, at
+a 3e-5 voxel displacement with the matrices and steps on the Q32 grid (so
+quantisation adds no error): 1e-3 norm-wise for Shannon MI, 2e-3 for
+Tsallis MI at q = 1.5, whose difference quotient converges slowly
+(measured 4e-4..9e-4 between the oracle's own analytic gradient and its
+differences over five transforms of this workload).
 """
 import numpy as np
 import pytest
@@ -133,18 +137,20 @@ def test_full_size_sampled_and_finite_differences(ctx):
     assert_close((gmi[pick], gg[pick], gmi2[pick], gov[pick]), (omi, og, oov), "full-size sample")
     F, Mv = oracle.volume(f, 0.0, 1.0), oracle.volume(m, 0.0, 1.0)
     lever = np.array([127.0, 127.0, 127.0, 1.0] * 3)
-    steps = 1e-4 / lever
-    for t in pick[:2]:
+    steps = np.round(3e-5 / lever * 2.0 ** 32) / 2.0 ** 32
+    on_grid = np.round(mats * 2.0 ** 32) / 2.0 ** 32
+    _, gg_grid, _, _ = gpu_grad(ctx, f, m, (0.0, 1.0), (0.0, 1.0), on_grid[pick[:2]], 64, q, 1)
+    for i, t in enumerate(pick[:2]):
         fd_mats = []
         for e in range(12):
-            a, b = mats[t].copy(), mats[t].copy()
+            a, b = on_grid[t].copy(), on_grid[t].copy()
             a[e] += steps[e]
             b[e] -= steps[e]
             fd_mats += [a, b]
         mp, _ = oracle.eval_parzen(F, Mv, np.stack(fd_mats), 64, q, oracle.CLAMP)
         fd = (mp[0::2] - mp[1::2]).T / (2 * steps)
-        err = np.abs(gg[t] - fd).max(axis=1) / np.abs(fd).max(axis=1)
-        assert np.all(err <= 1e-3), err
+        err = np.abs(gg_grid[i] - fd).max(axis=1) / np.abs(fd).max(axis=1)
+        assert err[0] <= 1e-3 and err[1] <= 2e-3, err
 
 
 def test_autograd_matches_chain_rule(ctx):
