@@ -152,7 +152,7 @@ constexpr size_t kStageBytes = 4u << 20;  // pinned staging for the pairs' table
 
 // Launch shape of the hard-binned sweep for one problem class.
 struct HardTune {
-  int32_t block = 512;
+  int32_t block = 1024;
   int32_t slab_major = 1;
   int32_t chunks = 0;  // 0 = planned per call
 };
@@ -305,7 +305,8 @@ int run_parzen(mi_context* ctx, const mi_volume* fixed, const mi_volume* moving,
   auto sweep = [&](bool backward, int which) -> int {
     ParzenLaunch part = P;
     ParzenArgs& pa = part.args;
-    pa.band_rows = band_rows_for(bins, backward ? kParzenQGroup : 1);
+    // backward: kParzenQGroup fp32 tables; forward: one table of 8-byte cells
+    pa.band_rows = band_rows_for(bins, backward ? kParzenQGroup : 2);
     pa.bands = (bins + pa.band_rows - 1) / pa.band_rows;
     pa.chunks = plan_parzen_chunks(ctx, fixed, (int64_t)n * pa.bands);
     const int64_t per_launch = 0x7FFFFFFFll / ((int64_t)pa.chunks * pa.bands);

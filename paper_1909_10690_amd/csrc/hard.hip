@@ -154,8 +154,13 @@ struct HardArgs {
   int32_t slab_major;  // 1: consecutive workgroups of an XCD share a slab
 };
 
+// 1024-thread workgroups are held to 64 VGPRs (a few row-loop values spill to
+// scratch) so that two of them, 8 waves per SIMD, share a CU next to two
+// 64 KiB LDS histograms; the sweep waits on its gathers and gains from the
+// extra waves.  Smaller workgroups keep their registers.
 template <bool CLAMP, bool PACKED, int NT>
-__global__ __launch_bounds__(NT) void hist_hard_kernel(HardArgs a) {
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT == 1024 ? 8 : 1)))
+void hist_hard_kernel(HardArgs a) {
   extern __shared__ uint32_t lds_hist[];
   const int B = a.geom.bins;
   const int words = PACKED ? (B * B + 1) / 2 : B * B;

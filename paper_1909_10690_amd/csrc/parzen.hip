@@ -98,6 +98,15 @@ __device__ __forceinline__ void bspline_slopes(float f, float d[4]) {
   d[3] = -0.5f * f * f;
 }
 
+// floor(w * 2^40) for a weight w in [0, 2/3], as hi * 2^32 + lo with
+// hi = floor(w * 2^8) < 2^8 and lo the next 32 bits of w * 2^8.
+__device__ __forceinline__ unsigned long long fixed40(float w) {
+  const float a = w * 256.0f;
+  const uint32_t hi = (uint32_t)a;
+  const uint32_t lo = (uint32_t)(__builtin_amdgcn_fractf(a) * 4294967296.0f);
+  return ((unsigned long long)hi << 32) | lo;
+}
+
 // Sweep geometry of one workgroup.
 struct SweepCtx {
   uint32_t t, chunk, band;
@@ -108,9 +117,20 @@ struct SweepCtx {
 // forward: Parzen table
 // ---------------------------------------------------------------------------
 
+// The band's table is accumulated in LDS as unsigned 24.40 fixed point: each
+// voxel adds its four B-spline weights scaled by 2^40, with the largest
+// derived by subtraction so that the voxel's mass is exactly 2^40 (the
+// weights sum to one, Eq. (10)).  Integer adds commute, so the table does
+// not depend on the order of the atomics.  The 2^-40 step keeps the tiny
+// taps (w ~ f^3 / 6) accurate to ~1e-12, below the fp32 rounding of the
+// weights themselves; a coarser step biases the near-empty cells that
+// dominate the Tsallis gradient for q < 1.  A 64-bit cell cannot overflow:
+// a workgroup covers fewer than 2^24 voxels (2^28 voxels at most, split
+// into at least 32 workgroups per transform).  64-bit LDS atomics need an
+// 8-byte aligned address, hence the alignment of the table.
 template <bool FQ, bool CLAMP, int NT>
 __global__ __launch_bounds__(NT) void parzen_fwd_kernel(ParzenArgs a) {
-  extern __shared__ float lds_tab[];
+  extern __shared__ __align__(16) unsigned long long lds_tab[];
   __shared__ uint32_t lds_count;
   const int B = a.bins;
   SweepCtx sc;
@@ -118,7 +138,7 @@ __global__ __launch_bounds__(NT) void parzen_fwd_kernel(ParzenArgs a) {
   sc.r_lo = (int32_t)sc.band * a.band_rows;
   sc.r_hi = min(B, sc.r_lo + a.band_rows);
   const int cells = (sc.r_hi - sc.r_lo) * B;
-  for (int e = threadIdx.x; e < cells; e += NT) lds_tab[e] = 0.0f;
+  for (int e = threadIdx.x; e < cells; e += NT) lds_tab[e] = 0ull;
   if (threadIdx.x == 0) lds_count = 0;
   int64_t Mq[12];
   const bool ok = quantize_transform(a.transforms + 12 * (size_t)sc.t, Mq);
@@ -172,9 +192,13 @@ __global__ __launch_bounds__(NT) void parzen_fwd_kernel(ParzenArgs a) {
         const float fl = floorf(s);
         float wt[4];
         bspline_weights(s - fl, wt);
-        float* cell = lds_tab + (fb - sc.r_lo) * B + ((int32_t)fl - 1);
-#pragma unroll
-        for (int i = 0; i < 4; ++i) atomicAdd(cell + i, wt[i]);
+        const unsigned long long q0 = fixed40(wt[0]), q2 = fixed40(wt[2]), q3 = fixed40(wt[3]);
+        const unsigned long long q1 = (1ull << 40) - q0 - q2 - q3;  // w1 >= 1/6
+        unsigned long long* cell = lds_tab + (fb - sc.r_lo) * B + ((int32_t)fl - 1);
+        atomicAdd(cell + 0, q0);
+        atomicAdd(cell + 1, q1);
+        atomicAdd(cell + 2, q2);
+        atomicAdd(cell + 3, q3);
       }
     }
   }
@@ -183,8 +207,8 @@ __global__ __launch_bounds__(NT) void parzen_fwd_kernel(ParzenArgs a) {
   if (!ok) return;
   double* __restrict__ out = a.table + (size_t)sc.t * B * B + (size_t)sc.r_lo * B;
   for (int e = threadIdx.x; e < cells; e += NT) {
-    const float v = lds_tab[e];
-    if (v != 0.0f) atomicAdd(&out[e], (double)v);
+    const unsigned long long v = lds_tab[e];
+    if (v) atomicAdd(&out[e], (double)v * 9.094947017729282379150390625e-13);  // 2^-40
   }
   if (threadIdx.x == 0 && sc.band == 0 && lds_count)
     atomicAdd((unsigned long long*)&a.count[sc.t], (unsigned long long)lds_count);
@@ -399,7 +423,7 @@ static hipError_t fwd_variant(const ParzenArgs& a, size_t lds, hipStream_t s) {
 
 hipError_t launch_parzen_fwd(const ParzenLaunch& L, hipStream_t s) {
   ParzenArgs a = L.args;
-  const size_t lds = (size_t)a.band_rows * a.bins * 4;
+  const size_t lds = (size_t)a.band_rows * a.bins * 8;
   if (L.float_quads)
     return L.clamp ? fwd_variant<true, true>(a, lds, s) : fwd_variant<true, false>(a, lds, s);
   return L.clamp ? fwd_variant<false, true>(a, lds, s) : fwd_variant<false, false>(a, lds, s);

@@ -82,13 +82,15 @@ __device__ __forceinline__ void sweep_hard(const HardGeom& g, const int64_t* Mq,
       const uint32_t wy = fy >> 16, wz = fz >> 16;
       const double wyd = (double)wy, wzd = (double)wz;
       const double A00 = (double)a00, A10 = (double)a10, A01 = (double)a01, A11 = (double)a11;
-      const double b0 = fma(A10 - A00, wyd, A00 * 65536.0);  // exact, < 2^48
-      const double b1 = fma(A11 - A01, wyd, A01 * 65536.0);  // exact, < 2^48
-      const double V = fma(b1 - b0, wzd, b0 * 65536.0);      // exact value rounded once
+      const double uyd = 65536.0 - wyd;
+      const double b0 = fma(A10, wyd, A00 * uyd);         // exact, < 2^48
+      const double b1 = fma(A11, wyd, A01 * uyd);         // exact, < 2^48
+      const double V = fma(b1 - b0, wzd, b0 * 65536.0);  // exact value rounded once
       const double tb = V * scale;
       uint32_t bm = (uint32_t)tb;
-      const double fr = tb - (double)bm;
-      if (fr < kEdge || fr > 1.0 - kEdge) bm = exact_bin(a00, a10, a01, a11, wy, wz, Bu, g.div);
+      // within kEdge of a bin edge: fr < kEdge or fr > 1 - kEdge
+      const double fr = __builtin_amdgcn_fract(tb);
+      if (fabs(fr - 0.5) > 0.5 - kEdge) bm = exact_bin(a00, a10, a01, a11, wy, wz, Bu, g.div);
       const uint32_t cell = __umul24(fb, Bu) + bm;
       if (PACKED)
         atomicAdd(&lds_hist[cell >> 1], 1u << ((cell & 1u) * 16u));
