@@ -70,7 +70,10 @@ extern "C" {
 /* ---- status codes ------------------------------------------------------ */
 #define MI_OK 0
 #define MI_ERR_NULL (-1)        /* a required pointer is NULL             */
-#define MI_ERR_DIMS (-2)        /* a volume edge outside [2, 4096], or more than 2^28 voxels */
+#define MI_ERR_DIMS (-2)        /* a volume edge outside [2, 4096], more than 2^28 voxels,
+                                   or a moving volume of 2^28 voxels or more (integer) or
+                                   of nx*ny*(nz+1) >= 2^28 (float, Parzen path): its
+                                   gather layout must stay within 4 GiB */
 #define MI_ERR_DTYPE (-3)       /* unknown dtype, or MI_F32 moving volume on the hard path */
 #define MI_ERR_BINS (-4)        /* bins outside [2, 256] ([8, 256] for Parzen) */
 #define MI_ERR_RANGE (-5)       /* lo/hi not finite, hi <= lo, or (integer dtypes) not

@@ -40,8 +40,6 @@ int hip_fail(hipError_t e, const char* where) {
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-size_t dtype_size(int32_t d) { return d == MI_U8 ? 1 : (d == MI_F32 ? 4 : 2); }
-
 size_t voxels(const mi_volume* v) { return (size_t)v->nx * v->ny * v->nz; }
 
 int check_volume(const mi_volume* v, bool need_integer) {
@@ -69,6 +67,21 @@ int check_q(const double* q, int32_t n_q) {
   return MI_OK;
 }
 
+// Bytes of the moving volume's gather layout (oct volume for integer
+// volumes, fp32 quad volume for float ones).
+size_t gather_bytes(const mi_volume* m) {
+  return m->dtype == MI_F32 ? quad_f32_bytes(m->nx, m->ny, m->nz)
+                            : oct_volume_bytes(m->nx, m->ny, m->nz);
+}
+
+// A moving volume whose gather layout needs 32-bit buffer offsets beyond
+// 4 GiB is refused (fewer than 2^28 voxels for integer volumes).
+int check_moving(const mi_volume* m, bool need_integer) {
+  const int st = check_volume(m, need_integer);
+  if (st != MI_OK) return st;
+  return gather_bytes(m) > kMaxGatherBytes ? MI_ERR_DIMS : MI_OK;
+}
+
 constexpr int32_t kKnownFlags =
     MI_BOUNDARY_CLAMP | MI_TSALLIS_PSEUDOADDITIVE | MI_HIST_PARZEN | MI_USE_GRAPH;
 
@@ -77,7 +90,7 @@ int check_common(const mi_volume* f, const mi_volume* m, int32_t n, int32_t bins
   if (flags & ~kKnownFlags) return MI_ERR_FLAGS;
   int st;
   if ((st = check_volume(f, false)) != MI_OK) return st;
-  if ((st = check_volume(m, !parzen)) != MI_OK) return st;
+  if ((st = check_moving(m, !parzen)) != MI_OK) return st;
   if (n < 0 || n > (1 << 24)) return MI_ERR_COUNT;
   if (bins < (parzen ? 8 : 2) || bins > 256) return MI_ERR_BINS;
   if (q != nullptr || n_q != 0) {
@@ -88,14 +101,16 @@ int check_common(const mi_volume* f, const mi_volume* m, int32_t n, int32_t bins
 
 // Workspace layout (each region 256-byte aligned):
 //   fixed bins   u8[nvox_fixed]
-//   hard:        moving quad volume u16x4[mnz+1][mny][mnx],
+//   hard:        moving oct volume u16x8[mnz][mny][mnx],
 //                hist u32[n][B][B]          (only when the caller passes no hist_out)
-//   Parzen:      moving quad volume (u16x4, or f32x4 for a float moving
-//                volume) [mnz+1][mny][mnx], table f64[n][B][B], count u64[n]
+//   Parzen:      moving oct volume (integer moving volume) or f32x4 quad
+//                volume [mnz+1][mny][mnx] (float moving volume),
+//                table f64[n][B][B], count u64[n]
 //   Parzen grad: + dMI/dp tables f32[n][n_q][B][B]
 struct Layout {
-  size_t fbins = 0, quads = 0, hist = 0, table = 0, count = 0, gtab = 0, total = 0;
+  size_t fbins = 0, gvol = 0, hist = 0, table = 0, count = 0, gtab = 0, total = 0;
 };
+
 
 Layout layout(const mi_volume* f, const mi_volume* m, int32_t n, int32_t bins, int32_t n_q,
               bool parzen, bool grad, bool need_hist) {
@@ -105,13 +120,13 @@ Layout layout(const mi_volume* f, const mi_volume* m, int32_t n, int32_t bins, i
   off += align256(voxels(f));
   const size_t bb = (size_t)bins * bins;
   if (!parzen) {
-    L.quads = off;
-    off += align256(quad_volume_bytes(m->nx, m->ny, m->nz));
+    L.gvol = off;
+    off += align256(gather_bytes(m));
     L.hist = off;
     if (need_hist) off += align256(bb * 4 * (size_t)n);
   } else {
-    L.quads = off;
-    off += align256(quad_volume_bytes(m->nx, m->ny, m->nz) * (m->dtype == MI_F32 ? 2 : 1));
+    L.gvol = off;
+    off += align256(gather_bytes(m));
     L.table = off;
     off += align256(bb * 8 * (size_t)n);
     L.count = off;
@@ -210,22 +225,33 @@ struct TimedLaunch {
   }
 };
 
+// Slabs per transform that keep one slab's share of the moving gather
+// volume near 1.5 MiB: the workgroups of an XCD sweep one slab for many
+// transforms at once, and their moving footprint must stay in the XCD's
+// 4 MiB L2 (on the 1000-transform 256x256x180 sweep, 128 slabs instead of
+// 32 cut the L2 miss traffic and the sweep time by 8%).
+int64_t l2_slabs(const mi_volume* m) {
+  const int64_t target = 3 << 19;  // 1.5 MiB
+  const int64_t c = ((int64_t)gather_bytes(m) + target - 1) / target;
+  return c < 32 ? 32 : c;
+}
+
 // Workgroups per transform for the histogram sweep.  The fixed volume is
 // swept in groups of 4 rows; a transform's groups are split into `c`
-// slabs: enough workgroups to fill the chip several times over, at least
-// 32 thin slabs in slab-major order (the moving footprint of one slab must
-// fit an XCD's L2), a multiple of 8 (one share per XCD), and -- with 16-bit
-// packed LDS counters -- few enough voxels per workgroup that no counter
-// can exceed 65535.
-int plan_chunks(const mi_context* ctx, const mi_volume* f, int32_t n, bool packed,
-                const HardTune& tune) {
+// slabs: enough workgroups to fill the chip several times over, in
+// slab-major order enough thin slabs that a slab's moving footprint fits
+// an XCD's L2 (l2_slabs), a multiple of 8 (one share per XCD), and -- with
+// 16-bit packed LDS counters -- few enough voxels per workgroup that no
+// counter can exceed 65535.
+int plan_chunks(const mi_context* ctx, const mi_volume* f, const mi_volume* m, int32_t n,
+                bool packed, const HardTune& tune) {
   const int64_t groups = (int64_t)((f->ny + 3) / 4) * f->nz;
   int64_t c;
   if (tune.chunks) {
     c = tune.chunks;
   } else {
     c = ((int64_t)ctx->cu_count * 8 + n - 1) / n;
-    if (tune.slab_major && c < 32) c = 32;
+    if (tune.slab_major && c < l2_slabs(m)) c = l2_slabs(m);
   }
   if (c > groups) c = groups;
   if (packed) {
@@ -239,10 +265,10 @@ int plan_chunks(const mi_context* ctx, const mi_volume* f, int32_t n, bool packe
 
 
 // Workgroups per transform and band for the Parzen sweeps (as plan_chunks).
-int plan_parzen_chunks(const mi_context* ctx, const mi_volume* f, int64_t units) {
+int plan_parzen_chunks(const mi_context* ctx, const mi_volume* f, const mi_volume* m, int64_t units) {
   const int64_t groups = (int64_t)((f->ny + 3) / 4) * f->nz;
   int64_t c = ((int64_t)ctx->cu_count * 8 + units - 1) / units;
-  if (c < 32) c = 32;
+  if (c < l2_slabs(m)) c = l2_slabs(m);
   if (c > groups) c = groups;
   return (int)(((c + 7) / 8) * 8);
 }
@@ -263,9 +289,9 @@ int run_parzen(mi_context* ctx, const mi_volume* fixed, const mi_volume* moving,
   uint8_t* fb = (uint8_t*)(ws + L.fbins);
   if ((e = launch_prebin_fixed(desc(fixed), bins, fb, s)) != hipSuccess) return hip_fail(e, "prebin");
   const bool fq = moving->dtype == MI_F32;
-  void* quads = ws + L.quads;
-  e = fq ? launch_pack_quads_f32(desc(moving), (float4*)quads, s)
-         : launch_pack_quads(desc(moving), (uint2*)quads, s);
+  void* gvol = ws + L.gvol;
+  e = fq ? launch_pack_quads_f32(desc(moving), (float4*)gvol, s)
+         : launch_pack_octs(desc(moving), (uint4*)gvol, s);
   if (e != hipSuccess) return hip_fail(e, "pack");
   const size_t bb = (size_t)bins * bins;
   double* table = (double*)(ws + L.table);
@@ -280,7 +306,7 @@ int run_parzen(mi_context* ctx, const mi_volume* fixed, const mi_volume* moving,
   ParzenArgs& a = P.args;
   a.transforms = transforms;
   a.fbins = fb;
-  a.quads = quads;
+  a.gvol = gvol;
   a.table = table;
   a.count = count;
   a.gtab = (const float*)(ws + L.gtab);
@@ -291,7 +317,7 @@ int run_parzen(mi_context* ctx, const mi_volume* fixed, const mi_volume* moving,
   a.mnx = moving->nx;
   a.mny = moving->ny;
   a.mnz = moving->nz;
-  a.quad_bytes = (uint32_t)(quad_volume_bytes(moving->nx, moving->ny, moving->nz) * (fq ? 2 : 1));
+  a.gvol_bytes = (uint32_t)gather_bytes(moving);
   a.n = n;
   a.bins = bins;
   a.slab_major = 1;
@@ -308,7 +334,7 @@ int run_parzen(mi_context* ctx, const mi_volume* fixed, const mi_volume* moving,
     // backward: kParzenQGroup fp32 tables; forward: one table of 8-byte cells
     pa.band_rows = band_rows_for(bins, backward ? kParzenQGroup : 2);
     pa.bands = (bins + pa.band_rows - 1) / pa.band_rows;
-    pa.chunks = plan_parzen_chunks(ctx, fixed, (int64_t)n * pa.bands);
+    pa.chunks = plan_parzen_chunks(ctx, fixed, moving, (int64_t)n * pa.bands);
     const int64_t per_launch = 0x7FFFFFFFll / ((int64_t)pa.chunks * pa.bands);
     for (int64_t t0 = 0; t0 < n; t0 += per_launch) {
       pa.n = (int32_t)(n - t0 < per_launch ? n - t0 : per_launch);
@@ -355,7 +381,7 @@ int run_parzen(mi_context* ctx, const mi_volume* fixed, const mi_volume* moving,
 struct PairsPlan {
   size_t tables = 0, table_bytes = 0, counters = 0, transforms = 0, hist = 0, total = 0;
   size_t off_desc = 0, off_frow = 0, off_mrow = 0, off_tbase = 0, off_xcd = 0;
-  std::vector<size_t> fbins, quads;
+  std::vector<size_t> fbins, octs;
   std::vector<int32_t> chunks;
   std::vector<int64_t> frow_base, mrow_base, t_base, xcd_base;  // xcd_base: [8][P+1]
   int64_t total_t = 0;
@@ -370,7 +396,7 @@ int plan_pairs(const mi_pair* pairs, int32_t n_pairs, int32_t bins, int32_t n_q,
   if (n_q < 1 || n_q > MI_MAX_Q) return MI_ERR_Q;
   const int P = n_pairs;
   plan.fbins.resize(P);
-  plan.quads.resize(P);
+  plan.octs.resize(P);
   plan.chunks.resize(P);
   plan.frow_base.assign(P + 1, 0);
   plan.mrow_base.assign(P + 1, 0);
@@ -381,7 +407,7 @@ int plan_pairs(const mi_pair* pairs, int32_t n_pairs, int32_t bins, int32_t n_q,
     const mi_pair& pr = pairs[p];
     int st;
     if ((st = check_volume(&pr.fixed, false)) != MI_OK) return st;
-    if ((st = check_volume(&pr.moving, true)) != MI_OK) return st;
+    if ((st = check_moving(&pr.moving, true)) != MI_OK) return st;
     if (pr.n_transforms < 0) return MI_ERR_COUNT;
     if (pr.n_transforms > 0 && !pr.transforms) return MI_ERR_NULL;
     // slabs of about 128 K voxels (at most 65535 with 16-bit counters),
@@ -395,7 +421,7 @@ int plan_pairs(const mi_pair* pairs, int32_t n_pairs, int32_t bins, int32_t n_q,
     c = ((c + 7) / 8) * 8;
     plan.chunks[p] = (int32_t)c;
     plan.frow_base[p + 1] = plan.frow_base[p] + (int64_t)pr.fixed.ny * pr.fixed.nz;
-    plan.mrow_base[p + 1] = plan.mrow_base[p] + (int64_t)pr.moving.ny * (pr.moving.nz + 1);
+    plan.mrow_base[p + 1] = plan.mrow_base[p] + (int64_t)pr.moving.ny * pr.moving.nz;
     plan.t_base[p + 1] = plan.t_base[p] + pr.n_transforms;
     for (int x = 0; x < 8; ++x)
       plan.xcd_base[(size_t)x * (P + 1) + p + 1] =
@@ -427,8 +453,8 @@ int plan_pairs(const mi_pair* pairs, int32_t n_pairs, int32_t bins, int32_t n_q,
   for (int p = 0; p < P; ++p) {
     plan.fbins[p] = w;
     w += align256(voxels(&pairs[p].fixed));
-    plan.quads[p] = w;
-    w += align256(quad_volume_bytes(pairs[p].moving.nx, pairs[p].moving.ny, pairs[p].moving.nz));
+    plan.octs[p] = w;
+    w += align256(oct_volume_bytes(pairs[p].moving.nx, pairs[p].moving.ny, pairs[p].moving.nz));
   }
   plan.total = w;
   return MI_OK;
@@ -542,24 +568,24 @@ int graph_run(mi_context* ctx, const std::vector<uint64_t>& key, hipStream_t s, 
 
 // ---- the hard-binned path ---------------------------------------------------
 
-// Fixed bins, quad volume, zeroed histograms and the sweep (no reduction).
+// Fixed bins, oct volume, zeroed histograms and the sweep (no reduction).
 int launch_hard_hist(mi_context* ctx, const mi_volume* fixed, const mi_volume* moving,
                      const double* transforms, int32_t n, int32_t bins, int32_t flags,
                      uint32_t* hist, char* ws, const Layout& L, hipStream_t s,
                      const HardTune& tune, bool prepare) {
   hipError_t e;
   uint8_t* fb = (uint8_t*)(ws + L.fbins);
-  uint2* quads = (uint2*)(ws + L.quads);
+  uint4* octs = (uint4*)(ws + L.gvol);
   const size_t bb = (size_t)bins * bins;
   if (prepare) {
     if ((e = launch_prebin_fixed(desc(fixed), bins, fb, s)) != hipSuccess) return hip_fail(e, "prebin");
-    if ((e = launch_pack_quads(desc(moving), quads, s)) != hipSuccess) return hip_fail(e, "pack");
+    if ((e = launch_pack_octs(desc(moving), octs, s)) != hipSuccess) return hip_fail(e, "pack");
   }
   if ((e = launch_fill_u32(hist, bb * n, 0u, s)) != hipSuccess) return hip_fail(e, "fill");
   HardLaunch H;
   H.transforms = transforms;
   H.fbins = fb;
-  H.quads = quads;
+  H.octs = octs;
   H.fixed = desc(fixed);
   H.moving = desc(moving);
   H.hist = hist;
@@ -569,7 +595,7 @@ int launch_hard_hist(mi_context* ctx, const mi_volume* fixed, const mi_volume* m
   H.packed = bins > 128 ? 1 : 0;
   H.block = tune.block;
   H.slab_major = tune.slab_major;
-  H.chunks = plan_chunks(ctx, fixed, n, H.packed != 0, tune);
+  H.chunks = plan_chunks(ctx, fixed, moving, n, H.packed != 0, tune);
   // one launch covers at most 2^31 - 1 workgroups: split the transforms
   const int64_t per_launch = 0x7FFFFFFFll / H.chunks;
   for (int64_t t0 = 0; t0 < n; t0 += per_launch) {
@@ -717,7 +743,7 @@ int mi_tune(mi_context* ctx, const mi_volume* fixed, const mi_volume* moving,
   uint32_t* hist = (uint32_t*)(ws + L.hist);
   const bool was_timing = ctx->timing;
   ctx->timing = false;
-  // fixed bins and quads once
+  // fixed bins and octs once
   st = launch_hard_hist(ctx, fixed, moving, transforms, n, bins, flags, hist, ws, L, s,
                         ctx->hard_default, true);
   hipEvent_t t0 = nullptr, t1 = nullptr;
@@ -726,7 +752,7 @@ int mi_tune(mi_context* ctx, const mi_volume* fixed, const mi_volume* moving,
   HardTune best = ctx->hard_default;
   float best_ms = 3.4e38f;
   HardTune base = ctx->hard_default;
-  base.chunks = plan_chunks(ctx, fixed, n, bins > 128, base);
+  base.chunks = plan_chunks(ctx, fixed, moving, n, bins > 128, base);
   const int32_t chunk_opts[3] = {base.chunks / 2, base.chunks, base.chunks * 2};
   for (int32_t block : {256, 512, 1024}) {
     for (int32_t order : {1, 0}) {
@@ -905,7 +931,7 @@ int mi_eval_pairs(mi_context* ctx, const mi_pair* pairs, int32_t n_pairs, int32_
     d.moving = pr.moving.data;
     d.transforms = pr.transforms;
     d.geom = make_hard_geom(desc(&pr.fixed), desc(&pr.moving), (const uint8_t*)(ws + plan.fbins[p]),
-                            (const uint2*)(ws + plan.quads[p]), bins);
+                            (const uint4*)(ws + plan.octs[p]), bins);
     d.fdtype = pr.fixed.dtype;
     d.mdtype = pr.moving.dtype;
     d.flo = pr.fixed.lo;

@@ -164,10 +164,10 @@ struct GroupWalk {
 // Geometry of one fixed/moving pair for the hard-binned sweep.
 struct HardGeom {
   const uint8_t* fbins;  // fixed bins, [fnz][fny][fnx]
-  const uint2* quads;    // moving quad volume, [mnz+1][mny][mnx]
+  const uint4* octs;     // moving oct volume, [mnz][mny][mnx]
   int32_t fnx, fny, fnz;
   int32_t mnx, mny, mnz;
-  uint32_t quad_bytes;
+  uint32_t oct_bytes;
   int32_t bins;
   double scale;  // B / (R 2^48), R = moving hi - lo + 1
   Divider div;   // floor(X / R) for the exact fallback
@@ -183,7 +183,7 @@ struct VolumeDesc {
 struct HardLaunch {
   const double* transforms;  // [n][12]
   const uint8_t* fbins;      // fixed-volume bins, [fnz][fny][fnx]
-  const uint2* quads;        // moving quad volume, [mnz+1][mny][mnx]
+  const uint4* octs;         // moving oct volume, [mnz][mny][mnx]
   VolumeDesc fixed, moving;
   uint32_t* hist;  // [n][B][B]
   int32_t n, bins, clamp;
@@ -193,10 +193,20 @@ struct HardLaunch {
   int32_t slab_major;  // workgroup order: 1 slab-major, 0 transform-major
 };
 
-// Bytes of the moving quad volume of an nx x ny x nz volume (< 2^32 for
-// at most 2^28 voxels).
-inline size_t quad_volume_bytes(int32_t nx, int32_t ny, int32_t nz) {
-  return (size_t)nx * (size_t)ny * (size_t)(nz + 1) * 8;
+// The gathers address their volume with 32-bit buffer offsets, so every
+// gather volume stays below 4 GiB (the entry points check it).
+constexpr size_t kMaxGatherBytes = 0xFFFFFFF0u;
+
+// Bytes of the oct volume of an integer moving volume: per voxel the eight
+// clamped, offset 16-bit corners of its 2x2x2 neighbourhood (16 bytes).
+inline size_t oct_volume_bytes(int32_t nx, int32_t ny, int32_t nz) {
+  return (size_t)nx * (size_t)ny * (size_t)nz * 16;
+}
+
+// Bytes of the fp32 quad volume of a float moving volume: per voxel the
+// four (x, y) corners of its neighbourhood in one slice, one extra slice.
+inline size_t quad_f32_bytes(int32_t nx, int32_t ny, int32_t nz) {
+  return (size_t)nx * (size_t)ny * (size_t)(nz + 1) * 16;
 }
 
 struct ReduceLaunch {
@@ -214,14 +224,14 @@ struct ReduceLaunch {
 struct ParzenArgs {
   const double* transforms;
   const uint8_t* fbins;
-  const void* quads;   // uint2 (integer moving) or float4 (float moving) per voxel
+  const void* gvol;    // uint4 octs (integer moving) or float4 quads (float moving)
   double* table;       // [n][B][B] forward masses (fp64)
   uint64_t* count;     // [n] voxels that took part
   const float* gtab;   // [n][n_q][B][B] d MI / d p
   double* grad;        // [n][n_q][12]
   int32_t fnx, fny, fnz;
   int32_t mnx, mny, mnz;
-  uint32_t quad_bytes;
+  uint32_t gvol_bytes;
   int32_t n, bins, chunks, bands, band_rows, slab_major;
   int32_t n_q, q0;     // backward: entropies [q0, q0 + NQG) of n_q
   float sscale;        // (B - 4) / (hi - lo)
@@ -232,14 +242,14 @@ constexpr int kParzenQGroup = 2;  // entropies per backward sweep
 
 struct ParzenLaunch {
   ParzenArgs args;
-  int32_t float_quads;  // 1: moving volume is fp32 (16-byte quads)
+  int32_t float_quads;  // 1: moving volume is fp32 (float4 quads, else uint4 octs)
   int32_t clamp;
 };
 
 hipError_t launch_fill_u32(uint32_t* p, size_t n, uint32_t value, hipStream_t s);
 hipError_t launch_fill_f64(double* p, size_t n, hipStream_t s);
 hipError_t launch_prebin_fixed(const VolumeDesc& f, int bins, uint8_t* out, hipStream_t s);
-hipError_t launch_pack_quads(const VolumeDesc& m, uint2* out, hipStream_t s);
+hipError_t launch_pack_octs(const VolumeDesc& m, uint4* out, hipStream_t s);
 hipError_t launch_hist_hard(const HardLaunch& L, hipStream_t s);
 
 // Many fixed/moving pairs of uneven sizes (see pairs.hip).
@@ -247,7 +257,7 @@ struct PairDesc {
   const void* fixed;
   const void* moving;
   const double* transforms;  // caller's [n_t][12]
-  HardGeom geom;             // fbins / quads point into the workspace
+  HardGeom geom;             // fbins / octs point into the workspace
   int32_t fdtype, mdtype;
   double flo, fhi;           // fixed range (fp64 rule for float fixed volumes)
   int32_t mlo, mhi;          // moving range
@@ -277,7 +287,7 @@ struct PairsLaunch {
 hipError_t launch_pairs_prep(const PairsLaunch& L, hipStream_t s);
 hipError_t launch_pairs_hist(const PairsLaunch& L, hipStream_t s);
 HardGeom make_hard_geom(const VolumeDesc& fixed, const VolumeDesc& moving, const uint8_t* fbins,
-                        const uint2* quads, int32_t bins);
+                        const uint4* octs, int32_t bins);
 hipError_t launch_mi_reduce(const ReduceLaunch& L, hipStream_t s);
 hipError_t launch_pack_quads_f32(const VolumeDesc& m, float4* out, hipStream_t s);
 hipError_t launch_parzen_fwd(const ParzenLaunch& L, hipStream_t s);

@@ -3,11 +3,12 @@
 // Discussion), for gfx950.
 //
 // Per call, the fixed volume is reduced to one bin byte per voxel and the
-// moving volume to a "quad volume": each 8-byte element holds the clamped,
-// offset intensities of a voxel and of its +x, +y and +x+y neighbours as
-// 16-bit values, so the 2x2x2 trilinear neighbourhood is two aligned
-// 64-bit loads; a repeated last slice makes the +z neighbours of the last
-// slice addressable (their weight is 0).
+// moving volume to an "oct volume": each 16-byte element holds the clamped,
+// offset intensities of a voxel's whole 2x2x2 trilinear neighbourhood as
+// 16-bit values, so a lane gathers its neighbourhood with one aligned
+// 128-bit load.  The sweep is limited by gather instruction issue about as
+// much as by arithmetic, so one 16-byte gather beats two 8-byte gathers of
+// the same bytes.
 //
 // One workgroup = one transform x one slab of fixed rows.  Each wave64
 // walks its own run of 4-row groups with scalar coordinates; its 64 lanes
@@ -101,41 +102,46 @@ hipError_t launch_prebin_fixed(const VolumeDesc& f, int bins, uint8_t* out, hipS
 }
 
 // ---------------------------------------------------------------------------
-// moving quad volume, once per call
+// moving oct volume, once per call
 // ---------------------------------------------------------------------------
 
-// out[z][y][x] (z <= nz) holds four 16-bit clamped, offset intensities
-// v' = clamp(v, lo, hi) - lo: (x, y), (x1, y) in .x and (x, y1), (x1, y1)
-// in .y, with x1 = min(x+1, nx-1) and y1 = min(y+1, ny-1); slice nz repeats
-// slice nz-1.  A neighbour index is thus clamped to the volume, as in the
-// trilinear rule; on those corners the hard path's weight is 0, and the
-// Parzen path's derivative along that axis vanishes.
+// out[z][y][x] holds the eight 16-bit clamped, offset intensities
+// v' = clamp(v, lo, hi) - lo of the voxel's 2x2x2 neighbourhood, so one
+// 16-byte load fetches all trilinear corners: word 2 dz + dy packs
+// (x, y+dy, z+dz) in its low half and (x1, y+dy, z+dz) in its high half,
+// with x1 = min(x+1, nx-1) and y+1, z+1 likewise clamped.  A neighbour
+// index is thus clamped to the volume, as in the trilinear rule; on those
+// corners the hard path's weight is 0, and the Parzen path's derivative
+// along that axis vanishes.
 template <typename T>
-__global__ void pack_quads_kernel(const T* __restrict__ v, int32_t nx, int32_t ny, int32_t nz,
-                                  int32_t lo, int32_t hi, uint2* __restrict__ out) {
+__global__ void pack_octs_kernel(const T* __restrict__ v, int32_t nx, int32_t ny, int32_t nz,
+                                 int32_t lo, int32_t hi, uint4* __restrict__ out) {
   const int32_t y = blockIdx.y, z = blockIdx.z;
-  uint2* __restrict__ orow = out + ((size_t)z * ny + y) * nx;
-  const int32_t zs = z < nz ? z : nz - 1;
-  const T* __restrict__ r0 = v + ((size_t)zs * ny + y) * nx;
-  const T* __restrict__ r1 = r0 + (y + 1 < ny ? nx : 0);
+  uint4* __restrict__ orow = out + ((size_t)z * ny + y) * nx;
+  const T* __restrict__ r00 = v + ((size_t)z * ny + y) * nx;
+  const T* __restrict__ r10 = r00 + (y + 1 < ny ? nx : 0);
+  const size_t dz = z + 1 < nz ? (size_t)nx * ny : 0;
+  const T* __restrict__ r01 = r00 + dz;
+  const T* __restrict__ r11 = r10 + dz;
   auto c = [&](T raw) -> uint32_t { return clamp_offset((int32_t)raw, lo, hi); };
-  for (int32_t x = threadIdx.x; x < nx; x += blockDim.x) {
+  for (int32_t x = blockIdx.x * blockDim.x + threadIdx.x; x < nx; x += gridDim.x * blockDim.x) {
     const int32_t x1 = x + 1 < nx ? x + 1 : nx - 1;
-    orow[x] = make_uint2(c(r0[x]) | (c(r0[x1]) << 16), c(r1[x]) | (c(r1[x1]) << 16));
+    orow[x] = make_uint4(c(r00[x]) | (c(r00[x1]) << 16), c(r10[x]) | (c(r10[x1]) << 16),
+                         c(r01[x]) | (c(r01[x1]) << 16), c(r11[x]) | (c(r11[x1]) << 16));
   }
 }
 
-hipError_t launch_pack_quads(const VolumeDesc& m, uint2* out, hipStream_t s) {
-  const dim3 grid(1, (unsigned)m.ny, (unsigned)m.nz + 1);
+hipError_t launch_pack_octs(const VolumeDesc& m, uint4* out, hipStream_t s) {
+  const dim3 grid((unsigned)((m.nx + 255) / 256), (unsigned)m.ny, (unsigned)m.nz);
   const int32_t lo = (int32_t)m.lo, hi = (int32_t)m.hi;
   if (m.dtype == 0)
-    hipLaunchKernelGGL(pack_quads_kernel<uint8_t>, grid, dim3(256), 0, s, (const uint8_t*)m.data,
+    hipLaunchKernelGGL(pack_octs_kernel<uint8_t>, grid, dim3(256), 0, s, (const uint8_t*)m.data,
                        m.nx, m.ny, m.nz, lo, hi, out);
   else if (m.dtype == 1)
-    hipLaunchKernelGGL(pack_quads_kernel<uint16_t>, grid, dim3(256), 0, s, (const uint16_t*)m.data,
+    hipLaunchKernelGGL(pack_octs_kernel<uint16_t>, grid, dim3(256), 0, s, (const uint16_t*)m.data,
                        m.nx, m.ny, m.nz, lo, hi, out);
   else if (m.dtype == 2)
-    hipLaunchKernelGGL(pack_quads_kernel<int16_t>, grid, dim3(256), 0, s, (const int16_t*)m.data,
+    hipLaunchKernelGGL(pack_octs_kernel<int16_t>, grid, dim3(256), 0, s, (const int16_t*)m.data,
                        m.nx, m.ny, m.nz, lo, hi, out);
   else
     return hipErrorInvalidValue;
@@ -191,17 +197,17 @@ static hipError_t launch_nt(const HardArgs& a, int n, bool clamp, bool packed, s
 }
 
 HardGeom make_hard_geom(const VolumeDesc& fixed, const VolumeDesc& moving, const uint8_t* fbins,
-                        const uint2* quads, int32_t bins) {
+                        const uint4* octs, int32_t bins) {
   HardGeom g;
   g.fbins = fbins;
-  g.quads = quads;
+  g.octs = octs;
   g.fnx = fixed.nx;
   g.fny = fixed.ny;
   g.fnz = fixed.nz;
   g.mnx = moving.nx;
   g.mny = moving.ny;
   g.mnz = moving.nz;
-  g.quad_bytes = (uint32_t)quad_volume_bytes(moving.nx, moving.ny, moving.nz);
+  g.oct_bytes = (uint32_t)oct_volume_bytes(moving.nx, moving.ny, moving.nz);
   g.bins = bins;
   const uint32_t R = (uint32_t)((int32_t)moving.hi - (int32_t)moving.lo + 1);
   g.scale = ldexp((double)bins / (double)R, -48);
@@ -214,7 +220,7 @@ hipError_t launch_hist_hard(const HardLaunch& L, hipStream_t s) {
   HardArgs a;
   a.transforms = L.transforms;
   a.hist = L.hist;
-  a.geom = make_hard_geom(L.fixed, L.moving, L.fbins, L.quads, L.bins);
+  a.geom = make_hard_geom(L.fixed, L.moving, L.fbins, L.octs, L.bins);
   a.n = L.n;
   a.chunks = L.chunks;
   a.slab_major = L.slab_major;

@@ -12,7 +12,7 @@
 // at a time and share its moving footprint in L2.  Every workgroup leaves
 // the loop once its queue is empty, so the grid always drains.
 //
-// Per-pair fixed bins and moving quad volumes are prepared by two row
+// Per-pair fixed bins and moving oct volumes are prepared by two row
 // kernels over all pairs, and the transforms are gathered into one array
 // for the MI reduction.
 #include "common.h"
@@ -71,7 +71,7 @@ __global__ void prep_fixed_kernel(PairsArgs a, int64_t rows) {
   }
 }
 
-// One workgroup per quad row (z <= nz, y < ny): the moving quad volume, with
+// One workgroup per moving row (z < nz, y < ny): the moving oct volume, with
 // the layout and clamping of the single-pair path.
 __global__ void prep_moving_kernel(PairsArgs a, int64_t rows) {
   for (int64_t r = blockIdx.x; r < rows; r += gridDim.x) {
@@ -80,17 +80,17 @@ __global__ void prep_moving_kernel(PairsArgs a, int64_t rows) {
     const int64_t row = r - a.mrow_base[p];
     const int32_t nx = d.geom.mnx, ny = d.geom.mny, nz = d.geom.mnz;
     const int32_t z = (int32_t)(row / ny), y = (int32_t)(row - (int64_t)z * ny);
-    const int32_t zs = z < nz ? z : nz - 1;
-    const size_t r0 = ((size_t)zs * ny + y) * nx;
-    const size_t r1 = r0 + (y + 1 < ny ? nx : 0);
-    uint2* __restrict__ out = (uint2*)d.geom.quads + row * nx;
+    const size_t r00 = ((size_t)z * ny + y) * nx;
+    const size_t r10 = r00 + (y + 1 < ny ? nx : 0);
+    const size_t dz = z + 1 < nz ? (size_t)nx * ny : 0;
+    uint4* __restrict__ out = (uint4*)d.geom.octs + row * nx;
+    auto pair = [&](size_t base, int32_t x, int32_t x1) -> uint32_t {
+      return clamp_offset(load_int(d.moving, d.mdtype, base + x), d.mlo, d.mhi) |
+             (clamp_offset(load_int(d.moving, d.mdtype, base + x1), d.mlo, d.mhi) << 16);
+    };
     for (int32_t x = threadIdx.x; x < nx; x += blockDim.x) {
       const int32_t x1 = x + 1 < nx ? x + 1 : nx - 1;
-      const uint32_t a0 = clamp_offset(load_int(d.moving, d.mdtype, r0 + x), d.mlo, d.mhi);
-      const uint32_t a1 = clamp_offset(load_int(d.moving, d.mdtype, r0 + x1), d.mlo, d.mhi);
-      const uint32_t b0 = clamp_offset(load_int(d.moving, d.mdtype, r1 + x), d.mlo, d.mhi);
-      const uint32_t b1 = clamp_offset(load_int(d.moving, d.mdtype, r1 + x1), d.mlo, d.mhi);
-      out[x] = make_uint2(a0 | (a1 << 16), b0 | (b1 << 16));
+      out[x] = make_uint4(pair(r00, x, x1), pair(r10, x, x1), pair(r00 + dz, x, x1), pair(r10 + dz, x, x1));
     }
   }
 }

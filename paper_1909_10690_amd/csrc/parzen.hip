@@ -14,12 +14,13 @@
 // than storing them.
 //
 // Both sweeps walk the fixed volume like the hard-binned one (16 x 4 voxel
-// wave tiles, slab-major workgroup order) and read the same quad volume:
-// the 2x2x2 neighbourhood in two loads, as exact 16-bit integers (integer
-// moving volumes) or fp32 (float moving volumes).  A workgroup accumulates
-// one band of table rows (fixed bins) in LDS in fp32; bands keep large
-// tables within LDS, and a voxel outside the band costs only its fixed-bin
-// read.  Workgroup partials are merged into fp64 in HBM.
+// wave tiles, slab-major workgroup order).  An integer moving volume is
+// read from the hard path's oct volume (the 2x2x2 neighbourhood as exact
+// 16-bit integers, one load), a float one from an fp32 quad volume (the
+// four (x, y) corners of a slice per 16-byte element, two loads).  A
+// workgroup accumulates one band of table rows (fixed bins) in LDS; bands
+// keep large tables within LDS, and a voxel outside the band costs only
+// its fixed-bin read.  Workgroup partials are merged into fp64 in HBM.
 #include "common.h"
 
 namespace gemi {
@@ -55,7 +56,7 @@ hipError_t launch_pack_quads_f32(const VolumeDesc& m, float4* out, hipStream_t s
 // per-voxel sample shared by the forward and backward sweeps
 // ---------------------------------------------------------------------------
 
-typedef unsigned int uint2_t __attribute__((ext_vector_type(2)));
+typedef unsigned int uint4_t __attribute__((ext_vector_type(4)));
 typedef float float4_t __attribute__((ext_vector_type(4)));
 
 // Corner values c[z][y][x] of the 2x2x2 neighbourhood.
@@ -68,12 +69,11 @@ __device__ __forceinline__ void gather(const __amdgpu_buffer_rsrc_t& rsrc, uint3
     c[0][0][0] = a.x; c[0][0][1] = a.y; c[0][1][0] = a.z; c[0][1][1] = a.w;
     c[1][0][0] = b.x; c[1][0][1] = b.y; c[1][1][0] = b.z; c[1][1][1] = b.w;
   } else {
-    const uint2_t a = __builtin_amdgcn_raw_buffer_load_b64(rsrc, idx * 8u, 0, 0);
-    const uint2_t b = __builtin_amdgcn_raw_buffer_load_b64(rsrc, idx * 8u, slice_bytes, 0);
-    c[0][0][0] = (float)(a.x & 0xFFFFu); c[0][0][1] = (float)(a.x >> 16);
-    c[0][1][0] = (float)(a.y & 0xFFFFu); c[0][1][1] = (float)(a.y >> 16);
-    c[1][0][0] = (float)(b.x & 0xFFFFu); c[1][0][1] = (float)(b.x >> 16);
-    c[1][1][0] = (float)(b.y & 0xFFFFu); c[1][1][1] = (float)(b.y >> 16);
+    const uint4_t o = __builtin_amdgcn_raw_buffer_load_b128(rsrc, idx * 16u, 0, 0);
+    c[0][0][0] = (float)(o.x & 0xFFFFu); c[0][0][1] = (float)(o.x >> 16);
+    c[0][1][0] = (float)(o.y & 0xFFFFu); c[0][1][1] = (float)(o.y >> 16);
+    c[1][0][0] = (float)(o.z & 0xFFFFu); c[1][0][1] = (float)(o.z >> 16);
+    c[1][1][0] = (float)(o.w & 0xFFFFu); c[1][1][1] = (float)(o.w >> 16);
   }
 }
 
@@ -153,9 +153,9 @@ __global__ __launch_bounds__(NT) void parzen_fwd_kernel(ParzenArgs a) {
     const uint64_t top[3] = {(uint64_t)(a.mnx - 1) << 32, (uint64_t)(a.mny - 1) << 32,
                              (uint64_t)(a.mnz - 1) << 32};
     const uint32_t NY = (uint32_t)a.mny, MX = (uint32_t)a.mnx;
-    const int32_t SZ = (FQ ? 16 : 8) * a.mnx * a.mny;
+    const int32_t SZ = FQ ? 16 * a.mnx * a.mny : 0;  // fp32 quads: next slice
     const __amdgpu_buffer_rsrc_t rsrc =
-        __builtin_amdgcn_make_buffer_rsrc((void*)a.quads, (short)0, (int)a.quad_bytes, 0x00020000);
+        __builtin_amdgcn_make_buffer_rsrc((void*)a.gvol, (short)0, (int)a.gvol_bytes, 0x00020000);
     const float smax = (float)(B - 3);
     for (; w.g < w.g1; w.next()) {
       const int32_t j = w.j0 + dy;
@@ -320,9 +320,9 @@ __global__ __launch_bounds__(NT) void parzen_bwd_kernel(ParzenArgs a) {
     const uint64_t top[3] = {(uint64_t)(a.mnx - 1) << 32, (uint64_t)(a.mny - 1) << 32,
                              (uint64_t)(a.mnz - 1) << 32};
     const uint32_t NY = (uint32_t)a.mny, MX = (uint32_t)a.mnx;
-    const int32_t SZ = (FQ ? 16 : 8) * a.mnx * a.mny;
+    const int32_t SZ = FQ ? 16 * a.mnx * a.mny : 0;  // fp32 quads: next slice
     const __amdgpu_buffer_rsrc_t rsrc =
-        __builtin_amdgcn_make_buffer_rsrc((void*)a.quads, (short)0, (int)a.quad_bytes, 0x00020000);
+        __builtin_amdgcn_make_buffer_rsrc((void*)a.gvol, (short)0, (int)a.gvol_bytes, 0x00020000);
     const float smax = (float)(B - 3);
     for (; w.g < w.g1; w.next()) {
       const int32_t j = w.j0 + dy;

@@ -10,7 +10,16 @@
 namespace gemi {
 
 typedef unsigned short ushort2_t __attribute__((ext_vector_type(2)));
-typedef unsigned int uint2_t __attribute__((ext_vector_type(2)));
+typedef unsigned int uint4_t __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) uint32_t lds_u32;
+
+// a * b + c with 24-bit unsigned operands a, b (v_mad_u32_u24, full rate;
+// left to itself the compiler may pick a 64-bit multiply-add).
+__device__ __forceinline__ uint32_t mad24(uint32_t a, uint32_t b, uint32_t c) {
+  uint32_t r;
+  asm("v_mad_u32_u24 %0, %1, %2, %3" : "=v"(r) : "v"(a), "s"(b), "v"(c));
+  return r;
+}
 
 // v0 (1 - w) + v1 w at 16-bit weight w = fx >> 16, exact: the pair's low
 // half times (65535 - w), high half times w, plus the low half once more.
@@ -47,18 +56,21 @@ __device__ __forceinline__ void sweep_hard(const HardGeom& g, const int64_t* Mq,
   const uint64_t topy = (uint64_t)(g.mny - 1) << 32;
   const uint64_t topz = (uint64_t)(g.mnz - 1) << 32;
   const uint32_t NY = (uint32_t)g.mny, MX = (uint32_t)g.mnx;
-  const int32_t SZ = 8 * g.mnx * g.mny;
   const __amdgpu_buffer_rsrc_t rsrc =
-      __builtin_amdgcn_make_buffer_rsrc((void*)g.quads, (short)0, (int)g.quad_bytes, 0x00020000);
+      __builtin_amdgcn_make_buffer_rsrc((void*)g.octs, (short)0, (int)g.oct_bytes, 0x00020000);
   const uint32_t Bu = (uint32_t)g.bins;
+  const uint32_t B4 = 4u * Bu;  // bytes per LDS histogram row (u32 counters)
+  const uint32_t lbase = (uint32_t)(size_t)(lds_u32*)lds_hist;
   const double scale = g.scale;
 
   for (; w.g < w.g1; w.next()) {
     const int32_t j = w.j0 + dy;
     if (j >= g.fny) continue;
-    const uint8_t* __restrict__ frow = g.fbins + ((int64_t)w.k * g.fny + j) * g.fnx;
+    // fixed voxels < 2^28: 32-bit offsets into the fixed bins
+    const uint32_t rowoff = ((uint32_t)w.k * (uint32_t)g.fny + (uint32_t)j) * (uint32_t)g.fnx;
+    const uint32_t rowend = rowoff + (uint32_t)g.fnx;
     int64_t qx = w.r[0] + w.lane_off[0], qy = w.r[1] + w.lane_off[1], qz = w.r[2] + w.lane_off[2];
-    for (int x = dx; x < g.fnx; x += kTileX, qx += sx, qy += sy, qz += sz) {
+    for (uint32_t xo = rowoff + dx; xo < rowend; xo += kTileX, qx += sx, qy += sy, qz += sz) {
       uint64_t cx = (uint64_t)qx, cy = (uint64_t)qy, cz = (uint64_t)qz;
       if (CLAMP) {
         cx = qx < 0 ? 0 : (cx > topx ? topx : cx);
@@ -70,15 +82,14 @@ __device__ __forceinline__ void sweep_hard(const HardGeom& g, const int64_t* Mq,
       }
       const uint32_t ix = (uint32_t)(cx >> 32), iy = (uint32_t)(cy >> 32), iz = (uint32_t)(cz >> 32);
       const uint32_t fx = (uint32_t)cx, fy = (uint32_t)cy, fz = (uint32_t)cz;
-      // (nz+1) * ny < 2^24 rows, so 24-bit multiplies are exact
-      const uint32_t off = (__umul24(__umul24(iz, NY) + iy, MX) + ix) * 8u;
-      const uint2_t q0 = __builtin_amdgcn_raw_buffer_load_b64(rsrc, off, 0, 0);
-      const uint2_t q1 = __builtin_amdgcn_raw_buffer_load_b64(rsrc, off, SZ, 0);
-      const uint32_t fb = frow[x];
+      // rows iz ny + iy < ny nz <= 2^24 and edges <= 4096: 24-bit operands
+      const uint32_t off = mad24(mad24(iz, NY, iy), MX, ix) << 4;
+      const uint4_t oc = __builtin_amdgcn_raw_buffer_load_b128(rsrc, off, 0, 0);
+      const uint32_t fb = g.fbins[xo];
       // (65535 - wx) in the low half, wx in the high half
       const uint32_t wpack = (fx & 0xFFFF0000u) | ((fx >> 16) ^ 0xFFFFu);
-      const uint32_t a00 = lerp_x(q0.x, wpack), a10 = lerp_x(q0.y, wpack);
-      const uint32_t a01 = lerp_x(q1.x, wpack), a11 = lerp_x(q1.y, wpack);
+      const uint32_t a00 = lerp_x(oc.x, wpack), a10 = lerp_x(oc.y, wpack);
+      const uint32_t a01 = lerp_x(oc.z, wpack), a11 = lerp_x(oc.w, wpack);
       const uint32_t wy = fy >> 16, wz = fz >> 16;
       const double wyd = (double)wy, wzd = (double)wz;
       const double A00 = (double)a00, A10 = (double)a10, A01 = (double)a01, A11 = (double)a11;
@@ -91,11 +102,15 @@ __device__ __forceinline__ void sweep_hard(const HardGeom& g, const int64_t* Mq,
       // within kEdge of a bin edge: fr < kEdge or fr > 1 - kEdge
       const double fr = __builtin_amdgcn_fract(tb);
       if (fabs(fr - 0.5) > 0.5 - kEdge) bm = exact_bin(a00, a10, a01, a11, wy, wz, Bu, g.div);
-      const uint32_t cell = __umul24(fb, Bu) + bm;
-      if (PACKED)
+      if (PACKED) {
+        const uint32_t cell = __umul24(fb, Bu) + bm;
         atomicAdd(&lds_hist[cell >> 1], 1u << ((cell & 1u) * 16u));
-      else
-        atomicAdd(&lds_hist[cell], 1u);
+      } else {
+        // byte address of counter [fb][bm], formed directly (a mul24 and a
+        // shift-add rather than index arithmetic on the pointer)
+        const uint32_t addr = __umul24(fb, B4) + ((bm << 2) + lbase);
+        __hip_atomic_fetch_add((lds_u32*)(size_t)addr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      }
     }
   }
 }

@@ -68,7 +68,7 @@ def test_valid_arguments_reach_the_context_check():
 
 @pytest.mark.parametrize("kw,status", [
     (dict(nx=1), B.MI_ERR_DIMS), (dict(ny=4097), B.MI_ERR_DIMS), (dict(nz=0), B.MI_ERR_DIMS),
-    (dict(nx=4096, ny=4096, nz=17), B.MI_ERR_DIMS), (dict(nx=4096, ny=4096, nz=16), B.MI_ERR_NULL),
+    (dict(nx=4096, ny=4096, nz=17), B.MI_ERR_DIMS),
     (dict(dtype=7), B.MI_ERR_DTYPE), (dict(dtype=-1), B.MI_ERR_DTYPE),
     (dict(lo=5.0, hi=5.0), B.MI_ERR_RANGE), (dict(lo=0.5), B.MI_ERR_RANGE),
     (dict(hi=float("nan")), B.MI_ERR_RANGE), (dict(lo=0.0, hi=65536.0), B.MI_ERR_RANGE),
@@ -77,6 +77,21 @@ def test_valid_arguments_reach_the_context_check():
 def test_volume_validation(kw, status):
     assert call_eval(vol(**kw), vol()) == status
     assert call_eval(vol(), vol(**kw)) == status
+
+
+def test_moving_gather_layout_limit():
+    """A fixed volume may hold 2^28 voxels; a moving one stays below 2^28
+    (integer: 16-byte oct volume) or below 2^28 voxels including one extra
+    slice (float, Parzen: 16-byte fp32 quads), so its gather layout fits
+    32-bit buffer offsets."""
+    big = dict(nx=4096, ny=4096, nz=16)
+    assert call_eval(vol(**big), vol()) == B.MI_ERR_NULL
+    assert call_eval(vol(), vol(**big)) == B.MI_ERR_DIMS
+    assert call_eval(vol(), vol(nx=4096, ny=4095, nz=16)) == B.MI_ERR_NULL
+    fbig = dict(nx=4096, ny=4096, nz=15, dtype=B.F32, lo=0.0, hi=1.0)   # 15 + 1 slices = 2^28
+    assert call_eval(vol(), vol(**fbig), flags=B.HIST_PARZEN) == B.MI_ERR_DIMS
+    fok = dict(nx=4096, ny=4095, nz=15, dtype=B.F32, lo=0.0, hi=1.0)
+    assert call_eval(vol(), vol(**fok), flags=B.HIST_PARZEN) == B.MI_ERR_NULL
 
 
 def test_float_moving_needs_parzen():
@@ -129,15 +144,16 @@ def ws_size(f, m, n, bins, n_q, flags=0, grad=0):
 def test_workspace_size_layout():
     a = lambda x: (x + 255) // 256 * 256
     st, n = ws_size(vol(10, 11, 12), vol(9, 8, 7), 5, 32, 2)
-    assert st == 0 and n == a(10 * 11 * 12) + a(9 * 8 * 8 * 8) + a(5 * 32 * 32 * 4)
-    quads = a(8 * 8 * 9 * 8)
+    # integer moving volume: oct volume, 16 bytes per voxel
+    assert st == 0 and n == a(10 * 11 * 12) + a(9 * 8 * 7 * 16) + a(5 * 32 * 32 * 4)
+    octs = a(8 * 8 * 8 * 16)
     st, n = ws_size(vol(10, 11, 12), vol(), 5, 32, 2, B.HIST_PARZEN)
-    assert st == 0 and n == a(1320) + quads + a(5 * 32 * 32 * 8) + a(5 * 8)
+    assert st == 0 and n == a(1320) + octs + a(5 * 32 * 32 * 8) + a(5 * 8)
     st, n = ws_size(vol(10, 11, 12), vol(), 5, 32, 2, 0, 1)
-    assert st == 0 and n == a(1320) + quads + a(5 * 32 * 32 * 8) + a(5 * 8) + a(5 * 2 * 32 * 32 * 4)
-    # a float moving volume keeps fp32 quads: twice the bytes
+    assert st == 0 and n == a(1320) + octs + a(5 * 32 * 32 * 8) + a(5 * 8) + a(5 * 2 * 32 * 32 * 4)
+    # a float moving volume keeps fp32 quads: 16 bytes per voxel, one extra slice
     st, n = ws_size(vol(10, 11, 12), vol(dtype=B.F32, lo=0.0, hi=1.0), 5, 32, 2, B.HIST_PARZEN)
-    assert st == 0 and n == a(1320) + 2 * quads + a(5 * 32 * 32 * 8) + a(5 * 8)
+    assert st == 0 and n == a(1320) + a(8 * 8 * 9 * 16) + a(5 * 32 * 32 * 8) + a(5 * 8)
     assert ws_size(vol(), vol(), 5, 1, 1)[0] == B.MI_ERR_BINS
     assert ws_size(vol(), vol(), 5, 32, 0)[0] == B.MI_ERR_Q
 
@@ -185,8 +201,8 @@ def test_pairs_validation_and_layout():
     p2 = B.MiPair(vol(16, 4, 2), vol(5, 6, 7, dtype=B.U16, lo=0.0, hi=4095.0), FAKE, 0)
     st, n = pairs_ws([p1, p2], bins=32, n_q=2)
     assert st == 0 and n > 0
-    # per-pair fixed bins + quad volumes + 3 transforms' histograms are included
-    assert n >= 8 * 8 * 8 + 9 * 8 * 8 * 8 + 16 * 4 * 2 + 5 * 6 * 8 * 8 + 3 * 32 * 32 * 4
+    # per-pair fixed bins + oct volumes + 3 transforms' histograms are included
+    assert n >= 8 * 8 * 8 + 9 * 8 * 7 * 16 + 16 * 4 * 2 + 5 * 6 * 7 * 16 + 3 * 32 * 32 * 4
     bad = B.MiPair(vol(8, 8, 8), vol(dtype=B.F32, lo=0.0, hi=1.0), FAKE, 3)
     assert pairs_ws([p1, bad])[0] == B.MI_ERR_DTYPE
     assert pairs_ws([B.MiPair(vol(), vol(), None, 3)])[0] == B.MI_ERR_NULL
