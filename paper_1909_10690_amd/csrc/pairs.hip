@@ -50,16 +50,36 @@ __global__ void gather_transforms_kernel(PairsArgs a, int64_t total) {
   }
 }
 
-// One workgroup per fixed row: fixed bins.
+// Calls f(p, row, lane) for the rows of the concatenated row space
+// [base[0], base[P]) that fall to this workgroup: a contiguous range per
+// workgroup, one wave per row.  The pair is found once per wave and then
+// advanced as the rows ascend (a search per row would serialise dependent
+// loads on every row of small volumes).
+template <typename F>
+__device__ __forceinline__ void for_each_row(const int64_t* __restrict__ base, int P, int64_t rows,
+                                             F&& f) {
+  const int64_t per = (rows + gridDim.x - 1) / gridDim.x;
+  const int64_t r0 = (int64_t)blockIdx.x * per;
+  const int64_t r1 = r0 + per < rows ? r0 + per : rows;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int nw = blockDim.x >> 6;
+  const int lane = threadIdx.x & 63;
+  if (r0 + wave >= r1) return;
+  int p = find_pair(base, P, r0 + wave);
+  for (int64_t r = r0 + wave; r < r1; r += nw) {
+    while (r >= base[p + 1]) ++p;
+    f(p, r - base[p], lane);
+  }
+}
+
+// Fixed bins of every pair, one wave per fixed row.
 __global__ void prep_fixed_kernel(PairsArgs a, int64_t rows) {
-  for (int64_t r = blockIdx.x; r < rows; r += gridDim.x) {
-    const int p = find_pair(a.frow_base, a.n_pairs, r);
+  for_each_row(a.frow_base, a.n_pairs, rows, [&](int p, int64_t row, int lane) {
     const PairDesc& d = a.pairs[p];
-    const int64_t row = r - a.frow_base[p];
     const int32_t nx = d.geom.fnx;
     uint8_t* __restrict__ out = (uint8_t*)d.geom.fbins + row * nx;
     const size_t base = (size_t)row * nx;
-    for (int32_t x = threadIdx.x; x < nx; x += blockDim.x) {
+    for (int32_t x = lane; x < nx; x += 64) {
       uint32_t b;
       if (d.fdtype == 3)
         b = fixed_bin_real((double)((const float*)d.fixed)[base + x], d.flo, d.fhi, d.geom.bins);
@@ -68,16 +88,14 @@ __global__ void prep_fixed_kernel(PairsArgs a, int64_t rows) {
                           (uint32_t)d.geom.bins, d.fdiv);
       out[x] = (uint8_t)b;
     }
-  }
+  });
 }
 
-// One workgroup per moving row (z < nz, y < ny): the moving oct volume, with
-// the layout and clamping of the single-pair path.
+// Moving oct volumes of every pair, one wave per moving row (z < nz, y < ny),
+// with the layout and clamping of the single-pair path.
 __global__ void prep_moving_kernel(PairsArgs a, int64_t rows) {
-  for (int64_t r = blockIdx.x; r < rows; r += gridDim.x) {
-    const int p = find_pair(a.mrow_base, a.n_pairs, r);
+  for_each_row(a.mrow_base, a.n_pairs, rows, [&](int p, int64_t row, int lane) {
     const PairDesc& d = a.pairs[p];
-    const int64_t row = r - a.mrow_base[p];
     const int32_t nx = d.geom.mnx, ny = d.geom.mny, nz = d.geom.mnz;
     const int32_t z = (int32_t)(row / ny), y = (int32_t)(row - (int64_t)z * ny);
     const size_t r00 = ((size_t)z * ny + y) * nx;
@@ -88,11 +106,11 @@ __global__ void prep_moving_kernel(PairsArgs a, int64_t rows) {
       return clamp_offset(load_int(d.moving, d.mdtype, base + x), d.mlo, d.mhi) |
              (clamp_offset(load_int(d.moving, d.mdtype, base + x1), d.mlo, d.mhi) << 16);
     };
-    for (int32_t x = threadIdx.x; x < nx; x += blockDim.x) {
+    for (int32_t x = lane; x < nx; x += 64) {
       const int32_t x1 = x + 1 < nx ? x + 1 : nx - 1;
       out[x] = make_uint4(pair(r00, x, x1), pair(r10, x, x1), pair(r00 + dz, x, x1), pair(r10 + dz, x, x1));
     }
-  }
+  });
 }
 
 template <bool CLAMP, bool PACKED, int NT>
@@ -125,8 +143,11 @@ __global__ __launch_bounds__(NT) void hist_pairs_kernel(PairsArgs a) {
   }
 }
 
+// Workgroups (4 waves each) for a row kernel: a few per CU, fewer for small
+// row counts.
 static unsigned row_grid(int64_t rows) {
-  return (unsigned)(rows < 65536 ? (rows > 0 ? rows : 1) : 65536);
+  const int64_t g = (rows + 3) / 4;
+  return (unsigned)(g < 4096 ? (g > 0 ? g : 1) : 4096);
 }
 
 hipError_t launch_pairs_prep(const PairsLaunch& L, hipStream_t s) {
