@@ -21,7 +21,7 @@ import numpy as np
 
 from . import transforms as T
 
-BG, CSF, GREY, WHITE = 0, 1, 2, 3
+BG, CSF, GREY, WHITE, CALC = 0, 1, 2, 3, 4
 
 
 def _ellipsoid(p, c, a):
@@ -29,11 +29,21 @@ def _ellipsoid(p, c, a):
             ((p[2] - c[2]) / a[2]) ** 2) <= 1.0
 
 
+# Off-axis calcification-like spheres (label CALC; centre and radius in
+# units of the head's half-extent) for workloads registered with a full
+# affine: nested, axis-aligned ellipsoids alone are mapped onto their
+# rotated copies by a symmetric linear map, so a rotation could be traded
+# for a shear.
+FEATURES = ((-0.35, 0.30, -0.25, 0.09), (0.40, -0.20, 0.10, 0.08), (-0.20, -0.40, 0.30, 0.10),
+            (0.15, 0.45, -0.35, 0.07), (-0.45, -0.05, 0.05, 0.08), (0.30, 0.10, 0.45, 0.09))
+
+
 def head_labels(points_xyz, shape_xyz, jitter: float = 1.0, lesion: bool = True,
-                scale_xyz=(1.0, 1.0, 1.0)) -> np.ndarray:
+                scale_xyz=(1.0, 1.0, 1.0), features: bool = False) -> np.ndarray:
     """Tissue labels at points given in index units of a volume of
     ``shape_xyz``; ``points_xyz`` is a sequence of three broadcastable
-    coordinate arrays (x, y, z); ``scale_xyz`` stretches the anatomy per axis."""
+    coordinate arrays (x, y, z); ``scale_xyz`` stretches the anatomy per axis;
+    ``features`` adds the FEATURES spheres."""
     n = np.asarray(shape_xyz, dtype=np.float64)
     c = (n - 1.0) / 2.0
     h = n / 2.0 * np.asarray(scale_xyz, dtype=np.float64) * jitter
@@ -48,6 +58,9 @@ def head_labels(points_xyz, shape_xyz, jitter: float = 1.0, lesion: bool = True,
     if lesion:
         lc = c + h * np.array([0.30, 0.25, 0.20])
         lab[_ellipsoid(points_xyz, lc, h * 0.08)] = CSF
+    if features:
+        for fx, fy, fz, r in FEATURES:
+            lab[_ellipsoid(points_xyz, c + h * np.array([fx, fy, fz]), h * r)] = CALC
     return lab
 
 
@@ -65,7 +78,7 @@ def _slab_points(shape_xyz, z0: int, z1: int, M=None):
 
 
 def render_labels(shape_xyz, inv_map=None, jitter=1.0, lesion=True, scale_xyz=(1.0, 1.0, 1.0),
-                  anatomy_shape_xyz=None, chunk=64) -> np.ndarray:
+                  anatomy_shape_xyz=None, chunk=64, features=False) -> np.ndarray:
     """Label volume [nz][ny][nx].  ``inv_map`` (3x4) takes this volume's voxel
     index to the anatomy's index frame (``anatomy_shape_xyz``, default the
     same shape); identity when None."""
@@ -75,7 +88,8 @@ def render_labels(shape_xyz, inv_map=None, jitter=1.0, lesion=True, scale_xyz=(1
     for z0 in range(0, nz, chunk):
         z1 = min(nz, z0 + chunk)
         p = _slab_points(shape_xyz, z0, z1, inv_map)
-        out[z0:z1] = np.broadcast_to(head_labels(p, ana, jitter, lesion, scale_xyz), (z1 - z0, ny, nx))
+        out[z0:z1] = np.broadcast_to(head_labels(p, ana, jitter, lesion, scale_xyz, features),
+                                     (z1 - z0, ny, nx))
     return out
 
 
@@ -211,30 +225,34 @@ def uneven_pairs(n_pairs: int = 256, seed: int = 3, per_pair: int = 16, edges=ED
 
 
 def ct_mr_pair(fixed_shape=(512, 512, 300), moving_shape=(256, 256, 256), seed: int = 4) -> dict:
-    """CT-like i16 fixed (air -1000, brain 40+-20 HU, skull 700..1500 HU,
-    1 mm) against an MR-like u16 moving volume of the same anatomy at 2 mm
-    spacing; 256 bins; Tsallis q = 1.3 Parzen."""
+    """CT-like i16 fixed (air -1000, brain parenchyma 40 HU and CSF spaces
+    10 HU, both +N(0, 20), skull 700..1500 HU, 1 mm) against an MR-like u16
+    moving volume of the same anatomy at 2 mm spacing; 256 bins; Tsallis
+    q = 1.3 Parzen.  The CSF spaces (ventricles, an off-axis lesion) and the
+    FEATURES spheres (CT 400 HU, MR 200) give the CT internal structure that
+    pins down all 12 affine parameters."""
     rng = np.random.default_rng(seed)
     fs, ms = np.array([1.0, 1.0, 1.0]), np.array([2.0, 2.0, 2.0])
     fcen = T.fixed_centre(fixed_shape, fs)
     mcen = (np.asarray(moving_shape) - 1) / 2.0 * ms
     mo = fcen - mcen  # moving origin: same physical centre
-    lab_f = render_labels(fixed_shape, lesion=False, scale_xyz=(0.45, 0.45, 0.8))
+    lab_f = render_labels(fixed_shape, lesion=True, scale_xyz=(0.45, 0.45, 0.8), features=True)
     skull_f = render_labels(fixed_shape, lesion=False, scale_xyz=(0.50, 0.50, 0.86))
     fixed = np.full(lab_f.shape, -1000.0)
     fixed[skull_f > 0] = rng.uniform(700, 1500, int((skull_f > 0).sum()))
     brain = lab_f > 0
-    fixed[brain] = 40.0 + 20.0 * rng.standard_normal(int(brain.sum()))
+    ct_level = np.array([-1000.0, 10.0, 40.0, 40.0, 400.0])  # by label
+    fixed[brain] = ct_level[lab_f[brain]] + 20.0 * rng.standard_normal(int(brain.sum()))
     fixed = np.clip(np.rint(fixed), -1000, 1500).astype(np.int16)
     # moving voxel index -> fixed voxel index (same physical frame)
     m2f = np.zeros((3, 4))
     m2f[:, :3] = np.diag(ms / fs)
     m2f[:, 3] = mo / fs
-    lab_m = render_labels(moving_shape, inv_map=m2f, lesion=False, scale_xyz=(0.45, 0.45, 0.8),
-                          anatomy_shape_xyz=fixed_shape)
+    lab_m = render_labels(moving_shape, inv_map=m2f, lesion=True, scale_xyz=(0.45, 0.45, 0.8),
+                          anatomy_shape_xyz=fixed_shape, features=True)
     skull_m = render_labels(moving_shape, inv_map=m2f, lesion=False, scale_xyz=(0.50, 0.50, 0.86),
                             anatomy_shape_xyz=fixed_shape)
-    lev = np.array([0.0, 800.0, 1500.0, 2200.0])
+    lev = np.array([0.0, 800.0, 1500.0, 2200.0, 200.0])
     s = np.where(skull_m > 0, 300.0, 0.0)
     s = np.where(lab_m > 0, lev[lab_m], s)
     n1 = rng.standard_normal(s.shape)

@@ -7,6 +7,14 @@ strategy proposed in the Discussion: one histogram yields both entropies,
 so translation parameters follow the Tsallis-MI gradient and the linear
 part (rotation, scale, skew) the Shannon-MI gradient.
 
+Two parameterisations of the linear part: ``"affine"`` steps the 9 entries
+of A directly; ``"decomposed"`` steps A = R(angles) H(shears) diag(exp(s))
+(the factorisation of ``transforms.affine_matrix``), so that a rotation is a
+coordinate of its own.  Adam normalises each coordinate separately, and on
+anatomy whose rotations a shear can nearly undo, the MI ridge runs along
+the antisymmetric combination of two raw entries, where per-entry steps
+make little progress.
+
 The optimiser state (parameters, step, Adam moments) can be written to and
 resumed from a JSON checkpoint.
 """
@@ -20,16 +28,58 @@ import numpy as np
 import torch
 
 from . import binding as B
+from . import transforms as T
 from .autograd import Geometry
+
+
+def decomposed_to_affine(d) -> np.ndarray:
+    """(angles (rad), log-scales, shears (h_xy, h_xz, h_yz), t) -> (A.flat, t)."""
+    d = np.asarray(d, dtype=np.float64)
+    A = T.affine_matrix(np.rad2deg(d[0:3]), np.exp(d[3:6]), d[6:9])
+    return T.params_from(A, d[9:12])
+
+
+def affine_to_decomposed(p) -> np.ndarray:
+    """Inverse of decomposed_to_affine for det(A) > 0: A = Q U by QR with
+    U's diagonal made positive, Q = Rz Ry Rx, U = H diag(s)."""
+    p = np.asarray(p, dtype=np.float64)
+    A = p[:9].reshape(3, 3)
+    if not np.linalg.det(A) > 0:
+        raise ValueError("the linear part must have a positive determinant")
+    Q, U = np.linalg.qr(A)
+    sg = np.sign(np.diag(U))
+    Q, U = Q * sg, sg[:, None] * U
+    s = np.diag(U)
+    hxy, hxz, hyz = U[0, 1] / s[1], U[0, 2] / s[2], U[1, 2] / s[2]
+    ay = -np.arcsin(np.clip(Q[2, 0], -1.0, 1.0))
+    ax = np.arctan2(Q[2, 1], Q[2, 2])
+    az = np.arctan2(Q[1, 0], Q[0, 0])
+    return np.concatenate([[ax, ay, az], np.log(s), [hxy, hxz, hyz], p[9:12]])
+
+
+def decomposed_jacobian(d, h: float = 1e-6) -> np.ndarray:
+    """J[i, j] = d affine_params[i] / d d[j] by central differences (fp64)."""
+    J = np.zeros((12, 12))
+    for j in range(12):
+        e = np.zeros(12)
+        e[j] = h
+        J[:, j] = (decomposed_to_affine(d + e) - decomposed_to_affine(d - e)) / (2 * h)
+    return J
 
 
 @dataclass
 class RegState:
-    params: list          # 12 floats: A (row-major 3x3), t (3)
+    params: list          # 12 floats in the parameterisation `param`
     step: int = 0
+    param: str = "affine"  # "affine": A (row-major 3x3), t; "decomposed": see decomposed_to_affine
     m: list = field(default_factory=lambda: [0.0] * 12)
     v: list = field(default_factory=lambda: [0.0] * 12)
     history: list = field(default_factory=list)  # (step, MI per entropy)
+
+    def affine(self) -> np.ndarray:
+        """The state's transform as 12 centred affine parameters (A.flat, t)."""
+        p = np.asarray(self.params, dtype=np.float64)
+        return decomposed_to_affine(p) if self.param == "decomposed" else p
 
     def save(self, path: str) -> None:
         with open(path, "w") as f:
@@ -45,29 +95,41 @@ def register(gctx: B.Context, fixed: B.Volume, moving: B.Volume, geom: Geometry,
              params0, steps: int = 200, q_translation: float = 1.3, mixed: bool = True,
              lr_linear: float = 2e-3, lr_translation: float = 0.2, betas=(0.9, 0.999),
              flags: int = B.BOUNDARY_CLAMP, state: RegState | None = None,
-             checkpoint: str | None = None, every: int = 50, workspace=None) -> RegState:
-    """Maximises Parzen MI over the centred affine parameters.
+             checkpoint: str | None = None, every: int = 50, workspace=None,
+             param: str = "affine") -> RegState:
+    """Maximises Parzen MI over the centred affine parameters ``params0``
+    (A.flat, t), stepping them in the parameterisation ``param``.
 
     With ``mixed`` the objective's gradient takes the linear entries from
     Shannon MI and the translation entries from Tsallis MI at
     ``q_translation``; otherwise every entry follows Tsallis MI at that q.
+    A resumed ``state`` keeps its own parameterisation.
     """
     dev = fixed.tensor.device
     if state is None:
-        state = RegState(params=[float(x) for x in np.asarray(params0, dtype=np.float64).reshape(12)])
+        if param not in ("affine", "decomposed"):
+            raise ValueError(f"unknown parameterisation {param!r}")
+        p0 = np.asarray(params0, dtype=np.float64).reshape(12)
+        if param == "decomposed":
+            p0 = affine_to_decomposed(p0)
+        state = RegState(params=[float(x) for x in p0], param=param)
+    dec = state.param == "decomposed"
     q = [1.0, q_translation]
     lr = np.array([lr_linear] * 9 + [lr_translation] * 3)
     b1, b2 = betas
-    p = torch.tensor(state.params, dtype=torch.float64, device=dev).reshape(1, 12)
+    d = np.asarray(state.params, dtype=np.float64)
     if workspace is None:
         workspace = gctx.workspace(gctx.workspace_size(fixed, moving, 1, bins, len(q), flags | B.HIST_PARZEN, True))
     m = np.asarray(state.m, dtype=np.float64)
     v = np.asarray(state.v, dtype=np.float64)
     J = geom.J
     while state.step < steps:
-        M = geom.matrices(p)
+        pa = decomposed_to_affine(d) if dec else d
+        M = geom.matrices(torch.as_tensor(pa, dtype=torch.float64, device=dev).reshape(1, 12))
         mi, gM = gctx.grad(fixed, moving, M, bins, q, flags=flags, workspace=workspace)
-        gp = (gM[0] @ J).cpu().numpy()          # [n_q][12] d MI_q / d params
+        gp = (gM[0] @ J).cpu().numpy()          # [n_q][12] d MI_q / d (A, t)
+        if dec:
+            gp = gp @ decomposed_jacobian(d)    # d MI_q / d (angles, log-scales, shears, t)
         if mixed:
             g = np.concatenate([gp[0, :9], gp[1, 9:]])
         else:
@@ -78,8 +140,8 @@ def register(gctx: B.Context, fixed: B.Volume, moving: B.Volume, geom: Geometry,
         mh = m / (1 - b1 ** state.step)
         vh = v / (1 - b2 ** state.step)
         delta = lr * mh / (np.sqrt(vh) + 1e-12)
-        p += torch.as_tensor(delta, dtype=torch.float64, device=dev).reshape(1, 12)   # ascent
-        state.params = [float(x) for x in p.reshape(12).cpu().numpy()]
+        d = d + delta   # ascent
+        state.params = [float(x) for x in d]
         state.m, state.v = [float(x) for x in m], [float(x) for x in v]
         state.history.append((state.step, [float(x) for x in mi[0].cpu().numpy()]))
         if checkpoint and (state.step % every == 0 or state.step == steps):
