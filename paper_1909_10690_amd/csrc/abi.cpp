@@ -8,6 +8,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
 #include <mutex>
 #include <fstream>
 #include <sstream>
@@ -103,12 +104,14 @@ int check_common(const mi_volume* f, const mi_volume* m, int32_t n, int32_t bins
 //   fixed bins   u8[nvox_fixed]
 //   hard:        moving oct volume u16x8[mnz][mny][mnx],
 //                hist u32[n][B][B]          (only when the caller passes no hist_out)
+//                count u64[n], MI partial sums (reduce_part_bytes)
 //   Parzen:      moving oct volume (integer moving volume) or f32x4 quad
 //                volume [mnz+1][mny][mnx] (float moving volume),
-//                table f64[n][B][B], count u64[n]
+//                occupied-row map, table f64[n][B][B], count u64[n]
+//                MI partial sums (reduce_part_bytes)
 //   Parzen grad: + dMI/dp tables f32[n][n_q][B][B]
 struct Layout {
-  size_t fbins = 0, gvol = 0, hist = 0, table = 0, count = 0, gtab = 0, total = 0;
+  size_t fbins = 0, gvol = 0, hist = 0, rowmap = 0, table = 0, count = 0, part = 0, gtab = 0, total = 0;
 };
 
 
@@ -124,13 +127,21 @@ Layout layout(const mi_volume* f, const mi_volume* m, int32_t n, int32_t bins, i
     off += align256(gather_bytes(m));
     L.hist = off;
     if (need_hist) off += align256(bb * 4 * (size_t)n);
+    L.count = off;
+    off += align256(8 * (size_t)n);
+    L.part = off;
+    off += align256(reduce_part_bytes(n, bins, n_q));
   } else {
     L.gvol = off;
     off += align256(gather_bytes(m));
+    L.rowmap = off;
+    off += align256(sizeof(RowMap));
     L.table = off;
     off += align256(bb * 8 * (size_t)n);
     L.count = off;
     off += align256(8 * (size_t)n);
+    L.part = off;
+    off += align256(reduce_part_bytes(n, bins, n_q));
     if (grad) {
       L.gtab = off;
       off += align256(bb * 4 * (size_t)n * n_q);
@@ -288,6 +299,8 @@ int run_parzen(mi_context* ctx, const mi_volume* fixed, const mi_volume* moving,
   hipError_t e;
   uint8_t* fb = (uint8_t*)(ws + L.fbins);
   if ((e = launch_prebin_fixed(desc(fixed), bins, fb, s)) != hipSuccess) return hip_fail(e, "prebin");
+  RowMap* rows = (RowMap*)(ws + L.rowmap);
+  if ((e = launch_row_map(fb, voxels(fixed), bins, rows, s)) != hipSuccess) return hip_fail(e, "row map");
   const bool fq = moving->dtype == MI_F32;
   void* gvol = ws + L.gvol;
   e = fq ? launch_pack_quads_f32(desc(moving), (float4*)gvol, s)
@@ -306,6 +319,7 @@ int run_parzen(mi_context* ctx, const mi_volume* fixed, const mi_volume* moving,
   ParzenArgs& a = P.args;
   a.transforms = transforms;
   a.fbins = fb;
+  a.rows = rows;
   a.gvol = gvol;
   a.table = table;
   a.count = count;
@@ -332,7 +346,9 @@ int run_parzen(mi_context* ctx, const mi_volume* fixed, const mi_volume* moving,
     ParzenLaunch part = P;
     ParzenArgs& pa = part.args;
     // backward: kParzenQGroup fp32 tables; forward: one table of 8-byte cells
-    pa.band_rows = band_rows_for(bins, backward ? kParzenQGroup : 2);
+    // plus kHotCopies - 1 extra copies of the background row
+    pa.band_rows = backward ? band_rows_for(bins, kParzenQGroup)
+                            : std::min(bins, std::max(1, 65536 / (8 * bins) - (kHotCopies - 1)));
     pa.bands = (bins + pa.band_rows - 1) / pa.band_rows;
     pa.chunks = plan_parzen_chunks(ctx, fixed, moving, (int64_t)n * pa.bands);
     const int64_t per_launch = 0x7FFFFFFFll / ((int64_t)pa.chunks * pa.bands);
@@ -357,6 +373,7 @@ int run_parzen(mi_context* ctx, const mi_volume* fixed, const mi_volume* moving,
   memset(&R, 0, sizeof R);
   R.table = table;
   R.count = count;
+  R.part = (double*)(ws + L.part);
   R.transforms = transforms;
   R.n = n;
   R.bins = bins;
@@ -379,7 +396,7 @@ int run_parzen(mi_context* ctx, const mi_volume* fixed, const mi_volume* moving,
 
 // Layout and work split of a multi-pair call (hard histograms).
 struct PairsPlan {
-  size_t tables = 0, table_bytes = 0, counters = 0, transforms = 0, hist = 0, total = 0;
+  size_t tables = 0, table_bytes = 0, counters = 0, transforms = 0, hist = 0, count = 0, part = 0, total = 0;
   size_t off_desc = 0, off_frow = 0, off_mrow = 0, off_tbase = 0, off_xcd = 0;
   std::vector<size_t> fbins, octs;
   std::vector<int32_t> chunks;
@@ -450,6 +467,10 @@ int plan_pairs(const mi_pair* pairs, int32_t n_pairs, int32_t bins, int32_t n_q,
   w += align256(96 * (size_t)plan.total_t);
   plan.hist = w;
   w += align256(4 * (size_t)bins * bins * (size_t)plan.total_t);
+  plan.count = w;
+  w += align256(8 * (size_t)plan.total_t);
+  plan.part = w;
+  w += align256(reduce_part_bytes(plan.total_t, bins, n_q));
   for (int p = 0; p < P; ++p) {
     plan.fbins[p] = w;
     w += align256(voxels(&pairs[p].fixed));
@@ -620,6 +641,8 @@ int run_hard(mi_context* ctx, const mi_volume* fixed, const mi_volume* moving,
   ReduceLaunch R;
   memset(&R, 0, sizeof R);
   R.hist = hist;
+  R.count = (uint64_t*)(ws + L.count);
+  R.part = (double*)(ws + L.part);
   R.transforms = transforms;
   R.n = n;
   R.bins = bins;
@@ -999,6 +1022,8 @@ int mi_eval_pairs(mi_context* ctx, const mi_pair* pairs, int32_t n_pairs, int32_
     ReduceLaunch R;
     memset(&R, 0, sizeof R);
     R.hist = a.hist;
+    R.count = (uint64_t*)(ws + plan.count);
+    R.part = (double*)(ws + plan.part);
     R.transforms = a.transforms;
     R.n = (int32_t)plan.total_t;
     R.bins = bins;

@@ -209,10 +209,24 @@ inline size_t quad_f32_bytes(int32_t nx, int32_t ny, int32_t nz) {
   return (size_t)nx * (size_t)ny * (size_t)(nz + 1) * 16;
 }
 
+// The MI reduction splits each transform's table into reduce_splits(B)
+// slices of at most 8 rows (and the same 8 columns' marginals), one
+// workgroup each, so that one transform keeps many CUs busy; the slices'
+// compensated partial sums are merged in slice order, so the result does
+// not depend on scheduling or on how many transforms share the launch.
+__host__ __device__ inline int32_t reduce_splits(int32_t bins) { return bins >= 16 ? bins / 8 : 1; }
+
+// Bytes of the partial sums: per transform, slice and entropy, three
+// compensated (sum, error) pairs.
+inline size_t reduce_part_bytes(int64_t n, int32_t bins, int32_t n_q) {
+  return (size_t)n * reduce_splits(bins) * n_q * 3 * 16;
+}
+
 struct ReduceLaunch {
   const uint32_t* hist;  // [n][B][B] counts, or NULL when `table` is used
   const double* table;   // [n][B][B] Parzen masses, or NULL
-  const uint64_t* count; // [n] normaliser for Parzen tables
+  uint64_t* count;       // [n] N: given with a table; summed from hist otherwise
+  double* part;          // reduce_part_bytes(n, B, n_q) of partial sums
   const double* transforms;
   int32_t n, bins;
   QList q;
@@ -221,9 +235,22 @@ struct ReduceLaunch {
 };
 
 // Parzen sweeps (see parzen.hip).
+// Occupied fixed-bin rows of a Parzen call.  The Parzen sweeps index the
+// table's rows by "slot" (rank among the occupied rows), so that the LDS
+// bands cover only rows that hold voxels: a CT-like fixed volume occupies a
+// few clusters of its bins (air, soft tissue, bone) and empty bands would
+// still cost a full walk of the fixed volume each.
+struct RowMap {
+  uint32_t used[256];         // 1 for every bin some fixed voxel falls in
+  uint32_t row_of_slot[256];  // table row of each slot
+  uint32_t slot_of_row[256];  // slot of each occupied row
+  uint32_t n_slots;           // occupied rows
+};
+
 struct ParzenArgs {
   const double* transforms;
-  const uint8_t* fbins;
+  const uint8_t* fbins;       // fixed-volume slots (see RowMap)
+  const RowMap* rows;
   const void* gvol;    // uint4 octs (integer moving) or float4 quads (float moving)
   double* table;       // [n][B][B] forward masses (fp64)
   uint64_t* count;     // [n] voxels that took part
@@ -239,6 +266,11 @@ struct ParzenArgs {
 };
 
 constexpr int kParzenQGroup = 2;  // entropies per backward sweep
+constexpr int kHotCopies = 4;     // forward: LDS copies of the background row (slot 0)
+
+// Batches of at most this many transforms build each dMI/dp table with one
+// 1024-thread workgroup instead of a 256-thread one.
+constexpr int kFewTransforms = 256;
 
 struct ParzenLaunch {
   ParzenArgs args;
@@ -269,7 +301,7 @@ struct PairsArgs {
   const PairDesc* pairs;
   int32_t n_pairs;
   const int64_t* frow_base;  // [P+1] prefix of fixed rows
-  const int64_t* mrow_base;  // [P+1] prefix of quad rows, (mnz+1)*mny per pair
+  const int64_t* mrow_base;  // [P+1] prefix of moving rows, mnz*mny per pair
   const int64_t* t_base;     // [P+1] prefix of transforms
   const int64_t* xcd_base;   // [8][P+1] prefix of work items per XCD
   unsigned long long* counters;  // [8] work-queue heads
@@ -290,6 +322,7 @@ HardGeom make_hard_geom(const VolumeDesc& fixed, const VolumeDesc& moving, const
                         const uint4* octs, int32_t bins);
 hipError_t launch_mi_reduce(const ReduceLaunch& L, hipStream_t s);
 hipError_t launch_pack_quads_f32(const VolumeDesc& m, float4* out, hipStream_t s);
+hipError_t launch_row_map(uint8_t* fbins, size_t nvox, int32_t bins, RowMap* m, hipStream_t s);
 hipError_t launch_parzen_fwd(const ParzenLaunch& L, hipStream_t s);
 hipError_t launch_dmi_dp(const ParzenLaunch& L, const QList& q, hipStream_t s);
 hipError_t launch_parzen_bwd(const ParzenLaunch& L, hipStream_t s);

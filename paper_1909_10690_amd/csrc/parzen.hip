@@ -53,6 +53,92 @@ hipError_t launch_pack_quads_f32(const VolumeDesc& m, float4* out, hipStream_t s
 }
 
 // ---------------------------------------------------------------------------
+// occupied fixed-bin rows
+// ---------------------------------------------------------------------------
+
+// used[b] = 1 for every bin b that some fixed voxel falls in.  Each thread
+// scans 16 consecutive voxels and marks a bin only where it differs from
+// the previous voxel and is not yet marked, so long runs of one bin (air)
+// cost no LDS writes.
+__global__ __launch_bounds__(256) void rows_used_kernel(const uint8_t* __restrict__ fb, size_t n,
+                                                        uint32_t* __restrict__ used) {
+  __shared__ uint32_t u[256];
+  u[threadIdx.x] = 0;
+  __syncthreads();
+  const size_t n16 = n / 16;
+  const uint4* __restrict__ v = (const uint4*)fb;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n16; i += (size_t)gridDim.x * blockDim.x) {
+    const uint4 w = v[i];
+    const uint32_t words[4] = {w.x, w.y, w.z, w.w};
+    uint32_t prev = 0x100u;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      const uint32_t b = (words[k >> 2] >> ((k & 3) * 8)) & 0xFFu;
+      if (b != prev && !u[b]) u[b] = 1u;
+      prev = b;
+    }
+  }
+  if (blockIdx.x == 0)
+    for (size_t i = n16 * 16 + threadIdx.x; i < n; i += blockDim.x) u[fb[i]] = 1u;
+  __syncthreads();
+  if (u[threadIdx.x]) used[threadIdx.x] = 1u;
+}
+
+// Slots: rank of each occupied row among the occupied rows (one workgroup).
+__global__ __launch_bounds__(256) void row_map_kernel(RowMap* m, int32_t bins) {
+  __shared__ uint32_t pre[256];
+  const int r = threadIdx.x;
+  const uint32_t used = (r < bins && m->used[r]) ? 1u : 0u;
+  pre[r] = used;
+  __syncthreads();
+  if (r == 0) {
+    uint32_t sum = 0;
+    for (int i = 0; i < 256; ++i) {
+      const uint32_t u = pre[i];
+      pre[i] = sum;
+      sum += u;
+    }
+    m->n_slots = sum;
+  }
+  __syncthreads();
+  m->slot_of_row[r] = used ? pre[r] : 0u;
+  if (used) m->row_of_slot[pre[r]] = (uint32_t)r;
+}
+
+// fbins[i] <- slot of fbins[i], 16 voxels per thread.
+__global__ __launch_bounds__(256) void remap_rows_kernel(uint8_t* __restrict__ fb, size_t n,
+                                                         const RowMap* __restrict__ m) {
+  __shared__ uint32_t slot[256];
+  slot[threadIdx.x] = m->slot_of_row[threadIdx.x];
+  __syncthreads();
+  const size_t n16 = n / 16;
+  uint4* __restrict__ v = (uint4*)fb;
+  auto map4 = [&](uint32_t w) -> uint32_t {
+    return slot[w & 0xFFu] | (slot[(w >> 8) & 0xFFu] << 8) | (slot[(w >> 16) & 0xFFu] << 16) |
+           (slot[w >> 24] << 24);
+  };
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n16; i += (size_t)gridDim.x * blockDim.x) {
+    const uint4 w = v[i];
+    v[i] = make_uint4(map4(w.x), map4(w.y), map4(w.z), map4(w.w));
+  }
+  if (blockIdx.x == 0)
+    for (size_t i = n16 * 16 + threadIdx.x; i < n; i += blockDim.x) fb[i] = (uint8_t)slot[fb[i]];
+}
+
+hipError_t launch_row_map(uint8_t* fbins, size_t nvox, int32_t bins, RowMap* m, hipStream_t s) {
+  hipError_t e;
+  if ((e = launch_fill_u32(m->used, 256, 0u, s)) != hipSuccess) return e;
+  const size_t blocks = (nvox / 16 + 255) / 256;
+  const unsigned grid = (unsigned)(blocks < 1 ? 1 : (blocks > 2048 ? 2048 : blocks));
+  hipLaunchKernelGGL(rows_used_kernel, dim3(grid), dim3(256), 0, s, (const uint8_t*)fbins, nvox, m->used);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(row_map_kernel, dim3(1), dim3(256), 0, s, m, bins);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(remap_rows_kernel, dim3(grid), dim3(256), 0, s, fbins, nvox, (const RowMap*)m);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // per-voxel sample shared by the forward and backward sweeps
 // ---------------------------------------------------------------------------
 
@@ -110,8 +196,15 @@ __device__ __forceinline__ unsigned long long fixed40(float w) {
 // Sweep geometry of one workgroup.
 struct SweepCtx {
   uint32_t t, chunk, band;
-  int32_t r_lo, r_hi;  // fixed-bin rows of this band
+  int32_t r_lo, r_hi;  // slots (occupied fixed-bin rows) of this band
 };
+
+// Table row index of a band's cell e (slot r_lo + e / B, column e % B).
+__device__ __forceinline__ size_t band_cell_row(const RowMap* m, int32_t r_lo, int e, int B, int& col) {
+  const int rr = e / B;
+  col = e - rr * B;
+  return (size_t)m->row_of_slot[r_lo + rr] * B;
+}
 
 // ---------------------------------------------------------------------------
 // forward: Parzen table
@@ -128,6 +221,12 @@ struct SweepCtx {
 // a workgroup covers fewer than 2^24 voxels (2^28 voxels at most, split
 // into at least 32 workgroups per transform).  64-bit LDS atomics need an
 // 8-byte aligned address, hence the alignment of the table.
+//
+// Slot 0, the lowest occupied fixed bin, is the background of a medical
+// volume (air, most of a CT): whole waves add their taps into a handful of
+// its cells, and same-address LDS atomics serialise.  The band holding it
+// keeps kHotCopies copies of that row, lane l adding into copy l % kHotCopies;
+// the copies are summed at the flush.
 template <bool FQ, bool CLAMP, int NT>
 __global__ __launch_bounds__(NT) void parzen_fwd_kernel(ParzenArgs a) {
   extern __shared__ __align__(16) unsigned long long lds_tab[];
@@ -135,15 +234,19 @@ __global__ __launch_bounds__(NT) void parzen_fwd_kernel(ParzenArgs a) {
   const int B = a.bins;
   SweepCtx sc;
   block_work(a.chunks, a.n, a.bands, a.slab_major, sc.t, sc.chunk, sc.band);
+  const int32_t n_slots = (int32_t)a.rows->n_slots;
   sc.r_lo = (int32_t)sc.band * a.band_rows;
-  sc.r_hi = min(B, sc.r_lo + a.band_rows);
+  if (sc.r_lo >= n_slots) return;  // a band past the occupied rows (whole workgroup)
+  sc.r_hi = min(n_slots, sc.r_lo + a.band_rows);
   const int cells = (sc.r_hi - sc.r_lo) * B;
-  for (int e = threadIdx.x; e < cells; e += NT) lds_tab[e] = 0ull;
+  const int hot_cells = sc.r_lo == 0 ? (kHotCopies - 1) * B : 0;  // extra copies of slot 0
+  for (int e = threadIdx.x; e < cells + hot_cells; e += NT) lds_tab[e] = 0ull;
   if (threadIdx.x == 0) lds_count = 0;
   int64_t Mq[12];
   const bool ok = quantize_transform(a.transforms + 12 * (size_t)sc.t, Mq);
   __syncthreads();
   uint32_t taken = 0;
+  const int copy = (threadIdx.x & (kHotCopies - 1));  // this lane's copy of slot 0
   if (ok) {
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
@@ -194,7 +297,9 @@ __global__ __launch_bounds__(NT) void parzen_fwd_kernel(ParzenArgs a) {
         bspline_weights(s - fl, wt);
         const unsigned long long q0 = fixed40(wt[0]), q2 = fixed40(wt[2]), q3 = fixed40(wt[3]);
         const unsigned long long q1 = (1ull << 40) - q0 - q2 - q3;  // w1 >= 1/6
-        unsigned long long* cell = lds_tab + (fb - sc.r_lo) * B + ((int32_t)fl - 1);
+        int base = (fb - sc.r_lo) * B + ((int32_t)fl - 1);
+        if (fb == 0 && copy) base += cells + (copy - 1) * B;  // slot 0: lane's copy of the row
+        unsigned long long* cell = lds_tab + base;
         atomicAdd(cell + 0, q0);
         atomicAdd(cell + 1, q1);
         atomicAdd(cell + 2, q2);
@@ -205,10 +310,16 @@ __global__ __launch_bounds__(NT) void parzen_fwd_kernel(ParzenArgs a) {
   if (sc.band == 0 && taken) atomicAdd(&lds_count, taken);
   __syncthreads();
   if (!ok) return;
-  double* __restrict__ out = a.table + (size_t)sc.t * B * B + (size_t)sc.r_lo * B;
+  double* __restrict__ out = a.table + (size_t)sc.t * B * B;
   for (int e = threadIdx.x; e < cells; e += NT) {
-    const unsigned long long v = lds_tab[e];
-    if (v) atomicAdd(&out[e], (double)v * 9.094947017729282379150390625e-13);  // 2^-40
+    unsigned long long v = lds_tab[e];
+    if (e < hot_cells / (kHotCopies - 1))
+      for (int c = 1; c < kHotCopies; ++c) v += lds_tab[cells + (c - 1) * B + e];
+    if (v) {
+      int col;
+      const size_t row = band_cell_row(a.rows, sc.r_lo, e, B, col);
+      atomicAdd(&out[row + col], (double)v * 9.094947017729282379150390625e-13);  // 2^-40
+    }
   }
   if (threadIdx.x == 0 && sc.band == 0 && lds_count)
     atomicAdd((unsigned long long*)&a.count[sc.t], (unsigned long long)lds_count);
@@ -223,30 +334,34 @@ __global__ __launch_bounds__(NT) void parzen_fwd_kernel(ParzenArgs a) {
 //   Tsallis additive  G = q/(q-1) * (p^(q-1) - p_m^(q-1))
 //   Tsallis pseudo    G = q/(q-1) * (p^(q-1) - (1 + (1-q) S_q(F)) p_m^(q-1))
 // and G = 0 where p = 0 (no voxel there has a non-zero B-spline slope).
-__global__ __launch_bounds__(256) void dmi_dp_kernel(ParzenArgs a, QList ql) {
+// NT threads per transform: 1024 for small batches (see kFewTransforms).
+template <int NT>
+__global__ __launch_bounds__(NT) void dmi_dp_kernel(ParzenArgs a, QList ql) {
   const int B = a.bins;
   const size_t BB = (size_t)B * B;
   const int t = blockIdx.x;
-  __shared__ double pm[256], pf[256];
-  __shared__ double red[256];
+  __shared__ double pm[256], pf[256], cterm[256];
+  __shared__ double red[NT];
   const double* __restrict__ h = a.table + (size_t)t * BB;
   float* __restrict__ G = (float*)a.gtab + (size_t)t * ql.n * BB;
   int64_t Mq[12];
   const bool ok = quantize_transform(a.transforms + 12 * (size_t)t, Mq);
   const double N = (double)a.count[t];
   if (!ok || !(N > 0)) {
-    for (size_t e = threadIdx.x; e < BB * ql.n; e += 256) G[e] = 0.0f;
+    for (size_t e = threadIdx.x; e < BB * ql.n; e += NT) G[e] = 0.0f;
     return;
   }
   const double invN = 1.0 / N;
-  for (int i = threadIdx.x; i < B; i += 256) {
-    double r = 0, c = 0;
-    for (int k = 0; k < B; ++k) {
-      r += h[(size_t)i * B + k];
-      c += h[(size_t)k * B + i];
+  // marginals: rows by threads [0, B), columns by threads [B, 2B)
+  for (int i = threadIdx.x; i < 2 * B; i += NT) {
+    double sum = 0;
+    if (i < B) {
+      for (int k = 0; k < B; ++k) sum += h[(size_t)i * B + k];
+      pf[i] = sum * invN;
+    } else {
+      for (int k = 0; k < B; ++k) sum += h[(size_t)k * B + (i - B)];
+      pm[i - B] = sum * invN;
     }
-    pf[i] = r * invN;
-    pm[i] = c * invN;
   }
   __syncthreads();
   for (int iq = 0; iq < ql.n; ++iq) {
@@ -255,30 +370,32 @@ __global__ __launch_bounds__(256) void dmi_dp_kernel(ParzenArgs a, QList ql) {
     if (q != 1.0 && ql.pseudo) {
       // S_q(F) = -sum p expm1((q-1) ln p) / (q-1)
       double part = 0;
-      for (int i = threadIdx.x; i < B; i += 256)
+      for (int i = threadIdx.x; i < B; i += NT)
         if (pf[i] > 0) part += pf[i] * expm1(e1 * log(pf[i]));
       red[threadIdx.x] = part;
       __syncthreads();
-      for (int w = 128; w > 0; w >>= 1) {
+      for (int w = NT / 2; w > 0; w >>= 1) {
         if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
         __syncthreads();
       }
       fac = 1.0 + (1.0 - q) * (-red[0] / e1);
       __syncthreads();
     }
+    // per column: ln p_m (Shannon) or fac p_m^(q-1) (Tsallis), once
+    for (int i = threadIdx.x; i < B; i += NT)
+      cterm[i] = pm[i] > 0 ? (q == 1.0 ? log(pm[i]) : fac * pow(pm[i], e1)) : 0.0;
+    __syncthreads();
     float* __restrict__ Gq = G + (size_t)iq * BB;
-    for (size_t e = threadIdx.x; e < BB; e += 256) {
+    for (size_t e = threadIdx.x; e < BB; e += NT) {
       const double hv = h[e];
       double g = 0.0;
       if (hv > 0) {
-        const double p = hv * invN, m = pm[e % B];
-        if (q == 1.0)
-          g = log(p / m);
-        else
-          g = q / e1 * (pow(p, e1) - fac * pow(m, e1));
+        const double p = hv * invN, m = cterm[e % B];
+        g = q == 1.0 ? log(p) - m : q / e1 * (pow(p, e1) - m);
       }
       Gq[e] = (float)g;
     }
+    __syncthreads();
   }
 }
 
@@ -295,15 +412,21 @@ __global__ __launch_bounds__(NT) void parzen_bwd_kernel(ParzenArgs a) {
   const size_t BB = (size_t)B * B;
   SweepCtx sc;
   block_work(a.chunks, a.n, a.bands, a.slab_major, sc.t, sc.chunk, sc.band);
+  const int32_t n_slots = (int32_t)a.rows->n_slots;
   sc.r_lo = (int32_t)sc.band * a.band_rows;
-  sc.r_hi = min(B, sc.r_lo + a.band_rows);
+  if (sc.r_lo >= n_slots) return;  // a band past the occupied rows (whole workgroup)
+  sc.r_hi = min(n_slots, sc.r_lo + a.band_rows);
   const int cells = (sc.r_hi - sc.r_lo) * B;
   int64_t Mq[12];
   const bool ok = quantize_transform(a.transforms + 12 * (size_t)sc.t, Mq);
   const int nqg = min(NQG, a.n_q - a.q0);
   for (int g = 0; g < nqg; ++g) {
-    const float* __restrict__ src = a.gtab + ((size_t)sc.t * a.n_q + a.q0 + g) * BB + (size_t)sc.r_lo * B;
-    for (int e = threadIdx.x; e < cells; e += NT) lds_g[g * cells + e] = src[e];
+    const float* __restrict__ src = a.gtab + ((size_t)sc.t * a.n_q + a.q0 + g) * BB;
+    for (int e = threadIdx.x; e < cells; e += NT) {
+      int col;
+      const size_t row = band_cell_row(a.rows, sc.r_lo, e, B, col);
+      lds_g[g * cells + e] = src[row + col];
+    }
   }
   __syncthreads();
   float acc[NQG][12];
@@ -423,14 +546,17 @@ static hipError_t fwd_variant(const ParzenArgs& a, size_t lds, hipStream_t s) {
 
 hipError_t launch_parzen_fwd(const ParzenLaunch& L, hipStream_t s) {
   ParzenArgs a = L.args;
-  const size_t lds = (size_t)a.band_rows * a.bins * 8;
+  const size_t lds = (size_t)(a.band_rows + kHotCopies - 1) * a.bins * 8;
   if (L.float_quads)
     return L.clamp ? fwd_variant<true, true>(a, lds, s) : fwd_variant<true, false>(a, lds, s);
   return L.clamp ? fwd_variant<false, true>(a, lds, s) : fwd_variant<false, false>(a, lds, s);
 }
 
 hipError_t launch_dmi_dp(const ParzenLaunch& L, const QList& q, hipStream_t s) {
-  hipLaunchKernelGGL(dmi_dp_kernel, dim3((unsigned)L.args.n), dim3(256), 0, s, L.args, q);
+  if (L.args.n <= kFewTransforms)
+    hipLaunchKernelGGL(dmi_dp_kernel<1024>, dim3((unsigned)L.args.n), dim3(1024), 0, s, L.args, q);
+  else
+    hipLaunchKernelGGL(dmi_dp_kernel<256>, dim3((unsigned)L.args.n), dim3(256), 0, s, L.args, q);
   return hipGetLastError();
 }
 

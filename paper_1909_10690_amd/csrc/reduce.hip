@@ -4,6 +4,12 @@
 // sums per thread, wave64 shuffles and an ordered cross-wave combine, so
 // the result does not depend on scheduling.
 //
+// Three launches: (hard histograms only) N = sum of the counts, exact in
+// 64-bit integers; one workgroup per (transform, slice of <= 8 rows) for
+// the partial sums of its joint cells and of the marginals of its rows and
+// of the same-numbered columns; one small workgroup per transform merging
+// the slices in order.  Slicing spreads a single transform over B/8 CUs.
+//
 // With p = h / N over the cells of X (N = total count or, for Parzen
 // tables, the number of voxels that took part):
 //   Shannon  H(X) = -sum p ln p,                MI = H(F) + H(M) - H(F,M)
@@ -38,10 +44,10 @@ __device__ __forceinline__ Comp comp_merge(Comp a, Comp b) {
   return r;
 }
 
-// Block-wide sum of three compensated accumulators; every thread gets the
-// result.  Fixed combine order: xor-shuffle tree inside each wave, then
-// waves in index order.
-__device__ void block_sum3(Comp v[3], double out[3]) {
+// Block-wide sum of three compensated accumulators, valid in thread 0.
+// Fixed combine order: xor-shuffle tree inside each wave, then waves in
+// index order.
+__device__ void block_sum3(Comp v[3], Comp out[3]) {
   __shared__ Comp part[kBlock / 64][3];
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
@@ -57,111 +63,160 @@ __device__ void block_sum3(Comp v[3], double out[3]) {
   if (lane == 0)
     for (int k = 0; k < 3; ++k) part[wave][k] = v[k];
   __syncthreads();
-  for (int k = 0; k < 3; ++k) {
-    Comp acc = part[0][k];
-    for (int w = 1; w < kBlock / 64; ++w) acc = comp_merge(acc, part[w][k]);
-    out[k] = acc.s + acc.c;
-  }
+  if (threadIdx.x == 0)
+    for (int k = 0; k < 3; ++k) {
+      Comp acc = part[0][k];
+      for (int w = 1; w < kBlock / 64; ++w) acc = comp_merge(acc, part[w][k]);
+      out[k] = acc;
+    }
   __syncthreads();
 }
 
-template <bool TABLE>
-__global__ __launch_bounds__(kBlock) void mi_reduce_kernel(ReduceLaunch L) {
-  const int B = L.bins;
-  const size_t BB = (size_t)B * B;
-  const int t = blockIdx.x;
-  __shared__ double row[256], col[256];
-  __shared__ double total_sh;
+// Rows [r0, r1) of a B-row table split into S slices.
+__device__ __forceinline__ void slice_rows(int B, int S, int s, int& r0, int& r1) {
+  r0 = (int)(((int64_t)B * s) / S);
+  r1 = (int)(((int64_t)B * (s + 1)) / S);
+}
 
-  int64_t Mq[12];
-  const bool ok = quantize_transform(L.transforms + 12 * (size_t)t, Mq);
-  if (!ok) {
-    if (threadIdx.x < L.q.n) L.mi_out[(size_t)t * L.q.n + threadIdx.x] = __longlong_as_double(0x7FF8000000000000ll);
-    if (threadIdx.x == 0 && L.overlap_out) L.overlap_out[t] = 0;
-    return;
+// N[t] += the counts of the slice's rows (count zeroed beforehand).
+__global__ __launch_bounds__(kBlock) void hist_count_kernel(const uint32_t* __restrict__ hist, int B,
+                                                            int S, uint64_t* __restrict__ count) {
+  const int t = blockIdx.x / S, s = blockIdx.x - t * S;
+  int r0, r1;
+  slice_rows(B, S, s, r0, r1);
+  const uint32_t* __restrict__ h = hist + (size_t)t * B * B;
+  uint64_t sum = 0;
+  for (int e = r0 * B + threadIdx.x; e < r1 * B; e += kBlock) sum += h[e];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) sum += __shfl_xor(sum, off, 64);
+  __shared__ uint64_t wsum[kBlock / 64];
+  if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = sum;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint64_t tot = 0;
+    for (int w = 0; w < kBlock / 64; ++w) tot += wsum[w];
+    if (tot) atomicAdd((unsigned long long*)&count[t], (unsigned long long)tot);
   }
+}
+
+// One workgroup per (transform, slice): per q, the compensated sums
+//   joint  sum over the slice's cells of  f(p)
+//   fixed  sum over the slice's rows of   f(row marginal)
+//   moving sum over the slice's columns of f(column marginal)
+// with f(p) = p ln p (Shannon) or p expm1((q-1) ln p) (Tsallis), p = h / N.
+template <bool TABLE>
+__global__ __launch_bounds__(kBlock) void mi_partial_kernel(ReduceLaunch L) {
+  const int B = L.bins, S = reduce_splits(B);
+  const int t = blockIdx.x / S, s = blockIdx.x - t * S;
+  int64_t Mq[12];
+  if (!quantize_transform(L.transforms + 12 * (size_t)t, Mq)) return;
+  const double N = (double)L.count[t];
+  if (!(N > 0)) return;
+  const double invN = 1.0 / N;
+  int r0, r1;
+  slice_rows(B, S, s, r0, r1);
+  const int R = r1 - r0;  // <= 15
+  const size_t BB = (size_t)B * B;
   const uint32_t* __restrict__ h32 = TABLE ? nullptr : L.hist + t * BB;
   const double* __restrict__ hd = TABLE ? L.table + t * BB : nullptr;
   auto cell = [&](size_t e) -> double { return TABLE ? hd[e] : (double)h32[e]; };
 
-  // marginals: exact for counts (integer sums < 2^53), compensated for masses
-  for (int i = threadIdx.x; i < B; i += kBlock) {
-    Comp r = {0, 0}, c = {0, 0};
-    for (int k = 0; k < B; ++k) {
-      comp_add(r, cell((size_t)i * B + k));
-      comp_add(c, cell((size_t)k * B + i));
+  // marginals of the slice's rows (lines 0..R-1) and columns (lines R..2R-1):
+  // 8 lanes per line, exact for counts, compensated for masses
+  __shared__ double marg[32];
+  {
+    const int line = threadIdx.x >> 3, sub = threadIdx.x & 7;
+    Comp a = {0, 0};
+    if (line < 2 * R) {
+      const bool is_row = line < R;
+      const int i = r0 + (is_row ? line : line - R);
+      for (int k = sub; k < B; k += 8) comp_add(a, cell(is_row ? (size_t)i * B + k : (size_t)k * B + i));
     }
-    row[i] = r.s + r.c;
-    col[i] = c.s + c.c;
+#pragma unroll
+    for (int off = 4; off > 0; off >>= 1) {
+      Comp o;
+      o.s = __shfl_xor(a.s, off, 64);
+      o.c = __shfl_xor(a.c, off, 64);
+      a = comp_merge(a, o);
+    }
+    if (sub == 0 && line < 2 * R) marg[line] = a.s + a.c;
   }
   __syncthreads();
-  double N;
-  uint64_t n_int = 0;
-  if (TABLE) {
-    n_int = L.count[t];
-    N = (double)n_int;
-  } else {
-    if (threadIdx.x == 0) {
-      double s = 0;
-      for (int i = 0; i < B; ++i) s += row[i];  // integers: exact
-      total_sh = s;
-    }
-    __syncthreads();
-    N = total_sh;
-    n_int = (uint64_t)N;
-  }
-  if (threadIdx.x == 0 && L.overlap_out) L.overlap_out[t] = n_int;
-  if (!(N > 0)) {
-    if (threadIdx.x < L.q.n) L.mi_out[(size_t)t * L.q.n + threadIdx.x] = 0.0;
-    return;
-  }
-  const double invN = 1.0 / N;
 
+  Comp* __restrict__ out = (Comp*)L.part + (size_t)blockIdx.x * L.q.n * 3;
   for (int iq = 0; iq < L.q.n; ++iq) {
     const double q = L.q.q[iq];
     const bool shannon = (q == 1.0);
     const double qm1 = q - 1.0;
+    auto f = [&](double h) -> double {
+      const double p = h * invN, lp = log(p);
+      return shannon ? p * lp : p * expm1(qm1 * lp);
+    };
     Comp acc[3] = {{0, 0}, {0, 0}, {0, 0}};  // joint, fixed, moving
-    for (size_t e = threadIdx.x; e < BB; e += kBlock) {
+    for (size_t e = (size_t)r0 * B + threadIdx.x; e < (size_t)r1 * B; e += kBlock) {
       const double h = cell(e);
-      if (h > 0) {
-        const double p = h * invN, lp = log(p);
-        comp_add(acc[0], shannon ? p * lp : p * expm1(qm1 * lp));
-      }
+      if (h > 0) comp_add(acc[0], f(h));
     }
-    for (int i = threadIdx.x; i < B; i += kBlock) {
-      const double hr = row[i], hc = col[i];
-      if (hr > 0) {
-        const double p = hr * invN, lp = log(p);
-        comp_add(acc[1], shannon ? p * lp : p * expm1(qm1 * lp));
-      }
-      if (hc > 0) {
-        const double p = hc * invN, lp = log(p);
-        comp_add(acc[2], shannon ? p * lp : p * expm1(qm1 * lp));
-      }
+    if (threadIdx.x < 2 * R) {
+      const double h = marg[threadIdx.x];
+      if (h > 0) comp_add(acc[threadIdx.x < R ? 1 : 2], f(h));
     }
-    double s[3];
-    block_sum3(acc, s);
-    if (threadIdx.x == 0) {
-      double I;
-      if (shannon) {
-        I = (s[0] - s[1]) - s[2];
-      } else {
-        const double Sj = -s[0] / qm1, Sf = -s[1] / qm1, Sm = -s[2] / qm1;
-        I = (Sf + Sm) - Sj;
-        if (L.q.pseudo) I += (1.0 - q) * Sf * Sm;
-      }
-      L.mi_out[(size_t)t * L.q.n + iq] = I;
-    }
+    Comp tot[3];
+    block_sum3(acc, tot);
+    if (threadIdx.x == 0)
+      for (int k = 0; k < 3; ++k) out[iq * 3 + k] = tot[k];
   }
+}
+
+// One wave per transform: merge the slices in order and form MI per q.
+__global__ __launch_bounds__(64) void mi_final_kernel(ReduceLaunch L) {
+  const int t = blockIdx.x, iq = threadIdx.x;
+  const int S = reduce_splits(L.bins);
+  int64_t Mq[12];
+  if (!quantize_transform(L.transforms + 12 * (size_t)t, Mq)) {
+    if (iq < L.q.n) L.mi_out[(size_t)t * L.q.n + iq] = __longlong_as_double(0x7FF8000000000000ll);
+    if (iq == 0 && L.overlap_out) L.overlap_out[t] = 0;
+    return;
+  }
+  const uint64_t n_int = L.count[t];
+  if (iq == 0 && L.overlap_out) L.overlap_out[t] = n_int;
+  if (iq >= L.q.n) return;
+  if (n_int == 0) {
+    L.mi_out[(size_t)t * L.q.n + iq] = 0.0;
+    return;
+  }
+  const Comp* __restrict__ part = (const Comp*)L.part + (size_t)t * S * L.q.n * 3;
+  Comp acc[3] = {part[iq * 3], part[iq * 3 + 1], part[iq * 3 + 2]};
+  for (int s = 1; s < S; ++s)
+    for (int k = 0; k < 3; ++k) acc[k] = comp_merge(acc[k], part[((size_t)s * L.q.n + iq) * 3 + k]);
+  const double q = L.q.q[iq], qm1 = q - 1.0;
+  const double sj = acc[0].s + acc[0].c, sf = acc[1].s + acc[1].c, sm = acc[2].s + acc[2].c;
+  double I;
+  if (q == 1.0) {
+    I = (sj - sf) - sm;
+  } else {
+    const double Sj = -sj / qm1, Sf = -sf / qm1, Sm = -sm / qm1;
+    I = (Sf + Sm) - Sj;
+    if (L.q.pseudo) I += (1.0 - q) * Sf * Sm;
+  }
+  L.mi_out[(size_t)t * L.q.n + iq] = I;
 }
 
 hipError_t launch_mi_reduce(const ReduceLaunch& L, hipStream_t s) {
   if (L.n == 0) return hipSuccess;
-  if (L.table)
-    hipLaunchKernelGGL(mi_reduce_kernel<true>, dim3(L.n), dim3(kBlock), 0, s, L);
-  else
-    hipLaunchKernelGGL(mi_reduce_kernel<false>, dim3(L.n), dim3(kBlock), 0, s, L);
+  hipError_t e;
+  const int S = reduce_splits(L.bins);
+  const unsigned blocks = (unsigned)((int64_t)L.n * S);
+  if (!L.table) {
+    if ((e = launch_fill_u32((uint32_t*)L.count, 2 * (size_t)L.n, 0u, s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(hist_count_kernel, dim3(blocks), dim3(kBlock), 0, s, L.hist, L.bins, S, L.count);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(mi_partial_kernel<false>, dim3(blocks), dim3(kBlock), 0, s, L);
+  } else {
+    hipLaunchKernelGGL(mi_partial_kernel<true>, dim3(blocks), dim3(kBlock), 0, s, L);
+  }
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(mi_final_kernel, dim3((unsigned)L.n), dim3(64), 0, s, L);
   return hipGetLastError();
 }
 

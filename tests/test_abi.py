@@ -143,17 +143,21 @@ def ws_size(f, m, n, bins, n_q, flags=0, grad=0):
 
 def test_workspace_size_layout():
     a = lambda x: (x + 255) // 256 * 256
+    # MI partial sums: per transform, slice (B / 8 for B >= 16) and entropy,
+    # three compensated pairs of doubles
+    part = a(5 * (32 // 8) * 2 * 3 * 16)
     st, n = ws_size(vol(10, 11, 12), vol(9, 8, 7), 5, 32, 2)
-    # integer moving volume: oct volume, 16 bytes per voxel
-    assert st == 0 and n == a(10 * 11 * 12) + a(9 * 8 * 7 * 16) + a(5 * 32 * 32 * 4)
+    # integer moving volume: oct volume, 16 bytes per voxel; histograms; N per transform
+    assert st == 0 and n == a(10 * 11 * 12) + a(9 * 8 * 7 * 16) + a(5 * 32 * 32 * 4) + a(5 * 8) + part
     octs = a(8 * 8 * 8 * 16)
+    rowmap = a(3 * 256 * 4 + 4)   # occupied fixed-bin rows: used, row_of_slot, slot_of_row, n_slots
     st, n = ws_size(vol(10, 11, 12), vol(), 5, 32, 2, B.HIST_PARZEN)
-    assert st == 0 and n == a(1320) + octs + a(5 * 32 * 32 * 8) + a(5 * 8)
+    assert st == 0 and n == a(1320) + octs + rowmap + a(5 * 32 * 32 * 8) + a(5 * 8) + part
     st, n = ws_size(vol(10, 11, 12), vol(), 5, 32, 2, 0, 1)
-    assert st == 0 and n == a(1320) + octs + a(5 * 32 * 32 * 8) + a(5 * 8) + a(5 * 2 * 32 * 32 * 4)
+    assert st == 0 and n == a(1320) + octs + rowmap + a(5 * 32 * 32 * 8) + a(5 * 8) + part + a(5 * 2 * 32 * 32 * 4)
     # a float moving volume keeps fp32 quads: 16 bytes per voxel, one extra slice
     st, n = ws_size(vol(10, 11, 12), vol(dtype=B.F32, lo=0.0, hi=1.0), 5, 32, 2, B.HIST_PARZEN)
-    assert st == 0 and n == a(1320) + a(8 * 8 * 9 * 16) + a(5 * 32 * 32 * 8) + a(5 * 8)
+    assert st == 0 and n == a(1320) + a(8 * 8 * 9 * 16) + rowmap + a(5 * 32 * 32 * 8) + a(5 * 8) + part
     assert ws_size(vol(), vol(), 5, 1, 1)[0] == B.MI_ERR_BINS
     assert ws_size(vol(), vol(), 5, 32, 0)[0] == B.MI_ERR_Q
 

@@ -176,3 +176,25 @@ def test_autograd_matches_chain_rule(ctx):
     ref = np.einsum("q,nqe->ne", w.cpu().numpy(), og) @ J
     got = p.grad.cpu().numpy()
     assert np.abs(got - ref).max() <= GRAD_TOL * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("kind", ["two-rows", "all-rows"])
+def test_occupied_row_extremes(ctx, kind):
+    """The sweeps band only the occupied fixed-bin rows: a fixed volume with
+    two rows far apart (air / bone style) and one that fills all 256 rows
+    must both match the oracle."""
+    rng = np.random.default_rng(11 if kind == "two-rows" else 12)
+    shape = (36, 28, 22)
+    nx, ny, nz = shape
+    if kind == "two-rows":
+        f = np.where(rng.random((nz, ny, nx)) < 0.7, 0, 4095).astype(np.uint16)
+    else:
+        f = rng.integers(0, 4096, (nz, ny, nx)).astype(np.uint16)
+    m = inputs.intensities(inputs.render_labels(shape), (0, 3600, 2000, 1200), rng, 40.0, True, 0, 4095,
+                           np.uint16)
+    mats = np.stack([T.translation((0.4, -0.3, 0.2))] +
+                    list(inputs.random_affines(rng, 3, shape, rot=8, trans=3).reshape(-1, 3, 4))).reshape(-1, 12)
+    for flags in (0, 1):
+        assert_close(gpu_grad(ctx, f, m, (0, 4095), (0, 4095), mats, 256, [1.0, 1.3], flags),
+                     oracle_grad(f, m, (0, 4095), (0, 4095), mats, 256, [1.0, 1.3], flags),
+                     f"{kind} flags={flags}")
