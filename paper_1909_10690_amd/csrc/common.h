@@ -209,18 +209,28 @@ inline size_t quad_f32_bytes(int32_t nx, int32_t ny, int32_t nz) {
   return (size_t)nx * (size_t)ny * (size_t)(nz + 1) * 16;
 }
 
-// The MI reduction splits each transform's table into reduce_splits(B)
-// slices of at most 8 rows (and the same 8 columns' marginals), one
-// workgroup each, so that one transform keeps many CUs busy; the slices'
-// compensated partial sums are merged in slice order, so the result does
-// not depend on scheduling or on how many transforms share the launch.
-__host__ __device__ inline int32_t reduce_splits(int32_t bins) { return bins >= 16 ? bins / 8 : 1; }
+// The MI reduction splits each transform's table into reduce_splits(B, n)
+// row slices (with the same-numbered columns' marginals), one workgroup
+// each: a few transforms then still keep many CUs busy (1024 / n slices,
+// at most B / 8 of >= 8 rows), while a large batch uses one workgroup per
+// transform, whose per-workgroup overheads small slices would multiply.
+// The slices' compensated partial sums are merged in slice order, so a
+// result does not depend on scheduling; batches with the same slice count
+// give bit-identical results for the same transform.
+__host__ __device__ inline int32_t reduce_splits(int32_t bins, int64_t n) {
+  if (bins < 16 || n <= 0) return 1;
+  const int64_t s = 1024 / n;
+  return (int32_t)(s < 1 ? 1 : (s > bins / 8 ? bins / 8 : s));
+}
 
 // Bytes of the partial sums: per transform, slice and entropy, three
 // compensated (sum, error) pairs.
 inline size_t reduce_part_bytes(int64_t n, int32_t bins, int32_t n_q) {
-  return (size_t)n * reduce_splits(bins) * n_q * 3 * 16;
+  return (size_t)n * reduce_splits(bins, n) * n_q * 3 * 16;
 }
+
+// Slices with at most this many cells and marginals keep p and ln p in LDS.
+constexpr int kMaxSliceCells = 2304;
 
 struct ReduceLaunch {
   const uint32_t* hist;  // [n][B][B] counts, or NULL when `table` is used
@@ -229,6 +239,7 @@ struct ReduceLaunch {
   double* part;          // reduce_part_bytes(n, B, n_q) of partial sums
   const double* transforms;
   int32_t n, bins;
+  int32_t splits;        // reduce_splits(bins, n), set by launch_mi_reduce
   QList q;
   double* mi_out;        // [n][n_q]
   uint64_t* overlap_out; // [n] or NULL

@@ -5,10 +5,10 @@
 // the result does not depend on scheduling.
 //
 // Three launches: (hard histograms only) N = sum of the counts, exact in
-// 64-bit integers; one workgroup per (transform, slice of <= 8 rows) for
-// the partial sums of its joint cells and of the marginals of its rows and
-// of the same-numbered columns; one small workgroup per transform merging
-// the slices in order.  Slicing spreads a single transform over B/8 CUs.
+// 64-bit integers; one workgroup per (transform, row slice) for the partial
+// sums of its joint cells and of the marginals of its rows and of the
+// same-numbered columns; one small workgroup per transform merging the
+// slices in order.  Slicing spreads a single transform over up to B/8 CUs.
 //
 // With p = h / N over the cells of X (N = total count or, for Parzen
 // tables, the number of voxels that took part):
@@ -44,34 +44,6 @@ __device__ __forceinline__ Comp comp_merge(Comp a, Comp b) {
   return r;
 }
 
-// Block-wide sum of three compensated accumulators, valid in thread 0.
-// Fixed combine order: xor-shuffle tree inside each wave, then waves in
-// index order.
-__device__ void block_sum3(Comp v[3], Comp out[3]) {
-  __shared__ Comp part[kBlock / 64][3];
-#pragma unroll
-  for (int k = 0; k < 3; ++k) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-      Comp o;
-      o.s = __shfl_xor(v[k].s, off, 64);
-      o.c = __shfl_xor(v[k].c, off, 64);
-      v[k] = comp_merge(v[k], o);
-    }
-  }
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  if (lane == 0)
-    for (int k = 0; k < 3; ++k) part[wave][k] = v[k];
-  __syncthreads();
-  if (threadIdx.x == 0)
-    for (int k = 0; k < 3; ++k) {
-      Comp acc = part[0][k];
-      for (int w = 1; w < kBlock / 64; ++w) acc = comp_merge(acc, part[w][k]);
-      out[k] = acc;
-    }
-  __syncthreads();
-}
-
 // Rows [r0, r1) of a B-row table split into S slices.
 __device__ __forceinline__ void slice_rows(int B, int S, int s, int& r0, int& r1) {
   r0 = (int)(((int64_t)B * s) / S);
@@ -104,9 +76,9 @@ __global__ __launch_bounds__(kBlock) void hist_count_kernel(const uint32_t* __re
 //   fixed  sum over the slice's rows of   f(row marginal)
 //   moving sum over the slice's columns of f(column marginal)
 // with f(p) = p ln p (Shannon) or p expm1((q-1) ln p) (Tsallis), p = h / N.
-template <bool TABLE>
+template <bool TABLE, bool CACHED>
 __global__ __launch_bounds__(kBlock) void mi_partial_kernel(ReduceLaunch L) {
-  const int B = L.bins, S = reduce_splits(B);
+  const int B = L.bins, S = L.splits;
   const int t = blockIdx.x / S, s = blockIdx.x - t * S;
   int64_t Mq[12];
   if (!quantize_transform(L.transforms + 12 * (size_t)t, Mq)) return;
@@ -115,7 +87,7 @@ __global__ __launch_bounds__(kBlock) void mi_partial_kernel(ReduceLaunch L) {
   const double invN = 1.0 / N;
   int r0, r1;
   slice_rows(B, S, s, r0, r1);
-  const int R = r1 - r0;  // <= 15
+  const int R = r1 - r0;
   const size_t BB = (size_t)B * B;
   const uint32_t* __restrict__ h32 = TABLE ? nullptr : L.hist + t * BB;
   const double* __restrict__ hd = TABLE ? L.table + t * BB : nullptr;
@@ -123,9 +95,9 @@ __global__ __launch_bounds__(kBlock) void mi_partial_kernel(ReduceLaunch L) {
 
   // marginals of the slice's rows (lines 0..R-1) and columns (lines R..2R-1):
   // 8 lanes per line, exact for counts, compensated for masses
-  __shared__ double marg[32];
-  {
-    const int line = threadIdx.x >> 3, sub = threadIdx.x & 7;
+  __shared__ double marg[512];
+  for (int l0 = 0; l0 < 2 * R; l0 += kBlock / 8) {
+    const int line = l0 + (threadIdx.x >> 3), sub = threadIdx.x & 7;
     Comp a = {0, 0};
     if (line < 2 * R) {
       const bool is_row = line < R;
@@ -143,35 +115,71 @@ __global__ __launch_bounds__(kBlock) void mi_partial_kernel(ReduceLaunch L) {
   }
   __syncthreads();
 
-  Comp* __restrict__ out = (Comp*)L.part + (size_t)blockIdx.x * L.q.n * 3;
+  // CACHED: p and ln p of the slice's cells (first R B entries) and
+  // marginals (next 2R) once, so each entropy costs one expm1 per cell
+  // (none for Shannon); otherwise ln p is recomputed per entropy
+  constexpr int kCache = CACHED ? kMaxSliceCells : 1;  // host: R (B + 2) <= kMaxSliceCells
+  __shared__ double pv[kCache], lpv[kCache];
+  const int nc = R * B;
+  if (CACHED) {
+    for (int e = threadIdx.x; e < nc + 2 * R; e += kBlock) {
+      const double h = e < nc ? cell((size_t)r0 * B + e) : marg[e - nc];
+      const double p = h * invN;
+      pv[e] = h > 0 ? p : 0.0;
+      lpv[e] = h > 0 ? log(p) : 0.0;
+    }
+    __syncthreads();
+  }
+  // per entropy: compensated per-thread sums, a shuffle tree per wave into
+  // LDS; after all entropies one barrier and the waves merged in order
+  __shared__ Comp wpart[kMaxQ][3][kBlock / 64];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   for (int iq = 0; iq < L.q.n; ++iq) {
     const double q = L.q.q[iq];
     const bool shannon = (q == 1.0);
     const double qm1 = q - 1.0;
-    auto f = [&](double h) -> double {
-      const double p = h * invN, lp = log(p);
-      return shannon ? p * lp : p * expm1(qm1 * lp);
-    };
     Comp acc[3] = {{0, 0}, {0, 0}, {0, 0}};  // joint, fixed, moving
-    for (size_t e = (size_t)r0 * B + threadIdx.x; e < (size_t)r1 * B; e += kBlock) {
-      const double h = cell(e);
-      if (h > 0) comp_add(acc[0], f(h));
+    for (int e = threadIdx.x; e < nc + 2 * R; e += kBlock) {
+      double p, lp;
+      if (CACHED) {
+        p = pv[e];
+        lp = lpv[e];
+      } else {
+        const double h = e < nc ? cell((size_t)r0 * B + e) : marg[e - nc];
+        p = h > 0 ? h * invN : 0.0;
+        lp = h > 0 ? log(p) : 0.0;
+      }
+      if (p > 0) {
+        const int k = e < nc ? 0 : (e - nc < R ? 1 : 2);
+        comp_add(acc[k], shannon ? p * lp : p * expm1(qm1 * lp));
+      }
     }
-    if (threadIdx.x < 2 * R) {
-      const double h = marg[threadIdx.x];
-      if (h > 0) comp_add(acc[threadIdx.x < R ? 1 : 2], f(h));
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        Comp o;
+        o.s = __shfl_xor(acc[k].s, off, 64);
+        o.c = __shfl_xor(acc[k].c, off, 64);
+        acc[k] = comp_merge(acc[k], o);
+      }
+      if (lane == 0) wpart[iq][k][wave] = acc[k];
     }
-    Comp tot[3];
-    block_sum3(acc, tot);
-    if (threadIdx.x == 0)
-      for (int k = 0; k < 3; ++k) out[iq * 3 + k] = tot[k];
+  }
+  __syncthreads();
+  Comp* __restrict__ out = (Comp*)L.part + (size_t)blockIdx.x * L.q.n * 3;
+  if (threadIdx.x < L.q.n * 3) {
+    const int iq = threadIdx.x / 3, k = threadIdx.x - iq * 3;
+    Comp tot = wpart[iq][k][0];
+    for (int w = 1; w < kBlock / 64; ++w) tot = comp_merge(tot, wpart[iq][k][w]);
+    out[iq * 3 + k] = tot;
   }
 }
 
 // One wave per transform: merge the slices in order and form MI per q.
 __global__ __launch_bounds__(64) void mi_final_kernel(ReduceLaunch L) {
   const int t = blockIdx.x, iq = threadIdx.x;
-  const int S = reduce_splits(L.bins);
+  const int S = L.splits;
   int64_t Mq[12];
   if (!quantize_transform(L.transforms + 12 * (size_t)t, Mq)) {
     if (iq < L.q.n) L.mi_out[(size_t)t * L.q.n + iq] = __longlong_as_double(0x7FF8000000000000ll);
@@ -202,18 +210,30 @@ __global__ __launch_bounds__(64) void mi_final_kernel(ReduceLaunch L) {
   L.mi_out[(size_t)t * L.q.n + iq] = I;
 }
 
-hipError_t launch_mi_reduce(const ReduceLaunch& L, hipStream_t s) {
-  if (L.n == 0) return hipSuccess;
+template <bool TABLE>
+static void partial_variant(const ReduceLaunch& L, unsigned blocks, bool cached, hipStream_t s) {
+  if (cached)
+    hipLaunchKernelGGL((mi_partial_kernel<TABLE, true>), dim3(blocks), dim3(kBlock), 0, s, L);
+  else
+    hipLaunchKernelGGL((mi_partial_kernel<TABLE, false>), dim3(blocks), dim3(kBlock), 0, s, L);
+}
+
+hipError_t launch_mi_reduce(const ReduceLaunch& Lin, hipStream_t s) {
+  if (Lin.n == 0) return hipSuccess;
+  ReduceLaunch L = Lin;
+  L.splits = reduce_splits(L.bins, L.n);
   hipError_t e;
-  const int S = reduce_splits(L.bins);
+  const int S = L.splits;
   const unsigned blocks = (unsigned)((int64_t)L.n * S);
+  const int max_rows = (L.bins + S - 1) / S;
+  const bool cached = max_rows * (L.bins + 2) <= kMaxSliceCells;  // cells + 2 marginals per row
   if (!L.table) {
     if ((e = launch_fill_u32((uint32_t*)L.count, 2 * (size_t)L.n, 0u, s)) != hipSuccess) return e;
     hipLaunchKernelGGL(hist_count_kernel, dim3(blocks), dim3(kBlock), 0, s, L.hist, L.bins, S, L.count);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(mi_partial_kernel<false>, dim3(blocks), dim3(kBlock), 0, s, L);
+    partial_variant<false>(L, blocks, cached, s);
   } else {
-    hipLaunchKernelGGL(mi_partial_kernel<true>, dim3(blocks), dim3(kBlock), 0, s, L);
+    partial_variant<true>(L, blocks, cached, s);
   }
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(mi_final_kernel, dim3((unsigned)L.n), dim3(64), 0, s, L);

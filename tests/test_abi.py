@@ -143,9 +143,9 @@ def ws_size(f, m, n, bins, n_q, flags=0, grad=0):
 
 def test_workspace_size_layout():
     a = lambda x: (x + 255) // 256 * 256
-    # MI partial sums: per transform, slice (B / 8 for B >= 16) and entropy,
-    # three compensated pairs of doubles
-    part = a(5 * (32 // 8) * 2 * 3 * 16)
+    # MI partial sums: per transform, slice (min(1024 // n, B // 8) for
+    # B >= 16) and entropy, three compensated pairs of doubles
+    part = a(5 * min(1024 // 5, 32 // 8) * 2 * 3 * 16)
     st, n = ws_size(vol(10, 11, 12), vol(9, 8, 7), 5, 32, 2)
     # integer moving volume: oct volume, 16 bytes per voxel; histograms; N per transform
     assert st == 0 and n == a(10 * 11 * 12) + a(9 * 8 * 7 * 16) + a(5 * 32 * 32 * 4) + a(5 * 8) + part
