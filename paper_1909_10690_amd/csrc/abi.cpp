@@ -68,11 +68,18 @@ int check_q(const double* q, int32_t n_q) {
   return MI_OK;
 }
 
-// Bytes of the moving volume's gather layout (oct volume for integer
-// volumes, fp32 quad volume for float ones).
+// Bytes of the moving volume's gather layout on the Parzen path (16-bit
+// oct volume for integer volumes, fp32 quad volume for float ones); the
+// largest layout any path uses for the volume.
 size_t gather_bytes(const mi_volume* m) {
   return m->dtype == MI_F32 ? quad_f32_bytes(m->nx, m->ny, m->nz)
                             : oct_volume_bytes(m->nx, m->ny, m->nz);
+}
+
+// Bytes of the hard path's oct volume: 8-bit corners when the range allows.
+size_t hard_gather_bytes(const mi_volume* m) {
+  return oct8_range(m->lo, m->hi) ? oct8_volume_bytes(m->nx, m->ny, m->nz)
+                                  : oct_volume_bytes(m->nx, m->ny, m->nz);
 }
 
 // A moving volume whose gather layout needs 32-bit buffer offsets beyond
@@ -124,7 +131,7 @@ Layout layout(const mi_volume* f, const mi_volume* m, int32_t n, int32_t bins, i
   const size_t bb = (size_t)bins * bins;
   if (!parzen) {
     L.gvol = off;
-    off += align256(gather_bytes(m));
+    off += align256(hard_gather_bytes(m));
     L.hist = off;
     if (need_hist) off += align256(bb * 4 * (size_t)n);
     L.count = off;
@@ -241,9 +248,9 @@ struct TimedLaunch {
 // transforms at once, and their moving footprint must stay in the XCD's
 // 4 MiB L2 (on the 1000-transform 256x256x180 sweep, 128 slabs instead of
 // 32 cut the L2 miss traffic and the sweep time by 8%).
-int64_t l2_slabs(const mi_volume* m) {
+int64_t l2_slabs(size_t gather_volume_bytes) {
   const int64_t target = 3 << 19;  // 1.5 MiB
-  const int64_t c = ((int64_t)gather_bytes(m) + target - 1) / target;
+  const int64_t c = ((int64_t)gather_volume_bytes + target - 1) / target;
   return c < 32 ? 32 : c;
 }
 
@@ -262,7 +269,8 @@ int plan_chunks(const mi_context* ctx, const mi_volume* f, const mi_volume* m, i
     c = tune.chunks;
   } else {
     c = ((int64_t)ctx->cu_count * 8 + n - 1) / n;
-    if (tune.slab_major && c < l2_slabs(m)) c = l2_slabs(m);
+    const int64_t l2 = l2_slabs(hard_gather_bytes(m));
+    if (tune.slab_major && c < l2) c = l2;
   }
   if (c > groups) c = groups;
   if (packed) {
@@ -279,7 +287,8 @@ int plan_chunks(const mi_context* ctx, const mi_volume* f, const mi_volume* m, i
 int plan_parzen_chunks(const mi_context* ctx, const mi_volume* f, const mi_volume* m, int64_t units) {
   const int64_t groups = (int64_t)((f->ny + 3) / 4) * f->nz;
   int64_t c = ((int64_t)ctx->cu_count * 8 + units - 1) / units;
-  if (c < l2_slabs(m)) c = l2_slabs(m);
+  const int64_t l2 = l2_slabs(gather_bytes(m));
+  if (c < l2) c = l2;
   if (c > groups) c = groups;
   return (int)(((c + 7) / 8) * 8);
 }
@@ -402,6 +411,7 @@ struct PairsPlan {
   std::vector<int32_t> chunks;
   std::vector<int64_t> frow_base, mrow_base, t_base, xcd_base;  // xcd_base: [8][P+1]
   int64_t total_t = 0;
+  bool oct8 = true;  // every moving range <= 256: 8-bit corners for all pairs
 };
 
 int plan_pairs(const mi_pair* pairs, int32_t n_pairs, int32_t bins, int32_t n_q, int32_t flags,
@@ -471,11 +481,14 @@ int plan_pairs(const mi_pair* pairs, int32_t n_pairs, int32_t bins, int32_t n_q,
   w += align256(8 * (size_t)plan.total_t);
   plan.part = w;
   w += align256(reduce_part_bytes(plan.total_t, bins, n_q));
+  plan.oct8 = true;
+  for (int p = 0; p < P; ++p) plan.oct8 = plan.oct8 && oct8_range(pairs[p].moving.lo, pairs[p].moving.hi);
   for (int p = 0; p < P; ++p) {
     plan.fbins[p] = w;
     w += align256(voxels(&pairs[p].fixed));
     plan.octs[p] = w;
-    w += align256(oct_volume_bytes(pairs[p].moving.nx, pairs[p].moving.ny, pairs[p].moving.nz));
+    const mi_volume& mv = pairs[p].moving;
+    w += align256(plan.oct8 ? oct8_volume_bytes(mv.nx, mv.ny, mv.nz) : oct_volume_bytes(mv.nx, mv.ny, mv.nz));
   }
   plan.total = w;
   return MI_OK;
@@ -596,11 +609,13 @@ int launch_hard_hist(mi_context* ctx, const mi_volume* fixed, const mi_volume* m
                      const HardTune& tune, bool prepare) {
   hipError_t e;
   uint8_t* fb = (uint8_t*)(ws + L.fbins);
-  uint4* octs = (uint4*)(ws + L.gvol);
+  void* octs = ws + L.gvol;
   const size_t bb = (size_t)bins * bins;
   if (prepare) {
     if ((e = launch_prebin_fixed(desc(fixed), bins, fb, s)) != hipSuccess) return hip_fail(e, "prebin");
-    if ((e = launch_pack_octs(desc(moving), octs, s)) != hipSuccess) return hip_fail(e, "pack");
+    e = oct8_range(moving->lo, moving->hi) ? launch_pack_oct8(desc(moving), (uint2*)octs, s)
+                                           : launch_pack_octs(desc(moving), (uint4*)octs, s);
+    if (e != hipSuccess) return hip_fail(e, "pack");
   }
   if ((e = launch_fill_u32(hist, bb * n, 0u, s)) != hipSuccess) return hip_fail(e, "fill");
   HardLaunch H;
@@ -954,7 +969,11 @@ int mi_eval_pairs(mi_context* ctx, const mi_pair* pairs, int32_t n_pairs, int32_
     d.moving = pr.moving.data;
     d.transforms = pr.transforms;
     d.geom = make_hard_geom(desc(&pr.fixed), desc(&pr.moving), (const uint8_t*)(ws + plan.fbins[p]),
-                            (const uint4*)(ws + plan.octs[p]), bins);
+                            (const void*)(ws + plan.octs[p]), bins);
+    // one layout for every pair of the launch
+    d.geom.oct8 = plan.oct8 ? 1 : 0;
+    d.geom.oct_bytes = (uint32_t)(plan.oct8 ? oct8_volume_bytes(pr.moving.nx, pr.moving.ny, pr.moving.nz)
+                                            : oct_volume_bytes(pr.moving.nx, pr.moving.ny, pr.moving.nz));
     d.fdtype = pr.fixed.dtype;
     d.mdtype = pr.moving.dtype;
     d.flo = pr.fixed.lo;
@@ -1007,6 +1026,7 @@ int mi_eval_pairs(mi_context* ctx, const mi_pair* pairs, int32_t n_pairs, int32_
   L.moving_rows = plan.mrow_base[P];
   L.clamp = (flags & MI_BOUNDARY_CLAMP) ? 1 : 0;
   L.packed = bins > 128 ? 1 : 0;
+  L.oct8 = plan.oct8 ? 1 : 0;
   L.cu_count = ctx->cu_count;
   const size_t bb = (size_t)bins * bins;
   auto body = [&]() -> int {

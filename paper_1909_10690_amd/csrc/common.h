@@ -164,10 +164,11 @@ struct GroupWalk {
 // Geometry of one fixed/moving pair for the hard-binned sweep.
 struct HardGeom {
   const uint8_t* fbins;  // fixed bins, [fnz][fny][fnx]
-  const uint4* octs;     // moving oct volume, [mnz][mny][mnx]
+  const void* octs;      // moving oct volume, [mnz][mny][mnx]: u16x8, or u8x8 when oct8
   int32_t fnx, fny, fnz;
   int32_t mnx, mny, mnz;
   uint32_t oct_bytes;
+  int32_t oct8;          // 1: 8-bit corners (moving range R <= 256)
   int32_t bins;
   double scale;  // B / (R 2^48), R = moving hi - lo + 1
   Divider div;   // floor(X / R) for the exact fallback
@@ -183,7 +184,7 @@ struct VolumeDesc {
 struct HardLaunch {
   const double* transforms;  // [n][12]
   const uint8_t* fbins;      // fixed-volume bins, [fnz][fny][fnx]
-  const uint4* octs;         // moving oct volume, [mnz][mny][mnx]
+  const void* octs;          // moving oct volume, [mnz][mny][mnx] (u16x8 or u8x8)
   VolumeDesc fixed, moving;
   uint32_t* hist;  // [n][B][B]
   int32_t n, bins, clamp;
@@ -201,6 +202,14 @@ constexpr size_t kMaxGatherBytes = 0xFFFFFFF0u;
 // clamped, offset 16-bit corners of its 2x2x2 neighbourhood (16 bytes).
 inline size_t oct_volume_bytes(int32_t nx, int32_t ny, int32_t nz) {
   return (size_t)nx * (size_t)ny * (size_t)nz * 16;
+}
+
+// The hard path packs 8-bit corners (8 bytes per voxel) when the moving
+// range R = hi - lo + 1 is at most 256: the same single gather per voxel at
+// half the bytes, which matters where the moving volumes stream from HBM.
+inline bool oct8_range(double lo, double hi) { return hi - lo + 1.0 <= 256.0; }
+inline size_t oct8_volume_bytes(int32_t nx, int32_t ny, int32_t nz) {
+  return (size_t)nx * (size_t)ny * (size_t)nz * 8;
 }
 
 // Bytes of the fp32 quad volume of a float moving volume: per voxel the
@@ -293,6 +302,7 @@ hipError_t launch_fill_u32(uint32_t* p, size_t n, uint32_t value, hipStream_t s)
 hipError_t launch_fill_f64(double* p, size_t n, hipStream_t s);
 hipError_t launch_prebin_fixed(const VolumeDesc& f, int bins, uint8_t* out, hipStream_t s);
 hipError_t launch_pack_octs(const VolumeDesc& m, uint4* out, hipStream_t s);
+hipError_t launch_pack_oct8(const VolumeDesc& m, uint2* out, hipStream_t s);
 hipError_t launch_hist_hard(const HardLaunch& L, hipStream_t s);
 
 // Many fixed/moving pairs of uneven sizes (see pairs.hip).
@@ -325,12 +335,13 @@ struct PairsLaunch {
   PairsArgs args;
   int64_t total_t, fixed_rows, moving_rows;
   int32_t clamp, packed, cu_count;
+  int32_t oct8;  // every pair's moving volume packed with 8-bit corners
 };
 
 hipError_t launch_pairs_prep(const PairsLaunch& L, hipStream_t s);
 hipError_t launch_pairs_hist(const PairsLaunch& L, hipStream_t s);
 HardGeom make_hard_geom(const VolumeDesc& fixed, const VolumeDesc& moving, const uint8_t* fbins,
-                        const uint4* octs, int32_t bins);
+                        const void* octs, int32_t bins);
 hipError_t launch_mi_reduce(const ReduceLaunch& L, hipStream_t s);
 hipError_t launch_pack_quads_f32(const VolumeDesc& m, float4* out, hipStream_t s);
 hipError_t launch_row_map(uint8_t* fbins, size_t nvox, int32_t bins, RowMap* m, hipStream_t s);

@@ -131,6 +131,44 @@ __global__ void pack_octs_kernel(const T* __restrict__ v, int32_t nx, int32_t ny
   }
 }
 
+// The same neighbourhood with 8-bit corners (moving range R <= 256): byte
+// 4 dz + 2 dy + dx' of the element holds (x + dx', y + dy, z + dz), dx' = 0
+// for x and 1 for x1.
+template <typename T>
+__global__ void pack_oct8_kernel(const T* __restrict__ v, int32_t nx, int32_t ny, int32_t nz,
+                                 int32_t lo, int32_t hi, uint2* __restrict__ out) {
+  const int32_t y = blockIdx.y, z = blockIdx.z;
+  uint2* __restrict__ orow = out + ((size_t)z * ny + y) * nx;
+  const T* __restrict__ r00 = v + ((size_t)z * ny + y) * nx;
+  const T* __restrict__ r10 = r00 + (y + 1 < ny ? nx : 0);
+  const size_t dz = z + 1 < nz ? (size_t)nx * ny : 0;
+  const T* __restrict__ r01 = r00 + dz;
+  const T* __restrict__ r11 = r10 + dz;
+  auto c = [&](T raw) -> uint32_t { return clamp_offset((int32_t)raw, lo, hi); };
+  for (int32_t x = blockIdx.x * blockDim.x + threadIdx.x; x < nx; x += gridDim.x * blockDim.x) {
+    const int32_t x1 = x + 1 < nx ? x + 1 : nx - 1;
+    orow[x] = make_uint2(c(r00[x]) | (c(r00[x1]) << 8) | (c(r10[x]) << 16) | (c(r10[x1]) << 24),
+                         c(r01[x]) | (c(r01[x1]) << 8) | (c(r11[x]) << 16) | (c(r11[x1]) << 24));
+  }
+}
+
+hipError_t launch_pack_oct8(const VolumeDesc& m, uint2* out, hipStream_t s) {
+  const dim3 grid((unsigned)((m.nx + 255) / 256), (unsigned)m.ny, (unsigned)m.nz);
+  const int32_t lo = (int32_t)m.lo, hi = (int32_t)m.hi;
+  if (m.dtype == 0)
+    hipLaunchKernelGGL(pack_oct8_kernel<uint8_t>, grid, dim3(256), 0, s, (const uint8_t*)m.data,
+                       m.nx, m.ny, m.nz, lo, hi, out);
+  else if (m.dtype == 1)
+    hipLaunchKernelGGL(pack_oct8_kernel<uint16_t>, grid, dim3(256), 0, s, (const uint16_t*)m.data,
+                       m.nx, m.ny, m.nz, lo, hi, out);
+  else if (m.dtype == 2)
+    hipLaunchKernelGGL(pack_oct8_kernel<int16_t>, grid, dim3(256), 0, s, (const int16_t*)m.data,
+                       m.nx, m.ny, m.nz, lo, hi, out);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
 hipError_t launch_pack_octs(const VolumeDesc& m, uint4* out, hipStream_t s) {
   const dim3 grid((unsigned)((m.nx + 255) / 256), (unsigned)m.ny, (unsigned)m.nz);
   const int32_t lo = (int32_t)m.lo, hi = (int32_t)m.hi;
@@ -164,7 +202,7 @@ struct HardArgs {
 // scratch) so that two of them, 8 waves per SIMD, share a CU next to two
 // 64 KiB LDS histograms; the sweep waits on its gathers and gains from the
 // extra waves.  Smaller workgroups keep their registers.
-template <bool CLAMP, bool PACKED, int NT>
+template <bool CLAMP, bool PACKED, bool OCT8, int NT>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT == 1024 ? 8 : 1)))
 void hist_hard_kernel(HardArgs a) {
   extern __shared__ uint32_t lds_hist[];
@@ -176,28 +214,37 @@ void hist_hard_kernel(HardArgs a) {
   int64_t Mq[12];
   const bool ok = quantize_transform(a.transforms + 12 * (size_t)t, Mq);
   __syncthreads();
-  if (ok) sweep_hard<CLAMP, PACKED, NT / 64>(a.geom, Mq, a.chunks, chunk, lds_hist);
+  if (ok) sweep_hard<CLAMP, PACKED, OCT8, NT / 64>(a.geom, Mq, a.chunks, chunk, lds_hist);
   __syncthreads();
   if (ok) flush_hist<PACKED, NT>(lds_hist, B, a.hist + (size_t)t * B * B, false);
 }
 
-template <bool CLAMP, bool PACKED, int NT>
+template <bool CLAMP, bool PACKED, bool OCT8, int NT>
 static hipError_t launch_variant(const HardArgs& a, int n, size_t lds, hipStream_t s) {
-  hipLaunchKernelGGL((hist_hard_kernel<CLAMP, PACKED, NT>), dim3((unsigned)(n * a.chunks)),
+  hipLaunchKernelGGL((hist_hard_kernel<CLAMP, PACKED, OCT8, NT>), dim3((unsigned)(n * a.chunks)),
                      dim3(NT), lds, s, a);
   return hipGetLastError();
+}
+
+template <bool OCT8, int NT>
+static hipError_t launch_layout(const HardArgs& a, int n, bool clamp, bool packed, size_t lds,
+                                hipStream_t s) {
+  if (clamp)
+    return packed ? launch_variant<true, true, OCT8, NT>(a, n, lds, s)
+                  : launch_variant<true, false, OCT8, NT>(a, n, lds, s);
+  return packed ? launch_variant<false, true, OCT8, NT>(a, n, lds, s)
+                : launch_variant<false, false, OCT8, NT>(a, n, lds, s);
 }
 
 template <int NT>
 static hipError_t launch_nt(const HardArgs& a, int n, bool clamp, bool packed, size_t lds,
                             hipStream_t s) {
-  if (clamp)
-    return packed ? launch_variant<true, true, NT>(a, n, lds, s) : launch_variant<true, false, NT>(a, n, lds, s);
-  return packed ? launch_variant<false, true, NT>(a, n, lds, s) : launch_variant<false, false, NT>(a, n, lds, s);
+  return a.geom.oct8 ? launch_layout<true, NT>(a, n, clamp, packed, lds, s)
+                     : launch_layout<false, NT>(a, n, clamp, packed, lds, s);
 }
 
 HardGeom make_hard_geom(const VolumeDesc& fixed, const VolumeDesc& moving, const uint8_t* fbins,
-                        const uint4* octs, int32_t bins) {
+                        const void* octs, int32_t bins) {
   HardGeom g;
   g.fbins = fbins;
   g.octs = octs;
@@ -207,7 +254,9 @@ HardGeom make_hard_geom(const VolumeDesc& fixed, const VolumeDesc& moving, const
   g.mnx = moving.nx;
   g.mny = moving.ny;
   g.mnz = moving.nz;
-  g.oct_bytes = (uint32_t)oct_volume_bytes(moving.nx, moving.ny, moving.nz);
+  g.oct8 = oct8_range(moving.lo, moving.hi) ? 1 : 0;
+  g.oct_bytes = (uint32_t)(g.oct8 ? oct8_volume_bytes(moving.nx, moving.ny, moving.nz)
+                                  : oct_volume_bytes(moving.nx, moving.ny, moving.nz));
   g.bins = bins;
   const uint32_t R = (uint32_t)((int32_t)moving.hi - (int32_t)moving.lo + 1);
   g.scale = ldexp((double)bins / (double)R, -48);
@@ -236,15 +285,16 @@ hipError_t launch_hist_hard(const HardLaunch& L, hipStream_t s) {
 template <int NT>
 static hipError_t allow_big_lds() {
   const int bytes = 160 * 1024;
-  hipError_t e;
-  if ((e = hipFuncSetAttribute((const void*)hist_hard_kernel<false, false, NT>,
-                               hipFuncAttributeMaxDynamicSharedMemorySize, bytes)) != hipSuccess) return e;
-  if ((e = hipFuncSetAttribute((const void*)hist_hard_kernel<true, false, NT>,
-                               hipFuncAttributeMaxDynamicSharedMemorySize, bytes)) != hipSuccess) return e;
-  if ((e = hipFuncSetAttribute((const void*)hist_hard_kernel<false, true, NT>,
-                               hipFuncAttributeMaxDynamicSharedMemorySize, bytes)) != hipSuccess) return e;
-  return hipFuncSetAttribute((const void*)hist_hard_kernel<true, true, NT>,
-                             hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  const void* fns[8] = {
+      (const void*)hist_hard_kernel<false, false, false, NT>, (const void*)hist_hard_kernel<true, false, false, NT>,
+      (const void*)hist_hard_kernel<false, true, false, NT>, (const void*)hist_hard_kernel<true, true, false, NT>,
+      (const void*)hist_hard_kernel<false, false, true, NT>, (const void*)hist_hard_kernel<true, false, true, NT>,
+      (const void*)hist_hard_kernel<false, true, true, NT>, (const void*)hist_hard_kernel<true, true, true, NT>};
+  for (const void* f : fns) {
+    const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 hipError_t configure_hard_kernels() {

@@ -101,19 +101,28 @@ __global__ void prep_moving_kernel(PairsArgs a, int64_t rows) {
     const size_t r00 = ((size_t)z * ny + y) * nx;
     const size_t r10 = r00 + (y + 1 < ny ? nx : 0);
     const size_t dz = z + 1 < nz ? (size_t)nx * ny : 0;
-    uint4* __restrict__ out = (uint4*)d.geom.octs + row * nx;
-    auto pair = [&](size_t base, int32_t x, int32_t x1) -> uint32_t {
-      return clamp_offset(load_int(d.moving, d.mdtype, base + x), d.mlo, d.mhi) |
-             (clamp_offset(load_int(d.moving, d.mdtype, base + x1), d.mlo, d.mhi) << 16);
-    };
-    for (int32_t x = lane; x < nx; x += 64) {
-      const int32_t x1 = x + 1 < nx ? x + 1 : nx - 1;
-      out[x] = make_uint4(pair(r00, x, x1), pair(r10, x, x1), pair(r00 + dz, x, x1), pair(r10 + dz, x, x1));
+    auto v = [&](size_t i) -> uint32_t { return clamp_offset(load_int(d.moving, d.mdtype, i), d.mlo, d.mhi); };
+    if (d.geom.oct8) {
+      // 8-bit corners: byte 4 dz + 2 dy + dx' (layout of pack_oct8_kernel)
+      uint2* __restrict__ out = (uint2*)d.geom.octs + row * nx;
+      for (int32_t x = lane; x < nx; x += 64) {
+        const int32_t x1 = x + 1 < nx ? x + 1 : nx - 1;
+        out[x] = make_uint2(v(r00 + x) | (v(r00 + x1) << 8) | (v(r10 + x) << 16) | (v(r10 + x1) << 24),
+                            v(r00 + dz + x) | (v(r00 + dz + x1) << 8) | (v(r10 + dz + x) << 16) |
+                                (v(r10 + dz + x1) << 24));
+      }
+    } else {
+      uint4* __restrict__ out = (uint4*)d.geom.octs + row * nx;
+      for (int32_t x = lane; x < nx; x += 64) {
+        const int32_t x1 = x + 1 < nx ? x + 1 : nx - 1;
+        out[x] = make_uint4(v(r00 + x) | (v(r00 + x1) << 16), v(r10 + x) | (v(r10 + x1) << 16),
+                            v(r00 + dz + x) | (v(r00 + dz + x1) << 16), v(r10 + dz + x) | (v(r10 + dz + x1) << 16));
+      }
     }
   });
 }
 
-template <bool CLAMP, bool PACKED, int NT>
+template <bool CLAMP, bool PACKED, bool OCT8, int NT>
 __global__ __launch_bounds__(NT) void hist_pairs_kernel(PairsArgs a) {
   extern __shared__ uint32_t lds_hist[];
   __shared__ int64_t item_sh;
@@ -136,7 +145,7 @@ __global__ __launch_bounds__(NT) void hist_pairs_kernel(PairsArgs a) {
     const int64_t t = a.t_base[p] + tl;
     int64_t Mq[12];
     const bool ok = quantize_transform(a.transforms + 12 * t, Mq);
-    if (ok) sweep_hard<CLAMP, PACKED, NT / 64>(d.geom, Mq, d.chunks, chunk, lds_hist);
+    if (ok) sweep_hard<CLAMP, PACKED, OCT8, NT / 64>(d.geom, Mq, d.chunks, chunk, lds_hist);
     __syncthreads();
     if (ok) flush_hist<PACKED, NT>(lds_hist, B, a.hist + (size_t)t * B * B, true);
     __syncthreads();
@@ -167,11 +176,11 @@ hipError_t launch_pairs_prep(const PairsLaunch& L, hipStream_t s) {
 
 constexpr int kPairsBlock = 512;
 
-template <bool CLAMP, bool PACKED>
+template <bool CLAMP, bool PACKED, bool OCT8>
 static hipError_t pairs_variant(const PairsLaunch& L, hipStream_t s) {
   const int B = L.args.bins;
   const size_t lds = PACKED ? (((size_t)B * B + 1) / 2) * 4 : (size_t)B * B * 4;
-  const void* fn = (const void*)hist_pairs_kernel<CLAMP, PACKED, kPairsBlock>;
+  const void* fn = (const void*)hist_pairs_kernel<CLAMP, PACKED, OCT8, kPairsBlock>;
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
   if (e != hipSuccess) return e;
   int per_cu = 0;
@@ -180,15 +189,20 @@ static hipError_t pairs_variant(const PairsLaunch& L, hipStream_t s) {
   if (per_cu < 1) per_cu = 1;
   // every queue needs workgroups: a multiple of 8 (one share per XCD)
   const unsigned grid = (unsigned)(((per_cu * L.cu_count + 7) / 8) * 8);
-  hipLaunchKernelGGL((hist_pairs_kernel<CLAMP, PACKED, kPairsBlock>), dim3(grid), dim3(kPairsBlock),
+  hipLaunchKernelGGL((hist_pairs_kernel<CLAMP, PACKED, OCT8, kPairsBlock>), dim3(grid), dim3(kPairsBlock),
                      lds, s, L.args);
   return hipGetLastError();
 }
 
-hipError_t launch_pairs_hist(const PairsLaunch& L, hipStream_t s) {
+template <bool OCT8>
+static hipError_t pairs_layout(const PairsLaunch& L, hipStream_t s) {
   if (L.clamp)
-    return L.packed ? pairs_variant<true, true>(L, s) : pairs_variant<true, false>(L, s);
-  return L.packed ? pairs_variant<false, true>(L, s) : pairs_variant<false, false>(L, s);
+    return L.packed ? pairs_variant<true, true, OCT8>(L, s) : pairs_variant<true, false, OCT8>(L, s);
+  return L.packed ? pairs_variant<false, true, OCT8>(L, s) : pairs_variant<false, false, OCT8>(L, s);
+}
+
+hipError_t launch_pairs_hist(const PairsLaunch& L, hipStream_t s) {
+  return L.oct8 ? pairs_layout<true>(L, s) : pairs_layout<false>(L, s);
 }
 
 }  // namespace gemi

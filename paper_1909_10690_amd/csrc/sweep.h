@@ -10,6 +10,7 @@
 namespace gemi {
 
 typedef unsigned short ushort2_t __attribute__((ext_vector_type(2)));
+typedef unsigned int uint2_t __attribute__((ext_vector_type(2)));
 typedef unsigned int uint4_t __attribute__((ext_vector_type(4)));
 typedef __attribute__((address_space(3))) uint32_t lds_u32;
 
@@ -43,7 +44,9 @@ constexpr double kEdge = 1.0 / 536870912.0;  // 2^-29
 
 // Sweeps one slab of the fixed volume for one transform (Mq) into the
 // workgroup's LDS histogram.  NW waves share the slab's 4-row groups.
-template <bool CLAMP, bool PACKED, int NW>
+// OCT8: the oct volume holds 8-bit corners (one 64-bit gather), unpacked
+// into the 16-bit pairs of the x-lerp with byte permutes.
+template <bool CLAMP, bool PACKED, bool OCT8, int NW>
 __device__ __forceinline__ void sweep_hard(const HardGeom& g, const int64_t* Mq, int32_t chunks,
                                            uint32_t chunk, uint32_t* lds_hist) {
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -83,8 +86,18 @@ __device__ __forceinline__ void sweep_hard(const HardGeom& g, const int64_t* Mq,
       const uint32_t ix = (uint32_t)(cx >> 32), iy = (uint32_t)(cy >> 32), iz = (uint32_t)(cz >> 32);
       const uint32_t fx = (uint32_t)cx, fy = (uint32_t)cy, fz = (uint32_t)cz;
       // rows iz ny + iy < ny nz <= 2^24 and edges <= 4096: 24-bit operands
-      const uint32_t off = mad24(mad24(iz, NY, iy), MX, ix) << 4;
-      const uint4_t oc = __builtin_amdgcn_raw_buffer_load_b128(rsrc, off, 0, 0);
+      const uint32_t vox = mad24(mad24(iz, NY, iy), MX, ix);
+      uint4_t oc;
+      if (OCT8) {
+        // bytes (x,y), (x1,y), (x,y1), (x1,y1) of slice z in .x, of z1 in .y
+        const uint2_t d = __builtin_amdgcn_raw_buffer_load_b64(rsrc, vox << 3, 0, 0);
+        oc.x = __builtin_amdgcn_perm(0u, d.x, 0x0C010C00u);  // (b0, b1) as 16-bit halves
+        oc.y = __builtin_amdgcn_perm(0u, d.x, 0x0C030C02u);  // (b2, b3)
+        oc.z = __builtin_amdgcn_perm(0u, d.y, 0x0C010C00u);
+        oc.w = __builtin_amdgcn_perm(0u, d.y, 0x0C030C02u);
+      } else {
+        oc = __builtin_amdgcn_raw_buffer_load_b128(rsrc, vox << 4, 0, 0);
+      }
       const uint32_t fb = g.fbins[xo];
       // (65535 - wx) in the low half, wx in the high half
       const uint32_t wpack = (fx & 0xFFFF0000u) | ((fx >> 16) ^ 0xFFFFu);

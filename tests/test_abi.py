@@ -147,7 +147,11 @@ def test_workspace_size_layout():
     # B >= 16) and entropy, three compensated pairs of doubles
     part = a(5 * min(1024 // 5, 32 // 8) * 2 * 3 * 16)
     st, n = ws_size(vol(10, 11, 12), vol(9, 8, 7), 5, 32, 2)
-    # integer moving volume: oct volume, 16 bytes per voxel; histograms; N per transform
+    # moving range <= 256: oct volume of 8-bit corners, 8 bytes per voxel;
+    # histograms; N per transform
+    assert st == 0 and n == a(10 * 11 * 12) + a(9 * 8 * 7 * 8) + a(5 * 32 * 32 * 4) + a(5 * 8) + part
+    # a wider range: 16-bit corners, 16 bytes per voxel
+    st, n = ws_size(vol(10, 11, 12), vol(9, 8, 7, dtype=B.U16, lo=0.0, hi=4095.0), 5, 32, 2)
     assert st == 0 and n == a(10 * 11 * 12) + a(9 * 8 * 7 * 16) + a(5 * 32 * 32 * 4) + a(5 * 8) + part
     octs = a(8 * 8 * 8 * 16)
     rowmap = a(3 * 256 * 4 + 4)   # occupied fixed-bin rows: used, row_of_slot, slot_of_row, n_slots
@@ -205,7 +209,8 @@ def test_pairs_validation_and_layout():
     p2 = B.MiPair(vol(16, 4, 2), vol(5, 6, 7, dtype=B.U16, lo=0.0, hi=4095.0), FAKE, 0)
     st, n = pairs_ws([p1, p2], bins=32, n_q=2)
     assert st == 0 and n > 0
-    # per-pair fixed bins + oct volumes + 3 transforms' histograms are included
+    # per-pair fixed bins + oct volumes (16-bit corners: p2's range exceeds
+    # 256) + 3 transforms' histograms are included
     assert n >= 8 * 8 * 8 + 9 * 8 * 7 * 16 + 16 * 4 * 2 + 5 * 6 * 7 * 16 + 3 * 32 * 32 * 4
     bad = B.MiPair(vol(8, 8, 8), vol(dtype=B.F32, lo=0.0, hi=1.0), FAKE, 3)
     assert pairs_ws([p1, bad])[0] == B.MI_ERR_DTYPE
