@@ -29,6 +29,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "voxel-transform evals/s (warp+jointhist+MI) & MI-grad evals/s; % HBM roofline"
 HBM_PEAK_GBS = 8000.0
+VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12  # 256 CUs x 4 SIMD x 16 lanes per clock at 2.4 GHz
 PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "hist_hard_multimodal_traffic.txt")
 
 
@@ -44,9 +45,10 @@ def algorithmic_bytes_per_voxel_xform(fixed, moving, mats, bins) -> float:
             4.0 * bins * bins / fixed.size)
 
 
-def read_traffic(kernel_version: str):
-    """HBM bytes per launch from a committed rocprofv3 counter summary, if
-    it was taken on the current kernel build."""
+def read_profile(kernel_version: str, key: str):
+    """A figure of the committed rocprofv3 counter summary of the sweep (HBM
+    bytes per launch, VALU instructions per voxel-transform), if it was taken
+    on the current kernel build."""
     try:
         text = open(PROFILE_TRAFFIC).read()
     except OSError:
@@ -55,7 +57,7 @@ def read_traffic(kernel_version: str):
     if fields.get("kernel_version", "").strip() != kernel_version:
         return None
     try:
-        return float(fields["hbm_bytes_per_launch"])
+        return float(fields[key])
     except (KeyError, ValueError):
         return None
 
@@ -261,7 +263,9 @@ def main() -> int:
     k_avg_ms = k_ms / max(k_n, 1)
     balg = algorithmic_bytes_per_voxel_xform(fixed, moving, mats, bins)
     achieved = balg * vox_xf / (k_avg_ms * 1e-3) / 1e9
-    traffic = read_traffic(kernel_version())
+    kv = kernel_version()
+    traffic = read_profile(kv, "hbm_bytes_per_launch")
+    valu_per_vx = read_profile(kv, "valu_insts_per_voxel_xform")
     log(f"{value:.3e} voxel-xf/s, {ms_step:.2f} ms/step, hist kernel {k_avg_ms:.2f} ms, "
         f"reduce {r_ms / max(r_n, 1):.3f} ms")
 
@@ -280,6 +284,23 @@ def main() -> int:
                      "kernel": "hist_hard_kernel<uint16_t>", "kernel_ms": k_avg_ms,
                      "algorithmic_bytes_per_voxel_xform": balg},
     }
+
+    # LDS-atomic rate of the sweep (one 32-bit LDS add per counted voxel)
+    # against the measured peak of conflict-free LDS adds on this device
+    _, ov, _ = ctx.eval(F, Mv, tr, bins, q, workspace=ws)
+    atomics = float(ov.sum().item())
+    lds_peak = ctx.probe_lds_atomics()
+    lds_rate = atomics / (k_avg_ms * 1e-3)
+    result["lds_atomic"] = {"achieved": lds_rate, "peak": lds_peak, "unit": "lane-atomics/s",
+                            "frac": lds_rate / lds_peak, "per_voxel_xform": atomics / vox_xf,
+                            "peak_source": "mi_probe_lds_atomics (conflict-free ds_add_u32, measured)"}
+    # VALU issue: wave64 VALU instructions per voxel-transform (committed
+    # SQ_INSTS_VALU summary of this kernel build) x 64 lanes, against
+    # 256 CUs x 64 lanes/clock x 2.4 GHz
+    if valu_per_vx is not None:
+        alu = valu_per_vx * vox_xf / (k_avg_ms * 1e-3)
+        result["alu"] = {"achieved": alu / 1e12, "peak": VALU_PEAK_TOPS, "unit": "T lane-ops/s",
+                         "frac": alu / 1e12 / VALU_PEAK_TOPS, "valu_per_voxel_xform": valu_per_vx}
 
     if args.calibrate_copy:
         nel = args.calibrate_copy * (1 << 20) // 4

@@ -205,6 +205,15 @@ int mi_tune(mi_context *ctx, const mi_volume *fixed, const mi_volume *moving,
 int mi_timing_enable(mi_context *ctx, int enable);
 int mi_timing_read(mi_context *ctx, int which, double *total_ms, int64_t *launches);
 
+/* Measurement probe (not part of the metric): the device's peak rate of
+ * conflict-free 32-bit LDS atomic adds, in lane-atomics per second, the
+ * ceiling for the LDS-atomic rate of the histogram sweeps.  Synchronous:
+ * launches a short kernel on `stream`, waits for it and times it with HIP
+ * events.  `scratch` is a device buffer of at least `scratch_bytes` >= 4 MiB
+ * (overwritten).  Errors: MI_ERR_NULL, MI_ERR_WORKSPACE, MI_ERR_HIP. */
+int mi_probe_lds_atomics(mi_context *ctx, void *scratch, size_t scratch_bytes, void *stream,
+                         double *lane_atomics_per_s);
+
 /* Static description of a status code (never NULL).  For MI_ERR_HIP the
  * text of the last HIP error seen by this thread is appended. */
 const char *mi_status_string(int status);

@@ -49,7 +49,7 @@ class MiPair(ctypes.Structure):
 
 EXPORTS = ["mi_create", "mi_destroy", "mi_workspace_size", "mi_eval", "mi_grad",
            "mi_pairs_workspace_size", "mi_eval_pairs", "mi_tune", "mi_timing_enable",
-           "mi_timing_read", "mi_status_string"]
+           "mi_timing_read", "mi_probe_lds_atomics", "mi_status_string"]
 
 _lib = None
 
@@ -76,6 +76,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.mi_tune.argtypes = [vp, P(MiVolume), P(MiVolume), vp, i32, i32, i32, vp, sz, vp]
     lib.mi_timing_enable.argtypes = [vp, ctypes.c_int]
     lib.mi_timing_read.argtypes = [vp, ctypes.c_int, dp, P(ctypes.c_int64)]
+    lib.mi_probe_lds_atomics.argtypes = [vp, vp, sz, vp, dp]
     lib.mi_status_string.argtypes = [ctypes.c_int]
     lib.mi_status_string.restype = ctypes.c_char_p
     for name in EXPORTS:
@@ -143,6 +144,14 @@ class Context:
         _check(self.lib.mi_create(ctypes.byref(h), device), "mi_create")
         self.handle = h
         self._ws = None
+
+    def probe_lds_atomics(self, stream=None) -> float:
+        """Measured peak rate of conflict-free LDS atomic adds (lane-atomics/s)."""
+        scratch = self.workspace(4 << 20)
+        rate = ctypes.c_double()
+        _check(self.lib.mi_probe_lds_atomics(self.handle, _ptr(scratch), scratch.numel(), self._stream(stream),
+                                              ctypes.byref(rate)), "mi_probe_lds_atomics")
+        return rate.value
 
     def close(self) -> None:
         if self.handle:

@@ -1068,4 +1068,35 @@ int mi_eval_pairs(mi_context* ctx, const mi_pair* pairs, int32_t n_pairs, int32_
   return graph_run(ctx, key, s, body);
 }
 
+int mi_probe_lds_atomics(mi_context* ctx, void* scratch, size_t scratch_bytes, void* stream,
+                         double* lane_atomics_per_s) {
+  if (!ctx || !scratch || !lane_atomics_per_s) return MI_ERR_NULL;
+  // one 1024-thread workgroup of 4 KiB output per CU slot, two per CU
+  const int32_t blocks = 2 * ctx->cu_count;
+  const size_t need = (size_t)blocks * 1024 * 4;
+  if (scratch_bytes < need || scratch_bytes < ((size_t)4 << 20)) return MI_ERR_WORKSPACE;
+  hipError_t e;
+  if ((e = hipSetDevice(ctx->device)) != hipSuccess) return hip_fail(e, "hipSetDevice");
+  hipStream_t s = (hipStream_t)stream;
+  const int32_t iters = 1 << 14;
+  hipEvent_t t0 = nullptr, t1 = nullptr;
+  if ((e = hipEventCreate(&t0)) != hipSuccess || (e = hipEventCreate(&t1)) != hipSuccess) {
+    if (t0) (void)hipEventDestroy(t0);
+    return hip_fail(e, "probe events");
+  }
+  float ms = 0.0f;
+  int st = MI_OK;
+  if ((e = launch_lds_atomic_probe((uint32_t*)scratch, blocks, iters, s)) != hipSuccess ||  // warm-up
+      (e = hipEventRecord(t0, s)) != hipSuccess ||
+      (e = launch_lds_atomic_probe((uint32_t*)scratch, blocks, iters, s)) != hipSuccess ||
+      (e = hipEventRecord(t1, s)) != hipSuccess || (e = hipEventSynchronize(t1)) != hipSuccess ||
+      (e = hipEventElapsedTime(&ms, t0, t1)) != hipSuccess)
+    st = hip_fail(e, "lds atomic probe");
+  (void)hipEventDestroy(t0);
+  (void)hipEventDestroy(t1);
+  if (st != MI_OK) return st;
+  *lane_atomics_per_s = (double)blocks * 1024.0 * iters / (ms * 1e-3);
+  return MI_OK;
+}
+
 }  // extern "C"

@@ -349,5 +349,6 @@ hipError_t launch_parzen_fwd(const ParzenLaunch& L, hipStream_t s);
 hipError_t launch_dmi_dp(const ParzenLaunch& L, const QList& q, hipStream_t s);
 hipError_t launch_parzen_bwd(const ParzenLaunch& L, hipStream_t s);
 hipError_t configure_kernels();
+hipError_t launch_lds_atomic_probe(uint32_t* out, int32_t blocks, int32_t iters, hipStream_t s);
 
 }  // namespace gemi

@@ -31,6 +31,34 @@ def test_library_exports_every_declared_symbol():
         assert hasattr(lib, name), name
 
 
+def header_signatures():
+    text = open(HEADER).read()
+    sigs = {}
+    for name, params in re.findall(r"^(?:int|const char \*)\s*(mi_\w+)\(([^)]*)\);", text, re.M | re.S):
+        sigs[name] = [p.strip() for p in params.replace("\n", " ").split(",") if p.strip()]
+    return sigs
+
+
+def test_binding_declares_argument_types_of_every_entry_point():
+    """Every entry point has ctypes argtypes matching its C parameters: a
+    pointer or size_t passed without them would travel as a 32-bit int and
+    reach the library truncated."""
+    import ctypes
+    lib = B.load()
+    sigs = header_signatures()
+    assert sorted(sigs) == sorted(B.EXPORTS)
+    for name, params in sigs.items():
+        at = getattr(lib, name).argtypes
+        assert at is not None, name
+        assert len(at) == len(params), (name, at, params)
+        for p, t in zip(params, at):
+            if "*" in p or "size_t" in p:
+                wide = t in (ctypes.c_void_p, ctypes.c_size_t, ctypes.c_char_p) or issubclass(t, ctypes._Pointer)
+                assert wide, (name, p, t)
+            else:
+                assert t in (ctypes.c_int, ctypes.c_int32), (name, p, t)
+
+
 def test_header_constants_match_binding():
     text = open(HEADER).read()
     consts = dict((k, int(v, 0)) for k, v in re.findall(r"#define (MI_\w+) \(?(-?\w+)\)?", text))

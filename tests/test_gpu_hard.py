@@ -184,3 +184,10 @@ def test_timing_counts_launches(ctx):
     assert n == 3 and ms > 0
     ms, n = ctx.timing_read(B.TIMER_HARD)
     assert n == 0
+
+
+def test_lds_atomic_probe(ctx):
+    """The measurement probe returns a plausible peak: at least 1e12 and at
+    most 256 CUs x 64 lanes x 2.4 GHz lane-atomics per second."""
+    rate = ctx.probe_lds_atomics()
+    assert 1e12 < rate < 256 * 64 * 2.4e9 * 1.01, rate
