@@ -191,3 +191,24 @@ def test_lds_atomic_probe(ctx):
     most 256 CUs x 64 lanes x 2.4 GHz lane-atomics per second."""
     rate = ctx.probe_lds_atomics()
     assert 1e12 < rate < 256 * 64 * 2.4e9 * 1.01, rate
+
+
+@pytest.mark.parametrize("bins,mrange", [(64, (0, 4095)), (256, (0, 255)), (200, (10, 3000))])
+def test_maximum_edge_and_ragged_rows(ctx, bins, mrange):
+    """Rows of 4096 voxels (the largest edge) with ragged y/z extents (3 and 2
+    rows: partial 4-row groups), 16-bit and 8-bit oct volumes, u32 and packed
+    LDS counters, under shifts and small rotations in the x-y plane."""
+    rng = np.random.default_rng(13 + bins)
+    fixed = inputs.random_volume(rng, (4096, 3, 2), np.uint16, 0, 4095)
+    moving = inputs.random_volume(rng, (4096, 3, 3), np.uint16, mrange[0], mrange[1])
+    mats = [T.translation((0, 0, 0)), T.translation((-37.25, 0.5, 0.25)), T.translation((4000.5, 1.0, 1.5))]
+    for th in (0.02, -0.05):
+        M = np.zeros((3, 4))
+        M[:2, :2] = [[np.cos(th), -np.sin(th)], [np.sin(th), np.cos(th)]]
+        M[2, 2] = 1.0
+        M[:, 3] = (3.5, 1.0, 0.5)
+        mats.append(M)
+    mats = np.stack(mats).reshape(-1, 12)
+    for flags in (0, 1):
+        args = (fixed, moving, (0, 4095), mrange, mats, bins, [1.0, 1.5], flags)
+        assert_parity(run_gpu(ctx, *args), run_oracle(*args), f"4096 rows bins={bins} flags={flags}")

@@ -198,3 +198,19 @@ def test_occupied_row_extremes(ctx, kind):
         assert_close(gpu_grad(ctx, f, m, (0, 4095), (0, 4095), mats, 256, [1.0, 1.3], flags),
                      oracle_grad(f, m, (0, 4095), (0, 4095), mats, 256, [1.0, 1.3], flags),
                      f"{kind} flags={flags}")
+
+
+def test_maximum_edge_and_ragged_rows(ctx):
+    """Parzen MI and gradient on 4096-voxel rows with 3 x 2 (fixed) and 3 x 3
+    (moving) ragged y/z extents, f32 and u16 moving volumes."""
+    rng = np.random.default_rng(21)
+    shape_f, shape_m = (4096, 3, 2), (4096, 3, 3)
+    mats = np.stack([T.translation((0.25, 0.5, 0.25)), T.translation((-11.5, 0.75, 0.5))]).reshape(-1, 12)
+    f = inputs.random_volume(rng, shape_f, np.float32, 0.0, 1.0)
+    m = inputs.random_volume(rng, shape_m, np.float32, 0.0, 1.0)
+    assert_close(gpu_grad(ctx, f, m, (0.0, 1.0), (0.0, 1.0), mats, 32, [1.0, 1.5], 1),
+                 oracle_grad(f, m, (0.0, 1.0), (0.0, 1.0), mats, 32, [1.0, 1.5], 1), "f32 4096 rows")
+    fu = inputs.random_volume(rng, shape_f, np.uint16, 0, 4095)
+    mu = inputs.random_volume(rng, shape_m, np.uint16, 0, 4095)
+    assert_close(gpu_grad(ctx, fu, mu, (0, 4095), (0, 4095), mats, 64, [1.0], 1),
+                 oracle_grad(fu, mu, (0, 4095), (0, 4095), mats, 64, [1.0], 1), "u16 4096 rows")
