@@ -187,12 +187,17 @@ constexpr size_t kStageBytes = 4u << 20;  // pinned staging for the pairs' table
 struct HardTune {
   int32_t block = 1024;
   int32_t slab_major = 1;
-  int32_t chunks = 0;  // 0 = planned per call
+  int32_t chunks = 0;   // 0 = planned per call
+  int32_t packed = -1;  // LDS counters: -1 by bins (packed above 128), 0 u32, 1 two 16-bit per word
 };
+
+// LDS counter layout of a launch: packed is forced above 128 bins (a u32
+// histogram would not fit), chosen by the tuning otherwise.
+bool use_packed(const HardTune& t, int32_t bins) { return bins > 128 || t.packed == 1; }
 
 // Problem class of the tuning cache.
 struct TuneKey {
-  int32_t v[10];
+  int32_t v[11];
   bool operator==(const TuneKey& o) const { return memcmp(v, o.v, sizeof v) == 0; }
 };
 
@@ -500,8 +505,8 @@ TuneKey tune_key(const mi_volume* f, const mi_volume* m, int32_t n, int32_t bins
   TuneKey k;
   int32_t nb = 0;
   while ((1 << nb) < n && nb < 30) ++nb;
-  const int32_t v[10] = {f->nx, f->ny, f->nz, m->nx, m->ny, m->nz, m->dtype, bins,
-                         (flags & MI_BOUNDARY_CLAMP) ? 1 : 0, nb};
+  const int32_t v[11] = {f->nx, f->ny, f->nz, m->nx, m->ny, m->nz, m->dtype, bins,
+                         (flags & MI_BOUNDARY_CLAMP) ? 1 : 0, nb, oct8_range(m->lo, m->hi) ? 1 : 0};
   memcpy(k.v, v, sizeof v);
   return k;
 }
@@ -515,7 +520,7 @@ HardTune tune_for(const mi_context* ctx, const mi_volume* f, const mi_volume* m,
 }
 
 // Cache file: one problem class per line,
-//   gemi-tune fnx fny fnz mnx mny mnz mdtype bins clamp nbucket block slab_major chunks
+//   gemi-tune fnx fny fnz mnx mny mnz mdtype bins clamp nbucket oct8 block slab_major chunks packed
 void load_tune_file(mi_context* c) {
   std::ifstream in(c->tune_file);
   std::string line;
@@ -526,10 +531,10 @@ void load_tune_file(mi_context* c) {
     HardTune t;
     if (!(ss >> tag) || tag != "gemi-tune") continue;
     bool ok = true;
-    for (int i = 0; i < 10 && ok; ++i) ok = static_cast<bool>(ss >> k.v[i]);
-    ok = ok && (ss >> t.block >> t.slab_major >> t.chunks);
+    for (int i = 0; i < 11 && ok; ++i) ok = static_cast<bool>(ss >> k.v[i]);
+    ok = ok && (ss >> t.block >> t.slab_major >> t.chunks >> t.packed);
     if (!ok || (t.block != 256 && t.block != 512 && t.block != 1024) || t.chunks < 0 ||
-        t.chunks % 8 != 0)
+        t.chunks % 8 != 0 || t.packed < -1 || t.packed > 1)
       continue;
     c->tuned.emplace_back(k, t);
   }
@@ -540,8 +545,9 @@ void save_tune_file(const mi_context* c) {
   std::ofstream out(c->tune_file, std::ios::trunc);
   for (const auto& e : c->tuned) {
     out << "gemi-tune";
-    for (int i = 0; i < 10; ++i) out << ' ' << e.first.v[i];
-    out << ' ' << e.second.block << ' ' << e.second.slab_major << ' ' << e.second.chunks << '\n';
+    for (int i = 0; i < 11; ++i) out << ' ' << e.first.v[i];
+    out << ' ' << e.second.block << ' ' << e.second.slab_major << ' ' << e.second.chunks << ' '
+        << e.second.packed << '\n';
   }
 }
 
@@ -628,7 +634,7 @@ int launch_hard_hist(mi_context* ctx, const mi_volume* fixed, const mi_volume* m
   H.n = n;
   H.bins = bins;
   H.clamp = (flags & MI_BOUNDARY_CLAMP) ? 1 : 0;
-  H.packed = bins > 128 ? 1 : 0;
+  H.packed = use_packed(tune, bins) ? 1 : 0;
   H.block = tune.block;
   H.slab_major = tune.slab_major;
   H.chunks = plan_chunks(ctx, fixed, moving, n, H.packed != 0, tune);
@@ -790,8 +796,12 @@ int mi_tune(mi_context* ctx, const mi_volume* fixed, const mi_volume* moving,
   HardTune best = ctx->hard_default;
   float best_ms = 3.4e38f;
   HardTune base = ctx->hard_default;
-  base.chunks = plan_chunks(ctx, fixed, moving, n, bins > 128, base);
+  base.chunks = plan_chunks(ctx, fixed, moving, n, use_packed(base, bins), base);
   const int32_t chunk_opts[3] = {base.chunks / 2, base.chunks, base.chunks * 2};
+  // LDS counter layouts: u32 or packed 16-bit pairs (only packed fits above 128 bins)
+  const int32_t n_layouts = bins > 128 ? 1 : 2;
+  const int32_t layouts[2] = {bins > 128 ? 1 : 0, 1};
+  for (int32_t li = 0; li < n_layouts; ++li)
   for (int32_t block : {256, 512, 1024}) {
     for (int32_t order : {1, 0}) {
       for (int32_t c : chunk_opts) {
@@ -800,6 +810,7 @@ int mi_tune(mi_context* ctx, const mi_volume* fixed, const mi_volume* moving,
         cand.block = block;
         cand.slab_major = order;
         cand.chunks = ((c < 8 ? 8 : c) + 7) / 8 * 8;
+        cand.packed = layouts[li];
         float total = 0;
         for (int rep = 0; rep < 3 && st == MI_OK; ++rep) {
           if ((e = hipEventRecord(t0, s)) != hipSuccess) { st = hip_fail(e, "tune"); break; }

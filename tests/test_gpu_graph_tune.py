@@ -117,7 +117,9 @@ def test_tune_keeps_results_and_writes_cache(tmp_path):
         lines = [l for l in path.read_text().splitlines() if l.startswith("gemi-tune")]
         assert len(lines) == 1
         fields = lines[0].split()
-        assert fields[1:4] == ["96", "80", "48"] and fields[11] in ("256", "512", "1024")
+        # key: 10 shape/bins/boundary/batch fields + oct8; then block, order, chunks, LDS layout
+        assert fields[1:4] == ["96", "80", "48"] and fields[12] in ("256", "512", "1024")
+        assert fields[15] in ("0", "1")
         ctx.close()
         ctx2 = B.Context(0)   # reads the cache file
         again, _, _ = ctx2.eval(F, M, tr, 128, c["q"])
