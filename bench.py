@@ -210,9 +210,13 @@ def main() -> int:
                     help="minimum wall time of the CPU-oracle sample")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle leg")
     ap.add_argument("--no-extras", action="store_true", help="skip the plain-path and gradient legs")
-    ap.add_argument("--pairs", action="store_true", help="also time the 256 uneven pairs in one launch")
+    ap.add_argument("--pairs", action="store_true",
+                    help="time the 256 uneven pairs in one launch even with --no-extras")
     ap.add_argument("--register", action="store_true",
-                    help="also run the 200-iteration CT/MR registration (512x512x300 vs 256^3, 256 bins)")
+                    help="run the 200-iteration CT/MR registration (512x512x300 vs 256^3, 256 bins) "
+                         "even with --no-extras")
+    ap.add_argument("--no-pairs", action="store_true", help="skip the uneven-pairs leg")
+    ap.add_argument("--no-register", action="store_true", help="skip the registration leg")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="also run an elementwise copy of MIB MiB (read + write), the reference "
                          "kernel for scaling HBM byte counters")
@@ -333,9 +337,9 @@ def main() -> int:
     if not args.no_extras:
         result["mi_grad"] = grad_leg(ctx, B, inputs, dev, args)
 
-    if args.pairs:
+    if (args.pairs or not args.no_extras) and not args.no_pairs:
         result["pairs"] = pairs_leg(ctx, B, inputs, dev)
-    if args.register:
+    if (args.register or not args.no_extras) and not args.no_register:
         result["register"] = register_leg(ctx, B, inputs, dev)
 
     if not args.no_cpu:

@@ -107,6 +107,15 @@ extern "C" {
  * pointers may change between replays (e.g. transforms updated in place);
  * the context keeps the 16 most recent graphs. */
 #define MI_USE_GRAPH 0x1000
+/* The caller asserts that fixed, moving, bins, the boundary flag and the
+ * workspace are those of the previous call on this context that prepared
+ * them (same path: hard or Parzen), and that neither the volumes' contents
+ * nor the workspace have changed since: the per-call preparation (fixed
+ * binning, moving gather volume, occupied-row map) already in the workspace
+ * is reused.  The library still compares the arguments with its record of
+ * the last preparation and prepares again when they differ; it cannot see
+ * changed contents.  For loops over one volume pair (registration). */
+#define MI_VOLUMES_UNCHANGED 0x2000
 
 #define MI_MAX_Q 16
 #define MI_MAX_EDGE 4096

@@ -91,7 +91,7 @@ int check_moving(const mi_volume* m, bool need_integer) {
 }
 
 constexpr int32_t kKnownFlags =
-    MI_BOUNDARY_CLAMP | MI_TSALLIS_PSEUDOADDITIVE | MI_HIST_PARZEN | MI_USE_GRAPH;
+    MI_BOUNDARY_CLAMP | MI_TSALLIS_PSEUDOADDITIVE | MI_HIST_PARZEN | MI_USE_GRAPH | MI_VOLUMES_UNCHANGED;
 
 int check_common(const mi_volume* f, const mi_volume* m, int32_t n, int32_t bins, const double* q,
                  int32_t n_q, int32_t flags, bool parzen) {
@@ -116,9 +116,10 @@ int check_common(const mi_volume* f, const mi_volume* m, int32_t n, int32_t bins
 //                volume [mnz+1][mny][mnx] (float moving volume),
 //                occupied-row map, table f64[n][B][B], count u64[n]
 //                MI partial sums (reduce_part_bytes)
-//   Parzen grad: + dMI/dp tables f32[n][n_q][B][B]
+//   Parzen grad: + table marginals f64[n][2B], dMI/dp tables f32[n][n_q][B][B]
 struct Layout {
-  size_t fbins = 0, gvol = 0, hist = 0, rowmap = 0, table = 0, count = 0, part = 0, gtab = 0, total = 0;
+  size_t fbins = 0, gvol = 0, hist = 0, rowmap = 0, table = 0, count = 0, part = 0, marg = 0, gtab = 0,
+         total = 0;
 };
 
 
@@ -150,6 +151,8 @@ Layout layout(const mi_volume* f, const mi_volume* m, int32_t n, int32_t bins, i
     L.part = off;
     off += align256(reduce_part_bytes(n, bins, n_q));
     if (grad) {
+      L.marg = off;
+      off += align256(16 * (size_t)bins * n);
       L.gtab = off;
       off += align256(bb * 4 * (size_t)n * n_q);
     }
@@ -209,6 +212,7 @@ struct GraphEntry {
 constexpr size_t kMaxGraphs = 16;
 
 struct mi_context {
+  std::vector<uint64_t> last_prep;  // path, workspace, volumes and bins of the last preparation
   void* stage = nullptr;            // pinned host buffer, kStageBytes
   hipEvent_t stage_done = nullptr;  // recorded after the last copy out of `stage`
   bool stage_pending = false;
@@ -224,6 +228,27 @@ struct mi_context {
 };
 
 namespace {
+
+// Key of a per-call preparation (path, workspace, both volumes, bins).
+std::vector<uint64_t> prep_key(int path, const void* ws, const mi_volume* f, const mi_volume* m, int32_t bins) {
+  std::vector<uint64_t> k = {(uint64_t)path, (uint64_t)(uintptr_t)ws, (uint64_t)bins};
+  for (const mi_volume* v : {f, m}) {
+    uint64_t lo, hi;
+    memcpy(&lo, &v->lo, 8);
+    memcpy(&hi, &v->hi, 8);
+    k.insert(k.end(), {(uint64_t)(uintptr_t)v->data, (uint64_t)v->nx, (uint64_t)v->ny, (uint64_t)v->nz,
+                       (uint64_t)v->dtype, lo, hi});
+  }
+  return k;
+}
+
+// True when the caller allows reuse and the workspace already holds this
+// preparation; otherwise records the preparation about to be made.
+bool reuse_prep(mi_context* ctx, int32_t flags, std::vector<uint64_t> key) {
+  if ((flags & MI_VOLUMES_UNCHANGED) && key == ctx->last_prep) return true;
+  ctx->last_prep = std::move(key);
+  return false;
+}
 
 // Brackets one kernel launch with timing events when timing is enabled.
 struct TimedLaunch {
@@ -312,14 +337,16 @@ int run_parzen(mi_context* ctx, const mi_volume* fixed, const mi_volume* moving,
                const Layout& L, hipStream_t s) {
   hipError_t e;
   uint8_t* fb = (uint8_t*)(ws + L.fbins);
-  if ((e = launch_prebin_fixed(desc(fixed), bins, fb, s)) != hipSuccess) return hip_fail(e, "prebin");
   RowMap* rows = (RowMap*)(ws + L.rowmap);
-  if ((e = launch_row_map(fb, voxels(fixed), bins, rows, s)) != hipSuccess) return hip_fail(e, "row map");
   const bool fq = moving->dtype == MI_F32;
   void* gvol = ws + L.gvol;
-  e = fq ? launch_pack_quads_f32(desc(moving), (float4*)gvol, s)
-         : launch_pack_octs(desc(moving), (uint4*)gvol, s);
-  if (e != hipSuccess) return hip_fail(e, "pack");
+  if (!reuse_prep(ctx, flags, prep_key(2, ws, fixed, moving, bins))) {
+    if ((e = launch_prebin_fixed(desc(fixed), bins, fb, s)) != hipSuccess) return hip_fail(e, "prebin");
+    if ((e = launch_row_map(fb, voxels(fixed), bins, rows, s)) != hipSuccess) return hip_fail(e, "row map");
+    e = fq ? launch_pack_quads_f32(desc(moving), (float4*)gvol, s)
+           : launch_pack_octs(desc(moving), (uint4*)gvol, s);
+    if (e != hipSuccess) return hip_fail(e, "pack");
+  }
   const size_t bb = (size_t)bins * bins;
   double* table = (double*)(ws + L.table);
   uint64_t* count = (uint64_t*)(ws + L.count);
@@ -388,6 +415,8 @@ int run_parzen(mi_context* ctx, const mi_volume* fixed, const mi_volume* moving,
   R.table = table;
   R.count = count;
   R.part = (double*)(ws + L.part);
+  R.marg_out = grad_out ? (double*)(ws + L.marg) : nullptr;
+  P.args.marg = R.marg_out;
   R.transforms = transforms;
   R.n = n;
   R.bins = bins;
@@ -617,7 +646,7 @@ int launch_hard_hist(mi_context* ctx, const mi_volume* fixed, const mi_volume* m
   uint8_t* fb = (uint8_t*)(ws + L.fbins);
   void* octs = ws + L.gvol;
   const size_t bb = (size_t)bins * bins;
-  if (prepare) {
+  if (prepare && !reuse_prep(ctx, flags, prep_key(1, ws, fixed, moving, bins))) {
     if ((e = launch_prebin_fixed(desc(fixed), bins, fb, s)) != hipSuccess) return hip_fail(e, "prebin");
     e = oct8_range(moving->lo, moving->hi) ? launch_pack_oct8(desc(moving), (uint2*)octs, s)
                                            : launch_pack_octs(desc(moving), (uint4*)octs, s);

@@ -238,6 +238,12 @@ inline size_t reduce_part_bytes(int64_t n, int32_t bins, int32_t n_q) {
   return (size_t)n * reduce_splits(bins, n) * n_q * 3 * 16;
 }
 
+// Rows [r0, r1) of slice s of a B-row table split into S slices.
+__host__ __device__ inline void slice_rows(int B, int S, int s, int& r0, int& r1) {
+  r0 = (int)(((int64_t)B * s) / S);
+  r1 = (int)(((int64_t)B * (s + 1)) / S);
+}
+
 // Slices with at most this many cells and marginals keep p and ln p in LDS.
 constexpr int kMaxSliceCells = 2304;
 
@@ -249,6 +255,7 @@ struct ReduceLaunch {
   const double* transforms;
   int32_t n, bins;
   int32_t splits;        // reduce_splits(bins, n), set by launch_mi_reduce
+  double* marg_out;      // [n][2B] row then column marginals (masses), or NULL
   QList q;
   double* mi_out;        // [n][n_q]
   uint64_t* overlap_out; // [n] or NULL
@@ -275,6 +282,7 @@ struct ParzenArgs {
   double* table;       // [n][B][B] forward masses (fp64)
   uint64_t* count;     // [n] voxels that took part
   const float* gtab;   // [n][n_q][B][B] d MI / d p
+  const double* marg;  // [n][2B] row then column marginals of the table (from the reduction)
   double* grad;        // [n][n_q][12]
   int32_t fnx, fny, fnz;
   int32_t mnx, mny, mnz;
@@ -288,9 +296,6 @@ struct ParzenArgs {
 constexpr int kParzenQGroup = 2;  // entropies per backward sweep
 constexpr int kHotCopies = 4;     // forward: LDS copies of the background row (slot 0)
 
-// Batches of at most this many transforms build each dMI/dp table with one
-// 1024-thread workgroup instead of a 256-thread one.
-constexpr int kFewTransforms = 256;
 
 struct ParzenLaunch {
   ParzenArgs args;

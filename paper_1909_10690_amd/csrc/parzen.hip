@@ -334,34 +334,33 @@ __global__ __launch_bounds__(NT) void parzen_fwd_kernel(ParzenArgs a) {
 //   Tsallis additive  G = q/(q-1) * (p^(q-1) - p_m^(q-1))
 //   Tsallis pseudo    G = q/(q-1) * (p^(q-1) - (1 + (1-q) S_q(F)) p_m^(q-1))
 // and G = 0 where p = 0 (no voxel there has a non-zero B-spline slope).
-// NT threads per transform: 1024 for small batches (see kFewTransforms).
-template <int NT>
-__global__ __launch_bounds__(NT) void dmi_dp_kernel(ParzenArgs a, QList ql) {
+// One workgroup per (transform, row slice), sliced like the MI reduction:
+// the marginals come from the reduction (a.marg), so a slice reads only its
+// own rows of the table.  Per entropy the column terms ln p_m (Shannon) or
+// fac p_m^(q-1) (Tsallis) are formed once per workgroup.
+__global__ __launch_bounds__(256) void dmi_dp_kernel(ParzenArgs a, QList ql, int32_t S) {
   const int B = a.bins;
   const size_t BB = (size_t)B * B;
-  const int t = blockIdx.x;
+  const int t = blockIdx.x / S, sl = blockIdx.x - t * S;
+  int r0, r1;
+  slice_rows(B, S, sl, r0, r1);
   __shared__ double pm[256], pf[256], cterm[256];
-  __shared__ double red[NT];
+  __shared__ double red[256];
   const double* __restrict__ h = a.table + (size_t)t * BB;
   float* __restrict__ G = (float*)a.gtab + (size_t)t * ql.n * BB;
   int64_t Mq[12];
   const bool ok = quantize_transform(a.transforms + 12 * (size_t)t, Mq);
   const double N = (double)a.count[t];
   if (!ok || !(N > 0)) {
-    for (size_t e = threadIdx.x; e < BB * ql.n; e += NT) G[e] = 0.0f;
+    for (int iq = 0; iq < ql.n; ++iq)
+      for (int e = r0 * B + threadIdx.x; e < r1 * B; e += 256) G[(size_t)iq * BB + e] = 0.0f;
     return;
   }
   const double invN = 1.0 / N;
-  // marginals: rows by threads [0, B), columns by threads [B, 2B)
-  for (int i = threadIdx.x; i < 2 * B; i += NT) {
-    double sum = 0;
-    if (i < B) {
-      for (int k = 0; k < B; ++k) sum += h[(size_t)i * B + k];
-      pf[i] = sum * invN;
-    } else {
-      for (int k = 0; k < B; ++k) sum += h[(size_t)k * B + (i - B)];
-      pm[i - B] = sum * invN;
-    }
+  const double* __restrict__ mg = a.marg + (size_t)t * 2 * B;
+  for (int i = threadIdx.x; i < B; i += 256) {
+    pf[i] = mg[i] * invN;
+    pm[i] = mg[B + i] * invN;
   }
   __syncthreads();
   for (int iq = 0; iq < ql.n; ++iq) {
@@ -370,23 +369,22 @@ __global__ __launch_bounds__(NT) void dmi_dp_kernel(ParzenArgs a, QList ql) {
     if (q != 1.0 && ql.pseudo) {
       // S_q(F) = -sum p expm1((q-1) ln p) / (q-1)
       double part = 0;
-      for (int i = threadIdx.x; i < B; i += NT)
+      for (int i = threadIdx.x; i < B; i += 256)
         if (pf[i] > 0) part += pf[i] * expm1(e1 * log(pf[i]));
       red[threadIdx.x] = part;
       __syncthreads();
-      for (int w = NT / 2; w > 0; w >>= 1) {
+      for (int w = 128; w > 0; w >>= 1) {
         if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
         __syncthreads();
       }
       fac = 1.0 + (1.0 - q) * (-red[0] / e1);
       __syncthreads();
     }
-    // per column: ln p_m (Shannon) or fac p_m^(q-1) (Tsallis), once
-    for (int i = threadIdx.x; i < B; i += NT)
+    for (int i = threadIdx.x; i < B; i += 256)
       cterm[i] = pm[i] > 0 ? (q == 1.0 ? log(pm[i]) : fac * pow(pm[i], e1)) : 0.0;
     __syncthreads();
     float* __restrict__ Gq = G + (size_t)iq * BB;
-    for (size_t e = threadIdx.x; e < BB; e += NT) {
+    for (int e = r0 * B + threadIdx.x; e < r1 * B; e += 256) {
       const double hv = h[e];
       double g = 0.0;
       if (hv > 0) {
@@ -553,10 +551,8 @@ hipError_t launch_parzen_fwd(const ParzenLaunch& L, hipStream_t s) {
 }
 
 hipError_t launch_dmi_dp(const ParzenLaunch& L, const QList& q, hipStream_t s) {
-  if (L.args.n <= kFewTransforms)
-    hipLaunchKernelGGL(dmi_dp_kernel<1024>, dim3((unsigned)L.args.n), dim3(1024), 0, s, L.args, q);
-  else
-    hipLaunchKernelGGL(dmi_dp_kernel<256>, dim3((unsigned)L.args.n), dim3(256), 0, s, L.args, q);
+  const int32_t S = reduce_splits(L.args.bins, L.args.n);
+  hipLaunchKernelGGL(dmi_dp_kernel, dim3((unsigned)((int64_t)L.args.n * S)), dim3(256), 0, s, L.args, q, S);
   return hipGetLastError();
 }
 

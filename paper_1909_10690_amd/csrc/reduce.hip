@@ -44,12 +44,6 @@ __device__ __forceinline__ Comp comp_merge(Comp a, Comp b) {
   return r;
 }
 
-// Rows [r0, r1) of a B-row table split into S slices.
-__device__ __forceinline__ void slice_rows(int B, int S, int s, int& r0, int& r1) {
-  r0 = (int)(((int64_t)B * s) / S);
-  r1 = (int)(((int64_t)B * (s + 1)) / S);
-}
-
 // N[t] += the counts of the slice's rows (count zeroed beforehand).
 __global__ __launch_bounds__(kBlock) void hist_count_kernel(const uint32_t* __restrict__ hist, int B,
                                                             int S, uint64_t* __restrict__ count) {
@@ -111,7 +105,13 @@ __global__ __launch_bounds__(kBlock) void mi_partial_kernel(ReduceLaunch L) {
       o.c = __shfl_xor(a.c, off, 64);
       a = comp_merge(a, o);
     }
-    if (sub == 0 && line < 2 * R) marg[line] = a.s + a.c;
+    if (sub == 0 && line < 2 * R) {
+      marg[line] = a.s + a.c;
+      if (L.marg_out) {
+        const int i = line < R ? r0 + line : B + r0 + (line - R);
+        L.marg_out[(size_t)t * 2 * B + i] = a.s + a.c;
+      }
+    }
   }
   __syncthreads();
 

@@ -123,10 +123,14 @@ def register(gctx: B.Context, fixed: B.Volume, moving: B.Volume, geom: Geometry,
     m = np.asarray(state.m, dtype=np.float64)
     v = np.asarray(state.v, dtype=np.float64)
     J = geom.J
+    first = state.step
     while state.step < steps:
         pa = decomposed_to_affine(d) if dec else d
         M = geom.matrices(torch.as_tensor(pa, dtype=torch.float64, device=dev).reshape(1, 12))
-        mi, gM = gctx.grad(fixed, moving, M, bins, q, flags=flags, workspace=workspace)
+        # the volumes and workspace stay the same over the loop: after the
+        # first call the library reuses their preparation
+        reuse = B.VOLUMES_UNCHANGED if state.step > first else 0
+        mi, gM = gctx.grad(fixed, moving, M, bins, q, flags=flags | reuse, workspace=workspace)
         gp = (gM[0] @ J).cpu().numpy()          # [n_q][12] d MI_q / d (A, t)
         if dec:
             gp = gp @ decomposed_jacobian(d)    # d MI_q / d (angles, log-scales, shears, t)

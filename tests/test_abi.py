@@ -186,7 +186,9 @@ def test_workspace_size_layout():
     st, n = ws_size(vol(10, 11, 12), vol(), 5, 32, 2, B.HIST_PARZEN)
     assert st == 0 and n == a(1320) + octs + rowmap + a(5 * 32 * 32 * 8) + a(5 * 8) + part
     st, n = ws_size(vol(10, 11, 12), vol(), 5, 32, 2, 0, 1)
-    assert st == 0 and n == a(1320) + octs + rowmap + a(5 * 32 * 32 * 8) + a(5 * 8) + part + a(5 * 2 * 32 * 32 * 4)
+    # gradient: + the table marginals f64[n][2B] + dMI/dp tables f32[n][n_q][B][B]
+    assert st == 0 and n == (a(1320) + octs + rowmap + a(5 * 32 * 32 * 8) + a(5 * 8) + part + a(5 * 2 * 32 * 8)
+                             + a(5 * 2 * 32 * 32 * 4))
     # a float moving volume keeps fp32 quads: 16 bytes per voxel, one extra slice
     st, n = ws_size(vol(10, 11, 12), vol(dtype=B.F32, lo=0.0, hi=1.0), 5, 32, 2, B.HIST_PARZEN)
     assert st == 0 and n == a(1320) + a(8 * 8 * 9 * 16) + rowmap + a(5 * 32 * 32 * 8) + a(5 * 8) + part
@@ -213,7 +215,8 @@ def test_timing_and_pairs_null_checks():
 def test_graph_flag_accepted_and_unknown_bits_rejected():
     assert call_eval(vol(), vol(), flags=B.USE_GRAPH) == B.MI_ERR_NULL
     assert call_eval(vol(), vol(), flags=B.USE_GRAPH | B.HIST_PARZEN) == B.MI_ERR_NULL
-    assert call_eval(vol(), vol(), flags=0x2000) == B.MI_ERR_FLAGS
+    assert call_eval(vol(), vol(), flags=B.VOLUMES_UNCHANGED | B.HIST_PARZEN) == B.MI_ERR_NULL
+    assert call_eval(vol(), vol(), flags=0x4000) == B.MI_ERR_FLAGS
 
 
 def test_tune_validation():

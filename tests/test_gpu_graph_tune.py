@@ -128,3 +128,36 @@ def test_tune_keeps_results_and_writes_cache(tmp_path):
         ctx2.close()
     finally:
         del os.environ["MI_TUNE_CACHE"]
+
+
+def test_volume_preparation_reuse(ctx):
+    """MI_VOLUMES_UNCHANGED reuses the workspace's prepared volumes: repeated
+    calls match a fresh call, and a call whose volumes differ from the last
+    preparation prepares again (the flag cannot make it wrong)."""
+    import torch
+    from paper_1909_10690_amd import binding as B
+    c = inputs.parzen_gradient(n=40, n_transforms=5)
+    rng = np.random.default_rng(8)
+    other = c["moving"][:, :, ::-1].copy()
+    F = B.Volume.from_numpy(c["fixed"], 0.0, 1.0)
+    M = B.Volume.from_numpy(c["moving"], 0.0, 1.0)
+    M2 = B.Volume.from_numpy(other, 0.0, 1.0)
+    tr = torch.from_numpy(c["transforms"]).cuda()
+    ws = torch.empty(ctx.workspace_size(F, M, 5, 32, 2, B.BOUNDARY_CLAMP | B.HIST_PARZEN, True),
+                     dtype=torch.uint8, device="cuda")
+    fl = B.BOUNDARY_CLAMP
+    ref, ref_g = ctx.grad(F, M, tr, 32, [1.0, 1.5], flags=fl, workspace=ws)
+    ref2, ref2_g = ctx.grad(F, M2, tr, 32, [1.0, 1.5], flags=fl, workspace=ws)
+    for vol, r, rg in ((M, ref, ref_g), (M, ref, ref_g), (M2, ref2, ref2_g), (M2, ref2, ref2_g), (M, ref, ref_g)):
+        mi, g = ctx.grad(F, vol, tr, 32, [1.0, 1.5], flags=fl | B.VOLUMES_UNCHANGED, workspace=ws)
+        torch.cuda.synchronize()
+        np.testing.assert_allclose(mi.cpu().numpy(), r.cpu().numpy(), rtol=1e-12, atol=1e-15)
+        np.testing.assert_allclose(g.cpu().numpy(), rg.cpu().numpy(), rtol=1e-9, atol=1e-12)
+    # hard path, same workspace: a different path prepares again
+    h, _, _ = ctx.eval(B.Volume.from_numpy((c["fixed"] * 255).astype(np.uint8), 0, 255),
+                       B.Volume.from_numpy((c["moving"] * 255).astype(np.uint8), 0, 255), tr, 32, [1.0],
+                       flags=B.VOLUMES_UNCHANGED, workspace=torch.empty(1 << 26, dtype=torch.uint8, device="cuda"))
+    h0, _, _ = ctx.eval(B.Volume.from_numpy((c["fixed"] * 255).astype(np.uint8), 0, 255),
+                        B.Volume.from_numpy((c["moving"] * 255).astype(np.uint8), 0, 255), tr, 32, [1.0])
+    torch.cuda.synchronize()
+    assert torch.equal(h, h0)
