@@ -114,7 +114,8 @@ extern "C" {
  * binning, moving gather volume, occupied-row map) already in the workspace
  * is reused.  The library still compares the arguments with its record of
  * the last preparation and prepares again when they differ; it cannot see
- * changed contents.  For loops over one volume pair (registration). */
+ * changed contents.  Ignored by calls that use MI_USE_GRAPH (a captured
+ * graph always prepares).  For loops over one volume pair (registration). */
 #define MI_VOLUMES_UNCHANGED 0x2000
 
 #define MI_MAX_Q 16

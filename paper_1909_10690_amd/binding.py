@@ -204,14 +204,21 @@ class Context:
         return mi, ov, hist
 
     def grad(self, fixed: Volume, moving: Volume, transforms: torch.Tensor, bins: int, q=(1.0,),
-             flags: int = BOUNDARY_CLAMP, workspace: torch.Tensor | None = None, stream=None):
-        """Parzen MI[n][n_q] and dMI/dM[n][n_q][12]."""
+             flags: int = BOUNDARY_CLAMP, workspace: torch.Tensor | None = None, stream=None,
+             out: tuple | None = None):
+        """Parzen MI[n][n_q] and dMI/dM[n][n_q][12] (into ``out`` = (mi, grad) if given)."""
         dev = fixed.tensor.device
         transforms = transforms.to(device=dev, dtype=torch.float64).reshape(-1, 12).contiguous()
         n = transforms.shape[0]
         qs, qp = _qarr(q)
-        mi = torch.empty((n, len(qs)), dtype=torch.float64, device=dev)
-        g = torch.empty((n, len(qs), 12), dtype=torch.float64, device=dev)
+        if out is not None:
+            mi, g = out
+            if mi.shape != (n, len(qs)) or g.shape != (n, len(qs), 12) or mi.dtype != torch.float64 \
+                    or g.dtype != torch.float64 or not mi.is_contiguous() or not g.is_contiguous():
+                raise ValueError("out must be contiguous float64 tensors [n][n_q] and [n][n_q][12]")
+        else:
+            mi = torch.empty((n, len(qs)), dtype=torch.float64, device=dev)
+            g = torch.empty((n, len(qs), 12), dtype=torch.float64, device=dev)
         if workspace is None:
             workspace = self.workspace(self.workspace_size(fixed, moving, n, bins, len(qs), flags | HIST_PARZEN, True))
         f, m = fixed.c(), moving.c()

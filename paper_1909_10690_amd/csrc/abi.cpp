@@ -924,14 +924,18 @@ int mi_eval(mi_context* ctx, const mi_volume* fixed, const mi_volume* moving,
   hipError_t e;
   if ((e = hipSetDevice(ctx->device)) != hipSuccess) return hip_fail(e, "hipSetDevice");
   char* ws = (char*)workspace;
+  // a graph replays whatever it captured, so it always captures the
+  // preparation: reuse is decided per call, graphs run later
+  const bool graph = use_graph(ctx, flags, s);
+  const int32_t run_flags = graph ? (flags & ~MI_VOLUMES_UNCHANGED) : flags;
   auto body = [&]() -> int {
     if (parzen)
-      return run_parzen(ctx, fixed, moving, transforms, n, bins, q, n_q, flags, mi_out, overlap_out,
+      return run_parzen(ctx, fixed, moving, transforms, n, bins, q, n_q, run_flags, mi_out, overlap_out,
                         nullptr, ws, L, s);
-    return run_hard(ctx, fixed, moving, transforms, n, bins, q, n_q, flags, mi_out, overlap_out,
+    return run_hard(ctx, fixed, moving, transforms, n, bins, q, n_q, run_flags, mi_out, overlap_out,
                     hist_out, ws, L, s, tune_for(ctx, fixed, moving, n, bins, flags));
   };
-  if (!use_graph(ctx, flags, s)) return body();
+  if (!graph) return body();
   std::vector<uint64_t> key = {1, (uint64_t)(uintptr_t)transforms, (uint64_t)n, (uint64_t)bins,
                                (uint64_t)flags, (uint64_t)(uintptr_t)mi_out,
                                (uint64_t)(uintptr_t)overlap_out, (uint64_t)(uintptr_t)hist_out,
@@ -939,7 +943,9 @@ int mi_eval(mi_context* ctx, const mi_volume* fixed, const mi_volume* moving,
   key_volume(key, fixed);
   key_volume(key, moving);
   key_q(key, q, n_q);
-  return graph_run(ctx, key, s, body);
+  st = graph_run(ctx, key, s, body);
+  ctx->last_prep = prep_key(parzen ? 2 : 1, ws, fixed, moving, bins);  // the graph prepared them
+  return st;
 }
 
 int mi_grad(mi_context* ctx, const mi_volume* fixed, const mi_volume* moving,
@@ -957,11 +963,13 @@ int mi_grad(mi_context* ctx, const mi_volume* fixed, const mi_volume* moving,
   hipError_t e;
   if ((e = hipSetDevice(ctx->device)) != hipSuccess) return hip_fail(e, "hipSetDevice");
   hipStream_t s = (hipStream_t)stream;
+  const bool graph = use_graph(ctx, flags, s);
+  const int32_t run_flags = graph ? (flags & ~MI_VOLUMES_UNCHANGED) : flags;  // as in mi_eval
   auto body = [&]() -> int {
-    return run_parzen(ctx, fixed, moving, transforms, n, bins, q, n_q, flags, mi_out, nullptr,
+    return run_parzen(ctx, fixed, moving, transforms, n, bins, q, n_q, run_flags, mi_out, nullptr,
                       grad_out, (char*)workspace, L, s);
   };
-  if (!use_graph(ctx, flags, s)) return body();
+  if (!graph) return body();
   std::vector<uint64_t> key = {2, (uint64_t)(uintptr_t)transforms, (uint64_t)n, (uint64_t)bins,
                                (uint64_t)flags, (uint64_t)(uintptr_t)mi_out,
                                (uint64_t)(uintptr_t)grad_out, (uint64_t)(uintptr_t)workspace,
@@ -969,7 +977,9 @@ int mi_grad(mi_context* ctx, const mi_volume* fixed, const mi_volume* moving,
   key_volume(key, fixed);
   key_volume(key, moving);
   key_q(key, q, n_q);
-  return graph_run(ctx, key, s, body);
+  st = graph_run(ctx, key, s, body);
+  ctx->last_prep = prep_key(2, workspace, fixed, moving, bins);  // the graph prepared them
+  return st;
 }
 
 int mi_pairs_workspace_size(const mi_pair* pairs, int32_t n_pairs, int32_t bins, int32_t n_q,
@@ -997,6 +1007,7 @@ int mi_eval_pairs(mi_context* ctx, const mi_pair* pairs, int32_t n_pairs, int32_
   hipError_t e;
   if ((e = hipSetDevice(ctx->device)) != hipSuccess) return hip_fail(e, "hipSetDevice");
   char* ws = (char*)workspace;
+  ctx->last_prep.clear();  // the pairs' layout overwrites any single-pair preparation
 
   // device tables: descriptors, row / transform / per-XCD item prefixes
   const int P = n_pairs;

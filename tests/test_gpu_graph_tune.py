@@ -161,3 +161,47 @@ def test_volume_preparation_reuse(ctx):
                         B.Volume.from_numpy((c["moving"] * 255).astype(np.uint8), 0, 255), tr, 32, [1.0])
     torch.cuda.synchronize()
     assert torch.equal(h, h0)
+
+
+def test_preparation_reuse_with_graphs(ctx):
+    """Graphs always capture the preparation, and a graph launch updates the
+    library's record of what the workspace holds, so interleaving graph
+    replays and eager calls on two volume pairs with MI_VOLUMES_UNCHANGED
+    stays correct."""
+    import torch
+    from paper_1909_10690_amd import binding as B
+    c = inputs.parzen_gradient(n=40, n_transforms=5)
+    F = B.Volume.from_numpy(c["fixed"], 0.0, 1.0)
+    MA = B.Volume.from_numpy(c["moving"], 0.0, 1.0)
+    MB = B.Volume.from_numpy(c["moving"][::-1].copy(), 0.0, 1.0)
+    tr = torch.from_numpy(c["transforms"]).cuda()
+    fl = B.BOUNDARY_CLAMP
+    ws = torch.empty(ctx.workspace_size(F, MA, 5, 32, 2, fl | B.HIST_PARZEN, True), dtype=torch.uint8,
+                     device="cuda")
+    refs = {}
+    for name, M in (("A", MA), ("B", MB)):
+        mi, _ = ctx.grad(F, M, tr, 32, [1.0, 1.5], flags=fl)
+        torch.cuda.synchronize()
+        refs[name] = mi.cpu().numpy()
+    stream = torch.cuda.Stream()
+    U, G = B.VOLUMES_UNCHANGED, B.USE_GRAPH
+    outs = {n: (torch.empty((5, 2), dtype=torch.float64, device="cuda"),
+                torch.empty((5, 2, 12), dtype=torch.float64, device="cuda")) for n in "AB"}
+
+    def call(name, flags, graph):
+        M = MA if name == "A" else MB
+        if graph:
+            with torch.cuda.stream(stream):
+                mi, _ = ctx.grad(F, M, tr, 32, [1.0, 1.5], flags=flags | G, workspace=ws,
+                                 out=outs[name])
+            stream.synchronize()
+        else:
+            mi, _ = ctx.grad(F, M, tr, 32, [1.0, 1.5], flags=flags, workspace=ws)
+            torch.cuda.synchronize()
+        np.testing.assert_allclose(mi.cpu().numpy(), refs[name], rtol=1e-12, atol=1e-15)
+
+    seq = [("A", fl, False), ("A", fl | U, True), ("B", fl, False), ("A", fl | U, True),
+           ("B", fl | U, False), ("B", fl | U, True), ("A", fl | U, False), ("A", fl | U, True),
+           ("B", fl | U, True), ("A", fl | U, False)]
+    for name, flags, graph in seq:
+        call(name, flags, graph)
