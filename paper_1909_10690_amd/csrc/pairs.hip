@@ -79,6 +79,21 @@ __global__ void prep_fixed_kernel(PairsArgs a, int64_t rows) {
     const int32_t nx = d.geom.fnx;
     uint8_t* __restrict__ out = (uint8_t*)d.geom.fbins + row * nx;
     const size_t base = (size_t)row * nx;
+    if (d.fdtype == 0 && (nx & 3) == 0 && ((uintptr_t)d.fixed & 3) == 0) {
+      // u8 rows of a multiple of 4 voxels, 4-byte aligned volume: four voxels
+      // per lane, 32-bit loads and stores
+      const uint32_t* __restrict__ src = (const uint32_t*)((const uint8_t*)d.fixed + base);
+      for (int32_t x4 = lane; x4 < nx / 4; x4 += 64) {
+        const uint32_t w = src[x4];
+        uint32_t o = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+          o |= fixed_bin_int((int32_t)((w >> (8 * k)) & 0xFFu), (int32_t)d.flo, (int32_t)d.fhi,
+                             (uint32_t)d.geom.bins, d.fdiv) << (8 * k);
+        ((uint32_t*)out)[x4] = o;
+      }
+      return;
+    }
     for (int32_t x = lane; x < nx; x += 64) {
       uint32_t b;
       if (d.fdtype == 3)
@@ -102,7 +117,33 @@ __global__ void prep_moving_kernel(PairsArgs a, int64_t rows) {
     const size_t r10 = r00 + (y + 1 < ny ? nx : 0);
     const size_t dz = z + 1 < nz ? (size_t)nx * ny : 0;
     auto v = [&](size_t i) -> uint32_t { return clamp_offset(load_int(d.moving, d.mdtype, i), d.mlo, d.mhi); };
-    if (d.geom.oct8) {
+    if (d.geom.oct8 && d.mdtype == 0 && (nx & 3) == 0 && ((uintptr_t)d.moving & 3) == 0) {
+      // u8 rows of a multiple of 4 voxels, 4-byte aligned volume: four voxels
+      // per lane; each source row is read as one dword plus its next
+      // (clamped) byte
+      uint4* __restrict__ out = (uint4*)((uint2*)d.geom.octs + row * nx);
+      const uint8_t* __restrict__ mv = (const uint8_t*)d.moving;
+      const size_t src[4] = {r00, r10, r00 + dz, r10 + dz};
+      for (int32_t x4 = lane; x4 < nx / 4; x4 += 64) {
+        const int32_t x0 = 4 * x4, xn = x0 + 4 < nx ? x0 + 4 : nx - 1;
+        uint32_t b[4][5];  // b[row][i] = clamped, offset value at x0 + i (i = 4: the neighbour)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const uint32_t w = *(const uint32_t*)(mv + src[r] + x0);
+#pragma unroll
+          for (int i = 0; i < 4; ++i) b[r][i] = clamp_offset((int32_t)((w >> (8 * i)) & 0xFFu), d.mlo, d.mhi);
+          b[r][4] = clamp_offset((int32_t)mv[src[r] + xn], d.mlo, d.mhi);
+        }
+        uint32_t o[8];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          o[2 * i] = b[0][i] | (b[0][i + 1] << 8) | (b[1][i] << 16) | (b[1][i + 1] << 24);
+          o[2 * i + 1] = b[2][i] | (b[2][i + 1] << 8) | (b[3][i] << 16) | (b[3][i + 1] << 24);
+        }
+        out[2 * x4] = make_uint4(o[0], o[1], o[2], o[3]);
+        out[2 * x4 + 1] = make_uint4(o[4], o[5], o[6], o[7]);
+      }
+    } else if (d.geom.oct8) {
       // 8-bit corners: byte 4 dz + 2 dy + dx' (layout of pack_oct8_kernel)
       uint2* __restrict__ out = (uint2*)d.geom.octs + row * nx;
       for (int32_t x = lane; x < nx; x += 64) {

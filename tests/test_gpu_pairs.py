@@ -111,3 +111,33 @@ def test_uneven_pairs_full_size_sampled(ctx):
     for k in (0, 97, 255):
         o = oracle_pairs([pairs[k]], 64, [1.0], 0)
         check(g[16 * k:16 * (k + 1)], o)
+
+
+def test_u8_pairs_vector_and_scalar_prep(ctx):
+    """All-u8 pairs (8-bit oct volumes for every pair): rows whose length is
+    a multiple of 4 take the four-voxels-per-lane prep, the others the
+    per-voxel prep; a volume starting one byte into its buffer (unaligned
+    for 32-bit loads) must take the per-voxel prep too."""
+    import torch
+    from paper_1909_10690_amd import binding as B
+    rng = np.random.default_rng(31)
+    pairs = []
+    for shape in [(64, 9, 7), (33, 12, 9), (40, 17, 6), (36, 24, 5), (17, 9, 8)]:
+        f = inputs.random_volume(rng, shape, np.uint8, 0, 255)
+        m = inputs.random_volume(rng, shape, np.uint8, 20, 230)
+        mats = inputs.random_affines(rng, 3, shape, rot=15, trans=4)
+        pairs.append(dict(fixed=f, moving=m, frange=(0, 255), mrange=(20, 230), transforms=mats))
+    q = [1.0, 1.5]
+    check(run_pairs(ctx, pairs, 48, q, 0), oracle_pairs(pairs, 48, q, 0))
+    # the first pair again, its volumes one byte into their device buffers
+    p = pairs[0]
+    fb = torch.empty(p["fixed"].size + 1, dtype=torch.uint8, device="cuda")
+    mb = torch.empty(p["moving"].size + 1, dtype=torch.uint8, device="cuda")
+    fb[1:].copy_(torch.from_numpy(p["fixed"].reshape(-1)))
+    mb[1:].copy_(torch.from_numpy(p["moving"].reshape(-1)))
+    nz, ny, nx = p["fixed"].shape
+    F = B.Volume(fb[1:].view(nz, ny, nx), 0, 255)
+    M = B.Volume(mb[1:].view(nz, ny, nx), 20, 230)
+    got = ctx.eval_pairs([(F, M, torch.from_numpy(p["transforms"]).cuda())], 48, q).cpu().numpy()
+    ref = oracle_pairs([p], 48, q, 0)
+    check(got, ref)
