@@ -163,6 +163,23 @@ __global__ void prep_moving_kernel(PairsArgs a, int64_t rows) {
   });
 }
 
+// A value every lane holds alike, moved to scalar registers.  The work item
+// reaches the workgroup through LDS, so the compiler cannot tell that what is
+// derived from it is uniform: without the broadcast the pair's geometry stays
+// in vector registers, is reloaded inside the sweep, and each gather from the
+// moving volume runs a loop over the distinct buffer descriptors of the wave.
+template <typename T>
+__device__ __forceinline__ T uniform(const T& v) {
+  static_assert(sizeof(T) % 4 == 0, "32-bit words");
+  uint32_t w[sizeof(T) / 4];
+  __builtin_memcpy(w, &v, sizeof(T));
+#pragma unroll
+  for (unsigned i = 0; i < sizeof(T) / 4; ++i) w[i] = __builtin_amdgcn_readfirstlane(w[i]);
+  T r;
+  __builtin_memcpy(&r, w, sizeof(T));
+  return r;
+}
+
 template <bool CLAMP, bool PACKED, bool OCT8, int NT>
 __global__ __launch_bounds__(NT) void hist_pairs_kernel(PairsArgs a) {
   extern __shared__ uint32_t lds_hist[];
@@ -176,17 +193,18 @@ __global__ __launch_bounds__(NT) void hist_pairs_kernel(PairsArgs a) {
   for (;;) {
     if (threadIdx.x == 0) item_sh = (int64_t)atomicAdd(&a.counters[xcd], 1ull);
     __syncthreads();
-    const int64_t item = item_sh;
+    const int64_t item = uniform(item_sh);
     if (item >= total) break;  // the same for every thread of the workgroup
     const int p = find_pair(xbase, a.n_pairs, item);
-    const PairDesc& d = a.pairs[p];
+    const HardGeom geom = uniform(a.pairs[p].geom);
+    const int32_t n_t = uniform(a.pairs[p].n_t), chunks = uniform(a.pairs[p].chunks);
     const int64_t rem = item - xbase[p];
-    const int64_t slab = rem / d.n_t, tl = rem - slab * d.n_t;
-    const uint32_t chunk = xcd * (uint32_t)(d.chunks >> 3) + (uint32_t)slab;
-    const int64_t t = a.t_base[p] + tl;
+    const int64_t slab = rem / n_t, tl = rem - slab * n_t;
+    const uint32_t chunk = xcd * (uint32_t)(chunks >> 3) + (uint32_t)slab;
+    const int64_t t = uniform(a.t_base[p]) + tl;
     int64_t Mq[12];
     const bool ok = quantize_transform(a.transforms + 12 * t, Mq);
-    if (ok) sweep_hard<CLAMP, PACKED, OCT8, NT / 64>(d.geom, Mq, d.chunks, chunk, lds_hist);
+    if (ok) sweep_hard<CLAMP, PACKED, OCT8, NT / 64>(geom, Mq, chunks, chunk, lds_hist);
     __syncthreads();
     if (ok) flush_hist<PACKED, NT>(lds_hist, B, a.hist + (size_t)t * B * B, true);
     __syncthreads();

@@ -13,6 +13,9 @@ typedef unsigned short ushort2_t __attribute__((ext_vector_type(2)));
 typedef unsigned int uint2_t __attribute__((ext_vector_type(2)));
 typedef unsigned int uint4_t __attribute__((ext_vector_type(4)));
 typedef __attribute__((address_space(3))) uint32_t lds_u32;
+// Device-memory bytes: loads through such a pointer are global, not flat,
+// also when the pointer itself was read from memory.
+typedef const __attribute__((address_space(1))) uint8_t global_u8;
 
 // a * b + c with 24-bit unsigned operands a, b (v_mad_u32_u24, full rate;
 // left to itself the compiler may pick a 64-bit multiply-add).
@@ -98,7 +101,7 @@ __device__ __forceinline__ void sweep_hard(const HardGeom& g, const int64_t* Mq,
       } else {
         oc = __builtin_amdgcn_raw_buffer_load_b128(rsrc, vox << 4, 0, 0);
       }
-      const uint32_t fb = g.fbins[xo];
+      const uint32_t fb = ((global_u8*)g.fbins)[xo];
       // (65535 - wx) in the low half, wx in the high half
       const uint32_t wpack = (fx & 0xFFFF0000u) | ((fx >> 16) ^ 0xFFFFu);
       const uint32_t a00 = lerp_x(oc.x, wpack), a10 = lerp_x(oc.y, wpack);
