@@ -201,6 +201,49 @@ def pairs_leg(ctx, B, inputs, dev) -> dict:
                       "each, 64 bins, Shannon"}
 
 
+def maps_leg(ctx, B, inputs, dev, n: int = 51) -> dict:
+    """Parameter-space maps of the same 256x256x180 u16 image: 51^3 grids
+    of translations (+-25 mm), rotations (versors, the whole unit ball) and
+    scales (+-25%), 128 bins, six entropies from each histogram, then the
+    discrete gradient paths and capture range of every entropy's map."""
+    import torch
+    from paper_1909_10690_amd import maps
+    log("maps leg: generating the 256x256x180 u16 same-image phantom")
+    c = inputs.same_image()
+    F = B.Volume.from_numpy(c["fixed"], *c["fixed_range"], dev)
+    Mv = F  # the same image on both sides
+    q, bins = tuple(c["q"]), c["bins"]
+    shape_xyz = c["fixed"].shape[::-1]
+    mats = {f: torch.from_numpy(maps.map_transforms(f, n, shape_xyz)).to(dev) for f in maps.FAMILIES}
+    maps.mi_map(ctx, F, Mv, "translation", 3, 2.0, bins=bins, q=q)  # warm-up (workspace, kernels)
+    torch.cuda.synchronize()
+    out, total_s = {}, 0.0
+    for fam in maps.FAMILIES:
+        log(f"maps leg: {fam} {n}^3")
+        t0 = time.perf_counter()
+        m = maps.mi_map(ctx, F, Mv, fam, n, bins=bins, q=q, transforms=mats[fam])
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        res = maps.map_paths(ctx, m, 1)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        total_s += t2 - t0
+        centre = ((n // 2) * n + n // 2) * n + n // 2
+        caps = {}
+        for qi, r in zip(q, res):
+            ext, target, basin, radius = (int(x) for x in r["stats"].cpu().tolist())
+            caps[f"q={qi:g}"] = {"extrema": ext, "centre_is_optimum": target == centre,
+                                 "basin_fraction": basin / n ** 3, "capture_radius": radius}
+        out[fam] = {"ms_map": (t1 - t0) * 1e3, "ms_paths": (t2 - t1) * 1e3,
+                    "mi_evals_per_s": n ** 3 / (t1 - t0), "capture": caps}
+    evals = 3 * n ** 3
+    return {"value": evals / total_s, "unit": "MI evaluations/s (one transform, 6 entropies, incl. paths)",
+            "voxel_xf_per_s": evals * c["fixed"].size / total_s, "families": out,
+            "config": f"same 256x256x180 u16 image both sides, {n}^3 grids of translation (+-25 mm), "
+                      f"rotation (versor, unit ball) and scale (+-25%), 128 bins, q = {list(q)}, "
+                      "exclude boundary, ascent paths"}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -215,6 +258,10 @@ def main() -> int:
     ap.add_argument("--register", action="store_true",
                     help="run the 200-iteration CT/MR registration (512x512x300 vs 256^3, 256 bins) "
                          "even with --no-extras")
+    ap.add_argument("--maps", action="store_true",
+                    help="map the metric over 51^3 translation, rotation and scale grids (with paths) "
+                         "even with --no-extras")
+    ap.add_argument("--no-maps", action="store_true", help="skip the parameter-space maps leg")
     ap.add_argument("--no-pairs", action="store_true", help="skip the uneven-pairs leg")
     ap.add_argument("--no-register", action="store_true", help="skip the registration leg")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -339,6 +386,8 @@ def main() -> int:
 
     if (args.pairs or not args.no_extras) and not args.no_pairs:
         result["pairs"] = pairs_leg(ctx, B, inputs, dev)
+    if (args.maps or not args.no_extras) and not args.no_maps:
+        result["maps"] = maps_leg(ctx, B, inputs, dev)
     if (args.register or not args.no_extras) and not args.no_register:
         result["register"] = register_leg(ctx, B, inputs, dev)
 

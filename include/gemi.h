@@ -192,6 +192,36 @@ int mi_eval_pairs(mi_context *ctx, const mi_pair *pairs, int32_t n_pairs, int32_
                   const double *q, int32_t n_q, int32_t flags, double *mi_out, void *workspace,
                   size_t workspace_bytes, void *stream);
 
+/* Discrete gradient paths on a parameter-space map (Results: the metric of
+ * one transform family -- translation, rotation or scale -- evaluated over
+ * a 3D grid of its parameters, and the paths a gradient method follows on
+ * that map; Discussion: the capture range of each entropy).  A path steps
+ * from a grid point to the 26-connected neighbour of steepest rise of
+ * direction * values, the rise scaled by the reciprocal step length (1, or
+ * the fp64 values nearest 1/sqrt(2) and 1/sqrt(3)), ties to the first
+ * neighbour in (dz, dy, dx) order, each running -1, 0, 1; it stops at a
+ * point no neighbour rises from (a local extremum; NaN points are extrema
+ * and never entered).
+ *   values     device double[nz][ny][nx] (x fastest), e.g. one q's values
+ *              of mi_eval over a grid of transforms
+ *   direction  +1: paths climb to maxima; -1: they descend to minima
+ *   cx, cy, cz grid index of the expected optimum (the map's centre)
+ *   next_out   device int32[nz*ny*nx]: each point's successor (itself at an
+ *              extremum), as a flat index z*ny*nx + y*nx + x
+ *   sink_out   device int32[nz*ny*nx]: the extremum each point's path ends at
+ *   stats_out  device int64[4]: number of extrema; the extremum the centre's
+ *              path ends at; how many points end there; the capture radius,
+ *              the largest r such that every point within Chebyshev
+ *              distance r of the centre ends there (the largest such
+ *              distance in the grid when every point does)
+ * Errors, before any launch: MI_ERR_NULL (a pointer), MI_ERR_DIMS (an
+ * extent outside [1, 4096], more than 2^31 - 1 points, or the centre
+ * outside the grid), MI_ERR_FLAGS (direction not +1 or -1).  Asynchronous
+ * on `stream`; allocates nothing; the buffers must not overlap. */
+int mi_map_paths(mi_context *ctx, const double *values, int32_t nx, int32_t ny, int32_t nz,
+                 int32_t direction, int32_t cx, int32_t cy, int32_t cz, int32_t *next_out,
+                 int32_t *sink_out, int64_t *stats_out, void *stream);
+
 /* Autotuner of the hard-binned sweep (mi_eval and mi_eval_pairs share its
  * kernel).  Times the histogram kernel on these arguments for every
  * candidate launch shape (workgroup size 256/512/1024, slab-major or

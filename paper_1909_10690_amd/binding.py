@@ -50,7 +50,7 @@ class MiPair(ctypes.Structure):
 
 EXPORTS = ["mi_create", "mi_destroy", "mi_workspace_size", "mi_eval", "mi_grad",
            "mi_pairs_workspace_size", "mi_eval_pairs", "mi_tune", "mi_timing_enable",
-           "mi_timing_read", "mi_probe_lds_atomics", "mi_status_string"]
+           "mi_timing_read", "mi_probe_lds_atomics", "mi_map_paths", "mi_status_string"]
 
 _lib = None
 
@@ -78,6 +78,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.mi_timing_enable.argtypes = [vp, ctypes.c_int]
     lib.mi_timing_read.argtypes = [vp, ctypes.c_int, dp, P(ctypes.c_int64)]
     lib.mi_probe_lds_atomics.argtypes = [vp, vp, sz, vp, dp]
+    lib.mi_map_paths.argtypes = [vp, vp, i32, i32, i32, i32, i32, i32, i32, vp, vp, vp, vp]
     lib.mi_status_string.argtypes = [ctypes.c_int]
     lib.mi_status_string.restype = ctypes.c_char_p
     for name in EXPORTS:
@@ -271,6 +272,27 @@ class Context:
         f, m = fixed.c(), moving.c()
         _check(self.lib.mi_tune(self.handle, ctypes.byref(f), ctypes.byref(m), _ptr(transforms), n, bins,
                                 flags, _ptr(workspace), workspace.numel(), self._stream(stream)), "mi_tune")
+
+    def map_paths(self, values: torch.Tensor, direction: int = 1, centre=None, stream=None):
+        """Discrete gradient paths on a [nz][ny][nx] map (include/gemi.h,
+        mi_map_paths): returns (next, sink) int32 tensors of the map's shape
+        and stats int64[4] = (extrema, sink of the centre, its basin size,
+        capture radius), all on the map's device.  ``centre`` = (cx, cy, cz),
+        the grid centre by default."""
+        if values.dim() != 3:
+            raise ValueError("values must be a 3D [nz][ny][nx] map")
+        if values.device.type != "cuda":
+            raise ValueError("values must be a device (cuda) tensor")
+        values = values.to(dtype=torch.float64).contiguous()
+        nz, ny, nx = values.shape
+        cx, cy, cz = ((nx - 1) // 2, (ny - 1) // 2, (nz - 1) // 2) if centre is None else centre
+        nxt = torch.empty(values.shape, dtype=torch.int32, device=values.device)
+        sink = torch.empty(values.shape, dtype=torch.int32, device=values.device)
+        stats = torch.empty(4, dtype=torch.int64, device=values.device)
+        _check(self.lib.mi_map_paths(self.handle, _ptr(values), nx, ny, nz, int(direction), int(cx), int(cy),
+                                     int(cz), _ptr(nxt), _ptr(sink), _ptr(stats), self._stream(stream)),
+               "mi_map_paths")
+        return nxt, sink, stats
 
     def timing(self, enable: bool) -> None:
         _check(self.lib.mi_timing_enable(self.handle, int(enable)), "mi_timing_enable")

@@ -16,6 +16,7 @@
 #include <vector>
 
 #include "common.h"
+#include "paths.h"
 
 namespace gemi {
 hipError_t configure_hard_kernels();
@@ -980,6 +981,34 @@ int mi_grad(mi_context* ctx, const mi_volume* fixed, const mi_volume* moving,
   st = graph_run(ctx, key, s, body);
   ctx->last_prep = prep_key(2, workspace, fixed, moving, bins);  // the graph prepared them
   return st;
+}
+
+int mi_map_paths(mi_context* ctx, const double* values, int32_t nx, int32_t ny, int32_t nz,
+                 int32_t direction, int32_t cx, int32_t cy, int32_t cz, int32_t* next_out,
+                 int32_t* sink_out, int64_t* stats_out, void* stream) {
+  if (!values || !next_out || !sink_out || !stats_out) return MI_ERR_NULL;
+  if (nx < 1 || ny < 1 || nz < 1 || nx > MI_MAX_EDGE || ny > MI_MAX_EDGE || nz > MI_MAX_EDGE)
+    return MI_ERR_DIMS;
+  if ((int64_t)nx * ny * nz > (int64_t)INT32_MAX) return MI_ERR_DIMS;
+  if (cx < 0 || cx >= nx || cy < 0 || cy >= ny || cz < 0 || cz >= nz) return MI_ERR_DIMS;
+  if (direction != 1 && direction != -1) return MI_ERR_FLAGS;
+  if (!ctx) return MI_ERR_NULL;
+  hipError_t e;
+  if ((e = hipSetDevice(ctx->device)) != hipSuccess) return hip_fail(e, "hipSetDevice");
+  PathsLaunch L;
+  L.values = values;
+  L.nx = nx;
+  L.ny = ny;
+  L.nz = nz;
+  L.sign = (double)direction;
+  L.cx = cx;
+  L.cy = cy;
+  L.cz = cz;
+  L.next = next_out;
+  L.sink = sink_out;
+  L.stats = stats_out;
+  if ((e = launch_map_paths(L, (hipStream_t)stream)) != hipSuccess) return hip_fail(e, "map paths");
+  return MI_OK;
 }
 
 int mi_pairs_workspace_size(const mi_pair* pairs, int32_t n_pairs, int32_t bins, int32_t n_q,

@@ -163,6 +163,26 @@ def multimodal_sweep(shape_xyz=(256, 256, 180), seed: int = 1, n_tx=10, n_rot=10
                 q=[1.0, 0.5, 0.8, 1.2, 1.5, 2.0], truth=truth)
 
 
+def same_image(shape_xyz=(256, 256, 180), seed: int = 5, dtype=np.uint16) -> dict:
+    """One T1-like phantom used as both fixed and moving, the setting of the
+    paper's parameter-space maps (the same image on both sides, so the
+    optimum is the identity at the map's centre).  u16 levels 0/600/1600/2400
+    with Rician noise (sigma 40), range 0..4095, 128 bins; u8 levels
+    20/90/160/230 with Gaussian noise (sigma 8), range 0..255, 32 bins.
+    Entropies: Shannon and the Tsallis q the paper's maps show."""
+    rng = np.random.default_rng(seed)
+    lab = render_labels(shape_xyz)
+    if np.dtype(dtype) == np.uint8:
+        vol = intensities(lab, (20, 90, 160, 230), rng, 8.0, False, 0, 255, np.uint8)
+        rng_, bins = (0, 255), 32
+    else:
+        vol = intensities(lab, (0, 600, 1600, 2400), rng, 40.0, True, 0, 4095, np.uint16)
+        rng_, bins = (0, 4095), 128
+    return dict(name=f"same-image {shape_xyz[0]}x{shape_xyz[1]}x{shape_xyz[2]} {np.dtype(dtype).name}",
+                fixed=vol, moving=vol, fixed_range=rng_, moving_range=rng_, bins=bins,
+                q=[1.0, 0.5, 0.9, 1.1, 1.5, 2.0])
+
+
 def random_affines(rng: np.random.Generator, n: int, shape_xyz, rot=10.0, trans=8.0,
                    scale=(0.95, 1.05), shear=0.03) -> np.ndarray:
     mats = [np.zeros((3, 4))][:0]

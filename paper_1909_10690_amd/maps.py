@@ -1,0 +1,132 @@
+"""Parameter-space maps of the metric and the gradient paths on them.
+
+Results (Translation, Rotation, Scale): the metric of one transform family
+is evaluated over a 3D grid of that family's parameters -- 51 values per
+axis, e.g. translations from -25 to 25 mm, 51^3 = 132651 evaluations -- and
+the paths a gradient method follows on each map show which starting points
+reach the known optimum (the grid centre for a pair already registered);
+the Discussion compares the entropies by that capture range.
+
+Each grid point becomes one candidate 3x4 matrix; one batched ``mi_eval``
+per batch of points evaluates them all, every entropy from the same
+histogram; ``mi_map_paths`` then traces the discrete gradient paths and the
+capture statistics of each entropy's map.  This module builds the matrices
+(host-side transform setup, as for every call) and marshals the calls.
+
+Families, as parameters p of the fixed -> moving map T of Fig. 1 about the
+fixed volume's physical centre c:
+
+* ``translation``: T(x) = x + p (mm);
+* ``rotation``: T(x) = R(p) (x - c) + c, with p the vector part of a unit
+  quaternion (a versor): rotation by 2 asin|p| about p / |p|.  Points with
+  |p| > 1 are scaled onto the unit sphere, the rotation by 180 degrees about
+  p / |p| -- the paper maps every point outside the unit sphere to its
+  surface;
+* ``scale``: T(x) = diag(1 + p) (x - c) + c.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import transforms as T
+
+FAMILIES = ("translation", "rotation", "scale")
+DEFAULT_EXTENT = {"translation": 25.0, "rotation": 1.0, "scale": 0.25}
+
+
+def versor_matrices(v) -> np.ndarray:
+    """Rotation matrices [n][3][3] of versors with vector parts ``v`` [n][3]
+    (scaled onto the unit sphere where |v| > 1)."""
+    v = np.asarray(v, dtype=np.float64).reshape(-1, 3)
+    n2 = np.einsum("ij,ij->i", v, v)
+    outside = n2 > 1.0
+    v = np.where(outside[:, None], v / np.sqrt(np.where(outside, n2, 1.0))[:, None], v)
+    w = np.where(outside, 0.0, np.sqrt(np.clip(1.0 - n2, 0.0, None)))
+    x, y, z = v[:, 0], v[:, 1], v[:, 2]
+    R = np.empty((v.shape[0], 3, 3))
+    R[:, 0, 0] = 1 - 2 * (y * y + z * z)
+    R[:, 0, 1] = 2 * (x * y - w * z)
+    R[:, 0, 2] = 2 * (x * z + w * y)
+    R[:, 1, 0] = 2 * (x * y + w * z)
+    R[:, 1, 1] = 1 - 2 * (x * x + z * z)
+    R[:, 1, 2] = 2 * (y * z - w * x)
+    R[:, 2, 0] = 2 * (x * z - w * y)
+    R[:, 2, 1] = 2 * (y * z + w * x)
+    R[:, 2, 2] = 1 - 2 * (x * x + y * y)
+    return R
+
+
+def family_affines(family: str, p) -> tuple[np.ndarray, np.ndarray]:
+    """(A [n][3][3], t [n][3]) of the centred maps T(x) = A (x - c) + c + t
+    for parameter rows p [n][3]."""
+    p = np.asarray(p, dtype=np.float64).reshape(-1, 3)
+    eye = np.broadcast_to(np.eye(3), (p.shape[0], 3, 3)).copy()
+    if family == "translation":
+        return eye, p.copy()
+    if family == "rotation":
+        return versor_matrices(p), np.zeros_like(p)
+    if family == "scale":
+        return eye * (1.0 + p)[:, None, :], np.zeros_like(p)
+    raise ValueError(f"unknown family {family!r}; expected one of {FAMILIES}")
+
+
+def grid_params(n: int, extent: float) -> np.ndarray:
+    """Parameter rows [n^3][3] of the grid, x parameter fastest: row
+    (k n + j) n + i holds (g[i], g[j], g[k])."""
+    g = grid_axis(n, extent)
+    pz, py, px = np.meshgrid(g, g, g, indexing="ij")
+    return np.stack([px.reshape(-1), py.reshape(-1), pz.reshape(-1)], axis=1)
+
+
+def grid_axis(n: int, extent: float) -> np.ndarray:
+    """n parameter values from -extent to extent (the centre is 0 for odd n)."""
+    if n < 1:
+        raise ValueError("n must be >= 1")
+    return np.linspace(-extent, extent, n) if n > 1 else np.zeros(1)
+
+
+def map_transforms(family: str, n: int, fixed_shape_xyz, extent: float | None = None,
+                   fixed_spacing=(1.0, 1.0, 1.0), moving_spacing=(1.0, 1.0, 1.0),
+                   fixed_origin=(0.0, 0.0, 0.0), moving_origin=(0.0, 0.0, 0.0)) -> np.ndarray:
+    """Index-space matrices [n^3][12] of the family over an n^3 grid, grid
+    point (i, j, k) -- parameters (g[i], g[j], g[k]) -- at row (k n + j) n + i,
+    so a [n][n][n] view of any per-transform output is the [z][y][x] map."""
+    ext = DEFAULT_EXTENT[family] if extent is None else float(extent)
+    A, t = family_affines(family, grid_params(n, ext))
+    return T.index_matrices(A, t, fixed_shape_xyz, fixed_spacing, fixed_origin, moving_spacing, moving_origin)
+
+
+def mi_map(ctx, fixed, moving, family: str, n: int = 51, extent: float | None = None, bins: int = 64,
+           q=(1.0,), flags: int = 0, batch: int = 16384, transforms=None, **geometry):
+    """MI maps [n_q][n][n][n] (device float64, [z][y][x] order per q) of one
+    family over an n^3 grid: batches of grid points through ``ctx.eval``.
+    ``transforms`` (the [n^3][12] matrices, on the device) may be given to
+    skip building them; ``geometry`` takes the spacing / origin arguments of
+    :func:`map_transforms`."""
+    import torch
+    dev = fixed.tensor.device
+    if transforms is None:
+        nz, ny, nx = fixed.tensor.shape
+        transforms = torch.from_numpy(map_transforms(family, n, (nx, ny, nz), extent, **geometry)).to(dev)
+    total = n ** 3
+    if transforms.shape != (total, 12):
+        raise ValueError(f"transforms must be [{total}][12]")
+    qs = tuple(float(v) for v in np.atleast_1d(q))
+    out = torch.empty((total, len(qs)), dtype=torch.float64, device=dev)
+    for a in range(0, total, batch):
+        b = min(total, a + batch)
+        ctx.eval(fixed, moving, transforms[a:b], bins, qs, flags=flags, want_overlap=False, out=out[a:b])
+    return out.t().reshape(len(qs), n, n, n).contiguous()
+
+
+def map_paths(ctx, maps, direction: int = 1, centre=None) -> list[dict]:
+    """Discrete gradient paths on each map of ``maps`` ([n_q][nz][ny][nx] or
+    one [nz][ny][nx] map): per map, successors, sinks and the statistics
+    (extrema, sink of the centre, its basin size, capture radius)."""
+    if maps.dim() == 3:
+        maps = maps.unsqueeze(0)
+    res = []
+    for m in maps:
+        nxt, sink, stats = ctx.map_paths(m, direction, centre)
+        res.append({"next": nxt, "sink": sink, "stats": stats})
+    return res

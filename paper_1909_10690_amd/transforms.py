@@ -63,6 +63,22 @@ def index_matrix(A, t, fixed_shape_xyz, fixed_spacing=(1.0, 1.0, 1.0), fixed_ori
     return M
 
 
+def index_matrices(A, t, fixed_shape_xyz, fixed_spacing=(1.0, 1.0, 1.0), fixed_origin=(0.0, 0.0, 0.0),
+                   moving_spacing=(1.0, 1.0, 1.0), moving_origin=(0.0, 0.0, 0.0), centre=None) -> np.ndarray:
+    """:func:`index_matrix` of a batch: A [n][3][3], t [n][3] -> [n][12]."""
+    A = np.asarray(A, dtype=np.float64).reshape(-1, 3, 3)
+    t = np.asarray(t, dtype=np.float64).reshape(-1, 3)
+    Sf = np.diag(np.asarray(fixed_spacing, dtype=np.float64))
+    Sm_inv = np.diag(1.0 / np.asarray(moving_spacing, dtype=np.float64))
+    of = np.asarray(fixed_origin, dtype=np.float64)
+    om = np.asarray(moving_origin, dtype=np.float64)
+    c = fixed_centre(fixed_shape_xyz, fixed_spacing, fixed_origin) if centre is None else np.asarray(centre, dtype=np.float64)
+    M = np.zeros((A.shape[0], 3, 4))
+    M[:, :, :3] = Sm_inv @ A @ Sf
+    M[:, :, 3] = ((A @ (of - c)) + c + t - om) @ Sm_inv.T
+    return M.reshape(-1, 12)
+
+
 def index_jacobian(fixed_shape_xyz, fixed_spacing=(1.0, 1.0, 1.0), fixed_origin=(0.0, 0.0, 0.0),
                    moving_spacing=(1.0, 1.0, 1.0), moving_origin=(0.0, 0.0, 0.0), centre=None) -> np.ndarray:
     """J[e, p] = d M.flat[e] / d params[p], params = (A.flat (9), t (3)).

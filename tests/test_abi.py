@@ -212,6 +212,34 @@ def test_timing_and_pairs_null_checks():
     assert lib.mi_timing_read(None, 0, ctypes.byref(ms), ctypes.byref(n)) == B.MI_ERR_NULL
 
 
+@pytest.mark.parametrize("dims,centre,direction,status", [
+    ((51, 51, 51), (25, 25, 25), 1, B.MI_ERR_NULL),       # valid: reaches the context check
+    ((1, 1, 1), (0, 0, 0), -1, B.MI_ERR_NULL),
+    ((4096, 4096, 1), (0, 4095, 0), 1, B.MI_ERR_NULL),
+    ((0, 5, 5), (0, 0, 0), 1, B.MI_ERR_DIMS),
+    ((4097, 1, 1), (0, 0, 0), 1, B.MI_ERR_DIMS),
+    ((4096, 4096, 128), (0, 0, 0), 1, B.MI_ERR_DIMS),    # 2^31 points
+    ((5, 5, 5), (5, 0, 0), 1, B.MI_ERR_DIMS),
+    ((5, 5, 5), (0, -1, 0), 1, B.MI_ERR_DIMS),
+    ((5, 5, 5), (2, 2, 2), 0, B.MI_ERR_FLAGS),
+    ((5, 5, 5), (2, 2, 2), 2, B.MI_ERR_FLAGS),
+])
+def test_map_paths_validation(dims, centre, direction, status):
+    lib = B.load()
+    nx, ny, nz = dims
+    cx, cy, cz = centre
+    assert lib.mi_map_paths(None, FAKE, nx, ny, nz, direction, cx, cy, cz, FAKE, FAKE, FAKE, None) == status
+
+
+def test_map_paths_null_buffers():
+    lib = B.load()
+    for k in range(4):
+        ptrs = [FAKE] * 4
+        ptrs[k] = None
+        v, nx_, sk, st = ptrs
+        assert lib.mi_map_paths(None, v, 5, 5, 5, 1, 2, 2, 2, nx_, sk, st, None) == B.MI_ERR_NULL
+
+
 def test_graph_flag_accepted_and_unknown_bits_rejected():
     assert call_eval(vol(), vol(), flags=B.USE_GRAPH) == B.MI_ERR_NULL
     assert call_eval(vol(), vol(), flags=B.USE_GRAPH | B.HIST_PARZEN) == B.MI_ERR_NULL
