@@ -83,6 +83,7 @@ extern "C" {
 #define MI_ERR_UNSUPPORTED (-8) /* a valid request this build does not serve */
 #define MI_ERR_FLAGS (-9)       /* unknown flag bits */
 #define MI_ERR_COUNT (-10)      /* n_transforms (or n_pairs) negative or above 2^24 */
+#define MI_ERR_SAMPLE (-11)     /* sampling fraction not finite or not above 0 */
 #define MI_ERR_HIP (-20)        /* the HIP runtime reported an error (see mi_status_string) */
 #define MI_ERR_NO_DEVICE (-21)  /* no usable GPU with the requested index */
 
@@ -117,6 +118,10 @@ extern "C" {
  * changed contents.  Ignored by calls that use MI_USE_GRAPH (a captured
  * graph always prepares).  For loops over one volume pair (registration). */
 #define MI_VOLUMES_UNCHANGED 0x2000
+/* mi_workspace_size: size the workspace for mi_eval_sampled (adds the
+ * sample list, 8 bytes per fixed voxel).  Accepted (and implied) by
+ * mi_eval_sampled; rejected (MI_ERR_FLAGS) by the other calls. */
+#define MI_SAMPLED 0x4000
 
 #define MI_MAX_Q 16
 #define MI_MAX_EDGE 4096
@@ -162,6 +167,28 @@ int mi_eval(mi_context *ctx, const mi_volume *fixed, const mi_volume *moving,
             const double *transforms, int32_t n_transforms, int32_t bins, const double *q,
             int32_t n_q, int32_t flags, double *mi_out, uint64_t *overlap_out,
             uint32_t *hist_out, void *workspace, size_t workspace_bytes, void *stream);
+
+/* MI over a random subsample of the fixed voxels (Discussion: Mattes' MI
+ * samples voxels at random where MI over all voxels does not, and the paper
+ * leaves the effect of that sampling -- with binned histograms -- open).
+ * Arguments and results as mi_eval (hard or Parzen per `flags`), computed
+ * over the kept fixed voxels only; overlap_out counts the kept voxels that
+ * took part (the MI normaliser).  Fixed voxel i (linear index
+ * z*ny*nx + y*nx + x) is kept when the top 32 bits of the SplitMix64 output
+ * for counter i of the stream seeded with `seed` -- i.e. of
+ * mix(seed + (i + 1) * 0x9E3779B97F4A7C15) (Steele, Lea and Flood, OOPSLA
+ * 2014) -- are below floor(fraction * 2^32); every voxel when fraction >= 1.
+ * The sample depends only on (seed, fraction, fixed volume shape).
+ *   fraction  in (0, 1]: expected share of fixed voxels kept
+ *   seed      any 64-bit value
+ * Workspace: mi_workspace_size() with MI_SAMPLED in `flags`.  Always
+ * prepares the volumes (MI_VOLUMES_UNCHANGED is ignored).  MI_ERR_SAMPLE
+ * for a fraction that is not finite or not above 0. */
+int mi_eval_sampled(mi_context *ctx, const mi_volume *fixed, const mi_volume *moving,
+                    const double *transforms, int32_t n_transforms, int32_t bins, const double *q,
+                    int32_t n_q, int32_t flags, double fraction, uint64_t seed, double *mi_out,
+                    uint64_t *overlap_out, uint32_t *hist_out, void *workspace,
+                    size_t workspace_bytes, void *stream);
 
 /* Parzen MI and its gradient with respect to the 12 entries of each
  * index-space matrix (what a gradient optimiser of Eq. (3) consumes).

@@ -14,6 +14,10 @@ ctypes.  Every function cites the passage of the paper it follows:
   Parzen/B-spline variant are not printed in the paper; they follow the
   readings recorded in the repository's design notes.
 
+* Random subsampling (Discussion: Mattes' MI samples voxels at random):
+  SplitMix64 (Steele, Lea and Flood, OOPSLA 2014) from its published
+  definition decides, per fixed voxel, whether it takes part.
+
 Parity status: every function is pinned by tests in ``tests/test_oracle_*``
 against closed forms, library routines and exact rational brute force.
 """
@@ -89,6 +93,21 @@ def _load():
                                       ctypes.c_int, ctypes.c_int, dp, dp]
         lib.or_eval_parzen.argtypes = [vp, vp, dp, ctypes.c_int, ctypes.c_int, dp, ctypes.c_int,
                                        ctypes.c_int, ctypes.c_int, dp, P(ctypes.c_int64)]
+        u64 = ctypes.c_uint64
+        lib.or_splitmix64.argtypes = [u64, u64]
+        lib.or_splitmix64.restype = u64
+        lib.or_hist_hard_sampled.argtypes = [vp, vp, dp, ctypes.c_int, ctypes.c_int, ctypes.c_double, u64,
+                                             P(ctypes.c_uint32)]
+        lib.or_hist_hard_sampled.restype = ctypes.c_int64
+        lib.or_eval_hard_sampled.argtypes = [vp, vp, dp, ctypes.c_int, ctypes.c_int, dp, ctypes.c_int,
+                                             ctypes.c_int, ctypes.c_int, ctypes.c_double, u64, dp,
+                                             P(ctypes.c_int64), P(ctypes.c_uint32)]
+        lib.or_parzen_table_sampled.argtypes = [vp, vp, dp, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                                u64, dp]
+        lib.or_parzen_table_sampled.restype = ctypes.c_int64
+        lib.or_eval_parzen_sampled.argtypes = [vp, vp, dp, ctypes.c_int, ctypes.c_int, dp, ctypes.c_int,
+                                               ctypes.c_int, ctypes.c_int, ctypes.c_double, u64, dp,
+                                               P(ctypes.c_int64)]
         lib.or_num_threads.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -160,9 +179,16 @@ def mi_from_table(table: np.ndarray, N: float, q, form: int = ADDITIVE) -> np.nd
     return out
 
 
+def splitmix64(seed: int, i: int) -> int:
+    """SplitMix64 output for counter i of the stream seeded with ``seed``."""
+    return int(_load().or_splitmix64(seed & (2 ** 64 - 1), i))
+
+
 def eval_hard(fixed, moving, M, bins: int, q, boundary: int = EXCLUDE, form: int = ADDITIVE,
-              want_hist: bool = False):
-    """Hard-binned MI of a batch of transforms: (mi[n][nq], overlap[n], hist or None)."""
+              want_hist: bool = False, sample=None):
+    """Hard-binned MI of a batch of transforms: (mi[n][nq], overlap[n], hist or None).
+    ``sample`` = (fraction, seed) keeps each fixed voxel by the random
+    subsampling rule (Discussion); None keeps every voxel."""
     lib = _load()
     M = _mats(M)
     n = M.shape[0]
@@ -170,10 +196,11 @@ def eval_hard(fixed, moving, M, bins: int, q, boundary: int = EXCLUDE, form: int
     mi = np.zeros((n, len(qs)))
     ov = np.zeros(n, dtype=np.int64)
     hist = np.zeros((n, bins, bins), dtype=np.uint32) if want_hist else None
-    lib.or_eval_hard(ctypes.byref(fixed[0]), ctypes.byref(moving[0]), _ptr(M, ctypes.c_double), n,
-                     bins, _ptr(qs, ctypes.c_double), len(qs), boundary, form,
-                     _ptr(mi, ctypes.c_double), _ptr(ov, ctypes.c_int64),
-                     _ptr(hist, ctypes.c_uint32) if want_hist else None)
+    frac, seed = (1.0, 0) if sample is None else (float(sample[0]), int(sample[1]))
+    lib.or_eval_hard_sampled(ctypes.byref(fixed[0]), ctypes.byref(moving[0]), _ptr(M, ctypes.c_double), n,
+                             bins, _ptr(qs, ctypes.c_double), len(qs), boundary, form, frac, seed,
+                             _ptr(mi, ctypes.c_double), _ptr(ov, ctypes.c_int64),
+                             _ptr(hist, ctypes.c_uint32) if want_hist else None)
     return mi, ov, hist
 
 
@@ -185,13 +212,27 @@ def dbeta3(t: float) -> float:
     return _load().or_dbeta3(float(t))
 
 
-def parzen_table(fixed, moving, M, bins: int, boundary: int = CLAMP) -> tuple[np.ndarray, int]:
-    """Unnormalised Parzen joint table [bins][bins] and normaliser N."""
+def parzen_table(fixed, moving, M, bins: int, boundary: int = CLAMP, sample=None) -> tuple[np.ndarray, int]:
+    """Unnormalised Parzen joint table [bins][bins] and normaliser N
+    (``sample`` = (fraction, seed) as in :func:`eval_hard`)."""
     lib = _load()
     M = _mats(M)[0].copy()
     h = np.zeros((bins, bins))
-    n = lib.or_parzen_table(ctypes.byref(fixed[0]), ctypes.byref(moving[0]),
-                            _ptr(M, ctypes.c_double), bins, boundary, _ptr(h, ctypes.c_double))
+    frac, seed = (1.0, 0) if sample is None else (float(sample[0]), int(sample[1]))
+    n = lib.or_parzen_table_sampled(ctypes.byref(fixed[0]), ctypes.byref(moving[0]),
+                                    _ptr(M, ctypes.c_double), bins, boundary, frac, seed,
+                                    _ptr(h, ctypes.c_double))
+    return h, int(n)
+
+
+def hist_hard_sampled(fixed, moving, M, bins: int, boundary: int, fraction: float, seed: int):
+    """Hard-binned joint histogram and overlap count of one transform over the
+    fixed voxels the random subsampling rule keeps."""
+    lib = _load()
+    M = _mats(M)[0].copy()
+    h = np.zeros((bins, bins), dtype=np.uint32)
+    n = lib.or_hist_hard_sampled(ctypes.byref(fixed[0]), ctypes.byref(moving[0]), _ptr(M, ctypes.c_double),
+                                 bins, boundary, float(fraction), int(seed), _ptr(h, ctypes.c_uint32))
     return h, int(n)
 
 
@@ -209,17 +250,19 @@ def parzen_grad(fixed, moving, M, bins: int, q, boundary: int = CLAMP, form: int
     return mi, g
 
 
-def eval_parzen(fixed, moving, M, bins: int, q, boundary: int = CLAMP, form: int = ADDITIVE):
-    """Parzen MI [n][nq] and normaliser [n] of a batch of transforms."""
+def eval_parzen(fixed, moving, M, bins: int, q, boundary: int = CLAMP, form: int = ADDITIVE, sample=None):
+    """Parzen MI [n][nq] and normaliser [n] of a batch of transforms
+    (``sample`` = (fraction, seed) as in :func:`eval_hard`)."""
     lib = _load()
     M = _mats(M)
     n = M.shape[0]
     qs = _qs(q)
     mi = np.zeros((n, len(qs)))
     ov = np.zeros(n, dtype=np.int64)
-    lib.or_eval_parzen(ctypes.byref(fixed[0]), ctypes.byref(moving[0]), _ptr(M, ctypes.c_double),
-                       n, bins, _ptr(qs, ctypes.c_double), len(qs), boundary, form,
-                       _ptr(mi, ctypes.c_double), _ptr(ov, ctypes.c_int64))
+    frac, seed = (1.0, 0) if sample is None else (float(sample[0]), int(sample[1]))
+    lib.or_eval_parzen_sampled(ctypes.byref(fixed[0]), ctypes.byref(moving[0]), _ptr(M, ctypes.c_double),
+                               n, bins, _ptr(qs, ctypes.c_double), len(qs), boundary, form, frac, seed,
+                               _ptr(mi, ctypes.c_double), _ptr(ov, ctypes.c_int64))
     return mi, ov
 
 

@@ -38,6 +38,14 @@
  *    cubic B-spline beta3 at s = 1 + (v - lo)/(hi - lo) * (B - 4); fp64
  *    trilinear value; gradient of every MI output with respect to the 12
  *    entries of M (the quantity a gradient optimiser for Eq. (3) needs).
+ *  - Random subsampling (Discussion: Mattes' MI samples voxels at random,
+ *    MI over all voxels does not, and the effect is left open): fixed voxel
+ *    i (linear index, x fastest) takes part iff the top 32 bits of the
+ *    SplitMix64 output for counter i under a seed are below
+ *    floor(fraction * 2^32) (every voxel when fraction >= 1).  SplitMix64
+ *    (Steele, Lea and Flood, OOPSLA 2014) is written here from its
+ *    published definition: the i-th output (from 0) of the stream seeded
+ *    with s mixes s + (i + 1) * 0x9E3779B97F4A7C15.
  */
 #include <math.h>
 #include <stdint.h>
@@ -157,11 +165,27 @@ static int64_t fixed_bin(const or_volume *f, int64_t i, int64_t j, int64_t k, in
   return fixed_bin_int(f, vox_int(f, i, j, k), bins);
 }
 
-/* Joint histogram of one transform; hist is bins*bins counts, row = fixed
- * bin, column = moving bin.  Returns the overlap count, or -1 when the
- * transform is unusable (hist left zero). */
-int64_t or_hist_hard(const or_volume *f, const or_volume *m, const double M[12], int bins,
-                     int boundary, uint32_t *hist) {
+/* SplitMix64 output for counter i of the stream seeded with `seed`. */
+uint64_t or_splitmix64(uint64_t seed, uint64_t i) {
+  uint64_t z = seed + (i + 1) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+/* Whether fixed voxel `lin` takes part at this sampling fraction. */
+static int keep_voxel(double fraction, uint64_t seed, int64_t lin) {
+  if (fraction >= 1.0) return 1;
+  const uint64_t thr = (uint64_t)floor(fraction * 4294967296.0);
+  return (or_splitmix64(seed, (uint64_t)lin) >> 32) < thr;
+}
+
+/* Joint histogram of one transform over the fixed voxels kept by the
+ * sampling rule; hist is bins*bins counts, row = fixed bin, column = moving
+ * bin.  Returns the overlap count, or -1 when the transform is unusable
+ * (hist left zero). */
+int64_t or_hist_hard_sampled(const or_volume *f, const or_volume *m, const double M[12], int bins,
+                             int boundary, double fraction, uint64_t seed, uint32_t *hist) {
   memset(hist, 0, sizeof(uint32_t) * (size_t)bins * (size_t)bins);
   int64_t Mq[12];
   if (or_quantize(M, Mq)) return -1;
@@ -172,6 +196,7 @@ int64_t or_hist_hard(const or_volume *f, const or_volume *m, const double M[12],
   for (int64_t k = 0; k < f->nz; ++k)
     for (int64_t j = 0; j < f->ny; ++j)
       for (int64_t i = 0; i < f->nx; ++i) {
+        if (!keep_voxel(fraction, seed, (k * f->ny + j) * f->nx + i)) continue;
         i128 q[3];
         int clamped[3];
         for (int r = 0; r < 3; ++r) q[r] = coord_q32(Mq, r, i, j, k);
@@ -204,6 +229,12 @@ int64_t or_hist_hard(const or_volume *f, const or_volume *m, const double M[12],
         ++count;
       }
   return count;
+}
+
+/* The histogram over every fixed voxel. */
+int64_t or_hist_hard(const or_volume *f, const or_volume *m, const double M[12], int bins,
+                     int boundary, uint32_t *hist) {
+  return or_hist_hard_sampled(f, m, M, bins, boundary, 1.0, 0, hist);
 }
 
 /* ------------------------------------------------------------------ */
@@ -309,14 +340,14 @@ void or_mi_from_table(const double *table, int bins, double N, const double *qs,
 /* Hard-binned MI of n transforms (row-major [n][12]).  mi[n][nq] and
  * overlap[n]; an unusable transform gives NaN MI and overlap 0.  Transforms
  * are independent, so they are spread over OpenMP threads. */
-void or_eval_hard(const or_volume *f, const or_volume *m, const double *M, int n, int bins,
-                  const double *qs, int nq, int boundary, int form, double *mi,
-                  int64_t *overlap, uint32_t *hist_out) {
+void or_eval_hard_sampled(const or_volume *f, const or_volume *m, const double *M, int n, int bins,
+                          const double *qs, int nq, int boundary, int form, double fraction,
+                          uint64_t seed, double *mi, int64_t *overlap, uint32_t *hist_out) {
 #pragma omp parallel for schedule(dynamic, 1)
   for (int t = 0; t < n; ++t) {
     size_t nn = (size_t)bins * bins;
     uint32_t *h = hist_out ? hist_out + nn * (size_t)t : malloc(sizeof(uint32_t) * nn);
-    int64_t N = or_hist_hard(f, m, M + 12 * t, bins, boundary, h);
+    int64_t N = or_hist_hard_sampled(f, m, M + 12 * t, bins, boundary, fraction, seed, h);
     if (N < 0) {
       for (int a = 0; a < nq; ++a) mi[(size_t)t * nq + a] = NAN;
       overlap[t] = 0;
@@ -326,6 +357,12 @@ void or_eval_hard(const or_volume *f, const or_volume *m, const double *M, int n
     }
     if (!hist_out) free(h);
   }
+}
+
+void or_eval_hard(const or_volume *f, const or_volume *m, const double *M, int n, int bins,
+                  const double *qs, int nq, int boundary, int form, double *mi,
+                  int64_t *overlap, uint32_t *hist_out) {
+  or_eval_hard_sampled(f, m, M, n, bins, qs, nq, boundary, form, 1.0, 0, mi, overlap, hist_out);
 }
 
 /* ------------------------------------------------------------------ */
@@ -420,8 +457,8 @@ static psample parzen_sample(const or_volume *f, const or_volume *m, const int64
 /* Parzen joint table (unnormalised masses, fp64) of one transform.
  * Returns the number of voxels that took part (the normaliser N), or -1
  * when the transform is unusable. */
-int64_t or_parzen_table(const or_volume *f, const or_volume *m, const double M[12], int bins,
-                        int boundary, double *table) {
+int64_t or_parzen_table_sampled(const or_volume *f, const or_volume *m, const double M[12], int bins,
+                                int boundary, double fraction, uint64_t seed, double *table) {
   int64_t nn = (int64_t)bins * bins;
   for (int64_t e = 0; e < nn; ++e) table[e] = 0.0;
   int64_t Mq[12];
@@ -431,6 +468,7 @@ int64_t or_parzen_table(const or_volume *f, const or_volume *m, const double M[1
   for (int64_t k = 0; k < f->nz; ++k)
     for (int64_t j = 0; j < f->ny; ++j)
       for (int64_t i = 0; i < f->nx; ++i) {
+        if (!keep_voxel(fraction, seed, (k * f->ny + j) * f->nx + i)) continue;
         psample p = parzen_sample(f, m, Mq, bins, boundary, i, j, k);
         if (!p.take) continue;
         ++N;
@@ -440,6 +478,11 @@ int64_t or_parzen_table(const or_volume *f, const or_volume *m, const double M[1
   for (int64_t e = 0; e < nn; ++e) table[e] = (double)acc[e];
   free(acc);
   return N;
+}
+
+int64_t or_parzen_table(const or_volume *f, const or_volume *m, const double M[12], int bins,
+                        int boundary, double *table) {
+  return or_parzen_table_sampled(f, m, M, bins, boundary, 1.0, 0, table);
 }
 
 /* dMI/dp table for one q on a Parzen table h with normaliser N:
@@ -534,14 +577,14 @@ void or_grad_batch(const or_volume *f, const or_volume *m, const double *M, int 
 }
 
 /* Parzen MI (no gradient) of n transforms. */
-void or_eval_parzen(const or_volume *f, const or_volume *m, const double *M, int n, int bins,
-                    const double *qs, int nq, int boundary, int form, double *mi,
-                    int64_t *overlap) {
+void or_eval_parzen_sampled(const or_volume *f, const or_volume *m, const double *M, int n, int bins,
+                            const double *qs, int nq, int boundary, int form, double fraction,
+                            uint64_t seed, double *mi, int64_t *overlap) {
 #pragma omp parallel for schedule(dynamic, 1)
   for (int t = 0; t < n; ++t) {
     size_t nn = (size_t)bins * bins;
     double *h = malloc(sizeof(double) * nn);
-    int64_t N = or_parzen_table(f, m, M + 12 * t, bins, boundary, h);
+    int64_t N = or_parzen_table_sampled(f, m, M + 12 * t, bins, boundary, fraction, seed, h);
     if (N < 0) {
       for (int a = 0; a < nq; ++a) mi[(size_t)t * nq + a] = NAN;
       overlap[t] = 0;
@@ -551,6 +594,12 @@ void or_eval_parzen(const or_volume *f, const or_volume *m, const double *M, int
     }
     free(h);
   }
+}
+
+void or_eval_parzen(const or_volume *f, const or_volume *m, const double *M, int n, int bins,
+                    const double *qs, int nq, int boundary, int form, double *mi,
+                    int64_t *overlap) {
+  or_eval_parzen_sampled(f, m, M, n, bins, qs, nq, boundary, form, 1.0, 0, mi, overlap);
 }
 
 int or_num_threads(void) {

@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libgemi.so")
 MI_OK = 0
 MI_ERR_NULL, MI_ERR_DIMS, MI_ERR_DTYPE, MI_ERR_BINS, MI_ERR_RANGE = -1, -2, -3, -4, -5
 MI_ERR_Q, MI_ERR_WORKSPACE, MI_ERR_UNSUPPORTED, MI_ERR_FLAGS, MI_ERR_COUNT = -6, -7, -8, -9, -10
+MI_ERR_SAMPLE = -11
 MI_ERR_HIP, MI_ERR_NO_DEVICE = -20, -21
 U8, U16, I16, F32 = 0, 1, 2, 3
 BOUNDARY_EXCLUDE, BOUNDARY_CLAMP = 0x0, 0x1
@@ -26,6 +27,7 @@ TSALLIS_ADDITIVE, TSALLIS_PSEUDOADDITIVE = 0x0, 0x10
 HIST_HARD, HIST_PARZEN = 0x0, 0x100
 USE_GRAPH = 0x1000
 VOLUMES_UNCHANGED = 0x2000  # reuse the workspace's prepared volumes (see include/gemi.h)
+SAMPLED = 0x4000  # workspace sizing for eval_sampled
 TIMER_HARD, TIMER_PARZEN_FWD, TIMER_PARZEN_BWD, TIMER_PAIRS, TIMER_REDUCE = 0, 1, 2, 3, 4
 
 _TORCH_DTYPES = {torch.uint8: U8, torch.uint16: U16, torch.int16: I16, torch.float32: F32}
@@ -48,7 +50,7 @@ class MiPair(ctypes.Structure):
                 ("n_transforms", ctypes.c_int32)]
 
 
-EXPORTS = ["mi_create", "mi_destroy", "mi_workspace_size", "mi_eval", "mi_grad",
+EXPORTS = ["mi_create", "mi_destroy", "mi_workspace_size", "mi_eval", "mi_eval_sampled", "mi_grad",
            "mi_pairs_workspace_size", "mi_eval_pairs", "mi_tune", "mi_timing_enable",
            "mi_timing_read", "mi_probe_lds_atomics", "mi_map_paths", "mi_status_string"]
 
@@ -70,6 +72,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.mi_workspace_size.argtypes = [P(MiVolume), P(MiVolume), i32, i32, i32, i32, i32, P(sz)]
     lib.mi_eval.argtypes = [vp, P(MiVolume), P(MiVolume), vp, i32, i32, dp, i32, i32, vp, vp, vp,
                             vp, sz, vp]
+    lib.mi_eval_sampled.argtypes = [vp, P(MiVolume), P(MiVolume), vp, i32, i32, dp, i32, i32,
+                                    ctypes.c_double, ctypes.c_uint64, vp, vp, vp, vp, sz, vp]
     lib.mi_grad.argtypes = [vp, P(MiVolume), P(MiVolume), vp, i32, i32, dp, i32, i32, vp, vp, vp,
                             sz, vp]
     lib.mi_pairs_workspace_size.argtypes = [P(MiPair), i32, i32, i32, i32, P(sz)]
@@ -202,6 +206,29 @@ class Context:
                               bins, qp, len(qs), flags, _ptr(mi), _ptr(ov), _ptr(hist),
                               _ptr(workspace), workspace.numel(), self._stream(stream))
         _check(st, "mi_eval")
+        return mi, ov, hist
+
+    def eval_sampled(self, fixed: Volume, moving: Volume, transforms: torch.Tensor, bins: int, q=(1.0,),
+                     fraction: float = 0.1, seed: int = 0, flags: int = 0, want_hist: bool = False,
+                     want_overlap: bool = True, out=None, workspace: torch.Tensor | None = None, stream=None):
+        """MI[n][n_q] (+ overlap[n], hist) over a random subsample of the fixed
+        voxels (include/gemi.h, mi_eval_sampled): each kept with probability
+        ``fraction``, decided by SplitMix64 from (``seed``, voxel index)."""
+        dev = fixed.tensor.device
+        transforms = transforms.to(device=dev, dtype=torch.float64).reshape(-1, 12).contiguous()
+        n = transforms.shape[0]
+        qs, qp = _qarr(q)
+        mi = out if out is not None else torch.empty((n, len(qs)), dtype=torch.float64, device=dev)
+        ov = torch.empty(n, dtype=torch.int64, device=dev) if want_overlap else None
+        hist = torch.empty((n, bins, bins), dtype=torch.int32, device=dev) if want_hist else None
+        if workspace is None:
+            workspace = self.workspace(self.workspace_size(fixed, moving, n, bins, len(qs), flags | SAMPLED))
+        f, m = fixed.c(), moving.c()
+        st = self.lib.mi_eval_sampled(self.handle, ctypes.byref(f), ctypes.byref(m), _ptr(transforms), n, bins,
+                                      qp, len(qs), flags, float(fraction), int(seed) & (2 ** 64 - 1), _ptr(mi),
+                                      _ptr(ov), _ptr(hist), _ptr(workspace), workspace.numel(),
+                                      self._stream(stream))
+        _check(st, "mi_eval_sampled")
         return mi, ov, hist
 
     def grad(self, fixed: Volume, moving: Volume, transforms: torch.Tensor, bins: int, q=(1.0,),

@@ -91,8 +91,16 @@ int check_moving(const mi_volume* m, bool need_integer) {
   return gather_bytes(m) > kMaxGatherBytes ? MI_ERR_DIMS : MI_OK;
 }
 
-constexpr int32_t kKnownFlags =
-    MI_BOUNDARY_CLAMP | MI_TSALLIS_PSEUDOADDITIVE | MI_HIST_PARZEN | MI_USE_GRAPH | MI_VOLUMES_UNCHANGED;
+constexpr int32_t kKnownFlags = MI_BOUNDARY_CLAMP | MI_TSALLIS_PSEUDOADDITIVE | MI_HIST_PARZEN | MI_USE_GRAPH |
+                                MI_VOLUMES_UNCHANGED | MI_SAMPLED;
+
+// Random subsampling of the fixed volume (mi_eval_sampled).
+struct SampleSpec {
+  double fraction;  // share of fixed voxels kept (>= 1: all)
+  uint64_t seed;
+};
+
+int check_fraction(double fraction) { return (isfinite(fraction) && fraction > 0.0) ? MI_OK : MI_ERR_SAMPLE; }
 
 int check_common(const mi_volume* f, const mi_volume* m, int32_t n, int32_t bins, const double* q,
                  int32_t n_q, int32_t flags, bool parzen) {
@@ -118,14 +126,15 @@ int check_common(const mi_volume* f, const mi_volume* m, int32_t n, int32_t bins
 //                occupied-row map, table f64[n][B][B], count u64[n]
 //                MI partial sums (reduce_part_bytes)
 //   Parzen grad: + table marginals f64[n][2B], dMI/dp tables f32[n][n_q][B][B]
+//   sampled:     + sample list u32x2[nvox_fixed] and its length u64
 struct Layout {
   size_t fbins = 0, gvol = 0, hist = 0, rowmap = 0, table = 0, count = 0, part = 0, marg = 0, gtab = 0,
-         total = 0;
+         list = 0, nlist = 0, total = 0;
 };
 
 
 Layout layout(const mi_volume* f, const mi_volume* m, int32_t n, int32_t bins, int32_t n_q,
-              bool parzen, bool grad, bool need_hist) {
+              bool parzen, bool grad, bool need_hist, bool sampled = false) {
   Layout L;
   size_t off = 0;
   L.fbins = off;
@@ -157,6 +166,12 @@ Layout layout(const mi_volume* f, const mi_volume* m, int32_t n, int32_t bins, i
       L.gtab = off;
       off += align256(bb * 4 * (size_t)n * n_q);
     }
+  }
+  if (sampled) {
+    L.list = off;
+    off += align256(8 * voxels(f));
+    L.nlist = off;
+    off += 256;
   }
   L.total = off;
   return L;
@@ -324,6 +339,24 @@ int plan_parzen_chunks(const mi_context* ctx, const mi_volume* f, const mi_volum
   return (int)(((c + 7) / 8) * 8);
 }
 
+// Workgroups per transform (and band) for a sampled sweep over about
+// `expected` samples: enough to fill the chip, but at least ~4096 samples
+// per workgroup so that zeroing and flushing its LDS table stay small; a
+// multiple of 8 (one share per XCD).
+int plan_sampled_chunks(const mi_context* ctx, int64_t expected, int64_t units) {
+  int64_t c = ((int64_t)ctx->cu_count * 8 + units - 1) / units;
+  const int64_t cap = std::max<int64_t>(8, expected / 4096);
+  if (c > cap) c = cap;
+  if (c < 8) c = 8;
+  c = ((c + 7) / 8) * 8;
+  return (int)std::min<int64_t>(c, 1 << 20);
+}
+
+int64_t expected_samples(const mi_volume* f, const SampleSpec& smp) {
+  const double nv = (double)voxels(f);
+  return smp.fraction >= 1.0 ? (int64_t)nv : (int64_t)ceil(smp.fraction * nv);
+}
+
 // Rows of the table per band when `tables` fp32 tables of `bins` columns
 // share a 64 KiB LDS budget.
 int32_t band_rows_for(int32_t bins, int32_t tables) {
@@ -335,18 +368,28 @@ int32_t band_rows_for(int32_t bins, int32_t tables) {
 int run_parzen(mi_context* ctx, const mi_volume* fixed, const mi_volume* moving,
                const double* transforms, int32_t n, int32_t bins, const double* q, int32_t n_q,
                int32_t flags, double* mi_out, uint64_t* overlap_out, double* grad_out, char* ws,
-               const Layout& L, hipStream_t s) {
+               const Layout& L, hipStream_t s, const SampleSpec* smp = nullptr) {
   hipError_t e;
   uint8_t* fb = (uint8_t*)(ws + L.fbins);
   RowMap* rows = (RowMap*)(ws + L.rowmap);
   const bool fq = moving->dtype == MI_F32;
   void* gvol = ws + L.gvol;
-  if (!reuse_prep(ctx, flags, prep_key(2, ws, fixed, moving, bins))) {
+  // a sampled call always prepares (its list is not part of the record)
+  if (smp || !reuse_prep(ctx, flags, prep_key(2, ws, fixed, moving, bins))) {
     if ((e = launch_prebin_fixed(desc(fixed), bins, fb, s)) != hipSuccess) return hip_fail(e, "prebin");
     if ((e = launch_row_map(fb, voxels(fixed), bins, rows, s)) != hipSuccess) return hip_fail(e, "row map");
     e = fq ? launch_pack_quads_f32(desc(moving), (float4*)gvol, s)
            : launch_pack_octs(desc(moving), (uint4*)gvol, s);
     if (e != hipSuccess) return hip_fail(e, "pack");
+  }
+  uint2* list = (uint2*)(ws + L.list);
+  unsigned long long* nlist = (unsigned long long*)(ws + L.nlist);
+  if (smp) {
+    ctx->last_prep.clear();
+    if ((e = launch_fill_u32((uint32_t*)nlist, 2, 0u, s)) != hipSuccess) return hip_fail(e, "fill");
+    if ((e = launch_sample_list(fb, fixed->nx, fixed->ny, fixed->nz, smp->fraction, smp->seed, list, nlist, s)) !=
+        hipSuccess)
+      return hip_fail(e, "sample list");
   }
   const size_t bb = (size_t)bins * bins;
   double* table = (double*)(ws + L.table);
@@ -392,7 +435,8 @@ int run_parzen(mi_context* ctx, const mi_volume* fixed, const mi_volume* moving,
     pa.band_rows = backward ? band_rows_for(bins, kParzenQGroup)
                             : std::min(bins, std::max(1, 65536 / (8 * bins) - (kHotCopies - 1)));
     pa.bands = (bins + pa.band_rows - 1) / pa.band_rows;
-    pa.chunks = plan_parzen_chunks(ctx, fixed, moving, (int64_t)n * pa.bands);
+    pa.chunks = smp ? plan_sampled_chunks(ctx, expected_samples(fixed, *smp), (int64_t)n * pa.bands)
+                    : plan_parzen_chunks(ctx, fixed, moving, (int64_t)n * pa.bands);
     const int64_t per_launch = 0x7FFFFFFFll / ((int64_t)pa.chunks * pa.bands);
     for (int64_t t0 = 0; t0 < n; t0 += per_launch) {
       pa.n = (int32_t)(n - t0 < per_launch ? n - t0 : per_launch);
@@ -402,7 +446,9 @@ int run_parzen(mi_context* ctx, const mi_volume* fixed, const mi_volume* moving,
       pa.gtab = (const float*)(ws + L.gtab) + bb * n_q * t0;
       pa.grad = grad_out ? grad_out + (size_t)n_q * 12 * t0 : nullptr;
       TimedLaunch tl(ctx, which, s);
-      hipError_t err = backward ? launch_parzen_bwd(part, s) : launch_parzen_fwd(part, s);
+      hipError_t err = backward ? launch_parzen_bwd(part, s)
+                       : smp      ? launch_parzen_sampled_fwd(part, list, nlist, s)
+                                  : launch_parzen_fwd(part, s);
       if (err != hipSuccess) return hip_fail(err, backward ? "parzen_bwd" : "parzen_fwd");
       tl.done();
     }
@@ -642,12 +688,13 @@ int graph_run(mi_context* ctx, const std::vector<uint64_t>& key, hipStream_t s, 
 int launch_hard_hist(mi_context* ctx, const mi_volume* fixed, const mi_volume* moving,
                      const double* transforms, int32_t n, int32_t bins, int32_t flags,
                      uint32_t* hist, char* ws, const Layout& L, hipStream_t s,
-                     const HardTune& tune, bool prepare) {
+                     const HardTune& tune, bool prepare, const SampleSpec* smp = nullptr) {
   hipError_t e;
   uint8_t* fb = (uint8_t*)(ws + L.fbins);
   void* octs = ws + L.gvol;
   const size_t bb = (size_t)bins * bins;
-  if (prepare && !reuse_prep(ctx, flags, prep_key(1, ws, fixed, moving, bins))) {
+  // a sampled call always prepares (its list is not part of the record)
+  if (prepare && (smp || !reuse_prep(ctx, flags, prep_key(1, ws, fixed, moving, bins)))) {
     if ((e = launch_prebin_fixed(desc(fixed), bins, fb, s)) != hipSuccess) return hip_fail(e, "prebin");
     e = oct8_range(moving->lo, moving->hi) ? launch_pack_oct8(desc(moving), (uint2*)octs, s)
                                            : launch_pack_octs(desc(moving), (uint4*)octs, s);
@@ -667,7 +714,19 @@ int launch_hard_hist(mi_context* ctx, const mi_volume* fixed, const mi_volume* m
   H.packed = use_packed(tune, bins) ? 1 : 0;
   H.block = tune.block;
   H.slab_major = tune.slab_major;
-  H.chunks = plan_chunks(ctx, fixed, moving, n, H.packed != 0, tune);
+  uint2* list = (uint2*)(ws + L.list);
+  unsigned long long* nlist = (unsigned long long*)(ws + L.nlist);
+  if (smp) {
+    ctx->last_prep.clear();
+    if ((e = launch_fill_u32((uint32_t*)nlist, 2, 0u, s)) != hipSuccess) return hip_fail(e, "fill");
+    if ((e = launch_sample_list(fb, fixed->nx, fixed->ny, fixed->nz, smp->fraction, smp->seed, list, nlist, s)) !=
+        hipSuccess)
+      return hip_fail(e, "sample list");
+    H.packed = bins > 128 ? 1 : 0;
+    H.chunks = plan_sampled_chunks(ctx, expected_samples(fixed, *smp), n);
+  } else {
+    H.chunks = plan_chunks(ctx, fixed, moving, n, H.packed != 0, tune);
+  }
   // one launch covers at most 2^31 - 1 workgroups: split the transforms
   const int64_t per_launch = 0x7FFFFFFFll / H.chunks;
   for (int64_t t0 = 0; t0 < n; t0 += per_launch) {
@@ -676,7 +735,8 @@ int launch_hard_hist(mi_context* ctx, const mi_volume* fixed, const mi_volume* m
     part.transforms = transforms + 12 * t0;
     part.hist = hist + bb * t0;
     TimedLaunch tl(ctx, 0, s);
-    if ((e = launch_hist_hard(part, s)) != hipSuccess) return hip_fail(e, "hist_hard");
+    e = smp ? launch_hist_sampled(part, list, nlist, s) : launch_hist_hard(part, s);
+    if (e != hipSuccess) return hip_fail(e, smp ? "hist_sampled" : "hist_hard");
     tl.done();
   }
   return MI_OK;
@@ -685,9 +745,9 @@ int launch_hard_hist(mi_context* ctx, const mi_volume* fixed, const mi_volume* m
 int run_hard(mi_context* ctx, const mi_volume* fixed, const mi_volume* moving,
              const double* transforms, int32_t n, int32_t bins, const double* q, int32_t n_q,
              int32_t flags, double* mi_out, uint64_t* overlap_out, uint32_t* hist_out, char* ws,
-             const Layout& L, hipStream_t s, const HardTune& tune) {
+             const Layout& L, hipStream_t s, const HardTune& tune, const SampleSpec* smp = nullptr) {
   uint32_t* hist = hist_out ? hist_out : (uint32_t*)(ws + L.hist);
-  int st = launch_hard_hist(ctx, fixed, moving, transforms, n, bins, flags, hist, ws, L, s, tune, true);
+  int st = launch_hard_hist(ctx, fixed, moving, transforms, n, bins, flags, hist, ws, L, s, tune, true, smp);
   if (st != MI_OK) return st;
   ReduceLaunch R;
   memset(&R, 0, sizeof R);
@@ -723,6 +783,7 @@ const char* mi_status_string(int status) {
   case MI_ERR_WORKSPACE: return "workspace NULL or too small";
   case MI_ERR_UNSUPPORTED: return "request not supported";
   case MI_ERR_FLAGS: return "unknown flag bits";
+  case MI_ERR_SAMPLE: return "sampling fraction not finite or not above 0";
   case MI_ERR_COUNT: return "transform or pair count out of range";
   case MI_ERR_HIP: {
     static thread_local std::string s;
@@ -795,7 +856,8 @@ int mi_workspace_size(const mi_volume* fixed, const mi_volume* moving, int32_t n
   int st = check_common(fixed, moving, n, bins, nullptr, 0, flags, parzen);
   if (st != MI_OK) return st;
   if (n_q < 1 || n_q > MI_MAX_Q) return MI_ERR_Q;
-  *bytes = layout(fixed, moving, n, bins, n_q, parzen, for_grad != 0, true).total;
+  if ((flags & MI_SAMPLED) && for_grad) return MI_ERR_UNSUPPORTED;
+  *bytes = layout(fixed, moving, n, bins, n_q, parzen, for_grad != 0, true, (flags & MI_SAMPLED) != 0).total;
   return MI_OK;
 }
 
@@ -804,6 +866,7 @@ int mi_tune(mi_context* ctx, const mi_volume* fixed, const mi_volume* moving,
             size_t workspace_bytes, void* stream) {
   int st = check_common(fixed, moving, n, bins, nullptr, 0, flags & ~MI_USE_GRAPH, false);
   if (st != MI_OK) return st;
+  if (flags & MI_SAMPLED) return MI_ERR_FLAGS;
   if (flags & MI_HIST_PARZEN) return MI_ERR_UNSUPPORTED;
   if (n > 0 && !transforms) return MI_ERR_NULL;
   const Layout L = layout(fixed, moving, n, bins, 1, false, false, true);
@@ -914,6 +977,7 @@ int mi_eval(mi_context* ctx, const mi_volume* fixed, const mi_volume* moving,
   const bool parzen = (flags & MI_HIST_PARZEN) != 0;
   int st = check_common(fixed, moving, n, bins, q, n_q, flags, parzen);
   if (st != MI_OK) return st;
+  if (flags & MI_SAMPLED) return MI_ERR_FLAGS;  // mi_eval_sampled
   if ((st = check_q(q, n_q)) != MI_OK) return st;
   if (n > 0 && (!transforms || !mi_out)) return MI_ERR_NULL;
   if (parzen && hist_out) return MI_ERR_UNSUPPORTED;
@@ -949,12 +1013,56 @@ int mi_eval(mi_context* ctx, const mi_volume* fixed, const mi_volume* moving,
   return st;
 }
 
+int mi_eval_sampled(mi_context* ctx, const mi_volume* fixed, const mi_volume* moving,
+                    const double* transforms, int32_t n, int32_t bins, const double* q, int32_t n_q,
+                    int32_t flags, double fraction, uint64_t seed, double* mi_out, uint64_t* overlap_out,
+                    uint32_t* hist_out, void* workspace, size_t workspace_bytes, void* stream) {
+  const bool parzen = (flags & MI_HIST_PARZEN) != 0;
+  int st = check_common(fixed, moving, n, bins, q, n_q, flags, parzen);
+  if (st != MI_OK) return st;
+  if ((st = check_q(q, n_q)) != MI_OK) return st;
+  if ((st = check_fraction(fraction)) != MI_OK) return st;
+  if (n > 0 && (!transforms || !mi_out)) return MI_ERR_NULL;
+  if (parzen && hist_out) return MI_ERR_UNSUPPORTED;
+  const Layout L = layout(fixed, moving, n, bins, n_q, parzen, false, hist_out == nullptr, true);
+  if (!workspace || workspace_bytes < L.total) return MI_ERR_WORKSPACE;
+  if (!ctx) return MI_ERR_NULL;
+  if (n == 0) return MI_OK;
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e;
+  if ((e = hipSetDevice(ctx->device)) != hipSuccess) return hip_fail(e, "hipSetDevice");
+  char* ws = (char*)workspace;
+  const SampleSpec smp = {fraction, seed};
+  const int32_t run_flags = flags & ~(MI_VOLUMES_UNCHANGED | MI_SAMPLED);
+  auto body = [&]() -> int {
+    if (parzen)
+      return run_parzen(ctx, fixed, moving, transforms, n, bins, q, n_q, run_flags, mi_out, overlap_out,
+                        nullptr, ws, L, s, &smp);
+    return run_hard(ctx, fixed, moving, transforms, n, bins, q, n_q, run_flags, mi_out, overlap_out,
+                    hist_out, ws, L, s, tune_for(ctx, fixed, moving, n, bins, flags), &smp);
+  };
+  if (!use_graph(ctx, flags, s)) return body();
+  uint64_t fbits;
+  memcpy(&fbits, &fraction, 8);
+  std::vector<uint64_t> key = {4, (uint64_t)(uintptr_t)transforms, (uint64_t)n, (uint64_t)bins,
+                               (uint64_t)flags, fbits, seed, (uint64_t)(uintptr_t)mi_out,
+                               (uint64_t)(uintptr_t)overlap_out, (uint64_t)(uintptr_t)hist_out,
+                               (uint64_t)(uintptr_t)workspace, (uint64_t)(uintptr_t)s};
+  key_volume(key, fixed);
+  key_volume(key, moving);
+  key_q(key, q, n_q);
+  st = graph_run(ctx, key, s, body);
+  ctx->last_prep.clear();
+  return st;
+}
+
 int mi_grad(mi_context* ctx, const mi_volume* fixed, const mi_volume* moving,
             const double* transforms, int32_t n, int32_t bins, const double* q, int32_t n_q,
             int32_t flags, double* mi_out, double* grad_out, void* workspace,
             size_t workspace_bytes, void* stream) {
   int st = check_common(fixed, moving, n, bins, q, n_q, flags, true);
   if (st != MI_OK) return st;
+  if (flags & MI_SAMPLED) return MI_ERR_FLAGS;
   if ((st = check_q(q, n_q)) != MI_OK) return st;
   if (n > 0 && (!transforms || !mi_out || !grad_out)) return MI_ERR_NULL;
   const Layout L = layout(fixed, moving, n, bins, n_q, true, true, false);

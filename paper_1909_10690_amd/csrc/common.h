@@ -309,6 +309,12 @@ hipError_t launch_prebin_fixed(const VolumeDesc& f, int bins, uint8_t* out, hipS
 hipError_t launch_pack_octs(const VolumeDesc& m, uint4* out, hipStream_t s);
 hipError_t launch_pack_oct8(const VolumeDesc& m, uint2* out, hipStream_t s);
 hipError_t launch_hist_hard(const HardLaunch& L, hipStream_t s);
+// Random subsampling (sample.hip): the kept fixed voxels as list entries
+// {x | y << 12 | fixed bin << 24, z}; n_list must be zero beforehand.
+hipError_t launch_sample_list(const uint8_t* fbins, int32_t nx, int32_t ny, int32_t nz, double fraction,
+                              uint64_t seed, uint2* list, unsigned long long* n_list, hipStream_t s);
+hipError_t launch_hist_sampled(const HardLaunch& L, const uint2* list, const unsigned long long* n_list,
+                               hipStream_t s);
 
 // Many fixed/moving pairs of uneven sizes (see pairs.hip).
 struct PairDesc {
@@ -351,6 +357,8 @@ hipError_t launch_mi_reduce(const ReduceLaunch& L, hipStream_t s);
 hipError_t launch_pack_quads_f32(const VolumeDesc& m, float4* out, hipStream_t s);
 hipError_t launch_row_map(uint8_t* fbins, size_t nvox, int32_t bins, RowMap* m, hipStream_t s);
 hipError_t launch_parzen_fwd(const ParzenLaunch& L, hipStream_t s);
+hipError_t launch_parzen_sampled_fwd(const ParzenLaunch& L, const uint2* list, const unsigned long long* n_list,
+                                     hipStream_t s);
 hipError_t launch_dmi_dp(const ParzenLaunch& L, const QList& q, hipStream_t s);
 hipError_t launch_parzen_bwd(const ParzenLaunch& L, hipStream_t s);
 hipError_t configure_kernels();

@@ -219,6 +219,56 @@ void hist_hard_kernel(HardArgs a) {
   if (ok) flush_hist<PACKED, NT>(lds_hist, B, a.hist + (size_t)t * B * B, false);
 }
 
+// Sampled sweep: the workgroup's share of the sample list (entries
+// {x | y << 12 | fixed bin << 24, z}) for one transform, each sample's Q32
+// coordinates formed straight from the matrix.  With 16-bit counters the
+// share is counted in spans of at most 65535 samples, each flushed before
+// the next, so no counter can overflow whatever the sample count.
+template <bool CLAMP, bool PACKED, bool OCT8, int NT>
+__global__ __launch_bounds__(NT) void hist_sampled_kernel(HardArgs a, const uint2* __restrict__ list,
+                                                          const unsigned long long* __restrict__ n_list) {
+  extern __shared__ uint32_t lds_hist[];
+  const int B = a.geom.bins;
+  const int words = PACKED ? (B * B + 1) / 2 : B * B;
+  for (int e = threadIdx.x; e < words; e += NT) lds_hist[e] = 0;
+  uint32_t t, chunk, band;
+  block_work(a.chunks, a.n, 1, a.slab_major, t, chunk, band);
+  int64_t Mq[12];
+  const bool ok = quantize_transform(a.transforms + 12 * (size_t)t, Mq);
+  const int64_t ns = (int64_t)*n_list;
+  const int64_t s0 = ns * chunk / a.chunks, s1 = ns * (chunk + 1) / a.chunks;
+  const int64_t span = PACKED ? 65535 : s1 - s0;
+  const HardStep hs(a.geom, lds_hist);
+  uint32_t* out = a.hist + (size_t)t * B * B;
+  for (int64_t p0 = s0; p0 < s1; p0 += span) {
+    const int64_t p1 = p0 + span < s1 ? p0 + span : s1;
+    __syncthreads();
+    if (ok) {
+      for (int64_t e = p0 + threadIdx.x; e < p1; e += NT) {
+        const uint2 en = list[e];
+        const int64_t x = en.x & 0xFFFu, y = (en.x >> 12) & 0xFFFu, z = en.y;
+        const uint32_t fb = en.x >> 24;
+        const int64_t qx = Mq[0] * x + Mq[1] * y + Mq[2] * z + Mq[3];
+        const int64_t qy = Mq[4] * x + Mq[5] * y + Mq[6] * z + Mq[7];
+        const int64_t qz = Mq[8] * x + Mq[9] * y + Mq[10] * z + Mq[11];
+        hs.count<CLAMP, PACKED, OCT8>(qx, qy, qz, [&] { return fb; }, lds_hist);
+      }
+    }
+    __syncthreads();
+    if (ok) flush_hist<PACKED, NT>(lds_hist, B, out, true);
+  }
+}
+
+constexpr int kSampledBlock = 512;
+
+template <bool CLAMP, bool PACKED, bool OCT8>
+static hipError_t launch_sampled_variant(const HardArgs& a, const uint2* list, const unsigned long long* n_list,
+                                         size_t lds, hipStream_t s) {
+  hipLaunchKernelGGL((hist_sampled_kernel<CLAMP, PACKED, OCT8, kSampledBlock>), dim3((unsigned)(a.n * a.chunks)),
+                     dim3(kSampledBlock), lds, s, a, list, n_list);
+  return hipGetLastError();
+}
+
 template <bool CLAMP, bool PACKED, bool OCT8, int NT>
 static hipError_t launch_variant(const HardArgs& a, int n, size_t lds, hipStream_t s) {
   hipLaunchKernelGGL((hist_hard_kernel<CLAMP, PACKED, OCT8, NT>), dim3((unsigned)(n * a.chunks)),
@@ -282,6 +332,30 @@ hipError_t launch_hist_hard(const HardLaunch& L, hipStream_t s) {
   }
 }
 
+hipError_t launch_hist_sampled(const HardLaunch& L, const uint2* list, const unsigned long long* n_list,
+                               hipStream_t s) {
+  if (L.n == 0) return hipSuccess;
+  HardArgs a;
+  a.transforms = L.transforms;
+  a.hist = L.hist;
+  a.geom = make_hard_geom(L.fixed, L.moving, L.fbins, L.octs, L.bins);
+  a.n = L.n;
+  a.chunks = L.chunks;
+  a.slab_major = 1;
+  const size_t lds = L.packed ? (((size_t)L.bins * L.bins + 1) / 2) * 4 : (size_t)L.bins * L.bins * 4;
+  const bool o8 = a.geom.oct8 != 0;
+  if (L.clamp) {
+    if (L.packed) return o8 ? launch_sampled_variant<true, true, true>(a, list, n_list, lds, s)
+                            : launch_sampled_variant<true, true, false>(a, list, n_list, lds, s);
+    return o8 ? launch_sampled_variant<true, false, true>(a, list, n_list, lds, s)
+              : launch_sampled_variant<true, false, false>(a, list, n_list, lds, s);
+  }
+  if (L.packed) return o8 ? launch_sampled_variant<false, true, true>(a, list, n_list, lds, s)
+                          : launch_sampled_variant<false, true, false>(a, list, n_list, lds, s);
+  return o8 ? launch_sampled_variant<false, false, true>(a, list, n_list, lds, s)
+            : launch_sampled_variant<false, false, false>(a, list, n_list, lds, s);
+}
+
 template <int NT>
 static hipError_t allow_big_lds() {
   const int bytes = 160 * 1024;
@@ -299,6 +373,18 @@ static hipError_t allow_big_lds() {
 
 hipError_t configure_hard_kernels() {
   hipError_t e;
+  const void* sampled[8] = {
+      (const void*)hist_sampled_kernel<false, false, false, kSampledBlock>,
+      (const void*)hist_sampled_kernel<true, false, false, kSampledBlock>,
+      (const void*)hist_sampled_kernel<false, true, false, kSampledBlock>,
+      (const void*)hist_sampled_kernel<true, true, false, kSampledBlock>,
+      (const void*)hist_sampled_kernel<false, false, true, kSampledBlock>,
+      (const void*)hist_sampled_kernel<true, false, true, kSampledBlock>,
+      (const void*)hist_sampled_kernel<false, true, true, kSampledBlock>,
+      (const void*)hist_sampled_kernel<true, true, true, kSampledBlock>};
+  for (const void* f : sampled)
+    if ((e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024)) != hipSuccess)
+      return e;
   if ((e = allow_big_lds<256>()) != hipSuccess) return e;
   if ((e = allow_big_lds<512>()) != hipSuccess) return e;
   return allow_big_lds<1024>();

@@ -227,6 +227,97 @@ __device__ __forceinline__ size_t band_cell_row(const RowMap* m, int32_t r_lo, i
 // its cells, and same-address LDS atomics serialise.  The band holding it
 // keeps kHotCopies copies of that row, lane l adding into copy l % kHotCopies;
 // the copies are summed at the flush.
+// Per-launch constants of the forward step of one fixed voxel.
+struct ParzenFwdStep {
+  __amdgpu_buffer_rsrc_t rsrc;
+  uint64_t top[3];
+  uint32_t NY, MX;
+  int32_t SZ;  // fp32 quads: bytes to the next slice
+  int B;
+  float sscale, smax;
+
+  template <bool FQ>
+  __device__ __forceinline__ static ParzenFwdStep make(const ParzenArgs& a) {
+    ParzenFwdStep p;
+    p.top[0] = (uint64_t)(a.mnx - 1) << 32;
+    p.top[1] = (uint64_t)(a.mny - 1) << 32;
+    p.top[2] = (uint64_t)(a.mnz - 1) << 32;
+    p.NY = (uint32_t)a.mny;
+    p.MX = (uint32_t)a.mnx;
+    p.SZ = FQ ? 16 * a.mnx * a.mny : 0;
+    p.rsrc = __builtin_amdgcn_make_buffer_rsrc((void*)a.gvol, (short)0, (int)a.gvol_bytes, 0x00020000);
+    p.B = a.bins;
+    p.sscale = a.sscale;
+    p.smax = (float)(p.B - 3);
+    return p;
+  }
+
+  // One fixed voxel at exact Q32 moving coordinates q: clamped (CLAMP) or
+  // dropped outside [0, n - 1]; if it lies inside and its slot (from
+  // slot_of()) falls in the band's rows, its four B-spline taps go into the
+  // LDS table.  Returns whether the voxel takes part (inside).
+  template <bool FQ, bool CLAMP, typename SLOT>
+  __device__ __forceinline__ bool add(const int64_t q[3], SLOT&& slot_of, const SweepCtx& sc, int cells,
+                                      int copy, unsigned long long* lds_tab) const {
+    uint64_t cq[3];
+    bool inside = true;
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      cq[r] = (uint64_t)q[r];
+      if (CLAMP) cq[r] = q[r] < 0 ? 0 : (cq[r] > top[r] ? top[r] : cq[r]);
+      else inside = inside && cq[r] <= top[r];
+    }
+    if (!inside) return false;
+    const int32_t fb = slot_of();
+    if (fb < sc.r_lo || fb >= sc.r_hi) return true;
+    const uint32_t idx = __umul24(__umul24((uint32_t)(cq[2] >> 32), NY) + (uint32_t)(cq[1] >> 32), MX) +
+                         (uint32_t)(cq[0] >> 32);
+    float c[2][2][2];
+    gather<FQ>(rsrc, idx, SZ, c);
+    const float tx = (float)(uint32_t)cq[0] * 2.3283064365386963e-10f;
+    const float ty = (float)(uint32_t)cq[1] * 2.3283064365386963e-10f;
+    const float tz = (float)(uint32_t)cq[2] * 2.3283064365386963e-10f;
+    const float v0 = lerpf(lerpf(c[0][0][0], c[0][0][1], tx), lerpf(c[0][1][0], c[0][1][1], tx), ty);
+    const float v1 = lerpf(lerpf(c[1][0][0], c[1][0][1], tx), lerpf(c[1][1][0], c[1][1][1], tx), ty);
+    const float v = lerpf(v0, v1, tz);
+    const float s = fminf(fmaxf(fmaf(v, sscale, 1.0f), 1.0f), smax);
+    const float fl = floorf(s);
+    float wt[4];
+    bspline_weights(s - fl, wt);
+    const unsigned long long q0 = fixed40(wt[0]), q2 = fixed40(wt[2]), q3 = fixed40(wt[3]);
+    const unsigned long long q1 = (1ull << 40) - q0 - q2 - q3;  // w1 >= 1/6
+    int base = (fb - sc.r_lo) * B + ((int32_t)fl - 1);
+    if (fb == 0 && copy) base += cells + (copy - 1) * B;  // slot 0: lane's copy of the row
+    unsigned long long* cell = lds_tab + base;
+    atomicAdd(cell + 0, q0);
+    atomicAdd(cell + 1, q1);
+    atomicAdd(cell + 2, q2);
+    atomicAdd(cell + 3, q3);
+    return true;
+  }
+};
+
+// Adds the band's LDS table into the transform's HBM table (fp64) and, from
+// band 0, the count of voxels that took part.
+template <int NT>
+__device__ __forceinline__ void flush_parzen(const ParzenArgs& a, const SweepCtx& sc, int cells, int hot_cells,
+                                             const unsigned long long* lds_tab, uint32_t lds_count) {
+  const int B = a.bins;
+  double* __restrict__ out = a.table + (size_t)sc.t * B * B;
+  for (int e = threadIdx.x; e < cells; e += NT) {
+    unsigned long long v = lds_tab[e];
+    if (e < hot_cells / (kHotCopies - 1))
+      for (int c = 1; c < kHotCopies; ++c) v += lds_tab[cells + (c - 1) * B + e];
+    if (v) {
+      int col;
+      const size_t row = band_cell_row(a.rows, sc.r_lo, e, B, col);
+      atomicAdd(&out[row + col], (double)v * 9.094947017729282379150390625e-13);  // 2^-40
+    }
+  }
+  if (threadIdx.x == 0 && sc.band == 0 && lds_count)
+    atomicAdd((unsigned long long*)&a.count[sc.t], (unsigned long long)lds_count);
+}
+
 template <bool FQ, bool CLAMP, int NT>
 __global__ __launch_bounds__(NT) void parzen_fwd_kernel(ParzenArgs a) {
   extern __shared__ __align__(16) unsigned long long lds_tab[];
@@ -253,13 +344,7 @@ __global__ __launch_bounds__(NT) void parzen_fwd_kernel(ParzenArgs a) {
     const int dx = lane & (kTileX - 1), dy = lane / kTileX;
     GroupWalk w;
     w.init(Mq, a.fny, a.fnz, a.chunks, sc.chunk, wave, NT / 64, dx, dy);
-    const uint64_t top[3] = {(uint64_t)(a.mnx - 1) << 32, (uint64_t)(a.mny - 1) << 32,
-                             (uint64_t)(a.mnz - 1) << 32};
-    const uint32_t NY = (uint32_t)a.mny, MX = (uint32_t)a.mnx;
-    const int32_t SZ = FQ ? 16 * a.mnx * a.mny : 0;  // fp32 quads: next slice
-    const __amdgpu_buffer_rsrc_t rsrc =
-        __builtin_amdgcn_make_buffer_rsrc((void*)a.gvol, (short)0, (int)a.gvol_bytes, 0x00020000);
-    const float smax = (float)(B - 3);
+    const ParzenFwdStep ps = ParzenFwdStep::template make<FQ>(a);
     for (; w.g < w.g1; w.next()) {
       const int32_t j = w.j0 + dy;
       if (j >= a.fny) continue;
@@ -268,61 +353,60 @@ __global__ __launch_bounds__(NT) void parzen_fwd_kernel(ParzenArgs a) {
 #pragma unroll
       for (int r = 0; r < 3; ++r) q[r] = w.r[r] + w.lane_off[r];
       for (int x = dx; x < a.fnx; x += kTileX) {
-        uint64_t cq[3];
-        bool inside = true;
+        taken += ps.add<FQ, CLAMP>(q, [&] { return (int32_t)frow[x]; }, sc, cells, copy, lds_tab);
 #pragma unroll
-        for (int r = 0; r < 3; ++r) {
-          cq[r] = (uint64_t)q[r];
-          if (CLAMP) cq[r] = q[r] < 0 ? 0 : (cq[r] > top[r] ? top[r] : cq[r]);
-          else inside = inside && cq[r] <= top[r];
-          q[r] += w.step[r];
-        }
-        if (!inside) continue;
-        ++taken;
-        const int32_t fb = frow[x];
-        if (fb < sc.r_lo || fb >= sc.r_hi) continue;
-        const uint32_t idx = __umul24(__umul24((uint32_t)(cq[2] >> 32), NY) + (uint32_t)(cq[1] >> 32), MX) +
-                             (uint32_t)(cq[0] >> 32);
-        float c[2][2][2];
-        gather<FQ>(rsrc, idx, SZ, c);
-        const float tx = (float)(uint32_t)cq[0] * 2.3283064365386963e-10f;
-        const float ty = (float)(uint32_t)cq[1] * 2.3283064365386963e-10f;
-        const float tz = (float)(uint32_t)cq[2] * 2.3283064365386963e-10f;
-        const float v0 = lerpf(lerpf(c[0][0][0], c[0][0][1], tx), lerpf(c[0][1][0], c[0][1][1], tx), ty);
-        const float v1 = lerpf(lerpf(c[1][0][0], c[1][0][1], tx), lerpf(c[1][1][0], c[1][1][1], tx), ty);
-        const float v = lerpf(v0, v1, tz);
-        const float s = fminf(fmaxf(fmaf(v, a.sscale, 1.0f), 1.0f), smax);
-        const float fl = floorf(s);
-        float wt[4];
-        bspline_weights(s - fl, wt);
-        const unsigned long long q0 = fixed40(wt[0]), q2 = fixed40(wt[2]), q3 = fixed40(wt[3]);
-        const unsigned long long q1 = (1ull << 40) - q0 - q2 - q3;  // w1 >= 1/6
-        int base = (fb - sc.r_lo) * B + ((int32_t)fl - 1);
-        if (fb == 0 && copy) base += cells + (copy - 1) * B;  // slot 0: lane's copy of the row
-        unsigned long long* cell = lds_tab + base;
-        atomicAdd(cell + 0, q0);
-        atomicAdd(cell + 1, q1);
-        atomicAdd(cell + 2, q2);
-        atomicAdd(cell + 3, q3);
+        for (int r = 0; r < 3; ++r) q[r] += w.step[r];
       }
     }
   }
   if (sc.band == 0 && taken) atomicAdd(&lds_count, taken);
   __syncthreads();
   if (!ok) return;
-  double* __restrict__ out = a.table + (size_t)sc.t * B * B;
-  for (int e = threadIdx.x; e < cells; e += NT) {
-    unsigned long long v = lds_tab[e];
-    if (e < hot_cells / (kHotCopies - 1))
-      for (int c = 1; c < kHotCopies; ++c) v += lds_tab[cells + (c - 1) * B + e];
-    if (v) {
-      int col;
-      const size_t row = band_cell_row(a.rows, sc.r_lo, e, B, col);
-      atomicAdd(&out[row + col], (double)v * 9.094947017729282379150390625e-13);  // 2^-40
+  flush_parzen<NT>(a, sc, cells, hot_cells, lds_tab, lds_count);
+}
+
+// Sampled forward: as parzen_fwd_kernel over the workgroup's share of the
+// sample list (entries {x | y << 12 | slot << 24, z}), each sample's Q32
+// coordinates formed straight from the matrix.
+template <bool FQ, bool CLAMP, int NT>
+__global__ __launch_bounds__(NT) void parzen_sampled_fwd_kernel(ParzenArgs a, const uint2* __restrict__ list,
+                                                                const unsigned long long* __restrict__ n_list) {
+  extern __shared__ __align__(16) unsigned long long lds_tab[];
+  __shared__ uint32_t lds_count;
+  const int B = a.bins;
+  SweepCtx sc;
+  block_work(a.chunks, a.n, a.bands, a.slab_major, sc.t, sc.chunk, sc.band);
+  const int32_t n_slots = (int32_t)a.rows->n_slots;
+  sc.r_lo = (int32_t)sc.band * a.band_rows;
+  if (sc.r_lo >= n_slots) return;  // a band past the occupied rows (whole workgroup)
+  sc.r_hi = min(n_slots, sc.r_lo + a.band_rows);
+  const int cells = (sc.r_hi - sc.r_lo) * B;
+  const int hot_cells = sc.r_lo == 0 ? (kHotCopies - 1) * B : 0;
+  for (int e = threadIdx.x; e < cells + hot_cells; e += NT) lds_tab[e] = 0ull;
+  if (threadIdx.x == 0) lds_count = 0;
+  int64_t Mq[12];
+  const bool ok = quantize_transform(a.transforms + 12 * (size_t)sc.t, Mq);
+  __syncthreads();
+  uint32_t taken = 0;
+  const int copy = (threadIdx.x & (kHotCopies - 1));
+  if (ok) {
+    const ParzenFwdStep ps = ParzenFwdStep::template make<FQ>(a);
+    const int64_t ns = (int64_t)*n_list;
+    const int64_t s0 = ns * sc.chunk / a.chunks, s1 = ns * (sc.chunk + 1) / a.chunks;
+    for (int64_t e = s0 + threadIdx.x; e < s1; e += NT) {
+      const uint2 en = list[e];
+      const int64_t x = en.x & 0xFFFu, y = (en.x >> 12) & 0xFFFu, z = en.y;
+      const int32_t slot = (int32_t)(en.x >> 24);
+      int64_t q[3];
+#pragma unroll
+      for (int r = 0; r < 3; ++r) q[r] = Mq[4 * r] * x + Mq[4 * r + 1] * y + Mq[4 * r + 2] * z + Mq[4 * r + 3];
+      taken += ps.add<FQ, CLAMP>(q, [&] { return slot; }, sc, cells, copy, lds_tab);
     }
   }
-  if (threadIdx.x == 0 && sc.band == 0 && lds_count)
-    atomicAdd((unsigned long long*)&a.count[sc.t], (unsigned long long)lds_count);
+  if (sc.band == 0 && taken) atomicAdd(&lds_count, taken);
+  __syncthreads();
+  if (!ok) return;
+  flush_parzen<NT>(a, sc, cells, hot_cells, lds_tab, lds_count);
 }
 
 // ---------------------------------------------------------------------------
@@ -550,6 +634,25 @@ hipError_t launch_parzen_fwd(const ParzenLaunch& L, hipStream_t s) {
   return L.clamp ? fwd_variant<false, true>(a, lds, s) : fwd_variant<false, false>(a, lds, s);
 }
 
+template <bool FQ, bool CLAMP>
+static hipError_t sampled_fwd_variant(const ParzenArgs& a, const uint2* list, const unsigned long long* n_list,
+                                      size_t lds, hipStream_t s) {
+  hipLaunchKernelGGL((parzen_sampled_fwd_kernel<FQ, CLAMP, 512>), dim3((unsigned)(a.n * a.chunks * a.bands)),
+                     dim3(512), lds, s, a, list, n_list);
+  return hipGetLastError();
+}
+
+hipError_t launch_parzen_sampled_fwd(const ParzenLaunch& L, const uint2* list, const unsigned long long* n_list,
+                                     hipStream_t s) {
+  ParzenArgs a = L.args;
+  const size_t lds = (size_t)(a.band_rows + kHotCopies - 1) * a.bins * 8;
+  if (L.float_quads)
+    return L.clamp ? sampled_fwd_variant<true, true>(a, list, n_list, lds, s)
+                   : sampled_fwd_variant<true, false>(a, list, n_list, lds, s);
+  return L.clamp ? sampled_fwd_variant<false, true>(a, list, n_list, lds, s)
+                 : sampled_fwd_variant<false, false>(a, list, n_list, lds, s);
+}
+
 hipError_t launch_dmi_dp(const ParzenLaunch& L, const QList& q, hipStream_t s) {
   const int32_t S = reduce_splits(L.args.bins, L.args.n);
   hipLaunchKernelGGL(dmi_dp_kernel, dim3((unsigned)((int64_t)L.args.n * S)), dim3(256), 0, s, L.args, q, S);
@@ -577,6 +680,9 @@ static hipError_t allow_lds() {
   const int bytes = 64 * 1024;
   hipError_t e;
   if ((e = hipFuncSetAttribute((const void*)parzen_fwd_kernel<FQ, CLAMP, 512>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, bytes)) != hipSuccess)
+    return e;
+  if ((e = hipFuncSetAttribute((const void*)parzen_sampled_fwd_kernel<FQ, CLAMP, 512>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, bytes)) != hipSuccess)
     return e;
   return hipFuncSetAttribute((const void*)parzen_bwd_kernel<FQ, CLAMP, 2, 512>,

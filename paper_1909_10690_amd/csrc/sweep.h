@@ -45,6 +45,90 @@ static __device__ __noinline__ uint32_t exact_bin(uint32_t a00, uint32_t a10, ui
 
 constexpr double kEdge = 1.0 / 536870912.0;  // 2^-29
 
+// Per-launch constants of the hard-binned step of one fixed voxel: the
+// moving gather volume, its upper coordinates, the bin scale and the LDS
+// histogram's byte address.
+struct HardStep {
+  __amdgpu_buffer_rsrc_t rsrc;
+  uint64_t topx, topy, topz;
+  uint32_t NY, MX, Bu, B4, lbase;
+  double scale;
+  Divider div;
+
+  __device__ __forceinline__ HardStep(const HardGeom& g, uint32_t* lds_hist) {
+    topx = (uint64_t)(g.mnx - 1) << 32;
+    topy = (uint64_t)(g.mny - 1) << 32;
+    topz = (uint64_t)(g.mnz - 1) << 32;
+    NY = (uint32_t)g.mny;
+    MX = (uint32_t)g.mnx;
+    rsrc = __builtin_amdgcn_make_buffer_rsrc((void*)g.octs, (short)0, (int)g.oct_bytes, 0x00020000);
+    Bu = (uint32_t)g.bins;
+    B4 = 4u * Bu;  // bytes per LDS histogram row (u32 counters)
+    lbase = (uint32_t)(size_t)(lds_u32*)lds_hist;
+    scale = g.scale;
+    div = g.div;
+  }
+
+  // Counts one fixed voxel whose exact Q32 moving coordinates (qx, qy, qz)
+  // are given: clamped (CLAMP) or skipped when outside [0, n - 1] on any
+  // axis; fixed_bin() supplies its fixed bin (read after the gather is
+  // issued).
+  template <bool CLAMP, bool PACKED, bool OCT8, typename FB>
+  __device__ __forceinline__ void count(int64_t qx, int64_t qy, int64_t qz, FB&& fixed_bin,
+                                        uint32_t* lds_hist) const {
+    uint64_t cx = (uint64_t)qx, cy = (uint64_t)qy, cz = (uint64_t)qz;
+    if (CLAMP) {
+      cx = qx < 0 ? 0 : (cx > topx ? topx : cx);
+      cy = qy < 0 ? 0 : (cy > topy ? topy : cy);
+      cz = qz < 0 ? 0 : (cz > topz ? topz : cz);
+    } else {
+      // 0 <= q <= top; a negative q wraps to a huge unsigned value
+      if (cx > topx || cy > topy || cz > topz) return;
+    }
+    const uint32_t ix = (uint32_t)(cx >> 32), iy = (uint32_t)(cy >> 32), iz = (uint32_t)(cz >> 32);
+    const uint32_t fx = (uint32_t)cx, fy = (uint32_t)cy, fz = (uint32_t)cz;
+    // rows iz ny + iy < ny nz <= 2^24 and edges <= 4096: 24-bit operands
+    const uint32_t vox = mad24(mad24(iz, NY, iy), MX, ix);
+    uint4_t oc;
+    if (OCT8) {
+      // bytes (x,y), (x1,y), (x,y1), (x1,y1) of slice z in .x, of z1 in .y
+      const uint2_t d = __builtin_amdgcn_raw_buffer_load_b64(rsrc, vox << 3, 0, 0);
+      oc.x = __builtin_amdgcn_perm(0u, d.x, 0x0C010C00u);  // (b0, b1) as 16-bit halves
+      oc.y = __builtin_amdgcn_perm(0u, d.x, 0x0C030C02u);  // (b2, b3)
+      oc.z = __builtin_amdgcn_perm(0u, d.y, 0x0C010C00u);
+      oc.w = __builtin_amdgcn_perm(0u, d.y, 0x0C030C02u);
+    } else {
+      oc = __builtin_amdgcn_raw_buffer_load_b128(rsrc, vox << 4, 0, 0);
+    }
+    const uint32_t fb = fixed_bin();
+    // (65535 - wx) in the low half, wx in the high half
+    const uint32_t wpack = (fx & 0xFFFF0000u) | ((fx >> 16) ^ 0xFFFFu);
+    const uint32_t a00 = lerp_x(oc.x, wpack), a10 = lerp_x(oc.y, wpack);
+    const uint32_t a01 = lerp_x(oc.z, wpack), a11 = lerp_x(oc.w, wpack);
+    const uint32_t wy = fy >> 16, wz = fz >> 16;
+    const double wyd = (double)wy, wzd = (double)wz;
+    const double A00 = (double)a00, A10 = (double)a10, A01 = (double)a01, A11 = (double)a11;
+    const double uyd = 65536.0 - wyd;
+    const double b0 = fma(A10, wyd, A00 * uyd);         // exact, < 2^48
+    const double b1 = fma(A11, wyd, A01 * uyd);         // exact, < 2^48
+    const double V = fma(b1 - b0, wzd, b0 * 65536.0);  // exact value rounded once
+    const double tb = V * scale;
+    uint32_t bm = (uint32_t)tb;
+    // within kEdge of a bin edge: fr < kEdge or fr > 1 - kEdge
+    const double fr = __builtin_amdgcn_fract(tb);
+    if (fabs(fr - 0.5) > 0.5 - kEdge) bm = exact_bin(a00, a10, a01, a11, wy, wz, Bu, div);
+    if (PACKED) {
+      const uint32_t cell = __umul24(fb, Bu) + bm;
+      atomicAdd(&lds_hist[cell >> 1], 1u << ((cell & 1u) * 16u));
+    } else {
+      // byte address of counter [fb][bm], formed directly (a mul24 and a
+      // shift-add rather than index arithmetic on the pointer)
+      const uint32_t addr = __umul24(fb, B4) + ((bm << 2) + lbase);
+      __hip_atomic_fetch_add((lds_u32*)(size_t)addr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
+  }
+};
+
 // Sweeps one slab of the fixed volume for one transform (Mq) into the
 // workgroup's LDS histogram.  NW waves share the slab's 4-row groups.
 // OCT8: the oct volume holds 8-bit corners (one 64-bit gather), unpacked
@@ -58,16 +142,7 @@ __device__ __forceinline__ void sweep_hard(const HardGeom& g, const int64_t* Mq,
   GroupWalk w;
   w.init(Mq, g.fny, g.fnz, chunks, chunk, wave, NW, dx, dy);
   const int64_t sx = w.step[0], sy = w.step[1], sz = w.step[2];
-  const uint64_t topx = (uint64_t)(g.mnx - 1) << 32;
-  const uint64_t topy = (uint64_t)(g.mny - 1) << 32;
-  const uint64_t topz = (uint64_t)(g.mnz - 1) << 32;
-  const uint32_t NY = (uint32_t)g.mny, MX = (uint32_t)g.mnx;
-  const __amdgpu_buffer_rsrc_t rsrc =
-      __builtin_amdgcn_make_buffer_rsrc((void*)g.octs, (short)0, (int)g.oct_bytes, 0x00020000);
-  const uint32_t Bu = (uint32_t)g.bins;
-  const uint32_t B4 = 4u * Bu;  // bytes per LDS histogram row (u32 counters)
-  const uint32_t lbase = (uint32_t)(size_t)(lds_u32*)lds_hist;
-  const double scale = g.scale;
+  const HardStep hs(g, lds_hist);
 
   for (; w.g < w.g1; w.next()) {
     const int32_t j = w.j0 + dy;
@@ -76,58 +151,9 @@ __device__ __forceinline__ void sweep_hard(const HardGeom& g, const int64_t* Mq,
     const uint32_t rowoff = ((uint32_t)w.k * (uint32_t)g.fny + (uint32_t)j) * (uint32_t)g.fnx;
     const uint32_t rowend = rowoff + (uint32_t)g.fnx;
     int64_t qx = w.r[0] + w.lane_off[0], qy = w.r[1] + w.lane_off[1], qz = w.r[2] + w.lane_off[2];
-    for (uint32_t xo = rowoff + dx; xo < rowend; xo += kTileX, qx += sx, qy += sy, qz += sz) {
-      uint64_t cx = (uint64_t)qx, cy = (uint64_t)qy, cz = (uint64_t)qz;
-      if (CLAMP) {
-        cx = qx < 0 ? 0 : (cx > topx ? topx : cx);
-        cy = qy < 0 ? 0 : (cy > topy ? topy : cy);
-        cz = qz < 0 ? 0 : (cz > topz ? topz : cz);
-      } else {
-        // 0 <= q <= top; a negative q wraps to a huge unsigned value
-        if (cx > topx || cy > topy || cz > topz) continue;
-      }
-      const uint32_t ix = (uint32_t)(cx >> 32), iy = (uint32_t)(cy >> 32), iz = (uint32_t)(cz >> 32);
-      const uint32_t fx = (uint32_t)cx, fy = (uint32_t)cy, fz = (uint32_t)cz;
-      // rows iz ny + iy < ny nz <= 2^24 and edges <= 4096: 24-bit operands
-      const uint32_t vox = mad24(mad24(iz, NY, iy), MX, ix);
-      uint4_t oc;
-      if (OCT8) {
-        // bytes (x,y), (x1,y), (x,y1), (x1,y1) of slice z in .x, of z1 in .y
-        const uint2_t d = __builtin_amdgcn_raw_buffer_load_b64(rsrc, vox << 3, 0, 0);
-        oc.x = __builtin_amdgcn_perm(0u, d.x, 0x0C010C00u);  // (b0, b1) as 16-bit halves
-        oc.y = __builtin_amdgcn_perm(0u, d.x, 0x0C030C02u);  // (b2, b3)
-        oc.z = __builtin_amdgcn_perm(0u, d.y, 0x0C010C00u);
-        oc.w = __builtin_amdgcn_perm(0u, d.y, 0x0C030C02u);
-      } else {
-        oc = __builtin_amdgcn_raw_buffer_load_b128(rsrc, vox << 4, 0, 0);
-      }
-      const uint32_t fb = ((global_u8*)g.fbins)[xo];
-      // (65535 - wx) in the low half, wx in the high half
-      const uint32_t wpack = (fx & 0xFFFF0000u) | ((fx >> 16) ^ 0xFFFFu);
-      const uint32_t a00 = lerp_x(oc.x, wpack), a10 = lerp_x(oc.y, wpack);
-      const uint32_t a01 = lerp_x(oc.z, wpack), a11 = lerp_x(oc.w, wpack);
-      const uint32_t wy = fy >> 16, wz = fz >> 16;
-      const double wyd = (double)wy, wzd = (double)wz;
-      const double A00 = (double)a00, A10 = (double)a10, A01 = (double)a01, A11 = (double)a11;
-      const double uyd = 65536.0 - wyd;
-      const double b0 = fma(A10, wyd, A00 * uyd);         // exact, < 2^48
-      const double b1 = fma(A11, wyd, A01 * uyd);         // exact, < 2^48
-      const double V = fma(b1 - b0, wzd, b0 * 65536.0);  // exact value rounded once
-      const double tb = V * scale;
-      uint32_t bm = (uint32_t)tb;
-      // within kEdge of a bin edge: fr < kEdge or fr > 1 - kEdge
-      const double fr = __builtin_amdgcn_fract(tb);
-      if (fabs(fr - 0.5) > 0.5 - kEdge) bm = exact_bin(a00, a10, a01, a11, wy, wz, Bu, g.div);
-      if (PACKED) {
-        const uint32_t cell = __umul24(fb, Bu) + bm;
-        atomicAdd(&lds_hist[cell >> 1], 1u << ((cell & 1u) * 16u));
-      } else {
-        // byte address of counter [fb][bm], formed directly (a mul24 and a
-        // shift-add rather than index arithmetic on the pointer)
-        const uint32_t addr = __umul24(fb, B4) + ((bm << 2) + lbase);
-        __hip_atomic_fetch_add((lds_u32*)(size_t)addr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-      }
-    }
+    for (uint32_t xo = rowoff + dx; xo < rowend; xo += kTileX, qx += sx, qy += sy, qz += sz)
+      hs.count<CLAMP, PACKED, OCT8>(qx, qy, qz, [&] { return (uint32_t)((global_u8*)g.fbins)[xo]; },
+                                    lds_hist);
   }
 }
 

@@ -97,12 +97,14 @@ def map_transforms(family: str, n: int, fixed_shape_xyz, extent: float | None = 
 
 
 def mi_map(ctx, fixed, moving, family: str, n: int = 51, extent: float | None = None, bins: int = 64,
-           q=(1.0,), flags: int = 0, batch: int = 16384, transforms=None, **geometry):
+           q=(1.0,), flags: int = 0, batch: int = 16384, transforms=None, sample=None, **geometry):
     """MI maps [n_q][n][n][n] (device float64, [z][y][x] order per q) of one
-    family over an n^3 grid: batches of grid points through ``ctx.eval``.
-    ``transforms`` (the [n^3][12] matrices, on the device) may be given to
-    skip building them; ``geometry`` takes the spacing / origin arguments of
-    :func:`map_transforms`."""
+    family over an n^3 grid: batches of grid points through ``ctx.eval``
+    (or, with ``sample`` = (fraction, seed), ``ctx.eval_sampled``: every
+    point over the same random subset of fixed voxels, as Mattes' MI
+    samples them).  ``transforms`` (the [n^3][12] matrices, on the device)
+    may be given to skip building them; ``geometry`` takes the spacing /
+    origin arguments of :func:`map_transforms`."""
     import torch
     dev = fixed.tensor.device
     if transforms is None:
@@ -115,7 +117,11 @@ def mi_map(ctx, fixed, moving, family: str, n: int = 51, extent: float | None = 
     out = torch.empty((total, len(qs)), dtype=torch.float64, device=dev)
     for a in range(0, total, batch):
         b = min(total, a + batch)
-        ctx.eval(fixed, moving, transforms[a:b], bins, qs, flags=flags, want_overlap=False, out=out[a:b])
+        if sample is None:
+            ctx.eval(fixed, moving, transforms[a:b], bins, qs, flags=flags, want_overlap=False, out=out[a:b])
+        else:
+            ctx.eval_sampled(fixed, moving, transforms[a:b], bins, qs, fraction=sample[0], seed=sample[1],
+                             flags=flags, want_overlap=False, out=out[a:b])
     return out.t().reshape(len(qs), n, n, n).contiguous()
 
 

@@ -36,8 +36,9 @@ def coords(Mq, i, j, k) -> list[Fraction]:
 
 
 def hist_exact(fixed: np.ndarray, moving: np.ndarray, M, bins: int, frange, mrange,
-               clamp: bool = False) -> tuple[np.ndarray, int]:
-    """Joint histogram [bins][bins] and overlap count, exactly."""
+               clamp: bool = False, keep=None) -> tuple[np.ndarray, int]:
+    """Joint histogram [bins][bins] and overlap count, exactly; ``keep``
+    ([nz][ny][nx] booleans) limits it to a subset of the fixed voxels."""
     flo, fhi = int(frange[0]), int(frange[1])
     mlo, mhi = int(mrange[0]), int(mrange[1])
     Rf, Rm = fhi - flo + 1, mhi - mlo + 1
@@ -52,6 +53,8 @@ def hist_exact(fixed: np.ndarray, moving: np.ndarray, M, bins: int, frange, mran
     for k in range(nz):
         for j in range(ny):
             for i in range(nx):
+                if keep is not None and not keep[k, j, i]:
+                    continue
                 y = coords(Mq, i, j, k)
                 inside = all(0 <= y[r] <= mn[r] - 1 for r in range(3))
                 if not inside:

@@ -55,6 +55,10 @@ def test_binding_declares_argument_types_of_every_entry_point():
             if "*" in p or "size_t" in p:
                 wide = t in (ctypes.c_void_p, ctypes.c_size_t, ctypes.c_char_p) or issubclass(t, ctypes._Pointer)
                 assert wide, (name, p, t)
+            elif p.startswith("double"):
+                assert t is ctypes.c_double, (name, p, t)
+            elif p.startswith("uint64_t"):
+                assert t is ctypes.c_uint64, (name, p, t)
             else:
                 assert t in (ctypes.c_int, ctypes.c_int32), (name, p, t)
 
@@ -67,11 +71,12 @@ def test_header_constants_match_binding():
     assert consts["MI_HIST_PARZEN"] == B.HIST_PARZEN and consts["MI_BOUNDARY_CLAMP"] == B.BOUNDARY_CLAMP
     assert consts["MI_TSALLIS_PSEUDOADDITIVE"] == B.TSALLIS_PSEUDOADDITIVE
     assert consts["MI_USE_GRAPH"] == B.USE_GRAPH
+    assert consts["MI_SAMPLED"] == B.SAMPLED and consts["MI_ERR_SAMPLE"] == B.MI_ERR_SAMPLE
     assert ctypes.sizeof(B.MiVolume) == 40
 
 
 def test_status_strings():
-    for s in [0, -1, -2, -3, -4, -5, -6, -7, -8, -9, -10, -20, -21, 12345]:
+    for s in [0, -1, -2, -3, -4, -5, -6, -7, -8, -9, -10, -11, -20, -21, 12345]:
         assert isinstance(B.status_string(s), str) and B.status_string(s)
     assert B.status_string(0) == "ok"
 
@@ -244,7 +249,36 @@ def test_graph_flag_accepted_and_unknown_bits_rejected():
     assert call_eval(vol(), vol(), flags=B.USE_GRAPH) == B.MI_ERR_NULL
     assert call_eval(vol(), vol(), flags=B.USE_GRAPH | B.HIST_PARZEN) == B.MI_ERR_NULL
     assert call_eval(vol(), vol(), flags=B.VOLUMES_UNCHANGED | B.HIST_PARZEN) == B.MI_ERR_NULL
-    assert call_eval(vol(), vol(), flags=0x4000) == B.MI_ERR_FLAGS
+    assert call_eval(vol(), vol(), flags=B.SAMPLED) == B.MI_ERR_FLAGS  # mi_eval_sampled's flag
+    assert call_eval(vol(), vol(), flags=0x8000) == B.MI_ERR_FLAGS
+
+
+def call_sampled(f, m, fraction=0.25, seed=7, n=4, bins=32, flags=0, ws_bytes=1 << 40, hist=None, ws=FAKE):
+    lib = B.load()
+    qs = np.asarray((1.0, 2.0), dtype=np.float64)
+    return lib.mi_eval_sampled(None, ctypes.byref(f), ctypes.byref(m), FAKE, n, bins,
+                               qs.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), 2, flags, fraction, seed,
+                               FAKE, None, hist, ws, ws_bytes, None)
+
+
+def test_sampled_validation():
+    assert call_sampled(vol(), vol()) == B.MI_ERR_NULL            # valid: reaches the context check
+    assert call_sampled(vol(), vol(), fraction=1.0, seed=2 ** 64 - 1) == B.MI_ERR_NULL
+    assert call_sampled(vol(), vol(), fraction=3.0) == B.MI_ERR_NULL   # >= 1 keeps every voxel
+    assert call_sampled(vol(), vol(), flags=B.SAMPLED | B.HIST_PARZEN) == B.MI_ERR_NULL
+    for bad in (0.0, -0.5, float("nan"), float("inf")):
+        assert call_sampled(vol(), vol(), fraction=bad) == B.MI_ERR_SAMPLE
+    assert call_sampled(vol(), vol(), flags=0x8000) == B.MI_ERR_FLAGS
+    assert call_sampled(vol(), vol(), flags=B.HIST_PARZEN, hist=FAKE) == B.MI_ERR_UNSUPPORTED
+    assert call_sampled(vol(), vol(), ws=None) == B.MI_ERR_WORKSPACE
+    # the plain workspace is too small: the sample list is missing
+    st, plain = ws_size(vol(), vol(), 4, 32, 2)
+    st2, sampled = ws_size(vol(), vol(), 4, 32, 2, B.SAMPLED)
+    assert st == st2 == 0 and sampled == plain + 8 * 8 * 8 * 8 + 256
+    assert call_sampled(vol(), vol(), ws_bytes=plain) == B.MI_ERR_WORKSPACE
+    assert call_sampled(vol(), vol(), ws_bytes=sampled) == B.MI_ERR_NULL
+    # no sampled gradient
+    assert ws_size(vol(), vol(), 4, 32, 2, B.SAMPLED, 1)[0] == B.MI_ERR_UNSUPPORTED
 
 
 def test_tune_validation():
