@@ -33,11 +33,22 @@ __device__ __forceinline__ int find_pair(const int64_t* __restrict__ base, int P
   return lo;
 }
 
+// Device-memory views: the pairs' volume pointers are read from the pair
+// table, so without the address space the compiler would use flat accesses.
+typedef const __attribute__((address_space(1))) uint16_t global_u16;
+typedef const __attribute__((address_space(1))) int16_t global_i16;
+typedef const __attribute__((address_space(1))) uint32_t global_cu32;
+typedef const __attribute__((address_space(1))) float global_f32;
+typedef __attribute__((address_space(1))) uint8_t global_out8;
+typedef __attribute__((address_space(1))) uint32_t global_out32;
+typedef __attribute__((address_space(1))) uint2_t global_out2;
+typedef __attribute__((address_space(1))) uint4_t global_out4;
+
 __device__ __forceinline__ int32_t load_int(const void* p, int32_t dtype, size_t i) {
   switch (dtype) {
-  case 0: return ((const uint8_t*)p)[i];
-  case 1: return ((const uint16_t*)p)[i];
-  default: return ((const int16_t*)p)[i];
+  case 0: return ((global_u8*)p)[i];
+  case 1: return ((global_u16*)p)[i];
+  default: return ((global_i16*)p)[i];
   }
 }
 
@@ -48,119 +59,6 @@ __global__ void gather_transforms_kernel(PairsArgs a, int64_t total) {
     const double* src = a.pairs[p].transforms + 12 * (g - a.t_base[p]);
     for (int e = 0; e < 12; ++e) a.transforms[12 * g + e] = src[e];
   }
-}
-
-// Calls f(p, row, lane) for the rows of the concatenated row space
-// [base[0], base[P]) that fall to this workgroup: a contiguous range per
-// workgroup, one wave per row.  The pair is found once per wave and then
-// advanced as the rows ascend (a search per row would serialise dependent
-// loads on every row of small volumes).
-template <typename F>
-__device__ __forceinline__ void for_each_row(const int64_t* __restrict__ base, int P, int64_t rows,
-                                             F&& f) {
-  const int64_t per = (rows + gridDim.x - 1) / gridDim.x;
-  const int64_t r0 = (int64_t)blockIdx.x * per;
-  const int64_t r1 = r0 + per < rows ? r0 + per : rows;
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int nw = blockDim.x >> 6;
-  const int lane = threadIdx.x & 63;
-  if (r0 + wave >= r1) return;
-  int p = find_pair(base, P, r0 + wave);
-  for (int64_t r = r0 + wave; r < r1; r += nw) {
-    while (r >= base[p + 1]) ++p;
-    f(p, r - base[p], lane);
-  }
-}
-
-// Fixed bins of every pair, one wave per fixed row.
-__global__ void prep_fixed_kernel(PairsArgs a, int64_t rows) {
-  for_each_row(a.frow_base, a.n_pairs, rows, [&](int p, int64_t row, int lane) {
-    const PairDesc& d = a.pairs[p];
-    const int32_t nx = d.geom.fnx;
-    uint8_t* __restrict__ out = (uint8_t*)d.geom.fbins + row * nx;
-    const size_t base = (size_t)row * nx;
-    if (d.fdtype == 0 && (nx & 3) == 0 && ((uintptr_t)d.fixed & 3) == 0) {
-      // u8 rows of a multiple of 4 voxels, 4-byte aligned volume: four voxels
-      // per lane, 32-bit loads and stores
-      const uint32_t* __restrict__ src = (const uint32_t*)((const uint8_t*)d.fixed + base);
-      for (int32_t x4 = lane; x4 < nx / 4; x4 += 64) {
-        const uint32_t w = src[x4];
-        uint32_t o = 0;
-#pragma unroll
-        for (int k = 0; k < 4; ++k)
-          o |= fixed_bin_int((int32_t)((w >> (8 * k)) & 0xFFu), (int32_t)d.flo, (int32_t)d.fhi,
-                             (uint32_t)d.geom.bins, d.fdiv) << (8 * k);
-        ((uint32_t*)out)[x4] = o;
-      }
-      return;
-    }
-    for (int32_t x = lane; x < nx; x += 64) {
-      uint32_t b;
-      if (d.fdtype == 3)
-        b = fixed_bin_real((double)((const float*)d.fixed)[base + x], d.flo, d.fhi, d.geom.bins);
-      else
-        b = fixed_bin_int(load_int(d.fixed, d.fdtype, base + x), (int32_t)d.flo, (int32_t)d.fhi,
-                          (uint32_t)d.geom.bins, d.fdiv);
-      out[x] = (uint8_t)b;
-    }
-  });
-}
-
-// Moving oct volumes of every pair, one wave per moving row (z < nz, y < ny),
-// with the layout and clamping of the single-pair path.
-__global__ void prep_moving_kernel(PairsArgs a, int64_t rows) {
-  for_each_row(a.mrow_base, a.n_pairs, rows, [&](int p, int64_t row, int lane) {
-    const PairDesc& d = a.pairs[p];
-    const int32_t nx = d.geom.mnx, ny = d.geom.mny, nz = d.geom.mnz;
-    const int32_t z = (int32_t)(row / ny), y = (int32_t)(row - (int64_t)z * ny);
-    const size_t r00 = ((size_t)z * ny + y) * nx;
-    const size_t r10 = r00 + (y + 1 < ny ? nx : 0);
-    const size_t dz = z + 1 < nz ? (size_t)nx * ny : 0;
-    auto v = [&](size_t i) -> uint32_t { return clamp_offset(load_int(d.moving, d.mdtype, i), d.mlo, d.mhi); };
-    if (d.geom.oct8 && d.mdtype == 0 && (nx & 3) == 0 && ((uintptr_t)d.moving & 3) == 0) {
-      // u8 rows of a multiple of 4 voxels, 4-byte aligned volume: four voxels
-      // per lane; each source row is read as one dword plus its next
-      // (clamped) byte
-      uint4* __restrict__ out = (uint4*)((uint2*)d.geom.octs + row * nx);
-      const uint8_t* __restrict__ mv = (const uint8_t*)d.moving;
-      const size_t src[4] = {r00, r10, r00 + dz, r10 + dz};
-      for (int32_t x4 = lane; x4 < nx / 4; x4 += 64) {
-        const int32_t x0 = 4 * x4, xn = x0 + 4 < nx ? x0 + 4 : nx - 1;
-        uint32_t b[4][5];  // b[row][i] = clamped, offset value at x0 + i (i = 4: the neighbour)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const uint32_t w = *(const uint32_t*)(mv + src[r] + x0);
-#pragma unroll
-          for (int i = 0; i < 4; ++i) b[r][i] = clamp_offset((int32_t)((w >> (8 * i)) & 0xFFu), d.mlo, d.mhi);
-          b[r][4] = clamp_offset((int32_t)mv[src[r] + xn], d.mlo, d.mhi);
-        }
-        uint32_t o[8];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          o[2 * i] = b[0][i] | (b[0][i + 1] << 8) | (b[1][i] << 16) | (b[1][i + 1] << 24);
-          o[2 * i + 1] = b[2][i] | (b[2][i + 1] << 8) | (b[3][i] << 16) | (b[3][i + 1] << 24);
-        }
-        out[2 * x4] = make_uint4(o[0], o[1], o[2], o[3]);
-        out[2 * x4 + 1] = make_uint4(o[4], o[5], o[6], o[7]);
-      }
-    } else if (d.geom.oct8) {
-      // 8-bit corners: byte 4 dz + 2 dy + dx' (layout of pack_oct8_kernel)
-      uint2* __restrict__ out = (uint2*)d.geom.octs + row * nx;
-      for (int32_t x = lane; x < nx; x += 64) {
-        const int32_t x1 = x + 1 < nx ? x + 1 : nx - 1;
-        out[x] = make_uint2(v(r00 + x) | (v(r00 + x1) << 8) | (v(r10 + x) << 16) | (v(r10 + x1) << 24),
-                            v(r00 + dz + x) | (v(r00 + dz + x1) << 8) | (v(r10 + dz + x) << 16) |
-                                (v(r10 + dz + x1) << 24));
-      }
-    } else {
-      uint4* __restrict__ out = (uint4*)d.geom.octs + row * nx;
-      for (int32_t x = lane; x < nx; x += 64) {
-        const int32_t x1 = x + 1 < nx ? x + 1 : nx - 1;
-        out[x] = make_uint4(v(r00 + x) | (v(r00 + x1) << 16), v(r10 + x) | (v(r10 + x1) << 16),
-                            v(r00 + dz + x) | (v(r00 + dz + x1) << 16), v(r10 + dz + x) | (v(r10 + dz + x1) << 16));
-      }
-    }
-  });
 }
 
 // A value every lane holds alike, moved to scalar registers.  The work item
@@ -178,6 +76,119 @@ __device__ __forceinline__ T uniform(const T& v) {
   T r;
   __builtin_memcpy(&r, w, sizeof(T));
   return r;
+}
+
+// Calls f(p, row, lane) for the rows of the concatenated row space
+// [base[0], base[P]) that fall to this workgroup: a contiguous range per
+// workgroup, one wave per row.  The pair is found once per wave and then
+// advanced as the rows ascend (a search per row would serialise dependent
+// loads on every row of small volumes).
+template <typename F>
+__device__ __forceinline__ void for_each_row(const int64_t* __restrict__ base, int P, int64_t rows,
+                                             F&& f) {
+  const int64_t per = (rows + gridDim.x - 1) / gridDim.x;
+  const int64_t r0 = (int64_t)blockIdx.x * per;
+  const int64_t r1 = r0 + per < rows ? r0 + per : rows;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int nw = blockDim.x >> 6;
+  const int lane = threadIdx.x & 63;
+  if (r0 + wave >= r1) return;
+  int p = uniform(find_pair(base, P, r0 + wave));
+  for (int64_t r = r0 + wave; r < r1; r += nw) {
+    while (r >= uniform(base[p + 1])) ++p;
+    f(p, r - uniform(base[p]), lane);
+  }
+}
+
+// Fixed bins of every pair, one wave per fixed row.
+__global__ void prep_fixed_kernel(PairsArgs a, int64_t rows) {
+  for_each_row(a.frow_base, a.n_pairs, rows, [&](int p, int64_t row, int lane) {
+    const PairDesc d = uniform(a.pairs[p]);
+    const int32_t nx = d.geom.fnx;
+    global_out8* __restrict__ out = (global_out8*)d.geom.fbins + row * nx;
+    const size_t base = (size_t)row * nx;
+    if (d.fdtype == 0 && (nx & 3) == 0 && ((uintptr_t)d.fixed & 3) == 0) {
+      // u8 rows of a multiple of 4 voxels, 4-byte aligned volume: four voxels
+      // per lane, 32-bit loads and stores
+      global_cu32* __restrict__ src = (global_cu32*)((global_u8*)d.fixed + base);
+      for (int32_t x4 = lane; x4 < nx / 4; x4 += 64) {
+        const uint32_t w = src[x4];
+        uint32_t o = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+          o |= fixed_bin_int((int32_t)((w >> (8 * k)) & 0xFFu), (int32_t)d.flo, (int32_t)d.fhi,
+                             (uint32_t)d.geom.bins, d.fdiv) << (8 * k);
+        ((global_out32*)out)[x4] = o;
+      }
+      return;
+    }
+    for (int32_t x = lane; x < nx; x += 64) {
+      uint32_t b;
+      if (d.fdtype == 3)
+        b = fixed_bin_real((double)((global_f32*)d.fixed)[base + x], d.flo, d.fhi, d.geom.bins);
+      else
+        b = fixed_bin_int(load_int(d.fixed, d.fdtype, base + x), (int32_t)d.flo, (int32_t)d.fhi,
+                          (uint32_t)d.geom.bins, d.fdiv);
+      out[x] = (uint8_t)b;
+    }
+  });
+}
+
+// Moving oct volumes of every pair, one wave per moving row (z < nz, y < ny),
+// with the layout and clamping of the single-pair path.
+__global__ void prep_moving_kernel(PairsArgs a, int64_t rows) {
+  for_each_row(a.mrow_base, a.n_pairs, rows, [&](int p, int64_t row, int lane) {
+    const PairDesc d = uniform(a.pairs[p]);
+    const int32_t nx = d.geom.mnx, ny = d.geom.mny, nz = d.geom.mnz;
+    const int32_t z = (int32_t)(row / ny), y = (int32_t)(row - (int64_t)z * ny);
+    const size_t r00 = ((size_t)z * ny + y) * nx;
+    const size_t r10 = r00 + (y + 1 < ny ? nx : 0);
+    const size_t dz = z + 1 < nz ? (size_t)nx * ny : 0;
+    auto v = [&](size_t i) -> uint32_t { return clamp_offset(load_int(d.moving, d.mdtype, i), d.mlo, d.mhi); };
+    if (d.geom.oct8 && d.mdtype == 0 && (nx & 3) == 0 && ((uintptr_t)d.moving & 3) == 0) {
+      // u8 rows of a multiple of 4 voxels, 4-byte aligned volume: four voxels
+      // per lane; each source row is read as one dword plus its next
+      // (clamped) byte
+      global_out4* __restrict__ out = (global_out4*)((global_out2*)d.geom.octs + row * nx);
+      global_u8* __restrict__ mv = (global_u8*)d.moving;
+      const size_t src[4] = {r00, r10, r00 + dz, r10 + dz};
+      for (int32_t x4 = lane; x4 < nx / 4; x4 += 64) {
+        const int32_t x0 = 4 * x4, xn = x0 + 4 < nx ? x0 + 4 : nx - 1;
+        uint32_t b[4][5];  // b[row][i] = clamped, offset value at x0 + i (i = 4: the neighbour)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const uint32_t w = *(global_cu32*)(mv + src[r] + x0);
+#pragma unroll
+          for (int i = 0; i < 4; ++i) b[r][i] = clamp_offset((int32_t)((w >> (8 * i)) & 0xFFu), d.mlo, d.mhi);
+          b[r][4] = clamp_offset((int32_t)mv[src[r] + xn], d.mlo, d.mhi);
+        }
+        uint32_t o[8];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          o[2 * i] = b[0][i] | (b[0][i + 1] << 8) | (b[1][i] << 16) | (b[1][i + 1] << 24);
+          o[2 * i + 1] = b[2][i] | (b[2][i + 1] << 8) | (b[3][i] << 16) | (b[3][i + 1] << 24);
+        }
+        out[2 * x4] = uint4_t{o[0], o[1], o[2], o[3]};
+        out[2 * x4 + 1] = uint4_t{o[4], o[5], o[6], o[7]};
+      }
+    } else if (d.geom.oct8) {
+      // 8-bit corners: byte 4 dz + 2 dy + dx' (layout of pack_oct8_kernel)
+      global_out2* __restrict__ out = (global_out2*)d.geom.octs + row * nx;
+      for (int32_t x = lane; x < nx; x += 64) {
+        const int32_t x1 = x + 1 < nx ? x + 1 : nx - 1;
+        out[x] = uint2_t{v(r00 + x) | (v(r00 + x1) << 8) | (v(r10 + x) << 16) | (v(r10 + x1) << 24),
+                         v(r00 + dz + x) | (v(r00 + dz + x1) << 8) | (v(r10 + dz + x) << 16) |
+                             (v(r10 + dz + x1) << 24)};
+      }
+    } else {
+      global_out4* __restrict__ out = (global_out4*)d.geom.octs + row * nx;
+      for (int32_t x = lane; x < nx; x += 64) {
+        const int32_t x1 = x + 1 < nx ? x + 1 : nx - 1;
+        out[x] = uint4_t{v(r00 + x) | (v(r00 + x1) << 16), v(r10 + x) | (v(r10 + x1) << 16),
+                         v(r00 + dz + x) | (v(r00 + dz + x1) << 16), v(r10 + dz + x) | (v(r10 + dz + x1) << 16)};
+      }
+    }
+  });
 }
 
 template <bool CLAMP, bool PACKED, bool OCT8, int NT>
