@@ -352,8 +352,14 @@ __global__ __launch_bounds__(NT) void parzen_fwd_kernel(ParzenArgs a) {
       int64_t q[3];
 #pragma unroll
       for (int r = 0; r < 3; ++r) q[r] = w.r[r] + w.lane_off[r];
+      // each voxel's fixed bin is loaded one step ahead: the band test then
+      // waits on a load issued a voxel earlier, not on a fresh one before the
+      // gather can start
+      int32_t fb_next = dx < a.fnx ? (int32_t)frow[dx] : 0;
       for (int x = dx; x < a.fnx; x += kTileX) {
-        taken += ps.add<FQ, CLAMP>(q, [&] { return (int32_t)frow[x]; }, sc, cells, copy, lds_tab);
+        const int32_t fbv = fb_next;
+        if (x + kTileX < a.fnx) fb_next = (int32_t)frow[x + kTileX];
+        taken += ps.add<FQ, CLAMP>(q, [&] { return fbv; }, sc, cells, copy, lds_tab);
 #pragma unroll
         for (int r = 0; r < 3; ++r) q[r] += w.step[r];
       }
@@ -537,7 +543,10 @@ __global__ __launch_bounds__(NT) void parzen_bwd_kernel(ParzenArgs a) {
       int64_t q[3];
 #pragma unroll
       for (int r = 0; r < 3; ++r) q[r] = w.r[r] + w.lane_off[r];
+      int32_t fb_next = dx < a.fnx ? (int32_t)frow[dx] : 0;  // one step ahead, as in the forward
       for (int x = dx; x < a.fnx; x += kTileX) {
+        const int32_t fbv = fb_next;
+        if (x + kTileX < a.fnx) fb_next = (int32_t)frow[x + kTileX];
         uint64_t cq[3];
         bool inside = true, moves[3];
 #pragma unroll
@@ -550,7 +559,7 @@ __global__ __launch_bounds__(NT) void parzen_bwd_kernel(ParzenArgs a) {
           q[r] += w.step[r];
         }
         if (!inside) continue;
-        const int32_t fb = frow[x];
+        const int32_t fb = fbv;
         if (fb < sc.r_lo || fb >= sc.r_hi) continue;
         const uint32_t idx = __umul24(__umul24((uint32_t)(cq[2] >> 32), NY) + (uint32_t)(cq[1] >> 32), MX) +
                              (uint32_t)(cq[0] >> 32);
