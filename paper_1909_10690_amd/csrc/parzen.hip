@@ -227,10 +227,23 @@ __device__ __forceinline__ size_t band_cell_row(const RowMap* m, int32_t r_lo, i
 // its cells, and same-address LDS atomics serialise.  The band holding it
 // keeps kHotCopies copies of that row, lane l adding into copy l % kHotCopies;
 // the copies are summed at the flush.
+// Cell index and 32-bit fraction of an exact Q32 coordinate q on an axis of
+// n samples, q clamped to [0, (n - 1) 2^32]: the index is the high word held
+// to [0, n - 1]; the fraction is the low word while the high word lies in
+// [0, n - 2], and zero otherwise (at or past either end the clamped
+// coordinate is a whole sample).  The high word fits 32 bits for every
+// usable matrix (linear entries <= 2^16, translations <= 2^24).
+__device__ __forceinline__ void clamp_q32(int64_t q, int32_t n, uint32_t& cell, uint32_t& frac) {
+  const int32_t hi = (int32_t)(q >> 32);
+  cell = (uint32_t)min(max(hi, 0), n - 1);
+  frac = (uint32_t)hi < (uint32_t)(n - 1) ? (uint32_t)q : 0u;
+}
+
 // Per-launch constants of the forward step of one fixed voxel.
 struct ParzenFwdStep {
   __amdgpu_buffer_rsrc_t rsrc;
   uint64_t top[3];
+  int32_t n[3];
   uint32_t NY, MX;
   int32_t SZ;  // fp32 quads: bytes to the next slice
   int B;
@@ -242,6 +255,9 @@ struct ParzenFwdStep {
     p.top[0] = (uint64_t)(a.mnx - 1) << 32;
     p.top[1] = (uint64_t)(a.mny - 1) << 32;
     p.top[2] = (uint64_t)(a.mnz - 1) << 32;
+    p.n[0] = a.mnx;
+    p.n[1] = a.mny;
+    p.n[2] = a.mnz;
     p.NY = (uint32_t)a.mny;
     p.MX = (uint32_t)a.mnx;
     p.SZ = FQ ? 16 * a.mnx * a.mny : 0;
@@ -259,24 +275,27 @@ struct ParzenFwdStep {
   template <bool FQ, bool CLAMP, typename SLOT>
   __device__ __forceinline__ bool add(const int64_t q[3], SLOT&& slot_of, const SweepCtx& sc, int cells,
                                       int copy, unsigned long long* lds_tab) const {
-    uint64_t cq[3];
+    uint32_t cix[3], frac[3];
     bool inside = true;
 #pragma unroll
     for (int r = 0; r < 3; ++r) {
-      cq[r] = (uint64_t)q[r];
-      if (CLAMP) cq[r] = q[r] < 0 ? 0 : (cq[r] > top[r] ? top[r] : cq[r]);
-      else inside = inside && cq[r] <= top[r];
+      if (CLAMP) {
+        clamp_q32(q[r], n[r], cix[r], frac[r]);
+      } else {
+        inside = inside && (uint64_t)q[r] <= top[r];
+        cix[r] = (uint32_t)(q[r] >> 32);
+        frac[r] = (uint32_t)q[r];
+      }
     }
     if (!inside) return false;
     const int32_t fb = slot_of();
     if (fb < sc.r_lo || fb >= sc.r_hi) return true;
-    const uint32_t idx = __umul24(__umul24((uint32_t)(cq[2] >> 32), NY) + (uint32_t)(cq[1] >> 32), MX) +
-                         (uint32_t)(cq[0] >> 32);
+    const uint32_t idx = __umul24(__umul24(cix[2], NY) + cix[1], MX) + cix[0];
     float c[2][2][2];
     gather<FQ>(rsrc, idx, SZ, c);
-    const float tx = (float)(uint32_t)cq[0] * 2.3283064365386963e-10f;
-    const float ty = (float)(uint32_t)cq[1] * 2.3283064365386963e-10f;
-    const float tz = (float)(uint32_t)cq[2] * 2.3283064365386963e-10f;
+    const float tx = (float)frac[0] * 2.3283064365386963e-10f;
+    const float ty = (float)frac[1] * 2.3283064365386963e-10f;
+    const float tz = (float)frac[2] * 2.3283064365386963e-10f;
     const float v0 = lerpf(lerpf(c[0][0][0], c[0][0][1], tx), lerpf(c[0][1][0], c[0][1][1], tx), ty);
     const float v1 = lerpf(lerpf(c[1][0][0], c[1][0][1], tx), lerpf(c[1][1][0], c[1][1][1], tx), ty);
     const float v = lerpf(v0, v1, tz);
@@ -528,6 +547,7 @@ __global__ __launch_bounds__(NT) void parzen_bwd_kernel(ParzenArgs a) {
     const int dx = lane & (kTileX - 1), dy = lane / kTileX;
     GroupWalk w;
     w.init(Mq, a.fny, a.fnz, a.chunks, sc.chunk, wave, NW, dx, dy);
+    const int32_t nq[3] = {a.mnx, a.mny, a.mnz};
     const uint64_t top[3] = {(uint64_t)(a.mnx - 1) << 32, (uint64_t)(a.mny - 1) << 32,
                              (uint64_t)(a.mnz - 1) << 32};
     const uint32_t NY = (uint32_t)a.mny, MX = (uint32_t)a.mnx;
@@ -547,27 +567,30 @@ __global__ __launch_bounds__(NT) void parzen_bwd_kernel(ParzenArgs a) {
       for (int x = dx; x < a.fnx; x += kTileX) {
         const int32_t fbv = fb_next;
         if (x + kTileX < a.fnx) fb_next = (int32_t)frow[x + kTileX];
-        uint64_t cq[3];
+        uint32_t cell[3], frac[3];
         bool inside = true, moves[3];
 #pragma unroll
         for (int r = 0; r < 3; ++r) {
-          cq[r] = (uint64_t)q[r];
           // a clamped coordinate does not move with the transform
-          moves[r] = cq[r] <= top[r];
-          if (CLAMP) cq[r] = q[r] < 0 ? 0 : (cq[r] > top[r] ? top[r] : cq[r]);
-          else inside = inside && moves[r];
+          moves[r] = (uint64_t)q[r] <= top[r];
+          if (CLAMP) {
+            clamp_q32(q[r], nq[r], cell[r], frac[r]);
+          } else {
+            inside = inside && moves[r];
+            cell[r] = (uint32_t)(q[r] >> 32);
+            frac[r] = (uint32_t)q[r];
+          }
           q[r] += w.step[r];
         }
         if (!inside) continue;
         const int32_t fb = fbv;
         if (fb < sc.r_lo || fb >= sc.r_hi) continue;
-        const uint32_t idx = __umul24(__umul24((uint32_t)(cq[2] >> 32), NY) + (uint32_t)(cq[1] >> 32), MX) +
-                             (uint32_t)(cq[0] >> 32);
+        const uint32_t idx = __umul24(__umul24(cell[2], NY) + cell[1], MX) + cell[0];
         float c[2][2][2];
         gather<FQ>(rsrc, idx, SZ, c);
-        const float tx = (float)(uint32_t)cq[0] * 2.3283064365386963e-10f;
-        const float ty = (float)(uint32_t)cq[1] * 2.3283064365386963e-10f;
-        const float tz = (float)(uint32_t)cq[2] * 2.3283064365386963e-10f;
+        const float tx = (float)frac[0] * 2.3283064365386963e-10f;
+        const float ty = (float)frac[1] * 2.3283064365386963e-10f;
+        const float tz = (float)frac[2] * 2.3283064365386963e-10f;
         // x-lerps per (y, z) edge and their x-slopes
         const float e00 = lerpf(c[0][0][0], c[0][0][1], tx), e01 = lerpf(c[0][1][0], c[0][1][1], tx);
         const float e10 = lerpf(c[1][0][0], c[1][0][1], tx), e11 = lerpf(c[1][1][0], c[1][1][1], tx);
