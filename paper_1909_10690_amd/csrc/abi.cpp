@@ -490,7 +490,7 @@ struct PairsPlan {
   size_t off_desc = 0, off_frow = 0, off_mrow = 0, off_tbase = 0, off_xcd = 0;
   std::vector<size_t> fbins, octs;
   std::vector<int32_t> chunks;
-  std::vector<int64_t> frow_base, mrow_base, t_base, xcd_base;  // xcd_base: [8][P+1]
+  std::vector<int64_t> fchunk_base, mchunk_base, t_base, xcd_base;  // xcd_base: [8][P+1]
   int64_t total_t = 0;
   bool oct8 = true;  // every moving range <= 256: 8-bit corners for all pairs
 };
@@ -506,8 +506,8 @@ int plan_pairs(const mi_pair* pairs, int32_t n_pairs, int32_t bins, int32_t n_q,
   plan.fbins.resize(P);
   plan.octs.resize(P);
   plan.chunks.resize(P);
-  plan.frow_base.assign(P + 1, 0);
-  plan.mrow_base.assign(P + 1, 0);
+  plan.fchunk_base.assign(P + 1, 0);
+  plan.mchunk_base.assign(P + 1, 0);
   plan.t_base.assign(P + 1, 0);
   plan.xcd_base.assign(8 * (size_t)(P + 1), 0);
   const bool packed = bins > 128;
@@ -528,8 +528,8 @@ int plan_pairs(const mi_pair* pairs, int32_t n_pairs, int32_t bins, int32_t n_q,
     if (c < 8) c = 8;
     c = ((c + 7) / 8) * 8;
     plan.chunks[p] = (int32_t)c;
-    plan.frow_base[p + 1] = plan.frow_base[p] + (int64_t)pr.fixed.ny * pr.fixed.nz;
-    plan.mrow_base[p + 1] = plan.mrow_base[p] + (int64_t)pr.moving.ny * pr.moving.nz;
+    plan.fchunk_base[p + 1] = plan.fchunk_base[p] + ((int64_t)voxels(&pr.fixed) + kPrepChunk - 1) / kPrepChunk;
+    plan.mchunk_base[p + 1] = plan.mchunk_base[p] + ((int64_t)voxels(&pr.moving) + kPrepChunk - 1) / kPrepChunk;
     plan.t_base[p + 1] = plan.t_base[p] + pr.n_transforms;
     for (int x = 0; x < 8; ++x)
       plan.xcd_base[(size_t)x * (P + 1) + p + 1] =
@@ -1175,8 +1175,8 @@ int mi_eval_pairs(mi_context* ctx, const mi_pair* pairs, int32_t n_pairs, int32_
   std::vector<char> blob(plan.table_bytes, 0);
   char* b = blob.data();
   memcpy(b + plan.off_desc, desc_v.data(), sizeof(PairDesc) * P);
-  memcpy(b + plan.off_frow, plan.frow_base.data(), 8 * (P + 1));
-  memcpy(b + plan.off_mrow, plan.mrow_base.data(), 8 * (P + 1));
+  memcpy(b + plan.off_frow, plan.fchunk_base.data(), 8 * (P + 1));
+  memcpy(b + plan.off_mrow, plan.mchunk_base.data(), 8 * (P + 1));
   memcpy(b + plan.off_tbase, plan.t_base.data(), 8 * (P + 1));
   memcpy(b + plan.off_xcd, plan.xcd_base.data(), 8 * 8 * (P + 1));
   char* dtab = ws + plan.tables;
@@ -1201,8 +1201,8 @@ int mi_eval_pairs(mi_context* ctx, const mi_pair* pairs, int32_t n_pairs, int32_
   PairsArgs& a = L.args;
   a.pairs = (const PairDesc*)(dtab + plan.off_desc);
   a.n_pairs = P;
-  a.frow_base = (const int64_t*)(dtab + plan.off_frow);
-  a.mrow_base = (const int64_t*)(dtab + plan.off_mrow);
+  a.fchunk_base = (const int64_t*)(dtab + plan.off_frow);
+  a.mchunk_base = (const int64_t*)(dtab + plan.off_mrow);
   a.t_base = (const int64_t*)(dtab + plan.off_tbase);
   a.xcd_base = (const int64_t*)(dtab + plan.off_xcd);
   a.counters = (unsigned long long*)(ws + plan.counters);
@@ -1210,8 +1210,8 @@ int mi_eval_pairs(mi_context* ctx, const mi_pair* pairs, int32_t n_pairs, int32_
   a.hist = (uint32_t*)(ws + plan.hist);
   a.bins = bins;
   L.total_t = plan.total_t;
-  L.fixed_rows = plan.frow_base[P];
-  L.moving_rows = plan.mrow_base[P];
+  L.fixed_chunks = plan.fchunk_base[P];
+  L.moving_chunks = plan.mchunk_base[P];
   L.clamp = (flags & MI_BOUNDARY_CLAMP) ? 1 : 0;
   L.packed = bins > 128 ? 1 : 0;
   L.oct8 = plan.oct8 ? 1 : 0;

@@ -329,11 +329,13 @@ struct PairDesc {
   int32_t n_t, chunks;       // transforms, slabs (a multiple of 8)
 };
 
+constexpr int kPrepChunk = 256;  // voxels per wave in the pairs' preparation (4 per lane)
+
 struct PairsArgs {
   const PairDesc* pairs;
   int32_t n_pairs;
-  const int64_t* frow_base;  // [P+1] prefix of fixed rows
-  const int64_t* mrow_base;  // [P+1] prefix of moving rows, mnz*mny per pair
+  const int64_t* fchunk_base;  // [P+1] prefix of kPrepChunk-voxel chunks of the fixed volumes
+  const int64_t* mchunk_base;  // [P+1] the same for the moving volumes
   const int64_t* t_base;     // [P+1] prefix of transforms
   const int64_t* xcd_base;   // [8][P+1] prefix of work items per XCD
   unsigned long long* counters;  // [8] work-queue heads
@@ -344,7 +346,7 @@ struct PairsArgs {
 
 struct PairsLaunch {
   PairsArgs args;
-  int64_t total_t, fixed_rows, moving_rows;
+  int64_t total_t, fixed_chunks, moving_chunks;
   int32_t clamp, packed, cu_count;
   int32_t oct8;  // every pair's moving volume packed with 8-bit corners
 };

@@ -78,17 +78,17 @@ __device__ __forceinline__ T uniform(const T& v) {
   return r;
 }
 
-// Calls f(p, row, lane) for the rows of the concatenated row space
+// Calls f(p, item, lane) for the items of the concatenated item space
 // [base[0], base[P]) that fall to this workgroup: a contiguous range per
-// workgroup, one wave per row.  The pair is found once per wave and then
-// advanced as the rows ascend (a search per row would serialise dependent
-// loads on every row of small volumes).
+// workgroup, one wave per item.  The pair is found once per wave and then
+// advanced as the items ascend (a search per item would serialise dependent
+// loads on every item of small volumes).
 template <typename F>
-__device__ __forceinline__ void for_each_row(const int64_t* __restrict__ base, int P, int64_t rows,
-                                             F&& f) {
-  const int64_t per = (rows + gridDim.x - 1) / gridDim.x;
+__device__ __forceinline__ void for_each_item(const int64_t* __restrict__ base, int P, int64_t items,
+                                              F&& f) {
+  const int64_t per = (items + gridDim.x - 1) / gridDim.x;
   const int64_t r0 = (int64_t)blockIdx.x * per;
-  const int64_t r1 = r0 + per < rows ? r0 + per : rows;
+  const int64_t r1 = r0 + per < items ? r0 + per : items;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int nw = blockDim.x >> 6;
   const int lane = threadIdx.x & 63;
@@ -100,92 +100,100 @@ __device__ __forceinline__ void for_each_row(const int64_t* __restrict__ base, i
   }
 }
 
-// Fixed bins of every pair, one wave per fixed row.
-__global__ void prep_fixed_kernel(PairsArgs a, int64_t rows) {
-  for_each_row(a.frow_base, a.n_pairs, rows, [&](int p, int64_t row, int lane) {
+// Fixed bins of every pair, one wave per chunk of kPrepChunk consecutive
+// voxels (four per lane) of a pair's fixed volume: every lane busy whatever
+// the row length.
+__global__ void prep_fixed_kernel(PairsArgs a, int64_t chunks) {
+  for_each_item(a.fchunk_base, a.n_pairs, chunks, [&](int p, int64_t c, int lane) {
     const PairDesc d = uniform(a.pairs[p]);
-    const int32_t nx = d.geom.fnx;
-    global_out8* __restrict__ out = (global_out8*)d.geom.fbins + row * nx;
-    const size_t base = (size_t)row * nx;
-    if (d.fdtype == 0 && (nx & 3) == 0 && ((uintptr_t)d.fixed & 3) == 0) {
-      // u8 rows of a multiple of 4 voxels, 4-byte aligned volume: four voxels
-      // per lane, 32-bit loads and stores
-      global_cu32* __restrict__ src = (global_cu32*)((global_u8*)d.fixed + base);
-      for (int32_t x4 = lane; x4 < nx / 4; x4 += 64) {
-        const uint32_t w = src[x4];
-        uint32_t o = 0;
+    const int64_t nvox = (int64_t)d.geom.fnx * d.geom.fny * d.geom.fnz;
+    const int64_t v0 = c * kPrepChunk + 4 * lane;
+    if (v0 >= nvox) return;
+    global_out8* __restrict__ out = (global_out8*)d.geom.fbins;
+    if (d.fdtype == 0 && v0 + 4 <= nvox && ((uintptr_t)d.fixed & 3) == 0) {
+      // u8, 4-byte aligned volume: one 32-bit load and store for four voxels
+      // (the bins start 256-byte aligned and v0 is a multiple of 4)
+      const uint32_t w = *(global_cu32*)((global_u8*)d.fixed + v0);
+      uint32_t o = 0;
 #pragma unroll
-        for (int k = 0; k < 4; ++k)
-          o |= fixed_bin_int((int32_t)((w >> (8 * k)) & 0xFFu), (int32_t)d.flo, (int32_t)d.fhi,
-                             (uint32_t)d.geom.bins, d.fdiv) << (8 * k);
-        ((global_out32*)out)[x4] = o;
-      }
+      for (int k = 0; k < 4; ++k)
+        o |= fixed_bin_int((int32_t)((w >> (8 * k)) & 0xFFu), (int32_t)d.flo, (int32_t)d.fhi,
+                           (uint32_t)d.geom.bins, d.fdiv) << (8 * k);
+      *(global_out32*)(out + v0) = o;
       return;
     }
-    for (int32_t x = lane; x < nx; x += 64) {
+    for (int64_t v = v0; v < v0 + 4 && v < nvox; ++v) {
       uint32_t b;
       if (d.fdtype == 3)
-        b = fixed_bin_real((double)((global_f32*)d.fixed)[base + x], d.flo, d.fhi, d.geom.bins);
+        b = fixed_bin_real((double)((global_f32*)d.fixed)[v], d.flo, d.fhi, d.geom.bins);
       else
-        b = fixed_bin_int(load_int(d.fixed, d.fdtype, base + x), (int32_t)d.flo, (int32_t)d.fhi,
+        b = fixed_bin_int(load_int(d.fixed, d.fdtype, v), (int32_t)d.flo, (int32_t)d.fhi,
                           (uint32_t)d.geom.bins, d.fdiv);
-      out[x] = (uint8_t)b;
+      out[v] = (uint8_t)b;
     }
   });
 }
 
-// Moving oct volumes of every pair, one wave per moving row (z < nz, y < ny),
-// with the layout and clamping of the single-pair path.
-__global__ void prep_moving_kernel(PairsArgs a, int64_t rows) {
-  for_each_row(a.mrow_base, a.n_pairs, rows, [&](int p, int64_t row, int lane) {
+// Moving oct volumes of every pair, one wave per chunk of kPrepChunk
+// consecutive voxels (four per lane), with the layout and clamping of the
+// single-pair path.
+__global__ void prep_moving_kernel(PairsArgs a, int64_t chunks) {
+  for_each_item(a.mchunk_base, a.n_pairs, chunks, [&](int p, int64_t c, int lane) {
     const PairDesc d = uniform(a.pairs[p]);
     const int32_t nx = d.geom.mnx, ny = d.geom.mny, nz = d.geom.mnz;
-    const int32_t z = (int32_t)(row / ny), y = (int32_t)(row - (int64_t)z * ny);
-    const size_t r00 = ((size_t)z * ny + y) * nx;
-    const size_t r10 = r00 + (y + 1 < ny ? nx : 0);
-    const size_t dz = z + 1 < nz ? (size_t)nx * ny : 0;
+    const uint32_t nvox = (uint32_t)nx * (uint32_t)ny * (uint32_t)nz;  // < 2^28
+    const uint32_t v0 = (uint32_t)(c * kPrepChunk) + 4u * (uint32_t)lane;
+    if (v0 >= nvox) return;
     auto v = [&](size_t i) -> uint32_t { return clamp_offset(load_int(d.moving, d.mdtype, i), d.mlo, d.mhi); };
+    const uint32_t plane = (uint32_t)nx * (uint32_t)ny;
     if (d.geom.oct8 && d.mdtype == 0 && (nx & 3) == 0 && ((uintptr_t)d.moving & 3) == 0) {
-      // u8 rows of a multiple of 4 voxels, 4-byte aligned volume: four voxels
-      // per lane; each source row is read as one dword plus its next
-      // (clamped) byte
-      global_out4* __restrict__ out = (global_out4*)((global_out2*)d.geom.octs + row * nx);
+      // u8 rows of a multiple of 4 voxels, 4-byte aligned volume: the lane's
+      // four voxels share a row; each source row is read as one dword plus
+      // its next (clamped) byte
+      const uint32_t row = v0 / (uint32_t)nx, x0 = v0 - row * (uint32_t)nx;
+      const uint32_t z = row / (uint32_t)ny, y = row - z * (uint32_t)ny;
+      const size_t r00 = (size_t)row * nx;
+      const size_t r10 = r00 + (y + 1 < (uint32_t)ny ? nx : 0);
+      const size_t dz = z + 1 < (uint32_t)nz ? plane : 0;
       global_u8* __restrict__ mv = (global_u8*)d.moving;
       const size_t src[4] = {r00, r10, r00 + dz, r10 + dz};
-      for (int32_t x4 = lane; x4 < nx / 4; x4 += 64) {
-        const int32_t x0 = 4 * x4, xn = x0 + 4 < nx ? x0 + 4 : nx - 1;
-        uint32_t b[4][5];  // b[row][i] = clamped, offset value at x0 + i (i = 4: the neighbour)
+      const uint32_t xn = x0 + 4 < (uint32_t)nx ? x0 + 4 : (uint32_t)nx - 1;
+      uint32_t b[4][5];  // b[row][i] = clamped, offset value at x0 + i (i = 4: the neighbour)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const uint32_t w = *(global_cu32*)(mv + src[r] + x0);
+      for (int r = 0; r < 4; ++r) {
+        const uint32_t w = *(global_cu32*)(mv + src[r] + x0);
 #pragma unroll
-          for (int i = 0; i < 4; ++i) b[r][i] = clamp_offset((int32_t)((w >> (8 * i)) & 0xFFu), d.mlo, d.mhi);
-          b[r][4] = clamp_offset((int32_t)mv[src[r] + xn], d.mlo, d.mhi);
-        }
-        uint32_t o[8];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          o[2 * i] = b[0][i] | (b[0][i + 1] << 8) | (b[1][i] << 16) | (b[1][i + 1] << 24);
-          o[2 * i + 1] = b[2][i] | (b[2][i + 1] << 8) | (b[3][i] << 16) | (b[3][i + 1] << 24);
-        }
-        out[2 * x4] = uint4_t{o[0], o[1], o[2], o[3]};
-        out[2 * x4 + 1] = uint4_t{o[4], o[5], o[6], o[7]};
+        for (int i = 0; i < 4; ++i) b[r][i] = clamp_offset((int32_t)((w >> (8 * i)) & 0xFFu), d.mlo, d.mhi);
+        b[r][4] = clamp_offset((int32_t)mv[src[r] + xn], d.mlo, d.mhi);
       }
-    } else if (d.geom.oct8) {
-      // 8-bit corners: byte 4 dz + 2 dy + dx' (layout of pack_oct8_kernel)
-      global_out2* __restrict__ out = (global_out2*)d.geom.octs + row * nx;
-      for (int32_t x = lane; x < nx; x += 64) {
-        const int32_t x1 = x + 1 < nx ? x + 1 : nx - 1;
-        out[x] = uint2_t{v(r00 + x) | (v(r00 + x1) << 8) | (v(r10 + x) << 16) | (v(r10 + x1) << 24),
-                         v(r00 + dz + x) | (v(r00 + dz + x1) << 8) | (v(r10 + dz + x) << 16) |
-                             (v(r10 + dz + x1) << 24)};
+      uint32_t o[8];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        o[2 * i] = b[0][i] | (b[0][i + 1] << 8) | (b[1][i] << 16) | (b[1][i + 1] << 24);
+        o[2 * i + 1] = b[2][i] | (b[2][i + 1] << 8) | (b[3][i] << 16) | (b[3][i + 1] << 24);
       }
-    } else {
-      global_out4* __restrict__ out = (global_out4*)d.geom.octs + row * nx;
-      for (int32_t x = lane; x < nx; x += 64) {
-        const int32_t x1 = x + 1 < nx ? x + 1 : nx - 1;
-        out[x] = uint4_t{v(r00 + x) | (v(r00 + x1) << 16), v(r10 + x) | (v(r10 + x1) << 16),
-                         v(r00 + dz + x) | (v(r00 + dz + x1) << 16), v(r10 + dz + x) | (v(r10 + dz + x1) << 16)};
+      global_out4* __restrict__ out = (global_out4*)((global_out2*)d.geom.octs + v0);
+      out[0] = uint4_t{o[0], o[1], o[2], o[3]};
+      out[1] = uint4_t{o[4], o[5], o[6], o[7]};
+      return;
+    }
+    for (uint32_t vx = v0; vx < v0 + 4 && vx < nvox; ++vx) {
+      const uint32_t row = vx / (uint32_t)nx, x = vx - row * (uint32_t)nx;
+      const uint32_t z = row / (uint32_t)ny, y = row - z * (uint32_t)ny;
+      const size_t r00 = (size_t)row * nx;
+      const size_t r10 = r00 + (y + 1 < (uint32_t)ny ? nx : 0);
+      const size_t dz = z + 1 < (uint32_t)nz ? plane : 0;
+      const uint32_t x1 = x + 1 < (uint32_t)nx ? x + 1 : (uint32_t)nx - 1;
+      if (d.geom.oct8) {
+        // 8-bit corners: byte 4 dz + 2 dy + dx' (layout of pack_oct8_kernel)
+        ((global_out2*)d.geom.octs)[vx] =
+            uint2_t{v(r00 + x) | (v(r00 + x1) << 8) | (v(r10 + x) << 16) | (v(r10 + x1) << 24),
+                    v(r00 + dz + x) | (v(r00 + dz + x1) << 8) | (v(r10 + dz + x) << 16) |
+                        (v(r10 + dz + x1) << 24)};
+      } else {
+        ((global_out4*)d.geom.octs)[vx] =
+            uint4_t{v(r00 + x) | (v(r00 + x1) << 16), v(r10 + x) | (v(r10 + x1) << 16),
+                    v(r00 + dz + x) | (v(r00 + dz + x1) << 16), v(r10 + dz + x) | (v(r10 + dz + x1) << 16)};
       }
     }
   });
@@ -222,8 +230,8 @@ __global__ __launch_bounds__(NT) void hist_pairs_kernel(PairsArgs a) {
   }
 }
 
-// Workgroups (4 waves each) for a row kernel: a few per CU, fewer for small
-// row counts.
+// Workgroups (4 waves each) for a preparation kernel: a few per CU, fewer
+// for small item counts.
 static unsigned row_grid(int64_t rows) {
   const int64_t g = (rows + 3) / 4;
   return (unsigned)(g < 4096 ? (g > 0 ? g : 1) : 4096);
@@ -235,12 +243,12 @@ hipError_t launch_pairs_prep(const PairsLaunch& L, hipStream_t s) {
     hipLaunchKernelGGL(gather_transforms_kernel, dim3((unsigned)(blocks < 4096 ? blocks : 4096)),
                        dim3(256), 0, s, L.args, L.total_t);
   }
-  if (L.fixed_rows > 0)
-    hipLaunchKernelGGL(prep_fixed_kernel, dim3(row_grid(L.fixed_rows)), dim3(256), 0, s, L.args,
-                       L.fixed_rows);
-  if (L.moving_rows > 0)
-    hipLaunchKernelGGL(prep_moving_kernel, dim3(row_grid(L.moving_rows)), dim3(256), 0, s, L.args,
-                       L.moving_rows);
+  if (L.fixed_chunks > 0)
+    hipLaunchKernelGGL(prep_fixed_kernel, dim3(row_grid(L.fixed_chunks)), dim3(256), 0, s, L.args,
+                       L.fixed_chunks);
+  if (L.moving_chunks > 0)
+    hipLaunchKernelGGL(prep_moving_kernel, dim3(row_grid(L.moving_chunks)), dim3(256), 0, s, L.args,
+                       L.moving_chunks);
   return hipGetLastError();
 }
 
