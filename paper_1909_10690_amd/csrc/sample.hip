@@ -39,7 +39,7 @@ __global__ __launch_bounds__(kListThreads) void sample_list_kernel(const uint8_t
   const int64_t stride = (int64_t)gridDim.x * kListThreads;
   // every lane runs the same number of rounds (the ballot needs the whole wave)
   const int64_t rounds = (nvox + stride - 1) / stride;
-  const int64_t plane = (int64_t)nx * ny;
+  const uint32_t plane = (uint32_t)nx * (uint32_t)ny;
   for (int64_t r = 0; r < rounds; ++r) {
     const int64_t i = r * stride + blockIdx.x * (int64_t)kListThreads + threadIdx.x;
     const bool keep = i < nvox && (splitmix64(seed, (uint64_t)i) >> 32) < thr;
@@ -52,10 +52,11 @@ __global__ __launch_bounds__(kListThreads) void sample_list_kernel(const uint8_t
     if (lane == 0) base = atomicAdd(n_list, (unsigned long long)__popcll(mask));
     base = __shfl(base, 0, 64);
     if (keep) {
-      const int64_t z = i / plane, rem = i - z * plane;
-      const int64_t y = rem / nx, x = rem - y * nx;
-      list[base + below] = make_uint2((uint32_t)x | ((uint32_t)y << 12) | ((uint32_t)fbins[i] << 24),
-                                      (uint32_t)z);
+      // fixed voxels < 2^28: 32-bit divisions
+      const uint32_t iu = (uint32_t)i;
+      const uint32_t z = iu / plane, rem = iu - z * plane;
+      const uint32_t y = rem / (uint32_t)nx, x = rem - y * (uint32_t)nx;
+      list[base + below] = make_uint2(x | (y << 12) | ((uint32_t)fbins[i] << 24), z);
     }
   }
 }
