@@ -122,6 +122,14 @@ extern "C" {
  * sample list, 8 bytes per fixed voxel).  Accepted (and implied) by
  * mi_eval_sampled; rejected (MI_ERR_FLAGS) by the other calls. */
 #define MI_SAMPLED 0x4000
+/* Hint for hard-binned mi_eval (and mi_tune) calls whose transforms rotate
+ * the moving volume widely, such as a rotation map: each workgroup sweeps a
+ * compact brick of whole x rows instead of a thin slab of whole slices, so
+ * that the moving footprints of the transforms running at once overlap in
+ * L2.  Results are identical; applies to the 1024-thread launch shape (the
+ * default); slower for translation-like batches.  Ignored by the Parzen
+ * and sampled paths; mi_eval_pairs does not take it (MI_ERR_FLAGS). */
+#define MI_COMPACT_SLABS 0x8000
 
 #define MI_MAX_Q 16
 #define MI_MAX_EDGE 4096

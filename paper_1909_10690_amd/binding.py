@@ -28,6 +28,7 @@ HIST_HARD, HIST_PARZEN = 0x0, 0x100
 USE_GRAPH = 0x1000
 VOLUMES_UNCHANGED = 0x2000  # reuse the workspace's prepared volumes (see include/gemi.h)
 SAMPLED = 0x4000  # workspace sizing for eval_sampled
+COMPACT_SLABS = 0x8000  # hint: bricks instead of thin slabs (rotation-heavy batches)
 TIMER_HARD, TIMER_PARZEN_FWD, TIMER_PARZEN_BWD, TIMER_PAIRS, TIMER_REDUCE = 0, 1, 2, 3, 4
 
 _TORCH_DTYPES = {torch.uint8: U8, torch.uint16: U16, torch.int16: I16, torch.float32: F32}

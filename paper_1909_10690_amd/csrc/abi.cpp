@@ -92,7 +92,7 @@ int check_moving(const mi_volume* m, bool need_integer) {
 }
 
 constexpr int32_t kKnownFlags = MI_BOUNDARY_CLAMP | MI_TSALLIS_PSEUDOADDITIVE | MI_HIST_PARZEN | MI_USE_GRAPH |
-                                MI_VOLUMES_UNCHANGED | MI_SAMPLED;
+                                MI_VOLUMES_UNCHANGED | MI_SAMPLED | MI_COMPACT_SLABS;
 
 // Random subsampling of the fixed volume (mi_eval_sampled).
 struct SampleSpec {
@@ -701,7 +701,7 @@ int launch_hard_hist(mi_context* ctx, const mi_volume* fixed, const mi_volume* m
     if (e != hipSuccess) return hip_fail(e, "pack");
   }
   if ((e = launch_fill_u32(hist, bb * n, 0u, s)) != hipSuccess) return hip_fail(e, "fill");
-  HardLaunch H;
+  HardLaunch H{};
   H.transforms = transforms;
   H.fbins = fb;
   H.octs = octs;
@@ -714,6 +714,7 @@ int launch_hard_hist(mi_context* ctx, const mi_volume* fixed, const mi_volume* m
   H.packed = use_packed(tune, bins) ? 1 : 0;
   H.block = tune.block;
   H.slab_major = tune.slab_major;
+  H.brick = (flags & MI_COMPACT_SLABS) ? 1 : 0;
   uint2* list = (uint2*)(ws + L.list);
   unsigned long long* nlist = (unsigned long long*)(ws + L.nlist);
   if (smp) {

@@ -161,6 +161,86 @@ struct GroupWalk {
   }
 };
 
+// The same walk in brick order: the row groups of a slice are cut along y
+// into blocks of `yb` groups and a block is visited slice by slice before
+// the next, so a slab -- a contiguous range of that numbering -- is a brick
+// of whole x rows, about as many rows deep (4 yb) as slices long.  A thin
+// slab of whole slices leaves its moving footprint under a small change of
+// rotation; a brick keeps much of it, so the transforms a slab meets in turn
+// reuse the XCD's L2 when they rotate widely (a rotation map).  Row
+// coordinates stay exact: stepped by kTileY M[:,1] inside a block row and
+// recomputed at each wrap.
+struct GroupWalkBrick {
+  int64_t g, g1;
+  int32_t j0, k;
+  int32_t G, nz, yb, b0, b1;  // y groups, slices, block width, current block [b0, b1)
+  int64_t r[3], lane_off[3], step[3], adv[3], m1[3], m2[3], m3[3];
+
+  __host__ __device__ __forceinline__ void init(const int64_t* Mq, int32_t fny, int32_t fnz,
+                                                int32_t chunks, uint32_t chunk, int wave, int nwaves,
+                                                int dx, int dy) {
+    G = (fny + kTileY - 1) / kTileY;
+    nz = fnz;
+    const int64_t groups = (int64_t)G * fnz;
+    const int64_t s0 = groups * chunk / chunks, s1 = groups * (chunk + 1) / chunks;
+    g = s0 + (s1 - s0) * wave / nwaves;
+    g1 = s0 + (s1 - s0) * (wave + 1) / nwaves;
+    // 4 yb rows ~ slices per slab = per_slab / yb
+    const int64_t per_slab = (groups + chunks - 1) / chunks;
+    const int32_t w = (int32_t)sqrt((double)per_slab / kTileY);
+    yb = w < 1 ? 1 : (w > G ? G : w);
+    const int64_t full = G / yb, per_full = (int64_t)yb * fnz;
+    b0 = 0;
+    b1 = G;
+    k = 0;
+    j0 = 0;
+    if (g < g1) {
+      if (g < full * per_full) {
+        const int64_t blk = g / per_full, rem = g - blk * per_full;
+        b0 = (int32_t)blk * yb;
+        b1 = b0 + yb;
+        k = (int32_t)(rem / yb);
+        j0 = (b0 + (int32_t)(rem - (int64_t)k * yb)) * kTileY;
+      } else {  // the last, narrower block (G not a multiple of yb)
+        const int64_t rem = g - full * per_full;
+        b0 = (int32_t)full * yb;
+        const int32_t bw = G - b0;
+        k = (int32_t)(rem / bw);
+        j0 = (b0 + (int32_t)(rem - (int64_t)k * bw)) * kTileY;
+      }
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const int64_t m0 = Mq[4 * a];
+      m1[a] = Mq[4 * a + 1];
+      m2[a] = Mq[4 * a + 2];
+      m3[a] = Mq[4 * a + 3];
+      r[a] = m1[a] * j0 + m2[a] * k + m3[a];
+      lane_off[a] = m0 * dx + m1[a] * dy;
+      step[a] = m0 * kTileX;
+      adv[a] = m1[a] * kTileY;
+    }
+  }
+
+  __host__ __device__ __forceinline__ void next() {
+    ++g;
+    j0 += kTileY;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) r[a] += adv[a];
+    if (j0 >= b1 * kTileY) {
+      j0 = b0 * kTileY;
+      if (++k >= nz) {
+        k = 0;
+        b0 = b1;
+        b1 = b1 + yb < G ? b1 + yb : G;
+        j0 = b0 * kTileY;
+      }
+#pragma unroll
+      for (int a = 0; a < 3; ++a) r[a] = m1[a] * j0 + m2[a] * k + m3[a];
+    }
+  }
+};
+
 // Geometry of one fixed/moving pair for the hard-binned sweep.
 struct HardGeom {
   const uint8_t* fbins;  // fixed bins, [fnz][fny][fnx]
@@ -192,6 +272,7 @@ struct HardLaunch {
   int32_t packed;  // 1: two 16-bit counters per LDS word (bins > 128)
   int32_t block;   // threads per workgroup: 256, 512 or 1024
   int32_t slab_major;  // workgroup order: 1 slab-major, 0 transform-major
+  int32_t brick;       // 1: slabs as bricks (GroupWalkBrick; 1024-thread launches)
 };
 
 // The gathers address their volume with 32-bit buffer offsets, so every

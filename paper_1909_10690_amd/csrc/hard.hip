@@ -202,7 +202,8 @@ struct HardArgs {
 // scratch) so that two of them, 8 waves per SIMD, share a CU next to two
 // 64 KiB LDS histograms; the sweep waits on its gathers and gains from the
 // extra waves.  Smaller workgroups keep their registers.
-template <bool CLAMP, bool PACKED, bool OCT8, int NT>
+// BRICK: slabs as bricks (GroupWalkBrick) rather than thin slabs.
+template <bool CLAMP, bool PACKED, bool OCT8, int NT, bool BRICK = false>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT == 1024 ? 8 : 1)))
 void hist_hard_kernel(HardArgs a) {
   extern __shared__ uint32_t lds_hist[];
@@ -214,7 +215,12 @@ void hist_hard_kernel(HardArgs a) {
   int64_t Mq[12];
   const bool ok = quantize_transform(a.transforms + 12 * (size_t)t, Mq);
   __syncthreads();
-  if (ok) sweep_hard<CLAMP, PACKED, OCT8, NT / 64>(a.geom, Mq, a.chunks, chunk, lds_hist);
+  if (ok) {
+    if (BRICK)
+      sweep_hard<CLAMP, PACKED, OCT8, NT / 64, GroupWalkBrick>(a.geom, Mq, a.chunks, chunk, lds_hist);
+    else
+      sweep_hard<CLAMP, PACKED, OCT8, NT / 64>(a.geom, Mq, a.chunks, chunk, lds_hist);
+  }
   __syncthreads();
   if (ok) flush_hist<PACKED, NT>(lds_hist, B, a.hist + (size_t)t * B * B, false);
 }
@@ -269,28 +275,28 @@ static hipError_t launch_sampled_variant(const HardArgs& a, const uint2* list, c
   return hipGetLastError();
 }
 
-template <bool CLAMP, bool PACKED, bool OCT8, int NT>
+template <bool CLAMP, bool PACKED, bool OCT8, int NT, bool BRICK>
 static hipError_t launch_variant(const HardArgs& a, int n, size_t lds, hipStream_t s) {
-  hipLaunchKernelGGL((hist_hard_kernel<CLAMP, PACKED, OCT8, NT>), dim3((unsigned)(n * a.chunks)),
+  hipLaunchKernelGGL((hist_hard_kernel<CLAMP, PACKED, OCT8, NT, BRICK>), dim3((unsigned)(n * a.chunks)),
                      dim3(NT), lds, s, a);
   return hipGetLastError();
 }
 
-template <bool OCT8, int NT>
+template <bool OCT8, int NT, bool BRICK>
 static hipError_t launch_layout(const HardArgs& a, int n, bool clamp, bool packed, size_t lds,
                                 hipStream_t s) {
   if (clamp)
-    return packed ? launch_variant<true, true, OCT8, NT>(a, n, lds, s)
-                  : launch_variant<true, false, OCT8, NT>(a, n, lds, s);
-  return packed ? launch_variant<false, true, OCT8, NT>(a, n, lds, s)
-                : launch_variant<false, false, OCT8, NT>(a, n, lds, s);
+    return packed ? launch_variant<true, true, OCT8, NT, BRICK>(a, n, lds, s)
+                  : launch_variant<true, false, OCT8, NT, BRICK>(a, n, lds, s);
+  return packed ? launch_variant<false, true, OCT8, NT, BRICK>(a, n, lds, s)
+                : launch_variant<false, false, OCT8, NT, BRICK>(a, n, lds, s);
 }
 
-template <int NT>
+template <int NT, bool BRICK = false>
 static hipError_t launch_nt(const HardArgs& a, int n, bool clamp, bool packed, size_t lds,
                             hipStream_t s) {
-  return a.geom.oct8 ? launch_layout<true, NT>(a, n, clamp, packed, lds, s)
-                     : launch_layout<false, NT>(a, n, clamp, packed, lds, s);
+  return a.geom.oct8 ? launch_layout<true, NT, BRICK>(a, n, clamp, packed, lds, s)
+                     : launch_layout<false, NT, BRICK>(a, n, clamp, packed, lds, s);
 }
 
 HardGeom make_hard_geom(const VolumeDesc& fixed, const VolumeDesc& moving, const uint8_t* fbins,
@@ -327,7 +333,9 @@ hipError_t launch_hist_hard(const HardLaunch& L, hipStream_t s) {
   switch (L.block) {
   case 256: return launch_nt<256>(a, L.n, L.clamp, L.packed, lds, s);
   case 512: return launch_nt<512>(a, L.n, L.clamp, L.packed, lds, s);
-  case 1024: return launch_nt<1024>(a, L.n, L.clamp, L.packed, lds, s);
+  case 1024:  // bricks only with the default 1024-thread shape
+    return L.brick ? launch_nt<1024, true>(a, L.n, L.clamp, L.packed, lds, s)
+                   : launch_nt<1024>(a, L.n, L.clamp, L.packed, lds, s);
   default: return hipErrorInvalidValue;
   }
 }
@@ -356,14 +364,17 @@ hipError_t launch_hist_sampled(const HardLaunch& L, const uint2* list, const uns
             : launch_sampled_variant<false, false, false>(a, list, n_list, lds, s);
 }
 
-template <int NT>
+template <int NT, bool BRICK = false>
 static hipError_t allow_big_lds() {
   const int bytes = 160 * 1024;
-  const void* fns[8] = {
-      (const void*)hist_hard_kernel<false, false, false, NT>, (const void*)hist_hard_kernel<true, false, false, NT>,
-      (const void*)hist_hard_kernel<false, true, false, NT>, (const void*)hist_hard_kernel<true, true, false, NT>,
-      (const void*)hist_hard_kernel<false, false, true, NT>, (const void*)hist_hard_kernel<true, false, true, NT>,
-      (const void*)hist_hard_kernel<false, true, true, NT>, (const void*)hist_hard_kernel<true, true, true, NT>};
+  const void* fns[8] = {(const void*)hist_hard_kernel<false, false, false, NT, BRICK>,
+                        (const void*)hist_hard_kernel<true, false, false, NT, BRICK>,
+                        (const void*)hist_hard_kernel<false, true, false, NT, BRICK>,
+                        (const void*)hist_hard_kernel<true, true, false, NT, BRICK>,
+                        (const void*)hist_hard_kernel<false, false, true, NT, BRICK>,
+                        (const void*)hist_hard_kernel<true, false, true, NT, BRICK>,
+                        (const void*)hist_hard_kernel<false, true, true, NT, BRICK>,
+                        (const void*)hist_hard_kernel<true, true, true, NT, BRICK>};
   for (const void* f : fns) {
     const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
     if (e != hipSuccess) return e;
@@ -387,6 +398,7 @@ hipError_t configure_hard_kernels() {
       return e;
   if ((e = allow_big_lds<256>()) != hipSuccess) return e;
   if ((e = allow_big_lds<512>()) != hipSuccess) return e;
+  if ((e = allow_big_lds<1024, true>()) != hipSuccess) return e;
   return allow_big_lds<1024>();
 }
 

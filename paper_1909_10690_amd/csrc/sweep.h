@@ -130,16 +130,17 @@ struct HardStep {
 };
 
 // Sweeps one slab of the fixed volume for one transform (Mq) into the
-// workgroup's LDS histogram.  NW waves share the slab's 4-row groups.
+// workgroup's LDS histogram.  NW waves share the slab's 4-row groups, in
+// the order of Walk (thin slabs, or bricks).
 // OCT8: the oct volume holds 8-bit corners (one 64-bit gather), unpacked
 // into the 16-bit pairs of the x-lerp with byte permutes.
-template <bool CLAMP, bool PACKED, bool OCT8, int NW>
+template <bool CLAMP, bool PACKED, bool OCT8, int NW, typename Walk = GroupWalk>
 __device__ __forceinline__ void sweep_hard(const HardGeom& g, const int64_t* Mq, int32_t chunks,
                                            uint32_t chunk, uint32_t* lds_hist) {
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   const int dx = lane & (kTileX - 1), dy = lane / kTileX;
-  GroupWalk w;
+  Walk w;
   w.init(Mq, g.fny, g.fnz, chunks, chunk, wave, NW, dx, dy);
   const int64_t sx = w.step[0], sy = w.step[1], sz = w.step[2];
   const HardStep hs(g, lds_hist);

@@ -28,6 +28,7 @@ from __future__ import annotations
 
 import numpy as np
 
+from . import binding as B
 from . import transforms as T
 
 FAMILIES = ("translation", "rotation", "scale")
@@ -115,6 +116,10 @@ def mi_map(ctx, fixed, moving, family: str, n: int = 51, extent: float | None = 
         raise ValueError(f"transforms must be [{total}][12]")
     qs = tuple(float(v) for v in np.atleast_1d(q))
     out = torch.empty((total, len(qs)), dtype=torch.float64, device=dev)
+    if family == "rotation" and sample is None and not flags & B.HIST_PARZEN:
+        # rotations of every size run at once: compact bricks keep their
+        # moving footprints overlapping in L2 (results are identical)
+        flags |= B.COMPACT_SLABS
     for a in range(0, total, batch):
         b = min(total, a + batch)
         if sample is None:

@@ -72,6 +72,7 @@ def test_header_constants_match_binding():
     assert consts["MI_TSALLIS_PSEUDOADDITIVE"] == B.TSALLIS_PSEUDOADDITIVE
     assert consts["MI_USE_GRAPH"] == B.USE_GRAPH
     assert consts["MI_SAMPLED"] == B.SAMPLED and consts["MI_ERR_SAMPLE"] == B.MI_ERR_SAMPLE
+    assert consts["MI_COMPACT_SLABS"] == B.COMPACT_SLABS
     assert ctypes.sizeof(B.MiVolume) == 40
 
 
@@ -250,7 +251,9 @@ def test_graph_flag_accepted_and_unknown_bits_rejected():
     assert call_eval(vol(), vol(), flags=B.USE_GRAPH | B.HIST_PARZEN) == B.MI_ERR_NULL
     assert call_eval(vol(), vol(), flags=B.VOLUMES_UNCHANGED | B.HIST_PARZEN) == B.MI_ERR_NULL
     assert call_eval(vol(), vol(), flags=B.SAMPLED) == B.MI_ERR_FLAGS  # mi_eval_sampled's flag
-    assert call_eval(vol(), vol(), flags=0x8000) == B.MI_ERR_FLAGS
+    assert call_eval(vol(), vol(), flags=B.COMPACT_SLABS) == B.MI_ERR_NULL  # a hint: accepted
+    assert call_eval(vol(), vol(), flags=B.COMPACT_SLABS | B.HIST_PARZEN) == B.MI_ERR_NULL
+    assert call_eval(vol(), vol(), flags=0x10000) == B.MI_ERR_FLAGS
 
 
 def call_sampled(f, m, fraction=0.25, seed=7, n=4, bins=32, flags=0, ws_bytes=1 << 40, hist=None, ws=FAKE):
@@ -268,7 +271,7 @@ def test_sampled_validation():
     assert call_sampled(vol(), vol(), flags=B.SAMPLED | B.HIST_PARZEN) == B.MI_ERR_NULL
     for bad in (0.0, -0.5, float("nan"), float("inf")):
         assert call_sampled(vol(), vol(), fraction=bad) == B.MI_ERR_SAMPLE
-    assert call_sampled(vol(), vol(), flags=0x8000) == B.MI_ERR_FLAGS
+    assert call_sampled(vol(), vol(), flags=0x10000) == B.MI_ERR_FLAGS
     assert call_sampled(vol(), vol(), flags=B.HIST_PARZEN, hist=FAKE) == B.MI_ERR_UNSUPPORTED
     assert call_sampled(vol(), vol(), ws=None) == B.MI_ERR_WORKSPACE
     # the plain workspace is too small: the sample list is missing

@@ -106,6 +106,38 @@ def test_random_affines(ctx, case, flags):
                   run_oracle(fixed, moving, fr, mr, mats, bins, q, flags), f"case {case}")
 
 
+@pytest.mark.parametrize("case", range(len(CASES)))
+@pytest.mark.parametrize("boundary", [0, 1])
+def test_compact_slabs_hint(ctx, case, boundary):
+    """Bricks instead of thin slabs (MI_COMPACT_SLABS): the same exact
+    histograms, on every shape including ragged row groups and slices."""
+    from paper_1909_10690_amd import binding as B
+    fixed, moving, fr, mr, mats, bins = _random_case(case, 7 + boundary)
+    q = [1.0, 1.5]
+    print(f"compact slabs case {case} boundary {boundary}", flush=True)
+    g = run_gpu(ctx, fixed, moving, fr, mr, mats, bins, q, boundary | B.COMPACT_SLABS)
+    assert_parity(g, run_oracle(fixed, moving, fr, mr, mats, bins, q, boundary), f"case {case}")
+
+
+def test_compact_slabs_rotation_map(ctx):
+    """A rotation map of the same image with and without the hint (the maps
+    module sets it for rotations): identical MI maps."""
+    import torch
+    from paper_1909_10690_amd import binding as B
+    from paper_1909_10690_amd import maps
+    c = inputs.same_image((48, 40, 36), seed=2, dtype=np.uint16)
+    F = B.Volume.from_numpy(c["fixed"], *c["fixed_range"])
+    tr = torch.from_numpy(maps.map_transforms("rotation", 9, (48, 40, 36))).cuda()
+    a, _, ha = ctx.eval(F, F, tr, 128, (1.0, 2.0), want_hist=True)
+    b, _, hb = ctx.eval(F, F, tr, 128, (1.0, 2.0), flags=B.COMPACT_SLABS, want_hist=True)
+    m = maps.mi_map(ctx, F, F, "rotation", 9, bins=128, q=(1.0, 2.0), batch=100)
+    torch.cuda.synchronize()
+    assert torch.equal(ha, hb) and torch.equal(a, b)
+    # batches of 100 may slice the reduction differently: last bits only
+    ref = a.t().reshape(2, 9, 9, 9)
+    assert torch.all((m - ref).abs() <= 1e-12 * torch.clamp(ref.abs(), min=1.0))
+
+
 def test_integer_translations_tiny(ctx):
     import itertools
     rng = np.random.default_rng(5)
