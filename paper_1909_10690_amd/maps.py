@@ -97,15 +97,30 @@ def map_transforms(family: str, n: int, fixed_shape_xyz, extent: float | None = 
     return T.index_matrices(A, t, fixed_shape_xyz, fixed_spacing, fixed_origin, moving_spacing, moving_origin)
 
 
+def z_order(n: int) -> np.ndarray:
+    """Grid rows (x fastest) in Z order (Morton order of (i, j, k)): runs of
+    consecutive rows are compact blocks of the parameter grid."""
+    g = np.arange(n ** 3)
+    k, r = np.divmod(g, n * n)
+    j, i = np.divmod(r, n)
+    code = np.zeros_like(g)
+    for b in range(int(n - 1).bit_length() if n > 1 else 1):
+        code |= (((i >> b) & 1) << (3 * b)) | (((j >> b) & 1) << (3 * b + 1)) | (((k >> b) & 1) << (3 * b + 2))
+    return np.argsort(code, kind="stable")
+
+
 def mi_map(ctx, fixed, moving, family: str, n: int = 51, extent: float | None = None, bins: int = 64,
-           q=(1.0,), flags: int = 0, batch: int = 16384, transforms=None, sample=None, **geometry):
+           q=(1.0,), flags: int = 0, batch: int = 16384, transforms=None, sample=None,
+           order: str = "auto", compact: str | bool = "auto", **geometry):
     """MI maps [n_q][n][n][n] (device float64, [z][y][x] order per q) of one
     family over an n^3 grid: batches of grid points through ``ctx.eval``
     (or, with ``sample`` = (fraction, seed), ``ctx.eval_sampled``: every
     point over the same random subset of fixed voxels, as Mattes' MI
     samples them).  ``transforms`` (the [n^3][12] matrices, on the device)
     may be given to skip building them; ``geometry`` takes the spacing /
-    origin arguments of :func:`map_transforms`."""
+    origin arguments of :func:`map_transforms`.  ``order`` ("grid", "z" or
+    "auto") and ``compact`` (bool or "auto") choose the evaluation order of
+    the grid points and the compact-slab sweep; neither changes a value."""
     import torch
     dev = fixed.tensor.device
     if transforms is None:
@@ -116,10 +131,23 @@ def mi_map(ctx, fixed, moving, family: str, n: int = 51, extent: float | None = 
         raise ValueError(f"transforms must be [{total}][12]")
     qs = tuple(float(v) for v in np.atleast_1d(q))
     out = torch.empty((total, len(qs)), dtype=torch.float64, device=dev)
-    if family == "rotation" and sample is None and not flags & B.HIST_PARZEN:
-        # rotations of every size run at once: compact bricks keep their
-        # moving footprints overlapping in L2 (results are identical)
+    hard = sample is None and not flags & B.HIST_PARZEN
+    # the transforms of a batch run at once: in Z order they are compact
+    # blocks of the grid, and for rotations compact bricks keep their moving
+    # footprints overlapping in L2 (results are identical); the rows are put
+    # back in grid order afterwards
+    if compact == "auto":
+        compact = hard and family == "rotation"
+    if order == "auto":
+        order = "z" if hard and family == "rotation" else "grid"
+    if compact:
         flags |= B.COMPACT_SLABS
+    if order == "z":
+        order = torch.from_numpy(z_order(n)).to(dev)
+        transforms = transforms.index_select(0, order)
+        grid_out, out = out, torch.empty_like(out)
+    else:
+        order = None
     for a in range(0, total, batch):
         b = min(total, a + batch)
         if sample is None:
@@ -127,6 +155,9 @@ def mi_map(ctx, fixed, moving, family: str, n: int = 51, extent: float | None = 
         else:
             ctx.eval_sampled(fixed, moving, transforms[a:b], bins, qs, fraction=sample[0], seed=sample[1],
                              flags=flags, want_overlap=False, out=out[a:b])
+    if order is not None:
+        grid_out.index_copy_(0, order, out)
+        out = grid_out
     return out.t().reshape(len(qs), n, n, n).contiguous()
 
 
