@@ -190,6 +190,10 @@ hipError_t launch_pack_octs(const VolumeDesc& m, uint4* out, hipStream_t s) {
 // the histogram sweep
 // ---------------------------------------------------------------------------
 
+// Dynamic LDS limit of the hard sweeps (a u32 table up to 128 bins, 16-bit
+// pairs above: at most 128 KiB), within the 160 KiB of a workgroup.
+constexpr size_t kHardLdsMax = 160 * 1024;
+
 struct HardArgs {
   const double* transforms;
   uint32_t* hist;
@@ -330,6 +334,7 @@ hipError_t launch_hist_hard(const HardLaunch& L, hipStream_t s) {
   a.chunks = L.chunks;
   a.slab_major = L.slab_major;
   const size_t lds = L.packed ? (((size_t)L.bins * L.bins + 1) / 2) * 4 : (size_t)L.bins * L.bins * 4;
+  if (lds > kHardLdsMax) return hipErrorInvalidValue;  // above the limit the kernels are configured for
   switch (L.block) {
   case 256: return launch_nt<256>(a, L.n, L.clamp, L.packed, lds, s);
   case 512: return launch_nt<512>(a, L.n, L.clamp, L.packed, lds, s);
@@ -351,6 +356,7 @@ hipError_t launch_hist_sampled(const HardLaunch& L, const uint2* list, const uns
   a.chunks = L.chunks;
   a.slab_major = 1;
   const size_t lds = L.packed ? (((size_t)L.bins * L.bins + 1) / 2) * 4 : (size_t)L.bins * L.bins * 4;
+  if (lds > kHardLdsMax) return hipErrorInvalidValue;  // above the limit the kernels are configured for
   const bool o8 = a.geom.oct8 != 0;
   if (L.clamp) {
     if (L.packed) return o8 ? launch_sampled_variant<true, true, true>(a, list, n_list, lds, s)
@@ -366,7 +372,7 @@ hipError_t launch_hist_sampled(const HardLaunch& L, const uint2* list, const uns
 
 template <int NT, bool BRICK = false>
 static hipError_t allow_big_lds() {
-  const int bytes = 160 * 1024;
+  const int bytes = (int)kHardLdsMax;
   const void* fns[8] = {(const void*)hist_hard_kernel<false, false, false, NT, BRICK>,
                         (const void*)hist_hard_kernel<true, false, false, NT, BRICK>,
                         (const void*)hist_hard_kernel<false, true, false, NT, BRICK>,
@@ -394,7 +400,7 @@ hipError_t configure_hard_kernels() {
       (const void*)hist_sampled_kernel<false, true, true, kSampledBlock>,
       (const void*)hist_sampled_kernel<true, true, true, kSampledBlock>};
   for (const void* f : sampled)
-    if ((e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024)) != hipSuccess)
+    if ((e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kHardLdsMax)) != hipSuccess)
       return e;
   if ((e = allow_big_lds<256>()) != hipSuccess) return e;
   if ((e = allow_big_lds<512>()) != hipSuccess) return e;

@@ -258,6 +258,7 @@ template <bool CLAMP, bool PACKED, bool OCT8>
 static hipError_t pairs_variant(const PairsLaunch& L, hipStream_t s) {
   const int B = L.args.bins;
   const size_t lds = PACKED ? (((size_t)B * B + 1) / 2) * 4 : (size_t)B * B * 4;
+  if (lds > 150 * 1024) return hipErrorInvalidValue;  // the limit set below
   const void* fn = (const void*)hist_pairs_kernel<CLAMP, PACKED, OCT8, kPairsBlock>;
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
   if (e != hipSuccess) return e;

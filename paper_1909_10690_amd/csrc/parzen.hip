@@ -193,6 +193,12 @@ __device__ __forceinline__ unsigned long long fixed40(float w) {
   return ((unsigned long long)hi << 32) | lo;
 }
 
+// Dynamic LDS per workgroup of the Parzen sweeps: two per CU with the
+// static arrays beside them.  Larger budgets (fewer bands at 256 bins)
+// measured slower: 96 KiB and 128 KiB took the CT/MR iteration from 2.54 to
+// 3.04 and 3.16 ms (one workgroup per CU).
+constexpr size_t kParzenLdsMax = 64 * 1024;
+
 // Sweep geometry of one workgroup.
 struct SweepCtx {
   uint32_t t, chunk, band;
@@ -661,6 +667,7 @@ static hipError_t fwd_variant(const ParzenArgs& a, size_t lds, hipStream_t s) {
 hipError_t launch_parzen_fwd(const ParzenLaunch& L, hipStream_t s) {
   ParzenArgs a = L.args;
   const size_t lds = (size_t)(a.band_rows + kHotCopies - 1) * a.bins * 8;
+  if (lds > kParzenLdsMax) return hipErrorInvalidValue;  // bands are sized to fit
   if (L.float_quads)
     return L.clamp ? fwd_variant<true, true>(a, lds, s) : fwd_variant<true, false>(a, lds, s);
   return L.clamp ? fwd_variant<false, true>(a, lds, s) : fwd_variant<false, false>(a, lds, s);
@@ -678,6 +685,7 @@ hipError_t launch_parzen_sampled_fwd(const ParzenLaunch& L, const uint2* list, c
                                      hipStream_t s) {
   ParzenArgs a = L.args;
   const size_t lds = (size_t)(a.band_rows + kHotCopies - 1) * a.bins * 8;
+  if (lds > kParzenLdsMax) return hipErrorInvalidValue;  // bands are sized to fit
   if (L.float_quads)
     return L.clamp ? sampled_fwd_variant<true, true>(a, list, n_list, lds, s)
                    : sampled_fwd_variant<true, false>(a, list, n_list, lds, s);
@@ -701,15 +709,17 @@ static hipError_t bwd_variant(const ParzenArgs& a, size_t lds, hipStream_t s) {
 hipError_t launch_parzen_bwd(const ParzenLaunch& L, hipStream_t s) {
   ParzenArgs a = L.args;
   const size_t lds = (size_t)kParzenQGroup * a.band_rows * a.bins * 4;
+  if (lds > kParzenLdsMax) return hipErrorInvalidValue;  // bands are sized to fit
   if (L.float_quads)
     return L.clamp ? bwd_variant<true, true>(a, lds, s) : bwd_variant<true, false>(a, lds, s);
   return L.clamp ? bwd_variant<false, true>(a, lds, s) : bwd_variant<false, false>(a, lds, s);
 }
 
-// The bands are sized for at most 64 KiB of dynamic LDS per workgroup.
+// The bands are sized for at most kParzenLdsMax of dynamic LDS per
+// workgroup.
 template <bool FQ, bool CLAMP>
 static hipError_t allow_lds() {
-  const int bytes = 64 * 1024;
+  const int bytes = (int)kParzenLdsMax;
   hipError_t e;
   if ((e = hipFuncSetAttribute((const void*)parzen_fwd_kernel<FQ, CLAMP, 512>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, bytes)) != hipSuccess)
