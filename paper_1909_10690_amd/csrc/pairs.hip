@@ -12,9 +12,9 @@
 // at a time and share its moving footprint in L2.  Every workgroup leaves
 // the loop once its queue is empty, so the grid always drains.
 //
-// Per-pair fixed bins and moving oct volumes are prepared by two row
-// kernels over all pairs, and the transforms are gathered into one array
-// for the MI reduction.
+// Per-pair fixed bins and moving oct volumes are prepared by two kernels
+// over 256-voxel chunks of all pairs, and the transforms are gathered into
+// one array for the MI reduction.
 #include "common.h"
 #include "sweep.h"
 

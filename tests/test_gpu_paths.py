@@ -9,7 +9,8 @@ them; Discussion: capture range).
   pass of the grid-stride loop.
 * maps.mi_map (batched mi_eval over a grid of one family) against the
   oracle's MI of the same matrices, within 1e-12 * max(1, |MI|), for every
-  family and entropy, across several batches.
+  family and entropy, across several batches; a Mattes-style map (Parzen
+  bins over a random subset of the voxels) within 1e-6.
 """
 import zlib
 
@@ -120,3 +121,22 @@ def test_mi_map_matches_oracle(ctx, family):
     nxt, _, _ = ctx.map_paths(torch.from_numpy(got[0]).cuda(), 1)
     ci = (3 * n + 3) * n + 3
     assert int(nxt.reshape(-1)[ci]) == ci
+
+
+def test_sampled_parzen_map_matches_oracle(ctx):
+    """A Mattes-style map (Parzen bins over a random 30% of the fixed voxels)
+    against the oracle's sampled Parzen MI of the same matrices."""
+    from paper_1909_10690_amd import binding as B
+    c = inputs.same_image((20, 18, 16), seed=6, dtype=np.uint8)
+    q = (1.0, 2.0)
+    n, ext = 5, 4.0
+    M = maps.map_transforms("translation", n, (20, 18, 16), ext)
+    fv = B.Volume.from_numpy(c["fixed"], *c["fixed_range"])
+    print("sampled Parzen map", flush=True)
+    got = maps.mi_map(ctx, fv, fv, "translation", n, ext, bins=32, q=q,
+                      flags=B.HIST_PARZEN | B.BOUNDARY_CLAMP, sample=(0.3, 44), batch=40).cpu().numpy()
+    ref, _ = oracle.eval_parzen(oracle.volume(c["fixed"], *c["fixed_range"]),
+                                oracle.volume(c["moving"], *c["moving_range"]), M, 32, q,
+                                boundary=oracle.CLAMP, sample=(0.3, 44))
+    ref = ref.T.reshape(len(q), n, n, n)
+    assert np.all(np.abs(got - ref) <= 1e-6 * np.abs(ref))
