@@ -123,17 +123,19 @@ def test_mi_map_matches_oracle(ctx, family):
     assert int(nxt.reshape(-1)[ci]) == ci
 
 
-def test_sampled_parzen_map_matches_oracle(ctx):
+@pytest.mark.parametrize("family,ext", [("translation", 4.0), ("rotation", 1.0)])
+def test_sampled_parzen_map_matches_oracle(ctx, family, ext):
     """A Mattes-style map (Parzen bins over a random 30% of the fixed voxels)
-    against the oracle's sampled Parzen MI of the same matrices."""
+    against the oracle's sampled Parzen MI of the same matrices; rotation
+    maps run in Z order and are put back in grid order."""
     from paper_1909_10690_amd import binding as B
     c = inputs.same_image((20, 18, 16), seed=6, dtype=np.uint8)
     q = (1.0, 2.0)
-    n, ext = 5, 4.0
-    M = maps.map_transforms("translation", n, (20, 18, 16), ext)
+    n = 5
+    M = maps.map_transforms(family, n, (20, 18, 16), ext)
     fv = B.Volume.from_numpy(c["fixed"], *c["fixed_range"])
-    print("sampled Parzen map", flush=True)
-    got = maps.mi_map(ctx, fv, fv, "translation", n, ext, bins=32, q=q,
+    print(f"sampled Parzen map family={family}", flush=True)
+    got = maps.mi_map(ctx, fv, fv, family, n, ext, bins=32, q=q,
                       flags=B.HIST_PARZEN | B.BOUNDARY_CLAMP, sample=(0.3, 44), batch=40).cpu().numpy()
     ref, _ = oracle.eval_parzen(oracle.volume(c["fixed"], *c["fixed_range"]),
                                 oracle.volume(c["moving"], *c["moving_range"]), M, 32, q,
