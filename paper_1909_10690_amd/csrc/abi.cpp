@@ -528,8 +528,10 @@ int plan_pairs(const mi_pair* pairs, int32_t n_pairs, int32_t bins, int32_t n_q,
     if (c < 8) c = 8;
     c = ((c + 7) / 8) * 8;
     plan.chunks[p] = (int32_t)c;
-    plan.fchunk_base[p + 1] = plan.fchunk_base[p] + ((int64_t)voxels(&pr.fixed) + kPrepChunk - 1) / kPrepChunk;
-    plan.mchunk_base[p + 1] = plan.mchunk_base[p] + ((int64_t)voxels(&pr.moving) + kPrepChunk - 1) / kPrepChunk;
+    plan.fchunk_base[p + 1] =
+        plan.fchunk_base[p] + ((int64_t)voxels(&pr.fixed) + kPrepFixedChunk - 1) / kPrepFixedChunk;
+    plan.mchunk_base[p + 1] =
+        plan.mchunk_base[p] + ((int64_t)voxels(&pr.moving) + kPrepMovingChunk - 1) / kPrepMovingChunk;
     plan.t_base[p + 1] = plan.t_base[p] + pr.n_transforms;
     for (int x = 0; x < 8; ++x)
       plan.xcd_base[(size_t)x * (P + 1) + p + 1] =

@@ -410,13 +410,16 @@ struct PairDesc {
   int32_t n_t, chunks;       // transforms, slabs (a multiple of 8)
 };
 
-constexpr int kPrepChunk = 256;  // voxels per wave in the pairs' preparation (4 per lane)
+// Pairs' preparation: one wave per chunk of consecutive voxels of a volume,
+// 16 fixed or 8 moving voxels per lane.
+constexpr int kPrepFixedLane = 16, kPrepFixedChunk = 64 * kPrepFixedLane;
+constexpr int kPrepMovingLane = 8, kPrepMovingChunk = 64 * kPrepMovingLane;
 
 struct PairsArgs {
   const PairDesc* pairs;
   int32_t n_pairs;
-  const int64_t* fchunk_base;  // [P+1] prefix of kPrepChunk-voxel chunks of the fixed volumes
-  const int64_t* mchunk_base;  // [P+1] the same for the moving volumes
+  const int64_t* fchunk_base;  // [P+1] prefix of kPrepFixedChunk-voxel chunks of the fixed volumes
+  const int64_t* mchunk_base;  // [P+1] prefix of kPrepMovingChunk-voxel chunks of the moving volumes
   const int64_t* t_base;     // [P+1] prefix of transforms
   const int64_t* xcd_base;   // [8][P+1] prefix of work items per XCD
   unsigned long long* counters;  // [8] work-queue heads

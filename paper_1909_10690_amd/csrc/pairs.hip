@@ -38,6 +38,7 @@ __device__ __forceinline__ int find_pair(const int64_t* __restrict__ base, int P
 typedef const __attribute__((address_space(1))) uint16_t global_u16;
 typedef const __attribute__((address_space(1))) int16_t global_i16;
 typedef const __attribute__((address_space(1))) uint32_t global_cu32;
+typedef const __attribute__((address_space(1))) uint4_t global_cu4;
 typedef const __attribute__((address_space(1))) float global_f32;
 typedef __attribute__((address_space(1))) uint8_t global_out8;
 typedef __attribute__((address_space(1))) uint32_t global_out32;
@@ -78,13 +79,16 @@ __device__ __forceinline__ T uniform(const T& v) {
   return r;
 }
 
-// Calls f(p, item, lane) for the items of the concatenated item space
-// [base[0], base[P]) that fall to this workgroup: a contiguous range per
-// workgroup, one wave per item.  The pair is found once per wave and then
-// advanced as the items ascend (a search per item would serialise dependent
-// loads on every item of small volumes).
+// Calls f(d, item, lane) for the items of the concatenated item space
+// [base[0], base[P]) that fall to this workgroup, d being the descriptor of
+// the item's pair and item its index within the pair: a contiguous range
+// per workgroup, one wave per item.  The pair is found once per wave and
+// then advanced as the items ascend; its bounds and descriptor are loaded
+// again only when it changes (they come through vector loads, so a load
+// per item would put two dependent round trips before every item's data).
 template <typename F>
-__device__ __forceinline__ void for_each_item(const int64_t* __restrict__ base, int P, int64_t items,
+__device__ __forceinline__ void for_each_item(const PairDesc* __restrict__ pairs,
+                                              const int64_t* __restrict__ base, int P, int64_t items,
                                               F&& f) {
   const int64_t per = (items + gridDim.x - 1) / gridDim.x;
   const int64_t r0 = (int64_t)blockIdx.x * per;
@@ -94,35 +98,54 @@ __device__ __forceinline__ void for_each_item(const int64_t* __restrict__ base, 
   const int lane = threadIdx.x & 63;
   if (r0 + wave >= r1) return;
   int p = uniform(find_pair(base, P, r0 + wave));
+  int64_t lo = uniform(base[p]), hi = uniform(base[p + 1]);
+  PairDesc d = uniform(pairs[p]);
   for (int64_t r = r0 + wave; r < r1; r += nw) {
-    while (r >= uniform(base[p + 1])) ++p;
-    f(p, r - uniform(base[p]), lane);
+    if (r >= hi) {
+      do {
+        ++p;
+        lo = hi;
+        hi = uniform(base[p + 1]);
+      } while (r >= hi);
+      d = uniform(pairs[p]);
+    }
+    f(d, r - lo, lane);
   }
 }
 
-// Fixed bins of every pair, one wave per chunk of kPrepChunk consecutive
-// voxels (four per lane) of a pair's fixed volume: every lane busy whatever
-// the row length.
+// Fixed bins of every pair, one wave per chunk of kPrepFixedChunk
+// consecutive voxels of a pair's fixed volume: every lane busy whatever the
+// row length.  Full chunks of a u8 volume are read and their bins written in
+// 16-byte accesses, 16 voxels per lane (with four bytes per lane the pass
+// waited on one short load per wave at a time); otherwise lane l takes
+// voxels l, l + 64, ..., so each access of the wave covers consecutive
+// voxels.
 __global__ void prep_fixed_kernel(PairsArgs a, int64_t chunks) {
-  for_each_item(a.fchunk_base, a.n_pairs, chunks, [&](int p, int64_t c, int lane) {
-    const PairDesc d = uniform(a.pairs[p]);
+  for_each_item(a.pairs, a.fchunk_base, a.n_pairs, chunks, [&](const PairDesc& d, int64_t c, int lane) {
     const int64_t nvox = (int64_t)d.geom.fnx * d.geom.fny * d.geom.fnz;
-    const int64_t v0 = c * kPrepChunk + 4 * lane;
-    if (v0 >= nvox) return;
+    const int64_t c0 = c * kPrepFixedChunk;
     global_out8* __restrict__ out = (global_out8*)d.geom.fbins;
-    if (d.fdtype == 0 && v0 + 4 <= nvox && ((uintptr_t)d.fixed & 3) == 0) {
-      // u8, 4-byte aligned volume: one 32-bit load and store for four voxels
-      // (the bins start 256-byte aligned and v0 is a multiple of 4)
-      const uint32_t w = *(global_cu32*)((global_u8*)d.fixed + v0);
-      uint32_t o = 0;
+    // the form is chosen for the whole chunk (a full chunk of an aligned u8
+    // volume, or not), so every voxel of it is written once
+    if (d.fdtype == 0 && c0 + kPrepFixedChunk <= nvox && (((uintptr_t)d.fixed | (uintptr_t)out) & 15) == 0) {
+      const int64_t v0 = c0 + kPrepFixedLane * lane;  // a multiple of 16: 16-byte aligned accesses
+      const uint4_t w = *(global_cu4*)((global_u8*)d.fixed + v0);
+      uint4_t o;
 #pragma unroll
-      for (int k = 0; k < 4; ++k)
-        o |= fixed_bin_int((int32_t)((w >> (8 * k)) & 0xFFu), (int32_t)d.flo, (int32_t)d.fhi,
-                           (uint32_t)d.geom.bins, d.fdiv) << (8 * k);
-      *(global_out32*)(out + v0) = o;
+      for (int j = 0; j < 4; ++j) {
+        uint32_t bj = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+          bj |= fixed_bin_int((int32_t)((w[j] >> (8 * k)) & 0xFFu), (int32_t)d.flo, (int32_t)d.fhi,
+                              (uint32_t)d.geom.bins, d.fdiv) << (8 * k);
+        o[j] = bj;
+      }
+      *(global_out4*)(out + v0) = o;
       return;
     }
-    for (int64_t v = v0; v < v0 + 4 && v < nvox; ++v) {
+    for (int k = 0; k < kPrepFixedLane; ++k) {
+      const int64_t v = c0 + lane + 64 * k;
+      if (v >= nvox) break;
       uint32_t b;
       if (d.fdtype == 3)
         b = fixed_bin_real((double)((global_f32*)d.fixed)[v], d.flo, d.fhi, d.geom.bins);
@@ -134,50 +157,92 @@ __global__ void prep_fixed_kernel(PairsArgs a, int64_t chunks) {
   });
 }
 
-// Moving oct volumes of every pair, one wave per chunk of kPrepChunk
-// consecutive voxels (four per lane), with the layout and clamping of the
-// single-pair path.
+// floor(n / d) and its remainder, for n < 2^32 and 0 < d < 2^31, with inv =
+// 1 / d in fp64 (to within an ulp or two): n inv is within a relative 2^-50
+// of n / d, so less than 1 / d away for n < 2^50, and its truncation is the
+// quotient, or one less when d divides n; one correction step settles that.
+// (Cheaper than the integer division sequence: the preparation issues two
+// per pair of voxels.)
+__device__ __forceinline__ uint32_t udiv_rcp(uint32_t n, uint32_t d, double inv, uint32_t& rem) {
+  uint32_t q = (uint32_t)((double)n * inv);
+  uint32_t r = n - q * d;
+  if (r >= d) {
+    ++q;
+    r -= d;
+  }
+  rem = r;
+  return q;
+}
+
+// Moving oct volumes of every pair, one wave per chunk of kPrepMovingChunk
+// consecutive voxels, with the layout and clamping of the single-pair path.
+// Lanes take neighbouring voxels (pairs of them for u8 rows of even length)
+// so that every store of the wave writes one contiguous run of entries.
 __global__ void prep_moving_kernel(PairsArgs a, int64_t chunks) {
-  for_each_item(a.mchunk_base, a.n_pairs, chunks, [&](int p, int64_t c, int lane) {
-    const PairDesc d = uniform(a.pairs[p]);
+  for_each_item(a.pairs, a.mchunk_base, a.n_pairs, chunks, [&](const PairDesc& d, int64_t c, int lane) {
     const int32_t nx = d.geom.mnx, ny = d.geom.mny, nz = d.geom.mnz;
     const uint32_t nvox = (uint32_t)nx * (uint32_t)ny * (uint32_t)nz;  // < 2^28
-    const uint32_t v0 = (uint32_t)(c * kPrepChunk) + 4u * (uint32_t)lane;
-    if (v0 >= nvox) return;
-    auto v = [&](size_t i) -> uint32_t { return clamp_offset(load_int(d.moving, d.mdtype, i), d.mlo, d.mhi); };
+    const uint32_t c0 = (uint32_t)(c * kPrepMovingChunk);
     const uint32_t plane = (uint32_t)nx * (uint32_t)ny;
-    if (d.geom.oct8 && d.mdtype == 0 && (nx & 3) == 0 && ((uintptr_t)d.moving & 3) == 0) {
-      // u8 rows of a multiple of 4 voxels, 4-byte aligned volume: the lane's
-      // four voxels share a row; each source row is read as one dword plus
-      // its next (clamped) byte
-      const uint32_t row = v0 / (uint32_t)nx, x0 = v0 - row * (uint32_t)nx;
-      const uint32_t z = row / (uint32_t)ny, y = row - z * (uint32_t)ny;
-      const size_t r00 = (size_t)row * nx;
-      const size_t r10 = r00 + (y + 1 < (uint32_t)ny ? nx : 0);
-      const size_t dz = z + 1 < (uint32_t)nz ? plane : 0;
+    if (d.geom.oct8 && d.mdtype == 0 && (nx & 1) == 0 && ((uintptr_t)d.moving & 1) == 0) {
+      // u8 rows of even length: lane l takes voxel pairs (v, v + 1), v = c0 +
+      // 2 l + 128 k, which lie in one row, and writes their two 8-byte
+      // entries with one 16-byte store (the wave's stores cover consecutive
+      // pairs).  Each of the pair's four source rows (y, y + 1 and the next
+      // slice's two, clamped at the far edges) gives a 2-byte load at x and
+      // the byte at x + 2 (clamped to the last column).  All loads of the
+      // lane are issued before its first store.
+      constexpr int S = kPrepMovingLane / 2;
+      const double inv_nx = 1.0 / nx, inv_ny = 1.0 / ny;
       global_u8* __restrict__ mv = (global_u8*)d.moving;
-      const size_t src[4] = {r00, r10, r00 + dz, r10 + dz};
-      const uint32_t xn = x0 + 4 < (uint32_t)nx ? x0 + 4 : (uint32_t)nx - 1;
-      uint32_t b[4][5];  // b[row][i] = clamped, offset value at x0 + i (i = 4: the neighbour)
+      uint32_t w[S][4], e[S][4];
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const uint32_t w = *(global_cu32*)(mv + src[r] + x0);
+      for (int k = 0; k < S; ++k) {
+        uint32_t v = c0 + 2u * (uint32_t)lane + 128u * (uint32_t)k;
+        v = v < nvox ? v : nvox - 2;  // nvox is even; past the end the pair is loaded, not stored
+        uint32_t x, y;
+        const uint32_t row = udiv_rcp(v, (uint32_t)nx, inv_nx, x);
+        const uint32_t z = udiv_rcp(row, (uint32_t)ny, inv_ny, y);
+        const size_t r00 = (size_t)row * nx;
+        const size_t r10 = r00 + (y + 1 < (uint32_t)ny ? nx : 0);
+        const size_t dz = z + 1 < (uint32_t)nz ? (size_t)plane : 0;
+        const size_t src[4] = {r00, r10, r00 + dz, r10 + dz};
+        const uint32_t xn = x + 2 < (uint32_t)nx ? x + 2 : (uint32_t)nx - 1;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) b[r][i] = clamp_offset((int32_t)((w >> (8 * i)) & 0xFFu), d.mlo, d.mhi);
-        b[r][4] = clamp_offset((int32_t)mv[src[r] + xn], d.mlo, d.mhi);
+        for (int r = 0; r < 4; ++r) {
+          w[k][r] = ((global_u16*)(mv + src[r] + x))[0];
+          e[k][r] = mv[src[r] + xn];
+        }
       }
-      uint32_t o[8];
+      // with 8-bit corners R <= 256, so the clamp is the identity exactly
+      // when the range is 0..255
+      const bool ident = d.mlo == 0 && d.mhi == 255;
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        o[2 * i] = b[0][i] | (b[0][i + 1] << 8) | (b[1][i] << 16) | (b[1][i + 1] << 24);
-        o[2 * i + 1] = b[2][i] | (b[2][i + 1] << 8) | (b[3][i] << 16) | (b[3][i + 1] << 24);
+      for (int k = 0; k < S; ++k) {
+        const uint32_t v = c0 + 2u * (uint32_t)lane + 128u * (uint32_t)k;
+        if (v >= nvox) break;
+        uint32_t cw[4], t[4];  // values at x, x + 1 (cw) and x + 1, x + 2 (t) in bytes 0, 1
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          uint32_t b0 = w[k][r] & 0xFFu, b1 = w[k][r] >> 8, b2 = e[k][r];
+          if (!ident) {
+            b0 = clamp_offset((int32_t)b0, d.mlo, d.mhi);
+            b1 = clamp_offset((int32_t)b1, d.mlo, d.mhi);
+            b2 = clamp_offset((int32_t)b2, d.mlo, d.mhi);
+          }
+          cw[r] = b0 | (b1 << 8);
+          t[r] = b1 | (b2 << 8);
+        }
+        // entries: byte 4 dz + 2 dy + dx' (layout of pack_oct8_kernel)
+        *(global_out4*)((global_out2*)d.geom.octs + v) =
+            uint4_t{cw[0] | (cw[1] << 16), cw[2] | (cw[3] << 16), t[0] | (t[1] << 16), t[2] | (t[3] << 16)};
       }
-      global_out4* __restrict__ out = (global_out4*)((global_out2*)d.geom.octs + v0);
-      out[0] = uint4_t{o[0], o[1], o[2], o[3]};
-      out[1] = uint4_t{o[4], o[5], o[6], o[7]};
       return;
     }
-    for (uint32_t vx = v0; vx < v0 + 4 && vx < nvox; ++vx) {
+    auto val = [&](size_t i) -> uint32_t { return clamp_offset(load_int(d.moving, d.mdtype, i), d.mlo, d.mhi); };
+    for (int k = 0; k < kPrepMovingLane; ++k) {
+      const uint32_t vx = c0 + (uint32_t)lane + 64u * (uint32_t)k;
+      if (vx >= nvox) break;
       const uint32_t row = vx / (uint32_t)nx, x = vx - row * (uint32_t)nx;
       const uint32_t z = row / (uint32_t)ny, y = row - z * (uint32_t)ny;
       const size_t r00 = (size_t)row * nx;
@@ -187,13 +252,14 @@ __global__ void prep_moving_kernel(PairsArgs a, int64_t chunks) {
       if (d.geom.oct8) {
         // 8-bit corners: byte 4 dz + 2 dy + dx' (layout of pack_oct8_kernel)
         ((global_out2*)d.geom.octs)[vx] =
-            uint2_t{v(r00 + x) | (v(r00 + x1) << 8) | (v(r10 + x) << 16) | (v(r10 + x1) << 24),
-                    v(r00 + dz + x) | (v(r00 + dz + x1) << 8) | (v(r10 + dz + x) << 16) |
-                        (v(r10 + dz + x1) << 24)};
+            uint2_t{val(r00 + x) | (val(r00 + x1) << 8) | (val(r10 + x) << 16) | (val(r10 + x1) << 24),
+                    val(r00 + dz + x) | (val(r00 + dz + x1) << 8) | (val(r10 + dz + x) << 16) |
+                        (val(r10 + dz + x1) << 24)};
       } else {
         ((global_out4*)d.geom.octs)[vx] =
-            uint4_t{v(r00 + x) | (v(r00 + x1) << 16), v(r10 + x) | (v(r10 + x1) << 16),
-                    v(r00 + dz + x) | (v(r00 + dz + x1) << 16), v(r10 + dz + x) | (v(r10 + dz + x1) << 16)};
+            uint4_t{val(r00 + x) | (val(r00 + x1) << 16), val(r10 + x) | (val(r10 + x1) << 16),
+                    val(r00 + dz + x) | (val(r00 + dz + x1) << 16),
+                    val(r10 + dz + x) | (val(r10 + dz + x1) << 16)};
       }
     }
   });

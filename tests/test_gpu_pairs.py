@@ -114,30 +114,35 @@ def test_uneven_pairs_full_size_sampled(ctx):
 
 
 def test_u8_pairs_vector_and_scalar_prep(ctx):
-    """All-u8 pairs (8-bit oct volumes for every pair): rows whose length is
-    a multiple of 4 take the four-voxels-per-lane prep, the others the
-    per-voxel prep; a volume starting one byte into its buffer (unaligned
-    for 32-bit loads) must take the per-voxel prep too."""
+    """All-u8 pairs (8-bit oct volumes for every pair) through every branch
+    of the preparation: moving rows whose length is a multiple of 8 take the
+    eight-voxel runs, multiples of 4 two four-voxel runs, the others the
+    per-voxel path; fixed volumes take 16-byte accesses except for a ragged
+    tail of fewer than 16 voxels.  Volumes that start 1, 4 or 8 bytes into
+    their device buffers must fall back to the narrower or per-voxel paths
+    with the same result."""
     import torch
     from paper_1909_10690_amd import binding as B
     rng = np.random.default_rng(31)
     pairs = []
-    for shape in [(64, 9, 7), (33, 12, 9), (40, 17, 6), (36, 24, 5), (17, 9, 8)]:
+    for shape in [(20, 9, 16), (13, 12, 24), (40, 17, 12), (36, 24, 5), (17, 9, 8), (11, 7, 9)]:
         f = inputs.random_volume(rng, shape, np.uint8, 0, 255)
         m = inputs.random_volume(rng, shape, np.uint8, 20, 230)
         mats = inputs.random_affines(rng, 3, shape, rot=15, trans=4)
         pairs.append(dict(fixed=f, moving=m, frange=(0, 255), mrange=(20, 230), transforms=mats))
     q = [1.0, 1.5]
     check(run_pairs(ctx, pairs, 48, q, 0), oracle_pairs(pairs, 48, q, 0))
-    # the first pair again, its volumes one byte into their device buffers
+    # the first pair again, its volumes `shift` bytes into their device buffers
     p = pairs[0]
-    fb = torch.empty(p["fixed"].size + 1, dtype=torch.uint8, device="cuda")
-    mb = torch.empty(p["moving"].size + 1, dtype=torch.uint8, device="cuda")
-    fb[1:].copy_(torch.from_numpy(p["fixed"].reshape(-1)))
-    mb[1:].copy_(torch.from_numpy(p["moving"].reshape(-1)))
-    nz, ny, nx = p["fixed"].shape
-    F = B.Volume(fb[1:].view(nz, ny, nx), 0, 255)
-    M = B.Volume(mb[1:].view(nz, ny, nx), 20, 230)
-    got = ctx.eval_pairs([(F, M, torch.from_numpy(p["transforms"]).cuda())], 48, q).cpu().numpy()
     ref = oracle_pairs([p], 48, q, 0)
-    check(got, ref)
+    nz, ny, nx = p["fixed"].shape
+    for shift in (1, 4, 8):
+        print(f"prep shift={shift}", flush=True)
+        fb = torch.empty(p["fixed"].size + shift, dtype=torch.uint8, device="cuda")
+        mb = torch.empty(p["moving"].size + shift, dtype=torch.uint8, device="cuda")
+        fb[shift:].copy_(torch.from_numpy(p["fixed"].reshape(-1)))
+        mb[shift:].copy_(torch.from_numpy(p["moving"].reshape(-1)))
+        F = B.Volume(fb[shift:].view(nz, ny, nx), 0, 255)
+        M = B.Volume(mb[shift:].view(nz, ny, nx), 20, 230)
+        got = ctx.eval_pairs([(F, M, torch.from_numpy(p["transforms"]).cuda())], 48, q).cpu().numpy()
+        check(got, ref)
