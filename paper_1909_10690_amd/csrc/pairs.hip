@@ -13,8 +13,9 @@
 // the loop once its queue is empty, so the grid always drains.
 //
 // Per-pair fixed bins and moving oct volumes are prepared by two kernels
-// over 256-voxel chunks of all pairs, and the transforms are gathered into
-// one array for the MI reduction.
+// over chunks of consecutive voxels of all pairs (1024 fixed or 512 moving
+// voxels per wave), and the transforms are gathered into one array for the
+// MI reduction.
 #include "common.h"
 #include "sweep.h"
 
