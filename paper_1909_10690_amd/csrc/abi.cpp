@@ -530,8 +530,9 @@ int plan_pairs(const mi_pair* pairs, int32_t n_pairs, int32_t bins, int32_t n_q,
     plan.chunks[p] = (int32_t)c;
     plan.fchunk_base[p + 1] =
         plan.fchunk_base[p] + ((int64_t)voxels(&pr.fixed) + kPrepFixedChunk - 1) / kPrepFixedChunk;
-    plan.mchunk_base[p + 1] =
-        plan.mchunk_base[p] + ((int64_t)voxels(&pr.moving) + kPrepMovingChunk - 1) / kPrepMovingChunk;
+    const int64_t mplane = (int64_t)pr.moving.nx * pr.moving.ny;
+    plan.mchunk_base[p + 1] = plan.mchunk_base[p] + (mplane + kPrepPlaneRun - 1) / kPrepPlaneRun *
+                                                        ((pr.moving.nz + kPrepSlices - 1) / kPrepSlices);
     plan.t_base[p + 1] = plan.t_base[p] + pr.n_transforms;
     for (int x = 0; x < 8; ++x)
       plan.xcd_base[(size_t)x * (P + 1) + p + 1] =

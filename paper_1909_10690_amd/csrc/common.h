@@ -410,16 +410,17 @@ struct PairDesc {
   int32_t n_t, chunks;       // transforms, slabs (a multiple of 8)
 };
 
-// Pairs' preparation: one wave per chunk of consecutive voxels of a volume,
-// 16 fixed or 8 moving voxels per lane.
+// Pairs' preparation, one wave per item: fixed volumes in chunks of
+// consecutive voxels (16 per lane); moving volumes in runs of kPrepPlaneRun
+// voxels of an xy plane (two per lane) through blocks of kPrepSlices slices.
 constexpr int kPrepFixedLane = 16, kPrepFixedChunk = 64 * kPrepFixedLane;
-constexpr int kPrepMovingLane = 8, kPrepMovingChunk = 64 * kPrepMovingLane;
+constexpr int kPrepPlaneRun = 128, kPrepSlices = 8;
 
 struct PairsArgs {
   const PairDesc* pairs;
   int32_t n_pairs;
   const int64_t* fchunk_base;  // [P+1] prefix of kPrepFixedChunk-voxel chunks of the fixed volumes
-  const int64_t* mchunk_base;  // [P+1] prefix of kPrepMovingChunk-voxel chunks of the moving volumes
+  const int64_t* mchunk_base;  // [P+1] prefix of (plane run, slice block) items of the moving volumes
   const int64_t* t_base;     // [P+1] prefix of transforms
   const int64_t* xcd_base;   // [8][P+1] prefix of work items per XCD
   unsigned long long* counters;  // [8] work-queue heads

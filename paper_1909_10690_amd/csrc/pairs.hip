@@ -158,109 +158,96 @@ __global__ void prep_fixed_kernel(PairsArgs a, int64_t chunks) {
   });
 }
 
-// floor(n / d) and its remainder, for n < 2^32 and 0 < d < 2^31, with inv =
-// 1 / d in fp64 (to within an ulp or two): n inv is within a relative 2^-50
-// of n / d, so less than 1 / d away for n < 2^50, and its truncation is the
-// quotient, or one less when d divides n; one correction step settles that.
-// (Cheaper than the integer division sequence: the preparation issues two
-// per pair of voxels.)
-__device__ __forceinline__ uint32_t udiv_rcp(uint32_t n, uint32_t d, double inv, uint32_t& rem) {
-  uint32_t q = (uint32_t)((double)n * inv);
-  uint32_t r = n - q * d;
-  if (r >= d) {
-    ++q;
-    r -= d;
-  }
-  rem = r;
-  return q;
-}
-
-// Moving oct volumes of every pair, one wave per chunk of kPrepMovingChunk
-// consecutive voxels, with the layout and clamping of the single-pair path.
-// Lanes take neighbouring voxels (pairs of them for u8 rows of even length)
-// so that every store of the wave writes one contiguous run of entries.
-__global__ void prep_moving_kernel(PairsArgs a, int64_t chunks) {
-  for_each_item(a.pairs, a.mchunk_base, a.n_pairs, chunks, [&](const PairDesc& d, int64_t c, int lane) {
-    const int32_t nx = d.geom.mnx, ny = d.geom.mny, nz = d.geom.mnz;
-    const uint32_t nvox = (uint32_t)nx * (uint32_t)ny * (uint32_t)nz;  // < 2^28
-    const uint32_t c0 = (uint32_t)(c * kPrepMovingChunk);
-    const uint32_t plane = (uint32_t)nx * (uint32_t)ny;
+// Moving oct volumes of every pair, with the layout and clamping of the
+// single-pair path.  An item is a run of kPrepPlaneRun voxels of an xy
+// plane through a block of kPrepSlices consecutive slices: lane l takes
+// plane voxels 2l and 2l + 1 of the run at every slice of the block.  The
+// lane loads the source rows y and y + 1 of each slice of the block and of
+// the one after it once, all before its first store, and the entries of
+// slice z take slice z + 1's rows from registers; so a source row is
+// fetched once per block instead of once for its own slice and again for
+// the slice below (with flat chunks the moving preparation fetched 2.5x
+// its source volume).  Each 16-byte store of the wave covers consecutive
+// entries.
+__global__ void prep_moving_kernel(PairsArgs a, int64_t items) {
+  for_each_item(a.pairs, a.mchunk_base, a.n_pairs, items, [&](const PairDesc& d, int64_t c, int lane) {
+    const uint32_t nx = (uint32_t)d.geom.mnx, ny = (uint32_t)d.geom.mny, nz = (uint32_t)d.geom.mnz;
+    const uint32_t plane = nx * ny;  // nvox < 2^28
+    const uint32_t runs = (plane + kPrepPlaneRun - 1) / kPrepPlaneRun;
+    const uint32_t zb = (uint32_t)c / runs, run = (uint32_t)c - zb * runs;
+    const uint32_t z0 = zb * kPrepSlices;
+    const uint32_t nzb = nz - z0 < (uint32_t)kPrepSlices ? nz - z0 : (uint32_t)kPrepSlices;  // slices in the block
+    const uint32_t vp = run * kPrepPlaneRun + 2u * (uint32_t)lane;  // plane index of the lane's first voxel
+    if (vp >= plane) return;
     if (d.geom.oct8 && d.mdtype == 0 && (nx & 1) == 0 && ((uintptr_t)d.moving & 1) == 0) {
-      // u8 rows of even length: lane l takes voxel pairs (v, v + 1), v = c0 +
-      // 2 l + 128 k, which lie in one row, and writes their two 8-byte
-      // entries with one 16-byte store (the wave's stores cover consecutive
-      // pairs).  Each of the pair's four source rows (y, y + 1 and the next
-      // slice's two, clamped at the far edges) gives a 2-byte load at x and
-      // the byte at x + 2 (clamped to the last column).  All loads of the
-      // lane are issued before its first store.
-      constexpr int S = kPrepMovingLane / 2;
-      const double inv_nx = 1.0 / nx, inv_ny = 1.0 / ny;
+      // u8 rows of even length: the lane's two voxels (vp even) lie in one
+      // row.  Per slice and source row (y, y + 1 clamped): a 2-byte load at
+      // x and the byte at x + 2 (clamped to the last column).
+      const uint32_t y = vp / nx, x = vp - y * nx;
+      const size_t ry0 = vp, ry1 = y + 1 < ny ? (size_t)vp + nx : (size_t)vp;
+      const uint32_t xn = x + 2 < nx ? 2u : nx - 1u - x;  // offset of the byte after the pair
       global_u8* __restrict__ mv = (global_u8*)d.moving;
-      uint32_t w[S][4], e[S][4];
+      uint32_t w[kPrepSlices + 1][2], e[kPrepSlices + 1][2];
 #pragma unroll
-      for (int k = 0; k < S; ++k) {
-        uint32_t v = c0 + 2u * (uint32_t)lane + 128u * (uint32_t)k;
-        v = v < nvox ? v : nvox - 2;  // nvox is even; past the end the pair is loaded, not stored
-        uint32_t x, y;
-        const uint32_t row = udiv_rcp(v, (uint32_t)nx, inv_nx, x);
-        const uint32_t z = udiv_rcp(row, (uint32_t)ny, inv_ny, y);
-        const size_t r00 = (size_t)row * nx;
-        const size_t r10 = r00 + (y + 1 < (uint32_t)ny ? nx : 0);
-        const size_t dz = z + 1 < (uint32_t)nz ? (size_t)plane : 0;
-        const size_t src[4] = {r00, r10, r00 + dz, r10 + dz};
-        const uint32_t xn = x + 2 < (uint32_t)nx ? x + 2 : (uint32_t)nx - 1;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          w[k][r] = ((global_u16*)(mv + src[r] + x))[0];
-          e[k][r] = mv[src[r] + xn];
-        }
+      for (int k = 0; k <= kPrepSlices; ++k) {
+        uint32_t z = z0 + (uint32_t)k;
+        z = z < nz ? z : nz - 1;  // slice z0 + nzb is the block's last slice + 1, clamped
+        if ((uint32_t)k > nzb) z = z0;  // past the block: a valid slice, not used
+        const size_t sz = (size_t)z * plane;
+        w[k][0] = ((global_u16*)(mv + sz + ry0))[0];
+        e[k][0] = mv[sz + ry0 + xn];
+        w[k][1] = ((global_u16*)(mv + sz + ry1))[0];
+        e[k][1] = mv[sz + ry1 + xn];
       }
       // with 8-bit corners R <= 256, so the clamp is the identity exactly
       // when the range is 0..255
       const bool ident = d.mlo == 0 && d.mhi == 255;
+      uint32_t cw[kPrepSlices + 1][2], t[kPrepSlices + 1][2];  // (x, x+1) and (x+1, x+2) in bytes 0, 1
 #pragma unroll
-      for (int k = 0; k < S; ++k) {
-        const uint32_t v = c0 + 2u * (uint32_t)lane + 128u * (uint32_t)k;
-        if (v >= nvox) break;
-        uint32_t cw[4], t[4];  // values at x, x + 1 (cw) and x + 1, x + 2 (t) in bytes 0, 1
+      for (int k = 0; k <= kPrepSlices; ++k)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
+        for (int r = 0; r < 2; ++r) {
           uint32_t b0 = w[k][r] & 0xFFu, b1 = w[k][r] >> 8, b2 = e[k][r];
           if (!ident) {
             b0 = clamp_offset((int32_t)b0, d.mlo, d.mhi);
             b1 = clamp_offset((int32_t)b1, d.mlo, d.mhi);
             b2 = clamp_offset((int32_t)b2, d.mlo, d.mhi);
           }
-          cw[r] = b0 | (b1 << 8);
-          t[r] = b1 | (b2 << 8);
+          cw[k][r] = b0 | (b1 << 8);
+          t[k][r] = b1 | (b2 << 8);
         }
+#pragma unroll
+      for (int k = 0; k < kPrepSlices; ++k) {
+        if ((uint32_t)k >= nzb) break;
         // entries: byte 4 dz + 2 dy + dx' (layout of pack_oct8_kernel)
-        *(global_out4*)((global_out2*)d.geom.octs + v) =
-            uint4_t{cw[0] | (cw[1] << 16), cw[2] | (cw[3] << 16), t[0] | (t[1] << 16), t[2] | (t[3] << 16)};
+        *(global_out4*)((global_out2*)d.geom.octs + (size_t)(z0 + k) * plane + vp) =
+            uint4_t{cw[k][0] | (cw[k][1] << 16), cw[k + 1][0] | (cw[k + 1][1] << 16),
+                    t[k][0] | (t[k][1] << 16), t[k + 1][0] | (t[k + 1][1] << 16)};
       }
       return;
     }
     auto val = [&](size_t i) -> uint32_t { return clamp_offset(load_int(d.moving, d.mdtype, i), d.mlo, d.mhi); };
-    for (int k = 0; k < kPrepMovingLane; ++k) {
-      const uint32_t vx = c0 + (uint32_t)lane + 64u * (uint32_t)k;
-      if (vx >= nvox) break;
-      const uint32_t row = vx / (uint32_t)nx, x = vx - row * (uint32_t)nx;
-      const uint32_t z = row / (uint32_t)ny, y = row - z * (uint32_t)ny;
-      const size_t r00 = (size_t)row * nx;
-      const size_t r10 = r00 + (y + 1 < (uint32_t)ny ? nx : 0);
-      const size_t dz = z + 1 < (uint32_t)nz ? plane : 0;
-      const uint32_t x1 = x + 1 < (uint32_t)nx ? x + 1 : (uint32_t)nx - 1;
-      if (d.geom.oct8) {
-        // 8-bit corners: byte 4 dz + 2 dy + dx' (layout of pack_oct8_kernel)
-        ((global_out2*)d.geom.octs)[vx] =
-            uint2_t{val(r00 + x) | (val(r00 + x1) << 8) | (val(r10 + x) << 16) | (val(r10 + x1) << 24),
-                    val(r00 + dz + x) | (val(r00 + dz + x1) << 8) | (val(r10 + dz + x) << 16) |
-                        (val(r10 + dz + x1) << 24)};
-      } else {
-        ((global_out4*)d.geom.octs)[vx] =
-            uint4_t{val(r00 + x) | (val(r00 + x1) << 16), val(r10 + x) | (val(r10 + x1) << 16),
-                    val(r00 + dz + x) | (val(r00 + dz + x1) << 16),
-                    val(r10 + dz + x) | (val(r10 + dz + x1) << 16)};
+    for (uint32_t j = 0; j < 2; ++j) {
+      const uint32_t v = vp + j;
+      if (v >= plane) break;
+      const uint32_t y = v / nx, x = v - y * nx;
+      const size_t row0 = (size_t)v - x, row1 = y + 1 < ny ? row0 + nx : row0;  // rows y, y + 1 (clamped)
+      const uint32_t x1 = x + 1 < nx ? x + 1 : nx - 1;
+      for (uint32_t k = 0; k < nzb; ++k) {
+        const uint32_t z = z0 + k;
+        const size_t s0 = (size_t)z * plane, s1 = z + 1 < nz ? s0 + plane : s0;  // slices z, z + 1 (clamped)
+        const size_t a0 = s0 + row0, a1 = s0 + row1, b0 = s1 + row0, b1 = s1 + row1;
+        const size_t out = s0 + v;
+        if (d.geom.oct8) {
+          // 8-bit corners: byte 4 dz + 2 dy + dx' (layout of pack_oct8_kernel)
+          ((global_out2*)d.geom.octs)[out] =
+              uint2_t{val(a0 + x) | (val(a0 + x1) << 8) | (val(a1 + x) << 16) | (val(a1 + x1) << 24),
+                      val(b0 + x) | (val(b0 + x1) << 8) | (val(b1 + x) << 16) | (val(b1 + x1) << 24)};
+        } else {
+          ((global_out4*)d.geom.octs)[out] =
+              uint4_t{val(a0 + x) | (val(a0 + x1) << 16), val(a1 + x) | (val(a1 + x1) << 16),
+                      val(b0 + x) | (val(b0 + x1) << 16), val(b1 + x) | (val(b1 + x1) << 16)};
+        }
       }
     }
   });

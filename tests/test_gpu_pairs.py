@@ -115,12 +115,13 @@ def test_uneven_pairs_full_size_sampled(ctx):
 
 def test_u8_pairs_vector_and_scalar_prep(ctx):
     """All-u8 pairs (8-bit oct volumes for every pair) through every branch
-    of the preparation: moving rows whose length is a multiple of 8 take the
-    eight-voxel runs, multiples of 4 two four-voxel runs, the others the
-    per-voxel path; fixed volumes take 16-byte accesses except for a ragged
-    tail of fewer than 16 voxels.  Volumes that start 1, 4 or 8 bytes into
-    their device buffers must fall back to the narrower or per-voxel paths
-    with the same result."""
+    of the preparation: moving rows of even length take the two-voxels-per-
+    lane path, odd lengths the per-voxel path, with ragged plane runs and
+    slice blocks (depths not a multiple of 8); fixed volumes take 16-byte
+    accesses except in a ragged last chunk.  Volumes that start 1, 4 or 8
+    bytes into their device buffers (1: odd addresses, per-voxel moving path;
+    4 and 8: not 16-byte aligned, per-voxel fixed path) give the same
+    result."""
     import torch
     from paper_1909_10690_amd import binding as B
     rng = np.random.default_rng(31)
