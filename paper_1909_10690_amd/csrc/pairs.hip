@@ -263,18 +263,35 @@ __global__ __launch_bounds__(NT) void hist_pairs_kernel(PairsArgs a) {
   const uint32_t xcd = blockIdx.x & 7u;
   const int64_t* __restrict__ xbase = a.xcd_base + (int64_t)xcd * (a.n_pairs + 1);
   const int64_t total = xbase[a.n_pairs];
+  // The items a workgroup takes from its queue ascend, so its pair only
+  // moves forward: the pair's bounds, geometry and counts are loaded again
+  // only when an item falls past it (a search per item put about log2 P
+  // dependent loads before every slab's sweep).
+  int p = -1;
+  int64_t p_lo = 0, p_hi = 0;  // xbase[p], xbase[p + 1]; xbase[0] = 0
+  HardGeom geom;
+  int32_t n_t = 0, chunks = 0;
+  int64_t t0 = 0;
   for (;;) {
     if (threadIdx.x == 0) item_sh = (int64_t)atomicAdd(&a.counters[xcd], 1ull);
     __syncthreads();
     const int64_t item = uniform(item_sh);
     if (item >= total) break;  // the same for every thread of the workgroup
-    const int p = find_pair(xbase, a.n_pairs, item);
-    const HardGeom geom = uniform(a.pairs[p].geom);
-    const int32_t n_t = uniform(a.pairs[p].n_t), chunks = uniform(a.pairs[p].chunks);
-    const int64_t rem = item - xbase[p];
+    if (item >= p_hi) {
+      do {  // item < total = xbase[P] bounds p + 1 <= P
+        ++p;
+        p_lo = p_hi;
+        p_hi = uniform(xbase[p + 1]);
+      } while (item >= p_hi);
+      geom = uniform(a.pairs[p].geom);
+      n_t = uniform(a.pairs[p].n_t);
+      chunks = uniform(a.pairs[p].chunks);
+      t0 = uniform(a.t_base[p]);
+    }
+    const int64_t rem = item - p_lo;
     const int64_t slab = rem / n_t, tl = rem - slab * n_t;
     const uint32_t chunk = xcd * (uint32_t)(chunks >> 3) + (uint32_t)slab;
-    const int64_t t = uniform(a.t_base[p]) + tl;
+    const int64_t t = t0 + tl;
     int64_t Mq[12];
     const bool ok = quantize_transform(a.transforms + 12 * t, Mq);
     if (ok) sweep_hard<CLAMP, PACKED, OCT8, NT / 64>(geom, Mq, chunks, chunk, lds_hist);
