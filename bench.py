@@ -294,8 +294,8 @@ def main() -> int:
                          "kernel for scaling HBM byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (asked for {args.gpus}); the metric path has no "
-              f"multi-GPU leg in this build", file=sys.stderr)
+        print(f"bench.py measures one GPU only (asked for {args.gpus}); the library runs the "
+              f"metric path on a single GPU and has no multi-GPU leg", file=sys.stderr)
         return 2
 
     import torch

@@ -80,7 +80,7 @@ extern "C" {
                                    integral, |lo|,|hi| > 2^31, or hi - lo + 1 > 65536 */
 #define MI_ERR_Q (-6)           /* n_q outside [1, 16], or a q not finite or <= 0 */
 #define MI_ERR_WORKSPACE (-7)   /* workspace NULL or smaller than mi_workspace_size() */
-#define MI_ERR_UNSUPPORTED (-8) /* a valid request this build does not serve */
+#define MI_ERR_UNSUPPORTED (-8) /* a valid request the library does not serve */
 #define MI_ERR_FLAGS (-9)       /* unknown flag bits */
 #define MI_ERR_COUNT (-10)      /* n_transforms (or n_pairs) negative or above 2^24 */
 #define MI_ERR_SAMPLE (-11)     /* sampling fraction not finite or not above 0 */
