@@ -13,9 +13,9 @@
 // the loop once its queue is empty, so the grid always drains.
 //
 // Per-pair fixed bins and moving oct volumes are prepared by two kernels
-// over chunks of consecutive voxels of all pairs (1024 fixed or 512 moving
-// voxels per wave), and the transforms are gathered into one array for the
-// MI reduction.
+// over the items of all pairs (runs of 1024 consecutive fixed voxels; runs
+// of 128 voxels of a moving xy plane through 8 slices), one wave per item,
+// and the transforms are gathered into one array for the MI reduction.
 #include "common.h"
 #include "sweep.h"
 
