@@ -79,6 +79,25 @@ def test_mixed_pairs(ctx, bins, flags):
     check(run_pairs(ctx, pairs, bins, q, flags), oracle_pairs(pairs, bins, q, flags))
 
 
+def test_runs_of_pairs_without_transforms(ctx):
+    """Pairs with no transforms have no work items: a workgroup's queue moves
+    past runs of them (the first pair, three in a row, the last) to the next
+    pair that has items."""
+    rng = np.random.default_rng(41)
+    pairs = []
+    for i in range(8):
+        shape = tuple(int(e) for e in rng.choice([12, 17, 24], 3))
+        f = inputs.random_volume(rng, shape, np.uint8, 0, 255)
+        m = inputs.random_volume(rng, shape, np.uint8, 0, 255)
+        nt = 0 if i in (0, 2, 3, 4, 7) else 3
+        mats = inputs.random_affines(rng, nt, shape, rot=10, trans=3)
+        pairs.append(dict(fixed=f, moving=m, frange=(0, 255), mrange=(0, 255), transforms=mats))
+    q = [1.0, 2.0]
+    got = run_pairs(ctx, pairs, 32, q, 0)
+    assert got.shape == (9, 2)
+    check(got, oracle_pairs(pairs, 32, q, 0))
+
+
 def test_pairs_equal_single_pair_calls(ctx):
     """One persistent launch over many pairs gives exactly what mi_eval gives
     pair by pair."""
