@@ -185,9 +185,12 @@ struct GroupWalkBrick {
     const int64_t s0 = groups * chunk / chunks, s1 = groups * (chunk + 1) / chunks;
     g = s0 + (s1 - s0) * wave / nwaves;
     g1 = s0 + (s1 - s0) * (wave + 1) / nwaves;
-    // 4 yb rows ~ slices per slab = per_slab / yb
+    // bricks of 4 yb rows by per_slab / yb slices, twice as many rows as
+    // slices (yb = sqrt(per_slab / 2)): on a 51^3 rotation map of a
+    // 256x256x180 volume 4.61 s, against 5.53 s for square bricks and
+    // 5.3-6.1 s for other widths
     const int64_t per_slab = (groups + chunks - 1) / chunks;
-    const int32_t w = (int32_t)sqrt((double)per_slab / kTileY);
+    const int32_t w = (int32_t)sqrt((double)per_slab * 0.5);
     yb = w < 1 ? 1 : (w > G ? G : w);
     const int64_t full = G / yb, per_full = (int64_t)yb * fnz;
     b0 = 0;
