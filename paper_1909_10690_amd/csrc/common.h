@@ -278,6 +278,16 @@ struct HardLaunch {
   int32_t brick;       // 1: slabs as bricks (GroupWalkBrick; 1024-thread launches)
 };
 
+// A dispatch counts its work-items in 32 bits: a grid of n x (workgroups
+// per transform) x threads beyond that wraps without an error and leaves
+// transforms unevaluated.  Batches larger than this many transforms go out
+// as several launches of whole transforms (below 2^31 work-items each).
+inline int32_t transforms_per_launch(int64_t workgroups_per_transform, int32_t threads) {
+  const int64_t per = workgroups_per_transform * threads;
+  const int64_t m = per > 0 ? (int64_t)0x7FFFFFFF / per : 1;
+  return (int32_t)(m < 1 ? 1 : (m > 0x7FFFFFFF ? 0x7FFFFFFF : m));
+}
+
 // The gathers address their volume with 32-bit buffer offsets, so every
 // gather volume stays below 4 GiB (the entry points check it).
 constexpr size_t kMaxGatherBytes = 0xFFFFFFF0u;

@@ -335,14 +335,24 @@ hipError_t launch_hist_hard(const HardLaunch& L, hipStream_t s) {
   a.slab_major = L.slab_major;
   const size_t lds = L.packed ? (((size_t)L.bins * L.bins + 1) / 2) * 4 : (size_t)L.bins * L.bins * 4;
   if (lds > kHardLdsMax) return hipErrorInvalidValue;  // above the limit the kernels are configured for
-  switch (L.block) {
-  case 256: return launch_nt<256>(a, L.n, L.clamp, L.packed, lds, s);
-  case 512: return launch_nt<512>(a, L.n, L.clamp, L.packed, lds, s);
-  case 1024:  // bricks only with the default 1024-thread shape
-    return L.brick ? launch_nt<1024, true>(a, L.n, L.clamp, L.packed, lds, s)
-                   : launch_nt<1024>(a, L.n, L.clamp, L.packed, lds, s);
-  default: return hipErrorInvalidValue;
+  if (L.block != 256 && L.block != 512 && L.block != 1024) return hipErrorInvalidValue;
+  const int32_t step = transforms_per_launch(L.chunks, L.block);
+  for (int32_t t0 = 0; t0 < L.n; t0 += step) {
+    HardArgs b = a;
+    b.n = L.n - t0 < step ? L.n - t0 : step;
+    b.transforms = a.transforms + 12 * (size_t)t0;
+    b.hist = a.hist + (size_t)t0 * L.bins * L.bins;
+    hipError_t e;
+    switch (L.block) {
+    case 256: e = launch_nt<256>(b, b.n, L.clamp, L.packed, lds, s); break;
+    case 512: e = launch_nt<512>(b, b.n, L.clamp, L.packed, lds, s); break;
+    default:  // 1024; bricks only with the default 1024-thread shape
+      e = L.brick ? launch_nt<1024, true>(b, b.n, L.clamp, L.packed, lds, s)
+                  : launch_nt<1024>(b, b.n, L.clamp, L.packed, lds, s);
+    }
+    if (e != hipSuccess) return e;
   }
+  return hipSuccess;
 }
 
 hipError_t launch_hist_sampled(const HardLaunch& L, const uint2* list, const unsigned long long* n_list,
@@ -358,16 +368,28 @@ hipError_t launch_hist_sampled(const HardLaunch& L, const uint2* list, const uns
   const size_t lds = L.packed ? (((size_t)L.bins * L.bins + 1) / 2) * 4 : (size_t)L.bins * L.bins * 4;
   if (lds > kHardLdsMax) return hipErrorInvalidValue;  // above the limit the kernels are configured for
   const bool o8 = a.geom.oct8 != 0;
-  if (L.clamp) {
-    if (L.packed) return o8 ? launch_sampled_variant<true, true, true>(a, list, n_list, lds, s)
-                            : launch_sampled_variant<true, true, false>(a, list, n_list, lds, s);
-    return o8 ? launch_sampled_variant<true, false, true>(a, list, n_list, lds, s)
-              : launch_sampled_variant<true, false, false>(a, list, n_list, lds, s);
+  auto one = [&](const HardArgs& b) -> hipError_t {
+    if (L.clamp) {
+      if (L.packed) return o8 ? launch_sampled_variant<true, true, true>(b, list, n_list, lds, s)
+                              : launch_sampled_variant<true, true, false>(b, list, n_list, lds, s);
+      return o8 ? launch_sampled_variant<true, false, true>(b, list, n_list, lds, s)
+                : launch_sampled_variant<true, false, false>(b, list, n_list, lds, s);
+    }
+    if (L.packed) return o8 ? launch_sampled_variant<false, true, true>(b, list, n_list, lds, s)
+                            : launch_sampled_variant<false, true, false>(b, list, n_list, lds, s);
+    return o8 ? launch_sampled_variant<false, false, true>(b, list, n_list, lds, s)
+              : launch_sampled_variant<false, false, false>(b, list, n_list, lds, s);
+  };
+  const int32_t step = transforms_per_launch(L.chunks, kSampledBlock);
+  for (int32_t t0 = 0; t0 < L.n; t0 += step) {
+    HardArgs b = a;
+    b.n = L.n - t0 < step ? L.n - t0 : step;
+    b.transforms = a.transforms + 12 * (size_t)t0;
+    b.hist = a.hist + (size_t)t0 * L.bins * L.bins;
+    const hipError_t e = one(b);
+    if (e != hipSuccess) return e;
   }
-  if (L.packed) return o8 ? launch_sampled_variant<false, true, true>(a, list, n_list, lds, s)
-                          : launch_sampled_variant<false, true, false>(a, list, n_list, lds, s);
-  return o8 ? launch_sampled_variant<false, false, true>(a, list, n_list, lds, s)
-            : launch_sampled_variant<false, false, false>(a, list, n_list, lds, s);
+  return hipSuccess;
 }
 
 template <int NT, bool BRICK = false>

@@ -664,13 +664,39 @@ static hipError_t fwd_variant(const ParzenArgs& a, size_t lds, hipStream_t s) {
   return hipGetLastError();
 }
 
+// The arguments of transforms [t0, t0 + n) of a batch: every per-transform
+// array advanced to t0 (launches of whole transforms, transforms_per_launch).
+static ParzenArgs sub_batch(const ParzenArgs& a, int32_t t0, int32_t n) {
+  ParzenArgs b = a;
+  const size_t BB = (size_t)a.bins * a.bins;
+  b.n = n;
+  b.transforms = a.transforms + 12 * (size_t)t0;
+  if (a.table) b.table = a.table + (size_t)t0 * BB;
+  if (a.count) b.count = a.count + t0;
+  if (a.gtab) b.gtab = a.gtab + (size_t)t0 * a.n_q * BB;
+  if (a.marg) b.marg = a.marg + (size_t)t0 * 2 * a.bins;
+  if (a.grad) b.grad = a.grad + (size_t)t0 * a.n_q * 12;
+  return b;
+}
+
+template <typename F>
+static hipError_t in_launches(const ParzenArgs& a, F&& launch) {
+  const int32_t step = transforms_per_launch((int64_t)a.chunks * a.bands, 512);
+  for (int32_t t0 = 0; t0 < a.n; t0 += step) {
+    const hipError_t e = launch(sub_batch(a, t0, a.n - t0 < step ? a.n - t0 : step));
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 hipError_t launch_parzen_fwd(const ParzenLaunch& L, hipStream_t s) {
-  ParzenArgs a = L.args;
-  const size_t lds = (size_t)(a.band_rows + kHotCopies - 1) * a.bins * 8;
+  const size_t lds = (size_t)(L.args.band_rows + kHotCopies - 1) * L.args.bins * 8;
   if (lds > kParzenLdsMax) return hipErrorInvalidValue;  // bands are sized to fit
-  if (L.float_quads)
-    return L.clamp ? fwd_variant<true, true>(a, lds, s) : fwd_variant<true, false>(a, lds, s);
-  return L.clamp ? fwd_variant<false, true>(a, lds, s) : fwd_variant<false, false>(a, lds, s);
+  return in_launches(L.args, [&](const ParzenArgs& a) {
+    if (L.float_quads)
+      return L.clamp ? fwd_variant<true, true>(a, lds, s) : fwd_variant<true, false>(a, lds, s);
+    return L.clamp ? fwd_variant<false, true>(a, lds, s) : fwd_variant<false, false>(a, lds, s);
+  });
 }
 
 template <bool FQ, bool CLAMP>
@@ -683,14 +709,15 @@ static hipError_t sampled_fwd_variant(const ParzenArgs& a, const uint2* list, co
 
 hipError_t launch_parzen_sampled_fwd(const ParzenLaunch& L, const uint2* list, const unsigned long long* n_list,
                                      hipStream_t s) {
-  ParzenArgs a = L.args;
-  const size_t lds = (size_t)(a.band_rows + kHotCopies - 1) * a.bins * 8;
+  const size_t lds = (size_t)(L.args.band_rows + kHotCopies - 1) * L.args.bins * 8;
   if (lds > kParzenLdsMax) return hipErrorInvalidValue;  // bands are sized to fit
-  if (L.float_quads)
-    return L.clamp ? sampled_fwd_variant<true, true>(a, list, n_list, lds, s)
-                   : sampled_fwd_variant<true, false>(a, list, n_list, lds, s);
-  return L.clamp ? sampled_fwd_variant<false, true>(a, list, n_list, lds, s)
-                 : sampled_fwd_variant<false, false>(a, list, n_list, lds, s);
+  return in_launches(L.args, [&](const ParzenArgs& a) {
+    if (L.float_quads)
+      return L.clamp ? sampled_fwd_variant<true, true>(a, list, n_list, lds, s)
+                     : sampled_fwd_variant<true, false>(a, list, n_list, lds, s);
+    return L.clamp ? sampled_fwd_variant<false, true>(a, list, n_list, lds, s)
+                   : sampled_fwd_variant<false, false>(a, list, n_list, lds, s);
+  });
 }
 
 hipError_t launch_dmi_dp(const ParzenLaunch& L, const QList& q, hipStream_t s) {
@@ -707,12 +734,13 @@ static hipError_t bwd_variant(const ParzenArgs& a, size_t lds, hipStream_t s) {
 }
 
 hipError_t launch_parzen_bwd(const ParzenLaunch& L, hipStream_t s) {
-  ParzenArgs a = L.args;
-  const size_t lds = (size_t)kParzenQGroup * a.band_rows * a.bins * 4;
+  const size_t lds = (size_t)kParzenQGroup * L.args.band_rows * L.args.bins * 4;
   if (lds > kParzenLdsMax) return hipErrorInvalidValue;  // bands are sized to fit
-  if (L.float_quads)
-    return L.clamp ? bwd_variant<true, true>(a, lds, s) : bwd_variant<true, false>(a, lds, s);
-  return L.clamp ? bwd_variant<false, true>(a, lds, s) : bwd_variant<false, false>(a, lds, s);
+  return in_launches(L.args, [&](const ParzenArgs& a) {
+    if (L.float_quads)
+      return L.clamp ? bwd_variant<true, true>(a, lds, s) : bwd_variant<true, false>(a, lds, s);
+    return L.clamp ? bwd_variant<false, true>(a, lds, s) : bwd_variant<false, false>(a, lds, s);
+  });
 }
 
 // The bands are sized for at most kParzenLdsMax of dynamic LDS per
