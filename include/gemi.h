@@ -30,6 +30,9 @@
  *    overlap gives MI 0, overlap 0, gradient 0; a transform with a
  *    non-finite entry, a linear entry beyond +-2^16 or a translation beyond
  *    +-2^24 gives MI NaN, overlap 0, gradient 0.
+ *  - Every transform of a batch (up to 2^24) is evaluated: a sweep whose
+ *    grid would pass the dispatch's 32-bit work-item count is issued as
+ *    several launches of whole transforms on the same stream.
  *
  * Definitions (the paper prints only Eq. (1)-(3); these are the readings
  * the library implements, identical in the CPU oracle used to test it):
