@@ -70,15 +70,11 @@ def kernel_version() -> str:
     return h.hexdigest()[:16]
 
 
-def cpu_baseline(c, min_seconds: float) -> dict:
-    """The oracle, as it stands, on evenly spaced transforms of the same
-    workload, one batch of (host threads) transforms at a time until
-    ``min_seconds`` of wall time have passed."""
-    import oracle
-    F = oracle.volume(c["fixed"], *c["fixed_range"])
-    M = oracle.volume(c["moving"], *c["moving_range"])
-    threads = oracle.num_threads()
-    order = np.random.default_rng(0).permutation(len(c["transforms"]))
+def _oracle_rate(oracle, F, M, c, order, threads: int, min_seconds: float):
+    """Voxel-transforms per second of the oracle at `threads` threads over
+    batches of `threads` transforms (taken in `order`) until ``min_seconds``
+    of wall time have passed."""
+    oracle.set_num_threads(threads)
     done, dt = 0, 0.0
     while dt < min_seconds and done < len(order):
         batch = c["transforms"][order[done:done + threads]]
@@ -86,10 +82,62 @@ def cpu_baseline(c, min_seconds: float) -> dict:
         oracle.eval_hard(F, M, batch, c["bins"], c["q"])
         dt += time.perf_counter() - t0
         done += len(batch)
-    rate = c["fixed"].size * done / dt
+    return c["fixed"].size * done / dt, done, dt
+
+
+def cpu_baseline(c, min_seconds: float) -> dict:
+    """The oracle, as it stands, on random transforms of the same workload:
+    at all host threads (the reported value) and at one thread."""
+    import oracle
+    F = oracle.volume(c["fixed"], *c["fixed_range"])
+    M = oracle.volume(c["moving"], *c["moving_range"])
+    threads = oracle.num_threads()
+    order = np.random.default_rng(0).permutation(len(c["transforms"]))
+    rate, done, dt = _oracle_rate(oracle, F, M, c, order, threads, min_seconds)
+    rate1, done1, dt1 = _oracle_rate(oracle, F, M, c, order, 1, min_seconds)
+    oracle.set_num_threads(threads)
     return {"value": rate, "unit": "voxel-transform evals/s", "cores": threads, "kind": "oracle",
             "sample": f"{done} of the 1000 transforms (random order, seed 0), full 256x256x180 "
-                      f"volume, all 6 entropies, {dt:.1f} s wall on {threads} threads"}
+                      f"volume, all 6 entropies, {dt:.1f} s wall on {threads} threads",
+            "single_thread": {"value": rate1, "unit": "voxel-transform evals/s", "cores": 1,
+                              "sample": f"{done1} transforms of the same order, {dt1:.1f} s wall on 1 thread"}}
+
+
+def plain_sweep_leg(ctx, B, inputs, dev, steps: int) -> dict:
+    """The plain method: 64^3 u8 head phantom against itself translated by
+    (3.5, -2, 1.25) voxels, 32 bins, Shannon MI over 21 x-translations in
+    [-10, 10] voxels, one mi_eval call per sweep."""
+    import torch
+    c = inputs.plain_translation()
+    F = B.Volume.from_numpy(c["fixed"], *c["fixed_range"], dev)
+    Mv = B.Volume.from_numpy(c["moving"], *c["moving_range"], dev)
+    tr = torch.from_numpy(c["transforms"]).to(dev)
+    n = len(c["transforms"])
+    ws = torch.empty(ctx.workspace_size(F, Mv, n, c["bins"], 1), dtype=torch.uint8, device=dev)
+    out = torch.empty((n, 1), dtype=torch.float64, device=dev)
+    for _ in range(3):
+        ctx.eval(F, Mv, tr, c["bins"], c["q"], out=out, want_overlap=False, workspace=ws)
+    torch.cuda.synchronize()
+    ctx.timing_read(B.TIMER_HARD)
+    ctx.timing(True)
+    reps = max(50, steps * 5)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        ctx.eval(F, Mv, tr, c["bins"], c["q"], out=out, want_overlap=False, workspace=ws)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ctx.timing(False)
+    k_ms, k_n = ctx.timing_read(B.TIMER_HARD)
+    best = int(np.argmax(out[:, 0].cpu().numpy()))
+    vox = c["fixed"].size * n
+    balg = algorithmic_bytes_per_voxel_xform(c["fixed"], c["moving"], c["transforms"], c["bins"])
+    k_avg = k_ms / max(k_n, 1)
+    return {"value": vox * reps / dt, "unit": "voxel-transform evals/s", "mi_evals_per_s": n * reps / dt,
+            "ms_per_sweep": dt / reps * 1e3, "kernel_ms": k_avg,
+            "kernel_hbm_frac": balg * vox / (k_avg * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "argmax_tx": float(c["transforms"][best][3]),
+            "config": "64^3 u8 head phantom, moving translated by (3.5, -2, 1.25) voxels, 32 bins, "
+                      "Shannon, 21 x-translations in [-10, 10]"}
 
 
 def grad_leg(ctx, B, inputs, dev, args) -> dict:
@@ -121,9 +169,19 @@ def grad_leg(ctx, B, inputs, dev, args) -> dict:
     ctx.timing(False)
     fwd_ms, fwd_n = ctx.timing_read(B.TIMER_PARZEN_FWD)
     bwd_ms, bwd_n = ctx.timing_read(B.TIMER_PARZEN_BWD)
+    fwd_k, bwd_k = fwd_ms / max(fwd_n, 1), bwd_ms / max(bwd_n, 1)
+    # algorithmic bytes per voxel-transform of one sweep: the f32 fixed voxel
+    # and the f32 moving voxels it covers (|det| of the linear part)
+    dets = np.abs(np.linalg.det(g["transforms"].reshape(-1, 3, 4)[:, :, :3]))
+    balg = 4.0 + 4.0 * float(dets.mean())
+    vox = g["fixed"].size * n
+    frac = lambda ms: balg * vox / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS
     return {"value": n * steps / dt, "unit": "MI-grad evals/s (forward + backward, 2 entropies)",
             "voxel_xf_per_s": g["fixed"].size * n * steps / dt, "ms_per_call": dt / steps * 1e3,
-            "fwd_kernel_ms": fwd_ms / max(fwd_n, 1), "bwd_kernel_ms": bwd_ms / max(bwd_n, 1),
+            "fwd_kernel_ms": fwd_k, "bwd_kernel_ms": bwd_k,
+            "roofline": {"bound": "hbm", "algorithmic_bytes_per_voxel_xform_per_sweep": balg,
+                         "fwd_frac": frac(fwd_k), "bwd_frac": frac(bwd_k),
+                         "fwd_plus_bwd_frac": 2 * balg * vox / ((fwd_k + bwd_k) * 1e-3) / 1e9 / HBM_PEAK_GBS},
             "config": "128^3 f32 phantoms, 64 random affines, 64-bin cubic B-spline Parzen "
                       "histogram, Shannon + Tsallis q=1.5, clamp boundary"}
 
@@ -156,6 +214,22 @@ def register_leg(ctx, B, inputs, dev, steps: int = 200) -> dict:
     s = register(ctx, F, M, geom, c["bins"], p0, steps=steps, q_translation=c["q"][0], param="decomposed")
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    # kernel times of the same loop, timed apart (events around every
+    # launch would add their own overhead to the iteration time above)
+    ctx.timing_read(B.TIMER_PARZEN_FWD)
+    ctx.timing_read(B.TIMER_PARZEN_BWD)
+    ctx.timing(True)
+    register(ctx, F, M, geom, c["bins"], p0, steps=20, q_translation=c["q"][0], param="decomposed")
+    torch.cuda.synchronize()
+    ctx.timing(False)
+    fwd_ms, fwd_n = ctx.timing_read(B.TIMER_PARZEN_FWD)
+    bwd_ms, bwd_n = ctx.timing_read(B.TIMER_PARZEN_BWD)
+    fwd_k, bwd_k = fwd_ms / max(fwd_n, 1), bwd_ms / max(bwd_n, 1)
+    # algorithmic bytes per fixed voxel and sweep: the i16 fixed voxel and
+    # the u16 moving voxels it covers (2 mm against 1 mm: 1/8 of a voxel)
+    balg = 2.0 + 2.0 / 8.0
+    nvox = c["fixed"].size
+    frac = lambda ms: balg * nvox / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS
     p = s.affine()
     A, t = p[:9].reshape(3, 3), p[9:]
     R = T.rotation_matrix(np.degrees(affine_to_decomposed(p)[:3]))   # rotation factor of A
@@ -169,6 +243,10 @@ def register_leg(ctx, B, inputs, dev, steps: int = 200) -> dict:
                             "translation_mm": float(np.abs(t).max()),
                             "linear_max_abs": float(np.abs(A - np.eye(3)).max())},
             "mi_first": s.history[0][1], "mi_last": s.history[-1][1],
+            "fwd_kernel_ms": fwd_k, "bwd_kernel_ms": bwd_k,
+            "roofline": {"bound": "hbm", "algorithmic_bytes_per_voxel_per_sweep": balg,
+                         "fwd_frac": frac(fwd_k), "bwd_frac": frac(bwd_k),
+                         "fwd_plus_bwd_frac": 2 * balg * nvox / ((fwd_k + bwd_k) * 1e-3) / 1e9 / HBM_PEAK_GBS},
             "config": "fixed 512x512x300 i16 CT-like (1 mm), moving 256^3 u16 MR-like (2 mm), "
                       "256-bin cubic B-spline Parzen, Shannon + Tsallis q=1.3, clamp boundary, "
                       "Adam over angles / log-scales / shears / translation"}
@@ -408,6 +486,7 @@ def main() -> int:
 
     if not args.no_extras:
         result["mi_grad"] = grad_leg(ctx, B, inputs, dev, args)
+        result["plain_sweep"] = plain_sweep_leg(ctx, B, inputs, dev, args.steps)
 
     if (args.pairs or not args.no_extras) and not args.no_pairs:
         result["pairs"] = pairs_leg(ctx, B, inputs, dev)
@@ -415,6 +494,18 @@ def main() -> int:
         result["maps"] = maps_leg(ctx, B, inputs, dev)
     if (args.register or not args.no_extras) and not args.no_register:
         result["register"] = register_leg(ctx, B, inputs, dev)
+
+    # the targets this measures against, stated with whether they are met
+    targets = {"hbm_roofline_frac": {"target": 0.60, "achieved": result["roofline"]["frac"]}}
+    if "plain_one_transform_per_launch" in result:
+        targets["batched_vs_plain"] = {"target": 10.0,
+                                       "achieved": result["plain_one_transform_per_launch"]["batched_speedup"]}
+    if "mi_grad" in result:
+        targets["gradient_path_hbm_roofline_frac"] = {
+            "target": 0.60, "achieved": result["mi_grad"]["roofline"]["fwd_plus_bwd_frac"]}
+    for v in targets.values():
+        v["met"] = bool(v["achieved"] >= v["target"])
+    result["targets"] = targets
 
     if not args.no_cpu:
         log(f"CPU oracle for at least {args.cpu_seconds} s")

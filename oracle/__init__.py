@@ -109,6 +109,7 @@ def _load():
                                                ctypes.c_int, ctypes.c_int, ctypes.c_double, u64, dp,
                                                P(ctypes.c_int64)]
         lib.or_num_threads.restype = ctypes.c_int
+        lib.or_set_num_threads.argtypes = [ctypes.c_int]
         _lib = lib
     return _lib
 
@@ -268,3 +269,8 @@ def eval_parzen(fixed, moving, M, bins: int, q, boundary: int = CLAMP, form: int
 
 def num_threads() -> int:
     return int(_load().or_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """OpenMP threads of later oracle calls (results do not depend on it)."""
+    _load().or_set_num_threads(int(n))

@@ -610,3 +610,13 @@ int or_num_threads(void) {
   return 1;
 #endif
 }
+
+/* Threads of later parallel loops (timing at one thread and at all cores). */
+void or_set_num_threads(int n) {
+#ifdef _OPENMP
+  extern void omp_set_num_threads(int);
+  omp_set_num_threads(n > 0 ? n : 1);
+#else
+  (void)n;
+#endif
+}

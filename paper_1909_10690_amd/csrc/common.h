@@ -6,6 +6,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include "plan.h"
+
 namespace gemi {
 
 constexpr int kMaxQ = 16;
@@ -278,16 +280,6 @@ struct HardLaunch {
   int32_t brick;       // 1: slabs as bricks (GroupWalkBrick; 1024-thread launches)
 };
 
-// A dispatch counts its work-items in 32 bits: a grid of n x (workgroups
-// per transform) x threads beyond that wraps without an error and leaves
-// transforms unevaluated.  Batches larger than this many transforms go out
-// as several launches of whole transforms (below 2^31 work-items each).
-inline int32_t transforms_per_launch(int64_t workgroups_per_transform, int32_t threads) {
-  const int64_t per = workgroups_per_transform * threads;
-  const int64_t m = per > 0 ? (int64_t)0x7FFFFFFF / per : 1;
-  return (int32_t)(m < 1 ? 1 : (m > 0x7FFFFFFF ? 0x7FFFFFFF : m));
-}
-
 // The gathers address their volume with 32-bit buffer offsets, so every
 // gather volume stays below 4 GiB (the entry points check it).
 constexpr size_t kMaxGatherBytes = 0xFFFFFFF0u;
@@ -397,6 +389,15 @@ struct ParzenLaunch {
   int32_t clamp;
 };
 
+// LDS guard of every launch with dynamic LDS: the kernel's static LDS (read
+// once with hipFuncGetAttributes) plus `dynamic` must fit the device's
+// per-workgroup maximum, and `dynamic` the maximum the kernel was
+// configured for (hipErrorInvalidValue otherwise; nothing is launched).
+// lds_register() records a kernel's static LDS and the device maximum at
+// configuration; lds_guard() looks up kernels it has not seen.
+hipError_t lds_register(const void* kernel);
+hipError_t lds_guard(const void* kernel, size_t dynamic, size_t configured_max);
+
 hipError_t launch_fill_u32(uint32_t* p, size_t n, uint32_t value, hipStream_t s);
 hipError_t launch_fill_f64(double* p, size_t n, hipStream_t s);
 hipError_t launch_prebin_fixed(const VolumeDesc& f, int bins, uint8_t* out, hipStream_t s);
@@ -461,7 +462,6 @@ hipError_t launch_parzen_sampled_fwd(const ParzenLaunch& L, const uint2* list, c
                                      hipStream_t s);
 hipError_t launch_dmi_dp(const ParzenLaunch& L, const QList& q, hipStream_t s);
 hipError_t launch_parzen_bwd(const ParzenLaunch& L, hipStream_t s);
-hipError_t configure_kernels();
 hipError_t launch_lds_atomic_probe(uint32_t* out, int32_t blocks, int32_t iters, hipStream_t s);
 
 }  // namespace gemi

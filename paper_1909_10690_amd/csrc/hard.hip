@@ -25,9 +25,59 @@
 #include "common.h"
 #include "sweep.h"
 
+#include <mutex>
+#include <utility>
+#include <vector>
+
 #pragma clang fp contract(off)
 
 namespace gemi {
+
+// ---------------------------------------------------------------------------
+// LDS guard
+// ---------------------------------------------------------------------------
+
+namespace {
+std::mutex g_lds_mu;
+std::vector<std::pair<const void*, size_t>> g_lds_static;  // kernel -> static LDS bytes
+size_t g_lds_device_max = 0;                               // LDS one workgroup may hold
+}  // namespace
+
+hipError_t lds_register(const void* kernel) {
+  hipFuncAttributes attr;
+  hipError_t e = hipFuncGetAttributes(&attr, kernel);
+  if (e != hipSuccess) return e;
+  int dev = 0, max_block = 0;
+  if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+  if ((e = hipDeviceGetAttribute(&max_block, hipDeviceAttributeMaxSharedMemoryPerBlock, dev)) != hipSuccess)
+    return e;
+  std::lock_guard<std::mutex> g(g_lds_mu);
+  g_lds_device_max = (size_t)max_block;
+  for (auto& k : g_lds_static)
+    if (k.first == kernel) {
+      k.second = attr.sharedSizeBytes;
+      return hipSuccess;
+    }
+  g_lds_static.emplace_back(kernel, attr.sharedSizeBytes);
+  return hipSuccess;
+}
+
+hipError_t lds_guard(const void* kernel, size_t dynamic, size_t configured_max) {
+  for (int pass = 0; pass < 2; ++pass) {
+    {
+      std::lock_guard<std::mutex> g(g_lds_mu);
+      for (const auto& k : g_lds_static)
+        if (k.first == kernel)
+          return lds_fits(dynamic, k.second, configured_max, g_lds_device_max) ? hipSuccess
+                                                                                : hipErrorInvalidValue;
+    }
+    if (pass == 0) {
+      const hipError_t e = lds_register(kernel);
+      if (e != hipSuccess) return e;
+    }
+  }
+  return hipErrorInvalidValue;
+}
 
 __global__ void fill_u32_kernel(uint32_t* __restrict__ p, size_t n, uint32_t v) {
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
@@ -274,6 +324,9 @@ constexpr int kSampledBlock = 512;
 template <bool CLAMP, bool PACKED, bool OCT8>
 static hipError_t launch_sampled_variant(const HardArgs& a, const uint2* list, const unsigned long long* n_list,
                                          size_t lds, hipStream_t s) {
+  const hipError_t e =
+      lds_guard((const void*)hist_sampled_kernel<CLAMP, PACKED, OCT8, kSampledBlock>, lds, kHardLdsMax);
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL((hist_sampled_kernel<CLAMP, PACKED, OCT8, kSampledBlock>), dim3((unsigned)(a.n * a.chunks)),
                      dim3(kSampledBlock), lds, s, a, list, n_list);
   return hipGetLastError();
@@ -281,6 +334,8 @@ static hipError_t launch_sampled_variant(const HardArgs& a, const uint2* list, c
 
 template <bool CLAMP, bool PACKED, bool OCT8, int NT, bool BRICK>
 static hipError_t launch_variant(const HardArgs& a, int n, size_t lds, hipStream_t s) {
+  const hipError_t e = lds_guard((const void*)hist_hard_kernel<CLAMP, PACKED, OCT8, NT, BRICK>, lds, kHardLdsMax);
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL((hist_hard_kernel<CLAMP, PACKED, OCT8, NT, BRICK>), dim3((unsigned)(n * a.chunks)),
                      dim3(NT), lds, s, a);
   return hipGetLastError();
@@ -334,7 +389,6 @@ hipError_t launch_hist_hard(const HardLaunch& L, hipStream_t s) {
   a.chunks = L.chunks;
   a.slab_major = L.slab_major;
   const size_t lds = L.packed ? (((size_t)L.bins * L.bins + 1) / 2) * 4 : (size_t)L.bins * L.bins * 4;
-  if (lds > kHardLdsMax) return hipErrorInvalidValue;  // above the limit the kernels are configured for
   if (L.block != 256 && L.block != 512 && L.block != 1024) return hipErrorInvalidValue;
   const int32_t step = transforms_per_launch(L.chunks, L.block);
   for (int32_t t0 = 0; t0 < L.n; t0 += step) {
@@ -366,7 +420,6 @@ hipError_t launch_hist_sampled(const HardLaunch& L, const uint2* list, const uns
   a.chunks = L.chunks;
   a.slab_major = 1;
   const size_t lds = L.packed ? (((size_t)L.bins * L.bins + 1) / 2) * 4 : (size_t)L.bins * L.bins * 4;
-  if (lds > kHardLdsMax) return hipErrorInvalidValue;  // above the limit the kernels are configured for
   const bool o8 = a.geom.oct8 != 0;
   auto one = [&](const HardArgs& b) -> hipError_t {
     if (L.clamp) {
@@ -404,8 +457,8 @@ static hipError_t allow_big_lds() {
                         (const void*)hist_hard_kernel<false, true, true, NT, BRICK>,
                         (const void*)hist_hard_kernel<true, true, true, NT, BRICK>};
   for (const void* f : fns) {
-    const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-    if (e != hipSuccess) return e;
+    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    if (e != hipSuccess || (e = lds_register(f)) != hipSuccess) return e;
   }
   return hipSuccess;
 }
@@ -422,7 +475,8 @@ hipError_t configure_hard_kernels() {
       (const void*)hist_sampled_kernel<false, true, true, kSampledBlock>,
       (const void*)hist_sampled_kernel<true, true, true, kSampledBlock>};
   for (const void* f : sampled)
-    if ((e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kHardLdsMax)) != hipSuccess)
+    if ((e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kHardLdsMax)) != hipSuccess ||
+        (e = lds_register(f)) != hipSuccess)
       return e;
   if ((e = allow_big_lds<256>()) != hipSuccess) return e;
   if ((e = allow_big_lds<512>()) != hipSuccess) return e;

@@ -324,15 +324,17 @@ hipError_t launch_pairs_prep(const PairsLaunch& L, hipStream_t s) {
 }
 
 constexpr int kPairsBlock = 512;
+// Dynamic LDS limit of the pairs sweep (a u32 table up to 128 bins, 16-bit
+// pairs above), leaving room for its static work-item slot.
+constexpr size_t kPairsLdsMax = 150 * 1024;
 
 template <bool CLAMP, bool PACKED, bool OCT8>
 static hipError_t pairs_variant(const PairsLaunch& L, hipStream_t s) {
   const int B = L.args.bins;
   const size_t lds = PACKED ? (((size_t)B * B + 1) / 2) * 4 : (size_t)B * B * 4;
-  if (lds > 150 * 1024) return hipErrorInvalidValue;  // the limit set below
   const void* fn = (const void*)hist_pairs_kernel<CLAMP, PACKED, OCT8, kPairsBlock>;
-  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
-  if (e != hipSuccess) return e;
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kPairsLdsMax);
+  if (e != hipSuccess || (e = lds_guard(fn, lds, kPairsLdsMax)) != hipSuccess) return e;
   int per_cu = 0;
   e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kPairsBlock, lds);
   if (e != hipSuccess) return e;

@@ -219,7 +219,8 @@ __device__ __forceinline__ size_t band_cell_row(const RowMap* m, int32_t r_lo, i
 // The band's table is accumulated in LDS as unsigned 24.40 fixed point: each
 // voxel adds its four B-spline weights scaled by 2^40, with the largest
 // derived by subtraction so that the voxel's mass is exactly 2^40 (the
-// weights sum to one, Eq. (10)).  Integer adds commute, so the table does
+// four cubic B-spline weights at any shift sum to one: partition of
+// unity).  Integer adds commute, so the table does
 // not depend on the order of the atomics.  The 2^-40 step keeps the tiny
 // taps (w ~ f^3 / 6) accurate to ~1e-12, below the fp32 rounding of the
 // weights themselves; a coarser step biases the near-empty cells that
@@ -659,6 +660,8 @@ __global__ __launch_bounds__(NT) void parzen_bwd_kernel(ParzenArgs a) {
 
 template <bool FQ, bool CLAMP>
 static hipError_t fwd_variant(const ParzenArgs& a, size_t lds, hipStream_t s) {
+  const hipError_t e = lds_guard((const void*)parzen_fwd_kernel<FQ, CLAMP, 512>, lds, kParzenLdsMax);
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL((parzen_fwd_kernel<FQ, CLAMP, 512>), dim3((unsigned)(a.n * a.chunks * a.bands)),
                      dim3(512), lds, s, a);
   return hipGetLastError();
@@ -691,7 +694,6 @@ static hipError_t in_launches(const ParzenArgs& a, F&& launch) {
 
 hipError_t launch_parzen_fwd(const ParzenLaunch& L, hipStream_t s) {
   const size_t lds = (size_t)(L.args.band_rows + kHotCopies - 1) * L.args.bins * 8;
-  if (lds > kParzenLdsMax) return hipErrorInvalidValue;  // bands are sized to fit
   return in_launches(L.args, [&](const ParzenArgs& a) {
     if (L.float_quads)
       return L.clamp ? fwd_variant<true, true>(a, lds, s) : fwd_variant<true, false>(a, lds, s);
@@ -702,6 +704,8 @@ hipError_t launch_parzen_fwd(const ParzenLaunch& L, hipStream_t s) {
 template <bool FQ, bool CLAMP>
 static hipError_t sampled_fwd_variant(const ParzenArgs& a, const uint2* list, const unsigned long long* n_list,
                                       size_t lds, hipStream_t s) {
+  const hipError_t e = lds_guard((const void*)parzen_sampled_fwd_kernel<FQ, CLAMP, 512>, lds, kParzenLdsMax);
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL((parzen_sampled_fwd_kernel<FQ, CLAMP, 512>), dim3((unsigned)(a.n * a.chunks * a.bands)),
                      dim3(512), lds, s, a, list, n_list);
   return hipGetLastError();
@@ -710,7 +714,6 @@ static hipError_t sampled_fwd_variant(const ParzenArgs& a, const uint2* list, co
 hipError_t launch_parzen_sampled_fwd(const ParzenLaunch& L, const uint2* list, const unsigned long long* n_list,
                                      hipStream_t s) {
   const size_t lds = (size_t)(L.args.band_rows + kHotCopies - 1) * L.args.bins * 8;
-  if (lds > kParzenLdsMax) return hipErrorInvalidValue;  // bands are sized to fit
   return in_launches(L.args, [&](const ParzenArgs& a) {
     if (L.float_quads)
       return L.clamp ? sampled_fwd_variant<true, true>(a, list, n_list, lds, s)
@@ -721,13 +724,23 @@ hipError_t launch_parzen_sampled_fwd(const ParzenLaunch& L, const uint2* list, c
 }
 
 hipError_t launch_dmi_dp(const ParzenLaunch& L, const QList& q, hipStream_t s) {
+  // sliced like the MI reduction of the whole batch, in launches of whole
+  // transforms below 2^31 work-items each
   const int32_t S = reduce_splits(L.args.bins, L.args.n);
-  hipLaunchKernelGGL(dmi_dp_kernel, dim3((unsigned)((int64_t)L.args.n * S)), dim3(256), 0, s, L.args, q, S);
-  return hipGetLastError();
+  const int32_t step = transforms_per_launch(S, 256);
+  for (int32_t t0 = 0; t0 < L.args.n; t0 += step) {
+    const ParzenArgs b = sub_batch(L.args, t0, L.args.n - t0 < step ? L.args.n - t0 : step);
+    hipLaunchKernelGGL(dmi_dp_kernel, dim3((unsigned)((int64_t)b.n * S)), dim3(256), 0, s, b, q, S);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 template <bool FQ, bool CLAMP>
 static hipError_t bwd_variant(const ParzenArgs& a, size_t lds, hipStream_t s) {
+  const hipError_t e = lds_guard((const void*)parzen_bwd_kernel<FQ, CLAMP, 2, 512>, lds, kParzenLdsMax);
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL((parzen_bwd_kernel<FQ, CLAMP, 2, 512>), dim3((unsigned)(a.n * a.chunks * a.bands)),
                      dim3(512), lds, s, a);
   return hipGetLastError();
@@ -735,7 +748,6 @@ static hipError_t bwd_variant(const ParzenArgs& a, size_t lds, hipStream_t s) {
 
 hipError_t launch_parzen_bwd(const ParzenLaunch& L, hipStream_t s) {
   const size_t lds = (size_t)kParzenQGroup * L.args.band_rows * L.args.bins * 4;
-  if (lds > kParzenLdsMax) return hipErrorInvalidValue;  // bands are sized to fit
   return in_launches(L.args, [&](const ParzenArgs& a) {
     if (L.float_quads)
       return L.clamp ? bwd_variant<true, true>(a, lds, s) : bwd_variant<true, false>(a, lds, s);
@@ -748,15 +760,14 @@ hipError_t launch_parzen_bwd(const ParzenLaunch& L, hipStream_t s) {
 template <bool FQ, bool CLAMP>
 static hipError_t allow_lds() {
   const int bytes = (int)kParzenLdsMax;
-  hipError_t e;
-  if ((e = hipFuncSetAttribute((const void*)parzen_fwd_kernel<FQ, CLAMP, 512>,
-                               hipFuncAttributeMaxDynamicSharedMemorySize, bytes)) != hipSuccess)
-    return e;
-  if ((e = hipFuncSetAttribute((const void*)parzen_sampled_fwd_kernel<FQ, CLAMP, 512>,
-                               hipFuncAttributeMaxDynamicSharedMemorySize, bytes)) != hipSuccess)
-    return e;
-  return hipFuncSetAttribute((const void*)parzen_bwd_kernel<FQ, CLAMP, 2, 512>,
-                             hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  const void* fns[3] = {(const void*)parzen_fwd_kernel<FQ, CLAMP, 512>,
+                        (const void*)parzen_sampled_fwd_kernel<FQ, CLAMP, 512>,
+                        (const void*)parzen_bwd_kernel<FQ, CLAMP, 2, 512>};
+  for (const void* f : fns) {
+    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    if (e != hipSuccess || (e = lds_register(f)) != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 hipError_t configure_parzen_kernels() {

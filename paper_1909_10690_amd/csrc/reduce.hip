@@ -224,20 +224,37 @@ hipError_t launch_mi_reduce(const ReduceLaunch& Lin, hipStream_t s) {
   L.splits = reduce_splits(L.bins, L.n);
   hipError_t e;
   const int S = L.splits;
-  const unsigned blocks = (unsigned)((int64_t)L.n * S);
   const int max_rows = (L.bins + S - 1) / S;
   const bool cached = max_rows * (L.bins + 2) <= kMaxSliceCells;  // cells + 2 marginals per row
-  if (!L.table) {
-    if ((e = launch_fill_u32((uint32_t*)L.count, 2 * (size_t)L.n, 0u, s)) != hipSuccess) return e;
-    hipLaunchKernelGGL(hist_count_kernel, dim3(blocks), dim3(kBlock), 0, s, L.hist, L.bins, S, L.count);
+  if (!L.table && (e = launch_fill_u32((uint32_t*)L.count, 2 * (size_t)L.n, 0u, s)) != hipSuccess) return e;
+  // launches of whole transforms, each below 2^31 work-items; the slice
+  // count stays that of the whole batch
+  const size_t BB = (size_t)L.bins * L.bins;
+  const int32_t step = transforms_per_launch(S, kBlock);
+  for (int32_t t0 = 0; t0 < L.n; t0 += step) {
+    ReduceLaunch P = L;
+    P.n = L.n - t0 < step ? L.n - t0 : step;
+    if (L.hist) P.hist = L.hist + (size_t)t0 * BB;
+    if (L.table) P.table = L.table + (size_t)t0 * BB;
+    P.count = L.count + t0;
+    P.part = L.part + (size_t)t0 * S * L.q.n * 3 * 2;  // (sum, error) pairs
+    P.transforms = L.transforms + 12 * (size_t)t0;
+    if (L.marg_out) P.marg_out = L.marg_out + (size_t)t0 * 2 * L.bins;
+    P.mi_out = L.mi_out + (size_t)t0 * L.q.n;
+    if (L.overlap_out) P.overlap_out = L.overlap_out + t0;
+    const unsigned blocks = (unsigned)((int64_t)P.n * S);
+    if (!P.table) {
+      hipLaunchKernelGGL(hist_count_kernel, dim3(blocks), dim3(kBlock), 0, s, P.hist, P.bins, S, P.count);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+      partial_variant<false>(P, blocks, cached, s);
+    } else {
+      partial_variant<true>(P, blocks, cached, s);
+    }
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    partial_variant<false>(L, blocks, cached, s);
-  } else {
-    partial_variant<true>(L, blocks, cached, s);
+    hipLaunchKernelGGL(mi_final_kernel, dim3((unsigned)P.n), dim3(64), 0, s, P);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
   }
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(mi_final_kernel, dim3((unsigned)L.n), dim3(64), 0, s, L);
-  return hipGetLastError();
+  return hipSuccess;
 }
 
 }  // namespace gemi

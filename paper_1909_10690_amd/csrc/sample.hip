@@ -15,9 +15,11 @@
 // {x | y << 12 | fixed bin << 24, z} (edges <= 4096, bins <= 256); the
 // sampled sweeps read it instead of walking the volume.  Each workgroup
 // writes its range of voxels in ascending order at a place reserved with
-// one atomic, so the order of the ranges varies from run to run; the
-// histograms built from the list do not (integer counts and the Parzen
-// path's fixed-point sums commute).
+// one atomic, so the order of the ranges varies from run to run.  Hard
+// histograms built from the list do not (integer counts commute).  Parzen
+// tables may, in the last bits: a workgroup's share of the list depends on
+// that order, and its exact fixed-point partial sums are rounded to fp64
+// and merged with fp64 atomics in scheduling order.
 #include "common.h"
 
 namespace gemi {
