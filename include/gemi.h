@@ -87,6 +87,8 @@ extern "C" {
 #define MI_ERR_FLAGS (-9)       /* unknown flag bits */
 #define MI_ERR_COUNT (-10)      /* n_transforms (or n_pairs) negative or above 2^24 */
 #define MI_ERR_SAMPLE (-11)     /* sampling fraction not finite or not above 0 */
+#define MI_ERR_TOO_LARGE (-12)  /* mi_eval_noalloc: the call needs more scratch than
+                                   MI_NOALLOC_SCRATCH_BYTES */
 #define MI_ERR_HIP (-20)        /* the HIP runtime reported an error (see mi_status_string) */
 #define MI_ERR_NO_DEVICE (-21)  /* no usable GPU with the requested index */
 
@@ -291,6 +293,34 @@ int mi_timing_read(mi_context *ctx, int which, double *total_ms, int64_t *launch
  * (overwritten).  Errors: MI_ERR_NULL, MI_ERR_WORKSPACE, MI_ERR_HIP. */
 int mi_probe_lds_atomics(mi_context *ctx, void *scratch, size_t scratch_bytes, void *stream,
                          double *lane_atomics_per_s);
+
+/* Allocation-free variant of mi_eval, for callers that cannot allocate
+ * device memory or call allocating routines around their launches (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Arguments, results and errors as mi_eval (hard or Parzen per
+ * `flags`), with no workspace: the scratch is a fixed device array of
+ * MI_NOALLOC_SCRATCH_BYTES (64 MiB) built into the library, one per GPU,
+ * held from the first mi_create on that GPU until the process ends.
+ *  - MI_ERR_TOO_LARGE, before any launch, when the call needs more scratch
+ *    than that.  It needs at most what mi_workspace_size() gives for the
+ *    same arguments (less when hist_out is given: the histograms then go
+ *    to the caller's buffer).
+ *  - MI_ERR_FLAGS for MI_USE_GRAPH (instantiating a graph allocates; the
+ *    caller may capture this call into its own graph instead) and
+ *    MI_SAMPLED.  MI_VOLUMES_UNCHANGED is ignored: every call prepares
+ *    its volumes.
+ *  - Calls no hipMalloc, hipFree, event creation or other allocating
+ *    routine; kernel timing (mi_timing_enable) does not record these calls.
+ *  - Every call on one GPU, from any context or thread, shares that GPU's
+ *    array, which keeps the last call's contents (each call clears what it
+ *    needs zeroed).  Calls that overlap on one GPU -- on different streams,
+ *    or from different threads without ordering -- race and give wrong
+ *    results; order them on one stream. */
+#define MI_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int mi_eval_noalloc(mi_context *ctx, const mi_volume *fixed, const mi_volume *moving,
+                    const double *transforms, int32_t n_transforms, int32_t bins, const double *q,
+                    int32_t n_q, int32_t flags, double *mi_out, uint64_t *overlap_out,
+                    uint32_t *hist_out, void *stream);
 
 /* Static description of a status code (never NULL).  For MI_ERR_HIP the
  * text of the last HIP error seen by this thread is appended. */

@@ -19,7 +19,8 @@ LIB_PATH = os.path.join(_HERE, "libgemi.so")
 MI_OK = 0
 MI_ERR_NULL, MI_ERR_DIMS, MI_ERR_DTYPE, MI_ERR_BINS, MI_ERR_RANGE = -1, -2, -3, -4, -5
 MI_ERR_Q, MI_ERR_WORKSPACE, MI_ERR_UNSUPPORTED, MI_ERR_FLAGS, MI_ERR_COUNT = -6, -7, -8, -9, -10
-MI_ERR_SAMPLE = -11
+MI_ERR_SAMPLE, MI_ERR_TOO_LARGE = -11, -12
+NOALLOC_SCRATCH_BYTES = 64 << 20  # MI_NOALLOC_SCRATCH_BYTES
 MI_ERR_HIP, MI_ERR_NO_DEVICE = -20, -21
 U8, U16, I16, F32 = 0, 1, 2, 3
 BOUNDARY_EXCLUDE, BOUNDARY_CLAMP = 0x0, 0x1
@@ -53,7 +54,7 @@ class MiPair(ctypes.Structure):
 
 EXPORTS = ["mi_create", "mi_destroy", "mi_workspace_size", "mi_eval", "mi_eval_sampled", "mi_grad",
            "mi_pairs_workspace_size", "mi_eval_pairs", "mi_tune", "mi_timing_enable",
-           "mi_timing_read", "mi_probe_lds_atomics", "mi_map_paths", "mi_status_string"]
+           "mi_timing_read", "mi_probe_lds_atomics", "mi_map_paths", "mi_eval_noalloc", "mi_status_string"]
 
 _lib = None
 
@@ -73,6 +74,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.mi_workspace_size.argtypes = [P(MiVolume), P(MiVolume), i32, i32, i32, i32, i32, P(sz)]
     lib.mi_eval.argtypes = [vp, P(MiVolume), P(MiVolume), vp, i32, i32, dp, i32, i32, vp, vp, vp,
                             vp, sz, vp]
+    lib.mi_eval_noalloc.argtypes = [vp, P(MiVolume), P(MiVolume), vp, i32, i32, dp, i32, i32, vp, vp, vp, vp]
     lib.mi_eval_sampled.argtypes = [vp, P(MiVolume), P(MiVolume), vp, i32, i32, dp, i32, i32,
                                     ctypes.c_double, ctypes.c_uint64, vp, vp, vp, vp, sz, vp]
     lib.mi_grad.argtypes = [vp, P(MiVolume), P(MiVolume), vp, i32, i32, dp, i32, i32, vp, vp, vp,
@@ -208,6 +210,25 @@ class Context:
                               _ptr(workspace), workspace.numel(), self._stream(stream))
         _check(st, "mi_eval")
         return mi, ov, hist
+
+    def eval_noalloc(self, fixed: Volume, moving: Volume, transforms: torch.Tensor, bins: int, q=(1.0,),
+                     flags: int = 0, out=None, overlap=None, hist=None, stream=None):
+        """mi_eval through the allocation-free entry point (include/gemi.h,
+        mi_eval_noalloc): the library's fixed device scratch instead of a
+        workspace.  The caller may pass the outputs (``out`` [n][n_q] float64,
+        ``overlap`` [n] int64, ``hist`` [n][bins][bins] int32) so that the
+        call itself allocates nothing; missing ones are allocated here."""
+        dev = fixed.tensor.device
+        transforms = transforms.to(device=dev, dtype=torch.float64).reshape(-1, 12).contiguous()
+        n = transforms.shape[0]
+        qs, qp = _qarr(q)
+        mi = out if out is not None else torch.empty((n, len(qs)), dtype=torch.float64, device=dev)
+        f, m = fixed.c(), moving.c()
+        st = self.lib.mi_eval_noalloc(self.handle, ctypes.byref(f), ctypes.byref(m), _ptr(transforms), n, bins,
+                                      qp, len(qs), flags, _ptr(mi), _ptr(overlap), _ptr(hist),
+                                      self._stream(stream))
+        _check(st, "mi_eval_noalloc")
+        return mi, overlap, hist
 
     def eval_sampled(self, fixed: Volume, moving: Volume, transforms: torch.Tensor, bins: int, q=(1.0,),
                      fraction: float = 0.1, seed: int = 0, flags: int = 0, want_hist: bool = False,

@@ -21,6 +21,8 @@
 namespace gemi {
 hipError_t configure_hard_kernels();
 hipError_t configure_parzen_kernels();
+hipError_t scratch_setup(int device);
+void* scratch_device_ptr(int device);
 }  // namespace gemi
 
 using namespace gemi;
@@ -789,6 +791,7 @@ const char* mi_status_string(int status) {
   case MI_ERR_FLAGS: return "unknown flag bits";
   case MI_ERR_SAMPLE: return "sampling fraction not finite or not above 0";
   case MI_ERR_COUNT: return "transform or pair count out of range";
+  case MI_ERR_TOO_LARGE: return "call needs more scratch than the library's fixed no-alloc buffer (MI_NOALLOC_SCRATCH_BYTES)";
   case MI_ERR_HIP: {
     static thread_local std::string s;
     s = "HIP error: " + g_last_hip;
@@ -812,6 +815,8 @@ int mi_create(mi_context** out, int device) {
   if ((e = hipSetDevice(device)) != hipSuccess) return hip_fail(e, "hipSetDevice");
   if ((e = configure_hard_kernels()) != hipSuccess) return hip_fail(e, "configure kernels");
   if ((e = configure_parzen_kernels()) != hipSuccess) return hip_fail(e, "configure kernels");
+  // the allocation-free entry point's scratch: this device's address of it
+  if ((e = scratch_setup(device)) != hipSuccess) return hip_fail(e, "scratch address");
   mi_context* c = new mi_context();
   c->device = device;
   if ((e = hipHostMalloc(&c->stage, kStageBytes, hipHostMallocDefault)) != hipSuccess ||
@@ -1014,6 +1019,43 @@ int mi_eval(mi_context* ctx, const mi_volume* fixed, const mi_volume* moving,
   key_q(key, q, n_q);
   st = graph_run(ctx, key, s, body);
   ctx->last_prep = prep_key(parzen ? 2 : 1, ws, fixed, moving, bins);  // the graph prepared them
+  return st;
+}
+
+int mi_eval_noalloc(mi_context* ctx, const mi_volume* fixed, const mi_volume* moving,
+                    const double* transforms, int32_t n, int32_t bins, const double* q, int32_t n_q,
+                    int32_t flags, double* mi_out, uint64_t* overlap_out, uint32_t* hist_out,
+                    void* stream) {
+  const bool parzen = (flags & MI_HIST_PARZEN) != 0;
+  if (flags & (MI_USE_GRAPH | MI_SAMPLED)) return MI_ERR_FLAGS;
+  int st = check_common(fixed, moving, n, bins, q, n_q, flags, parzen);
+  if (st != MI_OK) return st;
+  if ((st = check_q(q, n_q)) != MI_OK) return st;
+  if (n > 0 && (!transforms || !mi_out)) return MI_ERR_NULL;
+  if (parzen && hist_out) return MI_ERR_UNSUPPORTED;
+  const Layout L = layout(fixed, moving, n, bins, n_q, parzen, false, hist_out == nullptr);
+  if (L.total > MI_NOALLOC_SCRATCH_BYTES) return MI_ERR_TOO_LARGE;
+  if (!ctx) return MI_ERR_NULL;
+  if (n == 0) return MI_OK;
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e;
+  if ((e = hipSetDevice(ctx->device)) != hipSuccess) return hip_fail(e, "hipSetDevice");
+  // the device address looked up at mi_create (never the array's host-side name)
+  char* ws = (char*)scratch_device_ptr(ctx->device);
+  if (!ws) return hip_fail(hipErrorInvalidSymbol, "no-alloc scratch");
+  // other contexts on this device share the array: always prepare, and keep
+  // no record that a later call could take for a preparation still in place
+  const int32_t run_flags = flags & ~MI_VOLUMES_UNCHANGED;
+  const bool was_timing = ctx->timing;  // timing creates events: off for this call
+  ctx->timing = false;
+  if (parzen)
+    st = run_parzen(ctx, fixed, moving, transforms, n, bins, q, n_q, run_flags, mi_out, overlap_out, nullptr,
+                    ws, L, s);
+  else
+    st = run_hard(ctx, fixed, moving, transforms, n, bins, q, n_q, run_flags, mi_out, overlap_out, hist_out, ws,
+                  L, s, tune_for(ctx, fixed, moving, n, bins, flags));
+  ctx->timing = was_timing;
+  ctx->last_prep.clear();
   return st;
 }
 

@@ -1,0 +1,122 @@
+"""The allocation-free entry point mi_eval_noalloc (include/gemi.h): the
+library's fixed per-GPU scratch array instead of a caller's workspace.
+
+GPU: through the C ABI, against mi_eval (the entry point it is a variant
+of) on the same inputs -- hard histograms and overlaps bit-exact, MI within
+1e-12 max(1, |MI|) -- on two calls in a row, the second with smaller
+volumes, fewer transforms and fewer bins than the first (so it runs on the
+first call's leftovers in the shared array), for the hard path and the
+Parzen path.  CPU: the documented rejections, made before any launch."""
+import ctypes
+
+import numpy as np
+import pytest
+import torch
+
+from paper_1909_10690_amd import binding as B
+from paper_1909_10690_amd import inputs
+
+FAKE = 0x10000  # a non-NULL address that validation must never dereference
+MI_TOL = 1e-12
+
+
+def _vol(nx, ny, nz, dtype=B.U16, lo=0.0, hi=4095.0):
+    return B.MiVolume(FAKE, nx, ny, nz, dtype, lo, hi)
+
+
+def _noalloc(lib, f, m, n, bins, flags, hist=None):
+    q = (ctypes.c_double * 1)(1.0)
+    return lib.mi_eval_noalloc(None, ctypes.byref(f), ctypes.byref(m), FAKE, n, bins, q, 1, flags, FAKE, None,
+                               hist, None)
+
+
+def test_noalloc_rejects_calls_beyond_its_scratch():
+    lib = B.load()
+    big = _vol(256, 256, 180)  # 11.8 MB of fixed bins + 189 MB of moving octs
+    assert _noalloc(lib, big, big, 4, 64, 0) == B.MI_ERR_TOO_LARGE
+    # the histograms alone: 600 transforms x 256^2 x 4 B = 157 MB, plus 4 MB of
+    # octs -- fits once the caller takes them into its own buffer
+    mid = _vol(64, 64, 64)
+    assert _noalloc(lib, mid, mid, 600, 256, 0) == B.MI_ERR_TOO_LARGE
+    assert _noalloc(lib, mid, mid, 600, 256, 0, hist=FAKE) == B.MI_ERR_NULL  # valid; fails only on ctx
+    small = _vol(32, 32, 32)
+    assert _noalloc(lib, small, small, 8, 32, 0) == B.MI_ERR_NULL
+
+
+def test_noalloc_rejects_graph_and_sampling_flags():
+    lib = B.load()
+    v = _vol(32, 32, 32)
+    assert _noalloc(lib, v, v, 8, 32, B.USE_GRAPH) == B.MI_ERR_FLAGS
+    assert _noalloc(lib, v, v, 8, 32, B.SAMPLED) == B.MI_ERR_FLAGS
+    assert _noalloc(lib, v, v, 8, 32, B.VOLUMES_UNCHANGED) == B.MI_ERR_NULL  # accepted (ignored)
+    assert _noalloc(lib, v, v, 8, 1, 0) == B.MI_ERR_BINS
+    assert _noalloc(lib, v, v, 8, 32, B.HIST_PARZEN, hist=FAKE) == B.MI_ERR_UNSUPPORTED
+
+
+def _case(seed, shape_f, shape_m, n, dtype):
+    rng = np.random.default_rng(seed)
+    hi = 255 if dtype == np.uint8 else 4095
+    f = inputs.random_volume(rng, shape_f, dtype, 0, hi)
+    m = inputs.random_volume(rng, shape_m, dtype, 0, hi)
+    A = np.eye(3) + rng.uniform(-0.08, 0.08, (n, 3, 3))
+    t = rng.uniform(-3.0, 3.0, (n, 3, 1))
+    mats = np.concatenate([A, t], axis=2).reshape(n, 12)
+    mats[0] = [1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 0]
+    return f, m, mats, float(hi)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("parzen", [False, True])
+def test_noalloc_matches_mi_eval_on_two_calls(parzen):
+    ctx = B.Context(0)
+    try:
+        cases = [
+            # (seed, fixed shape, moving shape, transforms, dtype, bins, q)
+            (11, (40, 52, 66), (44, 50, 61), 37, np.uint16, 128, [1.0, 0.5, 2.0]),
+            (12, (19, 23, 30), (21, 17, 26), 9, np.uint8, 32, [1.0, 1.5]),
+        ]
+        flags = (B.HIST_PARZEN | B.BOUNDARY_CLAMP) if parzen else B.BOUNDARY_EXCLUDE
+        for seed, sf, sm, n, dt, bins, q in cases:
+            print(f"[no-alloc] parzen={parzen} seed={seed} fixed={sf} moving={sm} n={n} bins={bins}", flush=True)
+            f, m, mats, hi = _case(seed, sf, sm, n, dt)
+            F = B.Volume.from_numpy(f, 0.0, hi)
+            M = B.Volume.from_numpy(m, 0.0, hi)
+            tr = torch.from_numpy(mats).cuda()
+            ref_mi, ref_ov, ref_h = ctx.eval(F, M, tr, bins, q, flags=flags, want_hist=not parzen)
+            mi = torch.full((n, len(q)), float("nan"), dtype=torch.float64, device="cuda")
+            ov = torch.full((n,), -1, dtype=torch.int64, device="cuda")
+            h = None if parzen else torch.full((n, bins, bins), -1, dtype=torch.int32, device="cuda")
+            ctx.eval_noalloc(F, M, tr, bins, q, flags=flags, out=mi, overlap=ov, hist=h)
+            torch.cuda.synchronize()
+            if not parzen:
+                assert torch.equal(h, ref_h), "histograms differ from mi_eval"
+            assert torch.equal(ov, ref_ov), "overlap counts differ from mi_eval"
+            a, b = mi.cpu().numpy(), ref_mi.cpu().numpy()
+            err = np.abs(a - b) / np.maximum(1.0, np.abs(b))
+            assert np.isfinite(a).all() and err.max() <= MI_TOL, f"MI rel err {err.max()}"
+    finally:
+        ctx.close()
+
+
+@pytest.mark.gpu
+def test_noalloc_hard_without_hist_out_twice():
+    """The histograms in the scratch array (no hist_out): the second, smaller
+    call must clear the counts the first one left there."""
+    ctx = B.Context(0)
+    try:
+        for seed, sf, n, bins in [(21, (48, 40, 36), 50, 64), (22, (30, 28, 20), 6, 64)]:
+            print(f"[no-alloc] hard, no hist_out, seed={seed} fixed={sf} n={n}", flush=True)
+            f, m, mats, hi = _case(seed, sf, sf, n, np.uint8)
+            F = B.Volume.from_numpy(f, 0.0, hi)
+            M = B.Volume.from_numpy(m, 0.0, hi)
+            tr = torch.from_numpy(mats).cuda()
+            ref_mi, ref_ov, _ = ctx.eval(F, M, tr, bins, [1.0, 1.2])
+            mi = torch.empty((n, 2), dtype=torch.float64, device="cuda")
+            ov = torch.empty((n,), dtype=torch.int64, device="cuda")
+            ctx.eval_noalloc(F, M, tr, bins, [1.0, 1.2], out=mi, overlap=ov)
+            torch.cuda.synchronize()
+            assert torch.equal(ov, ref_ov)
+            a, b = mi.cpu().numpy(), ref_mi.cpu().numpy()
+            assert (np.abs(a - b) / np.maximum(1.0, np.abs(b))).max() <= MI_TOL
+    finally:
+        ctx.close()
