@@ -151,7 +151,7 @@ def grad_leg(ctx, B, inputs, dev, args) -> dict:
     tr = torch.from_numpy(g["transforms"]).to(dev)
     n, bins, q = len(tr), g["bins"], g["q"]
     flags = B.BOUNDARY_CLAMP
-    ws = torch.empty(ctx.workspace_size(F, M, n, bins, len(q), flags | B.HIST_PARZEN, True),
+    ws = torch.empty(ctx.workspace_size(F, M, n, bins, len(q), flags | B.HIST_PARZEN | B.GRADIENT),
                      dtype=torch.uint8, device=dev)
     log(f"gradient leg: {n} transforms x 128^3 f32, {bins} Parzen bins")
     for _ in range(2):
@@ -196,22 +196,19 @@ def register_leg(ctx, B, inputs, dev, steps: int = 200) -> dict:
     import numpy as np
     import torch
     from paper_1909_10690_amd import transforms as T
-    from paper_1909_10690_amd.autograd import Geometry
-    from paper_1909_10690_amd.register import affine_to_decomposed, register
+    from paper_1909_10690_amd.register import register
     log("register leg: building the 512x512x300 / 256^3 CT-MR pair")
     c = inputs.ct_mr_pair()
-    F = B.Volume.from_numpy(c["fixed"], *c["fixed_range"], dev)
-    M = B.Volume.from_numpy(c["moving"], *c["moving_range"], dev)
-    nz, ny, nx = c["fixed"].shape
-    geom = Geometry((nx, ny, nz), c["fixed_spacing"], (0.0, 0.0, 0.0), c["moving_spacing"],
-                    c["moving_origin"], dev)
+    F = B.Volume.from_numpy(c["fixed"], *c["fixed_range"], dev, spacing=c["fixed_spacing"])
+    M = B.Volume.from_numpy(c["moving"], *c["moving_range"], dev, spacing=c["moving_spacing"],
+                            origin=c["moving_origin"])
     st = c["start"]
     p0 = T.params_from(T.affine_matrix(st["angles"], st["scale"]), st["t"])
-    register(ctx, F, M, geom, c["bins"], p0, steps=3, q_translation=c["q"][0], param="decomposed")
+    register(ctx, F, M, c["bins"], p0, steps=3, q_translation=c["q"][0], param="decomposed")
     torch.cuda.synchronize()
     log(f"register leg: {steps} iterations")
     t0 = time.perf_counter()
-    s = register(ctx, F, M, geom, c["bins"], p0, steps=steps, q_translation=c["q"][0], param="decomposed")
+    s = register(ctx, F, M, c["bins"], p0, steps=steps, q_translation=c["q"][0], param="decomposed")
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     # kernel times of the same loop, timed apart (events around every
@@ -219,7 +216,7 @@ def register_leg(ctx, B, inputs, dev, steps: int = 200) -> dict:
     ctx.timing_read(B.TIMER_PARZEN_FWD)
     ctx.timing_read(B.TIMER_PARZEN_BWD)
     ctx.timing(True)
-    register(ctx, F, M, geom, c["bins"], p0, steps=20, q_translation=c["q"][0], param="decomposed")
+    register(ctx, F, M, c["bins"], p0, steps=20, q_translation=c["q"][0], param="decomposed")
     torch.cuda.synchronize()
     ctx.timing(False)
     fwd_ms, fwd_n = ctx.timing_read(B.TIMER_PARZEN_FWD)

@@ -27,19 +27,32 @@
  *    status means nothing was enqueued.  No exception or abort crosses
  *    the ABI.
  *  - Per-transform degenerate cases are not errors: a transform with no
- *    overlap gives MI 0, overlap 0, gradient 0; a transform with a
- *    non-finite entry, a linear entry beyond +-2^16 or a translation beyond
- *    +-2^24 gives MI NaN, overlap 0, gradient 0.
+ *    overlap gives MI 0, overlap 0, gradient 0; a transform whose
+ *    index-space matrix M has a non-finite entry, a linear entry beyond
+ *    +-2^16 or a translation beyond +-2^24 gives MI NaN, overlap 0,
+ *    gradient 0.
  *  - Every transform of a batch (up to 2^24) is evaluated: a sweep whose
  *    grid would pass the dispatch's 32-bit work-item count is issued as
  *    several launches of whole transforms on the same stream.
  *
  * Definitions (the paper prints only Eq. (1)-(3); these are the readings
  * the library implements, identical in the CPU oracle used to test it):
- *  - Transform: an index-space 3x4 matrix M, row-major, mapping fixed voxel
- *    index (i, j, k, 1) to a continuous moving voxel index.  M is quantised
- *    to signed Q32 fixed point, Mq = round-half-even(M * 2^32); coordinates
- *    are the exact int64 products Mq * (i, j, k, 1).
+ *  - Geometry: voxel index i = (i, j, k) of a volume sits at the physical
+ *    point origin + spacing * i (mm, per axis; voxel centres).
+ *  - Transform: a physical 3x4 matrix P, row-major, mapping a point x of
+ *    the fixed volume (mm) to the point P (x, 1) of the moving volume (mm)
+ *    (Fig. 1 Transform block; the Methodology's transforms are in mm).  The
+ *    library turns it into the index-space matrix M that maps fixed voxel
+ *    index (i, j, k, 1) to a continuous moving voxel index,
+ *    M = S_m^-1 (P (o_f + S_f i) - o_m), computed in fp64 one IEEE
+ *    operation at a time, never fused, in exactly this order
+ *    (sf, of: fixed spacing and origin; sm, om: moving):
+ *      M[r][c] = (P[r][c] * sf[c]) / sm[r]                    for c < 3
+ *      M[r][3] = ((((P[r][0] * of[0] + P[r][1] * of[1]) + P[r][2] * of[2])
+ *                 + P[r][3]) - om[r]) / sm[r]
+ *    With unit spacings and zero origins M equals P exactly.  M is
+ *    quantised to signed Q32 fixed point, Mq = round-half-even(M * 2^32);
+ *    coordinates are the exact int64 products Mq * (i, j, k, 1).
  *  - Overlap: MI_BOUNDARY_EXCLUDE keeps a fixed voxel iff every moving
  *    coordinate lies in [0, n - 1] (closed); MI_BOUNDARY_CLAMP clamps the
  *    coordinate to that interval and keeps every fixed voxel.
@@ -89,6 +102,8 @@ extern "C" {
 #define MI_ERR_SAMPLE (-11)     /* sampling fraction not finite or not above 0 */
 #define MI_ERR_TOO_LARGE (-12)  /* mi_eval_noalloc: the call needs more scratch than
                                    MI_NOALLOC_SCRATCH_BYTES */
+#define MI_ERR_GEOMETRY (-13)   /* a spacing not finite or not above 0, or an origin
+                                   entry not finite */
 #define MI_ERR_HIP (-20)        /* the HIP runtime reported an error (see mi_status_string) */
 #define MI_ERR_NO_DEVICE (-21)  /* no usable GPU with the requested index */
 
@@ -135,15 +150,22 @@ extern "C" {
  * default); slower for translation-like batches.  Ignored by the Parzen
  * and sampled paths; mi_eval_pairs does not take it (MI_ERR_FLAGS). */
 #define MI_COMPACT_SLABS 0x8000
+/* mi_workspace_size: size the workspace for mi_grad (adds the dMI/dp
+ * tables).  Accepted (and implied) by mi_grad; rejected (MI_ERR_FLAGS) by
+ * the other calls. */
+#define MI_GRADIENT 0x10000
 
 #define MI_MAX_Q 16
 #define MI_MAX_EDGE 4096
 
-/* A volume: tightly packed C-order [nz][ny][nx] (x fastest) on the device. */
+/* A volume: tightly packed C-order [nz][ny][nx] (x fastest) on the device,
+ * placed in physical space by its spacing and origin. */
 typedef struct mi_volume {
   const void *data; /* device pointer, nx*ny*nz elements of `dtype`        */
   int32_t nx, ny, nz; /* each in [2, 4096]; nx*ny*nz <= 2^28 */
   int32_t dtype;      /* MI_U8, MI_U16, MI_I16 or MI_F32                   */
+  double spacing[3];  /* mm between voxel centres along x, y, z; finite, > 0 */
+  double origin[3];   /* position (mm) of the centre of voxel (0, 0, 0); finite */
   double lo, hi;      /* intensity range mapped onto the bins              */
 } mi_volume;
 
@@ -159,15 +181,17 @@ int mi_create(mi_context **out, int device);
  * must have synchronised any stream still using the context. */
 int mi_destroy(mi_context *ctx);
 
-/* Bytes of device workspace that mi_eval (hard or Parzen, per `flags`) or,
- * with `for_grad` != 0, mi_grad needs for these arguments.  Host-only; no
- * GPU is touched.  Validates like the call it sizes. */
-int mi_workspace_size(const mi_volume *fixed, const mi_volume *moving, int32_t n_transforms,
-                      int32_t bins, int32_t n_q, int32_t flags, int32_t for_grad, size_t *bytes);
+/* Bytes of device workspace that mi_eval (hard or Parzen, per `flags`),
+ * mi_eval_sampled (with MI_SAMPLED) or mi_grad (with MI_GRADIENT) needs for
+ * these arguments.  Host-only; no GPU is touched; `ctx` may be NULL.
+ * Validates like the call it sizes. */
+int mi_workspace_size(mi_context *ctx, const mi_volume *fixed, const mi_volume *moving,
+                      int32_t n_transforms, int32_t bins, int32_t n_q, int32_t flags, size_t *bytes);
 
 /* MI of `n_transforms` candidate transforms (Fig. 1 Transform + Metric;
  * Eq. (1), Eq. (2); one histogram, every q).
- *   transforms  device double[n][12], row-major index-space 3x4 matrices
+ *   transforms  device double[n][12], row-major physical fixed -> moving
+ *               3x4 matrices (mm; see Transform above)
  *   bins        histogram bins per axis, 2..256
  *   q, n_q      HOST double[n_q] entropic indices (1.0 = Shannon), n_q <= 16
  *   flags       boundary | tsallis form | MI_HIST_HARD or MI_HIST_PARZEN
@@ -204,9 +228,12 @@ int mi_eval_sampled(mi_context *ctx, const mi_volume *fixed, const mi_volume *mo
                     size_t workspace_bytes, void *stream);
 
 /* Parzen MI and its gradient with respect to the 12 entries of each
- * index-space matrix (what a gradient optimiser of Eq. (3) consumes).
+ * physical matrix (what a gradient optimiser of Eq. (3) consumes).
  *   mi_out    device double[n][n_q]
- *   grad_out  device double[n][n_q][12], d MI / d M[r][c] at index r*4+c
+ *   grad_out  device double[n][n_q][12], d MI / d P[r][c] at index r*4+c,
+ *             P the caller's physical matrix (the sweep differentiates with
+ *             respect to the index-space entries; the library applies the
+ *             chain rule of the composition above)
  * `flags` selects boundary and Tsallis form; the histogram is always the
  * Parzen one (MI_HIST_PARZEN may be given or not).  The gradient holds the
  * set of overlapping voxels fixed (exact for MI_BOUNDARY_CLAMP). */
@@ -215,7 +242,8 @@ int mi_grad(mi_context *ctx, const mi_volume *fixed, const mi_volume *moving,
             int32_t n_q, int32_t flags, double *mi_out, double *grad_out, void *workspace,
             size_t workspace_bytes, void *stream);
 
-/* One fixed/moving pair and its own transforms (device double[n][12]). */
+/* One fixed/moving pair and its own physical transforms (device
+ * double[n][12]), each volume with its own spacing and origin. */
 typedef struct mi_pair {
   mi_volume fixed, moving;
   const double *transforms;

@@ -9,7 +9,9 @@ long-double entropies); this module builds it with gcc and wraps it with
 ctypes.  Every function cites the passage of the paper it follows:
 
 * Eq. (1) Shannon entropies, Eq. (2) MI, Discussion (one histogram serves
-  Shannon and Tsallis), Fig. 1 (transform -> metric pipeline).
+  Shannon and Tsallis), Fig. 1 (transform -> metric pipeline).  Transforms
+  are physical fixed -> moving 3x4 matrices (mm); each volume carries its
+  voxel spacing and origin, and ``compose`` gives the index-space matrix.
 * Tsallis entropy, trilinear interpolation, binning, overlap rule and the
   Parzen/B-spline variant are not printed in the paper; they follow the
   readings recorded in the repository's design notes.
@@ -54,7 +56,7 @@ def build(force: bool = True) -> str:
 class _Volume(ctypes.Structure):
     _fields_ = [("data", ctypes.c_void_p), ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
                 ("nz", ctypes.c_int32), ("dtype", ctypes.c_int32), ("lo", ctypes.c_double),
-                ("hi", ctypes.c_double)]
+                ("hi", ctypes.c_double), ("spacing", ctypes.c_double * 3), ("origin", ctypes.c_double * 3)]
 
 
 _lib = None
@@ -69,6 +71,7 @@ def _load():
         P = ctypes.POINTER
         vp = P(_Volume)
         dp = P(ctypes.c_double)
+        lib.or_compose.argtypes = [vp, vp, dp, dp]
         lib.or_quantize.argtypes = [dp, P(ctypes.c_int64)]
         lib.or_quantize.restype = ctypes.c_int
         lib.or_hist_hard.argtypes = [vp, vp, dp, ctypes.c_int, ctypes.c_int, P(ctypes.c_uint32)]
@@ -118,13 +121,16 @@ def _ptr(a, ctype):
     return a.ctypes.data_as(ctypes.POINTER(ctype))
 
 
-def volume(arr: np.ndarray, lo: float, hi: float) -> tuple:
-    """Describe a C-order [nz][ny][nx] array; keeps the array alive."""
+def volume(arr: np.ndarray, lo: float, hi: float, spacing=(1.0, 1.0, 1.0), origin=(0.0, 0.0, 0.0)) -> tuple:
+    """Describe a C-order [nz][ny][nx] array with its voxel spacing and the
+    position of voxel (0, 0, 0) (mm, x y z); keeps the array alive."""
     arr = np.ascontiguousarray(arr)
     if arr.ndim != 3 or arr.dtype not in _DTYPES:
         raise ValueError("volume must be a 3-D uint8/uint16/int16/float32 array")
     nz, ny, nx = arr.shape
-    v = _Volume(arr.ctypes.data, nx, ny, nz, _DTYPES[arr.dtype], float(lo), float(hi))
+    sp = (ctypes.c_double * 3)(*[float(x) for x in spacing])
+    og = (ctypes.c_double * 3)(*[float(x) for x in origin])
+    v = _Volume(arr.ctypes.data, nx, ny, nz, _DTYPES[arr.dtype], float(lo), float(hi), sp, og)
     return (v, arr)
 
 
@@ -135,6 +141,18 @@ def _mats(M) -> np.ndarray:
 
 def _qs(q) -> np.ndarray:
     return np.ascontiguousarray(np.atleast_1d(np.asarray(q, dtype=np.float64)))
+
+
+def compose(fixed, moving, P) -> np.ndarray:
+    """Index-space 3x4 matrix (fixed voxel index -> moving continuous index)
+    of one physical fixed -> moving matrix P, for the volumes' spacings and
+    origins (Fig. 1 Transform block; transforms in mm, Methodology)."""
+    lib = _load()
+    P = _mats(P)[0].copy()
+    out = np.zeros(12)
+    lib.or_compose(ctypes.byref(fixed[0]), ctypes.byref(moving[0]), _ptr(P, ctypes.c_double),
+                   _ptr(out, ctypes.c_double))
+    return out.reshape(3, 4)
 
 
 def quantize(M) -> tuple[np.ndarray, int]:
@@ -148,7 +166,8 @@ def quantize(M) -> tuple[np.ndarray, int]:
 
 def hist_hard(fixed, moving, M, bins: int, boundary: int = EXCLUDE) -> tuple[np.ndarray, int]:
     """Hard-binned joint histogram [bins][bins] (row = fixed bin) and overlap
-    count of one transform.  ``fixed``/``moving`` come from :func:`volume`."""
+    count of one physical transform M.  ``fixed``/``moving`` come from
+    :func:`volume`."""
     lib = _load()
     M = _mats(M)[0].copy()
     h = np.zeros((bins, bins), dtype=np.uint32)
@@ -238,7 +257,8 @@ def hist_hard_sampled(fixed, moving, M, bins: int, boundary: int, fraction: floa
 
 
 def parzen_grad(fixed, moving, M, bins: int, q, boundary: int = CLAMP, form: int = ADDITIVE):
-    """Parzen MI [n][nq] and gradient [n][nq][12] w.r.t. the index-space matrix."""
+    """Parzen MI [n][nq] and gradient [n][nq][12] w.r.t. the entries of the
+    physical matrix."""
     lib = _load()
     M = _mats(M)
     n = M.shape[0]

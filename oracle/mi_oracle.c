@@ -17,9 +17,13 @@
  * other rule below is a stated reading, listed with its reason in the design
  * notes of the repository):
  *
- *  - Transform block of Fig. 1: an index-space 3x4 affine map M takes fixed
- *    voxel index (i,j,k) to a continuous moving index.  M is quantised once
- *    to signed Q32 fixed point, Mq = round-half-even(M * 2^32).
+ *  - Transform block of Fig. 1: a physical 3x4 affine map P takes a point
+ *    of the fixed volume (mm) to a point of the moving volume (mm).  Voxel
+ *    index i of a volume sits at origin + spacing * i (voxel centres), so
+ *    the map from fixed voxel index to continuous moving index is
+ *    M = S_m^-1 (P (o_f + S_f i) - o_m), composed in fp64 in a fixed order
+ *    of single IEEE operations (or_compose).  M is quantised once to signed
+ *    Q32 fixed point, Mq = round-half-even(M * 2^32).
  *  - Overlap (EXCLUDE): a voxel counts iff every moving coordinate lies in
  *    the closed interval [0, n-1]; CLAMP clamps the coordinate instead and
  *    counts every fixed voxel.
@@ -37,7 +41,7 @@
  *  - Parzen variant: fixed side hard-binned, moving side weighted by the
  *    cubic B-spline beta3 at s = 1 + (v - lo)/(hi - lo) * (B - 4); fp64
  *    trilinear value; gradient of every MI output with respect to the 12
- *    entries of M (the quantity a gradient optimiser for Eq. (3) needs).
+ *    entries of P (the quantity a gradient optimiser for Eq. (3) needs).
  *  - Random subsampling (Discussion: Mattes' MI samples voxels at random,
  *    MI over all voxels does not, and the effect is left open): fixed voxel
  *    i (linear index, x fastest) takes part iff the top 32 bits of the
@@ -61,6 +65,8 @@ typedef struct {
   int32_t nx, ny, nz;
   int32_t dtype;
   double lo, hi;
+  double spacing[3]; /* mm per voxel along x, y, z */
+  double origin[3];  /* position (mm) of the centre of voxel (0, 0, 0) */
 } or_volume;
 
 typedef __int128 i128;
@@ -94,6 +100,29 @@ static double vox_real(const or_volume *v, int64_t ix, int64_t iy, int64_t iz) {
 /* ------------------------------------------------------------------ */
 /* transform quantisation                                              */
 /* ------------------------------------------------------------------ */
+
+/* Fixed voxel index -> continuous moving index of the physical map P:
+ *   M[r][c] = (P[r][c] * sf[c]) / sm[r]                                (c < 3)
+ *   M[r][3] = ((((P[r][0]*of[0] + P[r][1]*of[1]) + P[r][2]*of[2]) + P[r][3]) - om[r]) / sm[r]
+ * each operation rounded once (the file is built without contraction), in
+ * this order: the library documents the same order, so both sides quantise
+ * the same fp64 matrix. */
+void or_compose(const or_volume *f, const or_volume *m, const double P[12], double M[12]) {
+  for (int r = 0; r < 3; ++r) {
+    for (int c = 0; c < 3; ++c) {
+      double a = P[4 * r + c] * f->spacing[c];
+      M[4 * r + c] = a / m->spacing[r];
+    }
+    double o = P[4 * r + 0] * f->origin[0];
+    double o1 = P[4 * r + 1] * f->origin[1];
+    o = o + o1;
+    double o2 = P[4 * r + 2] * f->origin[2];
+    o = o + o2;
+    o = o + P[4 * r + 3];
+    o = o - m->origin[r];
+    M[4 * r + 3] = o / m->spacing[r];
+  }
+}
 
 /* Linear entries are bounded by 2^16 and translations by 2^24 so that, for
  * volumes of at most 4096 voxels per axis, every coordinate fits in int64.
@@ -184,9 +213,11 @@ static int keep_voxel(double fraction, uint64_t seed, int64_t lin) {
  * sampling rule; hist is bins*bins counts, row = fixed bin, column = moving
  * bin.  Returns the overlap count, or -1 when the transform is unusable
  * (hist left zero). */
-int64_t or_hist_hard_sampled(const or_volume *f, const or_volume *m, const double M[12], int bins,
+int64_t or_hist_hard_sampled(const or_volume *f, const or_volume *m, const double P[12], int bins,
                              int boundary, double fraction, uint64_t seed, uint32_t *hist) {
   memset(hist, 0, sizeof(uint32_t) * (size_t)bins * (size_t)bins);
+  double M[12];
+  or_compose(f, m, P, M);
   int64_t Mq[12];
   if (or_quantize(M, Mq)) return -1;
   const int64_t mlo = (int64_t)m->lo, mhi = (int64_t)m->hi;
@@ -232,9 +263,9 @@ int64_t or_hist_hard_sampled(const or_volume *f, const or_volume *m, const doubl
 }
 
 /* The histogram over every fixed voxel. */
-int64_t or_hist_hard(const or_volume *f, const or_volume *m, const double M[12], int bins,
+int64_t or_hist_hard(const or_volume *f, const or_volume *m, const double P[12], int bins,
                      int boundary, uint32_t *hist) {
-  return or_hist_hard_sampled(f, m, M, bins, boundary, 1.0, 0, hist);
+  return or_hist_hard_sampled(f, m, P, bins, boundary, 1.0, 0, hist);
 }
 
 /* ------------------------------------------------------------------ */
@@ -337,17 +368,17 @@ void or_mi_from_table(const double *table, int bins, double N, const double *qs,
   free(h);
 }
 
-/* Hard-binned MI of n transforms (row-major [n][12]).  mi[n][nq] and
+/* Hard-binned MI of n physical transforms (row-major [n][12]).  mi[n][nq] and
  * overlap[n]; an unusable transform gives NaN MI and overlap 0.  Transforms
  * are independent, so they are spread over OpenMP threads. */
-void or_eval_hard_sampled(const or_volume *f, const or_volume *m, const double *M, int n, int bins,
+void or_eval_hard_sampled(const or_volume *f, const or_volume *m, const double *P, int n, int bins,
                           const double *qs, int nq, int boundary, int form, double fraction,
                           uint64_t seed, double *mi, int64_t *overlap, uint32_t *hist_out) {
 #pragma omp parallel for schedule(dynamic, 1)
   for (int t = 0; t < n; ++t) {
     size_t nn = (size_t)bins * bins;
     uint32_t *h = hist_out ? hist_out + nn * (size_t)t : malloc(sizeof(uint32_t) * nn);
-    int64_t N = or_hist_hard_sampled(f, m, M + 12 * t, bins, boundary, fraction, seed, h);
+    int64_t N = or_hist_hard_sampled(f, m, P + 12 * t, bins, boundary, fraction, seed, h);
     if (N < 0) {
       for (int a = 0; a < nq; ++a) mi[(size_t)t * nq + a] = NAN;
       overlap[t] = 0;
@@ -359,10 +390,10 @@ void or_eval_hard_sampled(const or_volume *f, const or_volume *m, const double *
   }
 }
 
-void or_eval_hard(const or_volume *f, const or_volume *m, const double *M, int n, int bins,
+void or_eval_hard(const or_volume *f, const or_volume *m, const double *P, int n, int bins,
                   const double *qs, int nq, int boundary, int form, double *mi,
                   int64_t *overlap, uint32_t *hist_out) {
-  or_eval_hard_sampled(f, m, M, n, bins, qs, nq, boundary, form, 1.0, 0, mi, overlap, hist_out);
+  or_eval_hard_sampled(f, m, P, n, bins, qs, nq, boundary, form, 1.0, 0, mi, overlap, hist_out);
 }
 
 /* ------------------------------------------------------------------ */
@@ -457,10 +488,12 @@ static psample parzen_sample(const or_volume *f, const or_volume *m, const int64
 /* Parzen joint table (unnormalised masses, fp64) of one transform.
  * Returns the number of voxels that took part (the normaliser N), or -1
  * when the transform is unusable. */
-int64_t or_parzen_table_sampled(const or_volume *f, const or_volume *m, const double M[12], int bins,
+int64_t or_parzen_table_sampled(const or_volume *f, const or_volume *m, const double P[12], int bins,
                                 int boundary, double fraction, uint64_t seed, double *table) {
   int64_t nn = (int64_t)bins * bins;
   for (int64_t e = 0; e < nn; ++e) table[e] = 0.0;
+  double M[12];
+  or_compose(f, m, P, M);
   int64_t Mq[12];
   if (or_quantize(M, Mq)) return -1;
   long double *acc = calloc((size_t)nn, sizeof(long double));
@@ -480,9 +513,9 @@ int64_t or_parzen_table_sampled(const or_volume *f, const or_volume *m, const do
   return N;
 }
 
-int64_t or_parzen_table(const or_volume *f, const or_volume *m, const double M[12], int bins,
+int64_t or_parzen_table(const or_volume *f, const or_volume *m, const double P[12], int bins,
                         int boundary, double *table) {
-  return or_parzen_table_sampled(f, m, M, bins, boundary, 1.0, 0, table);
+  return or_parzen_table_sampled(f, m, P, bins, boundary, 1.0, 0, table);
 }
 
 /* dMI/dp table for one q on a Parzen table h with normaliser N:
@@ -521,13 +554,16 @@ static void dmi_dp(const double *h, int bins, double N, double q, int form, doub
 }
 
 /* Parzen MI and its gradient for one transform.  mi[nq], grad[nq][12]
- * (d MI / d M[r][c], row-major r*4+c).  Returns N, or -1 (unusable). */
-int64_t or_parzen_grad(const or_volume *f, const or_volume *m, const double M[12], int bins,
+ * (d MI / d P[r][c] of the physical matrix, row-major r*4+c).  The moving
+ * index is y_r = (sum_c P[r][c] x_c + P[r][3] - om[r]) / sm[r] with x the
+ * voxel's physical position, so d y_r / d P[r][c] = x_c / sm[r] and
+ * d y_r / d P[r][3] = 1 / sm[r].  Returns N, or -1 (unusable). */
+int64_t or_parzen_grad(const or_volume *f, const or_volume *m, const double P[12], int bins,
                        const double *qs, int nq, int boundary, int form, double *mi,
                        double *grad) {
   int64_t nn = (int64_t)bins * bins;
   double *h = malloc(sizeof(double) * (size_t)nn);
-  int64_t N = or_parzen_table(f, m, M, bins, boundary, h);
+  int64_t N = or_parzen_table(f, m, P, bins, boundary, h);
   for (int e = 0; e < 12 * nq; ++e) grad[e] = 0.0;
   if (N < 0) {
     for (int a = 0; a < nq; ++a) mi[a] = NAN;
@@ -539,6 +575,8 @@ int64_t or_parzen_grad(const or_volume *f, const or_volume *m, const double M[12
     free(h);
     return 0;
   }
+  double M[12];
+  or_compose(f, m, P, M);
   int64_t Mq[12];
   or_quantize(M, Mq);
   double *G = malloc(sizeof(double) * (size_t)nn * (size_t)nq);
@@ -550,13 +588,17 @@ int64_t or_parzen_grad(const or_volume *f, const or_volume *m, const double M[12
         psample p = parzen_sample(f, m, Mq, bins, boundary, i, j, k);
         if (!p.take) continue;
         int64_t k0 = (int64_t)floor(p.s) - 1;
-        const double xt[4] = {(double)i, (double)j, (double)k, 1.0};
+        /* the voxel's physical position, homogeneous */
+        const long double xt[4] = {(long double)f->origin[0] + (long double)f->spacing[0] * i,
+                                   (long double)f->origin[1] + (long double)f->spacing[1] * j,
+                                   (long double)f->origin[2] + (long double)f->spacing[2] * k, 1.0L};
         for (int a = 0; a < nq; ++a) {
           long double w = 0;
           for (int64_t kap = k0; kap < k0 + 4; ++kap)
             w -= (long double)G[nn * a + p.bf * bins + kap] * or_dbeta3((double)kap - p.s);
           for (int r = 0; r < 3; ++r)
-            for (int c = 0; c < 4; ++c) acc[12 * a + 4 * r + c] += w * p.dv[r] * xt[c];
+            for (int c = 0; c < 4; ++c)
+              acc[12 * a + 4 * r + c] += w * p.dv[r] * xt[c] / (long double)m->spacing[r];
         }
       }
   long double dsdv = (long double)(bins - 4) / ((long double)m->hi - (long double)m->lo);
@@ -568,23 +610,23 @@ int64_t or_parzen_grad(const or_volume *f, const or_volume *m, const double M[12
 }
 
 /* Parzen MI and gradient of n transforms, OpenMP over transforms. */
-void or_grad_batch(const or_volume *f, const or_volume *m, const double *M, int n, int bins,
+void or_grad_batch(const or_volume *f, const or_volume *m, const double *P, int n, int bins,
                    const double *qs, int nq, int boundary, int form, double *mi, double *grad) {
 #pragma omp parallel for schedule(dynamic, 1)
   for (int t = 0; t < n; ++t)
-    or_parzen_grad(f, m, M + 12 * t, bins, qs, nq, boundary, form, mi + (size_t)t * nq,
+    or_parzen_grad(f, m, P + 12 * t, bins, qs, nq, boundary, form, mi + (size_t)t * nq,
                    grad + (size_t)t * nq * 12);
 }
 
 /* Parzen MI (no gradient) of n transforms. */
-void or_eval_parzen_sampled(const or_volume *f, const or_volume *m, const double *M, int n, int bins,
+void or_eval_parzen_sampled(const or_volume *f, const or_volume *m, const double *P, int n, int bins,
                             const double *qs, int nq, int boundary, int form, double fraction,
                             uint64_t seed, double *mi, int64_t *overlap) {
 #pragma omp parallel for schedule(dynamic, 1)
   for (int t = 0; t < n; ++t) {
     size_t nn = (size_t)bins * bins;
     double *h = malloc(sizeof(double) * nn);
-    int64_t N = or_parzen_table_sampled(f, m, M + 12 * t, bins, boundary, fraction, seed, h);
+    int64_t N = or_parzen_table_sampled(f, m, P + 12 * t, bins, boundary, fraction, seed, h);
     if (N < 0) {
       for (int a = 0; a < nq; ++a) mi[(size_t)t * nq + a] = NAN;
       overlap[t] = 0;
@@ -596,10 +638,10 @@ void or_eval_parzen_sampled(const or_volume *f, const or_volume *m, const double
   }
 }
 
-void or_eval_parzen(const or_volume *f, const or_volume *m, const double *M, int n, int bins,
+void or_eval_parzen(const or_volume *f, const or_volume *m, const double *P, int n, int bins,
                     const double *qs, int nq, int boundary, int form, double *mi,
                     int64_t *overlap) {
-  or_eval_parzen_sampled(f, m, M, n, bins, qs, nq, boundary, form, 1.0, 0, mi, overlap);
+  or_eval_parzen_sampled(f, m, P, n, bins, qs, nq, boundary, form, 1.0, 0, mi, overlap);
 }
 
 int or_num_threads(void) {

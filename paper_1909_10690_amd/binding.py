@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libgemi.so")
 MI_OK = 0
 MI_ERR_NULL, MI_ERR_DIMS, MI_ERR_DTYPE, MI_ERR_BINS, MI_ERR_RANGE = -1, -2, -3, -4, -5
 MI_ERR_Q, MI_ERR_WORKSPACE, MI_ERR_UNSUPPORTED, MI_ERR_FLAGS, MI_ERR_COUNT = -6, -7, -8, -9, -10
-MI_ERR_SAMPLE, MI_ERR_TOO_LARGE = -11, -12
+MI_ERR_SAMPLE, MI_ERR_TOO_LARGE, MI_ERR_GEOMETRY = -11, -12, -13
 NOALLOC_SCRATCH_BYTES = 64 << 20  # MI_NOALLOC_SCRATCH_BYTES
 MI_ERR_HIP, MI_ERR_NO_DEVICE = -20, -21
 U8, U16, I16, F32 = 0, 1, 2, 3
@@ -30,6 +30,7 @@ USE_GRAPH = 0x1000
 VOLUMES_UNCHANGED = 0x2000  # reuse the workspace's prepared volumes (see include/gemi.h)
 SAMPLED = 0x4000  # workspace sizing for eval_sampled
 COMPACT_SLABS = 0x8000  # hint: bricks instead of thin slabs (rotation-heavy batches)
+GRADIENT = 0x10000  # workspace sizing for grad
 TIMER_HARD, TIMER_PARZEN_FWD, TIMER_PARZEN_BWD, TIMER_PAIRS, TIMER_REDUCE = 0, 1, 2, 3, 4
 
 _TORCH_DTYPES = {torch.uint8: U8, torch.uint16: U16, torch.int16: I16, torch.float32: F32}
@@ -43,8 +44,8 @@ class GemiError(RuntimeError):
 
 class MiVolume(ctypes.Structure):
     _fields_ = [("data", ctypes.c_void_p), ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
-                ("nz", ctypes.c_int32), ("dtype", ctypes.c_int32), ("lo", ctypes.c_double),
-                ("hi", ctypes.c_double)]
+                ("nz", ctypes.c_int32), ("dtype", ctypes.c_int32), ("spacing", ctypes.c_double * 3),
+                ("origin", ctypes.c_double * 3), ("lo", ctypes.c_double), ("hi", ctypes.c_double)]
 
 
 class MiPair(ctypes.Structure):
@@ -71,7 +72,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     i32, dp = ctypes.c_int32, P(ctypes.c_double)
     lib.mi_create.argtypes = [P(vp), ctypes.c_int]
     lib.mi_destroy.argtypes = [vp]
-    lib.mi_workspace_size.argtypes = [P(MiVolume), P(MiVolume), i32, i32, i32, i32, i32, P(sz)]
+    lib.mi_workspace_size.argtypes = [vp, P(MiVolume), P(MiVolume), i32, i32, i32, i32, P(sz)]
     lib.mi_eval.argtypes = [vp, P(MiVolume), P(MiVolume), vp, i32, i32, dp, i32, i32, vp, vp, vp,
                             vp, sz, vp]
     lib.mi_eval_noalloc.argtypes = [vp, P(MiVolume), P(MiVolume), vp, i32, i32, dp, i32, i32, vp, vp, vp, vp]
@@ -109,24 +110,32 @@ def _ptr(t) -> int | None:
 
 
 class Volume:
-    """A device volume [nz][ny][nx] with the intensity range mapped onto bins."""
+    """A device volume [nz][ny][nx] with the intensity range mapped onto bins,
+    its voxel spacing (mm, x y z) and the position of voxel (0, 0, 0)."""
 
-    def __init__(self, tensor: torch.Tensor, lo: float, hi: float):
+    def __init__(self, tensor: torch.Tensor, lo: float, hi: float, spacing=(1.0, 1.0, 1.0),
+                 origin=(0.0, 0.0, 0.0)):
         if tensor.dim() != 3:
             raise ValueError("volume must be 3-D [nz][ny][nx]")
         if tensor.dtype not in _TORCH_DTYPES:
             raise ValueError(f"unsupported dtype {tensor.dtype}")
         self.tensor = tensor.contiguous()
         self.lo, self.hi = float(lo), float(hi)
+        self.spacing = tuple(float(x) for x in spacing)
+        self.origin = tuple(float(x) for x in origin)
+        if len(self.spacing) != 3 or len(self.origin) != 3:
+            raise ValueError("spacing and origin take three values (x, y, z)")
 
     @classmethod
-    def from_numpy(cls, arr: np.ndarray, lo: float, hi: float, device="cuda") -> "Volume":
+    def from_numpy(cls, arr: np.ndarray, lo: float, hi: float, device="cuda", spacing=(1.0, 1.0, 1.0),
+                   origin=(0.0, 0.0, 0.0)) -> "Volume":
         t = torch.from_numpy(np.ascontiguousarray(arr))
-        return cls(t.to(device), lo, hi)
+        return cls(t.to(device), lo, hi, spacing, origin)
 
     def c(self) -> MiVolume:
         nz, ny, nx = self.tensor.shape
         return MiVolume(self.tensor.data_ptr(), nx, ny, nz, _TORCH_DTYPES[self.tensor.dtype],
+                        (ctypes.c_double * 3)(*self.spacing), (ctypes.c_double * 3)(*self.origin),
                         self.lo, self.hi)
 
 
@@ -184,11 +193,13 @@ class Context:
         return self._ws
 
     def workspace_size(self, fixed: Volume, moving: Volume, n: int, bins: int, n_q: int,
-                       flags: int = 0, for_grad: bool = False) -> int:
+                       flags: int = 0) -> int:
+        """Workspace bytes of eval (``flags``), eval_sampled (| SAMPLED) or
+        grad (| GRADIENT)."""
         out = ctypes.c_size_t()
         f, m = fixed.c(), moving.c()
-        _check(self.lib.mi_workspace_size(ctypes.byref(f), ctypes.byref(m), n, bins, n_q, flags,
-                                          int(for_grad), ctypes.byref(out)), "mi_workspace_size")
+        _check(self.lib.mi_workspace_size(self.handle, ctypes.byref(f), ctypes.byref(m), n, bins, n_q, flags,
+                                          ctypes.byref(out)), "mi_workspace_size")
         return out.value
 
     def eval(self, fixed: Volume, moving: Volume, transforms: torch.Tensor, bins: int, q=(1.0,),
@@ -256,7 +267,8 @@ class Context:
     def grad(self, fixed: Volume, moving: Volume, transforms: torch.Tensor, bins: int, q=(1.0,),
              flags: int = BOUNDARY_CLAMP, workspace: torch.Tensor | None = None, stream=None,
              out: tuple | None = None):
-        """Parzen MI[n][n_q] and dMI/dM[n][n_q][12] (into ``out`` = (mi, grad) if given)."""
+        """Parzen MI[n][n_q] and dMI/dP[n][n_q][12] with respect to the physical
+        matrices (into ``out`` = (mi, grad) if given)."""
         dev = fixed.tensor.device
         transforms = transforms.to(device=dev, dtype=torch.float64).reshape(-1, 12).contiguous()
         n = transforms.shape[0]
@@ -270,7 +282,8 @@ class Context:
             mi = torch.empty((n, len(qs)), dtype=torch.float64, device=dev)
             g = torch.empty((n, len(qs), 12), dtype=torch.float64, device=dev)
         if workspace is None:
-            workspace = self.workspace(self.workspace_size(fixed, moving, n, bins, len(qs), flags | HIST_PARZEN, True))
+            workspace = self.workspace(self.workspace_size(fixed, moving, n, bins, len(qs),
+                                                           flags | HIST_PARZEN | GRADIENT))
         f, m = fixed.c(), moving.c()
         st = self.lib.mi_grad(self.handle, ctypes.byref(f), ctypes.byref(m), _ptr(transforms), n,
                               bins, qp, len(qs), flags, _ptr(mi), _ptr(g), _ptr(workspace),

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgemi.so")
-SOURCES = ["abi.cpp", "hard.hip", "reduce.hip", "parzen.hip", "pairs.hip", "paths.hip", "probe.hip", "sample.hip", "noalloc.hip"]
+SOURCES = ["abi.cpp", "hard.hip", "reduce.hip", "parzen.hip", "pairs.hip", "paths.hip", "probe.hip", "sample.hip", "noalloc.hip", "transform.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

@@ -54,6 +54,8 @@ int check_volume(const mi_volume* v, bool need_integer) {
   for (int r = 0; r < 3; ++r)
     if (n[r] < 2 || n[r] > MI_MAX_EDGE) return MI_ERR_DIMS;
   if (voxels(v) > ((size_t)1 << 28)) return MI_ERR_DIMS;
+  for (int r = 0; r < 3; ++r)
+    if (!isfinite(v->spacing[r]) || !(v->spacing[r] > 0.0) || !isfinite(v->origin[r])) return MI_ERR_GEOMETRY;
   if (!isfinite(v->lo) || !isfinite(v->hi) || !(v->hi > v->lo)) return MI_ERR_RANGE;
   if (v->dtype != MI_F32) {
     if (v->lo != floor(v->lo) || v->hi != floor(v->hi)) return MI_ERR_RANGE;
@@ -94,7 +96,7 @@ int check_moving(const mi_volume* m, bool need_integer) {
 }
 
 constexpr int32_t kKnownFlags = MI_BOUNDARY_CLAMP | MI_TSALLIS_PSEUDOADDITIVE | MI_HIST_PARZEN | MI_USE_GRAPH |
-                                MI_VOLUMES_UNCHANGED | MI_SAMPLED | MI_COMPACT_SLABS;
+                                MI_VOLUMES_UNCHANGED | MI_SAMPLED | MI_COMPACT_SLABS | MI_GRADIENT;
 
 // Random subsampling of the fixed volume (mi_eval_sampled).
 struct SampleSpec {
@@ -119,6 +121,7 @@ int check_common(const mi_volume* f, const mi_volume* m, int32_t n, int32_t bins
 }
 
 // Workspace layout (each region 256-byte aligned):
+//   index-space matrices f64[n][12] (the caller's physical ones composed)
 //   fixed bins   u8[nvox_fixed]
 //   hard:        moving oct volume u16x8[mnz][mny][mnx],
 //                hist u32[n][B][B]          (only when the caller passes no hist_out)
@@ -130,7 +133,7 @@ int check_common(const mi_volume* f, const mi_volume* m, int32_t n, int32_t bins
 //   Parzen grad: + table marginals f64[n][2B], dMI/dp tables f32[n][n_q][B][B]
 //   sampled:     + sample list u32x2[nvox_fixed] and its length u64
 struct Layout {
-  size_t fbins = 0, gvol = 0, hist = 0, rowmap = 0, table = 0, count = 0, part = 0, marg = 0, gtab = 0,
+  size_t xf = 0, fbins = 0, gvol = 0, hist = 0, rowmap = 0, table = 0, count = 0, part = 0, marg = 0, gtab = 0,
          list = 0, nlist = 0, total = 0;
 };
 
@@ -139,6 +142,8 @@ Layout layout(const mi_volume* f, const mi_volume* m, int32_t n, int32_t bins, i
               bool parzen, bool grad, bool need_hist, bool sampled = false) {
   Layout L;
   size_t off = 0;
+  L.xf = off;
+  off += align256(96 * (size_t)n);
   L.fbins = off;
   off += align256(voxels(f));
   const size_t bb = (size_t)bins * bins;
@@ -189,6 +194,17 @@ VolumeDesc desc(const mi_volume* v) {
   d.lo = v->lo;
   d.hi = v->hi;
   return d;
+}
+
+Geometry geometry(const mi_volume* f, const mi_volume* m) {
+  Geometry g;
+  for (int r = 0; r < 3; ++r) {
+    g.fsp[r] = f->spacing[r];
+    g.forg[r] = f->origin[r];
+    g.msp[r] = m->spacing[r];
+    g.morg[r] = m->origin[r];
+  }
+  return g;
 }
 
 QList qlist(const double* q, int32_t n_q, int32_t flags) {
@@ -372,6 +388,13 @@ int run_parzen(mi_context* ctx, const mi_volume* fixed, const mi_volume* moving,
                int32_t flags, double* mi_out, uint64_t* overlap_out, double* grad_out, char* ws,
                const Layout& L, hipStream_t s, const SampleSpec* smp = nullptr) {
   hipError_t e;
+  // the caller's physical matrices -> index-space matrices in the workspace
+  {
+    double* M = (double*)(ws + L.xf);
+    if ((e = launch_compose(transforms, n, geometry(fixed, moving), M, s)) != hipSuccess)
+      return hip_fail(e, "compose");
+    transforms = M;
+  }
   uint8_t* fb = (uint8_t*)(ws + L.fbins);
   RowMap* rows = (RowMap*)(ws + L.rowmap);
   const bool fq = moving->dtype == MI_F32;
@@ -482,6 +505,9 @@ int run_parzen(mi_context* ctx, const mi_volume* fixed, const mi_volume* moving,
     P.args.q0 = q0;
     if ((st = sweep(true, 2)) != MI_OK) return st;
   }
+  // d MI / d M (index space) -> d MI / d P (the caller's physical entries)
+  if ((e = launch_grad_physical(grad_out, (int64_t)n * n_q, geometry(fixed, moving), s)) != hipSuccess)
+    return hip_fail(e, "grad chain rule");
   return MI_OK;
 }
 
@@ -638,12 +664,21 @@ bool use_graph(const mi_context* ctx, int32_t flags, hipStream_t s) {
   return (flags & MI_USE_GRAPH) && s != nullptr && !ctx->timing;
 }
 
+// A graph captures the composition with the volumes' spacings and origins
+// as kernel arguments, so they are part of the key.
 void key_volume(std::vector<uint64_t>& key, const mi_volume* v) {
   uint64_t lo, hi;
   memcpy(&lo, &v->lo, 8);
   memcpy(&hi, &v->hi, 8);
   key.insert(key.end(), {(uint64_t)(uintptr_t)v->data, (uint64_t)v->nx, (uint64_t)v->ny,
                          (uint64_t)v->nz, (uint64_t)v->dtype, lo, hi});
+  for (int r = 0; r < 3; ++r) {
+    uint64_t a, b;
+    memcpy(&a, &v->spacing[r], 8);
+    memcpy(&b, &v->origin[r], 8);
+    key.push_back(a);
+    key.push_back(b);
+  }
 }
 
 void key_q(std::vector<uint64_t>& key, const double* q, int32_t n_q) {
@@ -753,6 +788,11 @@ int run_hard(mi_context* ctx, const mi_volume* fixed, const mi_volume* moving,
              int32_t flags, double* mi_out, uint64_t* overlap_out, uint32_t* hist_out, char* ws,
              const Layout& L, hipStream_t s, const HardTune& tune, const SampleSpec* smp = nullptr) {
   uint32_t* hist = hist_out ? hist_out : (uint32_t*)(ws + L.hist);
+  // the caller's physical matrices -> index-space matrices in the workspace
+  double* M = (double*)(ws + L.xf);
+  hipError_t ce = launch_compose(transforms, n, geometry(fixed, moving), M, s);
+  if (ce != hipSuccess) return hip_fail(ce, "compose");
+  transforms = M;
   int st = launch_hard_hist(ctx, fixed, moving, transforms, n, bins, flags, hist, ws, L, s, tune, true, smp);
   if (st != MI_OK) return st;
   ReduceLaunch R;
@@ -858,15 +898,16 @@ int mi_destroy(mi_context* ctx) {
   return MI_OK;
 }
 
-int mi_workspace_size(const mi_volume* fixed, const mi_volume* moving, int32_t n, int32_t bins,
-                      int32_t n_q, int32_t flags, int32_t for_grad, size_t* bytes) {
+int mi_workspace_size(mi_context*, const mi_volume* fixed, const mi_volume* moving, int32_t n, int32_t bins,
+                      int32_t n_q, int32_t flags, size_t* bytes) {
   if (!bytes) return MI_ERR_NULL;
+  const bool for_grad = (flags & MI_GRADIENT) != 0;
   const bool parzen = for_grad || (flags & MI_HIST_PARZEN);
   int st = check_common(fixed, moving, n, bins, nullptr, 0, flags, parzen);
   if (st != MI_OK) return st;
   if (n_q < 1 || n_q > MI_MAX_Q) return MI_ERR_Q;
   if ((flags & MI_SAMPLED) && for_grad) return MI_ERR_UNSUPPORTED;
-  *bytes = layout(fixed, moving, n, bins, n_q, parzen, for_grad != 0, true, (flags & MI_SAMPLED) != 0).total;
+  *bytes = layout(fixed, moving, n, bins, n_q, parzen, for_grad, true, (flags & MI_SAMPLED) != 0).total;
   return MI_OK;
 }
 
@@ -875,7 +916,7 @@ int mi_tune(mi_context* ctx, const mi_volume* fixed, const mi_volume* moving,
             size_t workspace_bytes, void* stream) {
   int st = check_common(fixed, moving, n, bins, nullptr, 0, flags & ~MI_USE_GRAPH, false);
   if (st != MI_OK) return st;
-  if (flags & MI_SAMPLED) return MI_ERR_FLAGS;
+  if (flags & (MI_SAMPLED | MI_GRADIENT)) return MI_ERR_FLAGS;
   if (flags & MI_HIST_PARZEN) return MI_ERR_UNSUPPORTED;
   if (n > 0 && !transforms) return MI_ERR_NULL;
   const Layout L = layout(fixed, moving, n, bins, 1, false, false, true);
@@ -887,6 +928,13 @@ int mi_tune(mi_context* ctx, const mi_volume* fixed, const mi_volume* moving,
   if ((e = hipSetDevice(ctx->device)) != hipSuccess) return hip_fail(e, "hipSetDevice");
   char* ws = (char*)workspace;
   uint32_t* hist = (uint32_t*)(ws + L.hist);
+  // the caller's physical matrices -> index-space matrices, once
+  {
+    double* M = (double*)(ws + L.xf);
+    if ((e = launch_compose(transforms, n, geometry(fixed, moving), M, s)) != hipSuccess)
+      return hip_fail(e, "compose");
+    transforms = M;
+  }
   const bool was_timing = ctx->timing;
   ctx->timing = false;
   // fixed bins and octs once
@@ -986,7 +1034,7 @@ int mi_eval(mi_context* ctx, const mi_volume* fixed, const mi_volume* moving,
   const bool parzen = (flags & MI_HIST_PARZEN) != 0;
   int st = check_common(fixed, moving, n, bins, q, n_q, flags, parzen);
   if (st != MI_OK) return st;
-  if (flags & MI_SAMPLED) return MI_ERR_FLAGS;  // mi_eval_sampled
+  if (flags & (MI_SAMPLED | MI_GRADIENT)) return MI_ERR_FLAGS;  // mi_eval_sampled, mi_grad
   if ((st = check_q(q, n_q)) != MI_OK) return st;
   if (n > 0 && (!transforms || !mi_out)) return MI_ERR_NULL;
   if (parzen && hist_out) return MI_ERR_UNSUPPORTED;
@@ -1027,7 +1075,7 @@ int mi_eval_noalloc(mi_context* ctx, const mi_volume* fixed, const mi_volume* mo
                     int32_t flags, double* mi_out, uint64_t* overlap_out, uint32_t* hist_out,
                     void* stream) {
   const bool parzen = (flags & MI_HIST_PARZEN) != 0;
-  if (flags & (MI_USE_GRAPH | MI_SAMPLED)) return MI_ERR_FLAGS;
+  if (flags & (MI_USE_GRAPH | MI_SAMPLED | MI_GRADIENT)) return MI_ERR_FLAGS;
   int st = check_common(fixed, moving, n, bins, q, n_q, flags, parzen);
   if (st != MI_OK) return st;
   if ((st = check_q(q, n_q)) != MI_OK) return st;
@@ -1068,6 +1116,7 @@ int mi_eval_sampled(mi_context* ctx, const mi_volume* fixed, const mi_volume* mo
   if (st != MI_OK) return st;
   if ((st = check_q(q, n_q)) != MI_OK) return st;
   if ((st = check_fraction(fraction)) != MI_OK) return st;
+  if (flags & MI_GRADIENT) return MI_ERR_FLAGS;
   if (n > 0 && (!transforms || !mi_out)) return MI_ERR_NULL;
   if (parzen && hist_out) return MI_ERR_UNSUPPORTED;
   const Layout L = layout(fixed, moving, n, bins, n_q, parzen, false, hist_out == nullptr, true);
@@ -1202,6 +1251,7 @@ int mi_eval_pairs(mi_context* ctx, const mi_pair* pairs, int32_t n_pairs, int32_
     d.fixed = pr.fixed.data;
     d.moving = pr.moving.data;
     d.transforms = pr.transforms;
+    d.geo = geometry(&pr.fixed, &pr.moving);
     d.geom = make_hard_geom(desc(&pr.fixed), desc(&pr.moving), (const uint8_t*)(ws + plan.fbins[p]),
                             (const void*)(ws + plan.octs[p]), bins);
     // one layout for every pair of the launch

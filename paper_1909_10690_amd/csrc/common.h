@@ -42,6 +42,40 @@ __device__ __forceinline__ uint32_t div_small(uint32_t x, Divider d) {
   return (uint32_t)(((uint64_t)x * d.m) >> d.s);
 }
 
+// Spacings and origins of a fixed/moving pair: voxel index i of a volume
+// sits at origin + spacing * i (mm, per axis x, y, z).
+struct Geometry {
+  double fsp[3], forg[3];  // fixed
+  double msp[3], morg[3];  // moving
+};
+
+// Index-space matrix M (fixed voxel index -> continuous moving index) of a
+// physical fixed -> moving matrix P (Fig. 1 Transform block, mm):
+//   M[r][c] = (P[r][c] * fsp[c]) / msp[r]                                        (c < 3)
+//   M[r][3] = ((((P[r][0] forg[0] + P[r][1] forg[1]) + P[r][2] forg[2]) + P[r][3]) - morg[r]) / msp[r]
+// one IEEE operation at a time in exactly this order, never fused, so that
+// every implementation of the same definition quantises the same matrix.
+__device__ __forceinline__ void compose_index_matrix(const double* __restrict__ P, const Geometry& g,
+                                                     double* __restrict__ M) {
+#pragma clang fp contract(off)
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const double a = P[4 * r + c] * g.fsp[c];
+      M[4 * r + c] = a / g.msp[r];
+    }
+    double o = P[4 * r] * g.forg[0];
+    const double o1 = P[4 * r + 1] * g.forg[1];
+    o = o + o1;
+    const double o2 = P[4 * r + 2] * g.forg[2];
+    o = o + o2;
+    o = o + P[4 * r + 3];
+    o = o - g.morg[r];
+    M[4 * r + 3] = o / g.msp[r];
+  }
+}
+
 // Q32 quantisation of one index-space 3x4 transform: Mq = rne(M * 2^32).
 // A transform is usable when every entry is finite, linear entries are
 // within +-2^16 and translations within +-2^24 (so that every coordinate of
@@ -399,6 +433,12 @@ hipError_t lds_register(const void* kernel);
 hipError_t lds_guard(const void* kernel, size_t dynamic, size_t configured_max);
 
 hipError_t launch_fill_u32(uint32_t* p, size_t n, uint32_t value, hipStream_t s);
+// Index-space matrices M[n][12] of the caller's physical matrices P[n][12].
+hipError_t launch_compose(const double* P, int64_t n, const Geometry& g, double* M, hipStream_t s);
+// d MI / d P from d MI / d M in place, rows of 12 (gradients of `rows`
+// transform-entropy pairs): G_P[r][c] = (G_M[r][c] fsp[c] + G_M[r][3] forg[c]) / msp[r],
+// G_P[r][3] = G_M[r][3] / msp[r].
+hipError_t launch_grad_physical(double* grad, int64_t rows, const Geometry& g, hipStream_t s);
 hipError_t launch_fill_f64(double* p, size_t n, hipStream_t s);
 hipError_t launch_prebin_fixed(const VolumeDesc& f, int bins, uint8_t* out, hipStream_t s);
 hipError_t launch_pack_octs(const VolumeDesc& m, uint4* out, hipStream_t s);
@@ -415,7 +455,8 @@ hipError_t launch_hist_sampled(const HardLaunch& L, const uint2* list, const uns
 struct PairDesc {
   const void* fixed;
   const void* moving;
-  const double* transforms;  // caller's [n_t][12]
+  const double* transforms;  // caller's [n_t][12], physical
+  Geometry geo;              // the pair's spacings and origins
   HardGeom geom;             // fbins / octs point into the workspace
   int32_t fdtype, mdtype;
   double flo, fhi;           // fixed range (fp64 rule for float fixed volumes)
@@ -438,7 +479,7 @@ struct PairsArgs {
   const int64_t* t_base;     // [P+1] prefix of transforms
   const int64_t* xcd_base;   // [8][P+1] prefix of work items per XCD
   unsigned long long* counters;  // [8] work-queue heads
-  double* transforms;        // [T][12], gathered
+  double* transforms;        // [T][12], gathered and composed to index space
   uint32_t* hist;            // [T][B][B]
   int32_t bins;
 };

@@ -59,7 +59,9 @@ __global__ void gather_transforms_kernel(PairsArgs a, int64_t total) {
        g += (int64_t)gridDim.x * blockDim.x) {
     const int p = find_pair(a.t_base, a.n_pairs, g);
     const double* src = a.pairs[p].transforms + 12 * (g - a.t_base[p]);
-    for (int e = 0; e < 12; ++e) a.transforms[12 * g + e] = src[e];
+    double M[12];
+    compose_index_matrix(src, a.pairs[p].geo, M);
+    for (int e = 0; e < 12; ++e) a.transforms[12 * g + e] = M[e];
   }
 }
 

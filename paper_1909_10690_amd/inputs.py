@@ -13,7 +13,9 @@ This module holds no part of the metric's arithmetic.  Moving volumes are
 rendered analytically at the inverse-transformed position of each moving
 voxel (no interpolation), except the plain translation workload, whose
 moving volume is the fixed one resampled by scipy's order-1 spline
-(trilinear, edge-clamped).
+(trilinear, edge-clamped).  Transforms are physical fixed -> moving
+matrices; every workload but the CT/MR pair has unit spacings and zero
+origins, where physical and voxel coordinates coincide.
 """
 from __future__ import annotations
 
@@ -149,14 +151,15 @@ def multimodal_sweep(shape_xyz=(256, 256, 180), seed: int = 1, n_tx=10, n_rot=10
     rng = np.random.default_rng(seed)
     lab_f = render_labels(shape_xyz)
     fixed = intensities(lab_f, (0, 600, 1600, 2400), rng, 40.0, True, 0, 4095, np.uint16)
-    truth = T.index_matrix(T.affine_matrix((0, 0, 5.0), 1.03), (4.0, -3.0, 2.0), shape_xyz)
+    truth = T.centred_matrix(T.affine_matrix((0, 0, 5.0), 1.03), (4.0, -3.0, 2.0), T.fixed_centre(shape_xyz))
     lab_m = render_labels(shape_xyz, inv_map=invert(truth))
     moving = intensities(lab_m, (0, 3600, 2000, 1200), rng, 40.0, True, 0, 4095, np.uint16)
     mats = []
+    centre = T.fixed_centre(shape_xyz)
     for tx in np.linspace(-10, 10, n_tx):
         for th in np.linspace(-15, 15, n_rot):
             for s in np.linspace(0.9, 1.1, n_scale):
-                mats.append(T.index_matrix(T.affine_matrix((0, 0, th), s), (tx, 0, 0), shape_xyz))
+                mats.append(T.centred_matrix(T.affine_matrix((0, 0, th), s), (tx, 0, 0), centre))
     return dict(name="multimodal-sweep 256x256x180 u16", fixed=fixed, moving=moving,
                 fixed_range=(0, 4095), moving_range=(0, 4095),
                 transforms=np.stack(mats).reshape(-1, 12), bins=128,
@@ -191,7 +194,7 @@ def random_affines(rng: np.random.Generator, n: int, shape_xyz, rot=10.0, trans=
         t = rng.uniform(-trans, trans, 3)
         s = rng.uniform(scale[0], scale[1], 3)
         h = rng.uniform(-shear, shear, 3)
-        mats.append(T.index_matrix(T.affine_matrix(ang, s, h), t, shape_xyz))
+        mats.append(T.centred_matrix(T.affine_matrix(ang, s, h), t, T.fixed_centre(shape_xyz)))
     return np.stack(mats).reshape(-1, 12) if mats else np.zeros((0, 12))
 
 
@@ -202,8 +205,8 @@ def parzen_gradient(n: int = 128, seed: int = 2, n_transforms: int = 64) -> dict
     shape = (n, n, n)
     lab = render_labels(shape)
     fixed = (intensities(lab, (20, 90, 160, 230), rng, 8.0, False, 0, 255, np.float64) / 255.0).astype(np.float32)
-    truth = T.index_matrix(T.affine_matrix((3.0, -2.0, 4.0), (1.02, 0.98, 1.01), (0.01, 0.0, -0.01)),
-                           (2.5, -1.5, 1.0), shape)
+    truth = T.centred_matrix(T.affine_matrix((3.0, -2.0, 4.0), (1.02, 0.98, 1.01), (0.01, 0.0, -0.01)),
+                             (2.5, -1.5, 1.0), T.fixed_centre(shape))
     lab_m = render_labels(shape, inv_map=invert(truth))
     moving = (intensities(lab_m, (20, 90, 160, 230), rng, 8.0, False, 0, 255, np.float64) / 255.0).astype(np.float32)
     mats = random_affines(rng, n_transforms, shape)
@@ -220,7 +223,7 @@ def _one_pair(seed_seq, edges) -> dict:
     jit = rng.uniform(0.85, 1.1)
     lab = render_labels(shape, jitter=jit)
     fixed = intensities(lab, (20, 90, 160, 230), rng, 8.0, False, 0, 255, np.uint8)
-    truth = T.index_matrix(T.affine_matrix(rng.uniform(-5, 5, 3)), rng.uniform(-4, 4, 3), shape)
+    truth = T.centred_matrix(T.affine_matrix(rng.uniform(-5, 5, 3)), rng.uniform(-4, 4, 3), T.fixed_centre(shape))
     lab_m = render_labels(shape, inv_map=invert(truth), jitter=jit)
     moving = intensities(lab_m, (20, 90, 160, 230), rng, 8.0, False, 0, 255, np.uint8)
     mats = random_affines(rng, 16, shape, rot=10.0, trans=8.0, scale=(1.0, 1.0), shear=0.0)

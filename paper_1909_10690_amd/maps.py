@@ -87,14 +87,14 @@ def grid_axis(n: int, extent: float) -> np.ndarray:
 
 
 def map_transforms(family: str, n: int, fixed_shape_xyz, extent: float | None = None,
-                   fixed_spacing=(1.0, 1.0, 1.0), moving_spacing=(1.0, 1.0, 1.0),
-                   fixed_origin=(0.0, 0.0, 0.0), moving_origin=(0.0, 0.0, 0.0)) -> np.ndarray:
-    """Index-space matrices [n^3][12] of the family over an n^3 grid, grid
-    point (i, j, k) -- parameters (g[i], g[j], g[k]) -- at row (k n + j) n + i,
-    so a [n][n][n] view of any per-transform output is the [z][y][x] map."""
+                   fixed_spacing=(1.0, 1.0, 1.0), fixed_origin=(0.0, 0.0, 0.0)) -> np.ndarray:
+    """Physical matrices [n^3][12] of the family over an n^3 grid, about the
+    fixed volume's physical centre; grid point (i, j, k) -- parameters
+    (g[i], g[j], g[k]) -- at row (k n + j) n + i, so a [n][n][n] view of any
+    per-transform output is the [z][y][x] map."""
     ext = DEFAULT_EXTENT[family] if extent is None else float(extent)
     A, t = family_affines(family, grid_params(n, ext))
-    return T.index_matrices(A, t, fixed_shape_xyz, fixed_spacing, fixed_origin, moving_spacing, moving_origin)
+    return T.centred_matrices(A, t, T.fixed_centre(fixed_shape_xyz, fixed_spacing, fixed_origin))
 
 
 def z_order(n: int) -> np.ndarray:
@@ -111,21 +111,22 @@ def z_order(n: int) -> np.ndarray:
 
 def mi_map(ctx, fixed, moving, family: str, n: int = 51, extent: float | None = None, bins: int = 64,
            q=(1.0,), flags: int = 0, batch: int = 16384, transforms=None, sample=None,
-           order: str = "auto", compact: str | bool = "auto", **geometry):
+           order: str = "auto", compact: str | bool = "auto"):
     """MI maps [n_q][n][n][n] (device float64, [z][y][x] order per q) of one
     family over an n^3 grid: batches of grid points through ``ctx.eval``
     (or, with ``sample`` = (fraction, seed), ``ctx.eval_sampled``: every
     point over the same random subset of fixed voxels, as Mattes' MI
     samples them).  ``transforms`` (the [n^3][12] matrices, on the device)
-    may be given to skip building them; ``geometry`` takes the spacing /
-    origin arguments of :func:`map_transforms`.  ``order`` ("grid", "z" or
+    may be given to skip building them (by default they are built about the
+    fixed volume's physical centre).  ``order`` ("grid", "z" or
     "auto") and ``compact`` (bool or "auto") choose the evaluation order of
     the grid points and the compact-slab sweep; neither changes a value."""
     import torch
     dev = fixed.tensor.device
     if transforms is None:
         nz, ny, nx = fixed.tensor.shape
-        transforms = torch.from_numpy(map_transforms(family, n, (nx, ny, nz), extent, **geometry)).to(dev)
+        transforms = torch.from_numpy(map_transforms(family, n, (nx, ny, nz), extent, fixed.spacing,
+                                                     fixed.origin)).to(dev)
     total = n ** 3
     if transforms.shape != (total, 12):
         raise ValueError(f"transforms must be [{total}][12]")

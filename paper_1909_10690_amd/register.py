@@ -29,7 +29,7 @@ import torch
 
 from . import binding as B
 from . import transforms as T
-from .autograd import Geometry
+from .autograd import volume_centre
 
 
 def decomposed_to_affine(d) -> np.ndarray:
@@ -91,14 +91,16 @@ class RegState:
             return cls(**json.load(f))
 
 
-def register(gctx: B.Context, fixed: B.Volume, moving: B.Volume, geom: Geometry, bins: int,
+def register(gctx: B.Context, fixed: B.Volume, moving: B.Volume, bins: int,
              params0, steps: int = 200, q_translation: float = 1.3, mixed: bool = True,
              lr_linear: float = 2e-3, lr_translation: float = 0.2, betas=(0.9, 0.999),
              flags: int = B.BOUNDARY_CLAMP, state: RegState | None = None,
              checkpoint: str | None = None, every: int = 50, workspace=None,
-             param: str = "affine") -> RegState:
+             param: str = "affine", centre=None) -> RegState:
     """Maximises Parzen MI over the centred affine parameters ``params0``
-    (A.flat, t), stepping them in the parameterisation ``param``.
+    (A.flat, t) of y = A (x - c) + c + t, c = ``centre`` (mm; the fixed
+    volume's physical centre by default), stepping them in the
+    parameterisation ``param``.
 
     With ``mixed`` the objective's gradient takes the linear entries from
     Shannon MI and the translation entries from Tsallis MI at
@@ -119,19 +121,20 @@ def register(gctx: B.Context, fixed: B.Volume, moving: B.Volume, geom: Geometry,
     b1, b2 = betas
     d = np.asarray(state.params, dtype=np.float64)
     if workspace is None:
-        workspace = gctx.workspace(gctx.workspace_size(fixed, moving, 1, bins, len(q), flags | B.HIST_PARZEN, True))
+        workspace = gctx.workspace(gctx.workspace_size(fixed, moving, 1, bins, len(q), flags | B.HIST_PARZEN | B.GRADIENT))
     m = np.asarray(state.m, dtype=np.float64)
     v = np.asarray(state.v, dtype=np.float64)
-    J = geom.J
+    c = volume_centre(fixed) if centre is None else np.asarray(centre, dtype=np.float64)
+    J = T.centred_jacobian(c)              # d P / d (A, t), constant
     first = state.step
     while state.step < steps:
         pa = decomposed_to_affine(d) if dec else d
-        M = geom.matrices(torch.as_tensor(pa, dtype=torch.float64, device=dev).reshape(1, 12))
+        P = torch.as_tensor(T.centred_matrix(pa[:9], pa[9:], c).reshape(1, 12), dtype=torch.float64, device=dev)
         # the volumes and workspace stay the same over the loop: after the
         # first call the library reuses their preparation
         reuse = B.VOLUMES_UNCHANGED if state.step > first else 0
-        mi, gM = gctx.grad(fixed, moving, M, bins, q, flags=flags | reuse, workspace=workspace)
-        gp = (gM[0] @ J).cpu().numpy()          # [n_q][12] d MI_q / d (A, t)
+        mi, gP = gctx.grad(fixed, moving, P, bins, q, flags=flags | reuse, workspace=workspace)
+        gp = gP[0].cpu().numpy() @ J            # [n_q][12] d MI_q / d (A, t)
         if dec:
             gp = gp @ decomposed_jacobian(d)    # d MI_q / d (angles, log-scales, shears, t)
         if mixed:

@@ -1,18 +1,19 @@
-"""Affine transform parameterisations -> index-space 3x4 matrices.
+"""Affine transform parameterisations -> physical 3x4 matrices.
 
-The library takes, per candidate transform, a 3x4 matrix ``M`` that maps a
-fixed-volume voxel index (i, j, k) to a continuous moving-volume voxel index
-(the Transform block of Fig. 1: ``v(T(x))``).  This module builds those
-matrices from the physical, centred parameterisation used in registration
-(Introduction: translation, rotation, scale and skew form the affine family;
-12 degrees of freedom, Methodology):
+The library takes, per candidate transform, a 3x4 matrix ``P`` that maps a
+point of the fixed volume (mm) to a point of the moving volume (mm): the
+Transform block of Fig. 1, ``v(T(x))``; each volume carries its own voxel
+spacing and origin, and the library composes the voxel-index map itself.
+This module builds ``P`` from the centred parameterisation used in
+registration (Introduction: translation, rotation, scale and skew form the
+affine family; 12 degrees of freedom, Methodology):
 
-    y_phys = A (x_phys - c) + c + t,   x_phys = o_f + S_f i,   y_idx = S_m^-1 (y_phys - o_m)
+    y = A (x - c) + c + t,   i.e.   P = [A | c + t - A c],
 
-with ``c`` the physical centre of the fixed volume.  ``M`` is linear in the
-12 centred parameters (the 9 entries of A and the 3 of t), so gradients with
-respect to ``M`` map to gradients with respect to (A, t) through a constant
-Jacobian (:func:`index_jacobian`).
+with ``c`` a physical centre, by default that of the fixed volume.  ``P``
+is affine in the 12 centred parameters (the 9 entries of A and the 3 of
+t), so gradients with respect to ``P`` map to gradients with respect to
+(A, t) through a constant Jacobian (:func:`centred_jacobian`).
 
 The matrices are host-side inputs shared by the GPU library and the CPU
 oracle as data; nothing here computes any part of the metric.
@@ -41,58 +42,45 @@ def affine_matrix(angles_deg=(0.0, 0.0, 0.0), scale=(1.0, 1.0, 1.0), shear=(0.0,
 
 
 def fixed_centre(shape_xyz, spacing=(1.0, 1.0, 1.0), origin=(0.0, 0.0, 0.0)) -> np.ndarray:
+    """Physical centre of a volume: origin + (n - 1) / 2 * spacing."""
     n = np.asarray(shape_xyz, dtype=np.float64)
     return np.asarray(origin, dtype=np.float64) + (n - 1.0) / 2.0 * np.asarray(spacing, dtype=np.float64)
 
 
-def index_matrix(A, t, fixed_shape_xyz, fixed_spacing=(1.0, 1.0, 1.0), fixed_origin=(0.0, 0.0, 0.0),
-                 moving_spacing=(1.0, 1.0, 1.0), moving_origin=(0.0, 0.0, 0.0), centre=None) -> np.ndarray:
-    """Index-space 3x4 matrix (fixed voxel index -> moving voxel index)."""
+def centred_matrix(A, t, centre) -> np.ndarray:
+    """Physical 3x4 matrix of y = A (x - c) + c + t."""
     A = np.asarray(A, dtype=np.float64).reshape(3, 3)
     t = np.asarray(t, dtype=np.float64).reshape(3)
-    Sf = np.diag(np.asarray(fixed_spacing, dtype=np.float64))
-    Sm_inv = np.diag(1.0 / np.asarray(moving_spacing, dtype=np.float64))
-    of = np.asarray(fixed_origin, dtype=np.float64)
-    om = np.asarray(moving_origin, dtype=np.float64)
-    c = fixed_centre(fixed_shape_xyz, fixed_spacing, fixed_origin) if centre is None else np.asarray(centre, dtype=np.float64)
-    lin = Sm_inv @ A @ Sf
-    off = Sm_inv @ (A @ (of - c) + c + t - om)
-    M = np.zeros((3, 4))
-    M[:, :3] = lin
-    M[:, 3] = off
-    return M
+    c = np.asarray(centre, dtype=np.float64).reshape(3)
+    P = np.zeros((3, 4))
+    P[:, :3] = A
+    P[:, 3] = c + t - A @ c
+    return P
 
 
-def index_matrices(A, t, fixed_shape_xyz, fixed_spacing=(1.0, 1.0, 1.0), fixed_origin=(0.0, 0.0, 0.0),
-                   moving_spacing=(1.0, 1.0, 1.0), moving_origin=(0.0, 0.0, 0.0), centre=None) -> np.ndarray:
-    """:func:`index_matrix` of a batch: A [n][3][3], t [n][3] -> [n][12]."""
+def centred_matrices(A, t, centre) -> np.ndarray:
+    """:func:`centred_matrix` of a batch: A [n][3][3], t [n][3] -> [n][12]."""
     A = np.asarray(A, dtype=np.float64).reshape(-1, 3, 3)
     t = np.asarray(t, dtype=np.float64).reshape(-1, 3)
-    Sf = np.diag(np.asarray(fixed_spacing, dtype=np.float64))
-    Sm_inv = np.diag(1.0 / np.asarray(moving_spacing, dtype=np.float64))
-    of = np.asarray(fixed_origin, dtype=np.float64)
-    om = np.asarray(moving_origin, dtype=np.float64)
-    c = fixed_centre(fixed_shape_xyz, fixed_spacing, fixed_origin) if centre is None else np.asarray(centre, dtype=np.float64)
-    M = np.zeros((A.shape[0], 3, 4))
-    M[:, :, :3] = Sm_inv @ A @ Sf
-    M[:, :, 3] = ((A @ (of - c)) + c + t - om) @ Sm_inv.T
-    return M.reshape(-1, 12)
+    c = np.asarray(centre, dtype=np.float64).reshape(3)
+    P = np.zeros((A.shape[0], 3, 4))
+    P[:, :, :3] = A
+    P[:, :, 3] = c + t - A @ c
+    return P.reshape(-1, 12)
 
 
-def index_jacobian(fixed_shape_xyz, fixed_spacing=(1.0, 1.0, 1.0), fixed_origin=(0.0, 0.0, 0.0),
-                   moving_spacing=(1.0, 1.0, 1.0), moving_origin=(0.0, 0.0, 0.0), centre=None) -> np.ndarray:
-    """J[e, p] = d M.flat[e] / d params[p], params = (A.flat (9), t (3)).
+def centred_jacobian(centre) -> np.ndarray:
+    """J[e, p] = d P.flat[e] / d params[p], params = (A.flat (9), t (3)).
 
-    M depends linearly (affinely) on the parameters, so J is constant."""
+    P is affine in the parameters, so J is constant: d P[r][c] / d A[r][c] = 1,
+    d P[r][3] / d A[r][c] = -centre[c], d P[r][3] / d t[r] = 1."""
+    c = np.asarray(centre, dtype=np.float64).reshape(3)
     J = np.zeros((12, 12))
-    base = index_matrix(np.zeros((3, 3)), np.zeros(3), fixed_shape_xyz, fixed_spacing, fixed_origin,
-                        moving_spacing, moving_origin, centre).reshape(12)
-    for p in range(12):
-        e = np.zeros(12)
-        e[p] = 1.0
-        M = index_matrix(e[:9].reshape(3, 3), e[9:], fixed_shape_xyz, fixed_spacing, fixed_origin,
-                         moving_spacing, moving_origin, centre).reshape(12)
-        J[:, p] = M - base
+    for r in range(3):
+        for k in range(3):
+            J[4 * r + k, 3 * r + k] = 1.0
+            J[4 * r + 3, 3 * r + k] = -c[k]
+        J[4 * r + 3, 9 + r] = 1.0
     return J
 
 
@@ -101,7 +89,7 @@ def params_from(A, t) -> np.ndarray:
 
 
 def translation(t) -> np.ndarray:
-    """Pure index-space translation y = x + t."""
+    """Pure translation y = x + t."""
     M = np.zeros((3, 4))
     M[:, :3] = np.eye(3)
     M[:, 3] = np.asarray(t, dtype=np.float64)

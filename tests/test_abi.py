@@ -73,17 +73,22 @@ def test_header_constants_match_binding():
     assert consts["MI_USE_GRAPH"] == B.USE_GRAPH
     assert consts["MI_SAMPLED"] == B.SAMPLED and consts["MI_ERR_SAMPLE"] == B.MI_ERR_SAMPLE
     assert consts["MI_COMPACT_SLABS"] == B.COMPACT_SLABS
-    assert ctypes.sizeof(B.MiVolume) == 40
+    assert consts["MI_GRADIENT"] == B.GRADIENT and consts["MI_ERR_GEOMETRY"] == B.MI_ERR_GEOMETRY
+    assert consts["MI_ERR_TOO_LARGE"] == B.MI_ERR_TOO_LARGE
+    # data, nx, ny, nz, dtype, spacing[3], origin[3], lo, hi
+    assert ctypes.sizeof(B.MiVolume) == 88 and B.MiVolume.lo.offset == 72
 
 
 def test_status_strings():
-    for s in [0, -1, -2, -3, -4, -5, -6, -7, -8, -9, -10, -11, -20, -21, 12345]:
+    for s in [0, -1, -2, -3, -4, -5, -6, -7, -8, -9, -10, -11, -12, -13, -20, -21, 12345]:
         assert isinstance(B.status_string(s), str) and B.status_string(s)
     assert B.status_string(0) == "ok"
 
 
-def vol(nx=8, ny=8, nz=8, dtype=B.U8, lo=0.0, hi=255.0, data=FAKE):
-    return B.MiVolume(data, nx, ny, nz, dtype, lo, hi)
+def vol(nx=8, ny=8, nz=8, dtype=B.U8, lo=0.0, hi=255.0, data=FAKE, spacing=(1.0, 1.0, 1.0),
+        origin=(0.0, 0.0, 0.0)):
+    return B.MiVolume(data, nx, ny, nz, dtype, (ctypes.c_double * 3)(*spacing), (ctypes.c_double * 3)(*origin),
+                      lo, hi)
 
 
 def call_eval(f, m, n=4, bins=32, q=(1.0,), flags=0, transforms=FAKE, mi=FAKE, ws=FAKE,
@@ -107,6 +112,12 @@ def test_valid_arguments_reach_the_context_check():
     (dict(lo=5.0, hi=5.0), B.MI_ERR_RANGE), (dict(lo=0.5), B.MI_ERR_RANGE),
     (dict(hi=float("nan")), B.MI_ERR_RANGE), (dict(lo=0.0, hi=65536.0), B.MI_ERR_RANGE),
     (dict(data=None), B.MI_ERR_NULL),
+    (dict(spacing=(1.0, 0.0, 1.0)), B.MI_ERR_GEOMETRY), (dict(spacing=(-2.0, 1.0, 1.0)), B.MI_ERR_GEOMETRY),
+    (dict(spacing=(1.0, 1.0, float("inf"))), B.MI_ERR_GEOMETRY),
+    (dict(spacing=(1.0, float("nan"), 1.0)), B.MI_ERR_GEOMETRY),
+    (dict(origin=(0.0, float("nan"), 0.0)), B.MI_ERR_GEOMETRY),
+    (dict(origin=(float("-inf"), 0.0, 0.0)), B.MI_ERR_GEOMETRY),
+    (dict(spacing=(0.25, 3.0, 1e-3), origin=(-120.5, 7.0, 1e6)), B.MI_ERR_NULL),
 ])
 def test_volume_validation(kw, status):
     assert call_eval(vol(**kw), vol()) == status
@@ -168,9 +179,9 @@ def test_flags_count_pointers_workspace():
     assert call_eval(vol(), vol(), hist=FAKE, flags=B.HIST_PARZEN) == B.MI_ERR_UNSUPPORTED
 
 
-def ws_size(f, m, n, bins, n_q, flags=0, grad=0):
+def ws_size(f, m, n, bins, n_q, flags=0):
     out = ctypes.c_size_t()
-    st = B.load().mi_workspace_size(ctypes.byref(f), ctypes.byref(m), n, bins, n_q, flags, grad,
+    st = B.load().mi_workspace_size(None, ctypes.byref(f), ctypes.byref(m), n, bins, n_q, flags,
                                     ctypes.byref(out))
     return st, out.value
 
@@ -180,24 +191,25 @@ def test_workspace_size_layout():
     # MI partial sums: per transform, slice (min(1024 // n, B // 8) for
     # B >= 16) and entropy, three compensated pairs of doubles
     part = a(5 * min(1024 // 5, 32 // 8) * 2 * 3 * 16)
+    xf = a(5 * 96)  # the index-space matrices composed from the physical ones
     st, n = ws_size(vol(10, 11, 12), vol(9, 8, 7), 5, 32, 2)
     # moving range <= 256: oct volume of 8-bit corners, 8 bytes per voxel;
     # histograms; N per transform
-    assert st == 0 and n == a(10 * 11 * 12) + a(9 * 8 * 7 * 8) + a(5 * 32 * 32 * 4) + a(5 * 8) + part
+    assert st == 0 and n == xf + a(10 * 11 * 12) + a(9 * 8 * 7 * 8) + a(5 * 32 * 32 * 4) + a(5 * 8) + part
     # a wider range: 16-bit corners, 16 bytes per voxel
     st, n = ws_size(vol(10, 11, 12), vol(9, 8, 7, dtype=B.U16, lo=0.0, hi=4095.0), 5, 32, 2)
-    assert st == 0 and n == a(10 * 11 * 12) + a(9 * 8 * 7 * 16) + a(5 * 32 * 32 * 4) + a(5 * 8) + part
+    assert st == 0 and n == xf + a(10 * 11 * 12) + a(9 * 8 * 7 * 16) + a(5 * 32 * 32 * 4) + a(5 * 8) + part
     octs = a(8 * 8 * 8 * 16)
     rowmap = a(3 * 256 * 4 + 4)   # occupied fixed-bin rows: used, row_of_slot, slot_of_row, n_slots
     st, n = ws_size(vol(10, 11, 12), vol(), 5, 32, 2, B.HIST_PARZEN)
-    assert st == 0 and n == a(1320) + octs + rowmap + a(5 * 32 * 32 * 8) + a(5 * 8) + part
-    st, n = ws_size(vol(10, 11, 12), vol(), 5, 32, 2, 0, 1)
+    assert st == 0 and n == xf + a(1320) + octs + rowmap + a(5 * 32 * 32 * 8) + a(5 * 8) + part
+    st, n = ws_size(vol(10, 11, 12), vol(), 5, 32, 2, B.GRADIENT)
     # gradient: + the table marginals f64[n][2B] + dMI/dp tables f32[n][n_q][B][B]
-    assert st == 0 and n == (a(1320) + octs + rowmap + a(5 * 32 * 32 * 8) + a(5 * 8) + part + a(5 * 2 * 32 * 8)
+    assert st == 0 and n == (xf + a(1320) + octs + rowmap + a(5 * 32 * 32 * 8) + a(5 * 8) + part + a(5 * 2 * 32 * 8)
                              + a(5 * 2 * 32 * 32 * 4))
     # a float moving volume keeps fp32 quads: 16 bytes per voxel, one extra slice
     st, n = ws_size(vol(10, 11, 12), vol(dtype=B.F32, lo=0.0, hi=1.0), 5, 32, 2, B.HIST_PARZEN)
-    assert st == 0 and n == a(1320) + a(8 * 8 * 9 * 16) + rowmap + a(5 * 32 * 32 * 8) + a(5 * 8) + part
+    assert st == 0 and n == xf + a(1320) + a(8 * 8 * 9 * 16) + rowmap + a(5 * 32 * 32 * 8) + a(5 * 8) + part
     assert ws_size(vol(), vol(), 5, 1, 1)[0] == B.MI_ERR_BINS
     assert ws_size(vol(), vol(), 5, 32, 0)[0] == B.MI_ERR_Q
 
@@ -253,7 +265,8 @@ def test_graph_flag_accepted_and_unknown_bits_rejected():
     assert call_eval(vol(), vol(), flags=B.SAMPLED) == B.MI_ERR_FLAGS  # mi_eval_sampled's flag
     assert call_eval(vol(), vol(), flags=B.COMPACT_SLABS) == B.MI_ERR_NULL  # a hint: accepted
     assert call_eval(vol(), vol(), flags=B.COMPACT_SLABS | B.HIST_PARZEN) == B.MI_ERR_NULL
-    assert call_eval(vol(), vol(), flags=0x10000) == B.MI_ERR_FLAGS
+    assert call_eval(vol(), vol(), flags=B.GRADIENT) == B.MI_ERR_FLAGS  # mi_grad's sizing flag
+    assert call_eval(vol(), vol(), flags=0x20000) == B.MI_ERR_FLAGS
 
 
 def call_sampled(f, m, fraction=0.25, seed=7, n=4, bins=32, flags=0, ws_bytes=1 << 40, hist=None, ws=FAKE):
@@ -271,7 +284,8 @@ def test_sampled_validation():
     assert call_sampled(vol(), vol(), flags=B.SAMPLED | B.HIST_PARZEN) == B.MI_ERR_NULL
     for bad in (0.0, -0.5, float("nan"), float("inf")):
         assert call_sampled(vol(), vol(), fraction=bad) == B.MI_ERR_SAMPLE
-    assert call_sampled(vol(), vol(), flags=0x10000) == B.MI_ERR_FLAGS
+    assert call_sampled(vol(), vol(), flags=0x20000) == B.MI_ERR_FLAGS
+    assert call_sampled(vol(), vol(), flags=B.GRADIENT) == B.MI_ERR_FLAGS
     assert call_sampled(vol(), vol(), flags=B.HIST_PARZEN, hist=FAKE) == B.MI_ERR_UNSUPPORTED
     assert call_sampled(vol(), vol(), ws=None) == B.MI_ERR_WORKSPACE
     # the plain workspace is too small: the sample list is missing
@@ -281,7 +295,7 @@ def test_sampled_validation():
     assert call_sampled(vol(), vol(), ws_bytes=plain) == B.MI_ERR_WORKSPACE
     assert call_sampled(vol(), vol(), ws_bytes=sampled) == B.MI_ERR_NULL
     # no sampled gradient
-    assert ws_size(vol(), vol(), 4, 32, 2, B.SAMPLED, 1)[0] == B.MI_ERR_UNSUPPORTED
+    assert ws_size(vol(), vol(), 4, 32, 2, B.SAMPLED | B.GRADIENT)[0] == B.MI_ERR_UNSUPPORTED
 
 
 def test_tune_validation():

@@ -32,16 +32,17 @@ def workload():
     print("[ct-mr parity] generating 512x512x300 i16 / 256^3 u16", flush=True)
     c = inputs.ct_mr_pair()
     nz, ny, nx = c["fixed"].shape
-    geo = ((nx, ny, nz), c["fixed_spacing"], (0.0, 0.0, 0.0), c["moving_spacing"], c["moving_origin"])
+    centre = T.fixed_centre((nx, ny, nz), c["fixed_spacing"])
     st = c["start"]
     A0 = T.affine_matrix(st["angles"], st["scale"])
     params = [(A0, np.asarray(st["t"], dtype=np.float64)),
               (np.eye(3), np.zeros(3)),
               (T.affine_matrix((0.0, 0.0, 3.0), 1.02), np.asarray(st["t"]) / 2.0),
               (T.affine_matrix((2.5, -1.0, 0.0), (1.0, 0.98, 1.01), (0.02, 0.0, -0.01)), np.array([-3.0, 2.0, 1.5]))]
-    mats = np.stack([T.index_matrix(A, t, *geo).reshape(12) for A, t in params])
-    F = oracle.volume(c["fixed"], *c["fixed_range"])
-    M = oracle.volume(c["moving"], *c["moving_range"])
+    # physical (mm) fixed -> moving matrices; the volumes carry their spacings and origins
+    mats = np.stack([T.centred_matrix(A, t, centre).reshape(12) for A, t in params])
+    F = oracle.volume(c["fixed"], *c["fixed_range"], c["fixed_spacing"], (0.0, 0.0, 0.0))
+    M = oracle.volume(c["moving"], *c["moving_range"], c["moving_spacing"], c["moving_origin"])
     print("[ct-mr parity] oracle gradients of 4 transforms", flush=True)
     omi, og = oracle.parzen_grad(F, M, mats, 256, Q, oracle.CLAMP)
     return c, mats, omi, og
@@ -54,8 +55,9 @@ def test_ct_mr_full_size_gradient_parity(workload):
     print("[ct-mr parity] mi_grad / mi_eval on cuda:0", flush=True)
     ctx = B.Context(0)
     try:
-        Fv = B.Volume.from_numpy(c["fixed"], *c["fixed_range"])
-        Mv = B.Volume.from_numpy(c["moving"], *c["moving_range"])
+        Fv = B.Volume.from_numpy(c["fixed"], *c["fixed_range"], spacing=c["fixed_spacing"])
+        Mv = B.Volume.from_numpy(c["moving"], *c["moving_range"], spacing=c["moving_spacing"],
+                                 origin=c["moving_origin"])
         tr = torch.from_numpy(mats).cuda()
         mi, g = ctx.grad(Fv, Mv, tr, 256, Q, flags=B.BOUNDARY_CLAMP)
         mi2, ov, _ = ctx.eval(Fv, Mv, tr, 256, Q, flags=B.BOUNDARY_CLAMP | B.HIST_PARZEN)

@@ -69,7 +69,7 @@ def test_graph_gradient_and_pairs(ctx):
     M = B.Volume.from_numpy(c["moving"], 0.0, 1.0)
     tr = torch.from_numpy(c["transforms"]).cuda()
     stream = torch.cuda.Stream()
-    ws = torch.empty(ctx.workspace_size(F, M, 5, 32, 2, B.BOUNDARY_CLAMP | B.HIST_PARZEN, True),
+    ws = torch.empty(ctx.workspace_size(F, M, 5, 32, 2, B.BOUNDARY_CLAMP | B.HIST_PARZEN | B.GRADIENT),
                      dtype=torch.uint8, device="cuda")
     ref_mi, ref_g = ctx.grad(F, M, tr, 32, [1.0, 1.5])
     torch.cuda.synchronize()
@@ -143,7 +143,7 @@ def test_volume_preparation_reuse(ctx):
     M = B.Volume.from_numpy(c["moving"], 0.0, 1.0)
     M2 = B.Volume.from_numpy(other, 0.0, 1.0)
     tr = torch.from_numpy(c["transforms"]).cuda()
-    ws = torch.empty(ctx.workspace_size(F, M, 5, 32, 2, B.BOUNDARY_CLAMP | B.HIST_PARZEN, True),
+    ws = torch.empty(ctx.workspace_size(F, M, 5, 32, 2, B.BOUNDARY_CLAMP | B.HIST_PARZEN | B.GRADIENT),
                      dtype=torch.uint8, device="cuda")
     fl = B.BOUNDARY_CLAMP
     ref, ref_g = ctx.grad(F, M, tr, 32, [1.0, 1.5], flags=fl, workspace=ws)
@@ -176,7 +176,7 @@ def test_preparation_reuse_with_graphs(ctx):
     MB = B.Volume.from_numpy(c["moving"][::-1].copy(), 0.0, 1.0)
     tr = torch.from_numpy(c["transforms"]).cuda()
     fl = B.BOUNDARY_CLAMP
-    ws = torch.empty(ctx.workspace_size(F, MA, 5, 32, 2, fl | B.HIST_PARZEN, True), dtype=torch.uint8,
+    ws = torch.empty(ctx.workspace_size(F, MA, 5, 32, 2, fl | B.HIST_PARZEN | B.GRADIENT), dtype=torch.uint8,
                      device="cuda")
     refs = {}
     for name, M in (("A", MA), ("B", MB)):

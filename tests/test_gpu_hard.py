@@ -93,7 +93,7 @@ def _random_case(case, seed):
     mats = [T.translation((0, 0, 0)), T.translation((1, -1, 0)), T.translation((0.5, 0.25, -0.75))]
     for _ in range(13):
         A = T.affine_matrix(rng.uniform(-40, 40, 3), rng.uniform(0.7, 1.3, 3), rng.uniform(-0.2, 0.2, 3))
-        mats.append(T.index_matrix(A, rng.uniform(-6, 6, 3), fs))
+        mats.append(T.centred_matrix(A, rng.uniform(-6, 6, 3), T.fixed_centre(fs)))
     return fixed, moving, fr, mr, np.stack(mats).reshape(-1, 12), bins
 
 

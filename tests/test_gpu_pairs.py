@@ -60,7 +60,7 @@ def mixed_pairs(seed, n=7):
         lab = inputs.render_labels(shape)
         lev = np.linspace(r[0] + 10, r[1] - 10, 4)
         f = inputs.intensities(lab, lev, rng, 10.0, False, r[0], r[1], dt)
-        truth = T.index_matrix(T.affine_matrix(rng.uniform(-5, 5, 3)), rng.uniform(-2, 2, 3), shape)
+        truth = T.centred_matrix(T.affine_matrix(rng.uniform(-5, 5, 3)), rng.uniform(-2, 2, 3), T.fixed_centre(shape))
         m = inputs.intensities(inputs.render_labels(shape, inv_map=inputs.invert(truth)), lev[::-1], rng, 10.0,
                                False, r[0], r[1], dt)
         nt = int(rng.integers(0, 6))

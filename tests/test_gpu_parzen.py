@@ -34,11 +34,15 @@ def ctx():
     c.close()
 
 
-def gpu_grad(ctx, fixed, moving, fr, mr, mats, bins, q, flags):
+NO_GEO = ((1.0, 1.0, 1.0), (0.0, 0.0, 0.0), (1.0, 1.0, 1.0), (0.0, 0.0, 0.0))
+
+
+def gpu_grad(ctx, fixed, moving, fr, mr, mats, bins, q, flags, geo=NO_GEO):
+    """geo = (fixed spacing, fixed origin, moving spacing, moving origin)."""
     import torch
     from paper_1909_10690_amd import binding as B
-    F = B.Volume.from_numpy(fixed, *fr)
-    Mv = B.Volume.from_numpy(moving, *mr)
+    F = B.Volume.from_numpy(fixed, *fr, spacing=geo[0], origin=geo[1])
+    Mv = B.Volume.from_numpy(moving, *mr, spacing=geo[2], origin=geo[3])
     tr = torch.from_numpy(np.ascontiguousarray(np.asarray(mats, dtype=np.float64).reshape(-1, 12))).cuda()
     mi, g = ctx.grad(F, Mv, tr, bins, q, flags=flags)
     mi2, ov, _ = ctx.eval(F, Mv, tr, bins, q, flags=flags | B.HIST_PARZEN)
@@ -46,8 +50,8 @@ def gpu_grad(ctx, fixed, moving, fr, mr, mats, bins, q, flags):
     return mi.cpu().numpy(), g.cpu().numpy(), mi2.cpu().numpy(), ov.cpu().numpy()
 
 
-def oracle_grad(fixed, moving, fr, mr, mats, bins, q, flags):
-    F, Mv = oracle.volume(fixed, *fr), oracle.volume(moving, *mr)
+def oracle_grad(fixed, moving, fr, mr, mats, bins, q, flags, geo=NO_GEO):
+    F, Mv = oracle.volume(fixed, *fr, *geo[:2]), oracle.volume(moving, *mr, *geo[2:])
     form = oracle.PSEUDOADDITIVE if flags & 0x10 else oracle.ADDITIVE
     mi, g = oracle.parzen_grad(F, Mv, mats, bins, q, flags & 1, form)
     _, ov = oracle.eval_parzen(F, Mv, mats, bins, q, flags & 1, form)
@@ -72,7 +76,7 @@ def assert_close(gpu, orc, label):
 def _phantoms(shape, seed, dtype=np.float32):
     rng = np.random.default_rng(seed)
     lab = inputs.render_labels(shape)
-    truth = T.index_matrix(T.affine_matrix((4, -3, 6), 1.02), (1.2, -0.8, 0.5), shape)
+    truth = T.centred_matrix(T.affine_matrix((4, -3, 6), 1.02), (1.2, -0.8, 0.5), T.fixed_centre(shape))
     lab_m = inputs.render_labels(shape, inv_map=inputs.invert(truth))
     if np.dtype(dtype).kind == "f":
         f = (inputs.intensities(lab, (20, 90, 160, 230), rng, 8.0, False, 0, 255, np.float64) / 255.0).astype(dtype)
@@ -154,26 +158,32 @@ def test_full_size_sampled_and_finite_differences(ctx):
 
 
 def test_autograd_matches_chain_rule(ctx):
+    """torch autograd through the centred parameterisation (about the fixed
+    volume's physical centre, anisotropic spacings, non-zero origins) against
+    the oracle's physical gradient contracted with the parameterisation's
+    constant Jacobian."""
     import torch
     from paper_1909_10690_amd import binding as B
-    from paper_1909_10690_amd.autograd import Geometry, mutual_information
+    from paper_1909_10690_amd.autograd import identity_params, mutual_information
     f, m, fr, mr, _ = _phantoms((32, 28, 24), 9)
     shape = (32, 28, 24)
-    F, Mv = B.Volume.from_numpy(f, *fr), B.Volume.from_numpy(m, *mr)
-    geom = Geometry(shape)
-    p = geom.identity_params(3)
+    geo = ((1.25, 1.0, 0.75), (-20.0, 3.5, 10.25), (1.0, 1.125, 0.8), (-19.5, 3.0, 9.5))
+    F = B.Volume.from_numpy(f, *fr, spacing=geo[0], origin=geo[1])
+    Mv = B.Volume.from_numpy(m, *mr, spacing=geo[2], origin=geo[3])
+    p = identity_params(3)
     p[1, 9:] = torch.tensor([0.7, -0.4, 0.2], dtype=torch.float64)
     p[2, :9] = torch.as_tensor(T.affine_matrix((3, -2, 4), 1.03).reshape(9))
     p.requires_grad_(True)
     q = [1.0, 1.5]
-    mi = mutual_information(p, ctx, F, Mv, geom, 16, q)
+    mi = mutual_information(p, ctx, F, Mv, 16, q)
     w = torch.tensor([1.0, -0.5], dtype=torch.float64, device="cuda")
     (mi * w).sum().backward()
-    J = T.index_jacobian(shape)
-    M = (p.detach().cpu().numpy() @ J.T) + T.index_matrix(np.zeros((3, 3)), np.zeros(3), shape).reshape(12)
-    omi, og, _ = oracle_grad(f, m, fr, mr, M, 16, q, 1)
+    c = T.fixed_centre(shape, geo[0], geo[1])
+    pn = p.detach().cpu().numpy()
+    P = T.centred_matrices(pn[:, :9], pn[:, 9:], c)
+    omi, og, _ = oracle_grad(f, m, fr, mr, P, 16, q, 1, geo)
     np.testing.assert_allclose(mi.detach().cpu().numpy(), omi, rtol=MI_TOL)
-    ref = np.einsum("q,nqe->ne", w.cpu().numpy(), og) @ J
+    ref = np.einsum("q,nqe->ne", w.cpu().numpy(), og) @ T.centred_jacobian(c)
     got = p.grad.cpu().numpy()
     assert np.abs(got - ref).max() <= GRAD_TOL * np.abs(ref).max()
 

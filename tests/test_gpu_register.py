@@ -19,25 +19,22 @@ pytestmark = pytest.mark.gpu
 def setup():
     import torch
     from paper_1909_10690_amd import binding as B
-    from paper_1909_10690_amd.autograd import Geometry
     assert torch.cuda.is_available(), "GPU tests need a GPU"
     ctx = B.Context(0)
     c = inputs.ct_mr_pair(fixed_shape=(256, 256, 150), moving_shape=(128, 128, 128))
-    F = B.Volume.from_numpy(c["fixed"], *c["fixed_range"])
-    M = B.Volume.from_numpy(c["moving"], *c["moving_range"])
-    nz, ny, nx = c["fixed"].shape
-    geom = Geometry((nx, ny, nz), c["fixed_spacing"], (0.0, 0.0, 0.0), c["moving_spacing"],
-                    c["moving_origin"])
+    F = B.Volume.from_numpy(c["fixed"], *c["fixed_range"], spacing=c["fixed_spacing"])
+    M = B.Volume.from_numpy(c["moving"], *c["moving_range"], spacing=c["moving_spacing"],
+                            origin=c["moving_origin"])
     st = c["start"]
     p0 = T.params_from(T.affine_matrix(st["angles"], st["scale"]), st["t"])
-    yield ctx, F, M, geom, p0
+    yield ctx, F, M, p0
     ctx.close()
 
 
 def test_registration_recovers_the_truth(setup):
     from paper_1909_10690_amd.register import register
-    ctx, F, M, geom, p0 = setup
-    s = register(ctx, F, M, geom, 64, p0, steps=200, q_translation=1.3, param="decomposed")
+    ctx, F, M, p0 = setup
+    s = register(ctx, F, M, 64, p0, steps=200, q_translation=1.3, param="decomposed")
     p = s.affine()
     A, t = p[:9].reshape(3, 3), p[9:]
     assert s.history[-1][1][0] > s.history[0][1][0] + 0.02
@@ -47,11 +44,11 @@ def test_registration_recovers_the_truth(setup):
 
 def test_checkpoint_resume_continues_the_run(setup, tmp_path):
     from paper_1909_10690_amd.register import RegState, register
-    ctx, F, M, geom, p0 = setup
+    ctx, F, M, p0 = setup
     ck = str(tmp_path / "reg.json")
-    full = register(ctx, F, M, geom, 64, p0, steps=40, param="decomposed")
-    register(ctx, F, M, geom, 64, p0, steps=20, param="decomposed", checkpoint=ck, every=20)
-    resumed = register(ctx, F, M, geom, 64, None, steps=40, state=RegState.load(ck))
+    full = register(ctx, F, M, 64, p0, steps=40, param="decomposed")
+    register(ctx, F, M, 64, p0, steps=20, param="decomposed", checkpoint=ck, every=20)
+    resumed = register(ctx, F, M, 64, None, steps=40, state=RegState.load(ck))
     assert resumed.param == "decomposed" and resumed.step == 40
     # fp64 atomics merge workgroup partials in any order, so each gradient
     # varies at the 1e-15 level and Adam, which normalises every component,

@@ -34,7 +34,7 @@ def test_resampler_is_trilinear():
     rng = np.random.default_rng(21)
     vol = rng.uniform(0, 100, (9, 11, 13))
     A = T.affine_matrix((5.0, -3.0, 8.0), (1.05, 0.97, 1.0))
-    M = T.index_matrix(A, (0.7, -0.4, 0.3), (13, 11, 9))   # fixed index -> moving index
+    M = T.centred_matrix(A, (0.7, -0.4, 0.3), T.fixed_centre((13, 11, 9)))   # fixed index -> moving index
     out = inputs.resample_trilinear(vol, M)                 # out[i] = vol(M^-1 i)
     Mi = inputs.invert(M)
     checked = 0
@@ -50,7 +50,7 @@ def test_resampler_is_trilinear():
 def test_invert_composes_to_identity():
     rng = np.random.default_rng(22)
     for _ in range(20):
-        M = T.index_matrix(T.affine_matrix(rng.uniform(-30, 30, 3), rng.uniform(0.8, 1.2, 3)),
+        M = T.centred_matrix(T.affine_matrix(rng.uniform(-30, 30, 3), rng.uniform(0.8, 1.2, 3)),
                            rng.uniform(-5, 5, 3), (20, 30, 40))
         Mi = inputs.invert(M)
         p = rng.uniform(-10, 50, 3)
@@ -74,8 +74,8 @@ def test_multimodal_grid_and_ranges():
     assert w["moving"].dtype == np.uint16 and w["moving"].max() <= 4095
     assert w["q"] == [1.0, 0.5, 0.8, 1.2, 1.5, 2.0] and w["bins"] == 128
     # first and last grid points: tx -10, rot_z -15 deg, scale 0.9 / tx 10, rot_z 15, scale 1.1
-    first = T.index_matrix(T.affine_matrix((0, 0, -15.0), 0.9), (-10.0, 0, 0), (24, 20, 12)).reshape(12)
-    last = T.index_matrix(T.affine_matrix((0, 0, 15.0), 1.1), (10.0, 0, 0), (24, 20, 12)).reshape(12)
+    first = T.centred_matrix(T.affine_matrix((0, 0, -15.0), 0.9), (-10.0, 0, 0), T.fixed_centre((24, 20, 12))).reshape(12)
+    last = T.centred_matrix(T.affine_matrix((0, 0, 15.0), 1.1), (10.0, 0, 0), T.fixed_centre((24, 20, 12))).reshape(12)
     assert np.allclose(w["transforms"][0], first) and np.allclose(w["transforms"][-1], last)
 
 

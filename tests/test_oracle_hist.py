@@ -105,7 +105,7 @@ def test_random_affines_match_brute_force(seed):
     F, Mv = _vol(fixed, *fr), _vol(moving, *mr)
     for _ in range(25):
         A = T.affine_matrix(rng.uniform(-40, 40, 3), rng.uniform(0.7, 1.3, 3), rng.uniform(-0.2, 0.2, 3))
-        M = T.index_matrix(A, rng.uniform(-1.5, 1.5, 3), shape)
+        M = T.centred_matrix(A, rng.uniform(-1.5, 1.5, 3), T.fixed_centre(shape))
         for clamp in (False, True):
             h, n = oracle.hist_hard(F, Mv, M, 8, oracle.CLAMP if clamp else oracle.EXCLUDE)
             he, ne = bf.hist_exact(fixed, moving, M, 8, fr, mr, clamp=clamp)

@@ -35,7 +35,7 @@ def _case(seed=0, shape=(20, 18, 16), dtype=np.float32):
     rng = np.random.default_rng(seed)
     lab = inputs.render_labels(shape)
     f = inputs.intensities(lab, (20, 90, 160, 230), rng, 8.0, False, 0, 255, np.float64) / 255.0
-    truth = T.index_matrix(T.affine_matrix((4, -3, 6), 1.02), (1.2, -0.8, 0.5), shape)
+    truth = T.centred_matrix(T.affine_matrix((4, -3, 6), 1.02), (1.2, -0.8, 0.5), T.fixed_centre(shape))
     lab_m = inputs.render_labels(shape, inv_map=inputs.invert(truth))
     m = inputs.intensities(lab_m, (20, 90, 160, 230), rng, 8.0, False, 0, 255, np.float64) / 255.0
     return f.astype(dtype), m.astype(dtype), rng
@@ -103,20 +103,21 @@ def test_gradient_centred_params_chain_rule():
     f, m, rng = _case(seed=2, shape=(24, 24, 20))
     shape = f.shape[::-1]
     F, Mv = oracle.volume(f, 0.0, 1.0), oracle.volume(m, 0.0, 1.0)
-    J = T.index_jacobian(shape)
+    c = T.fixed_centre(shape)
+    J = T.centred_jacobian(c)
     A = T.affine_matrix((3, -2, 5), (1.01, 0.99, 1.0))
     t = np.array([0.7, -1.1, 0.4])
     p0 = T.params_from(A, t)
-    M0 = T.index_matrix(A, t, shape).reshape(12)
-    assert np.allclose(J @ p0 + T.index_matrix(np.zeros((3, 3)), np.zeros(3), shape).reshape(12), M0)
+    M0 = T.centred_matrix(A, t, c).reshape(12)
+    assert np.allclose(J @ p0 + T.centred_matrix(np.zeros((3, 3)), np.zeros(3), c).reshape(12), M0)
     mi, gM = oracle.parzen_grad(F, Mv, M0, 16, [1.0])
     gp = J.T @ gM[0, 0]
     for p, step in [(9, 1e-3), (10, 1e-3), (11, 1e-3), (0, 1e-4), (4, 1e-4), (1, 1e-4)]:
         pp, pm = p0.copy(), p0.copy()
         pp[p] += step
         pm[p] -= step
-        a, _ = oracle.eval_parzen(F, Mv, T.index_matrix(pp[:9], pp[9:], shape), 16, [1.0])
-        b, _ = oracle.eval_parzen(F, Mv, T.index_matrix(pm[:9], pm[9:], shape), 16, [1.0])
+        a, _ = oracle.eval_parzen(F, Mv, T.centred_matrix(pp[:9], pp[9:], c), 16, [1.0])
+        b, _ = oracle.eval_parzen(F, Mv, T.centred_matrix(pm[:9], pm[9:], c), 16, [1.0])
         fd = (a[0, 0] - b[0, 0]) / (2 * step)
         assert abs(gp[p] - fd) <= 1e-2 * np.abs(gp).max(), (p, gp[p], fd)
 

@@ -1,13 +1,14 @@
 """Host-side transform construction (Introduction / Methodology: the affine
 family of 12 degrees of freedom, applied about the fixed volume's centre;
 Fig. 1: the Transform block maps fixed voxels into the moving volume),
-checked on the CPU against the physical definition point by point and
-against closed forms.
+checked on the CPU against their definitions point by point and against
+closed forms.  (The composition of a physical matrix into voxel indices
+belongs to the metric; the oracle's is pinned in the oracle tests.)
 
-* The index-space matrix sends fixed voxel i to the moving index of the
-  same physical point: x = o_f + s_f i, y = A (x - c) + c + t,
-  m = (y - o_m) / s_m; the batch builder agrees with the single one, and
-  ``Geometry.matrices`` (the autograd path's linear map) with both.
+* The physical matrix of the centred parameterisation sends x to
+  A (x - c) + c + t; the batch builder agrees with the single one, the
+  torch builder of the autograd path with both, and the constant Jacobian
+  d P / d (A, t) with differences of the builder and with torch autograd.
 * Euler rotations are proper rotations; with no rotation and no shear the
   affine matrix is diag(scale).
 * The registration parameterisation (angles, log-scales, shears, t) round
@@ -20,43 +21,45 @@ import pytest
 from paper_1909_10690_amd import transforms as T
 
 
-def geometry(rng):
-    shape = tuple(int(v) for v in rng.integers(2, 40, 3))
-    return dict(fixed_shape_xyz=shape, fixed_spacing=rng.uniform(0.5, 2.0, 3), fixed_origin=rng.uniform(-50, 50, 3),
-                moving_spacing=rng.uniform(0.5, 2.0, 3), moving_origin=rng.uniform(-50, 50, 3))
-
-
-def test_index_matrix_follows_physical_points():
+def test_centred_matrix_follows_its_definition():
+    """P (x, 1) = A (x - c) + c + t for random points; batch = single."""
     rng = np.random.default_rng(11)
-    for _ in range(20):
-        g = geometry(rng)
-        A = T.affine_matrix(rng.uniform(-30, 30, 3), rng.uniform(0.8, 1.2, 3), rng.uniform(-0.1, 0.1, 3))
-        t = rng.uniform(-10, 10, 3)
-        M = T.index_matrix(A, t, **g)
-        n = np.asarray(g["fixed_shape_xyz"], dtype=np.float64)
-        c = g["fixed_origin"] + (n - 1) / 2 * g["fixed_spacing"]
+    A = np.stack([T.affine_matrix(rng.uniform(-30, 30, 3), rng.uniform(0.8, 1.2, 3), rng.uniform(-0.1, 0.1, 3))
+                  for _ in range(8)])
+    t = rng.uniform(-10, 10, (8, 3))
+    c = rng.uniform(-100, 100, 3)
+    Pb = T.centred_matrices(A, t, c).reshape(-1, 3, 4)
+    for k in range(8):
+        P = T.centred_matrix(A[k], t[k], c)
+        assert np.array_equal(P, Pb[k])
         for _ in range(10):
-            i = rng.integers(0, n).astype(np.float64)
-            x = g["fixed_origin"] + g["fixed_spacing"] * i
-            y = A @ (x - c) + c + t
-            m = (y - g["moving_origin"]) / g["moving_spacing"]
-            assert np.allclose(M[:, :3] @ i + M[:, 3], m, rtol=0, atol=1e-9)
+            x = rng.uniform(-200, 200, 3)
+            assert np.allclose(P[:, :3] @ x + P[:, 3], A[k] @ (x - c) + c + t[k], rtol=0, atol=1e-9)
 
 
-def test_batch_and_autograd_builders_agree():
+def test_centred_jacobian_and_torch_builder():
+    """The constant Jacobian d P / d (A, t) equals the difference of the
+    builder at unit parameter steps (P is affine in them); the torch builder
+    the autograd path uses equals the numpy one, and its autograd Jacobian
+    equals the constant one."""
     import torch
-    from paper_1909_10690_amd.autograd import Geometry
+    from paper_1909_10690_amd.autograd import centred_matrices
     rng = np.random.default_rng(12)
-    g = geometry(rng)
-    A = np.stack([T.affine_matrix(rng.uniform(-20, 20, 3), rng.uniform(0.9, 1.1, 3)) for _ in range(6)])
-    t = rng.uniform(-5, 5, (6, 3))
-    Mb = T.index_matrices(A, t, **g)
-    for k in range(6):
-        assert np.allclose(Mb[k], T.index_matrix(A[k], t[k], **g).reshape(12), rtol=0, atol=1e-12)
-    geo = Geometry(g["fixed_shape_xyz"], g["fixed_spacing"], g["fixed_origin"], g["moving_spacing"],
-                   g["moving_origin"], "cpu")
-    P = torch.as_tensor(np.concatenate([A.reshape(6, 9), t], axis=1))
-    assert np.allclose(geo.matrices(P).numpy(), Mb, rtol=0, atol=1e-9)
+    c = rng.uniform(-50, 50, 3)
+    J = T.centred_jacobian(c)
+    base = T.centred_matrix(np.zeros((3, 3)), np.zeros(3), c).reshape(12)
+    for p in range(12):
+        e = np.zeros(12)
+        e[p] = 1.0
+        assert np.allclose(T.centred_matrix(e[:9], e[9:], c).reshape(12) - base, J[:, p], rtol=0, atol=1e-12)
+    params = np.concatenate([np.stack([T.affine_matrix(rng.uniform(-20, 20, 3), rng.uniform(0.9, 1.1, 3))
+                                       for _ in range(5)]).reshape(5, 9), rng.uniform(-5, 5, (5, 3))], axis=1)
+    pt = torch.as_tensor(params)
+    assert np.allclose(centred_matrices(pt, c).numpy(), T.centred_matrices(params[:, :9], params[:, 9:], c),
+                       rtol=0, atol=1e-12)
+    Jt = torch.autograd.functional.jacobian(lambda v: centred_matrices(v.reshape(1, 12), c).reshape(12),
+                                            pt[0].clone())
+    assert np.allclose(Jt.numpy(), J, rtol=0, atol=1e-12)
 
 
 def test_rotations_and_plain_scale():

@@ -21,7 +21,8 @@ MI_TOL = 1e-12
 
 
 def _vol(nx, ny, nz, dtype=B.U16, lo=0.0, hi=4095.0):
-    return B.MiVolume(FAKE, nx, ny, nz, dtype, lo, hi)
+    one, zero = (ctypes.c_double * 3)(1.0, 1.0, 1.0), (ctypes.c_double * 3)(0.0, 0.0, 0.0)
+    return B.MiVolume(FAKE, nx, ny, nz, dtype, one, zero, lo, hi)
 
 
 def _noalloc(lib, f, m, n, bins, flags, hist=None):
