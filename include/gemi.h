@@ -253,7 +253,13 @@ typedef struct mi_pair {
 /* Hard-binned MI of many volume pairs of uneven sizes in one persistent
  * launch.  `pairs` is a HOST array; mi_out is device double[sum n][n_q],
  * pairs' rows concatenated in order.  Every pair uses `bins`, `q`, `flags`.
- * Workspace: mi_pairs_workspace_size(). */
+ * Workspace: mi_pairs_workspace_size().  Flags: boundary, Tsallis form,
+ * MI_USE_GRAPH, and MI_VOLUMES_UNCHANGED (the caller asserts that every
+ * pair's volumes, the bins and the workspace are those of the previous
+ * mi_eval_pairs call on this context and that no contents changed: the
+ * pairs' fixed bins and oct volumes in the workspace are reused; the
+ * transforms are always read afresh).  The launch shape is the one
+ * mi_tune_pairs chose for this class of pair set, if any. */
 int mi_pairs_workspace_size(const mi_pair *pairs, int32_t n_pairs, int32_t bins, int32_t n_q,
                             int32_t flags, size_t *bytes);
 int mi_eval_pairs(mi_context *ctx, const mi_pair *pairs, int32_t n_pairs, int32_t bins,
@@ -303,6 +309,25 @@ int mi_map_paths(mi_context *ctx, const double *values, int32_t nx, int32_t ny, 
 int mi_tune(mi_context *ctx, const mi_volume *fixed, const mi_volume *moving,
             const double *transforms, int32_t n_transforms, int32_t bins, int32_t flags,
             void *workspace, size_t workspace_bytes, void *stream);
+
+/* Autotuner of the persistent multi-pair sweep (mi_eval_pairs: the
+ * batched evaluation behind the Methodology's exhaustive per-family
+ * sweeps, over many volume pairs).
+ * Prepares the pairs once, then times the sweep for every candidate launch
+ * shape -- workgroup size 256/512/1024, about 64 K / 128 K / 256 K fixed
+ * voxels per slab (a work item sweeps one slab for one transform), u32 or
+ * packed 16-bit LDS counters (16-bit only with slabs of at most 65535
+ * voxels; forced above 128 bins) and slab-major or transform-major work
+ * items -- and keeps the fastest for this class of pair set (power-of-two
+ * buckets of the pair count, total fixed voxels and total transforms; bins;
+ * boundary; 8-bit corners) in the context, and in the MI_TUNE_CACHE file
+ * when that is set.  Results are unaffected (the sweep is exact whatever
+ * its shape).  Synchronous: waits for `stream`.  The workspace is the one
+ * mi_eval_pairs uses (mi_pairs_workspace_size(), any n_q); its contents are
+ * overwritten.  Flags: the boundary; MI_USE_GRAPH and MI_VOLUMES_UNCHANGED
+ * are refused (MI_ERR_FLAGS). */
+int mi_tune_pairs(mi_context *ctx, const mi_pair *pairs, int32_t n_pairs, int32_t bins, int32_t flags,
+                  void *workspace, size_t workspace_bytes, void *stream);
 
 /* Kernel timing.  While enabled, the library brackets every launch of its
  * histogram kernels with HIP events on the caller's stream.

@@ -55,7 +55,8 @@ class MiPair(ctypes.Structure):
 
 EXPORTS = ["mi_create", "mi_destroy", "mi_workspace_size", "mi_eval", "mi_eval_sampled", "mi_grad",
            "mi_pairs_workspace_size", "mi_eval_pairs", "mi_tune", "mi_timing_enable",
-           "mi_timing_read", "mi_probe_lds_atomics", "mi_map_paths", "mi_eval_noalloc", "mi_status_string"]
+           "mi_timing_read", "mi_probe_lds_atomics", "mi_map_paths", "mi_eval_noalloc", "mi_tune_pairs",
+           "mi_status_string"]
 
 _lib = None
 
@@ -83,6 +84,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.mi_pairs_workspace_size.argtypes = [P(MiPair), i32, i32, i32, i32, P(sz)]
     lib.mi_eval_pairs.argtypes = [vp, P(MiPair), i32, i32, dp, i32, i32, vp, vp, sz, vp]
     lib.mi_tune.argtypes = [vp, P(MiVolume), P(MiVolume), vp, i32, i32, i32, vp, sz, vp]
+    lib.mi_tune_pairs.argtypes = [vp, P(MiPair), i32, i32, i32, vp, sz, vp]
     lib.mi_timing_enable.argtypes = [vp, ctypes.c_int]
     lib.mi_timing_read.argtypes = [vp, ctypes.c_int, dp, P(ctypes.c_int64)]
     lib.mi_probe_lds_atomics.argtypes = [vp, vp, sz, vp, dp]
@@ -291,17 +293,10 @@ class Context:
         _check(st, "mi_grad")
         return mi, g
 
-    def eval_pairs(self, pairs, bins: int, q=(1.0,), flags: int = 0,
-                   workspace: torch.Tensor | None = None, stream=None):
-        """Hard MI of many (fixed, moving, transforms) pairs in one launch;
-        returns MI[sum n][n_q] with the pairs' rows concatenated."""
-        qs, qp = _qarr(q)
-        if not pairs:
-            return torch.zeros((0, len(qs)), dtype=torch.float64)
+    @staticmethod
+    def _pair_array(pairs):
         arr = (MiPair * len(pairs))()
-        total = 0
-        keep = []
-        dev = None
+        keep, total, dev = [], 0, None
         for i, (fv, mv, tr) in enumerate(pairs):
             tr = tr.to(device=fv.tensor.device, dtype=torch.float64).reshape(-1, 12).contiguous()
             keep.append(tr)
@@ -311,17 +306,44 @@ class Context:
             arr[i].transforms = tr.data_ptr()
             arr[i].n_transforms = tr.shape[0]
             total += tr.shape[0]
-        mi = torch.empty((total, len(qs)), dtype=torch.float64, device=dev)
+        return arr, keep, total, dev
+
+    def pairs_workspace_size(self, pairs, bins: int, n_q: int = 1, flags: int = 0) -> int:
+        arr, _keep, _, _ = self._pair_array(pairs)
+        nb = ctypes.c_size_t()
+        _check(self.lib.mi_pairs_workspace_size(arr, len(pairs), bins, n_q, flags, ctypes.byref(nb)),
+               "mi_pairs_workspace_size")
+        return nb.value
+
+    def eval_pairs(self, pairs, bins: int, q=(1.0,), flags: int = 0,
+                   workspace: torch.Tensor | None = None, stream=None, out=None):
+        """Hard MI of many (fixed, moving, transforms) pairs in one launch;
+        returns MI[sum n][n_q] with the pairs' rows concatenated (into
+        ``out`` if given)."""
+        qs, qp = _qarr(q)
+        if not pairs:
+            return torch.zeros((0, len(qs)), dtype=torch.float64)
+        arr, _keep, total, dev = self._pair_array(pairs)
+        mi = out if out is not None else torch.empty((total, len(qs)), dtype=torch.float64, device=dev)
         if workspace is None:
-            nb = ctypes.c_size_t()
-            _check(self.lib.mi_pairs_workspace_size(arr, len(pairs), bins, len(qs), flags,
-                                                    ctypes.byref(nb)), "mi_pairs_workspace_size")
-            workspace = self.workspace(nb.value)
+            workspace = self.workspace(self.pairs_workspace_size(pairs, bins, len(qs), flags))
         st = self.lib.mi_eval_pairs(self.handle, arr, len(pairs), bins, qp, len(qs), flags,
                                     _ptr(mi), _ptr(workspace), workspace.numel(),
                                     self._stream(stream))
         _check(st, "mi_eval_pairs")
         return mi
+
+    def tune_pairs(self, pairs, bins: int, flags: int = 0, workspace: torch.Tensor | None = None,
+                   stream=None) -> None:
+        """Autotunes the persistent multi-pair sweep's launch shape for this
+        class of pair set (synchronous; results are unaffected)."""
+        if not pairs:
+            return
+        arr, _keep, _, _ = self._pair_array(pairs)
+        if workspace is None:
+            workspace = self.workspace(self.pairs_workspace_size(pairs, bins, 1, flags))
+        _check(self.lib.mi_tune_pairs(self.handle, arr, len(pairs), bins, flags, _ptr(workspace),
+                                      workspace.numel(), self._stream(stream)), "mi_tune_pairs")
 
     def tune(self, fixed: Volume, moving: Volume, transforms: torch.Tensor, bins: int, flags: int = 0,
              workspace: torch.Tensor | None = None, stream=None) -> None:

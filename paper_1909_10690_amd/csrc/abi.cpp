@@ -232,6 +232,16 @@ struct HardTune {
 // histogram would not fit), chosen by the tuning otherwise.
 bool use_packed(const HardTune& t, int32_t bins) { return bins > 128 || t.packed == 1; }
 
+// Launch shape of the persistent multi-pair sweep: workgroup size, voxels
+// per slab (a work item sweeps one slab for one transform), LDS counter
+// layout and the order of a pair's work items.  Results do not depend on it.
+struct PairsTune {
+  int32_t block = 512;
+  int32_t slab_voxels = 131072;  // capped at 65535 with 16-bit counters
+  int32_t packed = -1;           // -1 by bins (packed above 128), 0 u32, 1 two 16-bit per word
+  int32_t transform_major = 0;
+};
+
 // Problem class of the tuning cache.
 struct TuneKey {
   int32_t v[11];
@@ -257,6 +267,8 @@ struct mi_context {
   std::mutex mu;
   std::vector<EventPair> events[kTimers];
   std::vector<std::pair<TuneKey, HardTune>> tuned;  // from mi_tune or the cache file
+  std::vector<std::pair<TuneKey, PairsTune>> pairs_tuned;  // from mi_tune_pairs or the cache file
+  std::vector<uint64_t> last_pairs_prep;  // pairs, bins and workspace of the last pairs preparation
   std::string tune_file;                            // MI_TUNE_CACHE, if set
   std::vector<GraphEntry> graphs;                   // MI_USE_GRAPH replays, oldest first
 };
@@ -520,12 +532,14 @@ struct PairsPlan {
   std::vector<int32_t> chunks;
   std::vector<int64_t> fchunk_base, mchunk_base, t_base, xcd_base;  // xcd_base: [8][P+1]
   int64_t total_t = 0;
-  bool oct8 = true;  // every moving range <= 256: 8-bit corners for all pairs
+  bool oct8 = true;    // every moving range <= 256: 8-bit corners for all pairs
+  bool packed = false;  // 16-bit LDS counters
 };
 
 int plan_pairs(const mi_pair* pairs, int32_t n_pairs, int32_t bins, int32_t n_q, int32_t flags,
-               PairsPlan& plan) {
-  if (flags & ~(MI_BOUNDARY_CLAMP | MI_TSALLIS_PSEUDOADDITIVE | MI_USE_GRAPH)) return MI_ERR_FLAGS;
+               PairsPlan& plan, const PairsTune& tune = PairsTune()) {
+  if (flags & ~(MI_BOUNDARY_CLAMP | MI_TSALLIS_PSEUDOADDITIVE | MI_USE_GRAPH | MI_VOLUMES_UNCHANGED))
+    return MI_ERR_FLAGS;
   if (n_pairs < 0 || n_pairs > (1 << 24)) return MI_ERR_COUNT;
   if (n_pairs > 0 && !pairs) return MI_ERR_NULL;
   if (bins < 2 || bins > 256) return MI_ERR_BINS;
@@ -538,7 +552,8 @@ int plan_pairs(const mi_pair* pairs, int32_t n_pairs, int32_t bins, int32_t n_q,
   plan.mchunk_base.assign(P + 1, 0);
   plan.t_base.assign(P + 1, 0);
   plan.xcd_base.assign(8 * (size_t)(P + 1), 0);
-  const bool packed = bins > 128;
+  const bool packed = bins > 128 || tune.packed == 1;
+  plan.packed = packed;
   for (int p = 0; p < P; ++p) {
     const mi_pair& pr = pairs[p];
     int st;
@@ -546,11 +561,12 @@ int plan_pairs(const mi_pair* pairs, int32_t n_pairs, int32_t bins, int32_t n_q,
     if ((st = check_moving(&pr.moving, true)) != MI_OK) return st;
     if (pr.n_transforms < 0) return MI_ERR_COUNT;
     if (pr.n_transforms > 0 && !pr.transforms) return MI_ERR_NULL;
-    // slabs of about 128 K voxels (at most 65535 with 16-bit counters),
-    // 8 or more, a multiple of 8
+    // slabs of about tune.slab_voxels voxels (at most 65535 with 16-bit
+    // counters), 8 or more, a multiple of 8
     const int64_t groups = (int64_t)((pr.fixed.ny + 3) / 4) * pr.fixed.nz;
     const int64_t gvox = 4 * (int64_t)pr.fixed.nx;
-    int64_t per = (packed ? 65535 : 131072) / gvox;
+    const int64_t target = packed ? std::min<int64_t>(65535, tune.slab_voxels) : tune.slab_voxels;
+    int64_t per = target / gvox;
     if (per < 1) per = 1;
     int64_t c = (groups + per - 1) / per;
     if (c < 8) c = 8;
@@ -628,6 +644,8 @@ HardTune tune_for(const mi_context* ctx, const mi_volume* f, const mi_volume* m,
 
 // Cache file: one problem class per line,
 //   gemi-tune fnx fny fnz mnx mny mnz mdtype bins clamp nbucket oct8 block slab_major chunks packed
+//   gemi-tune-pairs pairs voxels transforms bins clamp oct8 block slab_voxels packed transform_major
+// (the pairs' counts are power-of-two buckets).
 void load_tune_file(mi_context* c) {
   std::ifstream in(c->tune_file);
   std::string line;
@@ -636,7 +654,21 @@ void load_tune_file(mi_context* c) {
     std::string tag;
     TuneKey k;
     HardTune t;
-    if (!(ss >> tag) || tag != "gemi-tune") continue;
+    if (!(ss >> tag)) continue;
+    if (tag == "gemi-tune-pairs") {
+      memset(k.v, 0, sizeof k.v);
+      k.v[0] = -1;
+      PairsTune pt;
+      bool ok = true;
+      for (int i = 1; i < 7 && ok; ++i) ok = static_cast<bool>(ss >> k.v[i]);
+      ok = ok && (ss >> pt.block >> pt.slab_voxels >> pt.packed >> pt.transform_major);
+      if (ok && (pt.block == 256 || pt.block == 512 || pt.block == 1024) && pt.slab_voxels >= 4096 &&
+          pt.slab_voxels <= (1 << 22) && pt.packed >= -1 && pt.packed <= 1 &&
+          (pt.transform_major == 0 || pt.transform_major == 1))
+        c->pairs_tuned.emplace_back(k, pt);
+      continue;
+    }
+    if (tag != "gemi-tune") continue;
     bool ok = true;
     for (int i = 0; i < 11 && ok; ++i) ok = static_cast<bool>(ss >> k.v[i]);
     ok = ok && (ss >> t.block >> t.slab_major >> t.chunks >> t.packed);
@@ -655,6 +687,12 @@ void save_tune_file(const mi_context* c) {
     for (int i = 0; i < 11; ++i) out << ' ' << e.first.v[i];
     out << ' ' << e.second.block << ' ' << e.second.slab_major << ' ' << e.second.chunks << ' '
         << e.second.packed << '\n';
+  }
+  for (const auto& e : c->pairs_tuned) {
+    out << "gemi-tune-pairs";
+    for (int i = 1; i < 7; ++i) out << ' ' << e.first.v[i];
+    out << ' ' << e.second.block << ' ' << e.second.slab_voxels << ' ' << e.second.packed << ' '
+        << e.second.transform_major << '\n';
   }
 }
 
@@ -813,6 +851,187 @@ int run_hard(mi_context* ctx, const mi_volume* fixed, const mi_volume* moving,
   return MI_OK;
 }
 
+
+// ---- the multi-pair path -----------------------------------------------------
+
+// Problem class of a pair set for the tuning cache: pair count, total fixed
+// voxels and total transforms (power-of-two buckets), bins, boundary, corner
+// layout.
+TuneKey pairs_tune_key(const mi_pair* pairs, int32_t n_pairs, int32_t bins, int32_t flags) {
+  int64_t vox = 0, nt = 0;
+  bool oct8 = true;
+  for (int p = 0; p < n_pairs; ++p) {
+    vox += (int64_t)voxels(&pairs[p].fixed);
+    nt += pairs[p].n_transforms;
+    oct8 = oct8 && oct8_range(pairs[p].moving.lo, pairs[p].moving.hi);
+  }
+  auto bucket = [](int64_t v) {
+    int32_t b = 0;
+    while ((1ll << b) < v && b < 62) ++b;
+    return b;
+  };
+  TuneKey k;
+  memset(k.v, 0, sizeof k.v);
+  const int32_t v[7] = {-1, bucket(n_pairs), bucket(vox), bucket(nt), bins, (flags & MI_BOUNDARY_CLAMP) ? 1 : 0,
+                        oct8 ? 1 : 0};
+  memcpy(k.v, v, sizeof v);
+  return k;
+}
+
+PairsTune pairs_tune_for(const mi_context* ctx, const mi_pair* pairs, int32_t n_pairs, int32_t bins,
+                         int32_t flags) {
+  const TuneKey k = pairs_tune_key(pairs, n_pairs, bins, flags);
+  for (const auto& e : ctx->pairs_tuned)
+    if (e.first == k) return e.second;
+  return PairsTune();
+}
+
+// Key of a pairs preparation: every pair's volumes, bins, workspace, layout.
+std::vector<uint64_t> pairs_prep_key(const mi_pair* pairs, int32_t n_pairs, int32_t bins, const void* ws,
+                                     bool oct8) {
+  std::vector<uint64_t> k = {(uint64_t)n_pairs, (uint64_t)bins, (uint64_t)(uintptr_t)ws, oct8 ? 1u : 0u};
+  for (int p = 0; p < n_pairs; ++p)
+    for (const mi_volume* v : {&pairs[p].fixed, &pairs[p].moving}) {
+      uint64_t lo, hi;
+      memcpy(&lo, &v->lo, 8);
+      memcpy(&hi, &v->hi, 8);
+      k.insert(k.end(), {(uint64_t)(uintptr_t)v->data, (uint64_t)v->nx, (uint64_t)v->ny, (uint64_t)v->nz,
+                         (uint64_t)v->dtype, lo, hi});
+    }
+  return k;
+}
+
+// One multi-pair evaluation: descriptor and prefix tables uploaded, the
+// transforms gathered and composed, the pairs prepared (fixed bins, oct
+// volumes) when `prepare`, the persistent sweep, and (unless `sweep_only`)
+// the MI reduction.
+int run_pairs(mi_context* ctx, const mi_pair* pairs, int32_t n_pairs, int32_t bins, const double* q,
+              int32_t n_q, int32_t flags, double* mi_out, char* ws, hipStream_t s, const PairsPlan& plan,
+              const PairsTune& tune, bool prepare, bool sweep_only = false) {
+  hipError_t e;
+  // device tables: descriptors, row / transform / per-XCD item prefixes
+  const int P = n_pairs;
+  std::vector<PairDesc> desc_v(P);
+  for (int p = 0; p < P; ++p) {
+    const mi_pair& pr = pairs[p];
+    PairDesc& d = desc_v[p];
+    memset(&d, 0, sizeof d);
+    d.fixed = pr.fixed.data;
+    d.moving = pr.moving.data;
+    d.transforms = pr.transforms;
+    d.geo = geometry(&pr.fixed, &pr.moving);
+    d.geom = make_hard_geom(desc(&pr.fixed), desc(&pr.moving), (const uint8_t*)(ws + plan.fbins[p]),
+                            (const void*)(ws + plan.octs[p]), bins);
+    // one layout for every pair of the launch
+    d.geom.oct8 = plan.oct8 ? 1 : 0;
+    d.geom.oct_bytes = (uint32_t)(plan.oct8 ? oct8_volume_bytes(pr.moving.nx, pr.moving.ny, pr.moving.nz)
+                                            : oct_volume_bytes(pr.moving.nx, pr.moving.ny, pr.moving.nz));
+    d.fdtype = pr.fixed.dtype;
+    d.mdtype = pr.moving.dtype;
+    d.flo = pr.fixed.lo;
+    d.fhi = pr.fixed.hi;
+    d.mlo = (int32_t)pr.moving.lo;
+    d.mhi = (int32_t)pr.moving.hi;
+    if (pr.fixed.dtype != MI_F32) d.fdiv = make_divider((uint32_t)(pr.fixed.hi - pr.fixed.lo + 1.0));
+    d.n_t = pr.n_transforms;
+    d.chunks = plan.chunks[p];
+  }
+  std::vector<char> blob(plan.table_bytes, 0);
+  char* b = blob.data();
+  memcpy(b + plan.off_desc, desc_v.data(), sizeof(PairDesc) * P);
+  memcpy(b + plan.off_frow, plan.fchunk_base.data(), 8 * (P + 1));
+  memcpy(b + plan.off_mrow, plan.mchunk_base.data(), 8 * (P + 1));
+  memcpy(b + plan.off_tbase, plan.t_base.data(), 8 * (P + 1));
+  memcpy(b + plan.off_xcd, plan.xcd_base.data(), 8 * 8 * (P + 1));
+  char* dtab = ws + plan.tables;
+  if (plan.table_bytes <= kStageBytes) {
+    if (ctx->stage_pending && (e = hipEventSynchronize(ctx->stage_done)) != hipSuccess)
+      return hip_fail(e, "staging");
+    memcpy(ctx->stage, b, plan.table_bytes);
+    if ((e = hipMemcpyAsync(dtab, ctx->stage, plan.table_bytes, hipMemcpyHostToDevice, s)) != hipSuccess)
+      return hip_fail(e, "table upload");
+    if ((e = hipEventRecord(ctx->stage_done, s)) != hipSuccess) return hip_fail(e, "staging");
+    ctx->stage_pending = true;
+  } else {
+    // tables beyond the staging buffer: wait for earlier users of the
+    // workspace, then copy synchronously from pageable memory
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "table upload");
+    if ((e = hipMemcpy(dtab, b, plan.table_bytes, hipMemcpyHostToDevice)) != hipSuccess)
+      return hip_fail(e, "table upload");
+  }
+
+  PairsLaunch L;
+  memset(&L, 0, sizeof L);
+  PairsArgs& a = L.args;
+  a.pairs = (const PairDesc*)(dtab + plan.off_desc);
+  a.n_pairs = P;
+  a.fchunk_base = (const int64_t*)(dtab + plan.off_frow);
+  a.mchunk_base = (const int64_t*)(dtab + plan.off_mrow);
+  a.t_base = (const int64_t*)(dtab + plan.off_tbase);
+  a.xcd_base = (const int64_t*)(dtab + plan.off_xcd);
+  a.counters = (unsigned long long*)(ws + plan.counters);
+  a.transforms = (double*)(ws + plan.transforms);
+  a.hist = (uint32_t*)(ws + plan.hist);
+  a.bins = bins;
+  a.transform_major = tune.transform_major;
+  L.total_t = plan.total_t;
+  L.fixed_chunks = plan.fchunk_base[P];
+  L.moving_chunks = plan.mchunk_base[P];
+  L.clamp = (flags & MI_BOUNDARY_CLAMP) ? 1 : 0;
+  L.packed = plan.packed ? 1 : 0;
+  L.oct8 = plan.oct8 ? 1 : 0;
+  L.cu_count = ctx->cu_count;
+  L.block = tune.block;
+  const size_t bb = (size_t)bins * bins;
+  auto body = [&]() -> int {
+    hipError_t err;
+    if ((err = launch_fill_u32((uint32_t*)a.counters, 16, 0u, s)) != hipSuccess) return hip_fail(err, "fill");
+    if ((err = launch_fill_u32(a.hist, bb * plan.total_t, 0u, s)) != hipSuccess) return hip_fail(err, "fill");
+    if ((err = launch_pairs_prep(L, s, prepare)) != hipSuccess) return hip_fail(err, "pairs prep");
+    {
+      TimedLaunch tl(ctx, 3, s);
+      if ((err = launch_pairs_hist(L, s)) != hipSuccess) return hip_fail(err, "pairs hist");
+      tl.done();
+    }
+    if (sweep_only) return MI_OK;
+    ReduceLaunch R;
+    memset(&R, 0, sizeof R);
+    R.hist = a.hist;
+    R.count = (uint64_t*)(ws + plan.count);
+    R.part = (double*)(ws + plan.part);
+    R.transforms = a.transforms;
+    R.n = (int32_t)plan.total_t;
+    R.bins = bins;
+    R.q = qlist(q, n_q, flags);
+    R.mi_out = mi_out;
+    TimedLaunch tr(ctx, 4, s);
+    if ((err = launch_mi_reduce(R, s)) != hipSuccess) return hip_fail(err, "mi_reduce");
+    tr.done();
+    return MI_OK;
+  };
+  if (sweep_only || !use_graph(ctx, flags, s)) return body();
+  // the graph holds the launch shape and whether it prepares
+  std::vector<uint64_t> key = {3,
+                               (uint64_t)P,
+                               (uint64_t)bins,
+                               (uint64_t)flags,
+                               (uint64_t)(uintptr_t)mi_out,
+                               (uint64_t)(uintptr_t)ws,
+                               (uint64_t)(uintptr_t)s,
+                               prepare ? 1u : 0u,
+                               (uint64_t)tune.block,
+                               (uint64_t)tune.slab_voxels,
+                               (uint64_t)(tune.packed + 1),
+                               (uint64_t)tune.transform_major};
+  key_q(key, q, n_q);
+  for (int p = 0; p < P; ++p) {
+    key_volume(key, &pairs[p].fixed);
+    key_volume(key, &pairs[p].moving);
+    key.push_back((uint64_t)(uintptr_t)pairs[p].transforms);
+    key.push_back((uint64_t)pairs[p].n_transforms);
+  }
+  return graph_run(ctx, key, s, body);
+}
 }  // namespace
 
 extern "C" {
@@ -1235,121 +1454,101 @@ int mi_eval_pairs(mi_context* ctx, const mi_pair* pairs, int32_t n_pairs, int32_
   if (!workspace || workspace_bytes < plan.total) return MI_ERR_WORKSPACE;
   if (!ctx) return MI_ERR_NULL;
   if (plan.total_t == 0) return MI_OK;
-  hipStream_t s = (hipStream_t)stream;
   hipError_t e;
   if ((e = hipSetDevice(ctx->device)) != hipSuccess) return hip_fail(e, "hipSetDevice");
-  char* ws = (char*)workspace;
+  const PairsTune tune = pairs_tune_for(ctx, pairs, n_pairs, bins, flags);
+  if ((st = plan_pairs(pairs, n_pairs, bins, n_q, flags, plan, tune)) != MI_OK) return st;
+  // the pairs' preparation (fixed bins, oct volumes) is kept in the
+  // workspace and reused when the caller asserts unchanged volumes
+  std::vector<uint64_t> pkey = pairs_prep_key(pairs, n_pairs, bins, workspace, plan.oct8);
+  const bool prepare = !((flags & MI_VOLUMES_UNCHANGED) && pkey == ctx->last_pairs_prep);
   ctx->last_prep.clear();  // the pairs' layout overwrites any single-pair preparation
+  st = run_pairs(ctx, pairs, n_pairs, bins, q, n_q, flags, mi_out, (char*)workspace, (hipStream_t)stream, plan,
+                 tune, prepare);
+  ctx->last_pairs_prep = st == MI_OK ? pkey : std::vector<uint64_t>();
+  return st;
+}
 
-  // device tables: descriptors, row / transform / per-XCD item prefixes
-  const int P = n_pairs;
-  std::vector<PairDesc> desc_v(P);
-  for (int p = 0; p < P; ++p) {
-    const mi_pair& pr = pairs[p];
-    PairDesc& d = desc_v[p];
-    memset(&d, 0, sizeof d);
-    d.fixed = pr.fixed.data;
-    d.moving = pr.moving.data;
-    d.transforms = pr.transforms;
-    d.geo = geometry(&pr.fixed, &pr.moving);
-    d.geom = make_hard_geom(desc(&pr.fixed), desc(&pr.moving), (const uint8_t*)(ws + plan.fbins[p]),
-                            (const void*)(ws + plan.octs[p]), bins);
-    // one layout for every pair of the launch
-    d.geom.oct8 = plan.oct8 ? 1 : 0;
-    d.geom.oct_bytes = (uint32_t)(plan.oct8 ? oct8_volume_bytes(pr.moving.nx, pr.moving.ny, pr.moving.nz)
-                                            : oct_volume_bytes(pr.moving.nx, pr.moving.ny, pr.moving.nz));
-    d.fdtype = pr.fixed.dtype;
-    d.mdtype = pr.moving.dtype;
-    d.flo = pr.fixed.lo;
-    d.fhi = pr.fixed.hi;
-    d.mlo = (int32_t)pr.moving.lo;
-    d.mhi = (int32_t)pr.moving.hi;
-    if (pr.fixed.dtype != MI_F32) d.fdiv = make_divider((uint32_t)(pr.fixed.hi - pr.fixed.lo + 1.0));
-    d.n_t = pr.n_transforms;
-    d.chunks = plan.chunks[p];
+int mi_tune_pairs(mi_context* ctx, const mi_pair* pairs, int32_t n_pairs, int32_t bins, int32_t flags,
+                  void* workspace, size_t workspace_bytes, void* stream) {
+  if (flags & (MI_USE_GRAPH | MI_VOLUMES_UNCHANGED)) return MI_ERR_FLAGS;
+  PairsPlan plan;
+  int st = plan_pairs(pairs, n_pairs, bins, 1, flags, plan);
+  if (st != MI_OK) return st;
+  if (!workspace || workspace_bytes < plan.total) return MI_ERR_WORKSPACE;
+  if (!ctx) return MI_ERR_NULL;
+  if (plan.total_t == 0) return MI_OK;
+  hipError_t e;
+  if ((e = hipSetDevice(ctx->device)) != hipSuccess) return hip_fail(e, "hipSetDevice");
+  hipStream_t s = (hipStream_t)stream;
+  char* ws = (char*)workspace;
+  const bool was_timing = ctx->timing;
+  ctx->timing = false;
+  hipEvent_t t0 = nullptr, t1 = nullptr;
+  if ((e = hipEventCreate(&t0)) != hipSuccess || (e = hipEventCreate(&t1)) != hipSuccess) {
+    if (t0) (void)hipEventDestroy(t0);
+    ctx->timing = was_timing;
+    return hip_fail(e, "tune events");
   }
-  std::vector<char> blob(plan.table_bytes, 0);
-  char* b = blob.data();
-  memcpy(b + plan.off_desc, desc_v.data(), sizeof(PairDesc) * P);
-  memcpy(b + plan.off_frow, plan.fchunk_base.data(), 8 * (P + 1));
-  memcpy(b + plan.off_mrow, plan.mchunk_base.data(), 8 * (P + 1));
-  memcpy(b + plan.off_tbase, plan.t_base.data(), 8 * (P + 1));
-  memcpy(b + plan.off_xcd, plan.xcd_base.data(), 8 * 8 * (P + 1));
-  char* dtab = ws + plan.tables;
-  if (plan.table_bytes <= kStageBytes) {
-    if (ctx->stage_pending && (e = hipEventSynchronize(ctx->stage_done)) != hipSuccess)
-      return hip_fail(e, "staging");
-    memcpy(ctx->stage, b, plan.table_bytes);
-    if ((e = hipMemcpyAsync(dtab, ctx->stage, plan.table_bytes, hipMemcpyHostToDevice, s)) != hipSuccess)
-      return hip_fail(e, "table upload");
-    if ((e = hipEventRecord(ctx->stage_done, s)) != hipSuccess) return hip_fail(e, "staging");
-    ctx->stage_pending = true;
-  } else {
-    // tables beyond the staging buffer: wait for earlier users of the
-    // workspace, then copy synchronously from pageable memory
-    if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "table upload");
-    if ((e = hipMemcpy(dtab, b, plan.table_bytes, hipMemcpyHostToDevice)) != hipSuccess)
-      return hip_fail(e, "table upload");
-  }
-
-  PairsLaunch L;
-  memset(&L, 0, sizeof L);
-  PairsArgs& a = L.args;
-  a.pairs = (const PairDesc*)(dtab + plan.off_desc);
-  a.n_pairs = P;
-  a.fchunk_base = (const int64_t*)(dtab + plan.off_frow);
-  a.mchunk_base = (const int64_t*)(dtab + plan.off_mrow);
-  a.t_base = (const int64_t*)(dtab + plan.off_tbase);
-  a.xcd_base = (const int64_t*)(dtab + plan.off_xcd);
-  a.counters = (unsigned long long*)(ws + plan.counters);
-  a.transforms = (double*)(ws + plan.transforms);
-  a.hist = (uint32_t*)(ws + plan.hist);
-  a.bins = bins;
-  L.total_t = plan.total_t;
-  L.fixed_chunks = plan.fchunk_base[P];
-  L.moving_chunks = plan.mchunk_base[P];
-  L.clamp = (flags & MI_BOUNDARY_CLAMP) ? 1 : 0;
-  L.packed = bins > 128 ? 1 : 0;
-  L.oct8 = plan.oct8 ? 1 : 0;
-  L.cu_count = ctx->cu_count;
-  const size_t bb = (size_t)bins * bins;
-  auto body = [&]() -> int {
-    hipError_t err;
-    if ((err = launch_fill_u32((uint32_t*)a.counters, 16, 0u, s)) != hipSuccess) return hip_fail(err, "fill");
-    if ((err = launch_fill_u32(a.hist, bb * plan.total_t, 0u, s)) != hipSuccess) return hip_fail(err, "fill");
-    if ((err = launch_pairs_prep(L, s)) != hipSuccess) return hip_fail(err, "pairs prep");
-    {
-      TimedLaunch tl(ctx, 3, s);
-      if ((err = launch_pairs_hist(L, s)) != hipSuccess) return hip_fail(err, "pairs hist");
-      tl.done();
+  // the preparation once (it does not depend on the launch shape), then
+  // each candidate's sweep timed over three runs after a warm-up run
+  const double one = 1.0;
+  PairsTune best;
+  float best_ms = 3.4e38f;
+  std::vector<PairsTune> cands;
+  const int32_t layouts[2] = {bins > 128 ? 1 : 0, 1};
+  for (int li = 0; li < (bins > 128 ? 1 : 2); ++li)
+    for (int32_t block : {256, 512, 1024})
+      for (int32_t vox : {65536, 131072, 262144})
+        for (int32_t order : {0, 1}) {
+          PairsTune c;
+          c.block = block;
+          c.slab_voxels = vox;
+          c.packed = layouts[li];
+          c.transform_major = order;
+          if (c.packed == 1 && vox > 65536) continue;  // 16-bit counters: at most 65535 voxels per slab
+          cands.push_back(c);
+        }
+  bool prepared = false;
+  for (const PairsTune& c : cands) {
+    if (st != MI_OK) break;
+    PairsPlan cp;
+    if ((st = plan_pairs(pairs, n_pairs, bins, 1, flags, cp, c)) != MI_OK) break;
+    float total = 0;
+    for (int rep = 0; rep < 4 && st == MI_OK; ++rep) {
+      if ((e = hipEventRecord(t0, s)) != hipSuccess) { st = hip_fail(e, "tune"); break; }
+      st = run_pairs(ctx, pairs, n_pairs, bins, &one, 1, flags, nullptr, ws, s, cp, c, !prepared, true);
+      prepared = true;
+      if (st != MI_OK) break;
+      if ((e = hipEventRecord(t1, s)) != hipSuccess || (e = hipEventSynchronize(t1)) != hipSuccess) {
+        st = hip_fail(e, "tune");
+        break;
+      }
+      float ms = 0;
+      (void)hipEventElapsedTime(&ms, t0, t1);
+      if (rep > 0) total += ms;
     }
-    ReduceLaunch R;
-    memset(&R, 0, sizeof R);
-    R.hist = a.hist;
-    R.count = (uint64_t*)(ws + plan.count);
-    R.part = (double*)(ws + plan.part);
-    R.transforms = a.transforms;
-    R.n = (int32_t)plan.total_t;
-    R.bins = bins;
-    R.q = qlist(q, n_q, flags);
-    R.mi_out = mi_out;
-    TimedLaunch tr(ctx, 4, s);
-    if ((err = launch_mi_reduce(R, s)) != hipSuccess) return hip_fail(err, "mi_reduce");
-    tr.done();
-    return MI_OK;
-  };
-  if (!use_graph(ctx, flags, s)) return body();
-  std::vector<uint64_t> key = {3, (uint64_t)P, (uint64_t)bins, (uint64_t)flags,
-                               (uint64_t)(uintptr_t)mi_out, (uint64_t)(uintptr_t)workspace,
-                               (uint64_t)(uintptr_t)s};
-  key_q(key, q, n_q);
-  for (int p = 0; p < P; ++p) {
-    key_volume(key, &pairs[p].fixed);
-    key_volume(key, &pairs[p].moving);
-    key.push_back((uint64_t)(uintptr_t)pairs[p].transforms);
-    key.push_back((uint64_t)pairs[p].n_transforms);
+    if (st == MI_OK && total < best_ms) {
+      best_ms = total;
+      best = c;
+    }
   }
-  return graph_run(ctx, key, s, body);
+  (void)hipEventDestroy(t0);
+  (void)hipEventDestroy(t1);
+  ctx->timing = was_timing;
+  ctx->last_prep.clear();
+  ctx->last_pairs_prep.clear();
+  if (st != MI_OK) return st;
+  const TuneKey k = pairs_tune_key(pairs, n_pairs, bins, flags);
+  bool found = false;
+  for (auto& entry : ctx->pairs_tuned)
+    if (entry.first == k) {
+      entry.second = best;
+      found = true;
+    }
+  if (!found) ctx->pairs_tuned.emplace_back(k, best);
+  save_tune_file(ctx);
+  return MI_OK;
 }
 
 int mi_probe_lds_atomics(mi_context* ctx, void* scratch, size_t scratch_bytes, void* stream,

@@ -482,16 +482,20 @@ struct PairsArgs {
   double* transforms;        // [T][12], gathered and composed to index space
   uint32_t* hist;            // [T][B][B]
   int32_t bins;
+  int32_t transform_major;   // work-item order within a pair: 0 slab-major, 1 transform-major
 };
 
 struct PairsLaunch {
   PairsArgs args;
   int64_t total_t, fixed_chunks, moving_chunks;
   int32_t clamp, packed, cu_count;
+  int32_t block;  // threads per workgroup of the sweep: 256, 512 or 1024
   int32_t oct8;  // every pair's moving volume packed with 8-bit corners
 };
 
-hipError_t launch_pairs_prep(const PairsLaunch& L, hipStream_t s);
+// The transforms gathered and composed; with `volumes` also the pairs'
+// fixed bins and oct volumes.
+hipError_t launch_pairs_prep(const PairsLaunch& L, hipStream_t s, bool volumes = true);
 hipError_t launch_pairs_hist(const PairsLaunch& L, hipStream_t s);
 HardGeom make_hard_geom(const VolumeDesc& fixed, const VolumeDesc& moving, const uint8_t* fbins,
                         const void* octs, int32_t bins);

@@ -291,7 +291,17 @@ __global__ __launch_bounds__(NT) void hist_pairs_kernel(PairsArgs a) {
       t0 = uniform(a.t_base[p]);
     }
     const int64_t rem = item - p_lo;
-    const int64_t slab = rem / n_t, tl = rem - slab * n_t;
+    // slab-major items: one slab's transforms in a row (the slab's moving
+    // footprint stays in L2); transform-major: a transform's slabs in a row
+    int64_t slab, tl;
+    if (a.transform_major) {
+      const int64_t per = chunks >> 3;
+      tl = rem / per;
+      slab = rem - tl * per;
+    } else {
+      slab = rem / n_t;
+      tl = rem - slab * n_t;
+    }
     const uint32_t chunk = xcd * (uint32_t)(chunks >> 3) + (uint32_t)slab;
     const int64_t t = t0 + tl;
     int64_t Mq[12];
@@ -310,12 +320,13 @@ static unsigned row_grid(int64_t rows) {
   return (unsigned)(g < 4096 ? (g > 0 ? g : 1) : 4096);
 }
 
-hipError_t launch_pairs_prep(const PairsLaunch& L, hipStream_t s) {
+hipError_t launch_pairs_prep(const PairsLaunch& L, hipStream_t s, bool volumes) {
   if (L.total_t > 0) {
     const int64_t blocks = (L.total_t + 255) / 256;
     hipLaunchKernelGGL(gather_transforms_kernel, dim3((unsigned)(blocks < 4096 ? blocks : 4096)),
                        dim3(256), 0, s, L.args, L.total_t);
   }
+  if (!volumes) return hipGetLastError();
   if (L.fixed_chunks > 0)
     hipLaunchKernelGGL(prep_fixed_kernel, dim3(row_grid(L.fixed_chunks)), dim3(256), 0, s, L.args,
                        L.fixed_chunks);
@@ -325,34 +336,40 @@ hipError_t launch_pairs_prep(const PairsLaunch& L, hipStream_t s) {
   return hipGetLastError();
 }
 
-constexpr int kPairsBlock = 512;
 // Dynamic LDS limit of the pairs sweep (a u32 table up to 128 bins, 16-bit
 // pairs above), leaving room for its static work-item slot.
 constexpr size_t kPairsLdsMax = 150 * 1024;
 
-template <bool CLAMP, bool PACKED, bool OCT8>
+template <bool CLAMP, bool PACKED, bool OCT8, int NT>
 static hipError_t pairs_variant(const PairsLaunch& L, hipStream_t s) {
   const int B = L.args.bins;
   const size_t lds = PACKED ? (((size_t)B * B + 1) / 2) * 4 : (size_t)B * B * 4;
-  const void* fn = (const void*)hist_pairs_kernel<CLAMP, PACKED, OCT8, kPairsBlock>;
+  const void* fn = (const void*)hist_pairs_kernel<CLAMP, PACKED, OCT8, NT>;
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kPairsLdsMax);
   if (e != hipSuccess || (e = lds_guard(fn, lds, kPairsLdsMax)) != hipSuccess) return e;
   int per_cu = 0;
-  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kPairsBlock, lds);
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, NT, lds);
   if (e != hipSuccess) return e;
   if (per_cu < 1) per_cu = 1;
   // every queue needs workgroups: a multiple of 8 (one share per XCD)
   const unsigned grid = (unsigned)(((per_cu * L.cu_count + 7) / 8) * 8);
-  hipLaunchKernelGGL((hist_pairs_kernel<CLAMP, PACKED, OCT8, kPairsBlock>), dim3(grid), dim3(kPairsBlock),
-                     lds, s, L.args);
+  hipLaunchKernelGGL((hist_pairs_kernel<CLAMP, PACKED, OCT8, NT>), dim3(grid), dim3(NT), lds, s, L.args);
   return hipGetLastError();
+}
+
+template <bool CLAMP, bool PACKED, bool OCT8>
+static hipError_t pairs_block(const PairsLaunch& L, hipStream_t s) {
+  switch (L.block) {
+  case 256: return pairs_variant<CLAMP, PACKED, OCT8, 256>(L, s);
+  case 1024: return pairs_variant<CLAMP, PACKED, OCT8, 1024>(L, s);
+  default: return pairs_variant<CLAMP, PACKED, OCT8, 512>(L, s);
+  }
 }
 
 template <bool OCT8>
 static hipError_t pairs_layout(const PairsLaunch& L, hipStream_t s) {
-  if (L.clamp)
-    return L.packed ? pairs_variant<true, true, OCT8>(L, s) : pairs_variant<true, false, OCT8>(L, s);
-  return L.packed ? pairs_variant<false, true, OCT8>(L, s) : pairs_variant<false, false, OCT8>(L, s);
+  if (L.clamp) return L.packed ? pairs_block<true, true, OCT8>(L, s) : pairs_block<true, false, OCT8>(L, s);
+  return L.packed ? pairs_block<false, true, OCT8>(L, s) : pairs_block<false, false, OCT8>(L, s);
 }
 
 hipError_t launch_pairs_hist(const PairsLaunch& L, hipStream_t s) {

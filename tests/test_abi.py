@@ -340,3 +340,17 @@ def test_registration_checkpoint_roundtrip(tmp_path):
     r = RegState.load(str(p))
     assert r.params == s.params and r.step == 7 and r.m == s.m and r.v == s.v
     assert [tuple(h) if not isinstance(h, tuple) else h for h in r.history][0][0] == 1
+
+
+def test_tune_pairs_validation():
+    lib = B.load()
+    p1 = B.MiPair(vol(8, 8, 8), vol(9, 8, 7), FAKE, 3)
+    arr = (B.MiPair * 1)(p1)
+    ok = lib.mi_tune_pairs(None, arr, 1, 32, 0, FAKE, 1 << 40, None)
+    assert ok == B.MI_ERR_NULL  # valid: reaches the context check
+    assert lib.mi_tune_pairs(None, arr, 1, 32, B.USE_GRAPH, FAKE, 1 << 40, None) == B.MI_ERR_FLAGS
+    assert lib.mi_tune_pairs(None, arr, 1, 32, B.VOLUMES_UNCHANGED, FAKE, 1 << 40, None) == B.MI_ERR_FLAGS
+    assert lib.mi_tune_pairs(None, arr, 1, 300, 0, FAKE, 1 << 40, None) == B.MI_ERR_BINS
+    assert lib.mi_tune_pairs(None, arr, 1, 32, 0, None, 1 << 40, None) == B.MI_ERR_WORKSPACE
+    # mi_eval_pairs takes MI_VOLUMES_UNCHANGED
+    assert pairs_ws([p1], flags=B.VOLUMES_UNCHANGED)[0] == 0

@@ -205,3 +205,85 @@ def test_preparation_reuse_with_graphs(ctx):
            ("B", fl | U, True), ("A", fl | U, False)]
     for name, flags, graph in seq:
         call(name, flags, graph)
+
+
+def _pairs(seed, n=5, bins_dtype=np.uint8):
+    import torch
+    from paper_1909_10690_amd import binding as B
+    rng = np.random.default_rng(seed)
+    pairs = []
+    for k in range(n):
+        shape = tuple(int(e) for e in rng.choice([24, 33, 40, 57], 3))
+        f = inputs.random_volume(rng, shape, bins_dtype, 0, 255)
+        m = inputs.random_volume(rng, shape, bins_dtype, 0, 255)
+        mats = inputs.random_affines(rng, 3 + k % 3, shape, rot=10, trans=3)
+        pairs.append((B.Volume.from_numpy(f, 0, 255), B.Volume.from_numpy(m, 0, 255),
+                      torch.from_numpy(mats).cuda()))
+    return pairs
+
+
+@pytest.mark.parametrize("shape", ["256 65536 1 1", "1024 262144 0 0", "512 131072 0 1", "256 131072 1 0"])
+def test_pairs_launch_shapes_keep_results(tmp_path, shape):
+    """Every launch shape the pairs tuner can pick (workgroup size, slab
+    voxels, 16-bit or u32 counters, work-item order), forced through the
+    cache file, gives MI bit-identical to the default shape."""
+    import torch
+    from paper_1909_10690_amd import binding as B
+    print(f"[tune] pairs shape {shape}", flush=True)
+    path = tmp_path / "tune.txt"
+    os.environ["MI_TUNE_CACHE"] = str(path)
+    try:
+        ctx = B.Context(0)
+        pairs = _pairs(51)
+        ref = ctx.eval_pairs(pairs, 64, [1.0, 2.0]).cpu().numpy()
+        ctx.tune_pairs(pairs, 64)
+        tuned = ctx.eval_pairs(pairs, 64, [1.0, 2.0]).cpu().numpy()
+        assert np.array_equal(tuned, ref)
+        lines = [l for l in path.read_text().splitlines() if l.startswith("gemi-tune-pairs")]
+        assert len(lines) == 1
+        f = lines[0].split()
+        assert f[7] in ("256", "512", "1024") and f[9] in ("0", "1") and f[10] in ("0", "1")
+        path.write_text(" ".join(f[:7] + shape.split()) + "\n")
+        ctx.close()
+        ctx2 = B.Context(0)  # reads the forced shape
+        got = ctx2.eval_pairs(pairs, 64, [1.0, 2.0]).cpu().numpy()
+        torch.cuda.synchronize()
+        assert np.array_equal(got, ref), shape
+        ctx2.close()
+    finally:
+        del os.environ["MI_TUNE_CACHE"]
+
+
+def test_pairs_preparation_reuse(ctx):
+    """MI_VOLUMES_UNCHANGED on mi_eval_pairs keeps the pairs' fixed bins and
+    oct volumes: repeated calls, transforms rewritten in place, graph
+    replays and a different pair set through the same workspace (which
+    prepares again) all match eager calls."""
+    import torch
+    from paper_1909_10690_amd import binding as B
+    A, Bp = _pairs(61), _pairs(62, n=4)
+    q = [1.0, 0.5]
+    ws = torch.empty(max(ctx.pairs_workspace_size(A, 32, 2), ctx.pairs_workspace_size(Bp, 32, 2)),
+                     dtype=torch.uint8, device="cuda")
+    refA = ctx.eval_pairs(A, 32, q).cpu().numpy()
+    refB = ctx.eval_pairs(Bp, 32, q).cpu().numpy()
+    U = B.VOLUMES_UNCHANGED
+    for k, (ps, ref) in enumerate([(A, refA), (A, refA), (Bp, refB), (Bp, refB), (A, refA)]):
+        got = ctx.eval_pairs(ps, 32, q, flags=U, workspace=ws).cpu().numpy()
+        assert np.array_equal(got, ref), k
+    # transforms rewritten in place: the preparation stays, the matrices are read afresh
+    rng = np.random.default_rng(63)
+    for _, _, tr in A:
+        tr.view(-1, 3, 4)[:, :, 3] += torch.from_numpy(rng.uniform(-1, 1, (tr.shape[0], 3))).cuda()
+    fresh = ctx.eval_pairs(A, 32, q).cpu().numpy()
+    got = ctx.eval_pairs(A, 32, q, flags=U, workspace=ws).cpu().numpy()
+    assert np.array_equal(got, fresh) and not np.array_equal(fresh, refA)
+    stream = torch.cuda.Stream()
+    out = torch.empty_like(torch.from_numpy(fresh)).cuda()
+    for rep in range(3):
+        with torch.cuda.stream(stream):
+            ctx.eval_pairs(A, 32, q, flags=U | B.USE_GRAPH, workspace=ws, out=out, stream=stream)
+        stream.synchronize()
+        assert np.array_equal(out.cpu().numpy(), fresh), f"replay {rep}"
+        ctx.eval_pairs(Bp, 32, q, workspace=ws)  # eager work between replays: prepares B in the workspace
+        torch.cuda.synchronize()
