@@ -296,16 +296,33 @@ int mi_map_paths(mi_context *ctx, const double *values, int32_t nx, int32_t ny, 
                  int32_t direction, int32_t cx, int32_t cy, int32_t cz, int32_t *next_out,
                  int32_t *sink_out, int64_t *stats_out, void *stream);
 
-/* Autotuner of the hard-binned sweep (mi_eval and mi_eval_pairs share its
- * kernel).  Times the histogram kernel on these arguments for every
- * candidate launch shape (workgroup size 256/512/1024, slab-major or
- * transform-major workgroup order, three slab counts), keeps the fastest
- * for this problem class (volume shapes, moving dtype, bins, boundary, and
- * the power-of-two bucket of n_transforms) in the context, and, when the
- * environment variable MI_TUNE_CACHE names a file, records it there; later
- * contexts read that file at mi_create.  Results are unaffected (the sweep
- * is exact whatever its shape).  Synchronous: waits for `stream`.  The
- * workspace is the one mi_eval would use with hist_out = NULL. */
+/* Autotuner of the sweeps of mi_eval, mi_eval_sampled and mi_grad for this
+ * problem class (volume shapes, moving dtype, bins, boundary, and the
+ * power-of-two bucket of n_transforms): times the kernels on these
+ * arguments for every candidate launch shape, keeps the fastest in the
+ * context and, when the environment variable MI_TUNE_CACHE names a file,
+ * records it there; later contexts read that file at mi_create.
+ *  - Hard-binned (flags without MI_HIST_PARZEN): the histogram sweep, over
+ *    workgroup sizes 256/512/1024, slab-major or transform-major workgroup
+ *    order, three slab counts and (up to 128 bins) u32 or 16-bit LDS
+ *    counters.  Results are unaffected (the sweep is exact whatever its
+ *    shape).  The workspace is the one mi_eval would use with
+ *    hist_out = NULL.
+ *  - Parzen (MI_HIST_PARZEN): the forward sweep's, then the backward
+ *    sweep's workgroup size (512/1024) and LDS band budget (32, 64, 96 or
+ *    128 KiB: how many bands of table rows walk the fixed volume), then the
+ *    workgroup count (half, as planned, twice), timing forward and gradient
+ *    calls with one entropy.  MI changes only in the last bits (the order
+ *    in which workgroup partial sums merge), gradients at the level of the
+ *    fp32 per-lane partial sums, whose grouping follows the shape (~1e-7
+ *    relative).  The workspace is
+ *    mi_workspace_size() for these arguments with n_q = 2 and MI_GRADIENT;
+ *    its contents are overwritten.
+ * Synchronous: waits for `stream`.  MI_USE_GRAPH and MI_VOLUMES_UNCHANGED
+ * are ignored; MI_SAMPLED and MI_GRADIENT give MI_ERR_FLAGS.
+ * Environment defaults read at mi_create for untuned classes (measurement
+ * aids): MI_TUNE_HARD_BLOCK, MI_TUNE_HARD_ORDER, MI_TUNE_HARD_CHUNKS,
+ * MI_TUNE_PARZEN_BLOCK, MI_TUNE_PARZEN_LDS_KIB, MI_TUNE_PARZEN_CHUNK_SHIFT. */
 int mi_tune(mi_context *ctx, const mi_volume *fixed, const mi_volume *moving,
             const double *transforms, int32_t n_transforms, int32_t bins, int32_t flags,
             void *workspace, size_t workspace_bytes, void *stream);

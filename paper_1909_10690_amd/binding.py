@@ -347,12 +347,17 @@ class Context:
 
     def tune(self, fixed: Volume, moving: Volume, transforms: torch.Tensor, bins: int, flags: int = 0,
              workspace: torch.Tensor | None = None, stream=None) -> None:
-        """Autotunes the hard-binned sweep's launch shape for this problem class
-        (synchronous; results are unaffected)."""
+        """Autotunes the launch shape of the hard-binned sweep, or with
+        HIST_PARZEN in ``flags`` of the Parzen sweeps, for this problem class
+        (synchronous; hard results are unaffected, Parzen ones only in the
+        last bits)."""
         transforms = transforms.to(device=fixed.tensor.device, dtype=torch.float64).reshape(-1, 12).contiguous()
         n = transforms.shape[0]
         if workspace is None:
-            workspace = self.workspace(self.workspace_size(fixed, moving, n, bins, 1, flags))
+            if flags & HIST_PARZEN:
+                workspace = self.workspace(self.workspace_size(fixed, moving, n, bins, 2, flags | GRADIENT))
+            else:
+                workspace = self.workspace(self.workspace_size(fixed, moving, n, bins, 1, flags))
         f, m = fixed.c(), moving.c()
         _check(self.lib.mi_tune(self.handle, ctypes.byref(f), ctypes.byref(m), _ptr(transforms), n, bins,
                                 flags, _ptr(workspace), workspace.numel(), self._stream(stream)), "mi_tune")

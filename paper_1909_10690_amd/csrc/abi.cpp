@@ -74,11 +74,16 @@ int check_q(const double* q, int32_t n_q) {
 }
 
 // Bytes of the moving volume's gather layout on the Parzen path (16-bit
-// oct volume for integer volumes, fp32 quad volume for float ones); the
-// largest layout any path uses for the volume.
+// quad volume for integer volumes, fp32 quad volume for float ones).
+size_t parzen_gather_bytes(const mi_volume* m) {
+  return m->dtype == MI_F32 ? quad_f32_bytes(m->nx, m->ny, m->nz) : quad16_bytes(m->nx, m->ny, m->nz);
+}
+
+// The largest gather layout any path uses for the volume (the hard path's
+// 16-bit oct volume for integer volumes).
 size_t gather_bytes(const mi_volume* m) {
   return m->dtype == MI_F32 ? quad_f32_bytes(m->nx, m->ny, m->nz)
-                            : oct_volume_bytes(m->nx, m->ny, m->nz);
+                            : std::max(oct_volume_bytes(m->nx, m->ny, m->nz), quad16_bytes(m->nx, m->ny, m->nz));
 }
 
 // Bytes of the hard path's oct volume: 8-bit corners when the range allows.
@@ -128,12 +133,13 @@ int check_common(const mi_volume* f, const mi_volume* m, int32_t n, int32_t bins
 //                count u64[n], MI partial sums (reduce_part_bytes)
 //   Parzen:      moving oct volume (integer moving volume) or f32x4 quad
 //                volume [mnz+1][mny][mnx] (float moving volume),
-//                occupied-row map, table f64[n][B][B], count u64[n]
+//                occupied-row map, wave-tile slot masks u32[tiles],
+//                table f64[n][B][B], count u64[n]
 //                MI partial sums (reduce_part_bytes)
 //   Parzen grad: + table marginals f64[n][2B], dMI/dp tables f32[n][n_q][B][B]
 //   sampled:     + sample list u32x2[nvox_fixed] and its length u64
 struct Layout {
-  size_t xf = 0, fbins = 0, gvol = 0, hist = 0, rowmap = 0, table = 0, count = 0, part = 0, marg = 0, gtab = 0,
+  size_t xf = 0, fbins = 0, gvol = 0, hist = 0, rowmap = 0, tmask = 0, table = 0, count = 0, part = 0, marg = 0, gtab = 0,
          list = 0, nlist = 0, total = 0;
 };
 
@@ -158,9 +164,11 @@ Layout layout(const mi_volume* f, const mi_volume* m, int32_t n, int32_t bins, i
     off += align256(reduce_part_bytes(n, bins, n_q));
   } else {
     L.gvol = off;
-    off += align256(gather_bytes(m));
+    off += align256(parzen_gather_bytes(m));
     L.rowmap = off;
     off += align256(sizeof(RowMap));
+    L.tmask = off;
+    off += align256(4 * (size_t)parzen_tiles(f->nx, f->ny, f->nz));
     L.table = off;
     off += align256(bb * 8 * (size_t)n);
     L.count = off;
@@ -242,6 +250,34 @@ struct PairsTune {
   int32_t transform_major = 0;
 };
 
+// Launch shape of the Parzen sweeps, forward and backward each: workgroup
+// size and LDS budget per workgroup (the table's rows are split into bands
+// that fit it; fewer, larger bands mean fewer walks over the fixed volume
+// at one workgroup per CU); and workgroups per transform and band, as a
+// power-of-two multiple of the planned count.  Results vary only by the
+// merge order of workgroup partial sums (last bits).
+struct ParzenTune {
+  int32_t fwd_block = 512, fwd_lds_kib = 64;  // 256/512/1024; 16, 32, 64, 96 or 128
+  int32_t bwd_block = 512, bwd_lds_kib = 64;
+  int32_t chunk_shift = 0;  // -1, 0, 1: half, as planned, twice the workgroups
+};
+
+// The untuned shape.  Up to 64 bins a table fits one 64 KiB band, and
+// 512-thread workgroups (two per CU) were fastest on the 128^3, 64-bin
+// gradient (1.19 ms a call against 1.29-1.30 ms with 1024 threads); above
+// it, fewer, larger bands at one 1024-thread workgroup per CU were fastest
+// on the 512x512x300 / 256^3, 256-bin CT/MR gradient (forward 128 KiB:
+// 0.59 against 1.09 ms; backward 96 KiB: 1.00 against 1.09 ms).
+ParzenTune parzen_shape_for_bins(int32_t bins) {
+  ParzenTune t;
+  if (bins > 64) {
+    t.fwd_block = t.bwd_block = 1024;
+    t.fwd_lds_kib = 128;
+    t.bwd_lds_kib = 96;
+  }
+  return t;
+}
+
 // Problem class of the tuning cache.
 struct TuneKey {
   int32_t v[11];
@@ -268,6 +304,9 @@ struct mi_context {
   std::vector<EventPair> events[kTimers];
   std::vector<std::pair<TuneKey, HardTune>> tuned;  // from mi_tune or the cache file
   std::vector<std::pair<TuneKey, PairsTune>> pairs_tuned;  // from mi_tune_pairs or the cache file
+  std::vector<std::pair<TuneKey, ParzenTune>> parzen_tuned;  // from mi_tune (Parzen) or the cache file
+  bool parzen_env = false;    // MI_TUNE_PARZEN_* set: parzen_default replaces the shape by bins
+  ParzenTune parzen_default;  // launch shape when no tuned entry matches (with parzen_env)
   std::vector<uint64_t> last_pairs_prep;  // pairs, bins and workspace of the last pairs preparation
   std::string tune_file;                            // MI_TUNE_CACHE, if set
   std::vector<GraphEntry> graphs;                   // MI_USE_GRAPH replays, oldest first
@@ -363,7 +402,7 @@ int plan_chunks(const mi_context* ctx, const mi_volume* f, const mi_volume* m, i
 int plan_parzen_chunks(const mi_context* ctx, const mi_volume* f, const mi_volume* m, int64_t units) {
   const int64_t groups = (int64_t)((f->ny + 3) / 4) * f->nz;
   int64_t c = ((int64_t)ctx->cu_count * 8 + units - 1) / units;
-  const int64_t l2 = l2_slabs(gather_bytes(m));
+  const int64_t l2 = l2_slabs(parzen_gather_bytes(m));
   if (c < l2) c = l2;
   if (c > groups) c = groups;
   return (int)(((c + 7) / 8) * 8);
@@ -388,17 +427,39 @@ int64_t expected_samples(const mi_volume* f, const SampleSpec& smp) {
 }
 
 // Rows of the table per band when `tables` fp32 tables of `bins` columns
-// share a 64 KiB LDS budget.
-int32_t band_rows_for(int32_t bins, int32_t tables) {
-  int32_t r = (int32_t)(65536 / (4 * bins * tables));
-  return r < bins ? r : bins;
+// share an LDS budget of `budget` bytes (at most 64 KiB).
+int32_t band_rows_for(int32_t bins, int32_t tables, int32_t budget) {
+  int32_t r = (int32_t)(budget / (4 * bins * tables));
+  return r < 1 ? 1 : (r < bins ? r : bins);
+}
+
+// Problem class of a Parzen call: volume shapes, moving dtype, bins,
+// boundary, the power-of-two bucket of n and whether it is a gradient call.
+TuneKey parzen_tune_key(const mi_volume* f, const mi_volume* m, int32_t n, int32_t bins, int32_t flags) {
+  TuneKey k;
+  int32_t nb = 0;
+  while ((1 << nb) < n && nb < 30) ++nb;
+  const int32_t v[11] = {-2, f->nx, f->ny, f->nz, m->nx, m->ny, m->nz, m->dtype, bins,
+                         (flags & MI_BOUNDARY_CLAMP) ? 1 : 0, nb};
+  memcpy(k.v, v, sizeof v);
+  return k;
+}
+
+ParzenTune parzen_tune_for(const mi_context* ctx, const mi_volume* f, const mi_volume* m, int32_t n, int32_t bins,
+                           int32_t flags) {
+  const TuneKey k = parzen_tune_key(f, m, n, bins, flags);
+  for (const auto& e : ctx->parzen_tuned)
+    if (e.first == k) return e.second;
+  return ctx->parzen_env ? ctx->parzen_default : parzen_shape_for_bins(bins);
 }
 
 // The Parzen path: forward table, MI, and (grad_out != NULL) the gradient.
 int run_parzen(mi_context* ctx, const mi_volume* fixed, const mi_volume* moving,
                const double* transforms, int32_t n, int32_t bins, const double* q, int32_t n_q,
                int32_t flags, double* mi_out, uint64_t* overlap_out, double* grad_out, char* ws,
-               const Layout& L, hipStream_t s, const SampleSpec* smp = nullptr) {
+               const Layout& L, hipStream_t s, const SampleSpec* smp = nullptr,
+               const ParzenTune* tune_override = nullptr) {
+  const ParzenTune tune = tune_override ? *tune_override : parzen_tune_for(ctx, fixed, moving, n, bins, flags);
   hipError_t e;
   // the caller's physical matrices -> index-space matrices in the workspace
   {
@@ -415,8 +476,10 @@ int run_parzen(mi_context* ctx, const mi_volume* fixed, const mi_volume* moving,
   if (smp || !reuse_prep(ctx, flags, prep_key(2, ws, fixed, moving, bins))) {
     if ((e = launch_prebin_fixed(desc(fixed), bins, fb, s)) != hipSuccess) return hip_fail(e, "prebin");
     if ((e = launch_row_map(fb, voxels(fixed), bins, rows, s)) != hipSuccess) return hip_fail(e, "row map");
+    if ((e = launch_tile_mask(fb, fixed->nx, fixed->ny, fixed->nz, (uint32_t*)(ws + L.tmask), s)) != hipSuccess)
+      return hip_fail(e, "tile mask");
     e = fq ? launch_pack_quads_f32(desc(moving), (float4*)gvol, s)
-           : launch_pack_octs(desc(moving), (uint4*)gvol, s);
+           : launch_pack_quads16(desc(moving), (uint2*)gvol, s);
     if (e != hipSuccess) return hip_fail(e, "pack");
   }
   uint2* list = (uint2*)(ws + L.list);
@@ -442,6 +505,7 @@ int run_parzen(mi_context* ctx, const mi_volume* fixed, const mi_volume* moving,
   a.transforms = transforms;
   a.fbins = fb;
   a.rows = rows;
+  a.tile_mask = (const uint32_t*)(ws + L.tmask);
   a.gvol = gvol;
   a.table = table;
   a.count = count;
@@ -453,7 +517,7 @@ int run_parzen(mi_context* ctx, const mi_volume* fixed, const mi_volume* moving,
   a.mnx = moving->nx;
   a.mny = moving->ny;
   a.mnz = moving->nz;
-  a.gvol_bytes = (uint32_t)gather_bytes(moving);
+  a.gvol_bytes = (uint32_t)parzen_gather_bytes(moving);
   a.n = n;
   a.bins = bins;
   a.slab_major = 1;
@@ -467,13 +531,18 @@ int run_parzen(mi_context* ctx, const mi_volume* fixed, const mi_volume* moving,
   auto sweep = [&](bool backward, int which) -> int {
     ParzenLaunch part = P;
     ParzenArgs& pa = part.args;
+    part.block = backward ? tune.bwd_block : tune.fwd_block;
     // backward: kParzenQGroup fp32 tables; forward: one table of 8-byte cells
-    // plus kHotCopies - 1 extra copies of the background row
-    pa.band_rows = backward ? band_rows_for(bins, kParzenQGroup)
-                            : std::min(bins, std::max(1, 65536 / (8 * bins) - (kHotCopies - 1)));
+    // plus the copies of the background row's hot columns
+    const int32_t budget = (backward ? tune.bwd_lds_kib : tune.fwd_lds_kib) * 1024;
+    pa.band_rows = backward ? band_rows_for(bins, kParzenQGroup, budget)
+                            : std::min(bins, std::max(1, (budget / 8 - parzen_hot_cells(bins)) / bins));
     pa.bands = (bins + pa.band_rows - 1) / pa.band_rows;
-    pa.chunks = smp ? plan_sampled_chunks(ctx, expected_samples(fixed, *smp), (int64_t)n * pa.bands)
-                    : plan_parzen_chunks(ctx, fixed, moving, (int64_t)n * pa.bands);
+    int64_t chunks = smp ? plan_sampled_chunks(ctx, expected_samples(fixed, *smp), (int64_t)n * pa.bands)
+                         : plan_parzen_chunks(ctx, fixed, moving, (int64_t)n * pa.bands);
+    if (tune.chunk_shift > 0) chunks *= 2;
+    if (tune.chunk_shift < 0) chunks = std::max<int64_t>(8, ((chunks / 2 + 7) / 8) * 8);
+    pa.chunks = (int32_t)std::min<int64_t>(chunks, 1 << 24);
     const int64_t per_launch = 0x7FFFFFFFll / ((int64_t)pa.chunks * pa.bands);
     for (int64_t t0 = 0; t0 < n; t0 += per_launch) {
       pa.n = (int32_t)(n - t0 < per_launch ? n - t0 : per_launch);
@@ -645,6 +714,8 @@ HardTune tune_for(const mi_context* ctx, const mi_volume* f, const mi_volume* m,
 // Cache file: one problem class per line,
 //   gemi-tune fnx fny fnz mnx mny mnz mdtype bins clamp nbucket oct8 block slab_major chunks packed
 //   gemi-tune-pairs pairs voxels transforms bins clamp oct8 block slab_voxels packed transform_major
+//   gemi-tune-parzen fnx fny fnz mnx mny mnz mdtype bins clamp nbucket fwd_block fwd_lds_kib bwd_block
+//                    bwd_lds_kib chunk_shift
 // (the pairs' counts are power-of-two buckets).
 void load_tune_file(mi_context* c) {
   std::ifstream in(c->tune_file);
@@ -655,6 +726,19 @@ void load_tune_file(mi_context* c) {
     TuneKey k;
     HardTune t;
     if (!(ss >> tag)) continue;
+    if (tag == "gemi-tune-parzen") {
+      k.v[0] = -2;
+      ParzenTune pt;
+      bool ok = true;
+      for (int i = 1; i < 11 && ok; ++i) ok = static_cast<bool>(ss >> k.v[i]);
+      ok = ok && (ss >> pt.fwd_block >> pt.fwd_lds_kib >> pt.bwd_block >> pt.bwd_lds_kib >> pt.chunk_shift);
+      auto good_block = [](int32_t b) { return b == 256 || b == 512 || b == 1024; };
+      auto good_kib = [](int32_t v) { return v == 16 || v == 32 || v == 64 || v == 96 || v == 128; };
+      if (ok && good_block(pt.fwd_block) && good_block(pt.bwd_block) && good_kib(pt.fwd_lds_kib) &&
+          good_kib(pt.bwd_lds_kib) && pt.chunk_shift >= -1 && pt.chunk_shift <= 1)
+        c->parzen_tuned.emplace_back(k, pt);
+      continue;
+    }
     if (tag == "gemi-tune-pairs") {
       memset(k.v, 0, sizeof k.v);
       k.v[0] = -1;
@@ -687,6 +771,12 @@ void save_tune_file(const mi_context* c) {
     for (int i = 0; i < 11; ++i) out << ' ' << e.first.v[i];
     out << ' ' << e.second.block << ' ' << e.second.slab_major << ' ' << e.second.chunks << ' '
         << e.second.packed << '\n';
+  }
+  for (const auto& e : c->parzen_tuned) {
+    out << "gemi-tune-parzen";
+    for (int i = 1; i < 11; ++i) out << ' ' << e.first.v[i];
+    out << ' ' << e.second.fwd_block << ' ' << e.second.fwd_lds_kib << ' ' << e.second.bwd_block << ' '
+        << e.second.bwd_lds_kib << ' ' << e.second.chunk_shift << '\n';
   }
   for (const auto& e : c->pairs_tuned) {
     out << "gemi-tune-pairs";
@@ -851,6 +941,98 @@ int run_hard(mi_context* ctx, const mi_volume* fixed, const mi_volume* moving,
   return MI_OK;
 }
 
+
+// Autotuning of the Parzen sweeps (mi_tune with MI_HIST_PARZEN): the
+// forward's shape first (forward + MI calls), then the backward's with the
+// best forward (gradient calls), then the workgroup count, one entropy
+// (Shannon).  The workspace is the gradient workspace for two entropies;
+// the second entropy's dMI/dp tables hold the calls' MI and gradients.
+int tune_parzen(mi_context* ctx, const mi_volume* fixed, const mi_volume* moving, const double* transforms,
+                int32_t n, int32_t bins, int32_t flags, char* ws, const Layout& L, hipStream_t s) {
+  const size_t BB = (size_t)bins * bins;
+  char* spare = ws + L.gtab + align256(BB * 4 * (size_t)n);
+  double* mi = (double*)spare;
+  double* grad = (double*)(spare + align256(8 * (size_t)n));
+  const double one = 1.0;
+  const int32_t fl = (flags & (MI_BOUNDARY_CLAMP | MI_TSALLIS_PSEUDOADDITIVE)) | MI_HIST_PARZEN;
+  hipError_t e;
+  hipEvent_t t0 = nullptr, t1 = nullptr;
+  if ((e = hipEventCreate(&t0)) != hipSuccess || (e = hipEventCreate(&t1)) != hipSuccess) {
+    if (t0) (void)hipEventDestroy(t0);
+    return hip_fail(e, "tune events");
+  }
+  ParzenTune best = parzen_tune_for(ctx, fixed, moving, n, bins, flags);
+  // the preparation once; the timed calls reuse it
+  int st = run_parzen(ctx, fixed, moving, transforms, n, bins, &one, 1, fl, mi, nullptr, grad, ws, L, s, nullptr,
+                      &best);
+  auto timed = [&](const ParzenTune& c, bool with_grad, float& ms_out) -> int {
+    float total = 0;
+    for (int rep = 0; rep < 4; ++rep) {
+      if ((e = hipEventRecord(t0, s)) != hipSuccess) return hip_fail(e, "tune");
+      const int r = run_parzen(ctx, fixed, moving, transforms, n, bins, &one, 1, fl | MI_VOLUMES_UNCHANGED, mi,
+                               nullptr, with_grad ? grad : nullptr, ws, L, s, nullptr, &c);
+      if (r != MI_OK) return r;
+      if ((e = hipEventRecord(t1, s)) != hipSuccess || (e = hipEventSynchronize(t1)) != hipSuccess)
+        return hip_fail(e, "tune");
+      float ms = 0;
+      (void)hipEventElapsedTime(&ms, t0, t1);
+      if (rep > 0) total += ms;  // the first run warms caches
+    }
+    ms_out = total;
+    return MI_OK;
+  };
+  const int32_t blocks[2] = {512, 1024}, budgets[4] = {32, 64, 96, 128};
+  for (int pass = 0; pass < 2 && st == MI_OK; ++pass) {  // 0: forward, 1: backward
+    float best_ms = 3.4e38f;
+    ParzenTune keep = best;
+    for (int32_t b : blocks)
+      for (int32_t kib : budgets) {
+        ParzenTune c = best;
+        if (pass == 0) {
+          c.fwd_block = b;
+          c.fwd_lds_kib = kib;
+        } else {
+          c.bwd_block = b;
+          c.bwd_lds_kib = kib;
+        }
+        float ms = 0;
+        if ((st = timed(c, pass == 1, ms)) != MI_OK) break;
+        if (ms < best_ms) {
+          best_ms = ms;
+          keep = c;
+        }
+      }
+    best = keep;
+  }
+  if (st == MI_OK) {
+    float best_ms = 3.4e38f;
+    ParzenTune keep = best;
+    for (int32_t sh : {-1, 0, 1}) {
+      ParzenTune c = best;
+      c.chunk_shift = sh;
+      float ms = 0;
+      if ((st = timed(c, true, ms)) != MI_OK) break;
+      if (ms < best_ms) {
+        best_ms = ms;
+        keep = c;
+      }
+    }
+    best = keep;
+  }
+  (void)hipEventDestroy(t0);
+  (void)hipEventDestroy(t1);
+  if (st != MI_OK) return st;
+  const TuneKey k = parzen_tune_key(fixed, moving, n, bins, flags);
+  bool found = false;
+  for (auto& entry : ctx->parzen_tuned)
+    if (entry.first == k) {
+      entry.second = best;
+      found = true;
+    }
+  if (!found) ctx->parzen_tuned.emplace_back(k, best);
+  save_tune_file(ctx);
+  return MI_OK;
+}
 
 // ---- the multi-pair path -----------------------------------------------------
 
@@ -1093,6 +1275,27 @@ int mi_create(mi_context** out, int device) {
     const int v = atoi(k);
     if (v >= 8 && v % 8 == 0) c->hard_default.chunks = v;
   }
+  if (const char* b = getenv("MI_TUNE_PARZEN_BLOCK")) {
+    const int v = atoi(b);
+    if (v == 256 || v == 512 || v == 1024) {
+      c->parzen_default.fwd_block = c->parzen_default.bwd_block = v;
+      c->parzen_env = true;
+    }
+  }
+  if (const char* l = getenv("MI_TUNE_PARZEN_LDS_KIB")) {
+    const int v = atoi(l);
+    if (v == 16 || v == 32 || v == 64 || v == 96 || v == 128) {
+      c->parzen_default.fwd_lds_kib = c->parzen_default.bwd_lds_kib = v;
+      c->parzen_env = true;
+    }
+  }
+  if (const char* k = getenv("MI_TUNE_PARZEN_CHUNK_SHIFT")) {
+    const int v = atoi(k);
+    if (v >= -1 && v <= 1) {
+      c->parzen_default.chunk_shift = v;
+      c->parzen_env = true;
+    }
+  }
   if (const char* f = getenv("MI_TUNE_CACHE")) {
     c->tune_file = f;
     load_tune_file(c);
@@ -1133,11 +1336,26 @@ int mi_workspace_size(mi_context*, const mi_volume* fixed, const mi_volume* movi
 int mi_tune(mi_context* ctx, const mi_volume* fixed, const mi_volume* moving,
             const double* transforms, int32_t n, int32_t bins, int32_t flags, void* workspace,
             size_t workspace_bytes, void* stream) {
-  int st = check_common(fixed, moving, n, bins, nullptr, 0, flags & ~MI_USE_GRAPH, false);
+  const bool parzen = (flags & MI_HIST_PARZEN) != 0;
+  int st = check_common(fixed, moving, n, bins, nullptr, 0, flags & ~MI_USE_GRAPH, parzen);
   if (st != MI_OK) return st;
   if (flags & (MI_SAMPLED | MI_GRADIENT)) return MI_ERR_FLAGS;
-  if (flags & MI_HIST_PARZEN) return MI_ERR_UNSUPPORTED;
   if (n > 0 && !transforms) return MI_ERR_NULL;
+  if (parzen) {
+    const Layout PL = layout(fixed, moving, n, bins, 2, true, true, false);
+    if (!workspace || workspace_bytes < PL.total) return MI_ERR_WORKSPACE;
+    if (!ctx) return MI_ERR_NULL;
+    if (n == 0) return MI_OK;
+    hipError_t pe;
+    if ((pe = hipSetDevice(ctx->device)) != hipSuccess) return hip_fail(pe, "hipSetDevice");
+    const bool was = ctx->timing;
+    ctx->timing = false;
+    const int r = tune_parzen(ctx, fixed, moving, transforms, n, bins, flags, (char*)workspace, PL,
+                              (hipStream_t)stream);
+    ctx->timing = was;
+    ctx->last_prep.clear();
+    return r;
+  }
   const Layout L = layout(fixed, moving, n, bins, 1, false, false, true);
   if (!workspace || workspace_bytes < L.total) return MI_ERR_WORKSPACE;
   if (!ctx) return MI_ERR_NULL;

@@ -332,6 +332,15 @@ inline size_t oct8_volume_bytes(int32_t nx, int32_t ny, int32_t nz) {
   return (size_t)nx * (size_t)ny * (size_t)nz * 8;
 }
 
+// Bytes of the 16-bit quad volume of an integer moving volume on the Parzen
+// path: per voxel the four (x, y) corners of its neighbourhood in one slice
+// (clamped, offset values), one extra slice; two 8-byte loads per voxel at
+// half the footprint of the oct volume, which matters when one transform's
+// gathers cover a moving volume larger than the caches.
+inline size_t quad16_bytes(int32_t nx, int32_t ny, int32_t nz) {
+  return (size_t)nx * (size_t)ny * (size_t)(nz + 1) * 8;
+}
+
 // Bytes of the fp32 quad volume of a float moving volume: per voxel the
 // four (x, y) corners of its neighbourhood in one slice, one extra slice.
 inline size_t quad_f32_bytes(int32_t nx, int32_t ny, int32_t nz) {
@@ -398,6 +407,7 @@ struct ParzenArgs {
   const double* transforms;
   const uint8_t* fbins;       // fixed-volume slots (see RowMap)
   const RowMap* rows;
+  const uint32_t* tile_mask;  // [row groups][x tiles]: slot groups present in each 16 x 4 wave tile
   const void* gvol;    // uint4 octs (integer moving) or float4 quads (float moving)
   double* table;       // [n][B][B] forward masses (fp64)
   uint64_t* count;     // [n] voxels that took part
@@ -414,13 +424,38 @@ struct ParzenArgs {
 };
 
 constexpr int kParzenQGroup = 2;  // entropies per backward sweep
-constexpr int kHotCopies = 4;     // forward: LDS copies of the background row (slot 0)
+
+// Wave tiles of the Parzen walks (kTileX x kTileY fixed voxels, one wave
+// step): bit g of a tile's mask is set when a voxel of the tile has a slot
+// in [8 g, 8 g + 8).  A band's walk skips the tiles whose mask holds none
+// of its slots, so every band but the background's skips the background.
+constexpr int kSlotGroup = 8;
+inline int64_t parzen_tiles(int32_t nx, int32_t ny, int32_t nz) {
+  return (int64_t)((ny + kTileY - 1) / kTileY) * nz * ((nx + kTileX - 1) / kTileX);
+}
+__host__ __device__ inline uint32_t slot_group_mask(int32_t r_lo, int32_t r_hi) {
+  const int32_t g0 = r_lo / kSlotGroup, g1 = (r_hi - 1) / kSlotGroup;  // r_hi > r_lo
+  return (g1 >= 31 ? 0xFFFFFFFFu : ((2u << g1) - 1u)) & ~((1u << g0) - 1u);
+}
+
+// Forward sweeps: the background row (slot 0, the lowest occupied fixed
+// bin: air in a CT) receives most voxels, all into a few cells.  Its first
+// parzen_hot_cols(B) columns get kHotCopies private copies in LDS, lane l
+// adding into copy l % kHotCopies; each copy is one cell longer than the
+// columns it covers, so the same column of consecutive copies falls in
+// different LDS banks.
+constexpr int kHotCopies = 16;
+constexpr int kHotCols = 64;
+__host__ __device__ inline int32_t parzen_hot_cols(int32_t bins) { return bins < kHotCols ? bins : kHotCols; }
+__host__ __device__ inline int32_t parzen_hot_stride(int32_t bins) { return parzen_hot_cols(bins) + 1; }
+__host__ __device__ inline int32_t parzen_hot_cells(int32_t bins) { return kHotCopies * parzen_hot_stride(bins); }
 
 
 struct ParzenLaunch {
   ParzenArgs args;
   int32_t float_quads;  // 1: moving volume is fp32 (float4 quads, else uint4 octs)
   int32_t clamp;
+  int32_t block;        // threads per workgroup of the sweeps: 256, 512 or 1024
 };
 
 // LDS guard of every launch with dynamic LDS: the kernel's static LDS (read
@@ -501,7 +536,10 @@ HardGeom make_hard_geom(const VolumeDesc& fixed, const VolumeDesc& moving, const
                         const void* octs, int32_t bins);
 hipError_t launch_mi_reduce(const ReduceLaunch& L, hipStream_t s);
 hipError_t launch_pack_quads_f32(const VolumeDesc& m, float4* out, hipStream_t s);
+hipError_t launch_pack_quads16(const VolumeDesc& m, uint2* out, hipStream_t s);
 hipError_t launch_row_map(uint8_t* fbins, size_t nvox, int32_t bins, RowMap* m, hipStream_t s);
+// Tile masks of the slotted fixed volume (see kSlotGroup).
+hipError_t launch_tile_mask(const uint8_t* slots, int32_t nx, int32_t ny, int32_t nz, uint32_t* mask, hipStream_t s);
 hipError_t launch_parzen_fwd(const ParzenLaunch& L, hipStream_t s);
 hipError_t launch_parzen_sampled_fwd(const ParzenLaunch& L, const uint2* list, const unsigned long long* n_list,
                                      hipStream_t s);

@@ -14,10 +14,11 @@
 // than storing them.
 //
 // Both sweeps walk the fixed volume like the hard-binned one (16 x 4 voxel
-// wave tiles, slab-major workgroup order).  An integer moving volume is
-// read from the hard path's oct volume (the 2x2x2 neighbourhood as exact
-// 16-bit integers, one load), a float one from an fp32 quad volume (the
-// four (x, y) corners of a slice per 16-byte element, two loads).  A
+// wave tiles, slab-major workgroup order).  The moving volume is read from
+// a quad volume: the four (x, y) corners of the voxel's neighbourhood in a
+// slice per element, two loads (slices z and z + 1) per voxel; 8-byte
+// elements of exact 16-bit integers for an integer volume, 16-byte fp32
+// elements for a float one.  A
 // workgroup accumulates one band of table rows (fixed bins) in LDS; bands
 // keep large tables within LDS, and a voxel outside the band costs only
 // its fixed-bin read.  Workgroup partials are merged into fp64 in HBM.
@@ -43,6 +44,38 @@ __global__ void pack_quads_f32_kernel(const float* __restrict__ v, int32_t nx, i
     const int32_t x1 = x + 1 < nx ? x + 1 : nx - 1;
     orow[x] = make_float4(c(r0[x]), c(r0[x1]), c(r1[x]), c(r1[x1]));
   }
+}
+
+// out[z][y][x] (z <= nz) = (v'(x,y) | v'(x1,y) << 16, v'(x,y1) | v'(x1,y1) << 16)
+// for an integer volume, v' = clamp(v, lo, hi) - lo < 2^16, neighbour
+// indices clamped, slice nz = nz-1.
+template <typename T>
+__global__ void pack_quads16_kernel(const T* __restrict__ v, int32_t nx, int32_t ny, int32_t nz, int32_t lo,
+                                    int32_t hi, uint2* __restrict__ out) {
+  const int32_t y = blockIdx.y, z = blockIdx.z;
+  uint2* __restrict__ orow = out + ((size_t)z * ny + y) * nx;
+  const int32_t zs = z < nz ? z : nz - 1;
+  const T* __restrict__ r0 = v + ((size_t)zs * ny + y) * nx;
+  const T* __restrict__ r1 = r0 + (y + 1 < ny ? nx : 0);
+  auto c = [&](int32_t a) -> uint32_t { return (uint32_t)((a < lo ? lo : (a > hi ? hi : a)) - lo); };
+  for (int32_t x = threadIdx.x; x < nx; x += blockDim.x) {
+    const int32_t x1 = x + 1 < nx ? x + 1 : nx - 1;
+    orow[x] = make_uint2(c(r0[x]) | (c(r0[x1]) << 16), c(r1[x]) | (c(r1[x1]) << 16));
+  }
+}
+
+hipError_t launch_pack_quads16(const VolumeDesc& m, uint2* out, hipStream_t s) {
+  const dim3 grid(1, (unsigned)m.ny, (unsigned)m.nz + 1);
+  const int32_t lo = (int32_t)m.lo, hi = (int32_t)m.hi;
+  switch (m.dtype) {
+  case 0: hipLaunchKernelGGL(pack_quads16_kernel<uint8_t>, grid, dim3(256), 0, s, (const uint8_t*)m.data, m.nx, m.ny,
+                             m.nz, lo, hi, out); break;
+  case 1: hipLaunchKernelGGL(pack_quads16_kernel<uint16_t>, grid, dim3(256), 0, s, (const uint16_t*)m.data, m.nx,
+                             m.ny, m.nz, lo, hi, out); break;
+  default: hipLaunchKernelGGL(pack_quads16_kernel<int16_t>, grid, dim3(256), 0, s, (const int16_t*)m.data, m.nx,
+                              m.ny, m.nz, lo, hi, out); break;
+  }
+  return hipGetLastError();
 }
 
 hipError_t launch_pack_quads_f32(const VolumeDesc& m, float4* out, hipStream_t s) {
@@ -138,6 +171,34 @@ hipError_t launch_row_map(uint8_t* fbins, size_t nvox, int32_t bins, RowMap* m, 
   return hipGetLastError();
 }
 
+// One thread per wave tile (kTileX x kTileY voxels of one slice): the OR of
+// the slot groups of its voxels.
+__global__ __launch_bounds__(256) void tile_mask_kernel(const uint8_t* __restrict__ slots, int32_t nx, int32_t ny,
+                                                        int32_t nz, uint32_t* __restrict__ mask) {
+  const int32_t XT = (nx + kTileX - 1) / kTileX, G = (ny + kTileY - 1) / kTileY;
+  const int64_t tiles = (int64_t)G * nz * XT;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < tiles; t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t g = t / XT;
+    const int32_t xt = (int32_t)(t - g * XT);
+    const int32_t k = (int32_t)(g / G), j0 = (int32_t)(g - (int64_t)k * G) * kTileY;
+    const int32_t x0 = xt * kTileX, x1 = min(nx, x0 + kTileX);
+    uint32_t m = 0;
+    for (int32_t j = j0; j < min(ny, j0 + kTileY); ++j) {
+      const uint8_t* row = slots + ((int64_t)k * ny + j) * nx;
+      for (int32_t x = x0; x < x1; ++x) m |= 1u << (row[x] / kSlotGroup);
+    }
+    mask[t] = m;
+  }
+}
+
+hipError_t launch_tile_mask(const uint8_t* slots, int32_t nx, int32_t ny, int32_t nz, uint32_t* mask, hipStream_t s) {
+  const int64_t tiles = parzen_tiles(nx, ny, nz);
+  const int64_t blocks = (tiles + 255) / 256;
+  hipLaunchKernelGGL(tile_mask_kernel, dim3((unsigned)(blocks < 8192 ? (blocks > 0 ? blocks : 1) : 8192)), dim3(256),
+                     0, s, slots, nx, ny, nz, mask);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 // per-voxel sample shared by the forward and backward sweeps
 // ---------------------------------------------------------------------------
@@ -145,7 +206,11 @@ hipError_t launch_row_map(uint8_t* fbins, size_t nvox, int32_t bins, RowMap* m, 
 typedef unsigned int uint4_t __attribute__((ext_vector_type(4)));
 typedef float float4_t __attribute__((ext_vector_type(4)));
 
-// Corner values c[z][y][x] of the 2x2x2 neighbourhood.
+typedef unsigned int uint2_t __attribute__((ext_vector_type(2)));
+
+// Corner values c[z][y][x] of the 2x2x2 neighbourhood: two quads, slices z
+// and z + 1 (`slice_bytes` apart), fp32 (FQ, 16 bytes each) or 16-bit
+// integers (8 bytes each).
 template <bool FQ>
 __device__ __forceinline__ void gather(const __amdgpu_buffer_rsrc_t& rsrc, uint32_t idx,
                                        int32_t slice_bytes, float c[2][2][2]) {
@@ -155,11 +220,12 @@ __device__ __forceinline__ void gather(const __amdgpu_buffer_rsrc_t& rsrc, uint3
     c[0][0][0] = a.x; c[0][0][1] = a.y; c[0][1][0] = a.z; c[0][1][1] = a.w;
     c[1][0][0] = b.x; c[1][0][1] = b.y; c[1][1][0] = b.z; c[1][1][1] = b.w;
   } else {
-    const uint4_t o = __builtin_amdgcn_raw_buffer_load_b128(rsrc, idx * 16u, 0, 0);
-    c[0][0][0] = (float)(o.x & 0xFFFFu); c[0][0][1] = (float)(o.x >> 16);
-    c[0][1][0] = (float)(o.y & 0xFFFFu); c[0][1][1] = (float)(o.y >> 16);
-    c[1][0][0] = (float)(o.z & 0xFFFFu); c[1][0][1] = (float)(o.z >> 16);
-    c[1][1][0] = (float)(o.w & 0xFFFFu); c[1][1][1] = (float)(o.w >> 16);
+    const uint2_t a = __builtin_amdgcn_raw_buffer_load_b64(rsrc, idx * 8u, 0, 0);
+    const uint2_t b = __builtin_amdgcn_raw_buffer_load_b64(rsrc, idx * 8u, slice_bytes, 0);
+    c[0][0][0] = (float)(a.x & 0xFFFFu); c[0][0][1] = (float)(a.x >> 16);
+    c[0][1][0] = (float)(a.y & 0xFFFFu); c[0][1][1] = (float)(a.y >> 16);
+    c[1][0][0] = (float)(b.x & 0xFFFFu); c[1][0][1] = (float)(b.x >> 16);
+    c[1][1][0] = (float)(b.y & 0xFFFFu); c[1][1][1] = (float)(b.y >> 16);
   }
 }
 
@@ -193,11 +259,10 @@ __device__ __forceinline__ unsigned long long fixed40(float w) {
   return ((unsigned long long)hi << 32) | lo;
 }
 
-// Dynamic LDS per workgroup of the Parzen sweeps: two per CU with the
-// static arrays beside them.  Larger budgets (fewer bands at 256 bins)
-// measured slower: 96 KiB and 128 KiB took the CT/MR iteration from 2.54 to
-// 3.04 and 3.16 ms (one workgroup per CU).
-constexpr size_t kParzenLdsMax = 64 * 1024;
+// Dynamic LDS limit of the Parzen sweeps: band budgets up to 128 KiB (the
+// launch shape picks one), with room for the static arrays beside them
+// within the 160 KiB a workgroup may hold.
+constexpr size_t kParzenLdsMax = 144 * 1024;
 
 // Sweep geometry of one workgroup.
 struct SweepCtx {
@@ -231,9 +296,10 @@ __device__ __forceinline__ size_t band_cell_row(const RowMap* m, int32_t r_lo, i
 //
 // Slot 0, the lowest occupied fixed bin, is the background of a medical
 // volume (air, most of a CT): whole waves add their taps into a handful of
-// its cells, and same-address LDS atomics serialise.  The band holding it
-// keeps kHotCopies copies of that row, lane l adding into copy l % kHotCopies;
-// the copies are summed at the flush.
+// its cells, and same-address and same-bank LDS atomics serialise.  The
+// band holding it keeps kHotCopies bank-skewed copies of the row's first
+// parzen_hot_cols(B) columns (common.h), lane l adding into copy
+// l % kHotCopies; the copies are summed at the flush.
 // Cell index and 32-bit fraction of an exact Q32 coordinate q on an axis of
 // n samples, q clamped to [0, (n - 1) 2^32]: the index is the high word held
 // to [0, n - 1]; the fraction is the low word while the high word lies in
@@ -246,13 +312,42 @@ __device__ __forceinline__ void clamp_q32(int64_t q, int32_t n, uint32_t& cell, 
   frac = (uint32_t)hi < (uint32_t)(n - 1) ? (uint32_t)q : 0u;
 }
 
+// Where a fixed voxel reads the moving volume: gather index, 32-bit
+// fractions per axis, and whether it takes part (EXCLUDE drops voxels
+// outside the volume).
+struct Loc {
+  uint32_t idx, frac[3];
+  bool inside;
+};
+
+// A voxel's moving neighbourhood as loaded: two quads, a: slice z, b:
+// slice z + 1 (fp32: all four words; 16-bit integers: .x and .y).
+struct Raw {
+  uint4_t a, b;
+};
+
+// Corner values c[z][y][x] of a loaded neighbourhood.
+template <bool FQ>
+__device__ __forceinline__ void unpack(const Raw& d, float c[2][2][2]) {
+  if (FQ) {
+    const float4_t a = __builtin_bit_cast(float4_t, d.a), b = __builtin_bit_cast(float4_t, d.b);
+    c[0][0][0] = a.x; c[0][0][1] = a.y; c[0][1][0] = a.z; c[0][1][1] = a.w;
+    c[1][0][0] = b.x; c[1][0][1] = b.y; c[1][1][0] = b.z; c[1][1][1] = b.w;
+  } else {
+    c[0][0][0] = (float)(d.a.x & 0xFFFFu); c[0][0][1] = (float)(d.a.x >> 16);
+    c[0][1][0] = (float)(d.a.y & 0xFFFFu); c[0][1][1] = (float)(d.a.y >> 16);
+    c[1][0][0] = (float)(d.b.x & 0xFFFFu); c[1][0][1] = (float)(d.b.x >> 16);
+    c[1][1][0] = (float)(d.b.y & 0xFFFFu); c[1][1][1] = (float)(d.b.y >> 16);
+  }
+}
+
 // Per-launch constants of the forward step of one fixed voxel.
 struct ParzenFwdStep {
   __amdgpu_buffer_rsrc_t rsrc;
   uint64_t top[3];
   int32_t n[3];
   uint32_t NY, MX;
-  int32_t SZ;  // fp32 quads: bytes to the next slice
+  int32_t SZ;  // bytes to the next slice of quads
   int B;
   float sscale, smax;
 
@@ -267,7 +362,7 @@ struct ParzenFwdStep {
     p.n[2] = a.mnz;
     p.NY = (uint32_t)a.mny;
     p.MX = (uint32_t)a.mnx;
-    p.SZ = FQ ? 16 * a.mnx * a.mny : 0;
+    p.SZ = (FQ ? 16 : 8) * a.mnx * a.mny;
     p.rsrc = __builtin_amdgcn_make_buffer_rsrc((void*)a.gvol, (short)0, (int)a.gvol_bytes, 0x00020000);
     p.B = a.bins;
     p.sscale = a.sscale;
@@ -275,34 +370,54 @@ struct ParzenFwdStep {
     return p;
   }
 
-  // One fixed voxel at exact Q32 moving coordinates q: clamped (CLAMP) or
-  // dropped outside [0, n - 1]; if it lies inside and its slot (from
-  // slot_of()) falls in the band's rows, its four B-spline taps go into the
-  // LDS table.  Returns whether the voxel takes part (inside).
-  template <bool FQ, bool CLAMP, typename SLOT>
-  __device__ __forceinline__ bool add(const int64_t q[3], SLOT&& slot_of, const SweepCtx& sc, int cells,
-                                      int copy, unsigned long long* lds_tab) const {
-    uint32_t cix[3], frac[3];
-    bool inside = true;
+  // Where a fixed voxel at exact Q32 moving coordinates q reads the moving
+  // volume: clamped (CLAMP) or dropped outside [0, n - 1].
+  template <bool CLAMP>
+  __device__ __forceinline__ Loc locate(const int64_t q[3]) const {
+    Loc l;
+    l.inside = true;
+    uint32_t cix[3];
 #pragma unroll
     for (int r = 0; r < 3; ++r) {
       if (CLAMP) {
-        clamp_q32(q[r], n[r], cix[r], frac[r]);
+        clamp_q32(q[r], n[r], cix[r], l.frac[r]);
       } else {
-        inside = inside && (uint64_t)q[r] <= top[r];
+        l.inside = l.inside && (uint64_t)q[r] <= top[r];
         cix[r] = (uint32_t)(q[r] >> 32);
-        frac[r] = (uint32_t)q[r];
+        l.frac[r] = (uint32_t)q[r];
       }
     }
-    if (!inside) return false;
-    const int32_t fb = slot_of();
-    if (fb < sc.r_lo || fb >= sc.r_hi) return true;
-    const uint32_t idx = __umul24(__umul24(cix[2], NY) + cix[1], MX) + cix[0];
+    l.idx = __umul24(__umul24(cix[2], NY) + cix[1], MX) + cix[0];
+    return l;
+  }
+
+  // The voxel's 2x2x2 moving neighbourhood as stored (uint4 octs, or two
+  // float4 quads).
+  template <bool FQ>
+  __device__ __forceinline__ Raw fetch(uint32_t idx) const {
+    Raw d;
+    if (FQ) {
+      d.a = __builtin_amdgcn_raw_buffer_load_b128(rsrc, idx * 16u, 0, 0);
+      d.b = __builtin_amdgcn_raw_buffer_load_b128(rsrc, idx * 16u, SZ, 0);
+    } else {
+      const uint2_t lo = __builtin_amdgcn_raw_buffer_load_b64(rsrc, idx * 8u, 0, 0);
+      const uint2_t hi = __builtin_amdgcn_raw_buffer_load_b64(rsrc, idx * 8u, SZ, 0);
+      d.a = uint4_t{lo.x, lo.y, 0u, 0u};
+      d.b = uint4_t{hi.x, hi.y, 0u, 0u};
+    }
+    return d;
+  }
+
+  // The four B-spline taps of a located, fetched voxel of slot fb (in the
+  // band) into the LDS table.
+  template <bool FQ>
+  __device__ __forceinline__ void taps(const Raw& d, const Loc& l, int32_t fb, const SweepCtx& sc, int cells,
+                                       int copy, unsigned long long* lds_tab) const {
     float c[2][2][2];
-    gather<FQ>(rsrc, idx, SZ, c);
-    const float tx = (float)frac[0] * 2.3283064365386963e-10f;
-    const float ty = (float)frac[1] * 2.3283064365386963e-10f;
-    const float tz = (float)frac[2] * 2.3283064365386963e-10f;
+    unpack<FQ>(d, c);
+    const float tx = (float)l.frac[0] * 2.3283064365386963e-10f;
+    const float ty = (float)l.frac[1] * 2.3283064365386963e-10f;
+    const float tz = (float)l.frac[2] * 2.3283064365386963e-10f;
     const float v0 = lerpf(lerpf(c[0][0][0], c[0][0][1], tx), lerpf(c[0][1][0], c[0][1][1], tx), ty);
     const float v1 = lerpf(lerpf(c[1][0][0], c[1][0][1], tx), lerpf(c[1][1][0], c[1][1][1], tx), ty);
     const float v = lerpf(v0, v1, tz);
@@ -312,35 +427,50 @@ struct ParzenFwdStep {
     bspline_weights(s - fl, wt);
     const unsigned long long q0 = fixed40(wt[0]), q2 = fixed40(wt[2]), q3 = fixed40(wt[3]);
     const unsigned long long q1 = (1ull << 40) - q0 - q2 - q3;  // w1 >= 1/6
-    int base = (fb - sc.r_lo) * B + ((int32_t)fl - 1);
-    if (fb == 0 && copy) base += cells + (copy - 1) * B;  // slot 0: lane's copy of the row
+    const int32_t col0 = (int32_t)fl - 1;
+    int base = (fb - sc.r_lo) * B + col0;
+    // slot 0 (in band 0 only): the lane's copy of the row's hot columns
+    if (fb == 0 && col0 + 3 < parzen_hot_cols(B)) base = cells + copy * parzen_hot_stride(B) + col0;
     unsigned long long* cell = lds_tab + base;
     atomicAdd(cell + 0, q0);
     atomicAdd(cell + 1, q1);
     atomicAdd(cell + 2, q2);
     atomicAdd(cell + 3, q3);
+  }
+
+  // One fixed voxel at exact Q32 moving coordinates q: if it lies inside
+  // (or CLAMP) and its slot falls in the band's rows, its four B-spline taps
+  // go into the LDS table.  Returns whether the voxel took part in this band
+  // (each voxel belongs to one band, so the bands' counts add up to N).
+  template <bool FQ, bool CLAMP>
+  __device__ __forceinline__ bool add(const int64_t q[3], int32_t fb, const SweepCtx& sc, int cells, int copy,
+                                      unsigned long long* lds_tab) const {
+    const Loc l = locate<CLAMP>(q);
+    if (!l.inside || fb < sc.r_lo || fb >= sc.r_hi) return false;
+    taps<FQ>(fetch<FQ>(l.idx), l, fb, sc, cells, copy, lds_tab);
     return true;
   }
 };
 
-// Adds the band's LDS table into the transform's HBM table (fp64) and, from
-// band 0, the count of voxels that took part.
+// Adds the band's LDS table into the transform's HBM table (fp64) and the
+// count of the band's voxels that took part.
 template <int NT>
 __device__ __forceinline__ void flush_parzen(const ParzenArgs& a, const SweepCtx& sc, int cells, int hot_cells,
                                              const unsigned long long* lds_tab, uint32_t lds_count) {
   const int B = a.bins;
   double* __restrict__ out = a.table + (size_t)sc.t * B * B;
+  const int hot_cols = hot_cells ? parzen_hot_cols(B) : 0, hot_stride = parzen_hot_stride(B);
   for (int e = threadIdx.x; e < cells; e += NT) {
     unsigned long long v = lds_tab[e];
-    if (e < hot_cells / (kHotCopies - 1))
-      for (int c = 1; c < kHotCopies; ++c) v += lds_tab[cells + (c - 1) * B + e];
+    if (e < hot_cols)  // slot 0's row is the band's first
+      for (int c = 0; c < kHotCopies; ++c) v += lds_tab[cells + c * hot_stride + e];
     if (v) {
       int col;
       const size_t row = band_cell_row(a.rows, sc.r_lo, e, B, col);
       atomicAdd(&out[row + col], (double)v * 9.094947017729282379150390625e-13);  // 2^-40
     }
   }
-  if (threadIdx.x == 0 && sc.band == 0 && lds_count)
+  if (threadIdx.x == 0 && lds_count)
     atomicAdd((unsigned long long*)&a.count[sc.t], (unsigned long long)lds_count);
 }
 
@@ -356,7 +486,7 @@ __global__ __launch_bounds__(NT) void parzen_fwd_kernel(ParzenArgs a) {
   if (sc.r_lo >= n_slots) return;  // a band past the occupied rows (whole workgroup)
   sc.r_hi = min(n_slots, sc.r_lo + a.band_rows);
   const int cells = (sc.r_hi - sc.r_lo) * B;
-  const int hot_cells = sc.r_lo == 0 ? (kHotCopies - 1) * B : 0;  // extra copies of slot 0
+  const int hot_cells = sc.r_lo == 0 ? parzen_hot_cells(B) : 0;  // copies of slot 0's hot columns
   for (int e = threadIdx.x; e < cells + hot_cells; e += NT) lds_tab[e] = 0ull;
   if (threadIdx.x == 0) lds_count = 0;
   int64_t Mq[12];
@@ -371,27 +501,32 @@ __global__ __launch_bounds__(NT) void parzen_fwd_kernel(ParzenArgs a) {
     GroupWalk w;
     w.init(Mq, a.fny, a.fnz, a.chunks, sc.chunk, wave, NT / 64, dx, dy);
     const ParzenFwdStep ps = ParzenFwdStep::template make<FQ>(a);
+    const int32_t XT = (a.fnx + kTileX - 1) / kTileX;
+    const uint32_t band_groups = slot_group_mask(sc.r_lo, sc.r_hi);
     for (; w.g < w.g1; w.next()) {
       const int32_t j = w.j0 + dy;
-      if (j >= a.fny) continue;
-      const uint8_t* __restrict__ frow = a.fbins + ((int64_t)w.k * a.fny + j) * a.fnx;
+      const bool row_ok = j < a.fny;
+      const uint8_t* __restrict__ frow = a.fbins + ((int64_t)w.k * a.fny + (row_ok ? j : 0)) * a.fnx;
+      const uint32_t* __restrict__ tmask = a.tile_mask + (int64_t)w.g * XT;
       int64_t q[3];
 #pragma unroll
       for (int r = 0; r < 3; ++r) q[r] = w.r[r] + w.lane_off[r];
-      // each voxel's fixed bin is loaded one step ahead: the band test then
-      // waits on a load issued a voxel earlier, not on a fresh one before the
-      // gather can start
-      int32_t fb_next = dx < a.fnx ? (int32_t)frow[dx] : 0;
-      for (int x = dx; x < a.fnx; x += kTileX) {
+      // the wave's tiles in x, a uniform trip count: a tile without slots of
+      // this band is skipped whole; each voxel's fixed bin is loaded one
+      // step ahead, so the band test waits on a load issued a tile earlier
+      int32_t fb_next = row_ok && dx < a.fnx ? (int32_t)frow[dx] : -1;
+      for (int32_t ti = 0; ti < XT; ++ti) {
+        const int32_t x = ti * kTileX + dx;
         const int32_t fbv = fb_next;
-        if (x + kTileX < a.fnx) fb_next = (int32_t)frow[x + kTileX];
-        taken += ps.add<FQ, CLAMP>(q, [&] { return fbv; }, sc, cells, copy, lds_tab);
+        if (row_ok && x + kTileX < a.fnx) fb_next = (int32_t)frow[x + kTileX];
+        if ((tmask[ti] & band_groups) && fbv >= 0 && x < a.fnx)
+          taken += ps.add<FQ, CLAMP>(q, fbv, sc, cells, copy, lds_tab);
 #pragma unroll
         for (int r = 0; r < 3; ++r) q[r] += w.step[r];
       }
     }
   }
-  if (sc.band == 0 && taken) atomicAdd(&lds_count, taken);
+  if (taken) atomicAdd(&lds_count, taken);
   __syncthreads();
   if (!ok) return;
   flush_parzen<NT>(a, sc, cells, hot_cells, lds_tab, lds_count);
@@ -413,7 +548,7 @@ __global__ __launch_bounds__(NT) void parzen_sampled_fwd_kernel(ParzenArgs a, co
   if (sc.r_lo >= n_slots) return;  // a band past the occupied rows (whole workgroup)
   sc.r_hi = min(n_slots, sc.r_lo + a.band_rows);
   const int cells = (sc.r_hi - sc.r_lo) * B;
-  const int hot_cells = sc.r_lo == 0 ? (kHotCopies - 1) * B : 0;
+  const int hot_cells = sc.r_lo == 0 ? parzen_hot_cells(B) : 0;
   for (int e = threadIdx.x; e < cells + hot_cells; e += NT) lds_tab[e] = 0ull;
   if (threadIdx.x == 0) lds_count = 0;
   int64_t Mq[12];
@@ -432,10 +567,10 @@ __global__ __launch_bounds__(NT) void parzen_sampled_fwd_kernel(ParzenArgs a, co
       int64_t q[3];
 #pragma unroll
       for (int r = 0; r < 3; ++r) q[r] = Mq[4 * r] * x + Mq[4 * r + 1] * y + Mq[4 * r + 2] * z + Mq[4 * r + 3];
-      taken += ps.add<FQ, CLAMP>(q, [&] { return slot; }, sc, cells, copy, lds_tab);
+      taken += ps.add<FQ, CLAMP>(q, slot, sc, cells, copy, lds_tab);
     }
   }
-  if (sc.band == 0 && taken) atomicAdd(&lds_count, taken);
+  if (taken) atomicAdd(&lds_count, taken);
   __syncthreads();
   if (!ok) return;
   flush_parzen<NT>(a, sc, cells, hot_cells, lds_tab, lds_count);
@@ -558,22 +693,31 @@ __global__ __launch_bounds__(NT) void parzen_bwd_kernel(ParzenArgs a) {
     const uint64_t top[3] = {(uint64_t)(a.mnx - 1) << 32, (uint64_t)(a.mny - 1) << 32,
                              (uint64_t)(a.mnz - 1) << 32};
     const uint32_t NY = (uint32_t)a.mny, MX = (uint32_t)a.mnx;
-    const int32_t SZ = FQ ? 16 * a.mnx * a.mny : 0;  // fp32 quads: next slice
+    const int32_t SZ = (FQ ? 16 : 8) * a.mnx * a.mny;  // quads: next slice
     const __amdgpu_buffer_rsrc_t rsrc =
         __builtin_amdgcn_make_buffer_rsrc((void*)a.gvol, (short)0, (int)a.gvol_bytes, 0x00020000);
     const float smax = (float)(B - 3);
+    const int32_t XT = (a.fnx + kTileX - 1) / kTileX;
+    const uint32_t band_groups = slot_group_mask(sc.r_lo, sc.r_hi);
     for (; w.g < w.g1; w.next()) {
       const int32_t j = w.j0 + dy;
-      if (j >= a.fny) continue;
-      const uint8_t* __restrict__ frow = a.fbins + ((int64_t)w.k * a.fny + j) * a.fnx;
+      const bool row_ok = j < a.fny;
+      const uint8_t* __restrict__ frow = a.fbins + ((int64_t)w.k * a.fny + (row_ok ? j : 0)) * a.fnx;
+      const uint32_t* __restrict__ tmask = a.tile_mask + (int64_t)w.g * XT;
       const float fj = (float)j, fk = (float)w.k;
       int64_t q[3];
 #pragma unroll
       for (int r = 0; r < 3; ++r) q[r] = w.r[r] + w.lane_off[r];
-      int32_t fb_next = dx < a.fnx ? (int32_t)frow[dx] : 0;  // one step ahead, as in the forward
-      for (int x = dx; x < a.fnx; x += kTileX) {
+      int32_t fb_next = row_ok && dx < a.fnx ? (int32_t)frow[dx] : -1;  // one step ahead, as in the forward
+      for (int32_t ti = 0; ti < XT; ++ti) {
+        const int32_t x = ti * kTileX + dx;
         const int32_t fbv = fb_next;
-        if (x + kTileX < a.fnx) fb_next = (int32_t)frow[x + kTileX];
+        if (row_ok && x + kTileX < a.fnx) fb_next = (int32_t)frow[x + kTileX];
+        if (!(tmask[ti] & band_groups) || fbv < 0 || x >= a.fnx) {  // a tile without this band's slots
+#pragma unroll
+          for (int r = 0; r < 3; ++r) q[r] += w.step[r];
+          continue;
+        }
         uint32_t cell[3], frac[3];
         bool inside = true, moves[3];
 #pragma unroll
@@ -658,12 +802,12 @@ __global__ __launch_bounds__(NT) void parzen_bwd_kernel(ParzenArgs a) {
 // launchers
 // ---------------------------------------------------------------------------
 
-template <bool FQ, bool CLAMP>
+template <bool FQ, bool CLAMP, int NT>
 static hipError_t fwd_variant(const ParzenArgs& a, size_t lds, hipStream_t s) {
-  const hipError_t e = lds_guard((const void*)parzen_fwd_kernel<FQ, CLAMP, 512>, lds, kParzenLdsMax);
+  const hipError_t e = lds_guard((const void*)parzen_fwd_kernel<FQ, CLAMP, NT>, lds, kParzenLdsMax);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((parzen_fwd_kernel<FQ, CLAMP, 512>), dim3((unsigned)(a.n * a.chunks * a.bands)),
-                     dim3(512), lds, s, a);
+  hipLaunchKernelGGL((parzen_fwd_kernel<FQ, CLAMP, NT>), dim3((unsigned)(a.n * a.chunks * a.bands)), dim3(NT),
+                     lds, s, a);
   return hipGetLastError();
 }
 
@@ -683,8 +827,8 @@ static ParzenArgs sub_batch(const ParzenArgs& a, int32_t t0, int32_t n) {
 }
 
 template <typename F>
-static hipError_t in_launches(const ParzenArgs& a, F&& launch) {
-  const int32_t step = transforms_per_launch((int64_t)a.chunks * a.bands, 512);
+static hipError_t in_launches(const ParzenArgs& a, int32_t block, F&& launch) {
+  const int32_t step = transforms_per_launch((int64_t)a.chunks * a.bands, block);
   for (int32_t t0 = 0; t0 < a.n; t0 += step) {
     const hipError_t e = launch(sub_batch(a, t0, a.n - t0 < step ? a.n - t0 : step));
     if (e != hipSuccess) return e;
@@ -692,34 +836,52 @@ static hipError_t in_launches(const ParzenArgs& a, F&& launch) {
   return hipSuccess;
 }
 
+// Calls f.template operator()<NT>() for the launch's workgroup size.
+template <typename F>
+static hipError_t by_block(int32_t block, F&& f) {
+  switch (block) {
+  case 256: return f.template operator()<256>();
+  case 1024: return f.template operator()<1024>();
+  default: return f.template operator()<512>();
+  }
+}
+
+static int32_t block_of(const ParzenLaunch& L) {
+  return (L.block == 256 || L.block == 1024) ? L.block : 512;
+}
+
 hipError_t launch_parzen_fwd(const ParzenLaunch& L, hipStream_t s) {
-  const size_t lds = (size_t)(L.args.band_rows + kHotCopies - 1) * L.args.bins * 8;
-  return in_launches(L.args, [&](const ParzenArgs& a) {
-    if (L.float_quads)
-      return L.clamp ? fwd_variant<true, true>(a, lds, s) : fwd_variant<true, false>(a, lds, s);
-    return L.clamp ? fwd_variant<false, true>(a, lds, s) : fwd_variant<false, false>(a, lds, s);
+  const size_t lds = ((size_t)L.args.band_rows * L.args.bins + parzen_hot_cells(L.args.bins)) * 8;
+  return in_launches(L.args, block_of(L), [&](const ParzenArgs& a) {
+    return by_block(L.block, [&]<int NT>() {
+      if (L.float_quads)
+        return L.clamp ? fwd_variant<true, true, NT>(a, lds, s) : fwd_variant<true, false, NT>(a, lds, s);
+      return L.clamp ? fwd_variant<false, true, NT>(a, lds, s) : fwd_variant<false, false, NT>(a, lds, s);
+    });
   });
 }
 
-template <bool FQ, bool CLAMP>
+template <bool FQ, bool CLAMP, int NT>
 static hipError_t sampled_fwd_variant(const ParzenArgs& a, const uint2* list, const unsigned long long* n_list,
                                       size_t lds, hipStream_t s) {
-  const hipError_t e = lds_guard((const void*)parzen_sampled_fwd_kernel<FQ, CLAMP, 512>, lds, kParzenLdsMax);
+  const hipError_t e = lds_guard((const void*)parzen_sampled_fwd_kernel<FQ, CLAMP, NT>, lds, kParzenLdsMax);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((parzen_sampled_fwd_kernel<FQ, CLAMP, 512>), dim3((unsigned)(a.n * a.chunks * a.bands)),
-                     dim3(512), lds, s, a, list, n_list);
+  hipLaunchKernelGGL((parzen_sampled_fwd_kernel<FQ, CLAMP, NT>), dim3((unsigned)(a.n * a.chunks * a.bands)),
+                     dim3(NT), lds, s, a, list, n_list);
   return hipGetLastError();
 }
 
 hipError_t launch_parzen_sampled_fwd(const ParzenLaunch& L, const uint2* list, const unsigned long long* n_list,
                                      hipStream_t s) {
-  const size_t lds = (size_t)(L.args.band_rows + kHotCopies - 1) * L.args.bins * 8;
-  return in_launches(L.args, [&](const ParzenArgs& a) {
-    if (L.float_quads)
-      return L.clamp ? sampled_fwd_variant<true, true>(a, list, n_list, lds, s)
-                     : sampled_fwd_variant<true, false>(a, list, n_list, lds, s);
-    return L.clamp ? sampled_fwd_variant<false, true>(a, list, n_list, lds, s)
-                   : sampled_fwd_variant<false, false>(a, list, n_list, lds, s);
+  const size_t lds = ((size_t)L.args.band_rows * L.args.bins + parzen_hot_cells(L.args.bins)) * 8;
+  return in_launches(L.args, block_of(L), [&](const ParzenArgs& a) {
+    return by_block(L.block, [&]<int NT>() {
+      if (L.float_quads)
+        return L.clamp ? sampled_fwd_variant<true, true, NT>(a, list, n_list, lds, s)
+                       : sampled_fwd_variant<true, false, NT>(a, list, n_list, lds, s);
+      return L.clamp ? sampled_fwd_variant<false, true, NT>(a, list, n_list, lds, s)
+                     : sampled_fwd_variant<false, false, NT>(a, list, n_list, lds, s);
+    });
   });
 }
 
@@ -737,37 +899,47 @@ hipError_t launch_dmi_dp(const ParzenLaunch& L, const QList& q, hipStream_t s) {
   return hipSuccess;
 }
 
-template <bool FQ, bool CLAMP>
+template <bool FQ, bool CLAMP, int NT>
 static hipError_t bwd_variant(const ParzenArgs& a, size_t lds, hipStream_t s) {
-  const hipError_t e = lds_guard((const void*)parzen_bwd_kernel<FQ, CLAMP, 2, 512>, lds, kParzenLdsMax);
+  const hipError_t e = lds_guard((const void*)parzen_bwd_kernel<FQ, CLAMP, 2, NT>, lds, kParzenLdsMax);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((parzen_bwd_kernel<FQ, CLAMP, 2, 512>), dim3((unsigned)(a.n * a.chunks * a.bands)),
-                     dim3(512), lds, s, a);
+  hipLaunchKernelGGL((parzen_bwd_kernel<FQ, CLAMP, 2, NT>), dim3((unsigned)(a.n * a.chunks * a.bands)), dim3(NT),
+                     lds, s, a);
   return hipGetLastError();
 }
 
 hipError_t launch_parzen_bwd(const ParzenLaunch& L, hipStream_t s) {
   const size_t lds = (size_t)kParzenQGroup * L.args.band_rows * L.args.bins * 4;
-  return in_launches(L.args, [&](const ParzenArgs& a) {
-    if (L.float_quads)
-      return L.clamp ? bwd_variant<true, true>(a, lds, s) : bwd_variant<true, false>(a, lds, s);
-    return L.clamp ? bwd_variant<false, true>(a, lds, s) : bwd_variant<false, false>(a, lds, s);
+  return in_launches(L.args, block_of(L), [&](const ParzenArgs& a) {
+    return by_block(L.block, [&]<int NT>() {
+      if (L.float_quads)
+        return L.clamp ? bwd_variant<true, true, NT>(a, lds, s) : bwd_variant<true, false, NT>(a, lds, s);
+      return L.clamp ? bwd_variant<false, true, NT>(a, lds, s) : bwd_variant<false, false, NT>(a, lds, s);
+    });
   });
 }
 
 // The bands are sized for at most kParzenLdsMax of dynamic LDS per
 // workgroup.
-template <bool FQ, bool CLAMP>
-static hipError_t allow_lds() {
+template <bool FQ, bool CLAMP, int NT>
+static hipError_t allow_lds_nt() {
   const int bytes = (int)kParzenLdsMax;
-  const void* fns[3] = {(const void*)parzen_fwd_kernel<FQ, CLAMP, 512>,
-                        (const void*)parzen_sampled_fwd_kernel<FQ, CLAMP, 512>,
-                        (const void*)parzen_bwd_kernel<FQ, CLAMP, 2, 512>};
+  const void* fns[3] = {(const void*)parzen_fwd_kernel<FQ, CLAMP, NT>,
+                        (const void*)parzen_sampled_fwd_kernel<FQ, CLAMP, NT>,
+                        (const void*)parzen_bwd_kernel<FQ, CLAMP, 2, NT>};
   for (const void* f : fns) {
     hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
     if (e != hipSuccess || (e = lds_register(f)) != hipSuccess) return e;
   }
   return hipSuccess;
+}
+
+template <bool FQ, bool CLAMP>
+static hipError_t allow_lds() {
+  hipError_t e;
+  if ((e = allow_lds_nt<FQ, CLAMP, 256>()) != hipSuccess) return e;
+  if ((e = allow_lds_nt<FQ, CLAMP, 512>()) != hipSuccess) return e;
+  return allow_lds_nt<FQ, CLAMP, 1024>();
 }
 
 hipError_t configure_parzen_kernels() {

@@ -199,8 +199,10 @@ def test_workspace_size_layout():
     # a wider range: 16-bit corners, 16 bytes per voxel
     st, n = ws_size(vol(10, 11, 12), vol(9, 8, 7, dtype=B.U16, lo=0.0, hi=4095.0), 5, 32, 2)
     assert st == 0 and n == xf + a(10 * 11 * 12) + a(9 * 8 * 7 * 16) + a(5 * 32 * 32 * 4) + a(5 * 8) + part
-    octs = a(8 * 8 * 8 * 16)
-    rowmap = a(3 * 256 * 4 + 4)   # occupied fixed-bin rows: used, row_of_slot, slot_of_row, n_slots
+    octs = a(8 * 8 * 9 * 8)  # Parzen: 16-bit quads, 8 bytes per voxel, one extra slice
+    # occupied fixed-bin rows (used, row_of_slot, slot_of_row, n_slots), then
+    # one u32 slot-group mask per 16 x 4 wave tile of the fixed volume
+    rowmap = a(3 * 256 * 4 + 4) + a(4 * ((11 + 3) // 4) * 12 * ((10 + 15) // 16))
     st, n = ws_size(vol(10, 11, 12), vol(), 5, 32, 2, B.HIST_PARZEN)
     assert st == 0 and n == xf + a(1320) + octs + rowmap + a(5 * 32 * 32 * 8) + a(5 * 8) + part
     st, n = ws_size(vol(10, 11, 12), vol(), 5, 32, 2, B.GRADIENT)
@@ -302,8 +304,19 @@ def test_tune_validation():
     lib = B.load()
     f, m = vol(), vol()
     assert lib.mi_tune(None, ctypes.byref(f), ctypes.byref(m), FAKE, 4, 32, 0, FAKE, 1 << 40, None) == B.MI_ERR_NULL
+    # Parzen tuning: valid arguments reach the context check; a workspace
+    # sized for one entropy's gradient is too small (it needs n_q = 2)
     assert lib.mi_tune(None, ctypes.byref(f), ctypes.byref(m), FAKE, 4, 32, B.HIST_PARZEN, FAKE, 1 << 40,
-                       None) == B.MI_ERR_UNSUPPORTED
+                       None) == B.MI_ERR_NULL
+    st, one = ws_size(f, m, 4, 32, 1, B.HIST_PARZEN | B.GRADIENT)
+    st2, two = ws_size(f, m, 4, 32, 2, B.HIST_PARZEN | B.GRADIENT)
+    assert st == st2 == 0 and two > one
+    assert lib.mi_tune(None, ctypes.byref(f), ctypes.byref(m), FAKE, 4, 32, B.HIST_PARZEN, FAKE, one,
+                       None) == B.MI_ERR_WORKSPACE
+    assert lib.mi_tune(None, ctypes.byref(f), ctypes.byref(m), FAKE, 4, 32, B.HIST_PARZEN, FAKE, two,
+                       None) == B.MI_ERR_NULL
+    assert lib.mi_tune(None, ctypes.byref(f), ctypes.byref(m), FAKE, 4, 32, B.SAMPLED, FAKE, 1 << 40,
+                       None) == B.MI_ERR_FLAGS
     assert lib.mi_tune(None, ctypes.byref(f), ctypes.byref(m), FAKE, 4, 1, 0, FAKE, 1 << 40, None) == B.MI_ERR_BINS
 
 

@@ -287,3 +287,50 @@ def test_pairs_preparation_reuse(ctx):
         assert np.array_equal(out.cpu().numpy(), fresh), f"replay {rep}"
         ctx.eval_pairs(Bp, 32, q, workspace=ws)  # eager work between replays: prepares B in the workspace
         torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("forced", [None, "512 32 1024 128 -1", "1024 64 512 16 1", "256 96 256 64 0"])
+def test_parzen_tune_and_shapes_keep_results(tmp_path, forced):
+    """mi_tune with MI_HIST_PARZEN picks forward and backward launch shapes;
+    MI and gradients after tuning, and under shapes forced through the cache
+    file (workgroup sizes, LDS band budgets, workgroup counts), match the
+    default shape's: MI to the last bits (merge order of fp64 partial sums),
+    gradients to the fp32 rounding of the per-lane partial sums, whose
+    grouping follows the shape (1e-6 of the largest entry)."""
+    import torch
+    from paper_1909_10690_amd import binding as B
+    print(f"[tune] parzen forced={forced}", flush=True)
+    path = tmp_path / "tune.txt"
+    os.environ["MI_TUNE_CACHE"] = str(path)
+    try:
+        ctx = B.Context(0)
+        rng = np.random.default_rng(71)
+        shape = (70, 52, 40)
+        lab = inputs.render_labels(shape)
+        f = inputs.intensities(lab, (0, 600, 1600, 2400), rng, 40.0, True, 0, 4095, np.uint16)
+        m = inputs.intensities(lab, (0, 3600, 2000, 1200), rng, 40.0, True, 0, 4095, np.uint16)
+        F, M = B.Volume.from_numpy(f, 0, 4095), B.Volume.from_numpy(m, 0, 4095)
+        tr = torch.from_numpy(inputs.random_affines(rng, 3, shape, rot=6, trans=3)).cuda()
+        q = [1.0, 1.3]
+        fl = B.BOUNDARY_CLAMP
+        ref_mi, ref_g = ctx.grad(F, M, tr, 256, q, flags=fl)
+        ref_mi, ref_g = ref_mi.cpu().numpy(), ref_g.cpu().numpy()
+        ctx.tune(F, M, tr, 256, flags=fl | B.HIST_PARZEN)
+        lines = [l for l in path.read_text().splitlines() if l.startswith("gemi-tune-parzen")]
+        assert len(lines) == 1
+        fields = lines[0].split()
+        assert fields[1:4] == ["70", "52", "40"] and fields[11] in ("512", "1024") and fields[13] in ("512", "1024")
+        if forced:
+            path.write_text(" ".join(fields[:11] + forced.split()) + "\n")
+            ctx.close()
+            ctx = B.Context(0)
+        mi, g = ctx.grad(F, M, tr, 256, q, flags=fl)
+        mi2, _, _ = ctx.eval(F, M, tr, 256, q, flags=fl | B.HIST_PARZEN)
+        torch.cuda.synchronize()
+        for a in (mi.cpu().numpy(), mi2.cpu().numpy()):
+            np.testing.assert_allclose(a, ref_mi, rtol=1e-12, atol=1e-15)
+        scale = np.abs(ref_g).max(axis=2, keepdims=True)
+        assert (np.abs(g.cpu().numpy() - ref_g) <= 1e-6 * scale).all()
+        ctx.close()
+    finally:
+        del os.environ["MI_TUNE_CACHE"]
