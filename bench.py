@@ -20,6 +20,7 @@ import argparse
 import json
 import os
 import sys
+import tempfile
 import time
 
 import numpy as np
@@ -35,6 +36,27 @@ PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "hist_hard_multimodal_traffic.t
 
 def log(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+_SHAPE_FIELDS = {"gemi-tune": ("block", "slab_major", "chunks", "packed"),
+                 "gemi-tune-parzen": ("fwd_block", "fwd_lds_kib", "bwd_block", "bwd_lds_kib", "chunk_shift"),
+                 "gemi-tune-pairs": ("block", "slab_voxels", "packed", "transform_major")}
+
+
+def tuned_shape(B, cache: str, kind: str, **key) -> dict | None:
+    """The launch shape the tuner recorded last for the problem class whose
+    key fields include ``key`` (None if it recorded none)."""
+    hit = None
+    for e in B.read_tune_cache(cache):
+        if e["kind"] == kind and all(e.get(k) == v for k, v in key.items()):
+            hit = e
+    return None if hit is None else {f: hit[f] for f in _SHAPE_FIELDS[kind]}
+
+
+def shape_source(args, shape) -> str:
+    if shape is None:
+        return "default (no tuned entry)"
+    return "MI_TUNE_CACHE entry" if args.no_tune else "tuned in this run"
 
 
 def algorithmic_bytes_per_voxel_xform(fixed, moving, mats, bins) -> float:
@@ -140,7 +162,7 @@ def plain_sweep_leg(ctx, B, inputs, dev, steps: int) -> dict:
                       "Shannon, 21 x-translations in [-10, 10]"}
 
 
-def grad_leg(ctx, B, inputs, dev, args) -> dict:
+def grad_leg(ctx, B, inputs, dev, args, cache: str) -> dict:
     """MI-grad evaluations per second: mi_grad (Parzen forward, MI, dMI/dp,
     backward) over the 128^3 f32 workload's 64 random affines, 64 bins,
     Shannon and Tsallis q = 1.5."""
@@ -153,7 +175,11 @@ def grad_leg(ctx, B, inputs, dev, args) -> dict:
     flags = B.BOUNDARY_CLAMP
     ws = torch.empty(ctx.workspace_size(F, M, n, bins, len(q), flags | B.HIST_PARZEN | B.GRADIENT),
                      dtype=torch.uint8, device=dev)
-    log(f"gradient leg: {n} transforms x 128^3 f32, {bins} Parzen bins")
+    log(f"gradient leg: {n} transforms x 128^3 f32, {bins} Parzen bins; tuning the Parzen sweeps")
+    if not args.no_tune:
+        ctx.tune(F, M, tr, bins, flags | B.HIST_PARZEN, workspace=ws)
+    shape = tuned_shape(B, cache, "gemi-tune-parzen", fnx=g["fixed"].shape[2], bins=bins,
+                        n_bucket=(n - 1).bit_length())
     for _ in range(2):
         ctx.grad(F, M, tr, bins, q, flags=flags, workspace=ws)
     torch.cuda.synchronize()
@@ -182,11 +208,12 @@ def grad_leg(ctx, B, inputs, dev, args) -> dict:
             "roofline": {"bound": "hbm", "algorithmic_bytes_per_voxel_xform_per_sweep": balg,
                          "fwd_frac": frac(fwd_k), "bwd_frac": frac(bwd_k),
                          "fwd_plus_bwd_frac": 2 * balg * vox / ((fwd_k + bwd_k) * 1e-3) / 1e9 / HBM_PEAK_GBS},
+            "launch": {"parzen_shape": shape, "shape_source": shape_source(args, shape)},
             "config": "128^3 f32 phantoms, 64 random affines, 64-bin cubic B-spline Parzen "
                       "histogram, Shannon + Tsallis q=1.5, clamp boundary"}
 
 
-def register_leg(ctx, B, inputs, dev, steps: int = 200) -> dict:
+def register_leg(ctx, B, inputs, dev, args, cache: str, steps: int = 200) -> dict:
     """Gradient-ascent registration of the 512x512x300 i16 CT-like phantom to
     the 256^3 u16 MR-like one (2 mm spacing), 256 Parzen bins, from a known
     misregistration (rot_z 6 deg, t (8, -5, 4) mm, scale 1.04; the truth is
@@ -196,7 +223,7 @@ def register_leg(ctx, B, inputs, dev, steps: int = 200) -> dict:
     import numpy as np
     import torch
     from paper_1909_10690_amd import transforms as T
-    from paper_1909_10690_amd.register import register
+    from paper_1909_10690_amd.register import register, volume_centre
     log("register leg: building the 512x512x300 / 256^3 CT-MR pair")
     c = inputs.ct_mr_pair()
     F = B.Volume.from_numpy(c["fixed"], *c["fixed_range"], dev, spacing=c["fixed_spacing"])
@@ -204,6 +231,11 @@ def register_leg(ctx, B, inputs, dev, steps: int = 200) -> dict:
                             origin=c["moving_origin"])
     st = c["start"]
     p0 = T.params_from(T.affine_matrix(st["angles"], st["scale"]), st["t"])
+    log("register leg: tuning the Parzen sweeps at the start transform")
+    P0 = T.centred_matrix(p0[:9], p0[9:], volume_centre(F)).reshape(1, 12)
+    if not args.no_tune:
+        ctx.tune(F, M, torch.from_numpy(P0).to(dev), c["bins"], B.BOUNDARY_CLAMP | B.HIST_PARZEN)
+    shape = tuned_shape(B, cache, "gemi-tune-parzen", fnx=c["fixed"].shape[2], bins=c["bins"], n_bucket=0)
     register(ctx, F, M, c["bins"], p0, steps=3, q_translation=c["q"][0], param="decomposed")
     torch.cuda.synchronize()
     log(f"register leg: {steps} iterations")
@@ -244,34 +276,61 @@ def register_leg(ctx, B, inputs, dev, steps: int = 200) -> dict:
             "roofline": {"bound": "hbm", "algorithmic_bytes_per_voxel_per_sweep": balg,
                          "fwd_frac": frac(fwd_k), "bwd_frac": frac(bwd_k),
                          "fwd_plus_bwd_frac": 2 * balg * nvox / ((fwd_k + bwd_k) * 1e-3) / 1e9 / HBM_PEAK_GBS},
+            "launch": {"parzen_shape": shape, "shape_source": shape_source(args, shape)},
             "config": "fixed 512x512x300 i16 CT-like (1 mm), moving 256^3 u16 MR-like (2 mm), "
                       "256-bin cubic B-spline Parzen, Shannon + Tsallis q=1.3, clamp boundary, "
                       "Adam over angles / log-scales / shears / translation"}
 
 
-def pairs_leg(ctx, B, inputs, dev) -> dict:
-    """256 uneven u8 pairs x 16 rigid transforms, 64 bins, one persistent launch."""
+def pairs_leg(ctx, B, inputs, dev, args, cache: str) -> dict:
+    """256 uneven u8 pairs x 16 rigid transforms, 64 bins, one persistent
+    launch: the launch shape tuned first (mi_tune_pairs), kernel time from
+    eager calls, then the call replayed as a HIP graph with the pairs'
+    preparation reused (MI_USE_GRAPH | MI_VOLUMES_UNCHANGED)."""
     import torch
     log("pairs leg: generating 256 uneven pairs")
     raw = inputs.uneven_pairs()
     pairs = [(B.Volume.from_numpy(p["fixed"], 0, 255, dev), B.Volume.from_numpy(p["moving"], 0, 255, dev),
               torch.from_numpy(p["transforms"]).to(dev)) for p in raw]
     vox = sum(p["fixed"].size for p in raw) * 16
+    bins = 64
+    ws = torch.empty(ctx.pairs_workspace_size(pairs, bins, 1), dtype=torch.uint8, device=dev)
+    out = torch.empty((16 * len(pairs), 1), dtype=torch.float64, device=dev)
+    if not args.no_tune:
+        log("pairs leg: tuning the persistent launch")
+        ctx.tune_pairs(pairs, bins, workspace=ws)
+    shape = tuned_shape(B, cache, "gemi-tune-pairs", bins=bins)
     for _ in range(2):
-        ctx.eval_pairs(pairs, 64, [1.0])
+        ctx.eval_pairs(pairs, bins, [1.0], workspace=ws, out=out)
     torch.cuda.synchronize()
+    ref = out.clone()
     ctx.timing_read(B.TIMER_PAIRS)
     ctx.timing(True)
-    steps = 3
+    steps = 5
     t0 = time.perf_counter()
     for _ in range(steps):
-        ctx.eval_pairs(pairs, 64, [1.0])
+        ctx.eval_pairs(pairs, bins, [1.0], workspace=ws, out=out)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     ctx.timing(False)
     k_ms, k_n = ctx.timing_read(B.TIMER_PAIRS)
-    return {"value": vox * steps / dt, "unit": "voxel-transform evals/s", "ms_per_call": dt / steps * 1e3,
+    gs = torch.cuda.Stream()
+    gflags = B.USE_GRAPH | B.VOLUMES_UNCHANGED
+    out.zero_()
+    torch.cuda.synchronize()
+    for _ in range(2):
+        ctx.eval_pairs(pairs, bins, [1.0], flags=gflags, workspace=ws, out=out, stream=gs)
+    gs.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ctx.eval_pairs(pairs, bins, [1.0], flags=gflags, workspace=ws, out=out, stream=gs)
+    gs.synchronize()
+    gdt = time.perf_counter() - t0
+    return {"value": vox * steps / gdt, "unit": "voxel-transform evals/s", "ms_per_call": gdt / steps * 1e3,
             "kernel_ms": k_ms / max(k_n, 1), "voxel_transforms": int(vox),
+            "eager": {"value": vox * steps / dt, "ms_per_call": dt / steps * 1e3},
+            "launch": {"pairs_shape": shape, "shape_source": shape_source(args, shape),
+                       "graph": True, "volumes_unchanged": True, "mi_identical": bool(torch.equal(out, ref))},
             "config": "256 u8 pairs, edges from {64,96,128,160,192,256} per axis, 16 rigid transforms "
                       "each, 64 bins, Shannon"}
 
@@ -352,6 +411,9 @@ def main() -> int:
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="minimum wall time of the CPU-oracle sample")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle leg")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="skip the launch-shape tuners (shapes then come from the MI_TUNE_CACHE file, "
+                         "if the caller names one, else the defaults); for profiled runs")
     ap.add_argument("--no-extras", action="store_true", help="skip the plain-path and gradient legs")
     ap.add_argument("--pairs", action="store_true",
                     help="time the 256 uneven pairs in one launch even with --no-extras")
@@ -381,6 +443,14 @@ def main() -> int:
     c = inputs.multimodal_sweep()
     fixed, moving, mats = c["fixed"], c["moving"], c["transforms"]
     n, bins, q = len(mats), c["bins"], c["q"]
+    # the tuners record their choices in MI_TUNE_CACHE; a private file unless
+    # the caller names one, so that the line can say which shapes ran
+    own_cache = "MI_TUNE_CACHE" not in os.environ
+    if own_cache:
+        fd, cache = tempfile.mkstemp(prefix="gemi-tune-", suffix=".txt")
+        os.close(fd)
+        os.environ["MI_TUNE_CACHE"] = cache
+    cache = os.environ["MI_TUNE_CACHE"]
     ctx = B.Context(0)
     dev = "cuda:0"
     F = B.Volume.from_numpy(fixed, *c["fixed_range"], dev)
@@ -392,6 +462,12 @@ def main() -> int:
     def step():
         ctx.eval(F, Mv, tr, bins, q, out=out, want_overlap=False, workspace=ws)
 
+    if not args.no_tune:
+        log("tuning the hard sweep's launch shape for this problem class")
+        ctx.tune(F, Mv, tr, bins, workspace=ws)
+    hard_shape = tuned_shape(B, cache, "gemi-tune", fnx=fixed.shape[2], bins=bins, mnx=moving.shape[2],
+                             n_bucket=(n - 1).bit_length())
+    log(f"tuned shape: {hard_shape}")
     log(f"warmup {args.warmup} steps")
     for _ in range(args.warmup):
         step()
@@ -435,6 +511,32 @@ def main() -> int:
                      "kernel": "hist_hard_kernel<uint16_t>", "kernel_ms": k_avg_ms,
                      "algorithmic_bytes_per_voxel_xform": balg},
     }
+
+    # the same step replayed as a HIP graph (MI_USE_GRAPH) on a side stream;
+    # graph replays carry no per-launch events, so this pass has wall time
+    # only, and its MI must equal the eager step's bit for bit
+    ref_out = out.clone()
+    gs = torch.cuda.Stream()
+
+    def gstep():
+        ctx.eval(F, Mv, tr, bins, q, flags=B.USE_GRAPH, out=out, want_overlap=False, workspace=ws, stream=gs)
+
+    log(f"graph replay: {args.steps} steps")
+    out.zero_()
+    torch.cuda.synchronize()
+    for _ in range(max(2, args.warmup)):
+        gstep()
+    gs.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        gstep()
+    gs.synchronize()
+    gdt = time.perf_counter() - t0
+    result["launch"] = {
+        "hist_shape": hard_shape, "shape_source": shape_source(args, hard_shape),
+        "timed_region": "eager mi_eval calls on the default stream, HIP events around each kernel",
+        "graph": {"ms_per_step": gdt / args.steps * 1e3, "value": vox_xf * args.steps / gdt,
+                  "vs_eager": dt / gdt, "mi_identical": bool(torch.equal(out, ref_out))}}
 
     # LDS-atomic rate of the sweep (one 32-bit LDS add per counted voxel)
     # against the measured peak of conflict-free LDS adds on this device
@@ -482,15 +584,15 @@ def main() -> int:
                                                     "batched_speedup": value / plain}
 
     if not args.no_extras:
-        result["mi_grad"] = grad_leg(ctx, B, inputs, dev, args)
+        result["mi_grad"] = grad_leg(ctx, B, inputs, dev, args, cache)
         result["plain_sweep"] = plain_sweep_leg(ctx, B, inputs, dev, args.steps)
 
     if (args.pairs or not args.no_extras) and not args.no_pairs:
-        result["pairs"] = pairs_leg(ctx, B, inputs, dev)
+        result["pairs"] = pairs_leg(ctx, B, inputs, dev, args, cache)
     if (args.maps or not args.no_extras) and not args.no_maps:
         result["maps"] = maps_leg(ctx, B, inputs, dev)
     if (args.register or not args.no_extras) and not args.no_register:
-        result["register"] = register_leg(ctx, B, inputs, dev)
+        result["register"] = register_leg(ctx, B, inputs, dev, args, cache)
 
     # the targets this measures against, stated with whether they are met
     targets = {"hbm_roofline_frac": {"target": 0.60, "achieved": result["roofline"]["frac"]}}
@@ -510,6 +612,8 @@ def main() -> int:
 
     print(json.dumps(result), flush=True)
     ctx.close()
+    if own_cache:
+        os.remove(cache)
     return 0
 
 

@@ -154,6 +154,41 @@ def flags_of(boundary: str = "exclude", tsallis: str = "additive", parzen: bool 
     return f
 
 
+# Field names of the three kinds of line in an MI_TUNE_CACHE file (the
+# problem-class key, then the launch shape), as the library writes them.
+_TUNE_FIELDS = {
+    "gemi-tune": ("fnx", "fny", "fnz", "mnx", "mny", "mnz", "mdtype", "bins", "clamp", "n_bucket", "oct8",
+                  "block", "slab_major", "chunks", "packed"),
+    "gemi-tune-parzen": ("fnx", "fny", "fnz", "mnx", "mny", "mnz", "mdtype", "bins", "clamp", "n_bucket",
+                         "fwd_block", "fwd_lds_kib", "bwd_block", "bwd_lds_kib", "chunk_shift"),
+    "gemi-tune-pairs": ("pairs_bucket", "voxels_bucket", "transforms_bucket", "bins", "clamp", "oct8",
+                        "block", "slab_voxels", "packed", "transform_major"),
+}
+
+
+def read_tune_cache(path: str) -> list[dict]:
+    """The entries of an MI_TUNE_CACHE file as dicts ({"kind": tag, field:
+    value, ...}); lines of another form are skipped."""
+    out = []
+    try:
+        with open(path) as fh:
+            lines = fh.read().splitlines()
+    except OSError:
+        return out
+    for line in lines:
+        parts = line.split()
+        if not parts or parts[0] not in _TUNE_FIELDS:
+            continue
+        names = _TUNE_FIELDS[parts[0]]
+        try:
+            vals = [int(v) for v in parts[1:]]
+        except ValueError:
+            continue
+        if len(vals) == len(names):
+            out.append({"kind": parts[0], **dict(zip(names, vals))})
+    return out
+
+
 class Context:
     """A libgemi context on one HIP device."""
 

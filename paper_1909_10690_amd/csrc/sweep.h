@@ -85,6 +85,14 @@ struct HardStep {
       // 0 <= q <= top; a negative q wraps to a huge unsigned value
       if (cx > topx || cy > topy || cz > topz) return;
     }
+    count_inside<PACKED, OCT8>(cx, cy, cz, fixed_bin, lds_hist);
+  }
+
+  // Counts one fixed voxel whose coordinates lie in [0, n - 1] on every
+  // axis (no test, no clamp).
+  template <bool PACKED, bool OCT8, typename FB>
+  __device__ __forceinline__ void count_inside(uint64_t cx, uint64_t cy, uint64_t cz, FB&& fixed_bin,
+                                               uint32_t* lds_hist) const {
     const uint32_t ix = (uint32_t)(cx >> 32), iy = (uint32_t)(cy >> 32), iz = (uint32_t)(cz >> 32);
     const uint32_t fx = (uint32_t)cx, fy = (uint32_t)cy, fz = (uint32_t)cz;
     // rows iz ny + iy < ny nz <= 2^24 and edges <= 4096: 24-bit operands
@@ -101,8 +109,9 @@ struct HardStep {
       oc = __builtin_amdgcn_raw_buffer_load_b128(rsrc, vox << 4, 0, 0);
     }
     const uint32_t fb = fixed_bin();
-    // (65535 - wx) in the low half, wx in the high half
-    const uint32_t wpack = (fx & 0xFFFF0000u) | ((fx >> 16) ^ 0xFFFFu);
+    // (65535 - wx) in the low half, wx in the high half: the high halves of
+    // ~fx and fx, one byte permute
+    const uint32_t wpack = __builtin_amdgcn_perm(fx, ~fx, 0x07060302u);
     const uint32_t a00 = lerp_x(oc.x, wpack), a10 = lerp_x(oc.y, wpack);
     const uint32_t a01 = lerp_x(oc.z, wpack), a11 = lerp_x(oc.w, wpack);
     const uint32_t wy = fy >> 16, wz = fz >> 16;

@@ -6,6 +6,7 @@
   instructions per voxel-transform) are used only when the summary was taken
   on the current sweep sources: a different source hash gives None, the
   summary's own hash gives its figure.
+* The tuning-cache reader behind the line's launch shapes.
 """
 import os
 import subprocess
@@ -37,3 +38,29 @@ def test_profile_figures_follow_the_source_hash():
     traffic = bench.read_profile(committed, "hbm_bytes_per_launch")
     assert traffic is not None and traffic > 0
     assert (bench.read_profile(kv, "hbm_bytes_per_launch") is not None) == (kv == committed)
+
+
+def test_tune_cache_lines_and_shape_lookup(tmp_path):
+    """The three kinds of MI_TUNE_CACHE line, in the library's field order,
+    parse into keys and shapes; malformed lines are skipped; the bench's
+    lookup returns the last entry of the asked class."""
+    sys.path.insert(0, ROOT)
+    import bench
+    from paper_1909_10690_amd import binding as B
+    p = tmp_path / "tune.txt"
+    p.write_text("gemi-tune 256 256 180 256 256 180 1 128 0 10 0 512 1 2048 0\n"
+                 "gemi-tune 256 256 180 256 256 180 1 128 0 10 0 1024 0 0 1\n"
+                 "gemi-tune 1 2 3\n"
+                 "gemi-tune-parzen 512 512 300 256 256 256 1 256 1 0 1024 128 1024 96 0\n"
+                 "gemi-tune-pairs 8 25 12 64 0 1 256 65536 1 1\n"
+                 "something else\n")
+    e = B.read_tune_cache(str(p))
+    assert [x["kind"] for x in e] == ["gemi-tune", "gemi-tune", "gemi-tune-parzen", "gemi-tune-pairs"]
+    assert e[0]["n_bucket"] == 10 and e[0]["chunks"] == 2048 and e[2]["bwd_lds_kib"] == 96
+    assert e[3]["pairs_bucket"] == 8 and e[3]["transform_major"] == 1
+    assert bench.tuned_shape(B, str(p), "gemi-tune", fnx=256, bins=128) == \
+        {"block": 1024, "slab_major": 0, "chunks": 0, "packed": 1}
+    assert bench.tuned_shape(B, str(p), "gemi-tune-parzen", bins=256) == \
+        {"fwd_block": 1024, "fwd_lds_kib": 128, "bwd_block": 1024, "bwd_lds_kib": 96, "chunk_shift": 0}
+    assert bench.tuned_shape(B, str(p), "gemi-tune-pairs", bins=32) is None
+    assert B.read_tune_cache(str(tmp_path / "missing.txt")) == []
