@@ -465,7 +465,9 @@ struct ParzenLaunch {
 // lds_register() records a kernel's static LDS and the device maximum at
 // configuration; lds_guard() looks up kernels it has not seen.
 hipError_t lds_register(const void* kernel);
-hipError_t lds_guard(const void* kernel, size_t dynamic, size_t configured_max);
+// at_zero: the kernel addresses its dynamic LDS from address 0, so it must
+// keep no static LDS.
+hipError_t lds_guard(const void* kernel, size_t dynamic, size_t configured_max, bool at_zero = false);
 
 hipError_t launch_fill_u32(uint32_t* p, size_t n, uint32_t value, hipStream_t s);
 // Index-space matrices M[n][12] of the caller's physical matrices P[n][12].

@@ -62,14 +62,15 @@ hipError_t lds_register(const void* kernel) {
   return hipSuccess;
 }
 
-hipError_t lds_guard(const void* kernel, size_t dynamic, size_t configured_max) {
+hipError_t lds_guard(const void* kernel, size_t dynamic, size_t configured_max, bool at_zero) {
   for (int pass = 0; pass < 2; ++pass) {
     {
       std::lock_guard<std::mutex> g(g_lds_mu);
       for (const auto& k : g_lds_static)
         if (k.first == kernel)
-          return lds_fits(dynamic, k.second, configured_max, g_lds_device_max) ? hipSuccess
-                                                                                : hipErrorInvalidValue;
+          return lds_fits(dynamic, k.second, configured_max, g_lds_device_max) && (!at_zero || k.second == 0)
+                     ? hipSuccess
+                     : hipErrorInvalidValue;
     }
     if (pass == 0) {
       const hipError_t e = lds_register(kernel);
@@ -298,7 +299,7 @@ __global__ __launch_bounds__(NT) void hist_sampled_kernel(HardArgs a, const uint
   const int64_t ns = (int64_t)*n_list;
   const int64_t s0 = ns * chunk / a.chunks, s1 = ns * (chunk + 1) / a.chunks;
   const int64_t span = PACKED ? 65535 : s1 - s0;
-  const HardStep hs(a.geom, lds_hist);
+  const HardStep hs(a.geom, lds_hist, OCT8);
   uint32_t* out = a.hist + (size_t)t * B * B;
   for (int64_t p0 = s0; p0 < s1; p0 += span) {
     const int64_t p1 = p0 + span < s1 ? p0 + span : s1;
@@ -325,7 +326,7 @@ template <bool CLAMP, bool PACKED, bool OCT8>
 static hipError_t launch_sampled_variant(const HardArgs& a, const uint2* list, const unsigned long long* n_list,
                                          size_t lds, hipStream_t s) {
   const hipError_t e =
-      lds_guard((const void*)hist_sampled_kernel<CLAMP, PACKED, OCT8, kSampledBlock>, lds, kHardLdsMax);
+      lds_guard((const void*)hist_sampled_kernel<CLAMP, PACKED, OCT8, kSampledBlock>, lds, kHardLdsMax, true);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((hist_sampled_kernel<CLAMP, PACKED, OCT8, kSampledBlock>), dim3((unsigned)(a.n * a.chunks)),
                      dim3(kSampledBlock), lds, s, a, list, n_list);
@@ -334,7 +335,8 @@ static hipError_t launch_sampled_variant(const HardArgs& a, const uint2* list, c
 
 template <bool CLAMP, bool PACKED, bool OCT8, int NT, bool BRICK>
 static hipError_t launch_variant(const HardArgs& a, int n, size_t lds, hipStream_t s) {
-  const hipError_t e = lds_guard((const void*)hist_hard_kernel<CLAMP, PACKED, OCT8, NT, BRICK>, lds, kHardLdsMax);
+  const hipError_t e =
+      lds_guard((const void*)hist_hard_kernel<CLAMP, PACKED, OCT8, NT, BRICK>, lds, kHardLdsMax, true);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((hist_hard_kernel<CLAMP, PACKED, OCT8, NT, BRICK>), dim3((unsigned)(n * a.chunks)),
                      dim3(NT), lds, s, a);

@@ -258,9 +258,11 @@ __global__ void prep_moving_kernel(PairsArgs a, int64_t items) {
 template <bool CLAMP, bool PACKED, bool OCT8, int NT>
 __global__ __launch_bounds__(NT) void hist_pairs_kernel(PairsArgs a) {
   extern __shared__ uint32_t lds_hist[];
-  __shared__ int64_t item_sh;
   const int B = a.bins;
   const int words = PACKED ? (B * B + 1) / 2 : B * B;
+  // the work-item slot follows the histogram in the dynamic LDS (the sweep
+  // addresses the histogram from LDS address 0: no static LDS)
+  int64_t& item_sh = *(int64_t*)(lds_hist + ((words + 1) & ~1));
   for (int e = threadIdx.x; e < words; e += NT) lds_hist[e] = 0;
   const uint32_t xcd = blockIdx.x & 7u;
   const int64_t* __restrict__ xbase = a.xcd_base + (int64_t)xcd * (a.n_pairs + 1);
@@ -337,16 +339,17 @@ hipError_t launch_pairs_prep(const PairsLaunch& L, hipStream_t s, bool volumes) 
 }
 
 // Dynamic LDS limit of the pairs sweep (a u32 table up to 128 bins, 16-bit
-// pairs above), leaving room for its static work-item slot.
+// pairs above, and the work-item slot after it).
 constexpr size_t kPairsLdsMax = 150 * 1024;
 
 template <bool CLAMP, bool PACKED, bool OCT8, int NT>
 static hipError_t pairs_variant(const PairsLaunch& L, hipStream_t s) {
   const int B = L.args.bins;
-  const size_t lds = PACKED ? (((size_t)B * B + 1) / 2) * 4 : (size_t)B * B * 4;
+  const size_t words = PACKED ? ((size_t)B * B + 1) / 2 : (size_t)B * B;
+  const size_t lds = ((words + 1) & ~(size_t)1) * 4 + 8;  // histogram, then the 8-byte item slot
   const void* fn = (const void*)hist_pairs_kernel<CLAMP, PACKED, OCT8, NT>;
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kPairsLdsMax);
-  if (e != hipSuccess || (e = lds_guard(fn, lds, kPairsLdsMax)) != hipSuccess) return e;
+  if (e != hipSuccess || (e = lds_guard(fn, lds, kPairsLdsMax, true)) != hipSuccess) return e;
   int per_cu = 0;
   e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, NT, lds);
   if (e != hipSuccess) return e;

@@ -17,6 +17,24 @@ typedef __attribute__((address_space(3))) uint32_t lds_u32;
 // also when the pointer itself was read from memory.
 typedef const __attribute__((address_space(1))) uint8_t global_u8;
 
+// Loads of one record of a buffer whose descriptor has a stride: the
+// hardware forms base + index * stride, so the index needs no shift.
+__device__ uint4_t struct_load_b128(__amdgpu_buffer_rsrc_t rsrc, int vindex, int voffset, int soffset, int aux)
+    __asm("llvm.amdgcn.struct.ptr.buffer.load.v4i32");
+__device__ uint2_t struct_load_b64(__amdgpu_buffer_rsrc_t rsrc, int vindex, int voffset, int soffset, int aux)
+    __asm("llvm.amdgcn.struct.ptr.buffer.load.v2i32");
+
+// A value every lane holds alike, moved to scalar registers.  A value
+// computed by vector instructions stays in vector registers otherwise, and
+// the compiler drops a readfirstlane builtin of a value it knows is uniform,
+// so the move is written out.
+__device__ __forceinline__ int64_t uniform64(int64_t v) {
+  uint32_t lo, hi;
+  asm volatile("v_readfirstlane_b32 %0, %1" : "=s"(lo) : "v"((uint32_t)v));
+  asm volatile("v_readfirstlane_b32 %0, %1" : "=s"(hi) : "v"((uint32_t)((uint64_t)v >> 32)));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
 // a * b + c with 24-bit unsigned operands a, b (v_mad_u32_u24, full rate;
 // left to itself the compiler may pick a 64-bit multiply-add).
 __device__ __forceinline__ uint32_t mad24(uint32_t a, uint32_t b, uint32_t c) {
@@ -51,20 +69,24 @@ constexpr double kEdge = 1.0 / 536870912.0;  // 2^-29
 struct HardStep {
   __amdgpu_buffer_rsrc_t rsrc;
   uint64_t topx, topy, topz;
-  uint32_t NY, MX, Bu, B4, lbase;
+  uint32_t NY, MX, Bu, B4;
   double scale;
   Divider div;
 
-  __device__ __forceinline__ HardStep(const HardGeom& g, uint32_t* lds_hist) {
+  // oct8: the gather volume's records are 8-bit corners (8 bytes), as the
+  // kernel's OCT8 instance reads them; else 16-bit ones (16 bytes)
+  __device__ __forceinline__ HardStep(const HardGeom& g, uint32_t* lds_hist, bool oct8) {
     topx = (uint64_t)(g.mnx - 1) << 32;
     topy = (uint64_t)(g.mny - 1) << 32;
     topz = (uint64_t)(g.mnz - 1) << 32;
     NY = (uint32_t)g.mny;
     MX = (uint32_t)g.mnx;
-    rsrc = __builtin_amdgcn_make_buffer_rsrc((void*)g.octs, (short)0, (int)g.oct_bytes, 0x00020000);
+    // records of 8 (OCT8) or 16 bytes, indexed by voxel; the record bound is
+    // given in bytes, which is no tighter than any record count
+    rsrc = __builtin_amdgcn_make_buffer_rsrc((void*)g.octs, (short)(oct8 ? 8 : 16), (int)g.oct_bytes,
+                                             0x00020000);
     Bu = (uint32_t)g.bins;
     B4 = 4u * Bu;  // bytes per LDS histogram row (u32 counters)
-    lbase = (uint32_t)(size_t)(lds_u32*)lds_hist;
     scale = g.scale;
     div = g.div;
   }
@@ -85,30 +107,28 @@ struct HardStep {
       // 0 <= q <= top; a negative q wraps to a huge unsigned value
       if (cx > topx || cy > topy || cz > topz) return;
     }
-    count_inside<PACKED, OCT8>(cx, cy, cz, fixed_bin, lds_hist);
-  }
-
-  // Counts one fixed voxel whose coordinates lie in [0, n - 1] on every
-  // axis (no test, no clamp).
-  template <bool PACKED, bool OCT8, typename FB>
-  __device__ __forceinline__ void count_inside(uint64_t cx, uint64_t cy, uint64_t cz, FB&& fixed_bin,
-                                               uint32_t* lds_hist) const {
     const uint32_t ix = (uint32_t)(cx >> 32), iy = (uint32_t)(cy >> 32), iz = (uint32_t)(cz >> 32);
-    const uint32_t fx = (uint32_t)cx, fy = (uint32_t)cy, fz = (uint32_t)cz;
     // rows iz ny + iy < ny nz <= 2^24 and edges <= 4096: 24-bit operands
     const uint32_t vox = mad24(mad24(iz, NY, iy), MX, ix);
     uint4_t oc;
     if (OCT8) {
       // bytes (x,y), (x1,y), (x,y1), (x1,y1) of slice z in .x, of z1 in .y
-      const uint2_t d = __builtin_amdgcn_raw_buffer_load_b64(rsrc, vox << 3, 0, 0);
+      const uint2_t d = struct_load_b64(rsrc, (int)vox, 0, 0, 0);
       oc.x = __builtin_amdgcn_perm(0u, d.x, 0x0C010C00u);  // (b0, b1) as 16-bit halves
       oc.y = __builtin_amdgcn_perm(0u, d.x, 0x0C030C02u);  // (b2, b3)
       oc.z = __builtin_amdgcn_perm(0u, d.y, 0x0C010C00u);
       oc.w = __builtin_amdgcn_perm(0u, d.y, 0x0C030C02u);
     } else {
-      oc = __builtin_amdgcn_raw_buffer_load_b128(rsrc, vox << 4, 0, 0);
+      oc = struct_load_b128(rsrc, (int)vox, 0, 0, 0);
     }
-    const uint32_t fb = fixed_bin();
+    bin_count<PACKED>(oc, fixed_bin(), (uint32_t)cx, (uint32_t)cy, (uint32_t)cz, lds_hist);
+  }
+
+  // The moving bin from the 16-bit corner pairs oc and the Q32 fractions,
+  // exactly, and the count of cell [fb][bin].
+  template <bool PACKED>
+  __device__ __forceinline__ void bin_count(const uint4_t& oc, uint32_t fb, uint32_t fx, uint32_t fy,
+                                            uint32_t fz, uint32_t* lds_hist) const {
     // (65535 - wx) in the low half, wx in the high half: the high halves of
     // ~fx and fx, one byte permute
     const uint32_t wpack = __builtin_amdgcn_perm(fx, ~fx, 0x07060302u);
@@ -121,18 +141,21 @@ struct HardStep {
     const double b0 = fma(A10, wyd, A00 * uyd);         // exact, < 2^48
     const double b1 = fma(A11, wyd, A01 * uyd);         // exact, < 2^48
     const double V = fma(b1 - b0, wzd, b0 * 65536.0);  // exact value rounded once
-    const double tb = V * scale;
+    // the bin position shifted up by kEdge: its floor is the bin unless the
+    // exact position lies within kEdge of a bin edge, which is when the
+    // fraction falls below 2 kEdge (the rounding errors are far smaller)
+    const double tb = fma(V, scale, kEdge);
     uint32_t bm = (uint32_t)tb;
-    // within kEdge of a bin edge: fr < kEdge or fr > 1 - kEdge
-    const double fr = __builtin_amdgcn_fract(tb);
-    if (fabs(fr - 0.5) > 0.5 - kEdge) bm = exact_bin(a00, a10, a01, a11, wy, wz, Bu, div);
+    if (__builtin_amdgcn_fract(tb) < 2.0 * kEdge) bm = exact_bin(a00, a10, a01, a11, wy, wz, Bu, div);
     if (PACKED) {
       const uint32_t cell = __umul24(fb, Bu) + bm;
       atomicAdd(&lds_hist[cell >> 1], 1u << ((cell & 1u) * 16u));
     } else {
-      // byte address of counter [fb][bm], formed directly (a mul24 and a
-      // shift-add rather than index arithmetic on the pointer)
-      const uint32_t addr = __umul24(fb, B4) + ((bm << 2) + lbase);
+      // LDS byte address of counter [fb][bm], formed directly: a mul24 and
+      // a shift-add.  The kernels that sweep keep no static LDS, so their
+      // dynamic histogram starts at address 0 (lds_guard checks this at
+      // launch) and needs no base.
+      const uint32_t addr = (bm << 2) + __umul24(fb, B4);
       __hip_atomic_fetch_add((lds_u32*)(size_t)addr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     }
   }
@@ -149,21 +172,34 @@ __device__ __forceinline__ void sweep_hard(const HardGeom& g, const int64_t* Mq,
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   const int dx = lane & (kTileX - 1), dy = lane / kTileX;
+  // the matrix in scalar registers: the walk's row coordinates and steps
+  // are then scalar values, and only the lane offsets take vector registers
+  int64_t M[12];
+#pragma unroll
+  for (int e = 0; e < 12; ++e) M[e] = uniform64(Mq[e]);
   Walk w;
-  w.init(Mq, g.fny, g.fnz, chunks, chunk, wave, NW, dx, dy);
+  w.init(M, g.fny, g.fnz, chunks, chunk, wave, NW, dx, dy);
   const int64_t sx = w.step[0], sy = w.step[1], sz = w.step[2];
-  const HardStep hs(g, lds_hist);
+  const HardStep hs(g, lds_hist, OCT8);
+  // fixed bins through a buffer descriptor: the lane's offset within the
+  // tile in a vector register, the tile's in a scalar one (fixed voxels
+  // < 2^28: 32-bit offsets)
+  const uint32_t fnx = (uint32_t)g.fnx;
+  const __amdgpu_buffer_rsrc_t frsrc = __builtin_amdgcn_make_buffer_rsrc(
+      (void*)g.fbins, (short)0, (int)(fnx * (uint32_t)g.fny * (uint32_t)g.fnz), 0x00020000);
+  const int lane_f = (int)(dy * fnx + dx);
+  const int32_t full = (int32_t)(fnx / kTileX);      // x steps every lane of the tile takes
+  const bool tail = (uint32_t)dx < fnx % kTileX;  // the lane takes one more
 
   for (; w.g < w.g1; w.next()) {
     const int32_t j = w.j0 + dy;
     if (j >= g.fny) continue;
-    // fixed voxels < 2^28: 32-bit offsets into the fixed bins
-    const uint32_t rowoff = ((uint32_t)w.k * (uint32_t)g.fny + (uint32_t)j) * (uint32_t)g.fnx;
-    const uint32_t rowend = rowoff + (uint32_t)g.fnx;
+    uint32_t soff = ((uint32_t)w.k * (uint32_t)g.fny + (uint32_t)w.j0) * fnx;
     int64_t qx = w.r[0] + w.lane_off[0], qy = w.r[1] + w.lane_off[1], qz = w.r[2] + w.lane_off[2];
-    for (uint32_t xo = rowoff + dx; xo < rowend; xo += kTileX, qx += sx, qy += sy, qz += sz)
-      hs.count<CLAMP, PACKED, OCT8>(qx, qy, qz, [&] { return (uint32_t)((global_u8*)g.fbins)[xo]; },
-                                    lds_hist);
+    auto fixed_bin = [&] { return (uint32_t)__builtin_amdgcn_raw_buffer_load_b8(frsrc, lane_f, (int)soff, 0); };
+    for (int32_t it = 0; it < full; ++it, soff += kTileX, qx += sx, qy += sy, qz += sz)
+      hs.count<CLAMP, PACKED, OCT8>(qx, qy, qz, fixed_bin, lds_hist);
+    if (tail) hs.count<CLAMP, PACKED, OCT8>(qx, qy, qz, fixed_bin, lds_hist);
   }
 }
 
