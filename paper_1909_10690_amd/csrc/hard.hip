@@ -263,8 +263,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT == 1024 ?
 void hist_hard_kernel(HardArgs a) {
   extern __shared__ uint32_t lds_hist[];
   const int B = a.geom.bins;
-  const int words = PACKED ? (B * B + 1) / 2 : B * B;
-  for (int e = threadIdx.x; e < words; e += NT) lds_hist[e] = 0;
+  clear_hist<PACKED, NT>(lds_hist, B);
   uint32_t t, chunk, band;
   block_work(a.chunks, a.n, 1, a.slab_major, t, chunk, band);
   int64_t Mq[12];
@@ -290,8 +289,7 @@ __global__ __launch_bounds__(NT) void hist_sampled_kernel(HardArgs a, const uint
                                                           const unsigned long long* __restrict__ n_list) {
   extern __shared__ uint32_t lds_hist[];
   const int B = a.geom.bins;
-  const int words = PACKED ? (B * B + 1) / 2 : B * B;
-  for (int e = threadIdx.x; e < words; e += NT) lds_hist[e] = 0;
+  clear_hist<PACKED, NT>(lds_hist, B);
   uint32_t t, chunk, band;
   block_work(a.chunks, a.n, 1, a.slab_major, t, chunk, band);
   int64_t Mq[12];
@@ -390,7 +388,7 @@ hipError_t launch_hist_hard(const HardLaunch& L, hipStream_t s) {
   a.n = L.n;
   a.chunks = L.chunks;
   a.slab_major = L.slab_major;
-  const size_t lds = L.packed ? (((size_t)L.bins * L.bins + 1) / 2) * 4 : (size_t)L.bins * L.bins * 4;
+  const size_t lds = hist_lds_bytes(L.bins, L.packed);
   if (L.block != 256 && L.block != 512 && L.block != 1024) return hipErrorInvalidValue;
   const int32_t step = transforms_per_launch(L.chunks, L.block);
   for (int32_t t0 = 0; t0 < L.n; t0 += step) {
@@ -421,7 +419,7 @@ hipError_t launch_hist_sampled(const HardLaunch& L, const uint2* list, const uns
   a.n = L.n;
   a.chunks = L.chunks;
   a.slab_major = 1;
-  const size_t lds = L.packed ? (((size_t)L.bins * L.bins + 1) / 2) * 4 : (size_t)L.bins * L.bins * 4;
+  const size_t lds = hist_lds_bytes(L.bins, L.packed);
   const bool o8 = a.geom.oct8 != 0;
   auto one = [&](const HardArgs& b) -> hipError_t {
     if (L.clamp) {

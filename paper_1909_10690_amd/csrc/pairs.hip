@@ -259,11 +259,11 @@ template <bool CLAMP, bool PACKED, bool OCT8, int NT>
 __global__ __launch_bounds__(NT) void hist_pairs_kernel(PairsArgs a) {
   extern __shared__ uint32_t lds_hist[];
   const int B = a.bins;
-  const int words = PACKED ? (B * B + 1) / 2 : B * B;
+  const int words = B * hist_row_words(B, PACKED);
   // the work-item slot follows the histogram in the dynamic LDS (the sweep
   // addresses the histogram from LDS address 0: no static LDS)
   int64_t& item_sh = *(int64_t*)(lds_hist + ((words + 1) & ~1));
-  for (int e = threadIdx.x; e < words; e += NT) lds_hist[e] = 0;
+  clear_hist<PACKED, NT>(lds_hist, B);
   const uint32_t xcd = blockIdx.x & 7u;
   const int64_t* __restrict__ xbase = a.xcd_base + (int64_t)xcd * (a.n_pairs + 1);
   const int64_t total = xbase[a.n_pairs];
@@ -345,7 +345,7 @@ constexpr size_t kPairsLdsMax = 150 * 1024;
 template <bool CLAMP, bool PACKED, bool OCT8, int NT>
 static hipError_t pairs_variant(const PairsLaunch& L, hipStream_t s) {
   const int B = L.args.bins;
-  const size_t words = PACKED ? ((size_t)B * B + 1) / 2 : (size_t)B * B;
+  const size_t words = (size_t)B * hist_row_words(B, PACKED);
   const size_t lds = ((words + 1) & ~(size_t)1) * 4 + 8;  // histogram, then the 8-byte item slot
   const void* fn = (const void*)hist_pairs_kernel<CLAMP, PACKED, OCT8, NT>;
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kPairsLdsMax);

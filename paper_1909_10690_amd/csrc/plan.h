@@ -23,6 +23,21 @@ inline int32_t transforms_per_launch(int64_t workgroups_per_transform, int32_t t
   return (int32_t)(m < 1 ? 1 : (m > 0x7FFFFFFF ? 0x7FFFFFFF : m));
 }
 
+// 32-bit words per fixed-bin row of a hard sweep's LDS histogram: the row's
+// counters (u32, or two 16-bit ones per word when packed) and a pad that
+// makes the row width odd and not 1 modulo 32.  Unpadded rows of a
+// power-of-two width would put every cell of one moving bin in one of the
+// 32 LDS banks, and the counts of one wave, whose fixed bins differ by
+// noise, would queue on that bank; a skew of 3 banks per row spreads them
+// over the banks (a plain +1 skew would line up the anti-diagonals).
+constexpr int32_t hist_row_words(int32_t bins, bool packed) {
+  const int32_t w = (packed ? (bins + 1) / 2 : bins) + 3;
+  return (w & 1) ? w : w + 1;
+}
+constexpr size_t hist_lds_bytes(int32_t bins, bool packed) {
+  return (size_t)bins * (size_t)hist_row_words(bins, packed) * 4;
+}
+
 // Whether a launch's LDS fits: its dynamic request within the dynamic
 // maximum the kernel was configured for, and dynamic plus the kernel's
 // static arrays within what one workgroup of the device may hold.  A launch

@@ -69,7 +69,7 @@ constexpr double kEdge = 1.0 / 536870912.0;  // 2^-29
 struct HardStep {
   __amdgpu_buffer_rsrc_t rsrc;
   uint64_t topx, topy, topz;
-  uint32_t NY, MX, Bu, B4;
+  uint32_t NY, MX, Bu, row_bytes, row_cells;
   double scale;
   Divider div;
 
@@ -86,7 +86,10 @@ struct HardStep {
     rsrc = __builtin_amdgcn_make_buffer_rsrc((void*)g.octs, (short)(oct8 ? 8 : 16), (int)g.oct_bytes,
                                              0x00020000);
     Bu = (uint32_t)g.bins;
-    B4 = 4u * Bu;  // bytes per LDS histogram row (u32 counters)
+    // LDS histogram row pitch: in bytes (u32 counters), in 16-bit cells
+    // (packed counters)
+    row_bytes = 4u * (uint32_t)hist_row_words(g.bins, false);
+    row_cells = 2u * (uint32_t)hist_row_words(g.bins, true);
     scale = g.scale;
     div = g.div;
   }
@@ -148,14 +151,16 @@ struct HardStep {
     uint32_t bm = (uint32_t)tb;
     if (__builtin_amdgcn_fract(tb) < 2.0 * kEdge) bm = exact_bin(a00, a10, a01, a11, wy, wz, Bu, div);
     if (PACKED) {
-      const uint32_t cell = __umul24(fb, Bu) + bm;
+      // 16-bit cell of counter [fb][bm]; the row pitch is even, so the
+      // cell's word and half follow from it directly
+      const uint32_t cell = __umul24(fb, row_cells) + bm;
       atomicAdd(&lds_hist[cell >> 1], 1u << ((cell & 1u) * 16u));
     } else {
       // LDS byte address of counter [fb][bm], formed directly: a mul24 and
       // a shift-add.  The kernels that sweep keep no static LDS, so their
       // dynamic histogram starts at address 0 (lds_guard checks this at
       // launch) and needs no base.
-      const uint32_t addr = (bm << 2) + __umul24(fb, B4);
+      const uint32_t addr = (bm << 2) + __umul24(fb, row_bytes);
       __hip_atomic_fetch_add((lds_u32*)(size_t)addr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     }
   }
@@ -203,21 +208,33 @@ __device__ __forceinline__ void sweep_hard(const HardGeom& g, const int64_t* Mq,
   }
 }
 
-// Adds the non-zero LDS bins into a transform's HBM histogram (and clears
-// them for the next use of the LDS histogram when `rezero`).
+// Clears a workgroup's LDS histogram, padding included.
+template <bool PACKED, int NT>
+__device__ __forceinline__ void clear_hist(uint32_t* lds_hist, int B) {
+  const int words = B * hist_row_words(B, PACKED);
+  for (int e = threadIdx.x; e < words; e += NT) lds_hist[e] = 0;
+}
+
+// Adds the non-zero LDS bins into a transform's HBM histogram [B][B] (and
+// clears them for the next use of the LDS histogram when `rezero`): a wave
+// per fixed-bin row at a time, a lane per counter word.
 template <bool PACKED, int NT>
 __device__ __forceinline__ void flush_hist(uint32_t* lds_hist, int B, uint32_t* __restrict__ out,
                                            bool rezero) {
-  const int words = PACKED ? (B * B + 1) / 2 : B * B;
-  for (int e = threadIdx.x; e < words; e += NT) {
-    const uint32_t v = lds_hist[e];
-    if (v == 0) continue;
-    if (rezero) lds_hist[e] = 0;
-    if (PACKED) {
-      if (v & 0xFFFFu) atomicAdd(&out[2 * e], v & 0xFFFFu);
-      if (v >> 16) atomicAdd(&out[2 * e + 1], v >> 16);  // never set past the last bin
-    } else {
-      atomicAdd(&out[e], v);
+  const int pitch = hist_row_words(B, PACKED), used = PACKED ? (B + 1) / 2 : B;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int r = wave; r < B; r += NT / 64) {
+    uint32_t* __restrict__ row = out + (size_t)r * B;
+    for (int w = lane; w < used; w += 64) {
+      const uint32_t v = lds_hist[r * pitch + w];
+      if (v == 0) continue;
+      if (rezero) lds_hist[r * pitch + w] = 0;
+      if (PACKED) {
+        if (v & 0xFFFFu) atomicAdd(&row[2 * w], v & 0xFFFFu);
+        if (v >> 16) atomicAdd(&row[2 * w + 1], v >> 16);  // never set past the row's last bin
+      } else {
+        atomicAdd(&row[w], v);
+      }
     }
   }
 }

@@ -3,7 +3,9 @@
 A dispatch counts its work-items in 32 bits, so every launcher whose grid
 grows with the batch splits it into launches of whole transforms below 2^31
 work-items; and a launch's dynamic plus static LDS must fit one workgroup
-(a 160 KiB dynamic request beside 16 bytes of static LDS faulted once).
+(a 160 KiB dynamic request beside 16 bytes of static LDS faulted once);
+and the hard sweeps' LDS histogram rows are padded to a skewed odd pitch
+that still fits two 128-bin tables per CU.
 These are host rules; the GPU tests cover the launchers that apply them.
 """
 import os
@@ -55,6 +57,19 @@ int main() {
   if (lds_fits(64 * K + 1, 0, 64 * K, 160 * K)) { printf("above the configured maximum accepted\n"); ++bad; }
   if (lds_fits(0, 200 * K, 160 * K, 160 * K)) { printf("static above the device maximum accepted\n"); ++bad; }
   if (lds_fits((size_t)-1, 16, (size_t)-1, 160 * K)) { printf("wrapped sum accepted\n"); ++bad; }
+  // hard-sweep LDS histograms: rows padded to an odd pitch with a skew of 3
+  // banks or more for widths that are multiples of 32, at least the row's
+  // counters; two u32 128-bin tables per CU, and a 256-bin packed one with
+  // the pairs kernel's 8-byte slot within that kernel's 150 KiB
+  for (int B = 2; B <= 256; ++B)
+    for (int pk = 0; pk < 2; ++pk) {
+      const int w = hist_row_words(B, pk), used = pk ? (B + 1) / 2 : B;
+      if (w % 2 != 1 || w < used + 3 || w > used + 4) { printf("pitch %d for B=%d pk=%d\n", w, B, pk); ++bad; }
+      if (used % 32 == 0 && (w % 32 == 1 || w % 32 == 31)) { printf("unit skew B=%d pk=%d\n", B, pk); ++bad; }
+      if (hist_lds_bytes(B, pk) != (size_t)B * w * 4) { printf("bytes B=%d\n", B); ++bad; }
+    }
+  if (2 * hist_lds_bytes(128, false) > 160 * K) { printf("two 128-bin u32 tables do not fit a CU\n"); ++bad; }
+  if (hist_lds_bytes(256, true) + 16 > 150 * K) { printf("256-bin packed table too large\n"); ++bad; }
   printf(bad ? "FAIL %d\n" : "OK\n", bad);
   return bad ? 1 : 0;
 }
