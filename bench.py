@@ -87,7 +87,7 @@ def read_profile(kernel_version: str, key: str):
 def kernel_version() -> str:
     import hashlib
     h = hashlib.sha256()
-    for f in ("hard.hip", "sweep.h", "common.h"):
+    for f in ("hard.hip", "sweep.h", "common.h", "plan.h"):
         h.update(open(os.path.join(ROOT, "paper_1909_10690_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
@@ -547,6 +547,13 @@ def main() -> int:
     result["lds_atomic"] = {"achieved": lds_rate, "peak": lds_peak, "unit": "lane-atomics/s",
                             "frac": lds_rate / lds_peak, "per_voxel_xform": atomics / vox_xf,
                             "peak_source": "mi_probe_lds_atomics (conflict-free ds_add_u32, measured)"}
+    # bank conflicts of the same kernel build (committed SQ_LDS_BANK_CONFLICT
+    # summary): stall cycles per LDS instruction and as a share of the LDS's
+    # active cycles
+    for key in ("lds_conflict_cycles_per_lds_inst", "lds_conflict_frac_of_active"):
+        v = read_profile(kv, key)
+        if v is not None:
+            result["lds_atomic"][key] = v
     # VALU issue: wave64 VALU instructions per voxel-transform (committed
     # SQ_INSTS_VALU summary of this kernel build) x 64 lanes, against
     # 256 CUs x 64 lanes/clock x 2.4 GHz
