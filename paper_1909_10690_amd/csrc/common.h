@@ -92,6 +92,17 @@ __device__ __forceinline__ bool quantize_transform(const double* __restrict__ M,
   return ok;
 }
 
+// A value every lane holds alike, moved to scalar registers.  A value
+// computed by vector instructions stays in vector registers otherwise, and
+// the compiler drops a readfirstlane builtin of a value it knows is uniform,
+// so the move is written out.
+__device__ __forceinline__ int64_t uniform64(int64_t v) {
+  uint32_t lo, hi;
+  asm volatile("v_readfirstlane_b32 %0, %1" : "=s"(lo) : "v"((uint32_t)v));
+  asm volatile("v_readfirstlane_b32 %0, %1" : "=s"(hi) : "v"((uint32_t)((uint64_t)v >> 32)));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
 // ---------------------------------------------------------------------------
 // per-voxel input preparation shared by the single-pair and multi-pair paths
 // ---------------------------------------------------------------------------

@@ -24,17 +24,6 @@ __device__ uint4_t struct_load_b128(__amdgpu_buffer_rsrc_t rsrc, int vindex, int
 __device__ uint2_t struct_load_b64(__amdgpu_buffer_rsrc_t rsrc, int vindex, int voffset, int soffset, int aux)
     __asm("llvm.amdgcn.struct.ptr.buffer.load.v2i32");
 
-// A value every lane holds alike, moved to scalar registers.  A value
-// computed by vector instructions stays in vector registers otherwise, and
-// the compiler drops a readfirstlane builtin of a value it knows is uniform,
-// so the move is written out.
-__device__ __forceinline__ int64_t uniform64(int64_t v) {
-  uint32_t lo, hi;
-  asm volatile("v_readfirstlane_b32 %0, %1" : "=s"(lo) : "v"((uint32_t)v));
-  asm volatile("v_readfirstlane_b32 %0, %1" : "=s"(hi) : "v"((uint32_t)((uint64_t)v >> 32)));
-  return (int64_t)(((uint64_t)hi << 32) | lo);
-}
-
 // a * b + c with 24-bit unsigned operands a, b (v_mad_u32_u24, full rate;
 // left to itself the compiler may pick a 64-bit multiply-add).
 __device__ __forceinline__ uint32_t mad24(uint32_t a, uint32_t b, uint32_t c) {
