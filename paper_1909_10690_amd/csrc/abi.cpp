@@ -427,9 +427,9 @@ int64_t expected_samples(const mi_volume* f, const SampleSpec& smp) {
 }
 
 // Rows of the table per band when `tables` fp32 tables of `bins` columns
-// share an LDS budget of `budget` bytes (at most 64 KiB).
+// (rows padded to parzen_pitch) share an LDS budget of `budget` bytes.
 int32_t band_rows_for(int32_t bins, int32_t tables, int32_t budget) {
-  int32_t r = (int32_t)(budget / (4 * bins * tables));
+  int32_t r = (int32_t)(budget / (4 * parzen_pitch(bins) * tables));
   return r < 1 ? 1 : (r < bins ? r : bins);
 }
 
@@ -536,7 +536,7 @@ int run_parzen(mi_context* ctx, const mi_volume* fixed, const mi_volume* moving,
     // plus the copies of the background row's hot columns
     const int32_t budget = (backward ? tune.bwd_lds_kib : tune.fwd_lds_kib) * 1024;
     pa.band_rows = backward ? band_rows_for(bins, kParzenQGroup, budget)
-                            : std::min(bins, std::max(1, (budget / 8 - parzen_hot_cells(bins)) / bins));
+                            : std::min(bins, std::max(1, (budget / 8 - parzen_hot_cells(bins)) / parzen_pitch(bins)));
     pa.bands = (bins + pa.band_rows - 1) / pa.band_rows;
     int64_t chunks = smp ? plan_sampled_chunks(ctx, expected_samples(fixed, *smp), (int64_t)n * pa.bands)
                          : plan_parzen_chunks(ctx, fixed, moving, (int64_t)n * pa.bands);

@@ -456,6 +456,11 @@ __host__ __device__ inline uint32_t slot_group_mask(int32_t r_lo, int32_t r_hi) 
 // columns it covers, so the same column of consecutive copies falls in
 // different LDS banks.
 constexpr int kHotCopies = 16;
+// Row pitch (cells) of the Parzen sweeps' LDS tables: the band's B columns
+// and a pad of 3, so that one column of consecutive rows falls 3 (fp32
+// cells) or 6 (64-bit cells) banks apart, not in one bank as with a pitch
+// of B (a multiple of 32 words for the usual bin counts).
+__host__ __device__ inline int32_t parzen_pitch(int32_t bins) { return bins + 3; }
 constexpr int kHotCols = 64;
 __host__ __device__ inline int32_t parzen_hot_cols(int32_t bins) { return bins < kHotCols ? bins : kHotCols; }
 __host__ __device__ inline int32_t parzen_hot_stride(int32_t bins) { return parzen_hot_cols(bins) + 1; }

@@ -270,10 +270,11 @@ struct SweepCtx {
   int32_t r_lo, r_hi;  // slots (occupied fixed-bin rows) of this band
 };
 
-// Table row index of a band's cell e (slot r_lo + e / B, column e % B).
-__device__ __forceinline__ size_t band_cell_row(const RowMap* m, int32_t r_lo, int e, int B, int& col) {
-  const int rr = e / B;
-  col = e - rr * B;
+// Table row index of a band's LDS cell e (slot r_lo + e / pitch, column
+// e % pitch; columns B .. pitch - 1 are padding).
+__device__ __forceinline__ size_t band_cell_row(const RowMap* m, int32_t r_lo, int e, int B, int pitch, int& col) {
+  const int rr = e / pitch;
+  col = e - rr * pitch;
   return (size_t)m->row_of_slot[r_lo + rr] * B;
 }
 
@@ -348,7 +349,7 @@ struct ParzenFwdStep {
   int32_t n[3];
   uint32_t NY, MX;
   int32_t SZ;  // bytes to the next slice of quads
-  int B;
+  int B, pitch;
   float sscale, smax;
 
   template <bool FQ>
@@ -365,6 +366,7 @@ struct ParzenFwdStep {
     p.SZ = (FQ ? 16 : 8) * a.mnx * a.mny;
     p.rsrc = __builtin_amdgcn_make_buffer_rsrc((void*)a.gvol, (short)0, (int)a.gvol_bytes, 0x00020000);
     p.B = a.bins;
+    p.pitch = parzen_pitch(a.bins);
     p.sscale = a.sscale;
     p.smax = (float)(p.B - 3);
     return p;
@@ -428,7 +430,7 @@ struct ParzenFwdStep {
     const unsigned long long q0 = fixed40(wt[0]), q2 = fixed40(wt[2]), q3 = fixed40(wt[3]);
     const unsigned long long q1 = (1ull << 40) - q0 - q2 - q3;  // w1 >= 1/6
     const int32_t col0 = (int32_t)fl - 1;
-    int base = (fb - sc.r_lo) * B + col0;
+    int base = (fb - sc.r_lo) * pitch + col0;
     // slot 0 (in band 0 only): the lane's copy of the row's hot columns
     if (fb == 0 && col0 + 3 < parzen_hot_cols(B)) base = cells + copy * parzen_hot_stride(B) + col0;
     unsigned long long* cell = lds_tab + base;
@@ -464,9 +466,9 @@ __device__ __forceinline__ void flush_parzen(const ParzenArgs& a, const SweepCtx
     unsigned long long v = lds_tab[e];
     if (e < hot_cols)  // slot 0's row is the band's first
       for (int c = 0; c < kHotCopies; ++c) v += lds_tab[cells + c * hot_stride + e];
-    if (v) {
+    if (v) {  // (padding cells stay zero)
       int col;
-      const size_t row = band_cell_row(a.rows, sc.r_lo, e, B, col);
+      const size_t row = band_cell_row(a.rows, sc.r_lo, e, B, parzen_pitch(B), col);
       atomicAdd(&out[row + col], (double)v * 9.094947017729282379150390625e-13);  // 2^-40
     }
   }
@@ -485,7 +487,7 @@ __global__ __launch_bounds__(NT) void parzen_fwd_kernel(ParzenArgs a) {
   sc.r_lo = (int32_t)sc.band * a.band_rows;
   if (sc.r_lo >= n_slots) return;  // a band past the occupied rows (whole workgroup)
   sc.r_hi = min(n_slots, sc.r_lo + a.band_rows);
-  const int cells = (sc.r_hi - sc.r_lo) * B;
+  const int cells = (sc.r_hi - sc.r_lo) * parzen_pitch(B);
   const int hot_cells = sc.r_lo == 0 ? parzen_hot_cells(B) : 0;  // copies of slot 0's hot columns
   for (int e = threadIdx.x; e < cells + hot_cells; e += NT) lds_tab[e] = 0ull;
   if (threadIdx.x == 0) lds_count = 0;
@@ -547,7 +549,7 @@ __global__ __launch_bounds__(NT) void parzen_sampled_fwd_kernel(ParzenArgs a, co
   sc.r_lo = (int32_t)sc.band * a.band_rows;
   if (sc.r_lo >= n_slots) return;  // a band past the occupied rows (whole workgroup)
   sc.r_hi = min(n_slots, sc.r_lo + a.band_rows);
-  const int cells = (sc.r_hi - sc.r_lo) * B;
+  const int cells = (sc.r_hi - sc.r_lo) * parzen_pitch(B);
   const int hot_cells = sc.r_lo == 0 ? parzen_hot_cells(B) : 0;
   for (int e = threadIdx.x; e < cells + hot_cells; e += NT) lds_tab[e] = 0ull;
   if (threadIdx.x == 0) lds_count = 0;
@@ -665,7 +667,7 @@ __global__ __launch_bounds__(NT) void parzen_bwd_kernel(ParzenArgs a) {
   sc.r_lo = (int32_t)sc.band * a.band_rows;
   if (sc.r_lo >= n_slots) return;  // a band past the occupied rows (whole workgroup)
   sc.r_hi = min(n_slots, sc.r_lo + a.band_rows);
-  const int cells = (sc.r_hi - sc.r_lo) * B;
+  const int cells = (sc.r_hi - sc.r_lo) * parzen_pitch(B);
   int64_t Mq[12];
   const bool ok = quantize_transform(a.transforms + 12 * (size_t)sc.t, Mq);
   const int nqg = min(NQG, a.n_q - a.q0);
@@ -673,8 +675,8 @@ __global__ __launch_bounds__(NT) void parzen_bwd_kernel(ParzenArgs a) {
     const float* __restrict__ src = a.gtab + ((size_t)sc.t * a.n_q + a.q0 + g) * BB;
     for (int e = threadIdx.x; e < cells; e += NT) {
       int col;
-      const size_t row = band_cell_row(a.rows, sc.r_lo, e, B, col);
-      lds_g[g * cells + e] = src[row + col];
+      const size_t row = band_cell_row(a.rows, sc.r_lo, e, B, parzen_pitch(B), col);
+      lds_g[g * cells + e] = col < B ? src[row + col] : 0.0f;
     }
   }
   __syncthreads();
@@ -759,7 +761,7 @@ __global__ __launch_bounds__(NT) void parzen_bwd_kernel(ParzenArgs a) {
         const float fl = floorf(s);
         float d[4];
         bspline_slopes(s - fl, d);
-        const int col = (fb - sc.r_lo) * B + ((int32_t)fl - 1);
+        const int col = (fb - sc.r_lo) * parzen_pitch(B) + ((int32_t)fl - 1);
         const float xt[4] = {(float)x, fj, fk, 1.0f};
 #pragma unroll
         for (int g = 0; g < NQG; ++g) {
@@ -851,7 +853,7 @@ static int32_t block_of(const ParzenLaunch& L) {
 }
 
 hipError_t launch_parzen_fwd(const ParzenLaunch& L, hipStream_t s) {
-  const size_t lds = ((size_t)L.args.band_rows * L.args.bins + parzen_hot_cells(L.args.bins)) * 8;
+  const size_t lds = ((size_t)L.args.band_rows * parzen_pitch(L.args.bins) + parzen_hot_cells(L.args.bins)) * 8;
   return in_launches(L.args, block_of(L), [&](const ParzenArgs& a) {
     return by_block(L.block, [&]<int NT>() {
       if (L.float_quads)
@@ -873,7 +875,7 @@ static hipError_t sampled_fwd_variant(const ParzenArgs& a, const uint2* list, co
 
 hipError_t launch_parzen_sampled_fwd(const ParzenLaunch& L, const uint2* list, const unsigned long long* n_list,
                                      hipStream_t s) {
-  const size_t lds = ((size_t)L.args.band_rows * L.args.bins + parzen_hot_cells(L.args.bins)) * 8;
+  const size_t lds = ((size_t)L.args.band_rows * parzen_pitch(L.args.bins) + parzen_hot_cells(L.args.bins)) * 8;
   return in_launches(L.args, block_of(L), [&](const ParzenArgs& a) {
     return by_block(L.block, [&]<int NT>() {
       if (L.float_quads)
@@ -909,7 +911,7 @@ static hipError_t bwd_variant(const ParzenArgs& a, size_t lds, hipStream_t s) {
 }
 
 hipError_t launch_parzen_bwd(const ParzenLaunch& L, hipStream_t s) {
-  const size_t lds = (size_t)kParzenQGroup * L.args.band_rows * L.args.bins * 4;
+  const size_t lds = (size_t)kParzenQGroup * L.args.band_rows * parzen_pitch(L.args.bins) * 4;
   return in_launches(L.args, block_of(L), [&](const ParzenArgs& a) {
     return by_block(L.block, [&]<int NT>() {
       if (L.float_quads)
