@@ -133,7 +133,8 @@ int check_common(const mi_volume* f, const mi_volume* m, int32_t n, int32_t bins
 //                count u64[n], MI partial sums (reduce_part_bytes)
 //   Parzen:      moving oct volume (integer moving volume) or f32x4 quad
 //                volume [mnz+1][mny][mnx] (float moving volume),
-//                occupied-row map, wave-tile slot masks u32[tiles],
+//                occupied-row map, wave-tile slot masks u32[tiles] and
+//                their per-row-group ORs u32[row groups],
 //                table f64[n][B][B], count u64[n]
 //                MI partial sums (reduce_part_bytes)
 //   Parzen grad: + table marginals f64[n][2B], dMI/dp tables f32[n][n_q][B][B]
@@ -168,7 +169,7 @@ Layout layout(const mi_volume* f, const mi_volume* m, int32_t n, int32_t bins, i
     L.rowmap = off;
     off += align256(sizeof(RowMap));
     L.tmask = off;
-    off += align256(4 * (size_t)parzen_tiles(f->nx, f->ny, f->nz));
+    off += align256(4 * (size_t)(parzen_tiles(f->nx, f->ny, f->nz) + parzen_row_groups(f->ny, f->nz)));
     L.table = off;
     off += align256(bb * 8 * (size_t)n);
     L.count = off;
@@ -506,6 +507,7 @@ int run_parzen(mi_context* ctx, const mi_volume* fixed, const mi_volume* moving,
   a.fbins = fb;
   a.rows = rows;
   a.tile_mask = (const uint32_t*)(ws + L.tmask);
+  a.row_mask = a.tile_mask + parzen_tiles(fixed->nx, fixed->ny, fixed->nz);
   a.gvol = gvol;
   a.table = table;
   a.count = count;

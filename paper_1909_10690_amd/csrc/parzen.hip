@@ -191,11 +191,26 @@ __global__ __launch_bounds__(256) void tile_mask_kernel(const uint8_t* __restric
   }
 }
 
+// One thread per row group: the OR of its tiles' masks, after the tiles.
+__global__ __launch_bounds__(256) void row_mask_kernel(int32_t XT, int64_t groups, uint32_t* __restrict__ mask) {
+  const uint32_t* __restrict__ tiles = mask;
+  uint32_t* __restrict__ rows = mask + groups * XT;
+  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < groups; g += (int64_t)gridDim.x * blockDim.x) {
+    uint32_t m = 0;
+    for (int32_t t = 0; t < XT; ++t) m |= tiles[g * XT + t];
+    rows[g] = m;
+  }
+}
+
 hipError_t launch_tile_mask(const uint8_t* slots, int32_t nx, int32_t ny, int32_t nz, uint32_t* mask, hipStream_t s) {
   const int64_t tiles = parzen_tiles(nx, ny, nz);
   const int64_t blocks = (tiles + 255) / 256;
   hipLaunchKernelGGL(tile_mask_kernel, dim3((unsigned)(blocks < 8192 ? (blocks > 0 ? blocks : 1) : 8192)), dim3(256),
                      0, s, slots, nx, ny, nz, mask);
+  const int64_t groups = parzen_row_groups(ny, nz);
+  const int64_t gblocks = (groups + 255) / 256;
+  hipLaunchKernelGGL(row_mask_kernel, dim3((unsigned)(gblocks < 8192 ? (gblocks > 0 ? gblocks : 1) : 8192)),
+                     dim3(256), 0, s, (int32_t)((nx + kTileX - 1) / kTileX), groups, mask);
   return hipGetLastError();
 }
 
@@ -506,6 +521,7 @@ __global__ __launch_bounds__(NT) void parzen_fwd_kernel(ParzenArgs a) {
     const int32_t XT = (a.fnx + kTileX - 1) / kTileX;
     const uint32_t band_groups = slot_group_mask(sc.r_lo, sc.r_hi);
     for (; w.g < w.g1; w.next()) {
+      if (!(a.row_mask[w.g] & band_groups)) continue;  // no slot of this band in the row group
       const int32_t j = w.j0 + dy;
       const bool row_ok = j < a.fny;
       const uint8_t* __restrict__ frow = a.fbins + ((int64_t)w.k * a.fny + (row_ok ? j : 0)) * a.fnx;
@@ -702,6 +718,7 @@ __global__ __launch_bounds__(NT) void parzen_bwd_kernel(ParzenArgs a) {
     const int32_t XT = (a.fnx + kTileX - 1) / kTileX;
     const uint32_t band_groups = slot_group_mask(sc.r_lo, sc.r_hi);
     for (; w.g < w.g1; w.next()) {
+      if (!(a.row_mask[w.g] & band_groups)) continue;  // no slot of this band in the row group
       const int32_t j = w.j0 + dy;
       const bool row_ok = j < a.fny;
       const uint8_t* __restrict__ frow = a.fbins + ((int64_t)w.k * a.fny + (row_ok ? j : 0)) * a.fnx;

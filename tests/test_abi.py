@@ -201,8 +201,9 @@ def test_workspace_size_layout():
     assert st == 0 and n == xf + a(10 * 11 * 12) + a(9 * 8 * 7 * 16) + a(5 * 32 * 32 * 4) + a(5 * 8) + part
     octs = a(8 * 8 * 9 * 8)  # Parzen: 16-bit quads, 8 bytes per voxel, one extra slice
     # occupied fixed-bin rows (used, row_of_slot, slot_of_row, n_slots), then
-    # one u32 slot-group mask per 16 x 4 wave tile of the fixed volume
-    rowmap = a(3 * 256 * 4 + 4) + a(4 * ((11 + 3) // 4) * 12 * ((10 + 15) // 16))
+    # one u32 slot-group mask per 16 x 4 wave tile of the fixed volume and
+    # one per row group (4 rows of a slice)
+    rowmap = a(3 * 256 * 4 + 4) + a(4 * ((11 + 3) // 4) * 12 * ((10 + 15) // 16 + 1))
     st, n = ws_size(vol(10, 11, 12), vol(), 5, 32, 2, B.HIST_PARZEN)
     assert st == 0 and n == xf + a(1320) + octs + rowmap + a(5 * 32 * 32 * 8) + a(5 * 8) + part
     st, n = ws_size(vol(10, 11, 12), vol(), 5, 32, 2, B.GRADIENT)
