@@ -265,16 +265,17 @@ struct ParzenTune {
 
 // The untuned shape.  Up to 64 bins a table fits one 64 KiB band, and
 // 512-thread workgroups (two per CU) were fastest on the 128^3, 64-bin
-// gradient (1.19 ms a call against 1.29-1.30 ms with 1024 threads); above
-// it, fewer, larger bands at one 1024-thread workgroup per CU were fastest
-// on the 512x512x300 / 256^3, 256-bin CT/MR gradient (forward 128 KiB:
-// 0.59 against 1.09 ms; backward 96 KiB: 1.00 against 1.09 ms).
+// gradient (1.00 ms a call against 1.16 ms with 1024 threads and 128 KiB);
+// above it, fewer, larger bands at one 1024-thread workgroup per CU were
+// fastest on the 512x512x300 / 256^3, 256-bin CT/MR gradient: 128 KiB for
+// both sweeps, 1.26 ms an iteration (forward 0.56, backward 0.62 ms)
+// against 1.82 ms with 96 KiB and 1.88 ms with 64 KiB.
 ParzenTune parzen_shape_for_bins(int32_t bins) {
   ParzenTune t;
   if (bins > 64) {
     t.fwd_block = t.bwd_block = 1024;
     t.fwd_lds_kib = 128;
-    t.bwd_lds_kib = 96;
+    t.bwd_lds_kib = 128;
   }
   return t;
 }
