@@ -269,13 +269,15 @@ struct ParzenTune {
 // above it, fewer, larger bands at one 1024-thread workgroup per CU were
 // fastest on the 512x512x300 / 256^3, 256-bin CT/MR gradient: 128 KiB for
 // both sweeps, 1.26 ms an iteration (forward 0.56, backward 0.62 ms)
-// against 1.82 ms with 96 KiB and 1.88 ms with 64 KiB.
+// against 1.82 ms with 96 KiB and 1.88 ms with 64 KiB; and twice the
+// planned workgroups, 1.17 ms (half: 1.44 ms).
 ParzenTune parzen_shape_for_bins(int32_t bins) {
   ParzenTune t;
   if (bins > 64) {
     t.fwd_block = t.bwd_block = 1024;
     t.fwd_lds_kib = 128;
     t.bwd_lds_kib = 128;
+    t.chunk_shift = 1;
   }
   return t;
 }
