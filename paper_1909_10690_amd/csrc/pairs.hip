@@ -256,7 +256,7 @@ __global__ void prep_moving_kernel(PairsArgs a, int64_t items) {
 }
 
 template <bool CLAMP, bool PACKED, bool OCT8, int NT>
-__global__ __launch_bounds__(NT) void hist_pairs_kernel(PairsArgs a) {
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8))) void hist_pairs_kernel(PairsArgs a) {
   extern __shared__ uint32_t lds_hist[];
   const int B = a.bins;
   const int words = B * hist_row_words(B, PACKED);
