@@ -223,7 +223,7 @@ def register_leg(ctx, B, inputs, dev, args, cache: str, steps: int = 200) -> dic
     import numpy as np
     import torch
     from paper_1909_10690_amd import transforms as T
-    from paper_1909_10690_amd.register import register, volume_centre
+    from paper_1909_10690_amd.register import affine_to_decomposed, register, volume_centre
     log("register leg: building the 512x512x300 / 256^3 CT-MR pair")
     c = inputs.ct_mr_pair()
     F = B.Volume.from_numpy(c["fixed"], *c["fixed_range"], dev, spacing=c["fixed_spacing"])

@@ -64,3 +64,44 @@ def test_tune_cache_lines_and_shape_lookup(tmp_path):
         {"fwd_block": 1024, "fwd_lds_kib": 128, "bwd_block": 1024, "bwd_lds_kib": 96, "chunk_shift": 0}
     assert bench.tuned_shape(B, str(p), "gemi-tune-pairs", bins=32) is None
     assert B.read_tune_cache(str(tmp_path / "missing.txt")) == []
+
+
+def test_bench_functions_use_only_defined_names():
+    """Every name a bench.py function reads is a parameter, a local (an
+    assignment, loop or comprehension target, an import inside it or an
+    enclosing function), a module-level name or a builtin: the GPU legs run
+    only on the GPU, so a missing import would otherwise surface there."""
+    import ast
+    import builtins
+    tree = ast.parse(open(os.path.join(ROOT, "bench.py")).read())
+    module = set(dir(builtins))
+    for node in tree.body:
+        if isinstance(node, (ast.Import, ast.ImportFrom)):
+            module.update((a.asname or a.name).split(".")[0] for a in node.names)
+        elif isinstance(node, (ast.FunctionDef, ast.ClassDef)):
+            module.add(node.name)
+        elif isinstance(node, ast.Assign):
+            module.update(t.id for t in node.targets if isinstance(t, ast.Name))
+
+    def bound(fn):
+        names = {a.arg for a in fn.args.args + fn.args.kwonlyargs}
+        for n in ast.walk(fn):
+            if isinstance(n, ast.Name) and isinstance(n.ctx, ast.Store):
+                names.add(n.id)
+            elif isinstance(n, (ast.Import, ast.ImportFrom)):
+                names.update((a.asname or a.name).split(".")[0] for a in n.names)
+            elif isinstance(n, (ast.FunctionDef, ast.Lambda)) and n is not fn:
+                names.update(a.arg for a in n.args.args)
+                if isinstance(n, ast.FunctionDef):
+                    names.add(n.name)
+            elif isinstance(n, ast.arg):
+                names.add(n.arg)
+        return names
+
+    missing = []
+    for fn in [n for n in tree.body if isinstance(n, ast.FunctionDef)]:
+        known = module | bound(fn)
+        for n in ast.walk(fn):
+            if isinstance(n, ast.Name) and isinstance(n.ctx, ast.Load) and n.id not in known:
+                missing.append(f"{fn.name}: {n.id} (line {n.lineno})")
+    assert not missing, missing
