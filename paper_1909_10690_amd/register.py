@@ -57,13 +57,40 @@ def affine_to_decomposed(p) -> np.ndarray:
     return np.concatenate([[ax, ay, az], np.log(s), [hxy, hxz, hyz], p[9:12]])
 
 
-def decomposed_jacobian(d, h: float = 1e-6) -> np.ndarray:
-    """J[i, j] = d affine_params[i] / d d[j] by central differences (fp64)."""
+def decomposed_jacobian(d) -> np.ndarray:
+    """J[i, j] = d affine_params[i] / d d[j], analytically: with
+    A = Rz Ry Rx H S (S = diag(exp(log-scales)), H the unit upper-triangular
+    shear), an angle differentiates its own rotation factor, log-scale i
+    scales column i of A, and a shear entry moves one entry of H; t maps to
+    itself.  (Central differences took ~0.6 ms of host time a call, most of
+    a registration iteration's host share.)"""
+    d = np.asarray(d, dtype=np.float64)
+    ax, ay, az = d[0:3]
+    cx, sx, cy, sy, cz, sz = np.cos(ax), np.sin(ax), np.cos(ay), np.sin(ay), np.cos(az), np.sin(az)
+    Rx = np.array([[1, 0, 0], [0, cx, -sx], [0, sx, cx]])
+    Ry = np.array([[cy, 0, sy], [0, 1, 0], [-sy, 0, cy]])
+    Rz = np.array([[cz, -sz, 0], [sz, cz, 0], [0, 0, 1]])
+    dRx = np.array([[0, 0, 0], [0, -sx, -cx], [0, cx, -sx]])
+    dRy = np.array([[-sy, 0, cy], [0, 0, 0], [-cy, 0, -sy]])
+    dRz = np.array([[-sz, -cz, 0], [cz, -sz, 0], [0, 0, 0]])
+    hxy, hxz, hyz = d[6:9]
+    H = np.array([[1.0, hxy, hxz], [0.0, 1.0, hyz], [0.0, 0.0, 1.0]])
+    S = np.diag(np.exp(d[3:6]))
+    R = Rz @ Ry @ Rx
     J = np.zeros((12, 12))
-    for j in range(12):
-        e = np.zeros(12)
-        e[j] = h
-        J[:, j] = (decomposed_to_affine(d + e) - decomposed_to_affine(d - e)) / (2 * h)
+    J[:9, 0] = (Rz @ Ry @ dRx @ H @ S).reshape(9)
+    J[:9, 1] = (Rz @ dRy @ Rx @ H @ S).reshape(9)
+    J[:9, 2] = (dRz @ Ry @ Rx @ H @ S).reshape(9)
+    A = R @ H @ S
+    for i in range(3):
+        dA = np.zeros((3, 3))
+        dA[:, i] = A[:, i]
+        J[:9, 3 + i] = dA.reshape(9)
+    for j, (r, c) in enumerate(((0, 1), (0, 2), (1, 2))):
+        E = np.zeros((3, 3))
+        E[r, c] = 1.0
+        J[:9, 6 + j] = (R @ E @ S).reshape(9)
+    J[9:, 9:] = np.eye(3)
     return J
 
 
@@ -127,14 +154,24 @@ def register(gctx: B.Context, fixed: B.Volume, moving: B.Volume, bins: int,
     c = volume_centre(fixed) if centre is None else np.asarray(centre, dtype=np.float64)
     J = T.centred_jacobian(c)              # d P / d (A, t), constant
     first = state.step
+    nq = len(q)
+    # per step one host -> device copy of P (from pinned memory) and one
+    # device -> host copy of MI and dMI/dP together (one buffer)
+    P_host = torch.empty((1, 12), dtype=torch.float64, pin_memory=dev.type == "cuda")
+    P_dev = torch.empty((1, 12), dtype=torch.float64, device=dev)
+    res = torch.empty(nq * 13, dtype=torch.float64, device=dev)
+    mi_out, g_out = res[:nq].view(1, nq), res[nq:].view(1, nq, 12)
     while state.step < steps:
         pa = decomposed_to_affine(d) if dec else d
-        P = torch.as_tensor(T.centred_matrix(pa[:9], pa[9:], c).reshape(1, 12), dtype=torch.float64, device=dev)
+        P_host.numpy()[:] = T.centred_matrix(pa[:9], pa[9:], c).reshape(1, 12)
+        P_dev.copy_(P_host, non_blocking=True)
         # the volumes and workspace stay the same over the loop: after the
         # first call the library reuses their preparation
         reuse = B.VOLUMES_UNCHANGED if state.step > first else 0
-        mi, gP = gctx.grad(fixed, moving, P, bins, q, flags=flags | reuse, workspace=workspace)
-        gp = gP[0].cpu().numpy() @ J            # [n_q][12] d MI_q / d (A, t)
+        gctx.grad(fixed, moving, P_dev, bins, q, flags=flags | reuse, workspace=workspace, out=(mi_out, g_out))
+        h = res.cpu().numpy()                   # waits for the step; P_host is free again
+        mi, gP = h[:nq], h[nq:].reshape(nq, 12)
+        gp = gP @ J                             # [n_q][12] d MI_q / d (A, t)
         if dec:
             gp = gp @ decomposed_jacobian(d)    # d MI_q / d (angles, log-scales, shears, t)
         if mixed:
@@ -150,7 +187,7 @@ def register(gctx: B.Context, fixed: B.Volume, moving: B.Volume, bins: int,
         d = d + delta   # ascent
         state.params = [float(x) for x in d]
         state.m, state.v = [float(x) for x in m], [float(x) for x in v]
-        state.history.append((state.step, [float(x) for x in mi[0].cpu().numpy()]))
+        state.history.append((state.step, [float(x) for x in mi]))
         if checkpoint and (state.step % every == 0 or state.step == steps):
             state.save(checkpoint)
         if not all(math.isfinite(x) for x in state.params):

@@ -102,3 +102,20 @@ def test_decomposed_jacobian_at_identity():
         E[r, c] = 1.0
         assert np.allclose(J[:9, 6 + j], E.reshape(9), atol=1e-8)
     assert np.allclose(J[9:, 9:], np.eye(3), atol=1e-8) and np.allclose(J[:9, 9:], 0, atol=1e-8)
+
+
+def test_decomposed_jacobian_against_differences():
+    """The analytic Jacobian against central differences of
+    decomposed_to_affine at random parameters."""
+    from paper_1909_10690_amd.register import decomposed_jacobian, decomposed_to_affine
+    rng = np.random.default_rng(15)
+    h = 1e-6
+    for _ in range(50):
+        d = np.concatenate([rng.uniform(-0.6, 0.6, 3), rng.uniform(-0.2, 0.2, 3), rng.uniform(-0.2, 0.2, 3),
+                            rng.uniform(-10, 10, 3)])
+        J = decomposed_jacobian(d)
+        for j in range(12):
+            e = np.zeros(12)
+            e[j] = h
+            fd = (decomposed_to_affine(d + e) - decomposed_to_affine(d - e)) / (2 * h)
+            assert np.allclose(J[:, j], fd, rtol=0, atol=1e-8), j
