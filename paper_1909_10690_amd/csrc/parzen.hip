@@ -724,6 +724,12 @@ __global__ __launch_bounds__(NT) void parzen_bwd_kernel(ParzenArgs a) {
       const uint8_t* __restrict__ frow = a.fbins + ((int64_t)w.k * a.fny + (row_ok ? j : 0)) * a.fnx;
       const uint32_t* __restrict__ tmask = a.tile_mask + (int64_t)w.g * XT;
       const float fj = (float)j, fk = (float)w.k;
+      // per-lane sums over the row group's x steps of gr and gr x
+      float rs[NQG][3], rx[NQG][3];
+#pragma unroll
+      for (int g = 0; g < NQG; ++g)
+#pragma unroll
+        for (int r = 0; r < 3; ++r) rs[g][r] = rx[g][r] = 0.0f;
       int64_t q[3];
 #pragma unroll
       for (int r = 0; r < 3; ++r) q[r] = w.r[r] + w.lane_off[r];
@@ -779,7 +785,7 @@ __global__ __launch_bounds__(NT) void parzen_bwd_kernel(ParzenArgs a) {
         float d[4];
         bspline_slopes(s - fl, d);
         const int col = (fb - sc.r_lo) * parzen_pitch(B) + ((int32_t)fl - 1);
-        const float xt[4] = {(float)x, fj, fk, 1.0f};
+        const float fx = (float)x;
 #pragma unroll
         for (int g = 0; g < NQG; ++g) {
           if (g < nqg) {
@@ -788,12 +794,23 @@ __global__ __launch_bounds__(NT) void parzen_bwd_kernel(ParzenArgs a) {
 #pragma unroll
             for (int r = 0; r < 3; ++r) {
               const float gr = wv * dv[r];
-#pragma unroll
-              for (int cc = 0; cc < 4; ++cc) acc[g][4 * r + cc] = fmaf(gr, xt[cc], acc[g][4 * r + cc]);
+              rs[g][r] += gr;
+              rx[g][r] = fmaf(gr, fx, rx[g][r]);
             }
           }
         }
       }
+      // the row's sums into the gradient: along a lane's row only x varies,
+      // so the j, k and constant columns take the plain sum times j, k, 1
+#pragma unroll
+      for (int g = 0; g < NQG; ++g)
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+          acc[g][4 * r] += rx[g][r];
+          acc[g][4 * r + 1] = fmaf(rs[g][r], fj, acc[g][4 * r + 1]);
+          acc[g][4 * r + 2] = fmaf(rs[g][r], fk, acc[g][4 * r + 2]);
+          acc[g][4 * r + 3] += rs[g][r];
+        }
     }
   }
   // workgroup sum in fp64: shuffle tree per wave, then waves in order
