@@ -73,10 +73,12 @@ int check_q(const double* q, int32_t n_q) {
   return MI_OK;
 }
 
-// Bytes of the moving volume's gather layout on the Parzen path (16-bit
-// quad volume for integer volumes, fp32 quad volume for float ones).
-size_t parzen_gather_bytes(const mi_volume* m) {
-  return m->dtype == MI_F32 ? quad_f32_bytes(m->nx, m->ny, m->nz) : quad16_bytes(m->nx, m->ny, m->nz);
+// Bytes of the moving volume's gather layout on the Parzen path: fp32
+// quads for float volumes; for integer ones 16-bit quads on full sweeps and
+// 16-bit octs on sampled sweeps (one cache line per random sample).
+size_t parzen_gather_bytes(const mi_volume* m, bool sampled = false) {
+  if (m->dtype == MI_F32) return quad_f32_bytes(m->nx, m->ny, m->nz);
+  return sampled ? oct_volume_bytes(m->nx, m->ny, m->nz) : quad16_bytes(m->nx, m->ny, m->nz);
 }
 
 // The largest gather layout any path uses for the volume (the hard path's
@@ -165,7 +167,7 @@ Layout layout(const mi_volume* f, const mi_volume* m, int32_t n, int32_t bins, i
     off += align256(reduce_part_bytes(n, bins, n_q));
   } else {
     L.gvol = off;
-    off += align256(parzen_gather_bytes(m));
+    off += align256(parzen_gather_bytes(m, sampled));
     L.rowmap = off;
     off += align256(sizeof(RowMap));
     L.tmask = off;
@@ -482,8 +484,9 @@ int run_parzen(mi_context* ctx, const mi_volume* fixed, const mi_volume* moving,
     if ((e = launch_row_map(fb, voxels(fixed), bins, rows, s)) != hipSuccess) return hip_fail(e, "row map");
     if ((e = launch_tile_mask(fb, fixed->nx, fixed->ny, fixed->nz, (uint32_t*)(ws + L.tmask), s)) != hipSuccess)
       return hip_fail(e, "tile mask");
-    e = fq ? launch_pack_quads_f32(desc(moving), (float4*)gvol, s)
-           : launch_pack_quads16(desc(moving), (uint2*)gvol, s);
+    e = fq  ? launch_pack_quads_f32(desc(moving), (float4*)gvol, s)
+        : smp ? launch_pack_octs(desc(moving), (uint4*)gvol, s)
+              : launch_pack_quads16(desc(moving), (uint2*)gvol, s);
     if (e != hipSuccess) return hip_fail(e, "pack");
   }
   uint2* list = (uint2*)(ws + L.list);
@@ -522,7 +525,7 @@ int run_parzen(mi_context* ctx, const mi_volume* fixed, const mi_volume* moving,
   a.mnx = moving->nx;
   a.mny = moving->ny;
   a.mnz = moving->nz;
-  a.gvol_bytes = (uint32_t)parzen_gather_bytes(moving);
+  a.gvol_bytes = (uint32_t)parzen_gather_bytes(moving, smp != nullptr);
   a.n = n;
   a.bins = bins;
   a.slab_major = 1;

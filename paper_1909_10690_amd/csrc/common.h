@@ -420,7 +420,7 @@ struct ParzenArgs {
   const RowMap* rows;
   const uint32_t* tile_mask;  // [row groups][x tiles]: slot groups present in each 16 x 4 wave tile
   const uint32_t* row_mask;   // [row groups]: the OR of each row group's tile masks
-  const void* gvol;    // uint4 octs (integer moving) or float4 quads (float moving)
+  const void* gvol;    // integer moving: 16-bit quads (full sweeps) or octs (sampled); float: f32 quads
   double* table;       // [n][B][B] forward masses (fp64)
   uint64_t* count;     // [n] voxels that took part
   const float* gtab;   // [n][n_q][B][B] d MI / d p

@@ -408,12 +408,17 @@ struct ParzenFwdStep {
     return l;
   }
 
-  // The voxel's 2x2x2 moving neighbourhood as stored (uint4 octs, or two
-  // float4 quads).
-  template <bool FQ>
+  // The voxel's 2x2x2 moving neighbourhood as stored: two float4 quads
+  // (FQ), one 16-bit oct (OCT: all eight corners in one 16-byte record, as
+  // the hard path stores them), or two 16-bit quads.
+  template <bool FQ, bool OCT = false>
   __device__ __forceinline__ Raw fetch(uint32_t idx) const {
     Raw d;
-    if (FQ) {
+    if (OCT) {
+      const uint4_t o = __builtin_amdgcn_raw_buffer_load_b128(rsrc, idx * 16u, 0, 0);
+      d.a = uint4_t{o.x, o.y, 0u, 0u};
+      d.b = uint4_t{o.z, o.w, 0u, 0u};
+    } else if (FQ) {
       d.a = __builtin_amdgcn_raw_buffer_load_b128(rsrc, idx * 16u, 0, 0);
       d.b = __builtin_amdgcn_raw_buffer_load_b128(rsrc, idx * 16u, SZ, 0);
     } else {
@@ -459,12 +464,12 @@ struct ParzenFwdStep {
   // (or CLAMP) and its slot falls in the band's rows, its four B-spline taps
   // go into the LDS table.  Returns whether the voxel took part in this band
   // (each voxel belongs to one band, so the bands' counts add up to N).
-  template <bool FQ, bool CLAMP>
+  template <bool FQ, bool CLAMP, bool OCT = false>
   __device__ __forceinline__ bool add(const int64_t q[3], int32_t fb, const SweepCtx& sc, int cells, int copy,
                                       unsigned long long* lds_tab) const {
     const Loc l = locate<CLAMP>(q);
     if (!l.inside || fb < sc.r_lo || fb >= sc.r_hi) return false;
-    taps<FQ>(fetch<FQ>(l.idx), l, fb, sc, cells, copy, lds_tab);
+    taps<FQ>(fetch<FQ, OCT>(l.idx), l, fb, sc, cells, copy, lds_tab);
     return true;
   }
 };
@@ -585,7 +590,10 @@ __global__ __launch_bounds__(NT) void parzen_sampled_fwd_kernel(ParzenArgs a, co
       int64_t q[3];
 #pragma unroll
       for (int r = 0; r < 3; ++r) q[r] = Mq[4 * r] * x + Mq[4 * r + 1] * y + Mq[4 * r + 2] * z + Mq[4 * r + 3];
-      taken += ps.add<FQ, CLAMP>(q, slot, sc, cells, copy, lds_tab);
+      // integer moving volumes come as 16-bit octs here: a sample's eight
+      // corners in one cache line (the quads' two slices are two lines,
+      // and the samples of a list share few lines with each other)
+      taken += ps.add<FQ, CLAMP, !FQ>(q, slot, sc, cells, copy, lds_tab);
     }
   }
   if (taken) atomicAdd(&lds_count, taken);
