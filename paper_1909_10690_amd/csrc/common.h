@@ -10,6 +10,15 @@
 
 namespace gemi {
 
+// a * b + c with 24-bit unsigned operands a, b and b uniform
+// (v_mad_u32_u24, full rate; left to itself the compiler may pick the
+// quarter-rate 64-bit multiply-add).
+__device__ __forceinline__ uint32_t mad24(uint32_t a, uint32_t b, uint32_t c) {
+  uint32_t r;
+  asm("v_mad_u32_u24 %0, %1, %2, %3" : "=v"(r) : "v"(a), "s"(b), "v"(c));
+  return r;
+}
+
 constexpr int kMaxQ = 16;
 constexpr int kBlock = 256;  // threads per workgroup of the reduction kernels (4 wave64)
 
@@ -138,10 +147,11 @@ constexpr int kTileX = 16, kTileY = 4;  // a wave64 covers 16 x 4 fixed voxels a
 // Maps workgroup id -> (transform, slab, band).  Workgroups are dealt
 // round-robin to the 8 XCDs, so XCD x receives ids x, x+8, ...; those all
 // take slabs from the x-th eighth of the fixed volume.  Slab-major order
-// walks that eighth one thin slab at a time, all transforms (and bands) per
-// slab, so the workgroups resident on an XCD at once share one slab's
-// moving footprint in that XCD's L2; transform-major order finishes a
-// transform's slabs before the next transform.
+// (within a band, when there are several) walks that eighth one thin slab
+// at a time, all transforms per slab, so the workgroups resident on an XCD
+// at once share one slab's moving footprint in that XCD's L2;
+// transform-major order finishes a transform's slabs (all bands per slab)
+// before the next transform.
 __device__ __forceinline__ void block_work(int32_t chunks, int32_t n, int32_t bands,
                                            int32_t slab_major, uint32_t& t, uint32_t& chunk,
                                            uint32_t& band) {
@@ -150,10 +160,14 @@ __device__ __forceinline__ void block_work(int32_t chunks, int32_t n, int32_t ba
   const uint32_t c8 = (uint32_t)chunks >> 3;
   const uint32_t nb = (uint32_t)bands;
   if (slab_major) {
-    const uint32_t per = (uint32_t)n * nb;
-    const uint32_t cl = slot / per, rem = slot - cl * per;
-    t = rem / nb;
-    band = rem - t * nb;
+    // bands slowest: every workgroup of band 0 is dispatched before any of
+    // band 1, and so on.  A Parzen sweep's first band holds the background,
+    // nearly every voxel of a CT, so its workgroups are the long ones:
+    // dispatched first, they no longer trail the launch on a few CUs.
+    const uint32_t per = c8 * (uint32_t)n;
+    band = slot / per;
+    const uint32_t rem = slot - band * per, cl = rem / (uint32_t)n;
+    t = rem - cl * (uint32_t)n;
     chunk = xcd * c8 + cl;
   } else {
     const uint32_t per = c8 * nb;

@@ -285,14 +285,6 @@ struct SweepCtx {
   int32_t r_lo, r_hi;  // slots (occupied fixed-bin rows) of this band
 };
 
-// Table row index of a band's LDS cell e (slot r_lo + e / pitch, column
-// e % pitch; columns B .. pitch - 1 are padding).
-__device__ __forceinline__ size_t band_cell_row(const RowMap* m, int32_t r_lo, int e, int B, int pitch, int& col) {
-  const int rr = e / pitch;
-  col = e - rr * pitch;
-  return (size_t)m->row_of_slot[r_lo + rr] * B;
-}
-
 // ---------------------------------------------------------------------------
 // forward: Parzen table
 // ---------------------------------------------------------------------------
@@ -357,6 +349,88 @@ __device__ __forceinline__ void unpack(const Raw& d, float c[2][2][2]) {
   }
 }
 
+// The tiles of a row group that hold slots of a band, 64 tiles at a time:
+// lane i reads tile base + i's mask and a ballot gathers the wave's
+// answers, so the walk visits only those tiles and a tile without the
+// band's slots costs no load (bands other than the background's find their
+// slots in a few percent of the tiles).
+struct ActiveTiles {
+  uint64_t bits;  // tile base + i holds slots of the band (uniform)
+  int32_t base;
+
+  __device__ __forceinline__ ActiveTiles(const uint32_t* __restrict__ tmask, int32_t tb, int32_t XT, int lane,
+                                         uint32_t band_groups) {
+    const int32_t t = tb + lane;
+    const uint32_t m = t < XT ? tmask[t] : 0u;
+    bits = __ballot((m & band_groups) != 0u);
+    base = tb;
+  }
+  __device__ __forceinline__ bool any() const { return bits != 0; }
+  // the first tile, taken off the set
+  __device__ __forceinline__ int32_t first() {
+    const int32_t t = base + (int32_t)__builtin_ctzll(bits);
+    bits &= bits - 1;
+    return t;
+  }
+  // the next tile, taken off the set, or -1
+  __device__ __forceinline__ int32_t next() {
+    if (!bits) return -1;
+    return first();
+  }
+};
+
+// Slot of the fixed voxel at x of a lane's row, or -1 past the row.
+__device__ __forceinline__ int32_t fixed_slot(const uint8_t* __restrict__ frow, bool row_ok, int32_t x, int32_t nx) {
+  return row_ok && x < nx ? (int32_t)frow[x] : -1;
+}
+
+// Calls f(q, slot, x) for the voxels of a lane's row in a row group: x its
+// column, q its exact Q32 moving coordinates, slot its fixed slot (-1 past
+// the row), loaded one visited tile ahead.  A band that holds every slot
+// visits every tile in order; any other band only the tiles with its slots.
+template <typename F>
+__device__ __forceinline__ void row_tiles(const GroupWalk& w, const uint32_t* __restrict__ tmask, int32_t XT,
+                                          int lane, int dx, uint32_t band_groups, bool every,
+                                          const uint8_t* __restrict__ frow, bool row_ok, int32_t nx, F&& f) {
+  if (every) {
+    int64_t q[3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) q[r] = w.r[r] + w.lane_off[r];
+    int32_t fb_next = fixed_slot(frow, row_ok, dx, nx);
+    for (int32_t ti = 0; ti < XT; ++ti) {
+      const int32_t x = ti * kTileX + dx;
+      const int32_t fbv = fb_next;
+      if (ti + 1 < XT) fb_next = fixed_slot(frow, row_ok, x + kTileX, nx);
+      f(q, fbv, x);
+#pragma unroll
+      for (int r = 0; r < 3; ++r) q[r] += w.step[r];
+    }
+    return;
+  }
+  for (int32_t tb = 0; tb < XT; tb += 64) {
+    ActiveTiles at(tmask, tb, XT, lane, band_groups);
+    if (!at.any()) continue;
+    int32_t ti = at.first();
+    int64_t q[3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) q[r] = w.r[r] + w.lane_off[r] + w.step[r] * ti;
+    int32_t fb_next = fixed_slot(frow, row_ok, ti * kTileX + dx, nx);
+    for (;;) {
+      const int32_t fbv = fb_next;
+      const int32_t tn = at.next();
+      if (tn >= 0) fb_next = fixed_slot(frow, row_ok, tn * kTileX + dx, nx);
+      f(q, fbv, ti * kTileX + dx);
+      if (tn < 0) break;
+      // to the next visited tile one step at a time (a skipped tile costs
+      // three adds; a jump would need 64-bit products)
+      do {
+#pragma unroll
+        for (int r = 0; r < 3; ++r) q[r] += w.step[r];
+      } while (++ti < tn);
+    }
+  }
+}
+
 // Per-launch constants of the forward step of one fixed voxel.
 struct ParzenFwdStep {
   __amdgpu_buffer_rsrc_t rsrc;
@@ -404,7 +478,7 @@ struct ParzenFwdStep {
         l.frac[r] = (uint32_t)q[r];
       }
     }
-    l.idx = __umul24(__umul24(cix[2], NY) + cix[1], MX) + cix[0];
+    l.idx = mad24(mad24(cix[2], NY, cix[1]), MX, cix[0]);
     return l;
   }
 
@@ -450,7 +524,7 @@ struct ParzenFwdStep {
     const unsigned long long q0 = fixed40(wt[0]), q2 = fixed40(wt[2]), q3 = fixed40(wt[3]);
     const unsigned long long q1 = (1ull << 40) - q0 - q2 - q3;  // w1 >= 1/6
     const int32_t col0 = (int32_t)fl - 1;
-    int base = (fb - sc.r_lo) * pitch + col0;
+    int base = (int)__umul24((uint32_t)(fb - sc.r_lo), (uint32_t)pitch) + col0;  // fb >= r_lo
     // slot 0 (in band 0 only): the lane's copy of the row's hot columns
     if (fb == 0 && col0 + 3 < parzen_hot_cols(B)) base = cells + copy * parzen_hot_stride(B) + col0;
     unsigned long long* cell = lds_tab + base;
@@ -479,17 +553,19 @@ struct ParzenFwdStep {
 template <int NT>
 __device__ __forceinline__ void flush_parzen(const ParzenArgs& a, const SweepCtx& sc, int cells, int hot_cells,
                                              const unsigned long long* lds_tab, uint32_t lds_count) {
-  const int B = a.bins;
+  const int B = a.bins, pitch = parzen_pitch(B);
   double* __restrict__ out = a.table + (size_t)sc.t * B * B;
   const int hot_cols = hot_cells ? parzen_hot_cols(B) : 0, hot_stride = parzen_hot_stride(B);
-  for (int e = threadIdx.x; e < cells; e += NT) {
-    unsigned long long v = lds_tab[e];
-    if (e < hot_cols)  // slot 0's row is the band's first
-      for (int c = 0; c < kHotCopies; ++c) v += lds_tab[cells + c * hot_stride + e];
-    if (v) {  // (padding cells stay zero)
-      int col;
-      const size_t row = band_cell_row(a.rows, sc.r_lo, e, B, parzen_pitch(B), col);
-      atomicAdd(&out[row + col], (double)v * 9.094947017729282379150390625e-13);  // 2^-40
+  // a wave per band row, a lane per column: the row's table row is read
+  // once per wave, and no cell index is divided by the pitch
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int rr = wave; rr < sc.r_hi - sc.r_lo; rr += NT / 64) {
+    double* __restrict__ orow = out + (size_t)a.rows->row_of_slot[sc.r_lo + rr] * B;
+    for (int c = lane; c < B; c += 64) {
+      unsigned long long v = lds_tab[rr * pitch + c];
+      if (rr == 0 && c < hot_cols)  // slot 0's row is the band's first
+        for (int k = 0; k < kHotCopies; ++k) v += lds_tab[cells + k * hot_stride + c];
+      if (v) atomicAdd(&orow[c], (double)v * 9.094947017729282379150390625e-13);  // 2^-40
     }
   }
   if (threadIdx.x == 0 && lds_count)
@@ -525,28 +601,17 @@ __global__ __launch_bounds__(NT) void parzen_fwd_kernel(ParzenArgs a) {
     const ParzenFwdStep ps = ParzenFwdStep::template make<FQ>(a);
     const int32_t XT = (a.fnx + kTileX - 1) / kTileX;
     const uint32_t band_groups = slot_group_mask(sc.r_lo, sc.r_hi);
+    const bool every = sc.r_lo == 0 && sc.r_hi >= n_slots;  // the band holds every slot
     for (; w.g < w.g1; w.next()) {
       if (!(a.row_mask[w.g] & band_groups)) continue;  // no slot of this band in the row group
       const int32_t j = w.j0 + dy;
       const bool row_ok = j < a.fny;
       const uint8_t* __restrict__ frow = a.fbins + ((int64_t)w.k * a.fny + (row_ok ? j : 0)) * a.fnx;
       const uint32_t* __restrict__ tmask = a.tile_mask + (int64_t)w.g * XT;
-      int64_t q[3];
-#pragma unroll
-      for (int r = 0; r < 3; ++r) q[r] = w.r[r] + w.lane_off[r];
-      // the wave's tiles in x, a uniform trip count: a tile without slots of
-      // this band is skipped whole; each voxel's fixed bin is loaded one
-      // step ahead, so the band test waits on a load issued a tile earlier
-      int32_t fb_next = row_ok && dx < a.fnx ? (int32_t)frow[dx] : -1;
-      for (int32_t ti = 0; ti < XT; ++ti) {
-        const int32_t x = ti * kTileX + dx;
-        const int32_t fbv = fb_next;
-        if (row_ok && x + kTileX < a.fnx) fb_next = (int32_t)frow[x + kTileX];
-        if ((tmask[ti] & band_groups) && fbv >= 0 && x < a.fnx)
-          taken += ps.add<FQ, CLAMP>(q, fbv, sc, cells, copy, lds_tab);
-#pragma unroll
-        for (int r = 0; r < 3; ++r) q[r] += w.step[r];
-      }
+      row_tiles(w, tmask, XT, lane, dx, band_groups, every, frow, row_ok, a.fnx,
+                [&](const int64_t q[3], int32_t fbv, int32_t) {
+                  if (fbv >= 0) taken += ps.add<FQ, CLAMP>(q, fbv, sc, cells, copy, lds_tab);
+                });
     }
   }
   if (taken) atomicAdd(&lds_count, taken);
@@ -695,12 +760,26 @@ __global__ __launch_bounds__(NT) void parzen_bwd_kernel(ParzenArgs a) {
   int64_t Mq[12];
   const bool ok = quantize_transform(a.transforms + 12 * (size_t)sc.t, Mq);
   const int nqg = min(NQG, a.n_q - a.q0);
-  for (int g = 0; g < nqg; ++g) {
-    const float* __restrict__ src = a.gtab + ((size_t)sc.t * a.n_q + a.q0 + g) * BB;
-    for (int e = threadIdx.x; e < cells; e += NT) {
-      int col;
-      const size_t row = band_cell_row(a.rows, sc.r_lo, e, B, parzen_pitch(B), col);
-      lds_g[g * cells + e] = col < B ? src[row + col] : 0.0f;
+  {
+    // a wave per band row: the row's pitch cells (B <= 256, so at most 5 per
+    // lane), all loads issued before the first store
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, pitch = parzen_pitch(B);
+    const int nrows = sc.r_hi - sc.r_lo;
+    for (int g = 0; g < nqg; ++g) {
+      const float* __restrict__ src = a.gtab + ((size_t)sc.t * a.n_q + a.q0 + g) * BB;
+      for (int rr = wave; rr < nrows; rr += NW) {
+        const float* __restrict__ srow = src + (size_t)a.rows->row_of_slot[sc.r_lo + rr] * B;
+        float v[5];
+#pragma unroll
+        for (int k = 0; k < 5; ++k) {
+          const int c = lane + 64 * k;
+          v[k] = c < B ? srow[c] : 0.0f;
+        }
+        float* __restrict__ drow = lds_g + g * cells + rr * pitch;
+#pragma unroll
+        for (int k = 0; k < 5; ++k)
+          if (lane + 64 * k < pitch) drow[lane + 64 * k] = v[k];
+      }
     }
   }
   __syncthreads();
@@ -725,6 +804,7 @@ __global__ __launch_bounds__(NT) void parzen_bwd_kernel(ParzenArgs a) {
     const float smax = (float)(B - 3);
     const int32_t XT = (a.fnx + kTileX - 1) / kTileX;
     const uint32_t band_groups = slot_group_mask(sc.r_lo, sc.r_hi);
+    const bool every = sc.r_lo == 0 && sc.r_hi >= n_slots;  // the band holds every slot
     for (; w.g < w.g1; w.next()) {
       if (!(a.row_mask[w.g] & band_groups)) continue;  // no slot of this band in the row group
       const int32_t j = w.j0 + dy;
@@ -738,19 +818,8 @@ __global__ __launch_bounds__(NT) void parzen_bwd_kernel(ParzenArgs a) {
       for (int g = 0; g < NQG; ++g)
 #pragma unroll
         for (int r = 0; r < 3; ++r) rs[g][r] = rx[g][r] = 0.0f;
-      int64_t q[3];
-#pragma unroll
-      for (int r = 0; r < 3; ++r) q[r] = w.r[r] + w.lane_off[r];
-      int32_t fb_next = row_ok && dx < a.fnx ? (int32_t)frow[dx] : -1;  // one step ahead, as in the forward
-      for (int32_t ti = 0; ti < XT; ++ti) {
-        const int32_t x = ti * kTileX + dx;
-        const int32_t fbv = fb_next;
-        if (row_ok && x + kTileX < a.fnx) fb_next = (int32_t)frow[x + kTileX];
-        if (!(tmask[ti] & band_groups) || fbv < 0 || x >= a.fnx) {  // a tile without this band's slots
-#pragma unroll
-          for (int r = 0; r < 3; ++r) q[r] += w.step[r];
-          continue;
-        }
+      // one voxel of slot fb in this band at Q32 coordinates q, x its column
+      auto differentiate = [&](const int64_t q[3], int32_t fb, int32_t x) {
         uint32_t cell[3], frac[3];
         bool inside = true, moves[3];
 #pragma unroll
@@ -764,12 +833,9 @@ __global__ __launch_bounds__(NT) void parzen_bwd_kernel(ParzenArgs a) {
             cell[r] = (uint32_t)(q[r] >> 32);
             frac[r] = (uint32_t)q[r];
           }
-          q[r] += w.step[r];
         }
-        if (!inside) continue;
-        const int32_t fb = fbv;
-        if (fb < sc.r_lo || fb >= sc.r_hi) continue;
-        const uint32_t idx = __umul24(__umul24(cell[2], NY) + cell[1], MX) + cell[0];
+        if (!inside) return;
+        const uint32_t idx = mad24(mad24(cell[2], NY, cell[1]), MX, cell[0]);
         float c[2][2][2];
         gather<FQ>(rsrc, idx, SZ, c);
         const float tx = (float)frac[0] * 2.3283064365386963e-10f;
@@ -792,22 +858,26 @@ __global__ __launch_bounds__(NT) void parzen_bwd_kernel(ParzenArgs a) {
         const float fl = floorf(s);
         float d[4];
         bspline_slopes(s - fl, d);
-        const int col = (fb - sc.r_lo) * parzen_pitch(B) + ((int32_t)fl - 1);
+        const int col = (int)__umul24((uint32_t)(fb - sc.r_lo), (uint32_t)parzen_pitch(B)) + ((int32_t)fl - 1);
         const float fx = (float)x;
+        // every group reads a table (groups past nqg repeat the last one and
+        // are never written out), so no branch splits the groups' LDS reads
 #pragma unroll
         for (int g = 0; g < NQG; ++g) {
-          if (g < nqg) {
-            const float* Gr = lds_g + g * cells + col;
-            const float wv = -(Gr[0] * d[0] + Gr[1] * d[1] + Gr[2] * d[2] + Gr[3] * d[3]);
+          const float* Gr = lds_g + (g < nqg ? g : nqg - 1) * cells + col;
+          const float wv = -(Gr[0] * d[0] + Gr[1] * d[1] + Gr[2] * d[2] + Gr[3] * d[3]);
 #pragma unroll
-            for (int r = 0; r < 3; ++r) {
-              const float gr = wv * dv[r];
-              rs[g][r] += gr;
-              rx[g][r] = fmaf(gr, fx, rx[g][r]);
-            }
+          for (int r = 0; r < 3; ++r) {
+            const float gr = wv * dv[r];
+            rs[g][r] += gr;
+            rx[g][r] = fmaf(gr, fx, rx[g][r]);
           }
         }
-      }
+      };
+      row_tiles(w, tmask, XT, lane, dx, band_groups, every, frow, row_ok, a.fnx,
+                [&](const int64_t q[3], int32_t fbv, int32_t x) {
+                  if (fbv >= sc.r_lo && fbv < sc.r_hi) differentiate(q, fbv, x);
+                });
       // the row's sums into the gradient: along a lane's row only x varies,
       // so the j, k and constant columns take the plain sum times j, k, 1
 #pragma unroll

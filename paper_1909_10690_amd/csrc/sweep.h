@@ -24,14 +24,6 @@ __device__ uint4_t struct_load_b128(__amdgpu_buffer_rsrc_t rsrc, int vindex, int
 __device__ uint2_t struct_load_b64(__amdgpu_buffer_rsrc_t rsrc, int vindex, int voffset, int soffset, int aux)
     __asm("llvm.amdgcn.struct.ptr.buffer.load.v2i32");
 
-// a * b + c with 24-bit unsigned operands a, b (v_mad_u32_u24, full rate;
-// left to itself the compiler may pick a 64-bit multiply-add).
-__device__ __forceinline__ uint32_t mad24(uint32_t a, uint32_t b, uint32_t c) {
-  uint32_t r;
-  asm("v_mad_u32_u24 %0, %1, %2, %3" : "=v"(r) : "v"(a), "s"(b), "v"(c));
-  return r;
-}
-
 // v0 (1 - w) + v1 w at 16-bit weight w = fx >> 16, exact: the pair's low
 // half times (65535 - w), high half times w, plus the low half once more.
 __device__ __forceinline__ uint32_t lerp_x(uint32_t pair, uint32_t wpack) {
