@@ -328,6 +328,32 @@ class Context:
         _check(st, "mi_grad")
         return mi, g
 
+    def grad_fn(self, fixed: Volume, moving: Volume, transforms: torch.Tensor, bins: int, q, flags: int,
+                workspace: torch.Tensor, out: tuple, stream=None):
+        """A function f(extra_flags) that runs :meth:`grad` on these arguments
+        (device tensors, kept alive by the function) with ``flags |
+        extra_flags``: the arguments are checked and marshalled once, for
+        loops that call the same evaluation many times."""
+        dev = fixed.tensor.device
+        n = transforms.shape[0]
+        qs, qp = _qarr(q)
+        mi, g = out
+        if transforms.dtype != torch.float64 or not transforms.is_contiguous() or transforms.device != dev \
+                or transforms.shape != (n, 12):
+            raise ValueError("transforms must be a contiguous float64 device tensor [n][12]")
+        if mi.shape != (n, len(qs)) or g.shape != (n, len(qs), 12) or mi.dtype != torch.float64 \
+                or g.dtype != torch.float64 or not mi.is_contiguous() or not g.is_contiguous():
+            raise ValueError("out must be contiguous float64 tensors [n][n_q] and [n][n_q][12]")
+        f, m = fixed.c(), moving.c()
+        args = (self.handle, ctypes.byref(f), ctypes.byref(m), _ptr(transforms), n, bins, qp, len(qs))
+        tail = (_ptr(mi), _ptr(g), _ptr(workspace), workspace.numel(), self._stream(stream))
+        call, keep = self.lib.mi_grad, (f, m, qs, qp, transforms, mi, g, workspace)
+
+        def run(extra_flags: int = 0):
+            _check(call(*args, flags | extra_flags, *tail), "mi_grad")
+            return keep[5], keep[6]
+        return run
+
     @staticmethod
     def _pair_array(pairs):
         arr = (MiPair * len(pairs))()

@@ -142,8 +142,6 @@ __device__ __forceinline__ uint32_t clamp_offset(int32_t v, int32_t lo, int32_t 
 // the fixed-volume sweep shared by the histogram kernels
 // ---------------------------------------------------------------------------
 
-constexpr int kTileX = 16, kTileY = 4;  // a wave64 covers 16 x 4 fixed voxels at a time
-
 // Maps workgroup id -> (transform, slab, band).  Workgroups are dealt
 // round-robin to the 8 XCDs, so XCD x receives ids x, x+8, ...; those all
 // take slabs from the x-th eighth of the fixed volume.  Slab-major order
@@ -177,50 +175,6 @@ __device__ __forceinline__ void block_work(int32_t chunks, int32_t n, int32_t ba
     chunk = xcd * c8 + (rem - band * c8);
   }
 }
-
-// One wave's walk over its share of a slab: groups of kTileY consecutive
-// rows of one slice, visited in order with exact Q32 row coordinates.
-// Lane (dx, dy) of the 16 x 4 tile starts at r + lane_off and steps by
-// `step` = 16 M[:,0] along x.
-struct GroupWalk {
-  int64_t g, g1;
-  int32_t j0, k, G;
-  int64_t r[3], lane_off[3], step[3], adv[3], wrap[3];
-
-  __device__ __forceinline__ void init(const int64_t* Mq, int32_t fny, int32_t fnz,
-                                       int32_t chunks, uint32_t chunk, int wave, int nwaves,
-                                       int dx, int dy) {
-    G = (fny + kTileY - 1) / kTileY;
-    const int64_t groups = (int64_t)G * fnz;
-    const int64_t s0 = groups * chunk / chunks, s1 = groups * (chunk + 1) / chunks;
-    g = s0 + (s1 - s0) * wave / nwaves;
-    g1 = s0 + (s1 - s0) * (wave + 1) / nwaves;
-    k = (int32_t)(g / G);
-    j0 = (int32_t)(g - (int64_t)k * G) * kTileY;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      const int64_t m0 = Mq[4 * a], m1 = Mq[4 * a + 1], m2 = Mq[4 * a + 2], m3 = Mq[4 * a + 3];
-      r[a] = m1 * j0 + m2 * k + m3;
-      lane_off[a] = m0 * dx + m1 * dy;
-      step[a] = m0 * kTileX;
-      adv[a] = m1 * kTileY;
-      wrap[a] = m2 - m1 * ((int64_t)G * kTileY);
-    }
-  }
-
-  __device__ __forceinline__ void next() {
-    ++g;
-    j0 += kTileY;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) r[a] += adv[a];
-    if (j0 >= G * kTileY) {
-      j0 = 0;
-      ++k;
-#pragma unroll
-      for (int a = 0; a < 3; ++a) r[a] += wrap[a];
-    }
-  }
-};
 
 // The same walk in brick order: the row groups of a slice are cut along y
 // into blocks of `yb` groups and a block is visited slice by slice before

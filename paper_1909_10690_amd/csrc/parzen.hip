@@ -389,7 +389,7 @@ __device__ __forceinline__ int32_t fixed_slot(const uint8_t* __restrict__ frow, 
 // the row), loaded one visited tile ahead.  A band that holds every slot
 // visits every tile in order; any other band only the tiles with its slots.
 template <typename F>
-__device__ __forceinline__ void row_tiles(const GroupWalk& w, const uint32_t* __restrict__ tmask, int32_t XT,
+__device__ __forceinline__ void row_tiles(const GroupWalkFlex& w, const uint32_t* __restrict__ tmask, int32_t XT,
                                           int lane, int dx, uint32_t band_groups, bool every,
                                           const uint8_t* __restrict__ frow, bool row_ok, int32_t nx, F&& f) {
   if (every) {
@@ -596,8 +596,9 @@ __global__ __launch_bounds__(NT) void parzen_fwd_kernel(ParzenArgs a) {
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     const int dx = lane & (kTileX - 1), dy = lane / kTileX;
-    GroupWalk w;
-    w.init(Mq, a.fny, a.fnz, a.chunks, sc.chunk, wave, NT / 64, dx, dy);
+    // bands of rare slots (not the background's) interleave their waves
+    GroupWalkFlex w;
+    w.init(Mq, a.fny, a.fnz, a.chunks, sc.chunk, wave, NT / 64, dx, dy, sc.r_lo > 0);
     const ParzenFwdStep ps = ParzenFwdStep::template make<FQ>(a);
     const int32_t XT = (a.fnx + kTileX - 1) / kTileX;
     const uint32_t band_groups = slot_group_mask(sc.r_lo, sc.r_hi);
@@ -792,8 +793,8 @@ __global__ __launch_bounds__(NT) void parzen_bwd_kernel(ParzenArgs a) {
   const int lane = threadIdx.x & 63;
   if (ok && a.count[sc.t] > 0) {
     const int dx = lane & (kTileX - 1), dy = lane / kTileX;
-    GroupWalk w;
-    w.init(Mq, a.fny, a.fnz, a.chunks, sc.chunk, wave, NW, dx, dy);
+    GroupWalkFlex w;  // as in the forward
+    w.init(Mq, a.fny, a.fnz, a.chunks, sc.chunk, wave, NW, dx, dy, sc.r_lo > 0);
     const int32_t nq[3] = {a.mnx, a.mny, a.mnz};
     const uint64_t top[3] = {(uint64_t)(a.mnx - 1) << 32, (uint64_t)(a.mny - 1) << 32,
                              (uint64_t)(a.mnz - 1) << 32};

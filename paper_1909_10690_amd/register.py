@@ -33,10 +33,22 @@ from .autograd import volume_centre
 
 
 def decomposed_to_affine(d) -> np.ndarray:
-    """(angles (rad), log-scales, shears (h_xy, h_xz, h_yz), t) -> (A.flat, t)."""
-    d = np.asarray(d, dtype=np.float64)
-    A = T.affine_matrix(np.rad2deg(d[0:3]), np.exp(d[3:6]), d[6:9])
-    return T.params_from(A, d[9:12])
+    """(angles (rad), log-scales, shears (h_xy, h_xz, h_yz), t) -> (A.flat, t),
+    A = Rz Ry Rx H S as in ``transforms.affine_matrix``, written out in
+    scalars (the registration computes it before every sweep)."""
+    ax, ay, az, l0, l1, l2, hxy, hxz, hyz, t0, t1, t2 = (float(x) for x in np.asarray(d, dtype=np.float64))
+    cx, sx, cy, sy, cz, sz = math.cos(ax), math.sin(ax), math.cos(ay), math.sin(ay), math.cos(az), math.sin(az)
+    # R = Rz Ry Rx
+    r00, r01, r02 = cz * cy, cz * sy * sx - sz * cx, cz * sy * cx + sz * sx
+    r10, r11, r12 = sz * cy, sz * sy * sx + cz * cx, sz * sy * cx - cz * sx
+    r20, r21, r22 = -sy, cy * sx, cy * cx
+    # columns of R H, then scaled by S
+    s0, s1, s2 = math.exp(l0), math.exp(l1), math.exp(l2)
+    return np.array([
+        r00 * s0, (r00 * hxy + r01) * s1, (r00 * hxz + r01 * hyz + r02) * s2,
+        r10 * s0, (r10 * hxy + r11) * s1, (r10 * hxz + r11 * hyz + r12) * s2,
+        r20 * s0, (r20 * hxy + r21) * s1, (r20 * hxz + r21 * hyz + r22) * s2,
+        t0, t1, t2])
 
 
 def affine_to_decomposed(p) -> np.ndarray:
@@ -161,19 +173,24 @@ def register(gctx: B.Context, fixed: B.Volume, moving: B.Volume, bins: int,
     P_dev = torch.empty((1, 12), dtype=torch.float64, device=dev)
     res = torch.empty(nq * 13, dtype=torch.float64, device=dev)
     mi_out, g_out = res[:nq].view(1, nq), res[nq:].view(1, nq, 12)
+    grad = gctx.grad_fn(fixed, moving, P_dev, bins, q, flags, workspace, (mi_out, g_out))
+
+    def sync_state():
+        state.params = [float(x) for x in d]
+        state.m, state.v = [float(x) for x in m], [float(x) for x in v]
+
     while state.step < steps:
         pa = decomposed_to_affine(d) if dec else d
         P_host.numpy()[:] = T.centred_matrix(pa[:9], pa[9:], c).reshape(1, 12)
         P_dev.copy_(P_host, non_blocking=True)
         # the volumes and workspace stay the same over the loop: after the
         # first call the library reuses their preparation
-        reuse = B.VOLUMES_UNCHANGED if state.step > first else 0
-        gctx.grad(fixed, moving, P_dev, bins, q, flags=flags | reuse, workspace=workspace, out=(mi_out, g_out))
+        grad(B.VOLUMES_UNCHANGED if state.step > first else 0)
+        # while the device sweeps: the chain rule's Jacobian at this step
+        Jd = J @ decomposed_jacobian(d) if dec else J   # d P / d (angles, log-scales, shears, t) or d (A, t)
         h = res.cpu().numpy()                   # waits for the step; P_host is free again
         mi, gP = h[:nq], h[nq:].reshape(nq, 12)
-        gp = gP @ J                             # [n_q][12] d MI_q / d (A, t)
-        if dec:
-            gp = gp @ decomposed_jacobian(d)    # d MI_q / d (angles, log-scales, shears, t)
+        gp = gP @ Jd                            # [n_q][12] d MI_q / d parameters
         if mixed:
             g = np.concatenate([gp[0, :9], gp[1, 9:]])
         else:
@@ -185,11 +202,12 @@ def register(gctx: B.Context, fixed: B.Volume, moving: B.Volume, bins: int,
         vh = v / (1 - b2 ** state.step)
         delta = lr * mh / (np.sqrt(vh) + 1e-12)
         d = d + delta   # ascent
-        state.params = [float(x) for x in d]
-        state.m, state.v = [float(x) for x in m], [float(x) for x in v]
         state.history.append((state.step, [float(x) for x in mi]))
         if checkpoint and (state.step % every == 0 or state.step == steps):
+            sync_state()
             state.save(checkpoint)
-        if not all(math.isfinite(x) for x in state.params):
+        if not np.all(np.isfinite(d)):
+            sync_state()
             raise FloatingPointError("registration diverged")
+    sync_state()
     return state

@@ -84,6 +84,19 @@ def test_decomposed_parameters_round_trip():
         affine_to_decomposed(np.concatenate([np.diag([-1.0, 1.0, 1.0]).reshape(9), np.zeros(3)]))
 
 
+def test_decomposed_to_affine_matches_matrix_product():
+    """The scalar form equals R(angles) H(shears) diag(exp(log-scales)) built
+    from the 3x3 factors, with t passed through."""
+    from paper_1909_10690_amd.register import decomposed_to_affine
+    rng = np.random.default_rng(15)
+    for _ in range(50):
+        d = np.concatenate([rng.uniform(-0.6, 0.6, 3), rng.uniform(-0.2, 0.2, 3), rng.uniform(-0.2, 0.2, 3),
+                            rng.uniform(-10, 10, 3)])
+        A = T.affine_matrix(np.rad2deg(d[0:3]), np.exp(d[3:6]), d[6:9])
+        np.testing.assert_allclose(decomposed_to_affine(d), np.concatenate([A.reshape(9), d[9:]]),
+                                   rtol=0, atol=1e-14)
+
+
 def test_decomposed_jacobian_at_identity():
     from paper_1909_10690_amd.register import decomposed_jacobian
     J = decomposed_jacobian(np.zeros(12))
