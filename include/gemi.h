@@ -309,15 +309,15 @@ int mi_map_paths(mi_context *ctx, const double *values, int32_t nx, int32_t ny, 
  *    shape).  The workspace is the one mi_eval would use with
  *    hist_out = NULL.
  *  - Parzen (MI_HIST_PARZEN): the forward sweep's, then the backward
- *    sweep's workgroup size (512/1024) and LDS band budget (32, 64, 96 or
- *    128 KiB: how many bands of table rows walk the fixed volume), then the
- *    workgroup count (half, as planned, twice), timing forward and gradient
- *    calls with one entropy.  MI changes only in the last bits (the order
- *    in which workgroup partial sums merge), gradients at the level of the
- *    fp32 per-lane partial sums, whose grouping follows the shape (~1e-7
- *    relative).  The workspace is
- *    mi_workspace_size() for these arguments with n_q = 2 and MI_GRADIENT;
- *    its contents are overwritten.
+ *    sweep's workgroup size (256/512/1024) and LDS band budget (32, 64, 96
+ *    or 128 KiB: how many bands of table rows walk the fixed volume), then
+ *    the workgroup count (half, as planned, twice, four times), timing
+ *    forward and gradient calls with one entropy.  MI changes only in the
+ *    last bits (the order in which workgroup partial sums merge), gradients
+ *    at the level of the fp32 per-lane partial sums, whose grouping follows
+ *    the shape (~1e-7 relative).  The workspace is mi_workspace_size() for
+ *    these arguments with n_q = 2 and MI_GRADIENT; its contents are
+ *    overwritten.
  * Synchronous: waits for `stream`.  MI_USE_GRAPH and MI_VOLUMES_UNCHANGED
  * are ignored; MI_SAMPLED and MI_GRADIENT give MI_ERR_FLAGS.
  * Environment defaults read at mi_create for untuned classes (measurement

@@ -262,7 +262,7 @@ struct PairsTune {
 struct ParzenTune {
   int32_t fwd_block = 512, fwd_lds_kib = 64;  // 256/512/1024; 16, 32, 64, 96 or 128
   int32_t bwd_block = 512, bwd_lds_kib = 64;
-  int32_t chunk_shift = 0;  // -1, 0, 1: half, as planned, twice the workgroups
+  int32_t chunk_shift = 0;  // -1, 0, 1, 2: half, as planned, twice, four times the workgroups
 };
 
 // The untuned shape.  Up to 64 bins a table fits one 64 KiB band, and
@@ -548,7 +548,7 @@ int run_parzen(mi_context* ctx, const mi_volume* fixed, const mi_volume* moving,
     pa.bands = (bins + pa.band_rows - 1) / pa.band_rows;
     int64_t chunks = smp ? plan_sampled_chunks(ctx, expected_samples(fixed, *smp), (int64_t)n * pa.bands)
                          : plan_parzen_chunks(ctx, fixed, moving, (int64_t)n * pa.bands);
-    if (tune.chunk_shift > 0) chunks *= 2;
+    if (tune.chunk_shift > 0) chunks <<= tune.chunk_shift;
     if (tune.chunk_shift < 0) chunks = std::max<int64_t>(8, ((chunks / 2 + 7) / 8) * 8);
     pa.chunks = (int32_t)std::min<int64_t>(chunks, 1 << 24);
     const int64_t per_launch = 0x7FFFFFFFll / ((int64_t)pa.chunks * pa.bands);
@@ -743,7 +743,7 @@ void load_tune_file(mi_context* c) {
       auto good_block = [](int32_t b) { return b == 256 || b == 512 || b == 1024; };
       auto good_kib = [](int32_t v) { return v == 16 || v == 32 || v == 64 || v == 96 || v == 128; };
       if (ok && good_block(pt.fwd_block) && good_block(pt.bwd_block) && good_kib(pt.fwd_lds_kib) &&
-          good_kib(pt.bwd_lds_kib) && pt.chunk_shift >= -1 && pt.chunk_shift <= 1)
+          good_kib(pt.bwd_lds_kib) && pt.chunk_shift >= -1 && pt.chunk_shift <= 2)
         c->parzen_tuned.emplace_back(k, pt);
       continue;
     }
@@ -989,7 +989,7 @@ int tune_parzen(mi_context* ctx, const mi_volume* fixed, const mi_volume* moving
     ms_out = total;
     return MI_OK;
   };
-  const int32_t blocks[2] = {512, 1024}, budgets[4] = {32, 64, 96, 128};
+  const int32_t blocks[3] = {256, 512, 1024}, budgets[4] = {32, 64, 96, 128};
   for (int pass = 0; pass < 2 && st == MI_OK; ++pass) {  // 0: forward, 1: backward
     float best_ms = 3.4e38f;
     ParzenTune keep = best;
@@ -1015,7 +1015,7 @@ int tune_parzen(mi_context* ctx, const mi_volume* fixed, const mi_volume* moving
   if (st == MI_OK) {
     float best_ms = 3.4e38f;
     ParzenTune keep = best;
-    for (int32_t sh : {-1, 0, 1}) {
+    for (int32_t sh : {-1, 0, 1, 2}) {
       ParzenTune c = best;
       c.chunk_shift = sh;
       float ms = 0;
@@ -1299,7 +1299,7 @@ int mi_create(mi_context** out, int device) {
   }
   if (const char* k = getenv("MI_TUNE_PARZEN_CHUNK_SHIFT")) {
     const int v = atoi(k);
-    if (v >= -1 && v <= 1) {
+    if (v >= -1 && v <= 2) {
       c->parzen_default.chunk_shift = v;
       c->parzen_env = true;
     }

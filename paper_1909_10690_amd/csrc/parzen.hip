@@ -866,12 +866,13 @@ __global__ __launch_bounds__(NT) void parzen_bwd_kernel(ParzenArgs a) {
 #pragma unroll
         for (int g = 0; g < NQG; ++g) {
           const float* Gr = lds_g + (g < nqg ? g : nqg - 1) * cells + col;
-          const float wv = -(Gr[0] * d[0] + Gr[1] * d[1] + Gr[2] * d[2] + Gr[3] * d[3]);
+          // w(x) = -sum G beta3': subtracted below rather than negated
+          const float w = Gr[0] * d[0] + Gr[1] * d[1] + Gr[2] * d[2] + Gr[3] * d[3];
+          const float wx = w * fx;
 #pragma unroll
           for (int r = 0; r < 3; ++r) {
-            const float gr = wv * dv[r];
-            rs[g][r] += gr;
-            rx[g][r] = fmaf(gr, fx, rx[g][r]);
+            rs[g][r] = fmaf(-w, dv[r], rs[g][r]);
+            rx[g][r] = fmaf(-wx, dv[r], rx[g][r]);
           }
         }
       };

@@ -289,7 +289,8 @@ def test_pairs_preparation_reuse(ctx):
         torch.cuda.synchronize()
 
 
-@pytest.mark.parametrize("forced", [None, "512 32 1024 128 -1", "1024 64 512 16 1", "256 96 256 64 0"])
+@pytest.mark.parametrize("forced", [None, "512 32 1024 128 -1", "1024 64 512 16 1", "256 96 256 64 0",
+                                    "512 64 256 64 2"])
 def test_parzen_tune_and_shapes_keep_results(tmp_path, forced):
     """mi_tune with MI_HIST_PARZEN picks forward and backward launch shapes;
     MI and gradients after tuning, and under shapes forced through the cache
@@ -319,7 +320,8 @@ def test_parzen_tune_and_shapes_keep_results(tmp_path, forced):
         lines = [l for l in path.read_text().splitlines() if l.startswith("gemi-tune-parzen")]
         assert len(lines) == 1
         fields = lines[0].split()
-        assert fields[1:4] == ["70", "52", "40"] and fields[11] in ("512", "1024") and fields[13] in ("512", "1024")
+        assert fields[1:4] == ["70", "52", "40"] and fields[11] in ("256", "512", "1024") \
+            and fields[13] in ("256", "512", "1024") and fields[15] in ("-1", "0", "1", "2")
         if forced:
             path.write_text(" ".join(fields[:11] + forced.split()) + "\n")
             ctx.close()
