@@ -291,7 +291,24 @@ struct HardLaunch {
   int32_t block;   // threads per workgroup: 256, 512 or 1024
   int32_t slab_major;  // workgroup order: 1 slab-major, 0 transform-major
   int32_t brick;       // 1: slabs as bricks (GroupWalkBrick; 1024-thread launches)
+  // processing order (launch_order_transforms), or NULL: the workgroups of
+  // slot t sweep transform order[t] - order_t0; order_t0 is the batch index
+  // of this launch's first transform
+  const uint32_t* order;
+  int64_t order_t0;
 };
+
+// Transforms per block of the processing order: the order is sorted within
+// blocks of this many transforms, and launches that use it start at
+// multiples of it.
+constexpr int32_t kOrderBlock = 4096;
+
+// The processing order of a batch of n index-space matrices for the hard
+// sweep (order[i], absolute indices, a permutation of each block of
+// kOrderBlock transforms): transforms whose images of the fixed volume lie
+// at similar moving depths come together (see the kernel).
+hipError_t launch_order_transforms(const double* M, int32_t n, int32_t fnx, int32_t fny, int32_t fnz, uint32_t* order,
+                                   hipStream_t s);
 
 // The gathers address their volume with 32-bit buffer offsets, so every
 // gather volume stays below 4 GiB (the entry points check it).

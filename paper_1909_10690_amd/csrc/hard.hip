@@ -250,7 +250,9 @@ struct HardArgs {
   uint32_t* hist;
   HardGeom geom;
   int32_t n, chunks;
-  int32_t slab_major;  // 1: consecutive workgroups of an XCD share a slab
+  int32_t slab_major;     // 1: consecutive workgroups of an XCD share a slab
+  const uint32_t* order;  // processing order (absolute indices) or NULL
+  uint32_t order_base;    // absolute index of this launch's first transform
 };
 
 // 1024-thread workgroups are held to 64 VGPRs (a few row-loop values spill to
@@ -266,6 +268,7 @@ void hist_hard_kernel(HardArgs a) {
   clear_hist<PACKED, NT>(lds_hist, B);
   uint32_t t, chunk, band;
   block_work(a.chunks, a.n, 1, a.slab_major, t, chunk, band);
+  if (a.order) t = a.order[t] - a.order_base;
   int64_t Mq[12];
   const bool ok = quantize_transform(a.transforms + 12 * (size_t)t, Mq);
   __syncthreads();
@@ -388,14 +391,23 @@ hipError_t launch_hist_hard(const HardLaunch& L, hipStream_t s) {
   a.n = L.n;
   a.chunks = L.chunks;
   a.slab_major = L.slab_major;
+  a.order = nullptr;
+  a.order_base = 0;
   const size_t lds = hist_lds_bytes(L.bins, L.packed);
   if (L.block != 256 && L.block != 512 && L.block != 1024) return hipErrorInvalidValue;
-  const int32_t step = transforms_per_launch(L.chunks, L.block);
+  int32_t step = transforms_per_launch(L.chunks, L.block);
+  // with an order, launches start at multiples of its sorted blocks
+  const bool ordered = L.order && step >= kOrderBlock;
+  if (ordered) step -= step % kOrderBlock;
   for (int32_t t0 = 0; t0 < L.n; t0 += step) {
     HardArgs b = a;
     b.n = L.n - t0 < step ? L.n - t0 : step;
     b.transforms = a.transforms + 12 * (size_t)t0;
     b.hist = a.hist + (size_t)t0 * L.bins * L.bins;
+    if (ordered) {
+      b.order = L.order + t0;
+      b.order_base = (uint32_t)(L.order_t0 + t0);
+    }
     hipError_t e;
     switch (L.block) {
     case 256: e = launch_nt<256>(b, b.n, L.clamp, L.packed, lds, s); break;
@@ -419,6 +431,8 @@ hipError_t launch_hist_sampled(const HardLaunch& L, const uint2* list, const uns
   a.n = L.n;
   a.chunks = L.chunks;
   a.slab_major = 1;
+  a.order = nullptr;  // the sampled sweep keeps the batch order
+  a.order_base = 0;
   const size_t lds = hist_lds_bytes(L.bins, L.packed);
   const bool o8 = a.geom.oct8 != 0;
   auto one = [&](const HardArgs& b) -> hipError_t {
@@ -482,6 +496,77 @@ hipError_t configure_hard_kernels() {
   if ((e = allow_big_lds<512>()) != hipSuccess) return e;
   if ((e = allow_big_lds<1024, true>()) != hipSuccess) return e;
   return allow_big_lds<1024>();
+}
+
+
+// ---------------------------------------------------------------------------
+// processing order of a batch
+// ---------------------------------------------------------------------------
+
+// A thin slab of the fixed volume spans every x and y, so its image in the
+// moving volume is set by the moving z that each transform assigns to it:
+// workgroups that sweep one slab for transforms of similar z rows read the
+// same moving slices, which then stay in the XCD's L2.  Transforms are
+// keyed by four features of the index-space z row (M[2][.]) in moving
+// voxels: the image depth of the fixed centre, and how much that depth
+// changes across the fixed volume's z, x and y extents; the quantised
+// features are interleaved bit by bit (a Morton code), with the index in
+// the low bits, and each block of kOrderBlock transforms is sorted by that
+// key (bitonic, in LDS).  The histograms do not depend on the order.
+__global__ __launch_bounds__(1024) void order_transforms_kernel(const double* __restrict__ M, int32_t n,
+                                                                float cx, float cy, float cz, float ex, float ey,
+                                                                float ez, uint32_t* __restrict__ order) {
+  __shared__ unsigned long long key[kOrderBlock];
+  const int32_t base = (int32_t)blockIdx.x * kOrderBlock;
+  const int32_t m = min(kOrderBlock, n - base);
+  int32_t p = 1;
+  while (p < m) p <<= 1;
+  auto quant = [](float f) -> uint32_t {  // 13 bits, 2 moving voxels per step
+    const float v = floorf(f * 0.5f) + 4096.0f;
+    return (uint32_t)fminf(fmaxf(v, 0.0f), 8191.0f);
+  };
+  for (int32_t i = threadIdx.x; i < p; i += blockDim.x) {
+    unsigned long long k = ~0ull;
+    if (i < m) {
+      const double* r = M + 12 * (size_t)(base + i) + 8;  // z row
+      const float f[4] = {(float)(r[0] * cx + r[1] * cy + r[2] * cz + r[3]), (float)(r[2] * ez),
+                          (float)(r[0] * ex), (float)(r[1] * ey)};
+      uint32_t q[4];
+      for (int j = 0; j < 4; ++j) q[j] = quant(f[j]);
+      unsigned long long code = 0;
+      for (int b = 12; b >= 0; --b)
+        for (int j = 0; j < 4; ++j) code = (code << 1) | ((q[j] >> b) & 1u);
+      k = (code << 12) | (unsigned long long)i;  // 52-bit code, 12-bit index
+    }
+    key[i] = k;
+  }
+  __syncthreads();
+  for (int32_t size = 2; size <= p; size <<= 1)
+    for (int32_t stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int32_t i = threadIdx.x; i < p; i += blockDim.x) {
+        const int32_t j = i ^ stride;
+        if (j > i) {
+          const bool up = (i & size) == 0;
+          const unsigned long long a = key[i], b = key[j];
+          if ((a > b) == up) {
+            key[i] = b;
+            key[j] = a;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  for (int32_t i = threadIdx.x; i < m; i += blockDim.x) order[base + i] = (uint32_t)(base + (key[i] & 0xFFFu));
+}
+
+hipError_t launch_order_transforms(const double* M, int32_t n, int32_t fnx, int32_t fny, int32_t fnz, uint32_t* order,
+                                   hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const unsigned blocks = (unsigned)((n + kOrderBlock - 1) / kOrderBlock);
+  hipLaunchKernelGGL(order_transforms_kernel, dim3(blocks), dim3(1024), 0, s, M, n, 0.5f * (float)(fnx - 1),
+                     0.5f * (float)(fny - 1), 0.5f * (float)(fnz - 1), (float)(fnx - 1), (float)(fny - 1),
+                     (float)(fnz - 1), order);
+  return hipGetLastError();
 }
 
 }  // namespace gemi

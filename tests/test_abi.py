@@ -191,7 +191,9 @@ def test_workspace_size_layout():
     # MI partial sums: per transform, slice (min(1024 // n, B // 8) for
     # B >= 16) and entropy, three compensated pairs of doubles
     part = a(5 * min(1024 // 5, 32 // 8) * 2 * 3 * 16)
-    xf = a(5 * 96)  # the index-space matrices composed from the physical ones
+    # the index-space matrices composed from the physical ones, then the hard
+    # sweep's processing order (u32 per transform)
+    xf = a(5 * 96) + a(5 * 4)
     st, n = ws_size(vol(10, 11, 12), vol(9, 8, 7), 5, 32, 2)
     # moving range <= 256: oct volume of 8-bit corners, 8 bytes per voxel;
     # histograms; N per transform

@@ -138,6 +138,35 @@ def test_compact_slabs_rotation_map(ctx):
     assert torch.all((m - ref).abs() <= 1e-12 * torch.clamp(ref.abs(), min=1.0))
 
 
+@pytest.mark.parametrize("n,shape", [(300, (40, 36, 30)), (5000, (12, 10, 9))])
+def test_processing_order_keeps_histograms(ctx, n, shape):
+    """Batches of 64 transforms or more are swept in an order that groups
+    similar moving depths (sorted per block of 4096 transforms): every
+    transform's histogram, MI and overlap equal those of the same transform
+    evaluated in batches of 50, which keep the batch order.  The affines
+    turn about every axis and scale along z, so the order differs from the
+    batch order; n = 5000 spans two sorted blocks."""
+    import torch
+    from paper_1909_10690_amd import binding as B
+    rng = np.random.default_rng(404)
+    f = inputs.random_volume(rng, shape, np.uint16, 0, 4095)
+    m = inputs.random_volume(rng, shape, np.uint16, 0, 4095)
+    mats = inputs.random_affines(rng, n, shape, rot=25.0, trans=4.0, scale=(0.8, 1.25))
+    F, Mv = B.Volume.from_numpy(f, 0, 4095), B.Volume.from_numpy(m, 0, 4095)
+    q = (1.0, 1.5)
+    print(f"processing order n={n} shape={shape}", flush=True)
+    mi, ov, hist = ctx.eval(F, Mv, torch.from_numpy(mats).cuda(), 32, q, want_hist=True)
+    torch.cuda.synchronize()
+    for t0 in range(0, n, 50):
+        sub = torch.from_numpy(mats[t0:t0 + 50]).cuda()
+        mi_s, ov_s, h_s = ctx.eval(F, Mv, sub, 32, q, want_hist=True)
+        torch.cuda.synchronize()
+        assert torch.equal(hist[t0:t0 + 50], h_s), f"histograms of transforms {t0}..{t0 + 49}"
+        assert torch.equal(ov[t0:t0 + 50], ov_s)
+        # the reduction slices a batch of 50 and one of n differently: last bits
+        assert torch.all((mi[t0:t0 + 50] - mi_s).abs() <= 1e-12 * torch.clamp(mi_s.abs(), min=1.0))
+
+
 def test_integer_translations_tiny(ctx):
     import itertools
     rng = np.random.default_rng(5)
