@@ -269,14 +269,15 @@ void hist_hard_kernel(HardArgs a) {
   uint32_t t, chunk, band;
   block_work(a.chunks, a.n, 1, a.slab_major, t, chunk, band);
   if (a.order) t = a.order[t] - a.order_base;
+  const double* Md = a.transforms + 12 * (size_t)t;
   int64_t Mq[12];
-  const bool ok = quantize_transform(a.transforms + 12 * (size_t)t, Mq);
+  const bool ok = quantize_transform(Md, Mq);
   __syncthreads();
   if (ok) {
     if (BRICK)
-      sweep_hard<CLAMP, PACKED, OCT8, NT / 64, GroupWalkBrick>(a.geom, Mq, a.chunks, chunk, lds_hist);
+      sweep_hard<CLAMP, PACKED, OCT8, NT / 64, GroupWalkBrick>(a.geom, Md, Mq, a.chunks, chunk, lds_hist);
     else
-      sweep_hard<CLAMP, PACKED, OCT8, NT / 64>(a.geom, Mq, a.chunks, chunk, lds_hist);
+      sweep_hard<CLAMP, PACKED, OCT8, NT / 64>(a.geom, Md, Mq, a.chunks, chunk, lds_hist);
   }
   __syncthreads();
   if (ok) flush_hist<PACKED, NT>(lds_hist, B, a.hist + (size_t)t * B * B, false);

@@ -311,9 +311,10 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8))) void hi
     }
     const uint32_t chunk = xcd * (uint32_t)(chunks >> 3) + (uint32_t)slab;
     const int64_t t = t0 + tl;
+    const double* Md = a.transforms + 12 * t;
     int64_t Mq[12];
-    const bool ok = quantize_transform(a.transforms + 12 * t, Mq);
-    if (ok) sweep_hard<CLAMP, PACKED, OCT8, NT / 64, GroupWalkBrick>(geom, Mq, chunks, chunk, lds_hist);
+    const bool ok = quantize_transform(Md, Mq);
+    if (ok) sweep_hard<CLAMP, PACKED, OCT8, NT / 64, GroupWalkBrick>(geom, Md, Mq, chunks, chunk, lds_hist);
     __syncthreads();
     if (ok) flush_hist<PACKED, NT>(lds_hist, B, a.hist + (size_t)t * B * B, true);
     __syncthreads();

@@ -78,12 +78,14 @@ struct HardStep {
   // Counts one fixed voxel whose exact Q32 moving coordinates (qx, qy, qz)
   // are given: clamped (CLAMP) or skipped when outside [0, n - 1] on any
   // axis; fixed_bin() supplies its fixed bin (read after the gather is
-  // issued).
-  template <bool CLAMP, bool PACKED, bool OCT8, typename FB>
+  // issued).  CHECK false: the caller has established that the voxel lies
+  // inside on every axis, where clamping and skipping change nothing.
+  template <bool CLAMP, bool PACKED, bool OCT8, bool CHECK = true, typename FB>
   __device__ __forceinline__ void count(int64_t qx, int64_t qy, int64_t qz, FB&& fixed_bin,
                                         uint32_t* lds_hist) const {
     uint64_t cx = (uint64_t)qx, cy = (uint64_t)qy, cz = (uint64_t)qz;
-    if (CLAMP) {
+    if (!CHECK) {
+    } else if (CLAMP) {
       cx = qx < 0 ? 0 : (cx > topx ? topx : cx);
       cy = qy < 0 ? 0 : (cy > topy ? topy : cy);
       cz = qz < 0 ? 0 : (cz > topz ? topz : cz);
@@ -147,14 +149,47 @@ struct HardStep {
   }
 };
 
+// The x ranges of a wave's row groups (range_lane, range_value, row_spans):
+// lanes 0..15 hold the bound constants of the transform, and each row group
+// takes the least v of each group of four lanes with two quad permutes.
+struct RowRanges {
+  RangeLane c;
+  bool exact;  // uniform: every lane's constants exact
+
+  // Md: the transform's 12 entries (index space, row-major 3 x 4) in device
+  // memory; each lane reads its axis row and rounds it to Q32 as
+  // quantize_transform does.
+  __device__ __forceinline__ RowRanges(const double* Md, const HardGeom& g, int lane) {
+    const int a = (lane & 3) == 3 ? 0 : (lane & 3);
+    const double* row = Md + 4 * a;
+    const double q = 4294967296.0;
+    const double m0 = __builtin_rint(row[0] * q), m1 = __builtin_rint(row[1] * q);
+    const double m2 = __builtin_rint(row[2] * q), m3 = __builtin_rint(row[3] * q);
+    const int32_t n = a == 0 ? g.mnx : (a == 1 ? g.mny : g.mnz);
+    c = range_lane(lane, m0, m1, m2, m3, (double)(n - 1) * q);
+    exact = __builtin_amdgcn_ballot_w64(!c.exact) == 0;
+  }
+
+  // Spans of the row group at (j0, k); the whole wave takes part.
+  __device__ __forceinline__ RowSpans spans(int32_t j0, int32_t k, int32_t full, bool skip) const {
+    if (!exact) return RowSpans{0, full, full, full};
+    int32_t v = range_value(c, j0, k);
+    v = min(v, __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false));  // quad_perm 1,0,3,2
+    v = min(v, __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, false));  // quad_perm 2,3,0,1
+    return row_spans(__builtin_amdgcn_readlane(v, 0), __builtin_amdgcn_readlane(v, 4),
+                     __builtin_amdgcn_readlane(v, 8), __builtin_amdgcn_readlane(v, 12), full, skip);
+  }
+};
+
 // Sweeps one slab of the fixed volume for one transform (Mq) into the
 // workgroup's LDS histogram.  NW waves share the slab's 4-row groups, in
 // the order of Walk (thin slabs, or bricks).
 // OCT8: the oct volume holds 8-bit corners (one 64-bit gather), unpacked
 // into the 16-bit pairs of the x-lerp with byte permutes.
+// Md: the transform as stored (Mq is its Q32 rounding).
 template <bool CLAMP, bool PACKED, bool OCT8, int NW, typename Walk = GroupWalk>
-__device__ __forceinline__ void sweep_hard(const HardGeom& g, const int64_t* Mq, int32_t chunks,
-                                           uint32_t chunk, uint32_t* lds_hist) {
+__device__ __forceinline__ void sweep_hard(const HardGeom& g, const double* Md, const int64_t* Mq,
+                                           int32_t chunks, uint32_t chunk, uint32_t* lds_hist) {
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   const int dx = lane & (kTileX - 1), dy = lane / kTileX;
@@ -176,16 +211,38 @@ __device__ __forceinline__ void sweep_hard(const HardGeom& g, const int64_t* Mq,
   const int lane_f = (int)(dy * fnx + dx);
   const int32_t full = (int32_t)(fnx / kTileX);      // x steps every lane of the tile takes
   const bool tail = (uint32_t)dx < fnx % kTileX;  // the lane takes one more
+  const bool has_tail = fnx % kTileX != 0;
+  const RowRanges ranges(Md, g, lane);
 
   for (; w.g < w.g1; w.next()) {
+    // x steps [u0, c0) and [c1, u1) test each voxel, [c0, c1) has every
+    // lane inside; with EXCLUDE no lane counts outside [u0, u1)
+    const RowSpans sp = ranges.spans(w.j0, w.k, full, !CLAMP);
     const int32_t j = w.j0 + dy;
     if (j >= g.fny) continue;
-    uint32_t soff = ((uint32_t)w.k * (uint32_t)g.fny + (uint32_t)w.j0) * fnx;
+    const uint32_t row = ((uint32_t)w.k * (uint32_t)g.fny + (uint32_t)w.j0) * fnx;
+    uint32_t soff = row + (uint32_t)sp.u0 * kTileX;
     int64_t qx = w.r[0] + w.lane_off[0], qy = w.r[1] + w.lane_off[1], qz = w.r[2] + w.lane_off[2];
+    if (sp.u0 > 0) {
+      qx += sx * sp.u0;
+      qy += sy * sp.u0;
+      qz += sz * sp.u0;
+    }
     auto fixed_bin = [&] { return (uint32_t)__builtin_amdgcn_raw_buffer_load_b8(frsrc, lane_f, (int)soff, 0); };
-    for (int32_t it = 0; it < full; ++it, soff += kTileX, qx += sx, qy += sy, qz += sz)
+    int32_t it = sp.u0;
+    for (; it < sp.c0; ++it, soff += kTileX, qx += sx, qy += sy, qz += sz)
       hs.count<CLAMP, PACKED, OCT8>(qx, qy, qz, fixed_bin, lds_hist);
-    if (tail) hs.count<CLAMP, PACKED, OCT8>(qx, qy, qz, fixed_bin, lds_hist);
+    for (; it < sp.c1; ++it, soff += kTileX, qx += sx, qy += sy, qz += sz)
+      hs.count<CLAMP, PACKED, OCT8, false>(qx, qy, qz, fixed_bin, lds_hist);
+    for (; it < sp.u1; ++it, soff += kTileX, qx += sx, qy += sy, qz += sz)
+      hs.count<CLAMP, PACKED, OCT8>(qx, qy, qz, fixed_bin, lds_hist);
+    if (has_tail && tail) {
+      soff = row + (uint32_t)full * kTileX;
+      qx = w.r[0] + sx * full + w.lane_off[0];
+      qy = w.r[1] + sy * full + w.lane_off[1];
+      qz = w.r[2] + sz * full + w.lane_off[2];
+      hs.count<CLAMP, PACKED, OCT8>(qx, qy, qz, fixed_bin, lds_hist);
+    }
   }
 }
 
