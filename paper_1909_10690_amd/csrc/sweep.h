@@ -246,27 +246,39 @@ __device__ __forceinline__ void sweep_hard(const HardGeom& g, const double* Md, 
   }
 }
 
-// Clears a workgroup's LDS histogram, padding included.
+// Clears a workgroup's LDS histogram, padding included (16-byte stores,
+// then the last words).
 template <bool PACKED, int NT>
 __device__ __forceinline__ void clear_hist(uint32_t* lds_hist, int B) {
-  const int words = B * hist_row_words(B, PACKED);
-  for (int e = threadIdx.x; e < words; e += NT) lds_hist[e] = 0;
+  const int words = B * hist_row_words(B, PACKED), quads = words >> 2;
+  uint4_t* q = (uint4_t*)lds_hist;
+  for (int e = threadIdx.x; e < quads; e += NT) q[e] = uint4_t{0u, 0u, 0u, 0u};
+  for (int e = (quads << 2) + (int)threadIdx.x; e < words; e += NT) lds_hist[e] = 0;
 }
 
 // Adds the non-zero LDS bins into a transform's HBM histogram [B][B] (and
 // clears them for the next use of the LDS histogram when `rezero`): a wave
 // per fixed-bin row at a time, a lane per counter word.
+// A row holds at most 256 counter words (B <= 256), four per lane, so each
+// row is unrolled into four fixed chunks whose addresses differ from the
+// first by immediate offsets.
 template <bool PACKED, int NT>
 __device__ __forceinline__ void flush_hist(uint32_t* lds_hist, int B, uint32_t* __restrict__ out,
                                            bool rezero) {
   const int pitch = hist_row_words(B, PACKED), used = PACKED ? (B + 1) / 2 : B;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   for (int r = wave; r < B; r += NT / 64) {
     uint32_t* __restrict__ row = out + (size_t)r * B;
-    for (int w = lane; w < used; w += 64) {
-      const uint32_t v = lds_hist[r * pitch + w];
+    uint32_t* src = lds_hist + r * pitch;
+    uint32_t vs[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) vs[c] = lane + 64 * c < used ? src[lane + 64 * c] : 0u;  // reads issued together
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int w = lane + 64 * c;
+      const uint32_t v = vs[c];
       if (v == 0) continue;
-      if (rezero) lds_hist[r * pitch + w] = 0;
+      if (rezero) src[w] = 0;
       if (PACKED) {
         if (v & 0xFFFFu) atomicAdd(&row[2 * w], v & 0xFFFFu);
         if (v >> 16) atomicAdd(&row[2 * w + 1], v >> 16);  // never set past the row's last bin
