@@ -314,7 +314,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8))) void hi
     const double* Md = a.transforms + 12 * t;
     int64_t Mq[12];
     const bool ok = quantize_transform(Md, Mq);
-    if (ok) sweep_hard<CLAMP, PACKED, OCT8, NT / 64, GroupWalkBrick>(geom, Md, Mq, chunks, chunk, lds_hist);
+    if (ok) sweep_hard<CLAMP, PACKED, OCT8, NT / 64, GroupWalkBrick, false>(geom, Md, Mq, chunks, chunk, lds_hist);
     __syncthreads();
     if (ok) flush_hist<PACKED, NT>(lds_hist, B, a.hist + (size_t)t * B * B, true);
     __syncthreads();

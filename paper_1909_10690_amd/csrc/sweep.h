@@ -159,7 +159,7 @@ struct RowRanges {
   // Md: the transform's 12 entries (index space, row-major 3 x 4) in device
   // memory; each lane reads its axis row and rounds it to Q32 as
   // quantize_transform does.
-  __device__ __forceinline__ RowRanges(const double* Md, const HardGeom& g, int lane) {
+  __device__ __forceinline__ void init(const double* Md, const HardGeom& g, int lane) {
     const int a = (lane & 3) == 3 ? 0 : (lane & 3);
     const double* row = Md + 4 * a;
     const double q = 4294967296.0;
@@ -186,8 +186,10 @@ struct RowRanges {
 // the order of Walk (thin slabs, or bricks).
 // OCT8: the oct volume holds 8-bit corners (one 64-bit gather), unpacked
 // into the 16-bit pairs of the x-lerp with byte permutes.
-// Md: the transform as stored (Mq is its Q32 rounding).
-template <bool CLAMP, bool PACKED, bool OCT8, int NW, typename Walk = GroupWalk>
+// Md: the transform as stored (Mq is its Q32 rounding).  RANGES false: every
+// voxel is tested (the range lanes' registers would not fit a kernel already
+// at its register budget).
+template <bool CLAMP, bool PACKED, bool OCT8, int NW, typename Walk = GroupWalk, bool RANGES = true>
 __device__ __forceinline__ void sweep_hard(const HardGeom& g, const double* Md, const int64_t* Mq,
                                            int32_t chunks, uint32_t chunk, uint32_t* lds_hist) {
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -212,8 +214,21 @@ __device__ __forceinline__ void sweep_hard(const HardGeom& g, const double* Md, 
   const int32_t full = (int32_t)(fnx / kTileX);      // x steps every lane of the tile takes
   const bool tail = (uint32_t)dx < fnx % kTileX;  // the lane takes one more
   const bool has_tail = fnx % kTileX != 0;
-  const RowRanges ranges(Md, g, lane);
+  RowRanges ranges;
+  if (RANGES) ranges.init(Md, g, lane);
 
+  if constexpr (!RANGES) {
+    for (; w.g < w.g1; w.next()) {
+      if (w.j0 + dy >= g.fny) continue;
+      uint32_t soff = ((uint32_t)w.k * (uint32_t)g.fny + (uint32_t)w.j0) * fnx;
+      int64_t qx = w.r[0] + w.lane_off[0], qy = w.r[1] + w.lane_off[1], qz = w.r[2] + w.lane_off[2];
+      auto fixed_bin = [&] { return (uint32_t)__builtin_amdgcn_raw_buffer_load_b8(frsrc, lane_f, (int)soff, 0); };
+      for (int32_t it = 0; it < full; ++it, soff += kTileX, qx += sx, qy += sy, qz += sz)
+        hs.count<CLAMP, PACKED, OCT8>(qx, qy, qz, fixed_bin, lds_hist);
+      if (tail) hs.count<CLAMP, PACKED, OCT8>(qx, qy, qz, fixed_bin, lds_hist);
+    }
+    return;
+  }
   for (; w.g < w.g1; w.next()) {
     // x steps [u0, c0) and [c1, u1) test each voxel, [c0, c1) has every
     // lane inside; with EXCLUDE no lane counts outside [u0, u1)
