@@ -273,3 +273,31 @@ def test_maximum_edge_and_ragged_rows(ctx, bins, mrange):
     for flags in (0, 1):
         args = (fixed, moving, (0, 4095), mrange, mats, bins, [1.0, 1.5], flags)
         assert_parity(run_gpu(ctx, *args), run_oracle(*args), f"4096 rows bins={bins} flags={flags}")
+
+
+def test_row_ranges_faces_turns_and_outside_rows(ctx):
+    """Rows of 100 voxels (six 16-voxel steps and a ragged tail of 4): the
+    sweep runs the steps where every lane of a 16 x 4 tile is inside the
+    moving volume without per-voxel tests and, excluding the boundary,
+    leaves out those where no lane can be.  Integer x-translations put the
+    rows' ends exactly on the moving faces; quarter turns and mirrors about
+    z give zero and negative x steps; scalings and large shifts put whole
+    rows and tiles outside."""
+    rng = np.random.default_rng(17)
+    fixed = inputs.random_volume(rng, (100, 23, 9), np.uint16, 0, 4095)
+    moving = inputs.random_volume(rng, (90, 30, 11), np.uint16, 0, 4095)
+    mats = [T.translation((tx, ty, tz)) for tx in (-16, -10, 0, 4, 10, 32, 89)
+            for ty, tz in ((0, 0), (3.5, 1.0), (-2.0, -0.5))]
+    quarter = [
+        [[0, -1, 0, 29.0], [1, 0, 0, 0], [0, 0, 1, 0]],        # x steps along moving y
+        [[-1, 0, 0, 89.0], [0, 1, 0, 0.5], [0, 0, 1, 1.0]],    # mirrored x
+        [[0, 1, 0, 0], [-1, 0, 0, 99.0], [0, 0, 1, 0]],        # negative y steps
+        [[0, 0, 1, 0], [0, 1, 0, 0], [1, 0, 0, 0]],            # x steps along moving z
+        [[0, 0, 0, 40.0], [0, 1, 0, 0], [0, 0, 1, 0]],         # no x step at all
+        [[1.1, 0.05, 0, -3.0], [-0.05, 1.1, 0, -1.0], [0, 0, 1.2, -0.5]],
+        [[0.6, 0, 0, 20.25], [0, 0.9, 0, 2.0], [0, 0, 0.8, 1.0]],
+    ]
+    mats = np.concatenate([np.stack(mats).reshape(-1, 12), np.asarray(quarter, dtype=np.float64).reshape(-1, 12)])
+    for flags in (0, 1):
+        args = (fixed, moving, (0, 4095), (0, 4095), mats, 64, [1.0, 0.5], flags)
+        assert_parity(run_gpu(ctx, *args), run_oracle(*args), f"row ranges flags={flags}")
