@@ -282,7 +282,8 @@ def test_row_ranges_faces_turns_and_outside_rows(ctx):
     leaves out those where no lane can be.  Integer x-translations put the
     rows' ends exactly on the moving faces; quarter turns and mirrors about
     z give zero and negative x steps; scalings and large shifts put whole
-    rows and tiles outside."""
+    rows and tiles outside; large shears and a far translation take the
+    path that tests every voxel."""
     rng = np.random.default_rng(17)
     fixed = inputs.random_volume(rng, (100, 23, 9), np.uint16, 0, 4095)
     moving = inputs.random_volume(rng, (90, 30, 11), np.uint16, 0, 4095)
@@ -296,6 +297,10 @@ def test_row_ranges_faces_turns_and_outside_rows(ctx):
         [[0, 0, 0, 40.0], [0, 1, 0, 0], [0, 0, 1, 0]],         # no x step at all
         [[1.1, 0.05, 0, -3.0], [-0.05, 1.1, 0, -1.0], [0, 0, 1.2, -0.5]],
         [[0.6, 0, 0, 20.25], [0, 0.9, 0, 2.0], [0, 0, 0.8, 1.0]],
+        # entries too large for exact range arithmetic: every voxel tested
+        [[1, 100.0, 0, -1150.5], [0, 1, 0, 2.0], [0, 0, 1, 0]],
+        [[1, 0, 0, 200000.0], [0, 1, 0, 0], [0, 0, 1, 0]],
+        [[1, 0, 0, 0], [0, 1, 0, 0], [0, -70.0, 1, 800.0]],
     ]
     mats = np.concatenate([np.stack(mats).reshape(-1, 12), np.asarray(quarter, dtype=np.float64).reshape(-1, 12)])
     for flags in (0, 1):
