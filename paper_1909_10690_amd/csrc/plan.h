@@ -148,7 +148,7 @@ using GroupWalkFlex = GroupWalkT<true>;
 // bound itself, or minus the lower bound, so that each group's bound is the
 // least v of its four lanes.  The margin D = -/+ (ceil(|S| / 64) + 1) (every-
 // lane / some-lane range) is an integer of at least |S| / 64, so A + D stays
-// an exact integer in double (below 2^52), and the division and the
+// an exact integer in double (below 2^53), and the division and the
 // rounding to float err by far less than D / |S|: the every-lane range can
 // only come out narrower than exact, the some-lane range only wider, by one
 // iteration where a bound lies within D / |S| of an integer (a face hit
@@ -177,7 +177,8 @@ constexpr float kRangeClamp = 1048576.0f;  // |v| <= 2^20, far past any row's it
 // take no bound) and that axis's upper moving coordinate top = (n - 1) 2^32,
 // all as doubles (integers; exact below 2^53).  Everything is formed in
 // double: while |m0| < 2^47, |m1|, |m2| < 2^38 and |m3| < 2^49 (`exact`)
-// every value below is an integer below 2^52 and so exact.
+// every value below is an integer below 2^53 (a half-integer below 2^51
+// when S = 0, which makes m0 = 0) and so exact.
 GEMI_HOST_DEVICE inline RangeLane range_lane(int lane, double m0, double m1, double m2, double m3, double top) {
   RangeLane c{0.0, 0.0, 1073741824.0, 1.0, true};  // no bound: v clamps to 2^20
   if (lane >= 16 || (lane & 3) == 3) return c;
@@ -198,7 +199,7 @@ GEMI_HOST_DEVICE inline RangeLane range_lane(int lane, double m0, double m1, dou
   // S = 0: v is +-2^20 by the sign of A + 1/2 (no margin: A is an integer)
   c.a0 = step == 0 ? cst + 0.5 : cst + (every ? -margin : margin);
   c.inv = step == 0 ? 1152921504606846976.0 : 1.0 / mag;  // 2^60 when S = 0
-  // j0, k < 2^12: |A + D| < 2^38 2^12 + 2^38 2^12 + 2^51 < 2^52
+  // j0, k < 2^12: |A + D| < 2^50 + 2^50 + |m3| + 15 |m0| + 3 |m1| + top + margin < 2^53
   c.exact = __builtin_fabs(m0) < 140737488355328.0 && __builtin_fabs(m1) < 274877906944.0 &&
             __builtin_fabs(m2) < 274877906944.0 && __builtin_fabs(m3) < 562949953421312.0;
   return c;
