@@ -101,6 +101,24 @@ __device__ __forceinline__ bool quantize_transform(const double* __restrict__ M,
   return ok;
 }
 
+// quantize_transform for a whole wave at once: lane e < 12 rounds entry e
+// and the results are broadcast to scalar registers, with the same values
+// and the same validity test.  Every lane of the wave takes part.
+__device__ __forceinline__ bool quantize_transform_wave(const double* __restrict__ M, int64_t* Mq) {
+  const int lane = threadIdx.x & 63;
+  const int e = lane < 12 ? lane : 0;
+  const double m = M[e];
+  const double lim = (e % 4 == 3) ? 16777216.0 : 65536.0;
+  const bool bad = lane < 12 && !(fabs(m) <= lim);  // true for NaN and infinities
+  const int64_t v = __double2ll_rn(m * 4294967296.0);
+  const uint32_t lo = (uint32_t)v, hi = (uint32_t)((uint64_t)v >> 32);
+#pragma unroll
+  for (int i = 0; i < 12; ++i)
+    Mq[i] = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readlane(hi, i) << 32) |
+                      (uint32_t)__builtin_amdgcn_readlane(lo, i));
+  return __builtin_amdgcn_ballot_w64(bad) == 0;
+}
+
 // A value every lane holds alike, moved to scalar registers.  A value
 // computed by vector instructions stays in vector registers otherwise, and
 // the compiler drops a readfirstlane builtin of a value it knows is uniform,

@@ -313,8 +313,13 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8))) void hi
     const int64_t t = t0 + tl;
     const double* Md = a.transforms + 12 * t;
     int64_t Mq[12];
-    const bool ok = quantize_transform(Md, Mq);
-    if (ok) sweep_hard<CLAMP, PACKED, OCT8, NT / 64, GroupWalkBrick, false>(geom, Md, Mq, chunks, chunk, lds_hist);
+    const bool ok = quantize_transform(Md, Mq);  // (the wave-parallel form measured 0.8% slower here)
+    if (ok) {
+      int64_t Ms[12];
+#pragma unroll
+      for (int e = 0; e < 12; ++e) Ms[e] = uniform64(Mq[e]);
+      sweep_hard<CLAMP, PACKED, OCT8, NT / 64, GroupWalkBrick, false>(geom, Md, Ms, chunks, chunk, lds_hist);
+    }
     __syncthreads();
     if (ok) flush_hist<PACKED, NT>(lds_hist, B, a.hist + (size_t)t * B * B, true);
     __syncthreads();

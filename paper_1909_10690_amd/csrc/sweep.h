@@ -186,7 +186,8 @@ struct RowRanges {
 // the order of Walk (thin slabs, or bricks).
 // OCT8: the oct volume holds 8-bit corners (one 64-bit gather), unpacked
 // into the 16-bit pairs of the x-lerp with byte permutes.
-// Md: the transform as stored (Mq is its Q32 rounding).  RANGES false: every
+// Md: the transform as stored; Mq: its Q32 rounding, in scalar registers
+// (quantize_transform_wave).  RANGES false: every
 // voxel is tested (the range lanes' registers would not fit a kernel already
 // at its register budget).
 template <bool CLAMP, bool PACKED, bool OCT8, int NW, typename Walk = GroupWalk, bool RANGES = true>
@@ -195,11 +196,10 @@ __device__ __forceinline__ void sweep_hard(const HardGeom& g, const double* Md, 
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   const int dx = lane & (kTileX - 1), dy = lane / kTileX;
-  // the matrix in scalar registers: the walk's row coordinates and steps
-  // are then scalar values, and only the lane offsets take vector registers
-  int64_t M[12];
-#pragma unroll
-  for (int e = 0; e < 12; ++e) M[e] = uniform64(Mq[e]);
+  // the matrix in scalar registers (quantize_transform_wave puts it there):
+  // the walk's row coordinates and steps are then scalar values, and only
+  // the lane offsets take vector registers
+  const int64_t* M = Mq;
   Walk w;
   w.init(M, g.fny, g.fnz, chunks, chunk, wave, NW, dx, dy);
   const int64_t sx = w.step[0], sy = w.step[1], sz = w.step[2];
